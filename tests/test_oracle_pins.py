@@ -1,0 +1,386 @@
+"""Closed forms, exact special cases and invariants that pin the oracle (CPU only).
+
+P1 empty volume -> stack 1, image = background, exactly
+P2 constant cube, no coefficient: textbook emission-absorption (Eq. 2/3) over the chord
+P3 Beer-Lambert stack (Eq. 6): exact for an axis light, within one slab for an oblique one
+P5 opaque box: exact shadow footprint for every gather mode
+P6 light parallel to view: closed-form limit and convergence
+P7 stack lookup vs a dense march toward the light: second-order convergence
+P8 reductions (vanishing shell step == direct shadow)
+P9 invariants (alpha <= 1, 0 <= C <= alpha, stack monotone, termination bound)
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2008_06134_amd import workloads as W
+
+SQ3 = math.sqrt(3.0)
+MODES = ["shadow", "shell", "cone", "cone5"]
+
+
+def _mode(m):
+    return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
+
+
+def _const_tf(rgba):
+    return O.TF(np.tile(np.asarray(rgba, float), (256, 1)))
+
+
+def _tf_zero_then(rgba):
+    """alpha 0 at value 0, the given rgba for every other entry (value 0 stays empty)."""
+    t = np.tile(np.asarray(rgba, float), (256, 1))
+    t[0] = [0, 0, 0, 0]
+    return O.TF(t)
+
+
+# ------------------------------------------------------------------ P1
+
+@pytest.mark.parametrize("mode", ["none"] + MODES)
+@pytest.mark.parametrize("kind", ["ortho", "persp"])
+def test_p1_empty_volume_gives_background(mode, kind):
+    raw = np.zeros((12, 12, 12), np.uint8)
+    vol, tf = O.Volume(raw), O.TF(W.tf_ramp())
+    st = O.Stack(vol, tf, [1, 1, -1], 6, 10)
+    assert np.all(st.export() == 1.0)
+    bg = [0.1, 0.2, 0.3, 0.4]
+    cam = W.camera_ortho_front(10, 8) if kind == "ortho" else W.camera_orbit(10, 8, 0.7, 0.3)
+    m, extra = _mode(mode)
+    full, term, nt, nf = O.render(vol, tf, st, cam, m, 0.5, {"bg": bg, **extra})
+    assert np.all(full == np.asarray(bg)) and np.all(term == np.asarray(bg))
+    assert nf.sum() > 0  # rays did hit the cube
+
+
+# ------------------------------------------------------------------ P2
+
+def test_p2_constant_cube_ortho_chord_one():
+    N, a0, rgb = 16, 0.05, [0.9, 0.6, 0.3]
+    raw = np.full((N, N, N), 100, np.uint8)
+    vol, tf = O.Volume(raw), _const_tf(rgb + [a0])
+    cam = W.camera_ortho_front(32, 32, half_h=0.75)
+    full, term, nt, nf = O.render(vol, tf, None, cam, "none", 0.5)
+    a_pix = 1 - (1 - a0) ** N            # chord 1 = N reference lengths
+    hit = 0
+    for py in range(32):
+        for px in range(32):
+            x = 0.5 + (2 * (px + 0.5) / 32 - 1) * 0.75
+            z = 0.5 + (1 - 2 * (py + 0.5) / 32) * 0.75
+            if 0 < x < 1 and 0 < z < 1:
+                hit += 1
+                np.testing.assert_allclose(full[py, px], np.array(rgb + [1.0]) * a_pix, rtol=1e-12)
+                assert nf[py, px] == 2 * N   # chord / half-voxel step
+            elif not (0 <= x <= 1 and 0 <= z <= 1):
+                assert np.all(full[py, px] == 0)
+    assert hit > 100
+
+
+@pytest.mark.parametrize("step", [0.5, 0.37, 1.0])
+def test_p2_constant_cube_perspective_chords(step):
+    """Chord lengths from bisection on the inside indicator, independent of the slab test."""
+    N, a0, rgb = 16, 0.08, [0.2, 0.7, 0.5]
+    raw = np.full((N, N, N), 77, np.uint8)
+    vol, tf = O.Volume(raw), _const_tf(rgb + [a0])
+    cam = {"kind": "persp", "eye": [0.45, 0.55, -1.4], "target": [0.5, 0.5, 0.5], "up": [0, 1, 0],
+           "fovy_deg": 40.0, "width": 20, "height": 20}
+    full, term, nt, nf = O.render(vol, tf, None, cam, "none", step)
+    inside = lambda p: bool(np.all((p >= 0) & (p <= 1)))  # noqa: E731
+    checked = 0
+    for py in range(0, 20, 3):
+        for px in range(0, 20, 3):
+            o, d = O.camera_ray(cam, px, py)
+            ts = np.linspace(0, 5, 5001)
+            ins = np.array([inside(o + t * d) for t in ts])
+            if not ins.any():
+                assert np.all(full[py, px] == 0)
+                continue
+            lo, hi = ts[ins][0], ts[ins][-1]
+
+            def edge(a, b, enter):
+                for _ in range(80):
+                    m = 0.5 * (a + b)
+                    if inside(o + m * d) == enter:
+                        b = m
+                    else:
+                        a = m
+                return b if enter else a
+            t0 = edge(lo - 1e-3, lo, True)
+            t1 = edge(hi, hi + 1e-3, False)
+            D = t1 - t0
+            a_pix = 1 - (1 - a0) ** (D * N)
+            np.testing.assert_allclose(full[py, px], np.array(rgb + [1.0]) * a_pix, rtol=1e-9, atol=1e-12)
+            checked += 1
+    assert checked > 20
+
+
+def test_p2_termination_bound():
+    N = 16
+    raw = np.full((N, N, N), 200, np.uint8)
+    vol, tf = O.Volume(raw), _const_tf([1.0, 0.5, 0.25, 0.6])
+    cam = W.camera_ortho_front(16, 16, half_h=0.6)
+    full, term, nt, nf = O.render(vol, tf, None, cam, "none", 0.5)
+    eps = 2.0 ** -15
+    assert np.abs(full - term).max() <= eps
+    assert (nt < nf).any()                         # termination did happen
+    # terminated pixels keep at most eps of transmittance, and stopped at the first such sample
+    a_step = 1 - (1 - 0.6) ** 0.5
+    k_expect = math.ceil(math.log(eps) / math.log(1 - a_step))
+    assert (nt[nt < nf] == k_expect).all()
+
+
+# ------------------------------------------------------------------ P3
+
+def test_p3_beer_lambert_axis_light_exact():
+    N, n, res, a0 = 16, 16, 16, 0.07
+    raw = np.full((N, N, N), 90, np.uint8)
+    vol, tf = O.Volume(raw), _const_tf([1, 1, 1, a0])
+    st = O.Stack(vol, tf, [0, 0, 1], n, res)
+    S = st.export()
+    f = st.frame
+    u = -f["R"] + (np.arange(res) + 0.5) * 2 * f["R"] / res
+    k = np.arange(n)
+    expect = (1 - a0) ** ((k + 1) * (1.0 / n) * N)
+    for j in range(res):
+        for i in range(res):
+            if abs(u[i]) < 0.5 and abs(u[j]) < 0.5:
+                np.testing.assert_allclose(S[:, j, i], expect, rtol=1e-12)
+            elif abs(u[i]) > 0.5 or abs(u[j]) > 0.5:
+                assert np.all(S[:, j, i] == 1.0)
+
+
+@pytest.mark.parametrize("light", [[1, 1, -1], [0.3, -0.8, 0.5], [-1, 0.2, 0.1]])
+def test_p3_beer_lambert_oblique_within_one_slab(light):
+    N, n, res, a0 = 16, 24, 20, 0.05
+    raw = np.full((N, N, N), 90, np.uint8)
+    vol, tf = O.Volume(raw), _const_tf([1, 1, 1, a0])
+    st = O.Stack(vol, tf, light, n, res)
+    S = st.export()
+    f = st.frame
+    sigma = -math.log(1 - a0) * N
+    u = -f["R"] + (np.arange(res) + 0.5) * 2 * f["R"] / res
+    for j in range(res):
+        for i in range(res):
+            base = f["c"] + u[i] * f["U"] + u[j] * f["V"] - (f["L"] @ f["c"]) * f["L"]
+            # Liang-Barsky clip of the column line to the cube, parameter = distance along L
+            lo, hi = -np.inf, np.inf
+            for ax in range(3):
+                if abs(f["L"][ax]) < 1e-15:
+                    if not (0 <= base[ax] <= 1):
+                        lo, hi = 1, 0
+                    continue
+                t1, t2 = (0 - base[ax]) / f["L"][ax], (1 - base[ax]) / f["L"][ax]
+                lo, hi = max(lo, min(t1, t2)), min(hi, max(t1, t2))
+            for k in range(n):
+                face = f["dmin"] + (k + 1) * f["ds"]
+                d_in = max(0.0, min(hi, face) - lo) if hi > lo else 0.0
+                assert abs(S[k, j, i] - math.exp(-sigma * d_in)) <= sigma * f["ds"] + 1e-12
+
+
+# ------------------------------------------------------------------ P5
+
+def _p5_setup():
+    N = 32
+    plate = np.zeros((N, N, N), np.uint8)
+    plate[4:8, 4:28, 4:28] = 100                    # z in [4,8) voxels, partially transparent
+    both = plate.copy()
+    both[18:26, 8:24, 8:24] = 255                    # opaque box above the plate
+    tab = np.zeros((256, 4))
+    tab[:, 0], tab[:, 1], tab[:, 2] = 0.9, 0.8, 0.7
+    tab[:, 3] = np.linspace(0, 1, 256)               # value 255 -> alpha exactly 1
+    return N, plate, both, tab
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_p5_opaque_box_exact_shadow_footprint(mode):
+    N, plate, both, tab = _p5_setup()
+    n, res = 64, 96
+    light = np.array([0.3, 0.2, -1.0])
+    tf = O.TF(tab)
+    vplate, vboth = O.Volume(plate), O.Volume(both)
+    st_plate = O.Stack(vplate, tf, light, n, res)
+    st_box = O.Stack(vboth, tf, light, n, res)
+    # view the plate from below, looking up (+z): the plate is composited first
+    Wd = 40
+    cam = {"kind": "ortho", "eye": [0.5, 0.5, -1.0], "target": [0.5, 0.5, 0.5], "up": [0, 1, 0],
+           "ortho_half_h": 0.5, "width": Wd, "height": Wd}
+    m, extra = _mode(mode)
+    ref, _, _, _ = O.render(vplate, tf, st_plate, cam, m, 0.5, extra)
+    img, _, _, _ = O.render(vplate, tf, st_box, cam, m, 0.5, extra)
+
+    f = st_box.frame
+    L = f["L"]
+    texel = 2 * f["R"] / res
+    tap = {"shadow": 0.0, "shell": 1.0 / N, "cone": 2 * f["ds"] * math.sqrt(2.0),
+           "cone5": f["ds"] * math.sqrt(2.0)}[mode]
+    margin = math.sqrt(2) * texel + f["ds"] + tap + 1.0 / N
+    # fully opaque region of the box: where all 8 trilinear neighbours are box voxels
+    core_lo = np.array([8.5, 8.5, 18.5]) / N
+    core_hi = np.array([23.5, 23.5, 25.5]) / N
+    supp_lo = np.array([7.5, 7.5, 17.5]) / N         # where the box changes the volume at all
+    supp_hi = np.array([24.5, 24.5, 26.5]) / N
+
+    def back_ray_hits(p, lo, hi):
+        """Does p - s L, s > 0, meet the box [lo, hi]?"""
+        a, b = 0.0, np.inf
+        for ax in range(3):
+            dl = -L[ax]
+            if abs(dl) < 1e-15:
+                if not (lo[ax] <= p[ax] <= hi[ax]):
+                    return False
+                continue
+            t1, t2 = (lo[ax] - p[ax]) / dl, (hi[ax] - p[ax]) / dl
+            a, b = max(a, min(t1, t2)), min(b, max(t1, t2))
+        return b >= a
+
+    n_in = n_out = 0
+    for py in range(Wd):
+        for px in range(Wd):
+            o, d = O.camera_ray(cam, px, py)
+            # plate support (alpha > 0) along this ray: z in (3.5, 8.5) voxels
+            seg = [o + ((z / N) - o[2]) * d for z in np.linspace(3.5, 8.5, 21)]
+            if all(back_ray_hits(p, core_lo + margin, core_hi - margin) for p in (seg[0], seg[-1])):
+                n_in += 1
+                assert np.all(img[py, px, :3] == 0.0), (py, px, img[py, px])
+                assert img[py, px, 3] == ref[py, px, 3]
+            elif not any(back_ray_hits(p, supp_lo - margin, supp_hi + margin) for p in seg):
+                n_out += 1
+                assert np.all(img[py, px] == ref[py, px]), (py, px)
+    assert n_in >= 8 and n_out >= 100, (n_in, n_out)
+    # the plate is lit somewhere, so the shadow is not vacuous
+    assert ref[..., :3].max() > 0.05
+
+
+# ------------------------------------------------------------------ P6
+
+def test_p6_light_parallel_to_view_converges():
+    """L = fwd = +z, constant cube, direct shadow: C -> rgb/2 (1 - exp(-2 sigma D)).
+
+    When the ray steps coincide with the slabs the discrete sum telescopes to
+    the limit exactly; otherwise it converges to it at second order."""
+    N, a0, rgb = 8, 0.1, np.array([0.8, 0.4, 0.2])
+    raw = np.full((N, N, N), 120, np.uint8)
+    vol, tf = O.Volume(raw), _const_tf(list(rgb) + [a0])
+    sigma = -math.log(1 - a0) * N
+    limit = rgb / 2 * (1 - math.exp(-2 * sigma * 1.0))
+    cam = {"kind": "ortho", "eye": [0.5, 0.5, -1.0], "target": [0.5, 0.5, 0.5], "up": [0, 1, 0],
+           "ortho_half_h": 0.05, "width": 2, "height": 2}
+    for n, step in [(8, 1.0), (16, 0.5), (32, 0.25)]:
+        st = O.Stack(vol, tf, [0, 0, 1], n, 16)
+        full, _, _, _ = O.render(vol, tf, st, cam, "shadow", step)
+        assert np.abs(full[..., :3] - limit).max() < 1e-14
+    errs = []
+    for n, step in [(6, 0.9), (12, 0.45), (24, 0.225), (48, 0.1125)]:
+        st = O.Stack(vol, tf, [0, 0, 1], n, 16)
+        full, _, _, _ = O.render(vol, tf, st, cam, "shadow", step)
+        errs.append(np.abs(full[..., :3] - limit).max())
+    assert errs[-1] < 5e-6
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e0 / e1 > 3.0, errs
+
+
+# ------------------------------------------------------------------ P7
+
+def test_p7_stack_lookup_converges_to_dense_light_march():
+    """Transmittance from the stack vs exp(-integral of sigma) marched toward the light.
+
+    With the midpoint slab rule, faces at the layer boundaries and bilinear
+    texels, the error is second order in the slab and texel size; a half-slab
+    or half-texel misregistration, an exclusive layer or nearest-layer lookup
+    would each leave a first-order error."""
+    N = 16
+    g = (np.arange(N) + 0.5) / N
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    field = np.exp(-(((X - 0.45) ** 2 + (Y - 0.55) ** 2 + (Z - 0.5) ** 2) / (2 * 0.18 ** 2)))
+    raw = (0.6 * field).astype(np.float32)
+    vol = O.Volume(raw, scale=1.0)
+    tab = np.zeros((256, 4))
+    tab[:, 3] = 0.25 * np.linspace(0, 1, 256)        # smooth, kink-free alpha in value
+    tf = O.TF(tab)
+    light = np.array([0.4, -0.3, 0.85])
+    L = light / np.linalg.norm(light)
+    rng = np.random.default_rng(7)
+    pts = rng.uniform(0.3, 0.7, size=(40, 3))
+
+    def dense(p):
+        # distance back to the cube along -L
+        s_max = min(((0.0 - p[a]) / -L[a]) if -L[a] < 0 else ((1.0 - p[a]) / -L[a]) for a in range(3))
+        M = 4000
+        ds = s_max / M
+        tau = 0.0
+        for m in range(M):
+            q = p - (m + 0.5) * ds * L
+            a = O.tf_lookup(tf, O.volume_sample(vol, q))[3]
+            tau += -math.log(1 - a) * N * ds
+        return math.exp(-tau)
+
+    ref = np.array([dense(p) for p in pts])
+    errs = []
+    for n in [12, 24, 48, 96]:
+        st = O.Stack(vol, tf, light, n, n)
+        got = np.array([st.lookup(p) for p in pts])
+        errs.append(np.abs(got - ref).max())
+    assert errs[-1] < 1.2e-3
+    # convergence order ~2 (ratio ~4 per halving); first order would give ~2
+    assert errs[-2] / errs[-1] > 3.0 and errs[-3] / errs[-2] > 3.0, errs
+
+
+# ------------------------------------------------------------------ P8
+
+def test_p8_vanishing_shell_equals_shadow():
+    raw = W.sphere_u8(16, radius=6, density=180, noise=20, seed=3)
+    vol, tf = O.Volume(raw), O.TF(W.tf_ramp())
+    st = O.Stack(vol, tf, [1, 1, -1], 8, 16)
+    cam = W.camera_orbit(12, 12, 0.4, 0.3)
+    a, _, _, _ = O.render(vol, tf, st, cam, "shadow", 0.5)
+    b, _, _, _ = O.render(vol, tf, st, cam, "shell", 0.5, {"shell_h_vox": 1e-9})
+    assert np.abs(a - b).max() < 1e-8
+    # a constant stack (no attenuation anywhere) gives A = 1: "none" equals every mode
+    empty_tf = O.TF(np.zeros((256, 4)))
+    st1 = O.Stack(vol, empty_tf, [1, 1, -1], 8, 16)
+    ref, _, _, _ = O.render(vol, tf, None, cam, "none", 0.5)
+    for m in MODES:
+        mm, extra = _mode(m)
+        img, _, _, _ = O.render(vol, tf, st1, cam, mm, 0.5, extra)
+        assert np.abs(img - ref).max() < 1e-15
+
+
+def test_p8_gather_weights_bounded_by_taps():
+    """Equal weights summing to one: min over taps <= A <= max over taps."""
+    raw = W.sphere_u8(16, radius=6, density=180, noise=20, seed=4)
+    vol, tf = O.Volume(raw), O.TF(W.tf_ramp())
+    st = O.Stack(vol, tf, [0.2, 1, -0.4], 12, 16)
+    rng = np.random.default_rng(8)
+    for _ in range(100):
+        p = rng.uniform(0.2, 0.8, 3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        A = st.coefficient("shell", p, d)
+        h = 1.0 / 16
+        taps = [st.lookup(p + s * h * e) for e in np.eye(3) for s in (-1, 1)]
+        assert min(taps) - 1e-15 <= A <= max(taps) + 1e-15
+        assert A == pytest.approx(np.mean(taps), abs=1e-15)
+        assert 0.0 <= st.coefficient("cone", p, d) <= 1.0
+
+
+# ------------------------------------------------------------------ P9
+
+@pytest.mark.parametrize("mode", MODES)
+def test_p9_invariants_small_workload(mode):
+    w = W.WORKLOADS["small"]
+    raw = w.volume()
+    vol, tf = O.Volume(raw), O.TF(w.tf())
+    st = O.Stack(vol, tf, w.lights()[0], w.n_slices, w.res)
+    S = st.export()
+    assert S.min() >= 0.0 and S.max() <= 1.0
+    assert np.all(np.diff(S, axis=0) <= 0.0)            # monotone along the light
+    cam = w.camera(W=64, H=64)
+    m, extra = _mode(mode)
+    full, term, nt, nf = O.render(vol, tf, st, cam, m, 0.5, extra)
+    for img in (full, term):
+        a = img[..., 3]
+        assert a.min() >= 0.0 and a.max() <= 1.0
+        assert np.all(img[..., :3] >= 0.0)
+        assert np.all(img[..., :3] <= a[..., None] + 1e-15)
+    assert np.abs(full - term).max() <= 2.0 ** -15
+    assert np.all(nt <= nf)
