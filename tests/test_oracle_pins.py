@@ -384,3 +384,49 @@ def test_p9_invariants_small_workload(mode):
         assert np.all(img[..., :3] <= a[..., None] + 1e-15)
     assert np.abs(full - term).max() <= 2.0 ** -15
     assert np.all(nt <= nf)
+
+
+# ------------------------------------------------------------------ cone geometry (section 3.2.3, Eq. 11)
+
+def _half_space_stack(n=16, res=16):
+    """Light along +z; opaque for z >= 1/2: the stack is exactly 1 up to depth 1/2."""
+    N = 16
+    raw = np.zeros((N, N, N), np.uint8)
+    raw[8:] = 255
+    tab = np.zeros((256, 4))
+    tab[:, 3] = np.linspace(0, 1, 256)
+    return O.Stack(O.Volume(raw), O.TF(tab), [0, 0, 1], n, res)
+
+
+@pytest.mark.parametrize("grid", [0, 5])
+def test_cone_opens_toward_the_light(grid):
+    st = _half_space_stack()
+    opts = {"cone_grid": grid}
+    d = np.array([1.0, 0.3, 0.2]) / np.linalg.norm([1.0, 0.3, 0.2])
+    # lit side, within two slabs of the shadowing layer: every tap toward the light is lit
+    assert st.coefficient("cone", [0.5, 0.5, 0.45], d, opts) == 1.0
+    # the direct lookup there is lit too, a point beyond the layer is dark
+    assert st.lookup([0.5, 0.5, 0.45]) == 1.0
+    assert st.coefficient("cone", [0.5, 0.5, 0.9], d, opts) < 1e-6
+
+
+@pytest.mark.parametrize("grid", [0, 5])
+def test_cone_taps_invariant_under_quarter_turn_of_view(grid):
+    """Four ring angles (and the square lattice) map onto themselves when the
+    view turns by 90 degrees about L, so A must not change; a gather that
+    spread along B only would."""
+    N = 16
+    raw = np.zeros((N, N, N), np.uint8)
+    raw[2:14, 2:14, 10:14] = 255      # opaque wall, x in [10,14) voxels: the stack varies along x
+    tab = np.zeros((256, 4))
+    tab[:, 3] = np.linspace(0, 0.5, 256)
+    st = O.Stack(O.Volume(raw), O.TF(tab), [0, 0, 1], 16, 32)
+    opts = {"cone_grid": grid}
+    p = [0.58, 0.5, 0.7]
+    a_x = st.coefficient("cone", p, [-1.0, 0.0, 0.0], opts)   # B = +x
+    a_y = st.coefficient("cone", p, [0.0, -1.0, 0.0], opts)   # B = +y
+    a_xm = st.coefficient("cone", p, [1.0, 0.0, 0.0], opts)   # B = -x
+    assert a_x == pytest.approx(a_y, abs=1e-14) and a_x == pytest.approx(a_xm, abs=1e-14)
+    assert 0.0 < a_x < 1.0
+    # the ring radius is c_m tan(phi): a narrower cone reads a different neighbourhood
+    assert st.coefficient("cone", p, [-1.0, 0.0, 0.0], {"cone_grid": grid, "cone_tan": 0.2}) != pytest.approx(a_x)
