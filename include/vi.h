@@ -1,0 +1,209 @@
+/*
+ * vi.h -- C ABI of libvi: slice-based ray-casting volume illumination on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: D. Luo, "Interactive volume illumination of slice-based ray
+ * casting" (arXiv 2008.06134).  Two passes:
+ *   1. vi_build_attenuation -- the light-space illumination attenuation
+ *      buffer (section 3.2.1, Alg. 1): the volume is cut into n slabs
+ *      perpendicular to the light between the minimum and maximum light
+ *      distances of the unit cube (Eq. 8); opacity is composited slab by
+ *      slab (Eq. 4 applied to opacity) and the running transmittance after
+ *      every slab is stored as one res x res layer.
+ *   2. vi_render -- single-pass ray casting from the camera (section 4):
+ *      per sample a trilinear volume fetch, a transfer-function lookup,
+ *      the illumination coefficient gathered from the stack (section 3:
+ *      direct shadow; section 3.2.3: shell or cone distribution; slice
+ *      index by Eq. 9, slice UV by Eq. 10), emission weighted by that
+ *      coefficient (Eq. 7) and front-to-back compositing (Eq. 3) with
+ *      early ray termination.
+ *
+ * Geometry conventions (the paper leaves these open; the library fixes):
+ *   - the volume fills the unit cube [0,1]^3; voxel (x,y,z) is centred at
+ *     ((x+1/2)/N, (y+1/2)/N, (z+1/2)/N); storage raw[z][y][x], x fastest;
+ *     cubic volumes only (N^3);
+ *   - sampling is trilinear with clamp-to-edge; value = clamp(raw*scale,0,1)
+ *     per voxel before interpolation;
+ *   - the transfer function holds K RGBA float entries (non-premultiplied
+ *     colour, alpha per one voxel of path length) looked up linearly at
+ *     x = value*(K-1); a segment of length l has opacity 1-(1-a)^(l*N)
+ *     (the extinction form of Eq. 6);
+ *   - light_dir is the direction the light travels; slab k spans
+ *     [dmin + k ds, dmin + (k+1) ds] along it and is sampled at its middle;
+ *     layer k holds the transmittance after slab k;
+ *   - the light projection is orthographic over the square of half-width
+ *     sqrt(3)/2 about the cube centre in the (U,V) plane, V = L x U, U from
+ *     the coordinate axis least aligned with L;
+ *   - a stack lookup interpolates linearly in depth between layer faces
+ *     (index q of Eq. 9 lies between faces floor(q) and ceil(q); face f
+ *     holds layer f-1, face 0 is fully transmitting) and bilinearly inside
+ *     a layer; outside the texel grid the stack transmits fully;
+ *   - rays: pixel centres, y = 0 on top; segments of step_vox/N from the
+ *     cube entry with a shorter last segment, sampled at their middles;
+ *     termination once 1 - alpha_dst <= term_eps; premultiplied RGBA out,
+ *     background composited last.
+ *
+ * Memory: every large buffer (volume, transfer function, stack, image,
+ * sample counter) is a DEVICE pointer owned by the caller; the library
+ * allocates nothing for vi_build_attenuation / vi_render.  All work is
+ * enqueued asynchronously on `stream` (a hipStream_t; NULL = the null
+ * stream); the call returns after the launch.  Buffers must stay valid
+ * until that work completes.
+ *
+ * Errors: every int-returning call returns VI_OK (0) or a negative code;
+ * nothing throws across the ABI.  vi_last_error() returns a message for
+ * the calling thread's last failure.  Launch failures are reported as
+ * VI_E_DEVICE with the HIP error text in the message.
+ */
+#ifndef VI_H
+#define VI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VI_OK 0
+#define VI_E_INVALID_ARG (-1)
+#define VI_E_UNSUPPORTED (-2)
+#define VI_E_NO_MEMORY (-3)
+#define VI_E_DEVICE (-4)
+#define VI_E_BUSY (-5)
+#define VI_E_CANCELLED (-6)
+
+typedef void* vi_stream_t; /* a hipStream_t */
+
+typedef enum {
+    VI_U8 = 0,   /* volume: unsigned 8-bit                              */
+    VI_U16 = 1,  /* volume: unsigned 16-bit                             */
+    VI_F16 = 2,  /* volume: IEEE half                                   */
+    VI_F32 = 3,  /* volume: float; stack: float transmittance           */
+    VI_BF16 = 4  /* stack: bfloat16 optical depth (precision form)      */
+} vi_dtype;
+
+typedef enum {
+    VI_MODE_NONE = 0,   /* coefficient 1: unlit emission-absorption        */
+    VI_MODE_SHADOW = 1, /* transmittance at the sample itself (section 3)  */
+    VI_MODE_SHELL = 2,  /* shell distribution (section 3.2.3)              */
+    VI_MODE_CONE = 3    /* cone distribution (section 3.2.3, Eq. 11)       */
+} vi_mode;
+
+typedef enum { VI_CAM_ORTHO = 0, VI_CAM_PERSP = 1 } vi_camera_kind;
+
+/* A cubic volume in device memory, raw[z][y][x].  `scale` maps raw values
+ * to [0,1] (u8: 1/255, u16 12-bit data: 1/4095, f16/f32 normalised: 1). */
+typedef struct {
+    const void* data;
+    int dtype; /* VI_U8, VI_U16, VI_F16 or VI_F32 */
+    int n;     /* edge length N >= 2; N^3 * element size < 4 GiB */
+    float scale;
+} vi_volume;
+
+/* Transfer function: `n_entries` x 4 floats (r,g,b,a) in device memory,
+ * 2 <= n_entries <= 1024. */
+typedef struct {
+    const float* rgba;
+    int n_entries;
+} vi_tf;
+
+/* Attenuation stack descriptor, filled by vi_build_attenuation (or by
+ * vi_light_frame for the geometry alone).  `data` points at the caller's
+ * buffer of vi_slices_bytes(n, res, dtype) bytes, layout [k][j][i]: layer
+ * k, texel row j (along V), column i (along U).  F32 stores transmittance
+ * T_k; BF16 stores optical depth tau_k with T_k = exp(-tau_k).
+ * Geometry is kept in double as computed on the host (Eq. 8). */
+typedef struct {
+    void* data;
+    int dtype;          /* VI_F32 or VI_BF16 */
+    int n, res;         /* slabs, texels per side */
+    double L[3];        /* unit propagation direction */
+    double U[3], V[3];  /* light-plane basis */
+    double c[3];        /* cube centre */
+    double dmin, dmax;  /* Eq. 8 */
+    double ds;          /* slab thickness (dmax - dmin) / n */
+    double R;           /* half-width of the light square, sqrt(3)/2 */
+    int vol_n;          /* edge of the volume it was built from */
+    uint64_t tag;       /* identity of (volume, transfer function); 0 = unchecked */
+} vi_slices;
+
+/* Camera: orthographic (view along target-eye, half image height
+ * ortho_half_h in world units) or pinhole (full vertical field of view
+ * fovy_deg).  World = the unit-cube frame of the volume. */
+typedef struct {
+    int kind; /* VI_CAM_ORTHO or VI_CAM_PERSP */
+    double eye[3], target[3], up[3];
+    double fovy_deg;
+    double ortho_half_h;
+    int width, height; /* 1 .. 16384 each */
+} vi_camera;
+
+/* Render options; vi_default_render_opts fills the defaults shown. */
+typedef struct {
+    float ambient;      /* 0: shade = ambient + (1-ambient) * A            */
+    float light_rgb[3]; /* (1,1,1)                                          */
+    float bg[4];        /* (0,0,0,0), premultiplied, composited last       */
+    float term_eps;     /* 2^-15: stop once 1 - alpha_dst <= term_eps       */
+    int shell_count;    /* 1: cuboid shells, 6 taps each                    */
+    float shell_h_vox;  /* 1: shell r samples at +-(r+1)*h voxels along x,y,z */
+    int cone_rings;     /* 2: rings at m*ds toward the light, m = 1..rings  */
+    int cone_angles;    /* 4: taps per ring, angles 2*pi*q/angles           */
+    int cone_grid;      /* 0: ring form; G in 1..7: G x G lattice one slab toward the light */
+    float cone_tan;     /* 1: ring radius m*ds*cone_tan; lattice pitch ds*cone_tan/2 */
+} vi_render_opts;
+
+/* Library version string. */
+const char* vi_version(void);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* vi_last_error(void);
+
+/* Fill `o` with the defaults listed above.  Returns VI_E_INVALID_ARG on NULL. */
+int vi_default_render_opts(vi_render_opts* o);
+
+/* Bytes of a stack buffer: n * res * res * (4 for VI_F32, 2 for VI_BF16);
+ * 0 for invalid arguments. */
+size_t vi_slices_bytes(int n_slices, int slice_res, int slice_dtype);
+
+/* Host only: compute the light frame of Eq. 8 and the light projection
+ * for `light_dir` (need not be unit length; finite, non-zero) and fill
+ * the geometry fields of `out` (data = NULL, tag = 0).
+ * 1 <= n_slices <= 4096, 1 <= slice_res <= 8192. */
+int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int slice_dtype, vi_slices* out);
+
+/* Build the attenuation stack (section 3.2.1, Alg. 1) for light direction
+ * `light_dir` into `d_slices` (device, vi_slices_bytes bytes, 4-byte
+ * aligned) and describe it in `out_desc` (host).  One kernel launch on
+ * `stream`.  slice_dtype: VI_F32 (transmittance, product of per-slab
+ * (1-alpha)) or VI_BF16 (optical depth: the per-slab extinction summed in
+ * float and rounded to bfloat16 per layer; each slab adds at most 64).
+ * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes or a degenerate
+ * light; VI_E_UNSUPPORTED for dtypes or sizes outside the limits above or a
+ * stack of 4 GiB or more; VI_E_DEVICE if the launch fails. */
+int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n_slices,
+                         int slice_res, int slice_dtype, void* d_slices, vi_slices* out_desc,
+                         vi_stream_t stream);
+
+/* Ray-cast `cam` through the volume with the illumination coefficient
+ * `mode` gathered from `slices` (section 3.2.2 and 3.2.3) and write
+ * width*height premultiplied RGBA floats to `d_rgba` (device, 16-byte
+ * aligned, row-major, y = 0 on top).  step_vox > 0 is the ray step in
+ * voxels.  `opts` may be NULL (defaults).  `slices` may be NULL only for
+ * VI_MODE_NONE.  If `d_samples` (device) is non-NULL the number of
+ * segments composited (stopping at termination) is ADDED to it.
+ * Errors: VI_E_INVALID_ARG for NULL/misaligned pointers, bad sizes, a
+ * descriptor whose vol_n differs from the volume or whose non-zero tag
+ * names another (volume, transfer function); VI_E_UNSUPPORTED for dtypes
+ * outside the list; VI_E_DEVICE if the launch fails. */
+int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* slices, const vi_camera* cam, int mode,
+              float step_vox, const vi_render_opts* opts, float* d_rgba, unsigned long long* d_samples,
+              vi_stream_t stream);
+
+/* Identity tag vi_build_attenuation stores in vi_slices.tag for (vol, tf). */
+uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VI_H */

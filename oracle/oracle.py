@@ -76,6 +76,7 @@ def _load():
         lib = C.CDLL(_LIB)
         P = C.POINTER
         lib.vio_default_opts.argtypes = [P(_Opts)]
+        lib.vio_threads.restype = C.c_int
         lib.vio_light_frame.argtypes = [P(C.c_double), C.c_int, C.c_int, P(_Frame)]
         lib.vio_volume_sample.argtypes = [P(_Volume), P(C.c_double)]
         lib.vio_volume_sample.restype = C.c_double
@@ -111,6 +112,11 @@ def _dptr(a):
 
 def _vec(x):
     return (C.c_double * 3)(*[float(t) for t in x])
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().vio_threads())
 
 
 def default_opts() -> dict:

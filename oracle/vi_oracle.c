@@ -41,6 +41,15 @@ static void cross3(const double a[3], const double b[3], double r[3])
 }
 static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
 
+int vio_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void vio_default_opts(vio_opts* o)
 {
     /* Defaults of the readings: no ambient term and a white light (R16,

@@ -88,6 +88,7 @@ typedef struct {
  * full size touches only the columns it needs. */
 typedef struct vio_stack vio_stack;
 
+int    vio_threads(void); /* OpenMP threads the oracle uses by default */
 void   vio_default_opts(vio_opts* o);
 int    vio_light_frame(const double l[3], int n, int res, vio_frame* f);
 double vio_volume_sample(const vio_volume* v, const double p[3]);

@@ -1,0 +1,362 @@
+// vi_api.hip -- host side of the libvi C ABI: validation, the light frame in
+// double (Eq. 8, light projection of Eq. 10), kernel parameter set-up and
+// launches.  No allocation, no synchronisation.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "vi_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_err() { g_err[0] = 0; }
+
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+void cross3(const double* a, const double* b, double* r)
+{
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+size_t elem_size(int dt)
+{
+    switch (dt) {
+    case VI_U8: return 1;
+    case VI_U16: case VI_F16: case VI_BF16: return 2;
+    case VI_F32: return 4;
+    default: return 0;
+    }
+}
+
+int check_volume(const vi_volume* v)
+{
+    if (!v || !v->data) return fail(VI_E_INVALID_ARG, "volume or its data pointer is NULL");
+    if (v->dtype != VI_U8 && v->dtype != VI_U16 && v->dtype != VI_F16 && v->dtype != VI_F32)
+        return fail(VI_E_UNSUPPORTED, "volume dtype %d not supported", v->dtype);
+    if (v->n < 2) return fail(VI_E_INVALID_ARG, "volume edge %d < 2", v->n);
+    const double bytes = (double)v->n * v->n * v->n * (double)elem_size(v->dtype);
+    if (bytes >= 4294967296.0) return fail(VI_E_UNSUPPORTED, "volume of %.0f bytes exceeds 4 GiB", bytes);
+    if (((uintptr_t)v->data) % elem_size(v->dtype)) return fail(VI_E_INVALID_ARG, "volume pointer misaligned");
+    if (!(v->scale > 0.0f) || !isfinite(v->scale)) return fail(VI_E_INVALID_ARG, "volume scale must be > 0");
+    return VI_OK;
+}
+
+int check_tf(const vi_tf* tf)
+{
+    if (!tf || !tf->rgba) return fail(VI_E_INVALID_ARG, "transfer function or its pointer is NULL");
+    if (tf->n_entries < 2 || tf->n_entries > vi::kMaxTF)
+        return fail(VI_E_INVALID_ARG, "transfer function needs 2..%d entries, got %d", vi::kMaxTF, tf->n_entries);
+    if (((uintptr_t)tf->rgba) % 4) return fail(VI_E_INVALID_ARG, "transfer function pointer misaligned");
+    return VI_OK;
+}
+
+// Eq. 8 and the light projection: geometry of the stack in double.
+int fill_frame(const double l[3], int n, int res, int dt, vi_slices* f)
+{
+    if (!l || !f) return fail(VI_E_INVALID_ARG, "NULL light direction or descriptor");
+    if (n < 1 || n > 4096) return fail(VI_E_INVALID_ARG, "n_slices %d outside 1..4096", n);
+    if (res < 1 || res > 8192) return fail(VI_E_INVALID_ARG, "slice_res %d outside 1..8192", res);
+    if (dt != VI_F32 && dt != VI_BF16) return fail(VI_E_UNSUPPORTED, "slice dtype %d not supported", dt);
+    if (!isfinite(l[0]) || !isfinite(l[1]) || !isfinite(l[2]))
+        return fail(VI_E_INVALID_ARG, "light direction is not finite");
+    const double nl = sqrt(dot3(l, l));
+    if (!(nl > 0.0) || !isfinite(nl)) return fail(VI_E_INVALID_ARG, "light direction is zero");
+    memset(f, 0, sizeof *f);
+    for (int a = 0; a < 3; ++a) f->L[a] = l[a] / nl;
+    f->c[0] = f->c[1] = f->c[2] = 0.5;
+    // extreme distances along L over the cube's vertices: the vertex picks
+    // 0 or 1 per axis by the sign of L
+    f->dmin = f->dmax = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (f->L[a] < 0.0) f->dmin += f->L[a];
+        else f->dmax += f->L[a];
+    }
+    f->ds = (f->dmax - f->dmin) / n;
+    int js = 0;
+    for (int a = 1; a < 3; ++a)
+        if (fabs(f->L[a]) < fabs(f->L[js])) js = a;
+    double u[3] = {-f->L[js] * f->L[0], -f->L[js] * f->L[1], -f->L[js] * f->L[2]};
+    u[js] += 1.0;
+    const double nu = sqrt(dot3(u, u));
+    for (int a = 0; a < 3; ++a) f->U[a] = u[a] / nu;
+    cross3(f->L, f->U, f->V);
+    f->R = sqrt(3.0) / 2.0;
+    f->n = n;
+    f->res = res;
+    f->dtype = dt;
+    return VI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vi_version(void) { return "libvi 0.1 gfx950"; }
+
+const char* vi_last_error(void) { return g_err; }
+
+int vi_default_render_opts(vi_render_opts* o)
+{
+    if (!o) return fail(VI_E_INVALID_ARG, "NULL options");
+    o->ambient = 0.0f;
+    o->light_rgb[0] = o->light_rgb[1] = o->light_rgb[2] = 1.0f;
+    o->bg[0] = o->bg[1] = o->bg[2] = o->bg[3] = 0.0f;
+    o->term_eps = ldexpf(1.0f, -15);
+    o->shell_count = 1;
+    o->shell_h_vox = 1.0f;
+    o->cone_rings = 2;
+    o->cone_angles = 4;
+    o->cone_grid = 0;
+    o->cone_tan = 1.0f;
+    return VI_OK;
+}
+
+size_t vi_slices_bytes(int n, int res, int dt)
+{
+    if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16)) return 0;
+    return (size_t)n * (size_t)res * (size_t)res * elem_size(dt);
+}
+
+uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf)
+{
+    // FNV-1a over the identity of the inputs (pointers, sizes, dtype, scale)
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t x) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (x >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    if (vol) {
+        mix((uint64_t)(uintptr_t)vol->data);
+        mix((uint64_t)vol->n);
+        mix((uint64_t)vol->dtype);
+        uint32_t sb;
+        memcpy(&sb, &vol->scale, 4);
+        mix(sb);
+    }
+    if (tf) {
+        mix((uint64_t)(uintptr_t)tf->rgba);
+        mix((uint64_t)tf->n_entries);
+    }
+    return h ? h : 1;
+}
+
+int vi_light_frame(const double light_dir[3], int n, int res, int dt, vi_slices* out)
+{
+    clear_err();
+    return fill_frame(light_dir, n, res, dt, out);
+}
+
+int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n, int res,
+                         int dt, void* d_slices, vi_slices* out_desc, vi_stream_t stream)
+{
+    clear_err();
+    int rc;
+    if ((rc = check_volume(vol)) != VI_OK) return rc;
+    if ((rc = check_tf(tf)) != VI_OK) return rc;
+    if (!d_slices) return fail(VI_E_INVALID_ARG, "NULL stack buffer");
+    if (!out_desc) return fail(VI_E_INVALID_ARG, "NULL stack descriptor");
+    vi_slices f;
+    if ((rc = fill_frame(light_dir, n, res, dt, &f)) != VI_OK) return rc;
+    if (((uintptr_t)d_slices) % 4) return fail(VI_E_INVALID_ARG, "stack buffer must be 4-byte aligned");
+    if ((double)vi_slices_bytes(n, res, dt) >= 4294967296.0)
+        return fail(VI_E_UNSUPPORTED, "stack of %zu bytes exceeds 4 GiB", vi_slices_bytes(n, res, dt));
+
+    vi::BuildParams p;
+    memset(&p, 0, sizeof p);
+    p.vol = vol->data;
+    p.vol_dtype = vol->dtype;
+    p.N = vol->n;
+    p.M = vol->n / 2;
+    p.scale = vol->scale;
+    p.tf = tf->rgba;
+    p.K = tf->n_entries;
+    p.out = d_slices;
+    p.out_dtype = dt;
+    p.n = n;
+    p.res = res;
+    const double N = vol->n, texel = 2.0 * f.R / res, u0 = -f.R + 0.5 * texel;
+    const double d0 = f.dmin + 0.5 * f.ds, Lc = dot3(f.L, f.c);
+    for (int a = 0; a < 3; ++a) {
+        const double p0 = f.c[a] + u0 * f.U[a] + u0 * f.V[a] + (d0 - Lc) * f.L[a];
+        p.B0[a] = p0 * N - 0.5 - p.M;
+        p.BU[a] = f.U[a] * texel * N;
+        p.BV[a] = f.V[a] * texel * N;
+        p.AL[a] = (float)(f.L[a] * f.ds * N);
+    }
+    p.e = (float)(f.ds * N);
+    p.lo = (float)(-0.5 - p.M);
+    p.hi = (float)(N - 0.5 - p.M);
+    hipError_t e = vi::launch_build(p, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VI_E_DEVICE, "build launch failed: %s", hipGetErrorString(e));
+    f.data = d_slices;
+    f.vol_n = vol->n;
+    f.tag = vi_tag(vol, tf);
+    *out_desc = f;
+    return VI_OK;
+}
+
+int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const vi_camera* cam, int mode,
+              float step_vox, const vi_render_opts* opts, float* d_rgba, unsigned long long* d_samples,
+              vi_stream_t stream)
+{
+    clear_err();
+    int rc;
+    if ((rc = check_volume(vol)) != VI_OK) return rc;
+    if ((rc = check_tf(tf)) != VI_OK) return rc;
+    if (mode < VI_MODE_NONE || mode > VI_MODE_CONE) return fail(VI_E_UNSUPPORTED, "mode %d not supported", mode);
+    if (!cam) return fail(VI_E_INVALID_ARG, "NULL camera");
+    if (!d_rgba) return fail(VI_E_INVALID_ARG, "NULL output image");
+    if (((uintptr_t)d_rgba) % 16) return fail(VI_E_INVALID_ARG, "output image must be 16-byte aligned");
+    if (d_samples && ((uintptr_t)d_samples) % 8) return fail(VI_E_INVALID_ARG, "sample counter misaligned");
+    if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
+        return fail(VI_E_INVALID_ARG, "image size %dx%d outside 1..16384", cam->width, cam->height);
+    if (cam->kind != VI_CAM_ORTHO && cam->kind != VI_CAM_PERSP)
+        return fail(VI_E_INVALID_ARG, "camera kind %d", cam->kind);
+    if (!(step_vox > 0.0f) || !isfinite(step_vox)) return fail(VI_E_INVALID_ARG, "step_vox must be > 0");
+    vi_render_opts o;
+    if (opts) o = *opts;
+    else vi_default_render_opts(&o);
+    if (!(o.term_eps >= 0.0f) || !(o.ambient >= 0.0f && o.ambient <= 1.0f))
+        return fail(VI_E_INVALID_ARG, "term_eps must be >= 0 and ambient in [0,1]");
+    if (mode != VI_MODE_NONE) {
+        if (!sl || !sl->data) return fail(VI_E_INVALID_ARG, "mode %d needs a stack", mode);
+        if (sl->dtype != VI_F32 && sl->dtype != VI_BF16) return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);
+        if (sl->n < 1 || sl->res < 1) return fail(VI_E_INVALID_ARG, "stack descriptor has no size");
+        if (sl->vol_n != vol->n)
+            return fail(VI_E_INVALID_ARG, "stack built for a volume of edge %d, rendering %d", sl->vol_n, vol->n);
+        if (sl->tag != 0 && sl->tag != vi_tag(vol, tf))
+            return fail(VI_E_INVALID_ARG, "stack was built from another volume or transfer function");
+        if ((double)vi_slices_bytes(sl->n, sl->res, sl->dtype) >= 4294967296.0)
+            return fail(VI_E_UNSUPPORTED, "stack exceeds 4 GiB");
+    }
+
+    vi::RenderFrame F;
+    memset(&F, 0, sizeof F);
+    F.vol = vol->data;
+    F.vol_dtype = vol->dtype;
+    F.N = vol->n;
+    F.M = vol->n / 2;
+    F.scale = vol->scale;
+    F.tf = tf->rgba;
+    F.K = tf->n_entries;
+    F.mode = mode;
+    if (mode != VI_MODE_NONE) {
+        F.stack = sl->data;
+        F.stack_dtype = sl->dtype;
+        F.n = sl->n;
+        F.res = sl->res;
+        F.Mz = sl->n / 2;
+        F.Mr = sl->res / 2;
+        const double span = sl->dmax - sl->dmin, sc = sl->res / (2.0 * sl->R);
+        for (int a = 0; a < 3; ++a) {
+            F.Lq[a] = sl->n * sl->L[a] / span;
+            F.Ux[a] = sl->U[a] * sc;
+            F.Vy[a] = sl->V[a] * sc;
+            F.L[a] = sl->L[a];
+            F.U[a] = sl->U[a];
+            F.V[a] = sl->V[a];
+        }
+        F.Lq0 = -sl->n * sl->dmin / span - 1.0;  // index of Eq. 9 minus one
+        F.Ux0 = (-dot3(sl->U, sl->c) + sl->R) * sc - 0.5;
+        F.Vy0 = (-dot3(sl->V, sl->c) + sl->R) * sc - 0.5;
+        F.ds = sl->ds;
+    }
+    // camera basis
+    double fwd[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1], cam->target[2] - cam->eye[2]};
+    const double nf = sqrt(dot3(fwd, fwd));
+    if (!(nf > 0.0) || !isfinite(nf)) return fail(VI_E_INVALID_ARG, "camera eye equals target");
+    for (int a = 0; a < 3; ++a) fwd[a] /= nf;
+    double right[3], up2[3];
+    cross3(fwd, cam->up, right);
+    const double nr = sqrt(dot3(right, right));
+    if (!(nr > 1e-12) || !isfinite(nr)) return fail(VI_E_INVALID_ARG, "camera up is parallel to the view");
+    for (int a = 0; a < 3; ++a) right[a] /= nr;
+    cross3(right, fwd, up2);
+    F.cam_kind = cam->kind;
+    F.width = cam->width;
+    F.height = cam->height;
+    for (int a = 0; a < 3; ++a) {
+        F.eye[a] = cam->eye[a];
+        F.fwd[a] = fwd[a];
+        F.right[a] = right[a];
+        F.up[a] = up2[a];
+    }
+    const double aspect = (double)cam->width / cam->height;
+    if (cam->kind == VI_CAM_PERSP) {
+        if (!(cam->fovy_deg > 0.0 && cam->fovy_deg < 180.0)) return fail(VI_E_INVALID_ARG, "fovy outside (0,180)");
+        const double th = tan(0.5 * cam->fovy_deg * M_PI / 180.0);
+        F.tx = th * aspect;
+        F.ty = th;
+    } else {
+        if (!(cam->ortho_half_h > 0.0)) return fail(VI_E_INVALID_ARG, "ortho_half_h must be > 0");
+        F.tx = cam->ortho_half_h * aspect;
+        F.ty = cam->ortho_half_h;
+    }
+    F.dt = (double)step_vox / vol->n;
+    F.N_f = (float)vol->n;
+    F.ambient = o.ambient;
+    for (int c = 0; c < 3; ++c) F.light[c] = o.light_rgb[c];
+    for (int c = 0; c < 4; ++c) F.bg[c] = o.bg[c];
+    F.term_eps = o.term_eps;
+
+    if (mode == VI_MODE_SHELL) {
+        if (o.shell_count < 1 || 6 * o.shell_count > vi::kMaxTaps)
+            return fail(VI_E_INVALID_ARG, "shell_count must be 1..%d", vi::kMaxTaps / 6);
+        if (!(o.shell_h_vox >= 0.0f)) return fail(VI_E_INVALID_ARG, "shell_h_vox must be >= 0");
+        const double h = (double)o.shell_h_vox / vol->n;
+        int t = 0;
+        for (int r = 1; r <= o.shell_count; ++r)
+            for (int a = 0; a < 3; ++a)
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    const double off = sg * r * h;
+                    F.tz[t] = (float)(off * F.Lq[a]);
+                    F.tx_[t] = (float)(off * F.Ux[a]);
+                    F.ty_[t] = (float)(off * F.Vy[a]);
+                    ++t;
+                }
+        F.ntaps = t;
+        F.tap_w = 1.0f / t;
+    } else if (mode == VI_MODE_CONE) {
+        if (!(o.cone_tan >= 0.0f) || !isfinite(o.cone_tan)) return fail(VI_E_INVALID_ARG, "cone_tan must be >= 0");
+        F.cone_tan = o.cone_tan;
+        F.cone_grid = o.cone_grid;
+        if (o.cone_grid > 0) {
+            if (o.cone_grid > 7) return fail(VI_E_INVALID_ARG, "cone_grid must be 0..7");
+            F.ntaps = o.cone_grid * o.cone_grid;
+        } else {
+            if (o.cone_rings < 1 || o.cone_rings > 8 || o.cone_angles < 1 || o.cone_angles > 16)
+                return fail(VI_E_INVALID_ARG, "cone needs 1..8 rings and 1..16 angles");
+            F.cone_rings = o.cone_rings;
+            F.cone_angles = o.cone_angles;
+            for (int q = 0; q < o.cone_angles; ++q) {
+                const double th = 2.0 * M_PI * q / o.cone_angles;
+                F.cone_cos[q] = (float)cos(th);
+                F.cone_sin[q] = (float)sin(th);
+            }
+            F.ntaps = o.cone_rings * o.cone_angles;
+        }
+        F.tap_w = 1.0f / F.ntaps;
+    }
+    F.out = (float4*)d_rgba;
+    F.samples = d_samples;
+    hipError_t e = vi::launch_render(F, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VI_E_DEVICE, "render launch failed: %s", hipGetErrorString(e));
+    return VI_OK;
+}
+
+}  // extern "C"

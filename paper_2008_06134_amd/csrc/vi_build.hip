@@ -1,0 +1,99 @@
+// vi_build.hip -- light-space attenuation build (section 3.2.1, Alg. 1).
+//
+// One lane owns one texel column of the light square and scans the n slabs
+// from the light (Eq. 8 ordering): per slab it samples the volume at the slab
+// midpoint, looks up the transfer-function opacity, corrects it to the slab
+// thickness (extinction form, Eq. 6) and multiplies the running
+// transmittance by (1 - alpha) -- Eq. 4 applied to opacity.  Every layer is
+// written as soon as it is known, so the pass is a single streaming sweep:
+// the volume is read through the caches and the stack is written once,
+// coalesced along the texel row.
+//
+// Workgroup = 16 x 16 texels (4 waves of 16 x 4); the alpha column of the
+// transfer function sits in LDS.
+#include "vi_device.h"
+#include "vi_internal.h"
+
+namespace vi {
+
+constexpr int kBuildTile = 16;
+
+template <typename VT, int OUT_DTYPE>
+__global__ __launch_bounds__(256) void build_kernel(BuildParams P)
+{
+    extern __shared__ float s_alpha[];  // K entries
+    for (int t = threadIdx.x; t < P.K; t += blockDim.x) s_alpha[t] = P.tf[4 * t + 3];
+    __syncthreads();
+
+    const uint32_t tiles_x = (P.res + kBuildTile - 1) / kBuildTile;
+    const uint32_t tiles_y = tiles_x;
+    const uint32_t tile = xcd_swizzle(blockIdx.x, tiles_x * tiles_y);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = (int)(tile % tiles_x) * kBuildTile + (lane & 15);
+    const int j = (int)(tile / tiles_x) * kBuildTile + wave * 4 + (lane >> 4);
+    if (i >= P.res || j >= P.res) return;
+
+    // column base (slab 0 midpoint) in offset-voxel coordinates, in double
+    const float hx0 = (float)(P.B0[0] + i * P.BU[0] + j * P.BV[0]);
+    const float hy0 = (float)(P.B0[1] + i * P.BU[1] + j * P.BV[1]);
+    const float hz0 = (float)(P.B0[2] + i * P.BU[2] + j * P.BV[2]);
+
+    const VT* __restrict__ vol = (const VT*)P.vol;
+    const float Km1 = (float)(P.K - 1);
+    const size_t layer = (size_t)P.res * (size_t)P.res;
+    const size_t col = (size_t)j * P.res + i;
+    float T = 1.0f;     // transmittance (F32 form)
+    float tau = 0.0f;   // optical depth (BF16 form)
+    const float ln2 = 0.69314718055994531f;
+
+    for (int k = 0; k < P.n; ++k) {
+        const float kf = (float)k;
+        const float hx = fmaf(kf, P.AL[0], hx0);
+        const float hy = fmaf(kf, P.AL[1], hy0);
+        const float hz = fmaf(kf, P.AL[2], hz0);
+        // log2 of the slab's (1 - alpha)/e, 0 outside the cube (empty)
+        float l2 = 0.0f;
+        if (hx >= P.lo && hx <= P.hi && hy >= P.lo && hy <= P.hi && hz >= P.lo && hz <= P.hi) {
+            const float v = sample_volume<VT>(vol, P.N, P.M, P.scale, hx, hy, hz);
+            const float x = v * Km1;
+            const int e0 = min((int)x, P.K - 2);
+            const float w = x - (float)e0;
+            const float a = fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]);
+            l2 = fast_log2(fmaxf(1.0f - a, 0.0f));  // -inf for a = 1
+        }
+        if (OUT_DTYPE == VI_F32) {
+            // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
+            T *= fast_exp2(P.e * l2);
+            ((float*)P.out)[(size_t)k * layer + col] = T;
+        } else {
+            // sigma * ds = -e ln(1 - a), capped at 64 per slab
+            tau += fminf(-P.e * ln2 * l2, 64.0f);
+            ((uint16_t*)P.out)[(size_t)k * layer + col] = f32_to_bf16(tau);
+        }
+    }
+}
+
+template <typename VT>
+static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
+{
+    const uint32_t tiles = (uint32_t)((p.res + kBuildTile - 1) / kBuildTile);
+    dim3 grid(tiles * tiles), block(256);
+    const size_t lds = sizeof(float) * (size_t)p.K;
+    if (p.out_dtype == VI_F32)
+        hipLaunchKernelGGL((build_kernel<VT, VI_F32>), grid, block, lds, s, p);
+    else
+        hipLaunchKernelGGL((build_kernel<VT, VI_BF16>), grid, block, lds, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const BuildParams& p, hipStream_t s)
+{
+    switch (p.vol_dtype) {
+    case VI_U8: return launch_build_t<uint8_t>(p, s);
+    case VI_U16: return launch_build_t<uint16_t>(p, s);
+    case VI_F16: return launch_build_t<__half>(p, s);
+    default: return launch_build_t<float>(p, s);
+    }
+}
+
+}  // namespace vi

@@ -1,0 +1,87 @@
+// vi_internal.h -- shared host/device declarations of libvi (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vi.h"
+
+namespace vi {
+
+constexpr int kMaxTF = 1024;     // transfer-function entries staged in LDS
+constexpr int kMaxTaps = 49;     // largest gather (7 x 7 lattice)
+
+// ---------------------------------------------------------------------------
+// Build pass parameters.  Positions are carried in "offset voxel"
+// coordinates h = p*N - 1/2 - M, with M = floor(N/2) an integer, so that
+// floor/fraction of the voxel index g = h + M are exact and |h| <= ~0.9 N.
+// Column (i,j) at slab k sits at h = B(i,j) + k * AL, with B evaluated in
+// double on the device once per column.
+// ---------------------------------------------------------------------------
+struct BuildParams {
+    const void* vol;
+    int vol_dtype;
+    int N, M;
+    float scale;
+    const float* tf;   // K x 4
+    int K;
+    void* out;
+    int out_dtype;     // VI_F32 transmittance / VI_BF16 optical depth
+    int n, res;
+    double B0[3];      // h at (i,j,k) = (0,0,0)
+    double BU[3];      // d h / d i
+    double BV[3];      // d h / d j
+    float AL[3];       // d h / d k
+    float e;           // slab thickness in voxels: exponent of (1-a)
+    float lo, hi;      // cube in h coordinates: [-1/2 - M, N - 1/2 - M]
+};
+
+// ---------------------------------------------------------------------------
+// Render pass parameters (one frame).
+// ---------------------------------------------------------------------------
+struct RenderFrame {
+    // volume
+    const void* vol;
+    int vol_dtype;
+    int N, M;
+    float scale;
+    // transfer function
+    const float* tf;
+    int K;
+    // stack
+    const void* stack;
+    int stack_dtype;
+    int n, res;
+    int Mz, Mr;          // integer offsets of the light-grid coordinates
+    double Lq[3], Lq0;   // z = Lq . p + Lq0 - Mz       (Eq. 9 index minus one)
+    double Ux[3], Ux0;   // x = Ux . p + Ux0 - Mr       (Eq. 10 texel column)
+    double Vy[3], Vy0;   // y = Vy . p + Vy0 - Mr
+    double L[3], U[3], V[3];
+    double ds;
+    // camera
+    int cam_kind;
+    int width, height;
+    double eye[3], fwd[3], right[3], up[3];
+    double tx, ty;       // persp: tan(fovy/2)*W/H, tan(fovy/2); ortho: h*W/H, h
+    // march
+    int mode;
+    double dt;           // step in world units
+    float N_f;           // voxels per world unit (segment exponent scale)
+    float ambient, light[3], bg[4], term_eps;
+    // gather taps in light-grid units (shell: fixed; cone: per ray)
+    int ntaps;
+    float tap_w;
+    float tz[kMaxTaps], tx_[kMaxTaps], ty_[kMaxTaps];  // shell offsets
+    int cone_rings, cone_angles, cone_grid;
+    float cone_tan;
+    float cone_cos[16], cone_sin[16];
+    // output
+    float4* out;
+    unsigned long long* samples;
+};
+
+// launchers (vi_build.hip / vi_render.hip)
+hipError_t launch_build(const BuildParams& p, hipStream_t s);
+hipError_t launch_render(const RenderFrame& f, hipStream_t s);
+
+}  // namespace vi

@@ -1,0 +1,307 @@
+// vi_render.hip -- eye-space ray march with the slice-based illumination
+// coefficient (sections 3.2.2, 3.2.3 and 4).
+//
+// One lane marches one ray.  Per ray (double precision, once): the camera
+// ray, the slab test against the unit cube, the entry point in volume and
+// light-grid coordinates and the per-unit-length increments of both; for the
+// cone, the per-ray frame (B, L x B) in texel units.  Per segment (float):
+// position = entry + s * direction in offset coordinates (so the fraction of
+// every interpolation is taken on small magnitudes), trilinear fetch,
+// transfer function from LDS, extinction-corrected opacity, and -- only when
+// the opacity is non-zero -- the coefficient gather from the stack, then the
+// front-to-back update (Eq. 3) with the coefficient weighting the emission
+// (Eq. 7).  The lane leaves the loop when its ray exits or its remaining
+// transmittance drops to term_eps.
+//
+// Workgroup = 16 x 16 pixels, each wave an 8 x 8 pixel block so the rays of a
+// wave sample neighbouring voxels and texels.
+#include "vi_device.h"
+#include "vi_internal.h"
+
+namespace vi {
+
+// --------------------------------------------------------------------------
+// stack access
+// --------------------------------------------------------------------------
+template <int SDT>
+__device__ __forceinline__ float stack_texel(const void* __restrict__ S, uint32_t idx);
+
+template <>
+__device__ __forceinline__ float stack_texel<VI_F32>(const void* __restrict__ S, uint32_t idx)
+{
+    return ((const float*)S)[idx];
+}
+template <>
+__device__ __forceinline__ float stack_texel<VI_BF16>(const void* __restrict__ S, uint32_t idx)
+{
+    // optical depth -> transmittance per texel, before interpolation
+    const float log2e = 1.4426950408889634f;
+    return fast_exp2(-log2e * bf16_to_f32(((const uint16_t*)S)[idx]));
+}
+
+// Transmittance at light-grid offset coordinates (z, x, y): depth between
+// faces (layer z and z+1 in stack order, layer -1 = 1), bilinear in the
+// layer, fully transmitting outside the texel grid.
+template <int SDT>
+__device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, float x, float y)
+{
+    z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
+    const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
+    const float wz = z - fz, wx = x - fx, wy = y - fy;
+    const int k0 = (int)fz + F.Mz;
+    const int k1 = min(k0 + 1, F.n - 1);
+    const int i0 = (int)fx + F.Mr, j0 = (int)fy + F.Mr;
+    const int res = F.res;
+    const bool vi0 = (unsigned)i0 < (unsigned)res, vi1 = (unsigned)(i0 + 1) < (unsigned)res;
+    const bool vj0 = (unsigned)j0 < (unsigned)res, vj1 = (unsigned)(j0 + 1) < (unsigned)res;
+    const int ci0 = clampi(i0, 0, res - 1), ci1 = clampi(i0 + 1, 0, res - 1);
+    const int cj0 = clampi(j0, 0, res - 1), cj1 = clampi(j0 + 1, 0, res - 1);
+    const uint32_t ures = (uint32_t)res;
+
+    float t0 = 1.0f;
+    if (k0 >= 0) {
+        const uint32_t base = (uint32_t)k0 * ures;
+        const uint32_t r0 = (base + (uint32_t)cj0) * ures, r1 = (base + (uint32_t)cj1) * ures;
+        float a = stack_texel<SDT>(F.stack, r0 + ci0), b = stack_texel<SDT>(F.stack, r0 + ci1);
+        float c = stack_texel<SDT>(F.stack, r1 + ci0), d = stack_texel<SDT>(F.stack, r1 + ci1);
+        a = (vi0 && vj0) ? a : 1.0f;
+        b = (vi1 && vj0) ? b : 1.0f;
+        c = (vi0 && vj1) ? c : 1.0f;
+        d = (vi1 && vj1) ? d : 1.0f;
+        const float ab = fmaf(wx, b - a, a), cd = fmaf(wx, d - c, c);
+        t0 = fmaf(wy, cd - ab, ab);
+    }
+    float t1;
+    {
+        const uint32_t base = (uint32_t)k1 * ures;
+        const uint32_t r0 = (base + (uint32_t)cj0) * ures, r1 = (base + (uint32_t)cj1) * ures;
+        float a = stack_texel<SDT>(F.stack, r0 + ci0), b = stack_texel<SDT>(F.stack, r0 + ci1);
+        float c = stack_texel<SDT>(F.stack, r1 + ci0), d = stack_texel<SDT>(F.stack, r1 + ci1);
+        a = (vi0 && vj0) ? a : 1.0f;
+        b = (vi1 && vj0) ? b : 1.0f;
+        c = (vi0 && vj1) ? c : 1.0f;
+        d = (vi1 && vj1) ? d : 1.0f;
+        const float ab = fmaf(wx, b - a, a), cd = fmaf(wx, d - c, c);
+        t1 = fmaf(wy, cd - ab, ab);
+    }
+    return fmaf(wz, t1 - t0, t0);
+}
+
+// --------------------------------------------------------------------------
+// one ray
+// --------------------------------------------------------------------------
+struct ConeFrame {
+    float bx, by;  // B in texels per world unit (x, y)
+    float px, py;  // L x B in texels per world unit
+};
+
+template <int MODE, int SDT>
+__device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& cf, float z, float x, float y)
+{
+    if (MODE == VI_MODE_SHADOW) return stack_lookup<SDT>(F, z, x, y);
+    if (MODE == VI_MODE_SHELL) {
+        float s = 0.0f;
+        for (int t = 0; t < F.ntaps; ++t) s += stack_lookup<SDT>(F, z + F.tz[t], x + F.tx_[t], y + F.ty_[t]);
+        return s * F.tap_w;
+    }
+    // cone
+    float s = 0.0f;
+    if (F.cone_grid <= 0) {
+        for (int m = 1; m <= F.cone_rings; ++m) {
+            const float r = (float)m * (float)F.ds * F.cone_tan;
+            for (int q = 0; q < F.cone_angles; ++q) {
+                const float ca = F.cone_cos[q] * r, sa = F.cone_sin[q] * r;
+                s += stack_lookup<SDT>(F, z - (float)m, x + ca * cf.bx + sa * cf.px, y + ca * cf.by + sa * cf.py);
+            }
+        }
+    } else {
+        const int G = F.cone_grid;
+        const float rho = (float)F.ds * F.cone_tan * 0.5f, half = 0.5f * (float)(G - 1);
+        for (int ia = 0; ia < G; ++ia) {
+            const float a = ((float)ia - half) * rho;
+            for (int ib = 0; ib < G; ++ib) {
+                const float b = ((float)ib - half) * rho;
+                s += stack_lookup<SDT>(F, z - 1.0f, x + a * cf.bx + b * cf.px, y + a * cf.by + b * cf.py);
+            }
+        }
+    }
+    return s * F.tap_w;
+}
+
+template <typename VT, int MODE, int SDT>
+__device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf, int px, int py,
+                                             uint32_t& nsamp)
+{
+    // ---- camera ray (double)
+    const double xn = 2.0 * (px + 0.5) / F.width - 1.0;
+    const double yn = 1.0 - 2.0 * (py + 0.5) / F.height;
+    double o[3], d[3];
+    if (F.cam_kind == VI_CAM_PERSP) {
+        for (int a = 0; a < 3; ++a) {
+            o[a] = F.eye[a];
+            d[a] = F.fwd[a] + xn * F.tx * F.right[a] + yn * F.ty * F.up[a];
+        }
+        const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        for (int a = 0; a < 3; ++a) d[a] *= inv;
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            d[a] = F.fwd[a];
+            o[a] = F.eye[a] + xn * F.tx * F.right[a] + yn * F.ty * F.up[a];
+        }
+    }
+    // ---- slab test (double)
+    double tn = -1e300, tf = 1e300;
+    bool hit = true;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (o[a] < 0.0 || o[a] > 1.0) hit = false;
+            continue;
+        }
+        const double t1 = (0.0 - o[a]) / d[a], t2 = (1.0 - o[a]) / d[a];
+        tn = fmax(tn, fmin(t1, t2));
+        tf = fmin(tf, fmax(t1, t2));
+    }
+    const double ti = fmax(tn, 0.0);
+    float4 bg = make_float4(F.bg[0], F.bg[1], F.bg[2], F.bg[3]);
+    if (!hit || !(tf > ti)) return bg;
+
+    const double D = tf - ti;
+    const int K = (int)ceil(D / F.dt);
+    double pin[3];
+    for (int a = 0; a < 3; ++a) pin[a] = o[a] + ti * d[a];
+
+    // volume: offset-voxel coordinates at the entry and per unit length
+    const double Nd = (double)F.N;
+    const float hx0 = (float)(pin[0] * Nd - 0.5 - F.M), hy0 = (float)(pin[1] * Nd - 0.5 - F.M),
+                hz0 = (float)(pin[2] * Nd - 0.5 - F.M);
+    const float hdx = (float)(d[0] * Nd), hdy = (float)(d[1] * Nd), hdz = (float)(d[2] * Nd);
+    // light grid: depth index (Eq. 9, minus one) and texel coordinates (Eq. 10)
+    float qz0 = 0.f, qx0 = 0.f, qy0 = 0.f, qdz = 0.f, qdx = 0.f, qdy = 0.f;
+    ConeFrame cf = {0.f, 0.f, 0.f, 0.f};
+    if (MODE != VI_MODE_NONE) {
+        qz0 = (float)(F.Lq[0] * pin[0] + F.Lq[1] * pin[1] + F.Lq[2] * pin[2] + F.Lq0 - F.Mz);
+        qx0 = (float)(F.Ux[0] * pin[0] + F.Ux[1] * pin[1] + F.Ux[2] * pin[2] + F.Ux0 - F.Mr);
+        qy0 = (float)(F.Vy[0] * pin[0] + F.Vy[1] * pin[1] + F.Vy[2] * pin[2] + F.Vy0 - F.Mr);
+        qdz = (float)(F.Lq[0] * d[0] + F.Lq[1] * d[1] + F.Lq[2] * d[2]);
+        qdx = (float)(F.Ux[0] * d[0] + F.Ux[1] * d[1] + F.Ux[2] * d[2]);
+        qdy = (float)(F.Vy[0] * d[0] + F.Vy[1] * d[1] + F.Vy[2] * d[2]);
+        if (MODE == VI_MODE_CONE) {
+            // B: direction toward the viewer with its L component removed
+            double w[3] = {-d[0], -d[1], -d[2]};
+            const double wl = w[0] * F.L[0] + w[1] * F.L[1] + w[2] * F.L[2];
+            double B[3] = {w[0] - wl * F.L[0], w[1] - wl * F.L[1], w[2] - wl * F.L[2]};
+            const double nb = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+            if (nb < 1e-6) {
+                for (int a = 0; a < 3; ++a) B[a] = F.U[a];
+            } else {
+                for (int a = 0; a < 3; ++a) B[a] /= nb;
+            }
+            const double P[3] = {F.L[1] * B[2] - F.L[2] * B[1], F.L[2] * B[0] - F.L[0] * B[2],
+                                 F.L[0] * B[1] - F.L[1] * B[0]};
+            cf.bx = (float)(F.Ux[0] * B[0] + F.Ux[1] * B[1] + F.Ux[2] * B[2]);
+            cf.by = (float)(F.Vy[0] * B[0] + F.Vy[1] * B[1] + F.Vy[2] * B[2]);
+            cf.px = (float)(F.Ux[0] * P[0] + F.Ux[1] * P[1] + F.Ux[2] * P[2]);
+            cf.py = (float)(F.Vy[0] * P[0] + F.Vy[1] * P[1] + F.Vy[2] * P[2]);
+        }
+    }
+
+    const VT* __restrict__ vol = (const VT*)F.vol;
+    const float Df = (float)D, dtf = (float)F.dt;
+    const float Km1 = (float)(F.K - 1);
+    float Cr = 0.f, Cg = 0.f, Cb = 0.f, ad = 0.f;
+    int k = 0;
+    for (; k < K; ++k) {
+        const float s0 = (float)k * dtf;
+        const float s1 = fminf((float)(k + 1) * dtf, Df);
+        const float len = s1 - s0;
+        const float sm = 0.5f * (s0 + s1);
+        const float v = sample_volume<VT>(vol, F.N, F.M, F.scale, fmaf(sm, hdx, hx0), fmaf(sm, hdy, hy0),
+                                          fmaf(sm, hdz, hz0));
+        const float x = v * Km1;
+        const int e0 = min((int)x, F.K - 2);
+        const float w = x - (float)e0;
+        const float4 ta = s_tf[e0], tb = s_tf[e0 + 1];
+        const float a = clampf01(fmaf(w, tb.w - ta.w, ta.w));
+        float alpha = 0.0f;
+        if (len > 0.0f && a > 0.0f) alpha = 1.0f - fast_exp2(len * F.N_f * fast_log2(1.0f - a));
+        if (alpha > 0.0f) {
+            float A = 1.0f;
+            if (MODE != VI_MODE_NONE)
+                A = gather<MODE, SDT>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
+            const float shade = fmaf(1.0f - F.ambient, A, F.ambient);
+            const float wgt = (1.0f - ad) * alpha * shade;
+            Cr = fmaf(wgt * F.light[0], fmaf(w, tb.x - ta.x, ta.x), Cr);
+            Cg = fmaf(wgt * F.light[1], fmaf(w, tb.y - ta.y, ta.y), Cg);
+            Cb = fmaf(wgt * F.light[2], fmaf(w, tb.z - ta.z, ta.z), Cb);
+            ad = fmaf(1.0f - ad, alpha, ad);
+            if (1.0f - ad <= F.term_eps) {
+                ++k;
+                break;
+            }
+        }
+    }
+    nsamp += (uint32_t)k;
+    const float rem = 1.0f - ad;
+    return make_float4(fmaf(rem, bg.x, Cr), fmaf(rem, bg.y, Cg), fmaf(rem, bg.z, Cb), fmaf(rem, bg.w, ad));
+}
+
+// --------------------------------------------------------------------------
+// single-frame kernel
+// --------------------------------------------------------------------------
+template <typename VT, int MODE, int SDT>
+__global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
+{
+    extern __shared__ float4 s_tf[];  // K entries
+    for (int t = threadIdx.x; t < F.K; t += blockDim.x)
+        s_tf[t] = make_float4(F.tf[4 * t], F.tf[4 * t + 1], F.tf[4 * t + 2], F.tf[4 * t + 3]);
+    __syncthreads();
+
+    const uint32_t tiles_x = (F.width + 15) / 16, tiles_y = (F.height + 15) / 16;
+    const uint32_t tile = xcd_swizzle(blockIdx.x, tiles_x * tiles_y);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int px = (int)(tile % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = (int)(tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    uint32_t ns = 0;
+    if (px < F.width && py < F.height) {
+        const float4 c = render_ray<VT, MODE, SDT>(F, s_tf, px, py, ns);
+        F.out[(size_t)py * F.width + px] = c;
+    }
+    if (F.samples) {
+        // wave sum, one atomic per wave
+        for (int off = 32; off > 0; off >>= 1) ns += __shfl_xor(ns, off);
+        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
+    }
+}
+
+template <typename VT, int SDT>
+static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
+{
+    const uint32_t tiles = (uint32_t)(((f.width + 15) / 16) * ((f.height + 15) / 16));
+    dim3 grid(tiles), block(256);
+    const size_t lds = sizeof(float4) * (size_t)f.K;
+    switch (f.mode) {
+    case VI_MODE_NONE: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_NONE, SDT>), grid, block, lds, s, f); break;
+    case VI_MODE_SHADOW: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_SHADOW, SDT>), grid, block, lds, s, f); break;
+    case VI_MODE_SHELL: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_SHELL, SDT>), grid, block, lds, s, f); break;
+    default: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_CONE, SDT>), grid, block, lds, s, f); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename VT>
+static hipError_t launch_vt(const RenderFrame& f, hipStream_t s)
+{
+    return f.stack_dtype == VI_BF16 ? launch_mode<VT, VI_BF16>(f, s) : launch_mode<VT, VI_F32>(f, s);
+}
+
+hipError_t launch_render(const RenderFrame& f, hipStream_t s)
+{
+    switch (f.vol_dtype) {
+    case VI_U8: return launch_vt<uint8_t>(f, s);
+    case VI_U16: return launch_vt<uint16_t>(f, s);
+    case VI_F16: return launch_vt<__half>(f, s);
+    default: return launch_vt<float>(f, s);
+    }
+}
+
+}  // namespace vi

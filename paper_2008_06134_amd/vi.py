@@ -1,0 +1,274 @@
+"""Thin ctypes binding of libvi (the C ABI in ``include/vi.h``).
+
+Argument marshalling only: every step of both passes runs in the HIP kernels
+of ``libvi.so``.  PyTorch is used for device memory and streams.  If the
+library has not been built this module raises on first use -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvi.so")
+
+VI_U8, VI_U16, VI_F16, VI_F32, VI_BF16 = 0, 1, 2, 3, 4
+MODES = {"none": 0, "shadow": 1, "shell": 2, "cone": 3}
+ERRORS = {-1: "VI_E_INVALID_ARG", -2: "VI_E_UNSUPPORTED", -3: "VI_E_NO_MEMORY", -4: "VI_E_DEVICE",
+          -5: "VI_E_BUSY", -6: "VI_E_CANCELLED"}
+
+
+class VIError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Volume_t(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("n", C.c_int), ("scale", C.c_float)]
+
+
+class TF_t(C.Structure):
+    _fields_ = [("rgba", C.c_void_p), ("n_entries", C.c_int)]
+
+
+class Slices_t(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("n", C.c_int), ("res", C.c_int),
+                ("L", C.c_double * 3), ("U", C.c_double * 3), ("V", C.c_double * 3), ("c", C.c_double * 3),
+                ("dmin", C.c_double), ("dmax", C.c_double), ("ds", C.c_double), ("R", C.c_double),
+                ("vol_n", C.c_int), ("tag", C.c_uint64)]
+
+
+class Camera_t(C.Structure):
+    _fields_ = [("kind", C.c_int), ("eye", C.c_double * 3), ("target", C.c_double * 3), ("up", C.c_double * 3),
+                ("fovy_deg", C.c_double), ("ortho_half_h", C.c_double), ("width", C.c_int), ("height", C.c_int)]
+
+
+class RenderOpts_t(C.Structure):
+    _fields_ = [("ambient", C.c_float), ("light_rgb", C.c_float * 3), ("bg", C.c_float * 4),
+                ("term_eps", C.c_float), ("shell_count", C.c_int), ("shell_h_vox", C.c_float),
+                ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_float)]
+
+
+# every symbol declared in include/vi.h, with its ctypes signature
+SIGNATURES = {
+    "vi_version": ([], C.c_char_p),
+    "vi_last_error": ([], C.c_char_p),
+    "vi_default_render_opts": ([C.POINTER(RenderOpts_t)], C.c_int),
+    "vi_slices_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
+    "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.POINTER(Slices_t)], C.c_int),
+    "vi_build_attenuation": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_double), C.c_int, C.c_int,
+                              C.c_int, C.c_void_p, C.POINTER(Slices_t), C.c_void_p], C.c_int),
+    "vi_render": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(Slices_t), C.POINTER(Camera_t), C.c_int,
+                   C.c_float, C.POINTER(RenderOpts_t), C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "vi_tag": ([C.POINTER(Volume_t), C.POINTER(TF_t)], C.c_uint64),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libvi.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2008_06134_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise VIError(rc, lib().vi_last_error().decode())
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _vec3(x):
+    return (C.c_double * 3)(*[float(t) for t in x])
+
+
+# ---------------------------------------------------------------------------
+# inputs
+# ---------------------------------------------------------------------------
+
+_VOL_DT = {torch.uint8: VI_U8, torch.uint16: VI_U16, torch.int16: VI_U16, torch.float16: VI_F16,
+           torch.float32: VI_F32}
+_DEFAULT_SCALE = {VI_U8: 1.0 / 255.0, VI_U16: 1.0 / 4095.0, VI_F16: 1.0, VI_F32: 1.0}
+
+
+class Volume:
+    """A device-resident cubic volume raw[z][y][x] (u8, u16 -- stored as uint16 or
+    its int16 bit pattern --, f16 or f32) and the scale mapping raw values to [0,1]."""
+
+    def __init__(self, data: torch.Tensor, scale: float | None = None):
+        if data.dim() != 3 or not (data.shape[0] == data.shape[1] == data.shape[2]):
+            raise ValueError("volume must be a cubic N x N x N tensor")
+        if data.dtype not in _VOL_DT:
+            raise TypeError(f"unsupported volume dtype {data.dtype}")
+        self.data = data.contiguous()
+        self.dtype = _VOL_DT[data.dtype]
+        self.n = int(data.shape[0])
+        self.scale = float(_DEFAULT_SCALE[self.dtype] if scale is None else scale)
+        self.s = Volume_t(self.data.data_ptr(), self.dtype, self.n, self.scale)
+
+    @staticmethod
+    def from_numpy(raw, device="cuda", scale=None) -> "Volume":
+        import numpy as np
+        if raw.dtype == np.uint16:
+            t = torch.from_numpy(raw.view(np.int16)).to(device)
+        else:
+            t = torch.from_numpy(raw).to(device)
+        return Volume(t, scale)
+
+
+class TF:
+    """A K x 4 float32 RGBA transfer-function table on the device."""
+
+    def __init__(self, rgba: torch.Tensor):
+        if rgba.dim() != 2 or rgba.shape[1] != 4:
+            raise ValueError("transfer function must be K x 4")
+        self.data = rgba.to(torch.float32).contiguous()
+        self.s = TF_t(self.data.data_ptr(), int(self.data.shape[0]))
+
+    @staticmethod
+    def from_numpy(tab, device="cuda") -> "TF":
+        return TF(torch.from_numpy(tab).to(device=device, dtype=torch.float32))
+
+
+@dataclass
+class Slices:
+    """An attenuation stack: the device buffer and its descriptor."""
+    data: torch.Tensor | None
+    s: Slices_t
+
+    @property
+    def n(self):
+        return self.s.n
+
+    @property
+    def res(self):
+        return self.s.res
+
+    def frame(self) -> dict:
+        s = self.s
+        return {"L": list(s.L), "U": list(s.U), "V": list(s.V), "c": list(s.c), "dmin": s.dmin, "dmax": s.dmax,
+                "ds": s.ds, "R": s.R, "n": s.n, "res": s.res}
+
+
+def camera(cam: dict) -> Camera_t:
+    c = Camera_t()
+    c.kind = 1 if cam["kind"] in ("persp", 1) else 0
+    c.eye = _vec3(cam["eye"])
+    c.target = _vec3(cam["target"])
+    c.up = _vec3(cam["up"])
+    c.fovy_deg = float(cam.get("fovy_deg", 40.0))
+    c.ortho_half_h = float(cam.get("ortho_half_h", 0.5))
+    c.width = int(cam["width"])
+    c.height = int(cam["height"])
+    return c
+
+
+def default_opts() -> dict:
+    o = RenderOpts_t()
+    _check(lib().vi_default_render_opts(C.byref(o)))
+    return {"ambient": o.ambient, "light_rgb": list(o.light_rgb), "bg": list(o.bg), "term_eps": o.term_eps,
+            "shell_count": o.shell_count, "shell_h_vox": o.shell_h_vox, "cone_rings": o.cone_rings,
+            "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan}
+
+
+def render_opts(opts: dict | None) -> RenderOpts_t:
+    d = default_opts()
+    if opts:
+        d.update(opts)
+    o = RenderOpts_t()
+    o.ambient = d["ambient"]
+    o.light_rgb = (C.c_float * 3)(*d["light_rgb"])
+    o.bg = (C.c_float * 4)(*d["bg"])
+    o.term_eps = d["term_eps"]
+    o.shell_count = int(d["shell_count"])
+    o.shell_h_vox = d["shell_h_vox"]
+    o.cone_rings = int(d["cone_rings"])
+    o.cone_angles = int(d["cone_angles"])
+    o.cone_grid = int(d["cone_grid"])
+    o.cone_tan = d["cone_tan"]
+    return o
+
+
+# ---------------------------------------------------------------------------
+# calls
+# ---------------------------------------------------------------------------
+
+def slices_bytes(n: int, res: int, dtype: int = VI_F32) -> int:
+    return int(lib().vi_slices_bytes(n, res, dtype))
+
+
+def light_frame(light_dir, n: int, res: int, dtype: int = VI_F32) -> Slices:
+    s = Slices_t()
+    _check(lib().vi_light_frame(_vec3(light_dir), int(n), int(res), int(dtype), C.byref(s)))
+    return Slices(None, s)
+
+
+def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: int, dtype: int = VI_F32,
+                      out: torch.Tensor | None = None, stream=None) -> Slices:
+    """Attenuation stack for `light_dir` (section 3.2.1, Alg. 1); returns the stack
+    (n x res x res float32 transmittance, or bfloat16 optical depth) and its descriptor."""
+    tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
+    if out is None:
+        out = torch.empty((n_slices, slice_res, slice_res), dtype=tdt, device=vol.data.device)
+    if out.numel() * out.element_size() < slices_bytes(n_slices, slice_res, dtype):
+        raise ValueError("stack buffer too small")
+    s = Slices_t()
+    _check(lib().vi_build_attenuation(C.byref(vol.s), C.byref(tf.s), _vec3(light_dir), int(n_slices),
+                                      int(slice_res), int(dtype), C.c_void_p(out.data_ptr()), C.byref(s),
+                                      _stream(stream)))
+    return Slices(out, s)
+
+
+def render(vol: Volume, tf: TF, slices: Slices | None, cam: dict, mode: str, step_vox: float,
+           opts: dict | None = None, out: torch.Tensor | None = None, samples: torch.Tensor | None = None,
+           stream=None) -> torch.Tensor:
+    """Ray-cast one frame (sections 3.2.2-3.2.3, 4); returns H x W x 4 float32
+    premultiplied RGBA.  `samples` (int64 device tensor of one element) gets the
+    number of composited segments added to it."""
+    W, H = int(cam["width"]), int(cam["height"])
+    if out is None:
+        out = torch.empty((H, W, 4), dtype=torch.float32, device=vol.data.device)
+    if out.numel() < W * H * 4 or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("output must be a contiguous float32 tensor of H*W*4 elements")
+    o = render_opts(opts)
+    sp = C.byref(slices.s) if slices is not None else None
+    _check(lib().vi_render(C.byref(vol.s), C.byref(tf.s), sp, C.byref(camera(cam)), MODES[mode],
+                           C.c_float(step_vox), C.byref(o), C.c_void_p(out.data_ptr()),
+                           C.c_void_p(samples.data_ptr() if samples is not None else 0), _stream(stream)))
+    return out
+
+
+def tag(vol: Volume, tf: TF) -> int:
+    return int(lib().vi_tag(C.byref(vol.s), C.byref(tf.s)))
+
+
+def version() -> str:
+    return lib().vi_version().decode()
+
+
+def header_symbols() -> list:
+    """Function names declared in include/vi.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "vi.h")
+    text = open(hdr).read()
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(vi_\w+)\s*\(", text, flags=re.M)))
+

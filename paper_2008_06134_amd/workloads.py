@@ -110,15 +110,21 @@ def _phantom_ellipsoids(rng: np.random.Generator) -> list:
     return ells
 
 
-def _ellipsoid_cover(vol_z: np.ndarray, z: np.ndarray, y: np.ndarray, x: np.ndarray, N: int, e: _Ellipsoid):
-    """Soft indicator (about one voxel of partial-volume blur) of an ellipsoid on a z-chunk."""
+def _ellipsoid_cover(z: np.ndarray, y: np.ndarray, x: np.ndarray, N: int, e: _Ellipsoid):
+    """Soft indicator (about one voxel of partial-volume blur) of an ellipsoid on a
+    z-chunk; returns (cover, (y-slice, x-slice)) restricted to the ellipsoid's box."""
+    pad = 2.0 / N
+    ys = slice(int(max(0, np.floor((e.centre[1] - e.axes[1] - pad) * N))),
+               int(min(N, np.ceil((e.centre[1] + e.axes[1] + pad) * N))))
+    xs = slice(int(max(0, np.floor((e.centre[0] - e.axes[0] - pad) * N))),
+               int(min(N, np.ceil((e.centre[0] + e.axes[0] + pad) * N))))
     qz = ((z - e.centre[2]) / e.axes[2]) ** 2
-    qy = ((y - e.centre[1]) / e.axes[1]) ** 2
-    qx = ((x - e.centre[0]) / e.axes[0]) ** 2
+    qy = ((y[ys] - e.centre[1]) / e.axes[1]) ** 2
+    qx = ((x[xs] - e.centre[0]) / e.axes[0]) ** 2
     q = np.sqrt(qz[:, None, None] + qy[None, :, None] + qx[None, None, :])
     # approximate signed distance to the surface in voxels
     dist_vox = (q - 1.0) * float(e.axes.min()) * N
-    return np.clip(0.5 - dist_vox, 0.0, 1.0).astype(np.float32)
+    return np.clip(0.5 - dist_vox, 0.0, 1.0).astype(np.float32), (ys, xs)
 
 
 def _value_noise_axis_weights(N: int, spacing: float, G: int) -> np.ndarray:
@@ -132,31 +138,32 @@ def _value_noise_axis_weights(N: int, spacing: float, G: int) -> np.ndarray:
     return W
 
 
-def value_noise(N: int, rng: np.random.Generator, spacing: float = 32.0, octaves: int = 3,
-                z0: int = 0, z1: int | None = None, lattices=None):
-    """3-octave value noise in [0,1] (lattice spacing halves per octave, smoothstep),
-    evaluated on slices z0..z1.  ``lattices`` lets chunked callers reuse the draws."""
-    z1 = N if z1 is None else z1
-    if lattices is None:
-        lattices = []
+class ValueNoise:
+    """3-octave value noise in [0,1] on an N^3 voxel grid: uniform lattice values
+    (lattice spacing halves per octave, amplitude halves), smoothstep-interpolated.
+    The (y, x) contractions are done once; ``chunk(z0, z1)`` finishes slices."""
+
+    def __init__(self, N: int, rng: np.random.Generator, spacing: float = 32.0, octaves: int = 3):
+        self.N = N
+        self.parts = []
+        amp_sum = 0.0
         for o in range(octaves):
-            G = int(math.ceil(N / (spacing / 2 ** o))) + 2
-            lattices.append(rng.random((G, G, G), dtype=np.float32))
-    out = np.zeros((z1 - z0, N, N), dtype=np.float32)
-    amp_sum = 0.0
-    for o, lat in enumerate(lattices):
-        sp = spacing / 2 ** o
-        G = lat.shape[0]
-        W = _value_noise_axis_weights(N, sp, G)
-        Wz = W[z0:z1]
-        # out[z,y,x] = sum_abc lat[a,b,c] Wz[z,a] W[y,b] W[x,c]   (lat index order z,y,x)
-        t = np.tensordot(lat, W, axes=([2], [1]))      # (a, b, x)
-        t = np.tensordot(t, W, axes=([1], [1]))        # (a, x, y)
-        t = np.tensordot(Wz, t, axes=([1], [0]))       # (z, x, y)
-        amp = 0.5 ** o
-        out += amp * np.transpose(t, (0, 2, 1))
-        amp_sum += amp
-    return out / amp_sum, lattices
+            sp = spacing / 2 ** o
+            G = int(math.ceil(N / sp)) + 2
+            lat = rng.random((G, G, G), dtype=np.float32)      # lattice index order (z, y, x)
+            W = _value_noise_axis_weights(N, sp, G)
+            t = np.tensordot(lat, W, axes=([2], [1]))          # (a, b, x)
+            t = np.tensordot(t, W, axes=([1], [1]))            # (a, x, y)
+            amp = 0.5 ** o
+            self.parts.append((amp, W, np.ascontiguousarray(np.transpose(t, (0, 2, 1)))))  # (a, y, x)
+            amp_sum += amp
+        self.amp_sum = amp_sum
+
+    def chunk(self, z0: int, z1: int) -> np.ndarray:
+        out = np.zeros((z1 - z0, self.N, self.N), dtype=np.float32)
+        for amp, W, t in self.parts:
+            out += amp * np.tensordot(W[z0:z1], t, axes=([1], [0]))
+        return out / self.amp_sum
 
 
 def ct_phantom_u16(N: int, seed: int, vessels: bool = False, noise_sigma: float = 30.0,
@@ -171,10 +178,9 @@ def ct_phantom_u16(N: int, seed: int, vessels: bool = False, noise_sigma: float 
     ells = _phantom_ellipsoids(rng)
     thick = 6.0 / 256.0  # shell thickness, normalised
     ells[2].axes = ells[1].axes - thick
-    lat1 = lat2 = None
     if vessels:
-        _, lat1 = value_noise(N, rng, z0=0, z1=1)
-        _, lat2 = value_noise(N, rng, z0=0, z1=1)
+        noise1 = ValueNoise(N, rng)
+        noise2 = ValueNoise(N, rng)
     noise_rng = np.random.default_rng(seed + 1000)
     out = np.empty((N, N, N), dtype=np.uint16)
     y = _centres(N) / N
@@ -183,14 +189,17 @@ def ct_phantom_u16(N: int, seed: int, vessels: bool = False, noise_sigma: float 
         z1 = min(N, z0 + chunk)
         z = _centres(N)[z0:z1] / N
         val = np.zeros((z1 - z0, N, N), dtype=np.float32)
-        body = _ellipsoid_cover(val, z, y, x, N, ells[0])
+        body = np.zeros_like(val)
+        cov, (ys, xs) = _ellipsoid_cover(z, y, x, N, ells[0])
+        body[:, ys, xs] = cov
         val += body * ells[0].value
         for e in ells[1:]:
-            cov = _ellipsoid_cover(val, z, y, x, N, e)
-            val = val * (1.0 - cov) + cov * e.value
+            cov, (ys, xs) = _ellipsoid_cover(z, y, x, N, e)
+            sub = val[:, ys, xs]
+            val[:, ys, xs] = sub * (1.0 - cov) + cov * e.value
         if vessels:
-            n1, _ = value_noise(N, rng, z0=z0, z1=z1, lattices=lat1)
-            n2, _ = value_noise(N, rng, z0=z0, z1=z1, lattices=lat2)
+            n1 = noise1.chunk(z0, z1)
+            n2 = noise2.chunk(z0, z1)
             w, edge = 0.035, 0.015
             m = np.clip((w - np.abs(n1 - 0.5)) / edge, 0.0, 1.0) * np.clip((w - np.abs(n2 - 0.5)) / edge, 0.0, 1.0)
             m *= body  # vessels only inside the body

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP32 path: max-abs <= 1e-4 per RGBA channel, element by element, on the same
+seeded inputs -- full images at the small size, sampled pixels and stack
+columns (the oracle computes those one by one) at the medium and large sizes,
+in the launch configuration the benchmark times.  Edge cases: empty volume,
+ragged image and slice sizes, one slab, odd volume edges, rays that miss.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2008_06134_amd import vi
+from paper_2008_06134_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_IMG = 1e-4      # per RGBA channel, FP32 path
+TOL_STACK = 2e-5    # transmittance, FP32 product over <= 512 slabs
+
+DEV = "cuda"
+
+
+def _mode(m):
+    return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
+
+
+def gpu_inputs(raw, tab, scale=None):
+    return vi.Volume.from_numpy(raw, DEV, scale), vi.TF.from_numpy(tab, DEV)
+
+
+def gpu_render(vol, tf, st, cam, mode, step, opts=None):
+    cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+    img = vi.render(vol, tf, st, cam, mode, step, opts, samples=cnt)
+    torch.cuda.synchronize()
+    return img.cpu().double().numpy(), int(cnt.item())
+
+
+def report(name, err):
+    print(f"[parity] {name}: max-abs {err:.3e}", flush=True)
+
+
+# ---------------------------------------------------------------- small workload, full images
+
+@pytest.mark.parametrize("mode", ["shell", "shadow", "cone", "cone5", "none"])
+def test_small_full_image(mode):
+    w = W.WORKLOADS["small"]
+    raw, tab = w.volume(), w.tf()
+    light = w.lights()[0]
+    vol, tf = gpu_inputs(raw, tab)
+    st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res)
+    ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
+    S = ost.export()
+    err_s = np.abs(st.data.cpu().double().numpy() - S).max()
+    report("small stack", err_s)
+    assert err_s <= TOL_STACK
+    cam = w.camera()
+    m, extra = _mode(mode)
+    opts = {"bg": [0.1, 0.05, 0.02, 0.3], **extra}
+    img, ns = gpu_render(vol, tf, st, cam, m, w.step_vox, opts)
+    _, ref, nt, nf = O.render(O.Volume(raw), O.TF(tab), ost, cam, m, w.step_vox, opts, want_full=False)
+    err = np.abs(img - ref).max()
+    report(f"small {mode}", err)
+    assert err <= TOL_IMG
+    assert abs(ns - nt.sum()) <= 1e-3 * nt.sum() + 16
+
+
+# ---------------------------------------------------------------- medium / large, sampled
+
+def _sample_pixels(W_, H_, count, seed):
+    rng = np.random.default_rng(seed)
+    pix = rng.choice(W_ * H_, size=count, replace=False)
+    # plus a full middle row and column (ragged-tile edges included)
+    row = (H_ // 2) * W_ + np.arange(W_)
+    col = np.arange(H_) * W_ + W_ // 2
+    return np.unique(np.concatenate([pix, row, col]))
+
+
+def _sampled_parity(name, raw, tab, light, n, res, cam, mode, step, opts, npix, seed, cols=1500):
+    vol, tf = gpu_inputs(raw, tab)
+    st = vi.build_attenuation(vol, tf, light, n, res)
+    torch.cuda.synchronize()
+    ovol, otf = O.Volume(raw), O.TF(tab)
+    ost = O.Stack(ovol, otf, light, n, res)
+    rng = np.random.default_rng(seed + 1)
+    S = st.data
+    ij = rng.integers(0, res, size=(cols, 2))
+    got = S[:, ij[:, 1], ij[:, 0]].cpu().double().numpy()
+    want = np.stack([ost.column(i, j) for i, j in ij], axis=1)
+    err_s = np.abs(got - want).max()
+    report(f"{name} stack columns", err_s)
+    assert err_s <= TOL_STACK
+    img, ns = gpu_render(vol, tf, st, cam, mode, step, opts)
+    pix = _sample_pixels(cam["width"], cam["height"], npix, seed)
+    _, ref, nt, _ = O.render(ovol, otf, ost, cam, mode, step, opts, pixels=pix, want_full=False)
+    got = img.reshape(-1, 4)[pix]
+    err = np.abs(got - ref).max()
+    worst = pix[np.argmax(np.abs(got - ref).max(axis=1))]
+    report(f"{name} {mode} ({pix.size} px, worst pixel {worst % cam['width']},{worst // cam['width']})", err)
+    assert err <= TOL_IMG
+    return ns
+
+
+@pytest.fixture(scope="module")
+def medium():
+    w = W.WORKLOADS["medium"]
+    return w, w.volume(), w.tf()
+
+
+def test_medium_cone5x5_sampled(medium):
+    w, raw, tab = medium
+    _sampled_parity("medium", raw, tab, w.lights()[0], w.n_slices, w.res, w.camera(), "cone", w.step_vox,
+                    {"cone_grid": 5}, 3000, seed=11)
+
+
+@pytest.mark.parametrize("mode", ["shell", "cone"])
+def test_medium_other_modes_sampled(medium, mode):
+    w, raw, tab = medium
+    _sampled_parity("medium", raw, tab, w.lights()[0], w.n_slices, w.res, w.camera(), mode, w.step_vox,
+                    {}, 1500, seed=12)
+
+
+@pytest.fixture(scope="module")
+def large():
+    w = W.WORKLOADS["large"]
+    return w, w.volume(), w.tf()
+
+
+@pytest.mark.parametrize("light_index,mode", [(0, "shell"), (0, "cone"), (5, "shell"), (11, "cone")])
+def test_large_sampled(large, light_index, mode):
+    w, raw, tab = large
+    light = w.lights()[light_index]
+    _sampled_parity(f"large[{light_index}]", raw, tab, light, w.n_slices, w.res, w.camera(light_index), mode,
+                    w.step_vox, {}, 1500, seed=20 + light_index, cols=800)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_empty_volume_is_background_exactly():
+    raw = np.zeros((24, 24, 24), np.uint8)
+    tab = W.tf_ramp()
+    vol, tf = gpu_inputs(raw, tab)
+    st = vi.build_attenuation(vol, tf, [0.2, 0.5, -1], 7, 19)
+    assert torch.all(st.data == 1.0)
+    bg = [0.1, 0.2, 0.3, 0.4]
+    for m in ["shadow", "shell", "cone", "cone5", "none"]:
+        mm, extra = _mode(m)
+        img, ns = gpu_render(vol, tf, st, W.camera_orbit(37, 23, 0.3, 0.2), mm, 0.5, {"bg": bg, **extra})
+        assert np.all(img == np.asarray(bg, dtype=np.float32).astype(np.float64))
+        assert ns > 0
+
+
+def test_constant_cube_closed_form():
+    """Unlit constant cube, orthographic chord 1: alpha = 1-(1-a0)^N, C = rgb alpha."""
+    N, a0, rgb = 32, 0.03, [0.9, 0.6, 0.3]
+    raw = np.full((N, N, N), 100, np.uint8)
+    tab = np.tile(np.array(rgb + [a0]), (256, 1))
+    vol, tf = gpu_inputs(raw, tab)
+    cam = W.camera_ortho_front(40, 40, half_h=0.75)
+    img, ns = gpu_render(vol, tf, None, cam, "none", 0.5)
+    a_pix = 1 - (1 - a0) ** N
+    xs = 0.5 + (2 * (np.arange(40) + 0.5) / 40 - 1) * 0.75
+    inside = (xs > 0) & (xs < 1)
+    sel = img[np.ix_(inside, inside)]
+    np.testing.assert_allclose(sel[..., :3], np.broadcast_to(np.array(rgb) * a_pix, sel[..., :3].shape), atol=5e-6)
+    np.testing.assert_allclose(sel[..., 3], a_pix, atol=5e-6)
+    assert ns == int(inside.sum()) ** 2 * 2 * N
+
+
+@pytest.mark.parametrize("N,n,res,W_,H_,light,kind", [
+    (33, 1, 50, 37, 23, [0.3, -0.8, 0.5], "persp"),    # odd edge, one slab, ragged slices and image
+    (20, 9, 17, 1, 1, [1, 1, -1], "persp"),            # a single pixel
+    (16, 5, 3, 64, 17, [0, 0, -1], "ortho"),           # very coarse stack, axis light
+    (48, 64, 96, 50, 70, [-1, 0.1, 0.2], "persp"),     # slab thinner than a voxel
+])
+@pytest.mark.parametrize("mode", ["shell", "cone", "cone5"])
+def test_ragged_and_degenerate_shapes(N, n, res, W_, H_, light, kind, mode):
+    raw = W.sphere_u8(N, radius=N * 0.3, density=190, noise=25, seed=N)
+    tab = W.tf_ramp()
+    vol, tf = gpu_inputs(raw, tab)
+    st = vi.build_attenuation(vol, tf, light, n, res)
+    ost = O.Stack(O.Volume(raw), O.TF(tab), light, n, res)
+    err_s = np.abs(st.data.cpu().double().numpy() - ost.export()).max()
+    assert err_s <= TOL_STACK
+    cam = W.camera_orbit(W_, H_, 0.8, 0.4, distance=1.8) if kind == "persp" else W.camera_ortho_front(W_, H_)
+    m, extra = _mode(mode)
+    opts = {"bg": [0.2, 0.1, 0.0, 0.5], "ambient": 0.15, **extra}
+    img, ns = gpu_render(vol, tf, st, cam, m, 0.5, opts)
+    _, ref, nt, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, m, 0.5, opts, want_full=False)
+    err = np.abs(img - ref).max()
+    report(f"ragged N={N} n={n} res={res} {W_}x{H_} {mode}", err)
+    assert err <= TOL_IMG
+
+
+@pytest.mark.parametrize("dtype", [np.uint16, np.float16, np.float32])
+def test_volume_dtypes(dtype):
+    N = 40
+    base = W.ct_phantom_u16(N, seed=9)
+    if dtype == np.uint16:
+        raw, scale = base, None
+    elif dtype == np.float16:
+        raw, scale = W.to_f16_normalised(base), 1.0
+    else:
+        raw, scale = (base / 4095.0).astype(np.float32), 1.0
+    tab = W.tf_ct()
+    vol, tf = gpu_inputs(raw, tab, scale)
+    light = [0.4, 0.3, -0.8]
+    st = vi.build_attenuation(vol, tf, light, 40, 64)
+    ovol = O.Volume(raw, scale)
+    ost = O.Stack(ovol, O.TF(tab), light, 40, 64)
+    assert np.abs(st.data.cpu().double().numpy() - ost.export()).max() <= TOL_STACK
+    cam = W.camera_orbit(48, 40, 1.0, 0.35)
+    img, _ = gpu_render(vol, tf, st, cam, "shell", 0.5)
+    _, ref, _, _ = O.render(ovol, O.TF(tab), ost, cam, "shell", 0.5, want_full=False)
+    assert np.abs(img - ref).max() <= TOL_IMG
+
+
+def test_termination_off_matches_full_oracle():
+    w = W.WORKLOADS["small"]
+    raw, tab = w.volume(), w.tf()
+    vol, tf = gpu_inputs(raw, tab)
+    light = w.lights()[0]
+    st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res)
+    ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
+    cam = w.camera(W=96, H=96)
+    img, ns = gpu_render(vol, tf, st, cam, "shell", 0.5, {"term_eps": 0.0})
+    full, _, _, nf = O.render(O.Volume(raw), O.TF(tab), ost, cam, "shell", 0.5)
+    assert np.abs(img - full).max() <= TOL_IMG
+    assert ns == nf.sum()
+
+
+def test_stack_is_camera_independent_and_deterministic():
+    w = W.WORKLOADS["small"]
+    raw, tab = w.volume(), w.tf()
+    vol, tf = gpu_inputs(raw, tab)
+    a = vi.build_attenuation(vol, tf, w.lights()[0], w.n_slices, w.res)
+    b = vi.build_attenuation(vol, tf, w.lights()[0], w.n_slices, w.res)
+    torch.cuda.synchronize()
+    assert torch.equal(a.data, b.data)
+    S = a.data
+    assert float(S.min()) >= 0.0 and float(S.max()) <= 1.0
+    assert bool(torch.all(S[1:] <= S[:-1]))
+    cam = w.camera()
+    i1 = vi.render(vol, tf, a, cam, "shell", 0.5).clone()
+    i2 = vi.render(vol, tf, a, cam, "shell", 0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(i1, i2)
