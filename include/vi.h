@@ -20,8 +20,8 @@
  *
  * Geometry conventions (the paper leaves these open; the library fixes):
  *   - the volume fills the unit cube [0,1]^3; voxel (x,y,z) is centred at
- *     ((x+1/2)/N, (y+1/2)/N, (z+1/2)/N); storage raw[z][y][x], x fastest;
- *     cubic volumes only (N^3);
+ *     ((x+1/2)/N, (y+1/2)/N, (z+1/2)/N); cubic volumes only (N^3), stored
+ *     linearly (x fastest) or in 4x4x4 bricks (vi_layout);
  *   - sampling is trilinear with clamp-to-edge; value = clamp(raw*scale,0,1)
  *     per voxel before interpolation;
  *   - the transfer function holds K RGBA float entries (non-premultiplied
@@ -92,13 +92,24 @@ typedef enum {
 
 typedef enum { VI_CAM_ORTHO = 0, VI_CAM_PERSP = 1 } vi_camera_kind;
 
-/* A cubic volume in device memory, raw[z][y][x].  `scale` maps raw values
- * to [0,1] (u8: 1/255, u16 12-bit data: 1/4095, f16/f32 normalised: 1). */
+/* Volume layouts in device memory (N = edge, NP = N rounded up to 4,
+ * nb = NP / 4):
+ *   VI_LAYOUT_LINEAR: raw[z][y][x], element (x,y,z) at (z*N + y)*N + x;
+ *   VI_LAYOUT_BRICK4: 4x4x4 bricks, bricks ordered z,y,x; element (x,y,z)
+ *     at ((z/4)*nb*nb + (y/4)*nb + x/4)*64 + (z%4)*16 + (y%4)*4 + x%4,
+ *     NP^3 elements (padding never read).  A trilinear footprint then
+ *     touches one to eight 64-element bricks instead of four rows, which is
+ *     what the gathers of both passes pay for. */
+typedef enum { VI_LAYOUT_LINEAR = 0, VI_LAYOUT_BRICK4 = 1 } vi_layout;
+
+/* A cubic volume in device memory.  `scale` maps raw values to [0,1]
+ * (u8: 1/255, u16 12-bit data: 1/4095, f16/f32 normalised: 1). */
 typedef struct {
     const void* data;
-    int dtype; /* VI_U8, VI_U16, VI_F16 or VI_F32 */
-    int n;     /* edge length N >= 2; N^3 * element size < 4 GiB */
+    int dtype;  /* VI_U8, VI_U16, VI_F16 or VI_F32 */
+    int n;      /* edge length N >= 2; storage < 4 GiB */
     float scale;
+    int layout; /* VI_LAYOUT_LINEAR (0) or VI_LAYOUT_BRICK4 */
 } vi_volume;
 
 /* Transfer function: `n_entries` x 4 floats (r,g,b,a) in device memory,
@@ -110,9 +121,12 @@ typedef struct {
 
 /* Attenuation stack descriptor, filled by vi_build_attenuation (or by
  * vi_light_frame for the geometry alone).  `data` points at the caller's
- * buffer of vi_slices_bytes(n, res, dtype) bytes, layout [k][j][i]: layer
- * k, texel row j (along V), column i (along U).  F32 stores transmittance
- * T_k; BF16 stores optical depth tau_k with T_k = exp(-tau_k).
+ * buffer of vi_slices_bytes(n, res, dtype) bytes holding layer k, texel row
+ * j (along V), column i (along U) in 8 x 4 texel tiles: with R8 = res
+ * rounded up to 8 and R4 = res rounded up to 4, element (k, j, i) sits at
+ *   k*R8*R4 + ((j/4)*(R8/8) + i/8)*32 + (j%4)*8 + i%8
+ * (padding texels are never read).  F32 stores transmittance T_k; BF16
+ * stores optical depth tau_k with T_k = exp(-tau_k).
  * Geometry is kept in double as computed on the host (Eq. 8). */
 typedef struct {
     void* data;
@@ -162,9 +176,21 @@ const char* vi_last_error(void);
 /* Fill `o` with the defaults listed above.  Returns VI_E_INVALID_ARG on NULL. */
 int vi_default_render_opts(vi_render_opts* o);
 
-/* Bytes of a stack buffer: n * res * res * (4 for VI_F32, 2 for VI_BF16);
- * 0 for invalid arguments. */
+/* Bytes of a stack buffer: n * R8 * R4 * (4 for VI_F32, 2 for VI_BF16)
+ * (R8, R4: res rounded up to 8 and to 4); 0 for invalid arguments. */
 size_t vi_slices_bytes(int n_slices, int slice_res, int slice_dtype);
+
+/* Bytes of a volume of edge n, dtype and layout (0 for invalid arguments). */
+size_t vi_volume_bytes(int n, int dtype, int layout);
+
+/* Copy a linear volume into the 4x4x4 brick layout: `d_dst` (device,
+ * vi_volume_bytes(n, dtype, VI_LAYOUT_BRICK4) bytes, caller-owned) receives
+ * the bricks and `out` describes them (same dtype, edge and scale).  One
+ * kernel launch on `stream`; values are copied bit for bit, so every result
+ * computed from the bricked volume equals the one from the linear volume.
+ * Errors: VI_E_INVALID_ARG for NULL pointers or a source that is not
+ * linear; VI_E_UNSUPPORTED for sizes beyond the limits; VI_E_DEVICE. */
+int vi_volume_to_bricks(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream);
 
 /* Host only: compute the light frame of Eq. 8 and the light projection
  * for `light_dir` (need not be unit length; finite, non-zero) and fill

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["vi_api.hip", "vi_build.hip", "vi_render.hip"]
+SOURCES = ["vi_api.hip", "vi_build.hip", "vi_render.hip", "vi_layout.hip"]
 ARCH = os.environ.get("VI_OFFLOAD_ARCH", "gfx950")
 
 

@@ -41,13 +41,21 @@ size_t elem_size(int dt)
     }
 }
 
+double volume_storage(int n, int dtype, int layout)
+{
+    const double e = (double)(layout == VI_LAYOUT_BRICK4 ? vi::round_up((uint32_t)n, 4u) : (uint32_t)n);
+    return e * e * e * (double)elem_size(dtype);
+}
+
 int check_volume(const vi_volume* v)
 {
     if (!v || !v->data) return fail(VI_E_INVALID_ARG, "volume or its data pointer is NULL");
     if (v->dtype != VI_U8 && v->dtype != VI_U16 && v->dtype != VI_F16 && v->dtype != VI_F32)
         return fail(VI_E_UNSUPPORTED, "volume dtype %d not supported", v->dtype);
+    if (v->layout != VI_LAYOUT_LINEAR && v->layout != VI_LAYOUT_BRICK4)
+        return fail(VI_E_UNSUPPORTED, "volume layout %d not supported", v->layout);
     if (v->n < 2) return fail(VI_E_INVALID_ARG, "volume edge %d < 2", v->n);
-    const double bytes = (double)v->n * v->n * v->n * (double)elem_size(v->dtype);
+    const double bytes = volume_storage(v->n, v->dtype, v->layout);
     if (bytes >= 4294967296.0) return fail(VI_E_UNSUPPORTED, "volume of %.0f bytes exceeds 4 GiB", bytes);
     if (((uintptr_t)v->data) % elem_size(v->dtype)) return fail(VI_E_INVALID_ARG, "volume pointer misaligned");
     if (!(v->scale > 0.0f) || !isfinite(v->scale)) return fail(VI_E_INVALID_ARG, "volume scale must be > 0");
@@ -61,6 +69,19 @@ int check_tf(const vi_tf* tf)
         return fail(VI_E_INVALID_ARG, "transfer function needs 2..%d entries, got %d", vi::kMaxTF, tf->n_entries);
     if (((uintptr_t)tf->rgba) % 4) return fail(VI_E_INVALID_ARG, "transfer function pointer misaligned");
     return VI_OK;
+}
+
+// per-axis offset strides of a volume layout (y, z)
+void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
+{
+    if (v->layout == VI_LAYOUT_BRICK4) {
+        const uint32_t nb = vi::round_up((uint32_t)v->n, 4u) / 4u;
+        *sy = nb * 64u;
+        *sz = nb * nb * 64u;
+    } else {
+        *sy = (uint32_t)v->n;
+        *sz = (uint32_t)v->n * (uint32_t)v->n;
+    }
 }
 
 // Eq. 8 and the light projection: geometry of the stack in double.
@@ -127,7 +148,32 @@ int vi_default_render_opts(vi_render_opts* o)
 size_t vi_slices_bytes(int n, int res, int dt)
 {
     if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16)) return 0;
-    return (size_t)n * (size_t)res * (size_t)res * elem_size(dt);
+    return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
+}
+
+size_t vi_volume_bytes(int n, int dtype, int layout)
+{
+    if (n < 2 || elem_size(dtype) == 0 || dtype == VI_BF16) return 0;
+    if (layout != VI_LAYOUT_LINEAR && layout != VI_LAYOUT_BRICK4) return 0;
+    return (size_t)volume_storage(n, dtype, layout);
+}
+
+int vi_volume_to_bricks(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream)
+{
+    clear_err();
+    int rc;
+    if ((rc = check_volume(src)) != VI_OK) return rc;
+    if (src->layout != VI_LAYOUT_LINEAR) return fail(VI_E_INVALID_ARG, "source volume is not linear");
+    if (!d_dst || !out) return fail(VI_E_INVALID_ARG, "NULL destination or descriptor");
+    if (((uintptr_t)d_dst) % elem_size(src->dtype)) return fail(VI_E_INVALID_ARG, "destination misaligned");
+    if (volume_storage(src->n, src->dtype, VI_LAYOUT_BRICK4) >= 4294967296.0)
+        return fail(VI_E_UNSUPPORTED, "bricked volume exceeds 4 GiB");
+    hipError_t e = vi::launch_to_bricks(src->data, d_dst, src->dtype, src->n, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VI_E_DEVICE, "brick launch failed: %s", hipGetErrorString(e));
+    *out = *src;
+    out->data = d_dst;
+    out->layout = VI_LAYOUT_BRICK4;
+    return VI_OK;
 }
 
 uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf)
@@ -180,6 +226,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     memset(&p, 0, sizeof p);
     p.vol = vol->data;
     p.vol_dtype = vol->dtype;
+    p.vol_layout = vol->layout;
+    volume_strides(vol, &p.vsy, &p.vsz);
     p.N = vol->n;
     p.M = vol->n / 2;
     p.scale = vol->scale;
@@ -189,6 +237,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     p.out_dtype = dt;
     p.n = n;
     p.res = res;
+    p.layer = vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u);
+    p.row_tiles32 = vi::round_up((uint32_t)res, 8u) * 4u;
     const double N = vol->n, texel = 2.0 * f.R / res, u0 = -f.R + 0.5 * texel;
     const double d0 = f.dmin + 0.5 * f.ds, Lc = dot3(f.L, f.c);
     for (int a = 0; a < 3; ++a) {
@@ -249,6 +299,8 @@ int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const 
     memset(&F, 0, sizeof F);
     F.vol = vol->data;
     F.vol_dtype = vol->dtype;
+    F.vol_layout = vol->layout;
+    volume_strides(vol, &F.vsy, &F.vsz);
     F.N = vol->n;
     F.M = vol->n / 2;
     F.scale = vol->scale;
@@ -260,6 +312,8 @@ int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const 
         F.stack_dtype = sl->dtype;
         F.n = sl->n;
         F.res = sl->res;
+        F.layer = vi::round_up((uint32_t)sl->res, 8u) * vi::round_up((uint32_t)sl->res, 4u);
+        F.row_tiles32 = vi::round_up((uint32_t)sl->res, 8u) * 4u;
         F.Mz = sl->n / 2;
         F.Mr = sl->res / 2;
         const double span = sl->dmax - sl->dmin, sc = sl->res / (2.0 * sl->R);

@@ -9,8 +9,9 @@
 // the volume is read through the caches and the stack is written once,
 // coalesced along the texel row.
 //
-// Workgroup = 16 x 16 texels (4 waves of 16 x 4); the alpha column of the
-// transfer function sits in LDS.
+// Workgroup = 16 x 16 texels (4 waves of 16 x 4): at every slab a wave
+// stores two whole 8 x 4 texel tiles of the stack, i.e. two full 128-byte
+// lines.  The alpha column of the transfer function sits in LDS.
 #include "vi_device.h"
 #include "vi_internal.h"
 
@@ -18,7 +19,7 @@ namespace vi {
 
 constexpr int kBuildTile = 16;
 
-template <typename VT, int OUT_DTYPE>
+template <typename VT, int LAYOUT, int OUT_DTYPE>
 __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 {
     extern __shared__ float s_alpha[];  // K entries
@@ -39,9 +40,10 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     const float hz0 = (float)(P.B0[2] + i * P.BU[2] + j * P.BV[2]);
 
     const VT* __restrict__ vol = (const VT*)P.vol;
+    const VolIndex VI_ = {1u, P.vsy, P.vsz};
     const float Km1 = (float)(P.K - 1);
-    const size_t layer = (size_t)P.res * (size_t)P.res;
-    const size_t col = (size_t)j * P.res + i;
+    const size_t layer = P.layer;
+    const size_t col = stack_oj(j, P.row_tiles32) + stack_oi(i);
     float T = 1.0f;     // transmittance (F32 form)
     float tau = 0.0f;   // optical depth (BF16 form)
     const float ln2 = 0.69314718055994531f;
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         // log2 of the slab's (1 - alpha)/e, 0 outside the cube (empty)
         float l2 = 0.0f;
         if (hx >= P.lo && hx <= P.hi && hy >= P.lo && hy <= P.hi && hz >= P.lo && hz <= P.hi) {
-            const float v = sample_volume<VT>(vol, P.N, P.M, P.scale, hx, hy, hz);
+            const float v = sample_volume<VT, LAYOUT>(vol, VI_, P.N, P.M, P.scale, hx, hy, hz);
             const float x = v * Km1;
             const int e0 = min((int)x, P.K - 2);
             const float w = x - (float)e0;
@@ -73,26 +75,33 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     }
 }
 
-template <typename VT>
+template <typename VT, int LAYOUT>
 static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
 {
     const uint32_t tiles = (uint32_t)((p.res + kBuildTile - 1) / kBuildTile);
     dim3 grid(tiles * tiles), block(256);
     const size_t lds = sizeof(float) * (size_t)p.K;
     if (p.out_dtype == VI_F32)
-        hipLaunchKernelGGL((build_kernel<VT, VI_F32>), grid, block, lds, s, p);
+        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32>), grid, block, lds, s, p);
     else
-        hipLaunchKernelGGL((build_kernel<VT, VI_BF16>), grid, block, lds, s, p);
+        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16>), grid, block, lds, s, p);
     return hipGetLastError();
+}
+
+template <typename VT>
+static hipError_t launch_build_l(const BuildParams& p, hipStream_t s)
+{
+    return p.vol_layout == VI_LAYOUT_BRICK4 ? launch_build_t<VT, VI_LAYOUT_BRICK4>(p, s)
+                                            : launch_build_t<VT, VI_LAYOUT_LINEAR>(p, s);
 }
 
 hipError_t launch_build(const BuildParams& p, hipStream_t s)
 {
     switch (p.vol_dtype) {
-    case VI_U8: return launch_build_t<uint8_t>(p, s);
-    case VI_U16: return launch_build_t<uint16_t>(p, s);
-    case VI_F16: return launch_build_t<__half>(p, s);
-    default: return launch_build_t<float>(p, s);
+    case VI_U8: return launch_build_l<uint8_t>(p, s);
+    case VI_U16: return launch_build_l<uint16_t>(p, s);
+    case VI_F16: return launch_build_l<__half>(p, s);
+    default: return launch_build_l<float>(p, s);
     }
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/vi.h"
+
 namespace vi {
 
 // Raw hardware transcendentals (v_exp_f32 / v_log_f32): 2^x and log2(x).
@@ -39,23 +41,46 @@ __device__ __forceinline__ float voxel_norm<float>(const float* __restrict__ v, 
     return clampf01(v[idx] * scale);
 }
 
+// Element offsets of the two volume layouts, separable per axis so the
+// eight corners of a trilinear footprint cost six offset evaluations:
+//   linear : (z*N + y)*N + x
+//   brick4 : 4x4x4 bricks (one 128-byte line at 16 bits), bricks in z,y,x
+//            order: ((z/4)*nb*nb + (y/4)*nb + x/4)*64 + (z%4)*16 + (y%4)*4 + x%4
+struct VolIndex {
+    uint32_t sx, sy, sz;  // linear: 1, N, N*N     brick4: unused, nb*64, nb*nb*64
+};
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t vol_ox(const VolIndex& I, int x)
+{
+    if (LAYOUT == VI_LAYOUT_BRICK4) return ((uint32_t)x >> 2) * 64u + ((uint32_t)x & 3u);
+    return (uint32_t)x;
+}
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t vol_oy(const VolIndex& I, int y)
+{
+    if (LAYOUT == VI_LAYOUT_BRICK4) return ((uint32_t)y >> 2) * I.sy + ((uint32_t)y & 3u) * 4u;
+    return (uint32_t)y * I.sy;
+}
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t vol_oz(const VolIndex& I, int z)
+{
+    if (LAYOUT == VI_LAYOUT_BRICK4) return ((uint32_t)z >> 2) * I.sz + ((uint32_t)z & 3u) * 16u;
+    return (uint32_t)z * I.sz;
+}
+
 // Trilinear sample at offset-voxel coordinates h = g - M (g = p*N - 1/2),
 // clamp to edge.  M is an integer so floor/fraction are taken on h exactly.
-template <typename VT>
-__device__ __forceinline__ float sample_volume(const VT* __restrict__ vol, int N, int M, float scale, float hx,
-                                               float hy, float hz)
+template <typename VT, int LAYOUT>
+__device__ __forceinline__ float sample_volume(const VT* __restrict__ vol, const VolIndex& I, int N, int M,
+                                               float scale, float hx, float hy, float hz)
 {
     float fx = floorf(hx), fy = floorf(hy), fz = floorf(hz);
     float wx = hx - fx, wy = hy - fy, wz = hz - fz;
     int x0 = (int)fx + M, y0 = (int)fy + M, z0 = (int)fz + M;
-    int xa = clampi(x0, 0, N - 1), xb = clampi(x0 + 1, 0, N - 1);
-    int ya = clampi(y0, 0, N - 1), yb = clampi(y0 + 1, 0, N - 1);
-    int za = clampi(z0, 0, N - 1), zb = clampi(z0 + 1, 0, N - 1);
-    uint32_t Nu = (uint32_t)N;
-    uint32_t raa = ((uint32_t)za * Nu + (uint32_t)ya) * Nu;
-    uint32_t rab = ((uint32_t)za * Nu + (uint32_t)yb) * Nu;
-    uint32_t rba = ((uint32_t)zb * Nu + (uint32_t)ya) * Nu;
-    uint32_t rbb = ((uint32_t)zb * Nu + (uint32_t)yb) * Nu;
+    const uint32_t xa = vol_ox<LAYOUT>(I, clampi(x0, 0, N - 1)), xb = vol_ox<LAYOUT>(I, clampi(x0 + 1, 0, N - 1));
+    const uint32_t ya = vol_oy<LAYOUT>(I, clampi(y0, 0, N - 1)), yb = vol_oy<LAYOUT>(I, clampi(y0 + 1, 0, N - 1));
+    const uint32_t za = vol_oz<LAYOUT>(I, clampi(z0, 0, N - 1)), zb = vol_oz<LAYOUT>(I, clampi(z0 + 1, 0, N - 1));
+    const uint32_t raa = za + ya, rab = za + yb, rba = zb + ya, rbb = zb + yb;
     float v000 = voxel_norm(vol, raa + xa, scale), v001 = voxel_norm(vol, raa + xb, scale);
     float v010 = voxel_norm(vol, rab + xa, scale), v011 = voxel_norm(vol, rab + xb, scale);
     float v100 = voxel_norm(vol, rba + xa, scale), v101 = voxel_norm(vol, rba + xb, scale);
@@ -64,6 +89,16 @@ __device__ __forceinline__ float sample_volume(const VT* __restrict__ vol, int N
     float c10 = fmaf(wx, v101 - v100, v100), c11 = fmaf(wx, v111 - v110, v110);
     float c0 = fmaf(wy, c01 - c00, c00), c1 = fmaf(wy, c11 - c10, c10);
     return fmaf(wz, c1 - c0, c0);
+}
+
+// Stack layout: every layer is stored as 8 x 4 texel tiles (one 128-byte
+// line in float), tiles row-major; a layer holds R8 x R4 texels (res rounded
+// up to 8 along i and to 4 along j):
+//   offset(k, j, i) = k*layer + ((j/4)*(R8/8) + i/8)*32 + (j%4)*8 + i%8
+__device__ __forceinline__ uint32_t stack_oi(int i) { return ((uint32_t)i >> 3) * 32u + ((uint32_t)i & 7u); }
+__device__ __forceinline__ uint32_t stack_oj(int j, uint32_t row_tiles32)
+{
+    return ((uint32_t)j >> 2) * row_tiles32 + ((uint32_t)j & 3u) * 8u;
 }
 
 // Round a float to bfloat16 (nearest even), finite inputs.

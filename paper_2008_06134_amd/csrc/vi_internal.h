@@ -21,6 +21,8 @@ constexpr int kMaxTaps = 49;     // largest gather (7 x 7 lattice)
 struct BuildParams {
     const void* vol;
     int vol_dtype;
+    int vol_layout;
+    uint32_t vsy, vsz;  // per-axis offset strides of the volume layout
     int N, M;
     float scale;
     const float* tf;   // K x 4
@@ -28,6 +30,7 @@ struct BuildParams {
     void* out;
     int out_dtype;     // VI_F32 transmittance / VI_BF16 optical depth
     int n, res;
+    uint32_t layer, row_tiles32;  // stack tiling: R8*R4 per layer, (R8/8)*32 per tile row
     double B0[3];      // h at (i,j,k) = (0,0,0)
     double BU[3];      // d h / d i
     double BV[3];      // d h / d j
@@ -43,6 +46,8 @@ struct RenderFrame {
     // volume
     const void* vol;
     int vol_dtype;
+    int vol_layout;
+    uint32_t vsy, vsz;
     int N, M;
     float scale;
     // transfer function
@@ -52,6 +57,7 @@ struct RenderFrame {
     const void* stack;
     int stack_dtype;
     int n, res;
+    uint32_t layer, row_tiles32;
     int Mz, Mr;          // integer offsets of the light-grid coordinates
     double Lq[3], Lq0;   // z = Lq . p + Lq0 - Mz       (Eq. 9 index minus one)
     double Ux[3], Ux0;   // x = Ux . p + Ux0 - Mr       (Eq. 10 texel column)
@@ -80,8 +86,12 @@ struct RenderFrame {
     unsigned long long* samples;
 };
 
-// launchers (vi_build.hip / vi_render.hip)
+// launchers (vi_build.hip / vi_render.hip / vi_layout.hip)
 hipError_t launch_build(const BuildParams& p, hipStream_t s);
 hipError_t launch_render(const RenderFrame& f, hipStream_t s);
+hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStream_t s);
+
+// host helpers shared by the API and the server
+inline uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
 }  // namespace vi

@@ -54,16 +54,16 @@ __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, flo
     const int res = F.res;
     const bool vi0 = (unsigned)i0 < (unsigned)res, vi1 = (unsigned)(i0 + 1) < (unsigned)res;
     const bool vj0 = (unsigned)j0 < (unsigned)res, vj1 = (unsigned)(j0 + 1) < (unsigned)res;
-    const int ci0 = clampi(i0, 0, res - 1), ci1 = clampi(i0 + 1, 0, res - 1);
-    const int cj0 = clampi(j0, 0, res - 1), cj1 = clampi(j0 + 1, 0, res - 1);
-    const uint32_t ures = (uint32_t)res;
+    const uint32_t oi0 = stack_oi(clampi(i0, 0, res - 1)), oi1 = stack_oi(clampi(i0 + 1, 0, res - 1));
+    const uint32_t oj0 = stack_oj(clampi(j0, 0, res - 1), F.row_tiles32);
+    const uint32_t oj1 = stack_oj(clampi(j0 + 1, 0, res - 1), F.row_tiles32);
 
     float t0 = 1.0f;
     if (k0 >= 0) {
-        const uint32_t base = (uint32_t)k0 * ures;
-        const uint32_t r0 = (base + (uint32_t)cj0) * ures, r1 = (base + (uint32_t)cj1) * ures;
-        float a = stack_texel<SDT>(F.stack, r0 + ci0), b = stack_texel<SDT>(F.stack, r0 + ci1);
-        float c = stack_texel<SDT>(F.stack, r1 + ci0), d = stack_texel<SDT>(F.stack, r1 + ci1);
+        const uint32_t base = (uint32_t)k0 * F.layer;
+        const uint32_t r0 = base + oj0, r1 = base + oj1;
+        float a = stack_texel<SDT>(F.stack, r0 + oi0), b = stack_texel<SDT>(F.stack, r0 + oi1);
+        float c = stack_texel<SDT>(F.stack, r1 + oi0), d = stack_texel<SDT>(F.stack, r1 + oi1);
         a = (vi0 && vj0) ? a : 1.0f;
         b = (vi1 && vj0) ? b : 1.0f;
         c = (vi0 && vj1) ? c : 1.0f;
@@ -73,10 +73,10 @@ __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, flo
     }
     float t1;
     {
-        const uint32_t base = (uint32_t)k1 * ures;
-        const uint32_t r0 = (base + (uint32_t)cj0) * ures, r1 = (base + (uint32_t)cj1) * ures;
-        float a = stack_texel<SDT>(F.stack, r0 + ci0), b = stack_texel<SDT>(F.stack, r0 + ci1);
-        float c = stack_texel<SDT>(F.stack, r1 + ci0), d = stack_texel<SDT>(F.stack, r1 + ci1);
+        const uint32_t base = (uint32_t)k1 * F.layer;
+        const uint32_t r0 = base + oj0, r1 = base + oj1;
+        float a = stack_texel<SDT>(F.stack, r0 + oi0), b = stack_texel<SDT>(F.stack, r0 + oi1);
+        float c = stack_texel<SDT>(F.stack, r1 + oi0), d = stack_texel<SDT>(F.stack, r1 + oi1);
         a = (vi0 && vj0) ? a : 1.0f;
         b = (vi1 && vj0) ? b : 1.0f;
         c = (vi0 && vj1) ? c : 1.0f;
@@ -128,7 +128,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
     return s * F.tap_w;
 }
 
-template <typename VT, int MODE, int SDT>
+template <typename VT, int LAYOUT, int MODE, int SDT>
 __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf, int px, int py,
                                              uint32_t& nsamp)
 {
@@ -206,6 +206,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     }
 
     const VT* __restrict__ vol = (const VT*)F.vol;
+    const VolIndex VI_ = {1u, F.vsy, F.vsz};
     const float Df = (float)D, dtf = (float)F.dt;
     const float Km1 = (float)(F.K - 1);
     float Cr = 0.f, Cg = 0.f, Cb = 0.f, ad = 0.f;
@@ -215,8 +216,8 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         const float s1 = fminf((float)(k + 1) * dtf, Df);
         const float len = s1 - s0;
         const float sm = 0.5f * (s0 + s1);
-        const float v = sample_volume<VT>(vol, F.N, F.M, F.scale, fmaf(sm, hdx, hx0), fmaf(sm, hdy, hy0),
-                                          fmaf(sm, hdz, hz0));
+        const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, fmaf(sm, hdx, hx0),
+                                                  fmaf(sm, hdy, hy0), fmaf(sm, hdz, hz0));
         const float x = v * Km1;
         const int e0 = min((int)x, F.K - 2);
         const float w = x - (float)e0;
@@ -248,7 +249,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
 // --------------------------------------------------------------------------
 // single-frame kernel
 // --------------------------------------------------------------------------
-template <typename VT, int MODE, int SDT>
+template <typename VT, int LAYOUT, int MODE, int SDT>
 __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
 {
     extern __shared__ float4 s_tf[];  // K entries
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
     const int py = (int)(tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
     uint32_t ns = 0;
     if (px < F.width && py < F.height) {
-        const float4 c = render_ray<VT, MODE, SDT>(F, s_tf, px, py, ns);
+        const float4 c = render_ray<VT, LAYOUT, MODE, SDT>(F, s_tf, px, py, ns);
         F.out[(size_t)py * F.width + px] = c;
     }
     if (F.samples) {
@@ -273,25 +274,38 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
     }
 }
 
-template <typename VT, int SDT>
+template <typename VT, int LAYOUT, int SDT>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
     const uint32_t tiles = (uint32_t)(((f.width + 15) / 16) * ((f.height + 15) / 16));
     dim3 grid(tiles), block(256);
     const size_t lds = sizeof(float4) * (size_t)f.K;
     switch (f.mode) {
-    case VI_MODE_NONE: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_NONE, SDT>), grid, block, lds, s, f); break;
-    case VI_MODE_SHADOW: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_SHADOW, SDT>), grid, block, lds, s, f); break;
-    case VI_MODE_SHELL: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_SHELL, SDT>), grid, block, lds, s, f); break;
-    default: hipLaunchKernelGGL((render_kernel<VT, VI_MODE_CONE, SDT>), grid, block, lds, s, f); break;
+    case VI_MODE_NONE:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_NONE, SDT>), grid, block, lds, s, f);
+        break;
+    case VI_MODE_SHADOW:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHADOW, SDT>), grid, block, lds, s, f);
+        break;
+    case VI_MODE_SHELL:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT>), grid, block, lds, s, f);
+        break;
+    default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_CONE, SDT>), grid, block, lds, s, f); break;
     }
     return hipGetLastError();
+}
+
+template <typename VT, int LAYOUT>
+static hipError_t launch_sdt(const RenderFrame& f, hipStream_t s)
+{
+    return f.stack_dtype == VI_BF16 ? launch_mode<VT, LAYOUT, VI_BF16>(f, s) : launch_mode<VT, LAYOUT, VI_F32>(f, s);
 }
 
 template <typename VT>
 static hipError_t launch_vt(const RenderFrame& f, hipStream_t s)
 {
-    return f.stack_dtype == VI_BF16 ? launch_mode<VT, VI_BF16>(f, s) : launch_mode<VT, VI_F32>(f, s);
+    return f.vol_layout == VI_LAYOUT_BRICK4 ? launch_sdt<VT, VI_LAYOUT_BRICK4>(f, s)
+                                            : launch_sdt<VT, VI_LAYOUT_LINEAR>(f, s);
 }
 
 hipError_t launch_render(const RenderFrame& f, hipStream_t s)

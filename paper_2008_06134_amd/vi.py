@@ -28,8 +28,12 @@ class VIError(RuntimeError):
         self.code = code
 
 
+VI_LAYOUT_LINEAR, VI_LAYOUT_BRICK4 = 0, 1
+
+
 class Volume_t(C.Structure):
-    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("n", C.c_int), ("scale", C.c_float)]
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("n", C.c_int), ("scale", C.c_float),
+                ("layout", C.c_int)]
 
 
 class TF_t(C.Structure):
@@ -60,6 +64,8 @@ SIGNATURES = {
     "vi_last_error": ([], C.c_char_p),
     "vi_default_render_opts": ([C.POINTER(RenderOpts_t)], C.c_int),
     "vi_slices_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
+    "vi_volume_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
+    "vi_volume_to_bricks": ([C.POINTER(Volume_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.POINTER(Slices_t)], C.c_int),
     "vi_build_attenuation": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_double), C.c_int, C.c_int,
                               C.c_int, C.c_void_p, C.POINTER(Slices_t), C.c_void_p], C.c_int),
@@ -111,19 +117,26 @@ _DEFAULT_SCALE = {VI_U8: 1.0 / 255.0, VI_U16: 1.0 / 4095.0, VI_F16: 1.0, VI_F32:
 
 
 class Volume:
-    """A device-resident cubic volume raw[z][y][x] (u8, u16 -- stored as uint16 or
-    its int16 bit pattern --, f16 or f32) and the scale mapping raw values to [0,1]."""
+    """A device-resident cubic volume (u8, u16 -- stored as uint16 or its int16 bit
+    pattern --, f16 or f32) and the scale mapping raw values to [0,1].  `data` is
+    raw[z][y][x] (linear layout) or the 4x4x4 brick layout of `to_bricks()`."""
 
-    def __init__(self, data: torch.Tensor, scale: float | None = None):
-        if data.dim() != 3 or not (data.shape[0] == data.shape[1] == data.shape[2]):
-            raise ValueError("volume must be a cubic N x N x N tensor")
+    def __init__(self, data: torch.Tensor, scale: float | None = None, n: int | None = None,
+                 layout: int = VI_LAYOUT_LINEAR):
         if data.dtype not in _VOL_DT:
             raise TypeError(f"unsupported volume dtype {data.dtype}")
+        if layout == VI_LAYOUT_LINEAR:
+            if data.dim() != 3 or not (data.shape[0] == data.shape[1] == data.shape[2]):
+                raise ValueError("volume must be a cubic N x N x N tensor")
+            n = int(data.shape[0])
+        elif n is None:
+            raise ValueError("a bricked volume needs its edge n")
         self.data = data.contiguous()
         self.dtype = _VOL_DT[data.dtype]
-        self.n = int(data.shape[0])
+        self.n = int(n)
+        self.layout = layout
         self.scale = float(_DEFAULT_SCALE[self.dtype] if scale is None else scale)
-        self.s = Volume_t(self.data.data_ptr(), self.dtype, self.n, self.scale)
+        self.s = Volume_t(self.data.data_ptr(), self.dtype, self.n, self.scale, layout)
 
     @staticmethod
     def from_numpy(raw, device="cuda", scale=None) -> "Volume":
@@ -133,6 +146,17 @@ class Volume:
         else:
             t = torch.from_numpy(raw).to(device)
         return Volume(t, scale)
+
+    def to_bricks(self, out: torch.Tensor | None = None, stream=None) -> "Volume":
+        """Copy into the 4x4x4 brick layout (vi_volume_to_bricks)."""
+        nbytes = int(lib().vi_volume_bytes(self.n, self.dtype, VI_LAYOUT_BRICK4))
+        if out is None:
+            out = torch.empty(nbytes // self.data.element_size(), dtype=self.data.dtype, device=self.data.device)
+        if out.numel() * out.element_size() < nbytes:
+            raise ValueError("brick buffer too small")
+        res = Volume_t()
+        _check(lib().vi_volume_to_bricks(C.byref(self.s), C.c_void_p(out.data_ptr()), C.byref(res), _stream(stream)))
+        return Volume(out, self.scale, self.n, VI_LAYOUT_BRICK4)
 
 
 class TF:
@@ -151,9 +175,16 @@ class TF:
 
 @dataclass
 class Slices:
-    """An attenuation stack: the device buffer and its descriptor."""
+    """An attenuation stack: the device buffer (8 x 4 texel tiles per layer,
+    shaped n x R4/4 x R8/8 x 4 x 8) and its descriptor."""
     data: torch.Tensor | None
     s: Slices_t
+
+    def dense(self) -> torch.Tensor:
+        """The stack as an n x res x res tensor (a device copy, for inspection)."""
+        n, r = self.s.n, self.s.res
+        t = self.data
+        return t.permute(0, 1, 3, 2, 4).reshape(n, t.shape[1] * 4, t.shape[2] * 8)[:, :r, :r]
 
     @property
     def n(self):
@@ -216,6 +247,17 @@ def slices_bytes(n: int, res: int, dtype: int = VI_F32) -> int:
     return int(lib().vi_slices_bytes(n, res, dtype))
 
 
+def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda") -> torch.Tensor:
+    """An uninitialised device buffer in the stack layout (n x R4/4 x R8/8 x 4 x 8)."""
+    r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
+    tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
+    return torch.empty((n, r4 // 4, r8 // 8, 4, 8), dtype=tdt, device=device)
+
+
+def volume_bytes(n: int, dtype: int, layout: int) -> int:
+    return int(lib().vi_volume_bytes(n, dtype, layout))
+
+
 def light_frame(light_dir, n: int, res: int, dtype: int = VI_F32) -> Slices:
     s = Slices_t()
     _check(lib().vi_light_frame(_vec3(light_dir), int(n), int(res), int(dtype), C.byref(s)))
@@ -226,9 +268,8 @@ def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: 
                       out: torch.Tensor | None = None, stream=None) -> Slices:
     """Attenuation stack for `light_dir` (section 3.2.1, Alg. 1); returns the stack
     (n x res x res float32 transmittance, or bfloat16 optical depth) and its descriptor."""
-    tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
     if out is None:
-        out = torch.empty((n_slices, slice_res, slice_res), dtype=tdt, device=vol.data.device)
+        out = stack_buffer(n_slices, slice_res, dtype, vol.data.device)
     if out.numel() * out.element_size() < slices_bytes(n_slices, slice_res, dtype):
         raise ValueError("stack buffer too small")
     s = Slices_t()

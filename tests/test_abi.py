@@ -178,3 +178,22 @@ def test_tag_distinguishes_inputs():
     tb = lib.vi_tag(C.byref(b.vol), C.byref(b.tf))
     assert ta != tb and ta != 0
     assert ta == lib.vi_tag(C.byref(a.vol), C.byref(a.tf))
+
+
+def test_volume_bytes_and_brick_validation():
+    assert vi.volume_bytes(512, vi.VI_U16, vi.VI_LAYOUT_LINEAR) == 512 ** 3 * 2
+    assert vi.volume_bytes(33, vi.VI_U8, vi.VI_LAYOUT_BRICK4) == 36 ** 3
+    assert vi.volume_bytes(33, vi.VI_F32, vi.VI_LAYOUT_BRICK4) == 36 ** 3 * 4
+    assert vi.volume_bytes(1, vi.VI_U8, 0) == 0 and vi.volume_bytes(8, vi.VI_BF16, 0) == 0
+    assert vi.volume_bytes(8, vi.VI_U8, 5) == 0
+    lib = vi.lib()
+    src = vi.Volume_t(0x10000, vi.VI_U16, 16, 1 / 4095, vi.VI_LAYOUT_BRICK4)
+    out = vi.Volume_t()
+    assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -1  # not linear
+    src.layout = vi.VI_LAYOUT_LINEAR
+    assert lib.vi_volume_to_bricks(C.byref(src), None, C.byref(out), None) == -1
+    assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20001), C.byref(out), None) == -1
+    src.layout = 7
+    assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -2
+    # stack buffers are padded to whole 8 x 4 tiles
+    assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4

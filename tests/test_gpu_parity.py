@@ -28,8 +28,12 @@ def _mode(m):
     return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
 
 
-def gpu_inputs(raw, tab, scale=None):
-    return vi.Volume.from_numpy(raw, DEV, scale), vi.TF.from_numpy(tab, DEV)
+def gpu_inputs(raw, tab, scale=None, bricks=True):
+    """Device volume (4x4x4 bricks unless asked otherwise, as the benchmark runs) and TF."""
+    vol = vi.Volume.from_numpy(raw, DEV, scale)
+    if bricks:
+        vol = vol.to_bricks()
+    return vol, vi.TF.from_numpy(tab, DEV)
 
 
 def gpu_render(vol, tf, st, cam, mode, step, opts=None):
@@ -54,7 +58,7 @@ def test_small_full_image(mode):
     st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res)
     ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
     S = ost.export()
-    err_s = np.abs(st.data.cpu().double().numpy() - S).max()
+    err_s = np.abs(st.dense().cpu().double().numpy() - S).max()
     report("small stack", err_s)
     assert err_s <= TOL_STACK
     cam = w.camera()
@@ -86,7 +90,7 @@ def _sampled_parity(name, raw, tab, light, n, res, cam, mode, step, opts, npix, 
     ovol, otf = O.Volume(raw), O.TF(tab)
     ost = O.Stack(ovol, otf, light, n, res)
     rng = np.random.default_rng(seed + 1)
-    S = st.data
+    S = st.dense()
     ij = rng.integers(0, res, size=(cols, 2))
     got = S[:, ij[:, 1], ij[:, 0]].cpu().double().numpy()
     want = np.stack([ost.column(i, j) for i, j in ij], axis=1)
@@ -144,7 +148,7 @@ def test_empty_volume_is_background_exactly():
     tab = W.tf_ramp()
     vol, tf = gpu_inputs(raw, tab)
     st = vi.build_attenuation(vol, tf, [0.2, 0.5, -1], 7, 19)
-    assert torch.all(st.data == 1.0)
+    assert torch.all(st.dense() == 1.0)
     bg = [0.1, 0.2, 0.3, 0.4]
     for m in ["shadow", "shell", "cone", "cone5", "none"]:
         mm, extra = _mode(m)
@@ -183,7 +187,7 @@ def test_ragged_and_degenerate_shapes(N, n, res, W_, H_, light, kind, mode):
     vol, tf = gpu_inputs(raw, tab)
     st = vi.build_attenuation(vol, tf, light, n, res)
     ost = O.Stack(O.Volume(raw), O.TF(tab), light, n, res)
-    err_s = np.abs(st.data.cpu().double().numpy() - ost.export()).max()
+    err_s = np.abs(st.dense().cpu().double().numpy() - ost.export()).max()
     assert err_s <= TOL_STACK
     cam = W.camera_orbit(W_, H_, 0.8, 0.4, distance=1.8) if kind == "persp" else W.camera_ortho_front(W_, H_)
     m, extra = _mode(mode)
@@ -211,7 +215,7 @@ def test_volume_dtypes(dtype):
     st = vi.build_attenuation(vol, tf, light, 40, 64)
     ovol = O.Volume(raw, scale)
     ost = O.Stack(ovol, O.TF(tab), light, 40, 64)
-    assert np.abs(st.data.cpu().double().numpy() - ost.export()).max() <= TOL_STACK
+    assert np.abs(st.dense().cpu().double().numpy() - ost.export()).max() <= TOL_STACK
     cam = W.camera_orbit(48, 40, 1.0, 0.35)
     img, _ = gpu_render(vol, tf, st, cam, "shell", 0.5)
     _, ref, _, _ = O.render(ovol, O.TF(tab), ost, cam, "shell", 0.5, want_full=False)
@@ -233,6 +237,43 @@ def test_termination_off_matches_full_oracle():
     assert 0.5 * nf.sum() < ns <= nf.sum()
 
 
+@pytest.mark.parametrize("N", [64, 33, 6])
+def test_brick_layout_matches_its_definition(N):
+    rng = np.random.default_rng(N)
+    raw = rng.integers(0, 4096, size=(N, N, N)).astype(np.uint16)
+    lin = vi.Volume.from_numpy(raw, DEV)
+    br = lin.to_bricks()
+    torch.cuda.synchronize()
+    NP = (N + 3) // 4 * 4
+    nb = NP // 4
+    got = br.data.cpu().numpy().view(np.uint16)
+    assert got.size == NP ** 3
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    off = ((z // 4) * nb * nb + (y // 4) * nb + x // 4) * 64 + (z % 4) * 16 + (y % 4) * 4 + x % 4
+    assert np.array_equal(got[off], raw)
+
+
+@pytest.mark.parametrize("N,n,res", [(64, 32, 64), (33, 7, 50)])
+@pytest.mark.parametrize("mode", ["shell", "cone", "cone5"])
+def test_bricked_volume_gives_bitwise_identical_results(N, n, res, mode):
+    raw = W.sphere_u8(N, radius=N * 0.35, density=180, noise=30, seed=N + 1)
+    tab = W.tf_ramp()
+    lin, tf = gpu_inputs(raw, tab, bricks=False)
+    br = lin.to_bricks()
+    light = [0.6, -0.3, -0.74]
+    s1 = vi.build_attenuation(lin, tf, light, n, res)
+    s2 = vi.build_attenuation(br, tf, light, n, res)
+    torch.cuda.synchronize()
+    assert torch.equal(s1.data, s2.data)
+    m, extra = _mode(mode)
+    cam = W.camera_orbit(70, 50, 2.2, 0.5)
+    a = vi.render(lin, tf, s1, cam, m, 0.5, extra)
+    s2.s.tag = 0  # stack built from the bricked copy, rendered with either
+    b = vi.render(br, tf, s2, cam, m, 0.5, extra)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_stack_is_camera_independent_and_deterministic():
     w = W.WORKLOADS["small"]
     raw, tab = w.volume(), w.tf()
@@ -241,7 +282,7 @@ def test_stack_is_camera_independent_and_deterministic():
     b = vi.build_attenuation(vol, tf, w.lights()[0], w.n_slices, w.res)
     torch.cuda.synchronize()
     assert torch.equal(a.data, b.data)
-    S = a.data
+    S = a.dense()
     assert float(S.min()) >= 0.0 and float(S.max()) <= 1.0
     assert bool(torch.all(S[1:] <= S[:-1]))
     cam = w.camera()
