@@ -264,7 +264,7 @@ def test_bricked_volume_gives_bitwise_identical_results(N, n, res, mode):
     s1 = vi.build_attenuation(lin, tf, light, n, res)
     s2 = vi.build_attenuation(br, tf, light, n, res)
     torch.cuda.synchronize()
-    assert torch.equal(s1.data, s2.data)
+    assert torch.equal(s1.dense(), s2.dense())   # padding texels of the tiles are never written
     m, extra = _mode(mode)
     cam = W.camera_orbit(70, 50, 2.2, 0.5)
     a = vi.render(lin, tf, s1, cam, m, 0.5, extra)
@@ -281,7 +281,7 @@ def test_stack_is_camera_independent_and_deterministic():
     a = vi.build_attenuation(vol, tf, w.lights()[0], w.n_slices, w.res)
     b = vi.build_attenuation(vol, tf, w.lights()[0], w.n_slices, w.res)
     torch.cuda.synchronize()
-    assert torch.equal(a.data, b.data)
+    assert torch.equal(a.dense(), b.dense())
     S = a.dense()
     assert float(S.min()) >= 0.0 and float(S.max()) <= 1.0
     assert bool(torch.all(S[1:] <= S[:-1]))
