@@ -94,7 +94,7 @@ def main():
     tf = vi.TF.from_numpy(tab, dev)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    vol = vol_lin.to_bricks()  # one-off per volume: 4x4x4 brick layout
+    vol = vol_lin.to_bricks().with_minmax(8)  # one-off per volume: bricks + empty-space map
     torch.cuda.synchronize()
     brick_ms = (time.perf_counter() - tb) * 1e3
     del vol_lin
@@ -154,7 +154,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                 "bytes_per_launch": per_launch, "avg_launch_ms": round(float(avg_ms), 4)}
-    kernels = {"volume_to_bricks_ms_once": round(brick_ms, 3),
+    kernels = {"volume_prepare_ms_once": round(brick_ms, 3),
                "build_ms_mean": round(float(np.mean(build_ms)), 4),
                "build_hbm_frac": round((vol_bytes + stack_bytes) / (np.mean(build_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     for m, v in render_ms.items():
@@ -176,7 +176,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "fps": round(frames / wall, 3),
-        "config": {"workload": (f"{w.name}: {w.N}^3 {raw.dtype} phantom (4x4x4 bricks), "
+        "config": {"workload": (f"{w.name}: {w.N}^3 {raw.dtype} phantom (4x4x4 bricks, 8^3 empty-space cells), "
                                 f"{w.n_slices} slices x {w.res}^2 f32, "
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "
                                 f"{len(lights)} light directions (one rebuild per step)"),

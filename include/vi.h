@@ -103,13 +103,23 @@ typedef enum { VI_CAM_ORTHO = 0, VI_CAM_PERSP = 1 } vi_camera_kind;
 typedef enum { VI_LAYOUT_LINEAR = 0, VI_LAYOUT_BRICK4 = 1 } vi_layout;
 
 /* A cubic volume in device memory.  `scale` maps raw values to [0,1]
- * (u8: 1/255, u16 12-bit data: 1/4095, f16/f32 normalised: 1). */
+ * (u8: 1/255, u16 12-bit data: 1/4095, f16/f32 normalised: 1).
+ *
+ * Optional empty-space map (`minmax`, from vi_volume_minmax): for every
+ * cell of `cell`^3 voxels, the minimum and maximum normalised voxel value
+ * over the cell's voxels plus the next voxel along each axis, i.e. over
+ * every trilinear footprint whose lower corner lies in the cell.  Where all
+ * transfer-function entries that such values can reach have zero opacity, a
+ * segment's opacity is exactly zero and both passes skip its volume fetch:
+ * results are unchanged bit for bit. */
 typedef struct {
     const void* data;
     int dtype;  /* VI_U8, VI_U16, VI_F16 or VI_F32 */
     int n;      /* edge length N >= 2; storage < 4 GiB */
     float scale;
     int layout; /* VI_LAYOUT_LINEAR (0) or VI_LAYOUT_BRICK4 */
+    const float* minmax; /* NULL, or ceil(n/cell)^3 (min, max) float pairs, cells x fastest */
+    int cell;            /* cell edge in voxels (4, 8, 16 or 32) when minmax is set */
 } vi_volume;
 
 /* Transfer function: `n_entries` x 4 floats (r,g,b,a) in device memory,
@@ -192,6 +202,18 @@ size_t vi_volume_bytes(int n, int dtype, int layout);
  * linear; VI_E_UNSUPPORTED for sizes beyond the limits; VI_E_DEVICE. */
 int vi_volume_to_bricks(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream);
 
+/* Bytes of the empty-space map of a volume of edge n with cells of `cell`
+ * voxels: ceil(n/cell)^3 * 8 (0 for invalid arguments). */
+size_t vi_volume_minmax_bytes(int n, int cell);
+
+/* Compute the empty-space map of `vol` (any layout) into `d_minmax`
+ * (device, vi_volume_minmax_bytes bytes, caller-owned) and return in `out`
+ * a copy of `vol` that refers to it.  cell: 4, 8, 16 or 32.  One kernel
+ * launch on `stream`.  The map depends on the volume only; the transfer
+ * function is applied when rendering, so one map serves every TF.
+ * Errors: VI_E_INVALID_ARG for NULL pointers or a bad cell size. */
+int vi_volume_minmax(const vi_volume* vol, int cell, float* d_minmax, vi_volume* out, vi_stream_t stream);
+
 /* Host only: compute the light frame of Eq. 8 and the light projection
  * for `light_dir` (need not be unit length; finite, non-zero) and fill
  * the geometry fields of `out` (data = NULL, tag = 0).
@@ -228,6 +250,102 @@ int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* slices, co
 
 /* Identity tag vi_build_attenuation stores in vi_slices.tag for (vol, tf). */
 uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * The stack depends only on (volume, transfer function, light, n, res,
+ * dtype), not on the camera (the paper builds it once and reuses it while
+ * only the view changes, section 4), so the server keeps stacks resident
+ * in a device pool and reuses them across requests.  A scheduler thread
+ *   - admits requests first come first served while fewer than max_inflight
+ *     frames are unfinished and their stack is cached or fits in the pool
+ *     (least recently used unpinned stacks are evicted to make room; a stack
+ *     larger than the whole pool is rejected with VI_E_NO_MEMORY);
+ *   - builds missing stacks on its own build stream;
+ *   - renders 16x16-pixel tiles of all admitted frames, oldest first, in
+ *     launches of at most tiles_per_launch tiles that mix frames of
+ *     different volumes, sizes, cameras and modes; a launch waits on the
+ *     device (not the host) for the builds it needs, so builds overlap
+ *     renders; up to two launches are in flight;
+ *   - completes a frame when the launch holding its last tile finishes, and
+ *     admits waiting requests as slots and pool memory free up.
+ * Every pixel is computed by the same per-ray code as vi_render, so a
+ * frame is bit-identical whether rendered alone or in any mix.
+ * Memory: the library allocates the stack pool (stack_budget bytes, once,
+ * at creation) and small staging buffers; volumes, transfer functions,
+ * images and sample counters stay caller-owned device buffers that must
+ * outlive the requests using them.
+ * ---------------------------------------------------------------------- */
+typedef struct vi_server vi_server;
+
+typedef struct {
+    size_t stack_budget;       /* bytes of the device stack pool (> 0)                 */
+    int max_inflight;          /* admitted, unfinished frames: 1..256 (default 16)     */
+    int tiles_per_launch;      /* 16x16-pixel tiles per render launch (default 8192)   */
+    int device;                /* HIP device ordinal                                   */
+} vi_server_cfg;
+
+typedef struct {
+    int vol_id;                /* from vi_server_register_volume                        */
+    double light_dir[3];
+    int n_slices, slice_res, slice_dtype;
+    vi_camera camera;
+    int mode;
+    float step_vox;
+    vi_render_opts opts;       /* all fields used; start from vi_default_render_opts    */
+    float* d_rgba;             /* caller-owned device image, width*height*4 floats     */
+    unsigned long long* d_samples; /* optional device counter (added to), or NULL      */
+} vi_request;
+
+/* Request states reported by vi_server_poll / vi_server_wait. */
+#define VI_REQ_PENDING 0
+#define VI_REQ_ADMITTED 1
+#define VI_REQ_DONE 2
+
+typedef struct {
+    uint64_t submitted, completed, rejected, cancelled;
+    uint64_t stack_hits, stack_builds, evictions;
+    uint64_t launches, tiles;
+    double mean_frames_per_launch;     /* distinct frames per render launch               */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* completion - submission, completed frames */
+    double frames_per_s;               /* completed / (last completion - first submission) */
+    size_t pool_bytes, pool_in_use, pool_peak;
+} vi_stats;
+
+/* Create a server on cfg->device: allocates the stack pool and staging
+ * buffers, creates a render and a build stream (default priority) and
+ * starts the scheduler thread.  VI_E_NO_MEMORY if the pool cannot be
+ * allocated, VI_E_INVALID_ARG for bad sizes. */
+int vi_server_create(const vi_server_cfg* cfg, vi_server** out);
+
+/* Make a resident volume and transfer function known to the server (both
+ * stay caller-owned).  Returns its id in *vol_id. */
+int vi_server_register_volume(vi_server* srv, const vi_volume* vol, const vi_tf* tf, int* vol_id);
+
+/* Queue a frame; returns at once with its ticket.  Arguments are validated
+ * here (VI_E_INVALID_ARG / VI_E_UNSUPPORTED); VI_E_NO_MEMORY if its stack
+ * can never fit the pool. */
+int vi_server_submit(vi_server* srv, const vi_request* req, uint64_t* ticket);
+
+/* State of a ticket: VI_REQ_PENDING, VI_REQ_ADMITTED, VI_REQ_DONE, or a
+ * negative error code (e.g. VI_E_CANCELLED, VI_E_DEVICE). */
+int vi_server_poll(vi_server* srv, uint64_t ticket, int* state);
+
+/* Block until the ticket is done or failed, or timeout_ms passes (< 0:
+ * no limit).  Returns VI_OK when done, VI_E_BUSY on timeout, or the
+ * request's error code. */
+int vi_server_wait(vi_server* srv, uint64_t ticket, int timeout_ms);
+
+/* Cancel a request that has not been admitted yet (VI_E_BUSY if it has). */
+int vi_server_cancel(vi_server* srv, uint64_t ticket);
+
+/* Counters and latency percentiles since creation or the last reset. */
+int vi_server_stats(vi_server* srv, vi_stats* out);
+int vi_server_reset_stats(vi_server* srv);
+
+/* Finish all admitted and queued work, stop the thread, free the pool. */
+void vi_server_destroy(vi_server* srv);
 
 #ifdef __cplusplus
 }

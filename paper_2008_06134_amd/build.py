@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["vi_api.hip", "vi_build.hip", "vi_render.hip", "vi_layout.hip"]
+SOURCES = ["vi_api.hip", "vi_build.hip", "vi_render.hip", "vi_layout.hip", "vi_sched.cpp", "vi_server.hip"]
 ARCH = os.environ.get("VI_OFFLOAD_ARCH", "gfx950")
 
 
@@ -41,7 +41,7 @@ def build(verbose: bool = False) -> str:
     cc = hipcc()
 
     def compile_one(src):
-        obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
         cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

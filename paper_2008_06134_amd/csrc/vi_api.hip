@@ -59,7 +59,23 @@ int check_volume(const vi_volume* v)
     if (bytes >= 4294967296.0) return fail(VI_E_UNSUPPORTED, "volume of %.0f bytes exceeds 4 GiB", bytes);
     if (((uintptr_t)v->data) % elem_size(v->dtype)) return fail(VI_E_INVALID_ARG, "volume pointer misaligned");
     if (!(v->scale > 0.0f) || !isfinite(v->scale)) return fail(VI_E_INVALID_ARG, "volume scale must be > 0");
+    if (v->minmax) {
+        if (v->cell != 4 && v->cell != 8 && v->cell != 16 && v->cell != 32)
+            return fail(VI_E_INVALID_ARG, "empty-space cell %d must be 4, 8, 16 or 32", v->cell);
+        if (((uintptr_t)v->minmax) % 8) return fail(VI_E_INVALID_ARG, "empty-space map misaligned");
+    }
     return VI_OK;
+}
+
+int cell_shift(int cell) { return cell == 4 ? 2 : cell == 8 ? 3 : cell == 16 ? 4 : 5; }
+
+vi::OccMap occ_of(const vi_volume* v)
+{
+    vi::OccMap o;
+    o.mm = v->minmax ? (const float2*)v->minmax : nullptr;
+    o.shift = v->minmax ? cell_shift(v->cell) : 0;
+    o.nc = v->minmax ? ((uint32_t)v->n + (uint32_t)v->cell - 1) / (uint32_t)v->cell : 0;
+    return o;
 }
 
 int check_tf(const vi_tf* tf)
@@ -176,6 +192,33 @@ int vi_volume_to_bricks(const vi_volume* src, void* d_dst, vi_volume* out, vi_st
     return VI_OK;
 }
 
+size_t vi_volume_minmax_bytes(int n, int cell)
+{
+    if (n < 2 || (cell != 4 && cell != 8 && cell != 16 && cell != 32)) return 0;
+    const size_t nc = ((size_t)n + cell - 1) / cell;
+    return nc * nc * nc * 8;
+}
+
+int vi_volume_minmax(const vi_volume* vol, int cell, float* d_minmax, vi_volume* out, vi_stream_t stream)
+{
+    clear_err();
+    int rc;
+    if ((rc = check_volume(vol)) != VI_OK) return rc;
+    if (cell != 4 && cell != 8 && cell != 16 && cell != 32)
+        return fail(VI_E_INVALID_ARG, "cell %d must be 4, 8, 16 or 32", cell);
+    if (!d_minmax || !out) return fail(VI_E_INVALID_ARG, "NULL map or descriptor");
+    if (((uintptr_t)d_minmax) % 8) return fail(VI_E_INVALID_ARG, "map pointer must be 8-byte aligned");
+    uint32_t sy, sz;
+    volume_strides(vol, &sy, &sz);
+    hipError_t e = vi::launch_minmax(vol->data, vol->dtype, vol->layout, sy, sz, vol->n, vol->scale,
+                                     cell_shift(cell), d_minmax, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VI_E_DEVICE, "min/max launch failed: %s", hipGetErrorString(e));
+    *out = *vol;
+    out->minmax = d_minmax;
+    out->cell = cell;
+    return VI_OK;
+}
+
 uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf)
 {
     // FNV-1a over the identity of the inputs (pointers, sizes, dtype, scale)
@@ -228,6 +271,7 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     p.vol_dtype = vol->dtype;
     p.vol_layout = vol->layout;
     volume_strides(vol, &p.vsy, &p.vsz);
+    p.occ = occ_of(vol);
     p.N = vol->n;
     p.M = vol->n / 2;
     p.scale = vol->scale;
@@ -265,6 +309,24 @@ int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const 
               vi_stream_t stream)
 {
     clear_err();
+    vi::RenderFrame F;
+    int rc = vi::make_frame(vol, tf, sl, cam, mode, step_vox, opts, d_rgba, d_samples, &F);
+    if (rc != VI_OK) return rc;
+    hipError_t e = vi::launch_render(F, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VI_E_DEVICE, "render launch failed: %s", hipGetErrorString(e));
+    return VI_OK;
+}
+
+}  // extern "C"
+
+namespace vi {
+
+// Validate a render request and fill its kernel parameters (shared by
+// vi_render and the server, so a frame is computed identically by both).
+int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const vi_camera* cam, int mode,
+               float step_vox, const vi_render_opts* opts, float* d_rgba, unsigned long long* d_samples,
+               RenderFrame* out)
+{
     int rc;
     if ((rc = check_volume(vol)) != VI_OK) return rc;
     if ((rc = check_tf(tf)) != VI_OK) return rc;
@@ -295,12 +357,13 @@ int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const 
             return fail(VI_E_UNSUPPORTED, "stack exceeds 4 GiB");
     }
 
-    vi::RenderFrame F;
+    vi::RenderFrame& F = *out;
     memset(&F, 0, sizeof F);
     F.vol = vol->data;
     F.vol_dtype = vol->dtype;
     F.vol_layout = vol->layout;
     volume_strides(vol, &F.vsy, &F.vsz);
+    F.occ = occ_of(vol);
     F.N = vol->n;
     F.M = vol->n / 2;
     F.scale = vol->scale;
@@ -408,9 +471,13 @@ int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const 
     }
     F.out = (float4*)d_rgba;
     F.samples = d_samples;
-    hipError_t e = vi::launch_render(F, (hipStream_t)stream);
-    if (e != hipSuccess) return fail(VI_E_DEVICE, "render launch failed: %s", hipGetErrorString(e));
     return VI_OK;
 }
+
+int fail_msg(int code, const char* msg) { return fail(code, "%s", msg); }
+
+}  // namespace vi
+
+extern "C" {
 
 }  // extern "C"

@@ -22,8 +22,10 @@ constexpr int kBuildTile = 16;
 template <typename VT, int LAYOUT, int OUT_DTYPE>
 __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 {
-    extern __shared__ float s_alpha[];  // K entries
+    extern __shared__ float s_alpha[];  // K alphas, then K next-opaque indices
+    int* s_next = (int*)(s_alpha + P.K);
     for (int t = threadIdx.x; t < P.K; t += blockDim.x) s_alpha[t] = P.tf[4 * t + 3];
+    if (P.occ.mm) build_next_opaque(s_next, P.tf, P.K);
     __syncthreads();
 
     const uint32_t tiles_x = (P.res + kBuildTile - 1) / kBuildTile;
@@ -47,6 +49,8 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     float T = 1.0f;     // transmittance (F32 form)
     float tau = 0.0f;   // optical depth (BF16 form)
     const float ln2 = 0.69314718055994531f;
+    uint32_t last_cell = 0xffffffffu;
+    bool cell_is_empty = false;
 
     for (int k = 0; k < P.n; ++k) {
         const float kf = (float)k;
@@ -55,7 +59,18 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         const float hz = fmaf(kf, P.AL[2], hz0);
         // log2 of the slab's (1 - alpha)/e, 0 outside the cube (empty)
         float l2 = 0.0f;
-        if (hx >= P.lo && hx <= P.hi && hy >= P.lo && hy <= P.hi && hz >= P.lo && hz <= P.hi) {
+        bool fetch = hx >= P.lo && hx <= P.hi && hy >= P.lo && hy <= P.hi && hz >= P.lo && hz <= P.hi;
+        if (fetch && P.occ.mm) {
+            // empty-space map: a zero-opacity cell leaves T unchanged exactly
+            const uint32_t c = cell_of((int)floorf(hx) + P.M, (int)floorf(hy) + P.M, (int)floorf(hz) + P.M, P.N,
+                                       P.occ.shift, P.occ.nc);
+            if (c != last_cell) {
+                last_cell = c;
+                cell_is_empty = cell_empty(P.occ.mm[c], s_next, Km1, P.K);
+            }
+            fetch = !cell_is_empty;
+        }
+        if (fetch) {
             const float v = sample_volume<VT, LAYOUT>(vol, VI_, P.N, P.M, P.scale, hx, hy, hz);
             const float x = v * Km1;
             const int e0 = min((int)x, P.K - 2);
@@ -80,7 +95,7 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
 {
     const uint32_t tiles = (uint32_t)((p.res + kBuildTile - 1) / kBuildTile);
     dim3 grid(tiles * tiles), block(256);
-    const size_t lds = sizeof(float) * (size_t)p.K;
+    const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K;
     if (p.out_dtype == VI_F32)
         hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32>), grid, block, lds, s, p);
     else

@@ -101,6 +101,34 @@ __device__ __forceinline__ uint32_t stack_oj(int j, uint32_t row_tiles32)
     return ((uint32_t)j >> 2) * row_tiles32 + ((uint32_t)j & 3u) * 8u;
 }
 
+// Empty-space test.  s_next[e] = first transfer-function entry >= e with
+// non-zero opacity (K if none), built in LDS per workgroup.  A cell is empty
+// when no entry a value in [min, max] can interpolate between -- widened by
+// one entry on each side for rounding -- has opacity.
+__device__ __forceinline__ void build_next_opaque(int* s_next, const float* tf, int K)
+{
+    for (int e = threadIdx.x; e < K; e += blockDim.x) {
+        int j = e;
+        while (j < K && !(tf[4 * j + 3] > 0.0f)) ++j;
+        s_next[e] = j;
+    }
+}
+__device__ __forceinline__ bool cell_empty(const float2 m, const int* s_next, float Km1, int K)
+{
+    const int lo = max((int)(m.x * Km1) - 1, 0);
+    const int hi = min((int)(m.y * Km1) + 2, K - 1);
+    return s_next[lo] > hi;
+}
+// Cell index of a trilinear footprint whose lower corner is voxel (x0,y0,z0)
+// (before clamping).
+__device__ __forceinline__ uint32_t cell_of(int x0, int y0, int z0, int N, int shift, uint32_t nc)
+{
+    const uint32_t cx = (uint32_t)clampi(x0, 0, N - 1) >> shift;
+    const uint32_t cy = (uint32_t)clampi(y0, 0, N - 1) >> shift;
+    const uint32_t cz = (uint32_t)clampi(z0, 0, N - 1) >> shift;
+    return (cz * nc + cy) * nc + cx;
+}
+
 // Round a float to bfloat16 (nearest even), finite inputs.
 __device__ __forceinline__ uint16_t f32_to_bf16(float x)
 {

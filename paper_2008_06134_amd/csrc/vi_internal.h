@@ -18,11 +18,20 @@ constexpr int kMaxTaps = 49;     // largest gather (7 x 7 lattice)
 // Column (i,j) at slab k sits at h = B(i,j) + k * AL, with B evaluated in
 // double on the device once per column.
 // ---------------------------------------------------------------------------
+// Empty-space map: per cell of 2^shift voxels, (min, max) of the normalised
+// values over the cell's voxels and the next one along each axis.
+struct OccMap {
+    const float2* mm;   // nullptr: no skipping
+    int shift;
+    uint32_t nc;        // cells per axis
+};
+
 struct BuildParams {
     const void* vol;
     int vol_dtype;
     int vol_layout;
     uint32_t vsy, vsz;  // per-axis offset strides of the volume layout
+    OccMap occ;
     int N, M;
     float scale;
     const float* tf;   // K x 4
@@ -48,6 +57,7 @@ struct RenderFrame {
     int vol_dtype;
     int vol_layout;
     uint32_t vsy, vsz;
+    OccMap occ;
     int N, M;
     float scale;
     // transfer function
@@ -89,9 +99,17 @@ struct RenderFrame {
 // launchers (vi_build.hip / vi_render.hip / vi_layout.hip)
 hipError_t launch_build(const BuildParams& p, hipStream_t s);
 hipError_t launch_render(const RenderFrame& f, hipStream_t s);
+hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, const RenderFrame* d_frames,
+                               const uint32_t* d_tiles, uint32_t ntiles, int maxK, hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStream_t s);
+hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
+                         int shift, float* out, hipStream_t s);
 
 // host helpers shared by the API and the server
+int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const vi_camera* cam, int mode,
+               float step_vox, const vi_render_opts* opts, float* d_rgba, unsigned long long* d_samples,
+               RenderFrame* out);
+int fail_msg(int code, const char* msg);  // set the thread's vi_last_error message
 inline uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
 }  // namespace vi

@@ -43,4 +43,59 @@ hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStr
     }
 }
 
+// Empty-space map: one thread per cell, min/max of the normalised voxel
+// values over the cell's voxels plus one more along each axis (clamped).
+template <typename VT, int LAYOUT>
+__global__ __launch_bounds__(256) void minmax_kernel(const VT* __restrict__ vol, VolIndex I, int N, float scale,
+                                                     int shift, uint32_t nc, float2* __restrict__ out)
+{
+    const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+    if (c >= nc * nc * nc) return;
+    const int cx = (int)(c % nc), cy = (int)((c / nc) % nc), cz = (int)(c / (nc * nc));
+    const int B = 1 << shift;
+    const int x0 = cx * B, y0 = cy * B, z0 = cz * B;
+    const int x1 = min(x0 + B, N - 1), y1 = min(y0 + B, N - 1), z1 = min(z0 + B, N - 1);
+    float lo = 1.0f, hi = 0.0f;
+    for (int z = z0; z <= z1; ++z) {
+        const uint32_t oz = vol_oz<LAYOUT>(I, z);
+        for (int y = y0; y <= y1; ++y) {
+            const uint32_t oy = oz + vol_oy<LAYOUT>(I, y);
+            for (int x = x0; x <= x1; ++x) {
+                const float v = voxel_norm(vol, oy + vol_ox<LAYOUT>(I, x), scale);
+                lo = fminf(lo, v);
+                hi = fmaxf(hi, v);
+            }
+        }
+    }
+    out[c] = make_float2(lo, hi);
+}
+
+template <typename VT>
+static hipError_t launch_mm(const void* vol, int layout, VolIndex I, int N, float scale, int shift, float* out,
+                            hipStream_t s)
+{
+    const uint32_t nc = ((uint32_t)N + (1u << shift) - 1) >> shift;
+    const uint32_t cells = nc * nc * nc;
+    dim3 grid((cells + 255) / 256), block(256);
+    if (layout == VI_LAYOUT_BRICK4)
+        hipLaunchKernelGGL((minmax_kernel<VT, VI_LAYOUT_BRICK4>), grid, block, 0, s, (const VT*)vol, I, N, scale,
+                           shift, nc, (float2*)out);
+    else
+        hipLaunchKernelGGL((minmax_kernel<VT, VI_LAYOUT_LINEAR>), grid, block, 0, s, (const VT*)vol, I, N, scale,
+                           shift, nc, (float2*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
+                         int shift, float* out, hipStream_t s)
+{
+    const VolIndex I = {1u, vsy, vsz};
+    switch (dtype) {
+    case VI_U8: return launch_mm<uint8_t>(vol, layout, I, N, scale, shift, out, s);
+    case VI_U16: return launch_mm<uint16_t>(vol, layout, I, N, scale, shift, out, s);
+    case VI_F16: return launch_mm<__half>(vol, layout, I, N, scale, shift, out, s);
+    default: return launch_mm<float>(vol, layout, I, N, scale, shift, out, s);
+    }
+}
+
 }  // namespace vi

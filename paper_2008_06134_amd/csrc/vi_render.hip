@@ -129,8 +129,8 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
 }
 
 template <typename VT, int LAYOUT, int MODE, int SDT>
-__device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf, int px, int py,
-                                             uint32_t& nsamp)
+__device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf,
+                                             const int* __restrict__ s_next, int px, int py, uint32_t& nsamp)
 {
     // ---- camera ray (double)
     const double xn = 2.0 * (px + 0.5) / F.width - 1.0;
@@ -210,14 +210,26 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     const float Df = (float)D, dtf = (float)F.dt;
     const float Km1 = (float)(F.K - 1);
     float Cr = 0.f, Cg = 0.f, Cb = 0.f, ad = 0.f;
+    uint32_t last_cell = 0xffffffffu;
+    bool cell_is_empty = false;
     int k = 0;
     for (; k < K; ++k) {
         const float s0 = (float)k * dtf;
         const float s1 = fminf((float)(k + 1) * dtf, Df);
         const float len = s1 - s0;
         const float sm = 0.5f * (s0 + s1);
-        const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, fmaf(sm, hdx, hx0),
-                                                  fmaf(sm, hdy, hy0), fmaf(sm, hdz, hz0));
+        const float hx = fmaf(sm, hdx, hx0), hy = fmaf(sm, hdy, hy0), hz = fmaf(sm, hdz, hz0);
+        if (F.occ.mm) {
+            // empty-space map: a zero-opacity cell contributes nothing
+            const uint32_t c = cell_of((int)floorf(hx) + F.M, (int)floorf(hy) + F.M, (int)floorf(hz) + F.M, F.N,
+                                       F.occ.shift, F.occ.nc);
+            if (c != last_cell) {
+                last_cell = c;
+                cell_is_empty = cell_empty(F.occ.mm[c], s_next, Km1, F.K);
+            }
+            if (cell_is_empty) continue;
+        }
+        const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz);
         const float x = v * Km1;
         const int e0 = min((int)x, F.K - 2);
         const float w = x - (float)e0;
@@ -252,9 +264,11 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
 template <typename VT, int LAYOUT, int MODE, int SDT>
 __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
 {
-    extern __shared__ float4 s_tf[];  // K entries
+    extern __shared__ float4 s_tf[];  // K entries, then K next-opaque indices
+    int* s_next = (int*)(s_tf + F.K);
     for (int t = threadIdx.x; t < F.K; t += blockDim.x)
         s_tf[t] = make_float4(F.tf[4 * t], F.tf[4 * t + 1], F.tf[4 * t + 2], F.tf[4 * t + 3]);
+    if (F.occ.mm) build_next_opaque(s_next, F.tf, F.K);
     __syncthreads();
 
     const uint32_t tiles_x = (F.width + 15) / 16, tiles_y = (F.height + 15) / 16;
@@ -264,7 +278,7 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
     const int py = (int)(tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
     uint32_t ns = 0;
     if (px < F.width && py < F.height) {
-        const float4 c = render_ray<VT, LAYOUT, MODE, SDT>(F, s_tf, px, py, ns);
+        const float4 c = render_ray<VT, LAYOUT, MODE, SDT>(F, s_tf, s_next, px, py, ns);
         F.out[(size_t)py * F.width + px] = c;
     }
     if (F.samples) {
@@ -274,12 +288,83 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
     }
 }
 
+// --------------------------------------------------------------------------
+// batched kernel (serving): one workgroup per 16 x 16 tile of any frame of
+// the launch; the tile names its frame, whose parameters are read from
+// device memory.  Per pixel it runs the same render_ray as render_kernel, so
+// a frame is bit-identical alone and in a mix.
+// --------------------------------------------------------------------------
+template <typename VT, int LAYOUT, int SDT>
+__global__ __launch_bounds__(256) void render_batch_kernel(const RenderFrame* __restrict__ frames,
+                                                           const uint32_t* __restrict__ tiles, uint32_t ntiles)
+{
+    extern __shared__ float4 s_tf[];
+    const uint32_t b = xcd_swizzle(blockIdx.x, ntiles);
+    const uint32_t t = tiles[b];
+    const RenderFrame& F = frames[t >> 22];
+    int* s_next = (int*)(s_tf + F.K);
+    for (int i = threadIdx.x; i < F.K; i += blockDim.x)
+        s_tf[i] = make_float4(F.tf[4 * i], F.tf[4 * i + 1], F.tf[4 * i + 2], F.tf[4 * i + 3]);
+    if (F.occ.mm) build_next_opaque(s_next, F.tf, F.K);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int px = (int)(t & 2047u) * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = (int)((t >> 11) & 2047u) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    uint32_t ns = 0;
+    if (px < F.width && py < F.height) {
+        float4 c;
+        switch (F.mode) {
+        case VI_MODE_NONE: c = render_ray<VT, LAYOUT, VI_MODE_NONE, SDT>(F, s_tf, s_next, px, py, ns); break;
+        case VI_MODE_SHADOW: c = render_ray<VT, LAYOUT, VI_MODE_SHADOW, SDT>(F, s_tf, s_next, px, py, ns); break;
+        case VI_MODE_SHELL: c = render_ray<VT, LAYOUT, VI_MODE_SHELL, SDT>(F, s_tf, s_next, px, py, ns); break;
+        default: c = render_ray<VT, LAYOUT, VI_MODE_CONE, SDT>(F, s_tf, s_next, px, py, ns); break;
+        }
+        F.out[(size_t)py * F.width + px] = c;
+    }
+    if (F.samples) {
+        for (int off = 32; off > 0; off >>= 1) ns += __shfl_xor(ns, off);
+        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
+    }
+}
+
+template <typename VT, int LAYOUT, int SDT>
+static hipError_t launch_batch_t(const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
+                                 hipStream_t s)
+{
+    const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)maxK;
+    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT>), dim3(ntiles), dim3(256), lds, s, d_frames, d_tiles,
+                       ntiles);
+    return hipGetLastError();
+}
+
+template <typename VT>
+static hipError_t launch_batch_vt(int layout, int sdt, const RenderFrame* f, const uint32_t* t, uint32_t n, int K,
+                                  hipStream_t s)
+{
+    if (layout == VI_LAYOUT_BRICK4)
+        return sdt == VI_BF16 ? launch_batch_t<VT, VI_LAYOUT_BRICK4, VI_BF16>(f, t, n, K, s)
+                              : launch_batch_t<VT, VI_LAYOUT_BRICK4, VI_F32>(f, t, n, K, s);
+    return sdt == VI_BF16 ? launch_batch_t<VT, VI_LAYOUT_LINEAR, VI_BF16>(f, t, n, K, s)
+                          : launch_batch_t<VT, VI_LAYOUT_LINEAR, VI_F32>(f, t, n, K, s);
+}
+
+hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, const RenderFrame* d_frames,
+                               const uint32_t* d_tiles, uint32_t ntiles, int maxK, hipStream_t s)
+{
+    switch (vol_dtype) {
+    case VI_U8: return launch_batch_vt<uint8_t>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_U16: return launch_batch_vt<uint16_t>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_F16: return launch_batch_vt<__half>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
+    default: return launch_batch_vt<float>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
+    }
+}
+
 template <typename VT, int LAYOUT, int SDT>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
     const uint32_t tiles = (uint32_t)(((f.width + 15) / 16) * ((f.height + 15) / 16));
     dim3 grid(tiles), block(256);
-    const size_t lds = sizeof(float4) * (size_t)f.K;
+    const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K;
     switch (f.mode) {
     case VI_MODE_NONE:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_NONE, SDT>), grid, block, lds, s, f);

@@ -33,7 +33,7 @@ VI_LAYOUT_LINEAR, VI_LAYOUT_BRICK4 = 0, 1
 
 class Volume_t(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("n", C.c_int), ("scale", C.c_float),
-                ("layout", C.c_int)]
+                ("layout", C.c_int), ("minmax", C.c_void_p), ("cell", C.c_int)]
 
 
 class TF_t(C.Structure):
@@ -58,6 +58,25 @@ class RenderOpts_t(C.Structure):
                 ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_float)]
 
 
+class ServerCfg_t(C.Structure):
+    _fields_ = [("stack_budget", C.c_size_t), ("max_inflight", C.c_int), ("tiles_per_launch", C.c_int),
+                ("device", C.c_int)]
+
+
+class Request_t(C.Structure):
+    _fields_ = [("vol_id", C.c_int), ("light_dir", C.c_double * 3), ("n_slices", C.c_int), ("slice_res", C.c_int),
+                ("slice_dtype", C.c_int), ("camera", Camera_t), ("mode", C.c_int), ("step_vox", C.c_float),
+                ("opts", RenderOpts_t), ("d_rgba", C.c_void_p), ("d_samples", C.c_void_p)]
+
+
+class Stats_t(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "rejected", "cancelled", "stack_hits",
+                                          "stack_builds", "evictions", "launches", "tiles")] + \
+               [(k, C.c_double) for k in ("mean_frames_per_launch", "p50_ms", "p99_ms", "mean_ms", "max_ms",
+                                          "frames_per_s")] + \
+               [(k, C.c_size_t) for k in ("pool_bytes", "pool_in_use", "pool_peak")]
+
+
 # every symbol declared in include/vi.h, with its ctypes signature
 SIGNATURES = {
     "vi_version": ([], C.c_char_p),
@@ -66,12 +85,23 @@ SIGNATURES = {
     "vi_slices_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
     "vi_volume_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
     "vi_volume_to_bricks": ([C.POINTER(Volume_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
+    "vi_volume_minmax_bytes": ([C.c_int, C.c_int], C.c_size_t),
+    "vi_volume_minmax": ([C.POINTER(Volume_t), C.c_int, C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.POINTER(Slices_t)], C.c_int),
     "vi_build_attenuation": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_double), C.c_int, C.c_int,
                               C.c_int, C.c_void_p, C.POINTER(Slices_t), C.c_void_p], C.c_int),
     "vi_render": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(Slices_t), C.POINTER(Camera_t), C.c_int,
                    C.c_float, C.POINTER(RenderOpts_t), C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "vi_tag": ([C.POINTER(Volume_t), C.POINTER(TF_t)], C.c_uint64),
+    "vi_server_create": ([C.POINTER(ServerCfg_t), C.POINTER(C.c_void_p)], C.c_int),
+    "vi_server_register_volume": ([C.c_void_p, C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_int)], C.c_int),
+    "vi_server_submit": ([C.c_void_p, C.POINTER(Request_t), C.POINTER(C.c_uint64)], C.c_int),
+    "vi_server_poll": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_int)], C.c_int),
+    "vi_server_wait": ([C.c_void_p, C.c_uint64, C.c_int], C.c_int),
+    "vi_server_cancel": ([C.c_void_p, C.c_uint64], C.c_int),
+    "vi_server_stats": ([C.c_void_p, C.POINTER(Stats_t)], C.c_int),
+    "vi_server_reset_stats": ([C.c_void_p], C.c_int),
+    "vi_server_destroy": ([C.c_void_p], None),
 }
 
 _lib = None
@@ -136,7 +166,8 @@ class Volume:
         self.n = int(n)
         self.layout = layout
         self.scale = float(_DEFAULT_SCALE[self.dtype] if scale is None else scale)
-        self.s = Volume_t(self.data.data_ptr(), self.dtype, self.n, self.scale, layout)
+        self.minmax = None
+        self.s = Volume_t(self.data.data_ptr(), self.dtype, self.n, self.scale, layout, None, 0)
 
     @staticmethod
     def from_numpy(raw, device="cuda", scale=None) -> "Volume":
@@ -157,6 +188,21 @@ class Volume:
         res = Volume_t()
         _check(lib().vi_volume_to_bricks(C.byref(self.s), C.c_void_p(out.data_ptr()), C.byref(res), _stream(stream)))
         return Volume(out, self.scale, self.n, VI_LAYOUT_BRICK4)
+
+    def with_minmax(self, cell: int = 8, out: torch.Tensor | None = None, stream=None) -> "Volume":
+        """The same volume with an empty-space map of `cell`^3-voxel cells (vi_volume_minmax)."""
+        nbytes = int(lib().vi_volume_minmax_bytes(self.n, cell))
+        if nbytes == 0:
+            raise ValueError("invalid cell size")
+        if out is None:
+            out = torch.empty(nbytes // 4, dtype=torch.float32, device=self.data.device)
+        res = Volume_t()
+        _check(lib().vi_volume_minmax(C.byref(self.s), int(cell), C.c_void_p(out.data_ptr()), C.byref(res),
+                                      _stream(stream)))
+        v = Volume(self.data, self.scale, self.n, self.layout)
+        v.minmax = out
+        v.s = res
+        return v
 
 
 class TF:
@@ -313,3 +359,88 @@ def header_symbols() -> list:
     text = open(hdr).read()
     return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(vi_\w+)\s*\(", text, flags=re.M)))
 
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+REQ_PENDING, REQ_ADMITTED, REQ_DONE = 0, 1, 2
+
+
+class Server:
+    """The continuous-batching request loop of libvi (vi_server_*).
+
+    Volumes and transfer functions are registered once and stay resident;
+    each request names a volume, a light (n, res) and a camera/mode, and
+    renders into its own device image.  Stacks are cached in a device pool of
+    `stack_budget` bytes and reused while the light is unchanged."""
+
+    def __init__(self, stack_budget: int, max_inflight: int = 16, tiles_per_launch: int = 8192, device: int = 0):
+        cfg = ServerCfg_t(int(stack_budget), int(max_inflight), int(tiles_per_launch), int(device))
+        h = C.c_void_p()
+        _check(lib().vi_server_create(C.byref(cfg), C.byref(h)))
+        self.h = h
+        self._keep = {}     # ticket -> tensors that must outlive the request
+        self._vols = []
+
+    def register(self, vol: Volume, tf: TF) -> int:
+        vid = C.c_int()
+        _check(lib().vi_server_register_volume(self.h, C.byref(vol.s), C.byref(tf.s), C.byref(vid)))
+        self._vols.append((vol, tf))
+        return vid.value
+
+    def submit(self, vol_id: int, light_dir, n_slices: int, slice_res: int, cam: dict, mode: str,
+               step_vox: float, opts: dict | None = None, out: torch.Tensor | None = None,
+               samples: torch.Tensor | None = None, dtype: int = VI_F32, device="cuda") -> tuple:
+        W, H = int(cam["width"]), int(cam["height"])
+        if out is None:
+            out = torch.empty((H, W, 4), dtype=torch.float32, device=device)
+        r = Request_t()
+        r.vol_id = int(vol_id)
+        r.light_dir = _vec3(light_dir)
+        r.n_slices, r.slice_res, r.slice_dtype = int(n_slices), int(slice_res), int(dtype)
+        r.camera = camera(cam)
+        r.mode = MODES[mode]
+        r.step_vox = float(step_vox)
+        r.opts = render_opts(opts)
+        r.d_rgba = out.data_ptr()
+        r.d_samples = samples.data_ptr() if samples is not None else None
+        t = C.c_uint64()
+        _check(lib().vi_server_submit(self.h, C.byref(r), C.byref(t)))
+        self._keep[t.value] = (out, samples)
+        return t.value, out
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int()
+        _check(lib().vi_server_poll(self.h, int(ticket), C.byref(st)))
+        return st.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> int:
+        rc = lib().vi_server_wait(self.h, int(ticket), int(timeout_ms))
+        if rc != -5:
+            self._keep.pop(ticket, None)
+        return rc
+
+    def cancel(self, ticket: int) -> int:
+        return lib().vi_server_cancel(self.h, int(ticket))
+
+    def stats(self) -> dict:
+        s = Stats_t()
+        _check(lib().vi_server_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats_t._fields_}
+
+    def reset_stats(self):
+        _check(lib().vi_server_reset_stats(self.h))
+
+    def close(self):
+        if self.h:
+            lib().vi_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -197,3 +197,20 @@ def test_volume_bytes_and_brick_validation():
     assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -2
     # stack buffers are padded to whole 8 x 4 tiles
     assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4
+
+
+def test_minmax_validation():
+    lib = vi.lib()
+    assert lib.vi_volume_minmax_bytes(512, 8) == 64 ** 3 * 8
+    assert lib.vi_volume_minmax_bytes(33, 8) == 5 ** 3 * 8
+    assert lib.vi_volume_minmax_bytes(33, 5) == 0
+    v = vi.Volume_t(0x10000, vi.VI_U16, 16, 1 / 4095, 0, None, 0)
+    out = vi.Volume_t()
+    assert lib.vi_volume_minmax(C.byref(v), 6, C.c_void_p(0x20000), C.byref(out), None) == -1
+    assert lib.vi_volume_minmax(C.byref(v), 8, None, C.byref(out), None) == -1
+    assert lib.vi_volume_minmax(C.byref(v), 8, C.c_void_p(0x20004), C.byref(out), None) == -1
+    # a volume that claims a map with a bad cell size is rejected by every call
+    v.minmax, v.cell = 0x30000, 12
+    f = _Fake()
+    f.vol = v
+    assert _build(f) == -1

@@ -28,11 +28,14 @@ def _mode(m):
     return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
 
 
-def gpu_inputs(raw, tab, scale=None, bricks=True):
-    """Device volume (4x4x4 bricks unless asked otherwise, as the benchmark runs) and TF."""
+def gpu_inputs(raw, tab, scale=None, bricks=True, cell=8):
+    """Device volume -- by default as the benchmark runs it: 4x4x4 bricks with an
+    empty-space map of 8^3-voxel cells -- and TF."""
     vol = vi.Volume.from_numpy(raw, DEV, scale)
     if bricks:
         vol = vol.to_bricks()
+    if cell:
+        vol = vol.with_minmax(cell)
     return vol, vi.TF.from_numpy(tab, DEV)
 
 
@@ -258,7 +261,7 @@ def test_brick_layout_matches_its_definition(N):
 def test_bricked_volume_gives_bitwise_identical_results(N, n, res, mode):
     raw = W.sphere_u8(N, radius=N * 0.35, density=180, noise=30, seed=N + 1)
     tab = W.tf_ramp()
-    lin, tf = gpu_inputs(raw, tab, bricks=False)
+    lin, tf = gpu_inputs(raw, tab, bricks=False, cell=0)
     br = lin.to_bricks()
     light = [0.6, -0.3, -0.74]
     s1 = vi.build_attenuation(lin, tf, light, n, res)
@@ -272,6 +275,31 @@ def test_bricked_volume_gives_bitwise_identical_results(N, n, res, mode):
     b = vi.render(br, tf, s2, cam, m, 0.5, extra)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("cell", [4, 8, 32])
+@pytest.mark.parametrize("mode", ["shell", "cone5", "none"])
+def test_empty_space_map_changes_nothing(cell, mode):
+    """Skipping zero-opacity cells must give bit-identical stacks, images and counts."""
+    raw = W.ct_phantom_u16(48, seed=5, vessels=True)
+    tab = W.tf_ct()
+    plain, tf = gpu_inputs(raw, tab, cell=0)
+    mapped = plain.with_minmax(cell)
+    light = [0.3, 0.4, -0.86]
+    s1 = vi.build_attenuation(plain, tf, light, 40, 72)
+    s2 = vi.build_attenuation(mapped, tf, light, 40, 72)
+    torch.cuda.synchronize()
+    assert torch.equal(s1.dense(), s2.dense())
+    m, extra = _mode(mode)
+    cam = W.camera_orbit(90, 60, 0.7, 0.3)
+    a, na = gpu_render(plain, tf, s1, cam, m, 0.5, extra)
+    b, nb = gpu_render(mapped, tf, s1, cam, m, 0.5, extra)
+    assert np.array_equal(a, b) and na == nb
+    # with small cells the map does mark some cells empty (and others not)
+    mm = mapped.minmax.view(-1, 2).cpu().numpy()
+    assert (mm[:, 1] >= 0.2).any()
+    if cell <= 8:
+        assert (mm[:, 1] < 0.2).any()
 
 
 def test_stack_is_camera_independent_and_deterministic():

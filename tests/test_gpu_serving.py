@@ -1,0 +1,125 @@
+"""Serving on the GPU: every frame served in a mix equals the same frame rendered
+alone with vi_render (bit for bit), stacks are reused while the light is
+unchanged, eviction under a small pool keeps results right, and the server
+drains cleanly."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2008_06134_amd import vi
+from paper_2008_06134_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _volumes():
+    vols = []
+    for k, N in enumerate([48, 64, 80, 96]):
+        raw = W.ct_phantom_u16(N, seed=100 + k, vessels=(k % 2 == 1))
+        v = vi.Volume.from_numpy(raw, DEV).to_bricks().with_minmax(8)
+        vols.append((N, v, vi.TF.from_numpy(W.tf_ct(), DEV)))
+    return vols
+
+
+def _requests(vols, count, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [(64, 48), (96, 96), (128, 72), (80, 112), (33, 17)]
+    reqs = []
+    for i in range(count):
+        vi_ = int(rng.integers(len(vols)))
+        N = vols[vi_][0]
+        li = int(rng.integers(3))
+        light = W.light_from_angles(2 * math.pi * li / 3 + 0.1 * vi_, math.radians(35))
+        w, h = sizes[int(rng.integers(len(sizes)))]
+        cam = W.camera_orbit(w, h, float(rng.uniform(0, 2 * math.pi)), math.radians(20))
+        mode = ["shell", "cone", "cone5", "shadow"][int(rng.integers(4))]
+        reqs.append(dict(vol=vi_, light=light, n=N, res=min(2 * N, 1024), cam=cam, mode=mode))
+    return reqs
+
+
+def _alone(vols, r):
+    _, v, tf = vols[r["vol"]]
+    st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"])
+    m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
+    cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+    img = vi.render(v, tf, st, r["cam"], m, 0.5, extra, samples=cnt)
+    torch.cuda.synchronize()
+    return img.clone(), int(cnt.item())
+
+
+def _submit(srv, ids, r, samples=None):
+    m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
+    return srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], m, 0.5, extra, samples=samples)
+
+
+def test_mixed_burst_equals_frames_rendered_alone():
+    vols = _volumes()
+    reqs = _requests(vols, 40, seed=1)
+    srv = vi.Server(stack_budget=256 << 20, max_inflight=12, tiles_per_launch=64)
+    ids = [srv.register(v, tf) for _, v, tf in vols]
+    counters = [torch.zeros(1, dtype=torch.int64, device=DEV) for _ in reqs]
+    subs = [_submit(srv, ids, r, counters[i]) for i, r in enumerate(reqs)]
+    for t, _ in subs:
+        assert srv.wait(t, 60000) == 0
+    torch.cuda.synchronize()
+    st = srv.stats()
+    print(f"[serving] {st['completed']} frames, {st['launches']} launches, "
+          f"{st['mean_frames_per_launch']:.2f} frames/launch, hits {st['stack_hits']} builds {st['stack_builds']}",
+          flush=True)
+    assert st["completed"] == len(reqs)
+    assert st["mean_frames_per_launch"] > 1.0          # launches really mix frames
+    assert st["stack_hits"] > 0                         # the light repeats: stacks are reused
+    for i, r in enumerate(reqs):
+        ref, n_ref = _alone(vols, r)
+        assert torch.equal(subs[i][1], ref), f"request {i} differs from its standalone render"
+        assert int(counters[i].item()) == n_ref
+    srv.close()
+
+
+def test_small_pool_evicts_and_stays_correct():
+    vols = _volumes()
+    reqs = _requests(vols, 16, seed=2)
+    biggest = max(vi.slices_bytes(r["n"], r["res"]) for r in reqs)
+    srv = vi.Server(stack_budget=biggest + 4096, max_inflight=4, tiles_per_launch=32)
+    ids = [srv.register(v, tf) for _, v, tf in vols]
+    subs = [_submit(srv, ids, r) for r in reqs]
+    for t, _ in subs:
+        assert srv.wait(t, 60000) == 0
+    st = srv.stats()
+    assert st["evictions"] > 0 and st["pool_peak"] <= st["pool_bytes"]
+    for i, r in enumerate(reqs):
+        ref, _ = _alone(vols, r)
+        assert torch.equal(subs[i][1], ref)
+    srv.close()
+
+
+def test_oversized_and_invalid_requests_are_refused():
+    vols = _volumes()
+    srv = vi.Server(stack_budget=1 << 20, max_inflight=2)
+    ids = [srv.register(v, tf) for _, v, tf in vols]
+    cam = W.camera_orbit(32, 32, 0.3, 0.3)
+    with pytest.raises(vi.VIError) as e:
+        srv.submit(ids[0], [0, 0, 1], 64, 256, cam, "shell", 0.5)    # 16 MiB stack > 1 MiB pool
+    assert e.value.code == -3
+    with pytest.raises(vi.VIError):
+        srv.submit(ids[0], [0, 0, 0], 8, 8, cam, "shell", 0.5)       # degenerate light
+    t, img = srv.submit(ids[0], [0, 0, 1], 8, 16, cam, "shell", 0.5)
+    assert srv.wait(t, 30000) == 0
+    assert srv.stats()["rejected"] == 1
+    srv.close()
+
+
+def test_destroy_drains_queued_work():
+    vols = _volumes()
+    reqs = _requests(vols, 12, seed=3)
+    srv = vi.Server(stack_budget=256 << 20, max_inflight=2, tiles_per_launch=16)
+    ids = [srv.register(v, tf) for _, v, tf in vols]
+    subs = [_submit(srv, ids, r) for r in reqs]
+    srv.close()                         # must finish every queued frame first
+    torch.cuda.synchronize()
+    for i in (0, len(reqs) - 1):
+        ref, _ = _alone(vols, reqs[i])
+        assert torch.equal(subs[i][1], ref)
