@@ -31,26 +31,176 @@ def log(*a):
 
 
 def cpu_baseline(w, raw, tab, light, cam, modes, opts, stride, nthreads=0):
-    """The FP64 oracle on a stratified pixel sample of the same frames (stack
-    columns built on demand), timed on the host cores."""
+    """The FP64 oracle timed on the host cores on one step of the same workload:
+    the full attenuation build, then the step's frames on a stratified pixel
+    sample (every `stride`-th row and column); the frame time is scaled up by
+    the sampled fraction.  Rate = step samples / step time."""
     from oracle import oracle as O
     ovol, otf = O.Volume(raw), O.TF(tab)
     Wd, Hd = cam["width"], cam["height"]
     ys, xs = np.meshgrid(np.arange(stride // 2, Hd, stride), np.arange(stride // 2, Wd, stride), indexing="ij")
     pix = (ys * Wd + xs).ravel().astype(np.int64)
-    t0 = time.perf_counter()
+    frac = pix.size / (Wd * Hd)
     st = O.Stack(ovol, otf, light, w.n_slices, w.res)
+    t0 = time.perf_counter()
+    st.fill(nthreads)
+    t_build = time.perf_counter() - t0
     samples = 0
+    t0 = time.perf_counter()
     for m in modes:
         mm, extra = (m, {}) if m != "cone5" else ("cone", {"cone_grid": 5})
         _, _, nt, _ = O.render(ovol, otf, st, cam, mm, w.step_vox, {**opts, **extra}, pixels=pix,
                                want_full=False, nthreads=nthreads)
         samples += int(nt.sum())
-    dt = time.perf_counter() - t0
-    return {"value": samples / dt, "unit": "samples/s", "cores": O.threads(), "kind": "oracle",
-            "sample": (f"{pix.size} of {Wd * Hd} pixels (every {stride}th row and column) of the "
-                       f"{'+'.join(modes)} frames of light 0, {st.columns_built()} of {w.res ** 2} stack columns "
-                       f"built on demand; {samples} samples in {dt:.1f} s")}
+    t_render = time.perf_counter() - t0
+    step_time = t_build + t_render / frac
+    return {"value": round(samples / frac / step_time, 1), "unit": "samples/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": (f"light 0 of the large workload: full FP64 build of {w.res}^2 columns x {w.n_slices} slabs "
+                       f"in {t_build:.1f} s, then the {'+'.join(modes)} frames on {pix.size} of {Wd * Hd} pixels "
+                       f"(every {stride}th row and column, {samples} samples) in {t_render:.1f} s; the frame time "
+                       f"is scaled by 1/{frac:.3f}: {step_time:.1f} s per step")}
+
+
+# ---------------------------------------------------------------------------
+# serving: continuous batching vs sequential plain renders, Poisson arrivals
+# ---------------------------------------------------------------------------
+
+def _outputs(reqs, dev, per_size=8):
+    """A small ring of output images per image size (the bench never reads them)."""
+    import torch
+    rings, outs = {}, []
+    for r in reqs:
+        key = (r["cam"]["height"], r["cam"]["width"])
+        ring = rings.setdefault(key, {"bufs": [], "i": 0})
+        if len(ring["bufs"]) < per_size:
+            ring["bufs"].append(torch.empty((*key, 4), dtype=torch.float32, device=dev))
+        outs.append(ring["bufs"][ring["i"] % len(ring["bufs"])])
+        ring["i"] += 1
+    return outs
+
+
+def serve(vols, reqs, budget, max_inflight=16, tiles=8192, dev="cuda:0"):
+    """Submit `reqs` at their arrival times to the continuous-batching server."""
+    import torch
+    from paper_2008_06134_amd import vi
+    srv = vi.Server(budget, max_inflight, tiles)
+    ids = [srv.register(v, tf) for v, tf in vols]
+    outs = _outputs(reqs, dev)
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.perf_counter()
+    for r, o in zip(reqs, outs):
+        dt = t0 + r["arrival"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        t, _ = srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], r["mode"], 0.5, out=o)
+        tickets.append(t)
+    for t in tickets:
+        rc = srv.wait(t)
+        if rc != 0:
+            raise RuntimeError(f"request failed with {rc}")
+    st = srv.stats()
+    srv.close()
+    return {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "frames_per_s": round(st["frames_per_s"], 2), "stack_hits": st["stack_hits"],
+            "stack_builds": st["stack_builds"], "evictions": st["evictions"],
+            "frames_per_launch": round(st["mean_frames_per_launch"], 2)}
+
+
+def sequential(vols, reqs, budget, reuse=True, dev="cuda:0"):
+    """The plain per-frame renderer, one request at a time in arrival order, with
+    the same resident volumes and (if `reuse`) an LRU stack cache of `budget` bytes."""
+    import collections
+    import torch
+    from paper_2008_06134_amd import vi
+    outs = _outputs(reqs, dev)
+    cache, used = collections.OrderedDict(), 0
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r, o in zip(reqs, outs):
+        arrival = t0 + r["arrival"]
+        dt = arrival - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        v, tf = vols[r["vol"]]
+        key = (r["vol"], tuple(r["light"]), r["n"], r["res"])
+        st = cache.get(key) if reuse else None
+        if st is not None:
+            cache.move_to_end(key)
+        else:
+            need = vi.slices_bytes(r["n"], r["res"])
+            while reuse and cache and used + need > budget:
+                _, old = cache.popitem(last=False)
+                used -= vi.slices_bytes(old.n, old.res)
+            st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"])
+            if reuse:
+                cache[key] = st
+                used += need
+        vi.render(v, tf, st, r["cam"], r["mode"], 0.5, out=o)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - arrival) * 1e3)
+    span = time.perf_counter() - t0 - reqs[0]["arrival"]
+    lat = np.array(lat)
+    return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "frames_per_s": round(len(reqs) / span, 2)}
+
+
+def serving_inputs(vol_sizes, dev, vessels=True):
+    from paper_2008_06134_amd import vi
+    from paper_2008_06134_amd import workloads as W
+    tab = W.tf_ct()
+    vols = []
+    for i, N in enumerate(vol_sizes):
+        raw = W.serving_volume(N, i, vessels=vessels)
+        vols.append((vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(8), vi.TF.from_numpy(tab, dev)))
+    return vols
+
+
+def serving_capacity(vols, vol_sizes, budget, count=200, seed=99):
+    """Sequential plain renders back to back (all requests present at t=0): frames/s."""
+    from paper_2008_06134_amd import workloads as W
+    reqs = W.serving_requests(count, vol_sizes, 1e9, seed=seed)
+    for r in reqs:
+        r["arrival"] = 0.0
+    sequential(vols, reqs[:20], budget)          # warm-up
+    return sequential(vols, reqs, budget)["frames_per_s"]
+
+
+def serving_quick(dev, budget=16 << 30, count=300):
+    """The default bench's serving leg: 8 resident volumes 128^3-320^3, Poisson
+    arrivals at 0.9x the sequential capacity."""
+    from paper_2008_06134_amd import workloads as W
+    sizes = [128, 192, 256, 320, 128, 192, 256, 320]
+    vols = serving_inputs(sizes, dev, vessels=False)
+    cap = serving_capacity(vols, sizes, budget)
+    rate = 0.9 * cap
+    reqs = W.serving_requests(count, sizes, rate, seed=5)
+    serve(vols, reqs[:30], budget)                 # warm-up
+    out = {"volumes": "8 resident u16 phantoms 128^3-320^3 (bricks + empty-space map)",
+           "requests": count, "rate_hz": round(rate, 2), "sequential_capacity_fps": cap,
+           "served": serve(vols, reqs, budget), "sequential": sequential(vols, reqs, budget)}
+    return out
+
+
+def serving_sweep(dev, budget=48 << 30, count=2000, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
+    from paper_2008_06134_amd import workloads as W
+    sizes = W.serving_volume_sizes(64)
+    t0 = time.perf_counter()
+    vols = serving_inputs(sizes, dev)
+    log(f"64 serving volumes generated in {time.perf_counter() - t0:.0f} s")
+    cap = serving_capacity(vols, sizes, budget)
+    log(f"sequential capacity {cap:.1f} frames/s")
+    rows = []
+    for f in rates:
+        reqs = W.serving_requests(count, sizes, f * cap, seed=int(100 * f))
+        row = {"rate_x": f, "rate_hz": round(f * cap, 2), "served": serve(vols, reqs, budget),
+               "sequential": sequential(vols, reqs, budget),
+               "sequential_no_reuse": sequential(vols, reqs, budget, reuse=False)}
+        log(json.dumps(row))
+        rows.append(row)
+    return {"volumes": 64, "volume_edges": sizes, "requests_per_rate": count, "capacity_fps": cap, "rows": rows}
 
 
 def main():
@@ -61,6 +211,9 @@ def main():
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=2)
+    ap.add_argument("--no-serving", action="store_true", help="skip the short serving leg")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -81,6 +234,11 @@ def main():
     import torch
     from paper_2008_06134_amd import vi
     from paper_2008_06134_amd import workloads as W
+
+    if args.serving_sweep:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving_sweep": serving_sweep("cuda:0")}), flush=True)
+        return
 
     w = W.WORKLOADS[args.workload]
     t0 = time.perf_counter()
@@ -184,6 +342,11 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if not args.no_serving:
+        log("serving leg ...")
+        del stack, imgs
+        torch.cuda.empty_cache()
+        result["serving"] = serving_quick("cuda:0")
     if not args.no_cpu_baseline:
         log("timing the oracle on a pixel sample ...")
         opts = {}

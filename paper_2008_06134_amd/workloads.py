@@ -303,3 +303,53 @@ WORKLOADS = {
     "large": Workload("large", 512, 512, 1024, 0.5, ["shell", "cone"], seed=3),
     "precision": Workload("precision", 1024, 512, 1024, 0.5, ["shell", "cone"], seed=4),
 }
+
+
+# --------------------------------------------------------------------------
+# serving workload: a Poisson stream over many resident volumes
+# --------------------------------------------------------------------------
+
+SERVING_IMAGE_SIZES = [(512, 512), (1024, 768), (1280, 720), (1024, 1024), (1920, 1080)]
+
+
+def serving_volume_sizes(count: int = 64, seed: int = 5, sizes=(128, 192, 256, 320, 384, 448, 512)) -> list:
+    rng = np.random.default_rng(seed)
+    return [int(s) for s in rng.choice(sizes, size=count)]
+
+
+def serving_volume(N: int, index: int, seed: int = 5, vessels: bool = True) -> np.ndarray:
+    """Volume `index` of the serving set: the CT phantom generator with its own seed."""
+    return ct_phantom_u16(N, seed=seed * 1000 + index, vessels=vessels)
+
+
+def serving_requests(count: int, vol_sizes: list, rate_hz: float, seed: int = 5,
+                     image_sizes=SERVING_IMAGE_SIZES) -> list:
+    """`count` requests with exponential inter-arrival times of mean 1/rate_hz.
+
+    Each request picks a volume uniformly; every volume keeps a session whose
+    camera orbits 2 degrees per frame and whose light moves to a new seeded
+    direction every U{1..10} of its frames; image size uniform over
+    `image_sizes`; shell / cone 50/50.  Slab count n = N, slice resolution
+    min(2N, 1024)."""
+    rng = np.random.default_rng(seed)
+    nv = len(vol_sizes)
+    sess = [{"frame": 0, "az": float(rng.uniform(0, 2 * math.pi)), "left": int(rng.integers(1, 11)),
+             "light": light_from_angles(float(rng.uniform(0, 2 * math.pi)), math.radians(35 + rng.uniform(-5, 5)))}
+            for _ in range(nv)]
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += float(rng.exponential(1.0 / rate_hz))
+        v = int(rng.integers(nv))
+        s = sess[v]
+        if s["left"] == 0:
+            s["light"] = light_from_angles(float(rng.uniform(0, 2 * math.pi)), math.radians(35 + rng.uniform(-5, 5)))
+            s["left"] = int(rng.integers(1, 11))
+        s["left"] -= 1
+        W_, H_ = image_sizes[int(rng.integers(len(image_sizes)))]
+        cam = camera_orbit(W_, H_, s["az"] + math.radians(2.0) * s["frame"], math.radians(20.0))
+        s["frame"] += 1
+        N = vol_sizes[v]
+        out.append({"arrival": t, "vol": v, "light": list(s["light"]), "n": N, "res": min(2 * N, 1024),
+                    "cam": cam, "mode": "shell" if rng.random() < 0.5 else "cone"})
+    return out
