@@ -210,25 +210,57 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     const float Df = (float)D, dtf = (float)F.dt;
     const float Km1 = (float)(F.K - 1);
     float Cr = 0.f, Cg = 0.f, Cb = 0.f, ad = 0.f;
+    // Empty-space traversal: per-axis inverse step and cell edge.  A lane in a
+    // zero-opacity cell jumps to the last segment midpoint that lies inside
+    // that cell by a margin of kEps voxels (far above the float position
+    // error), so no segment with non-zero opacity is ever skipped.
+    const float kEps = 0.02f;
+    const float ihx = hdx != 0.f ? 1.0f / hdx : 0.f, ihy = hdy != 0.f ? 1.0f / hdy : 0.f,
+                ihz = hdz != 0.f ? 1.0f / hdz : 0.f;
+    const int B = 1 << F.occ.shift, last_c = (int)F.occ.nc - 1;
     uint32_t last_cell = 0xffffffffu;
     bool cell_is_empty = false;
     int k = 0;
-    for (; k < K; ++k) {
-        const float s0 = (float)k * dtf;
-        const float s1 = fminf((float)(k + 1) * dtf, Df);
-        const float len = s1 - s0;
-        const float sm = 0.5f * (s0 + s1);
-        const float hx = fmaf(sm, hdx, hx0), hy = fmaf(sm, hdy, hy0), hz = fmaf(sm, hdz, hz0);
-        if (F.occ.mm) {
-            // empty-space map: a zero-opacity cell contributes nothing
-            const uint32_t c = cell_of((int)floorf(hx) + F.M, (int)floorf(hy) + F.M, (int)floorf(hz) + F.M, F.N,
-                                       F.occ.shift, F.occ.nc);
+    while (k < K) {
+        float len, sm, hx, hy, hz;
+        // advance over zero-opacity cells to this lane's next candidate segment
+        for (;;) {
+            const float s0 = (float)k * dtf;
+            const float s1 = fminf((float)(k + 1) * dtf, Df);
+            len = s1 - s0;
+            sm = 0.5f * (s0 + s1);
+            hx = fmaf(sm, hdx, hx0);
+            hy = fmaf(sm, hdy, hy0);
+            hz = fmaf(sm, hdz, hz0);
+            if (!F.occ.mm) break;
+            const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1), gy = clampi((int)floorf(hy) + F.M, 0, F.N - 1),
+                      gz = clampi((int)floorf(hz) + F.M, 0, F.N - 1);
+            const int cx = gx >> F.occ.shift, cy = gy >> F.occ.shift, cz = gz >> F.occ.shift;
+            const uint32_t c = ((uint32_t)cz * F.occ.nc + (uint32_t)cy) * F.occ.nc + (uint32_t)cx;
             if (c != last_cell) {
                 last_cell = c;
                 cell_is_empty = cell_empty(F.occ.mm[c], s_next, Km1, F.K);
             }
-            if (cell_is_empty) continue;
+            if (!cell_is_empty) break;
+            // distance along the ray to the cell's faces moved inward by kEps
+            // (faces of edge cells toward the outside are at infinity)
+            float se = 3.4e38f;
+            const float lox = (float)(cx * B - F.M) + kEps, hix = (float)((cx + 1) * B - F.M) - kEps;
+            const float loy = (float)(cy * B - F.M) + kEps, hiy = (float)((cy + 1) * B - F.M) - kEps;
+            const float loz = (float)(cz * B - F.M) + kEps, hiz = (float)((cz + 1) * B - F.M) - kEps;
+            if (hdx > 0.f && cx < last_c) se = fminf(se, (hix - hx0) * ihx);
+            if (hdx < 0.f && cx > 0) se = fminf(se, (lox - hx0) * ihx);
+            if (hdy > 0.f && cy < last_c) se = fminf(se, (hiy - hy0) * ihy);
+            if (hdy < 0.f && cy > 0) se = fminf(se, (loy - hy0) * ihy);
+            if (hdz > 0.f && cz < last_c) se = fminf(se, (hiz - hz0) * ihz);
+            if (hdz < 0.f && cz > 0) se = fminf(se, (loz - hz0) * ihz);
+            // last full segment whose midpoint (j + 1/2) dt is <= se
+            const float jf = floorf(se / dtf - 0.5f);
+            const int jl = jf >= (float)(K - 1) ? K - 1 : (int)jf;
+            k = (k >= K - 1) ? K : min(max(k + 1, jl + 1), K - 1);
+            if (k >= K) break;
         }
+        if (k >= K) break;
         const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz);
         const float x = v * Km1;
         const int e0 = min((int)x, F.K - 2);
@@ -237,6 +269,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         const float a = clampf01(fmaf(w, tb.w - ta.w, ta.w));
         float alpha = 0.0f;
         if (len > 0.0f && a > 0.0f) alpha = 1.0f - fast_exp2(len * F.N_f * fast_log2(1.0f - a));
+        ++k;
         if (alpha > 0.0f) {
             float A = 1.0f;
             if (MODE != VI_MODE_NONE)
@@ -247,10 +280,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
             Cg = fmaf(wgt * F.light[1], fmaf(w, tb.y - ta.y, ta.y), Cg);
             Cb = fmaf(wgt * F.light[2], fmaf(w, tb.z - ta.z, ta.z), Cb);
             ad = fmaf(1.0f - ad, alpha, ad);
-            if (1.0f - ad <= F.term_eps) {
-                ++k;
-                break;
-            }
+            if (1.0f - ad <= F.term_eps) break;
         }
     }
     nsamp += (uint32_t)k;
