@@ -203,12 +203,67 @@ def serving_sweep(dev, budget=48 << 30, count=2000, rates=(0.25, 0.5, 0.75, 0.9,
     return {"volumes": 64, "volume_edges": sizes, "requests_per_rate": count, "capacity_fps": cap, "rows": rows}
 
 
+def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
+    """Time `args.steps` steps (build + every mode's frame for light i) after warm-up."""
+    import torch
+    from paper_2008_06134_amd import vi
+    vol_lin = vi.Volume.from_numpy(raw, dev, scale)
+    tf = vi.TF.from_numpy(tab, dev)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    vol = vol_lin.to_bricks().with_minmax(8)  # one-off per volume: bricks + empty-space map
+    torch.cuda.synchronize()
+    prep_ms = (time.perf_counter() - tb) * 1e3
+    del vol_lin
+    stack = vi.stack_buffer(w.n_slices, w.res, stack_dtype, dev)
+    cam0 = w.camera(0)
+    imgs = {m: torch.empty((cam0["height"], cam0["width"], 4), dtype=torch.float32, device=dev) for m in modes}
+    counters = {m: torch.zeros(1, dtype=torch.int64, device=dev) for m in modes}
+
+    def mode_args(m):
+        return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
+
+    def step(i, events=None):
+        li = i % len(lights)
+        cam = w.camera(li)
+        if events is not None:
+            events[0].record()
+        st = vi.build_attenuation(vol, tf, lights[li], w.n_slices, w.res, stack_dtype, out=stack)
+        if events is not None:
+            events[1].record()
+        for k, m in enumerate(modes):
+            mm, extra = mode_args(m)
+            vi.render(vol, tf, st, cam, mm, w.step_vox, extra, out=imgs[m], samples=counters[m])
+            if events is not None:
+                events[2 + k].record()
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    for c in counters.values():
+        c.zero_()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 + len(modes))] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    out = {"build_ms": [e[0].elapsed_time(e[1]) for e in evs],
+           "render_ms": {m: [e[1 + k].elapsed_time(e[2 + k]) for e in evs] for k, m in enumerate(modes)},
+           "samples": {m: int(counters[m].item()) for m in modes}, "wall": wall, "prep_ms": prep_ms,
+           "vol_bytes": raw.nbytes}
+    del vol, stack, imgs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
+    ap.add_argument("--workload", default="large", choices=["small", "medium", "large", "precision"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving leg")
@@ -248,61 +303,24 @@ def main():
     modes = w.modes if w.name != "medium" else ["cone5"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    vol_lin = vi.Volume.from_numpy(raw, dev)
-    tf = vi.TF.from_numpy(tab, dev)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    vol = vol_lin.to_bricks().with_minmax(8)  # one-off per volume: bricks + empty-space map
-    torch.cuda.synchronize()
-    brick_ms = (time.perf_counter() - tb) * 1e3
-    del vol_lin
-    stack = vi.stack_buffer(w.n_slices, w.res, vi.VI_F32, dev)
     cam0 = w.camera(0)
     Wd, Hd = cam0["width"], cam0["height"]
-    imgs = {m: torch.empty((Hd, Wd, 4), dtype=torch.float32, device=dev) for m in modes}
-    counters = {m: torch.zeros(1, dtype=torch.int64, device=dev) for m in modes}
-
-    def mode_args(m):
-        return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
-
-    def step(i, events=None):
-        li = i % len(lights)
-        cam = w.camera(li)
-        if events is not None:
-            events[0].record()
-        st = vi.build_attenuation(vol, tf, lights[li], w.n_slices, w.res, out=stack)
-        if events is not None:
-            events[1].record()
-        for k, m in enumerate(modes):
-            mm, extra = mode_args(m)
-            vi.render(vol, tf, st, cam, mm, w.step_vox, extra, out=imgs[m], samples=counters[m])
-            if events is not None:
-                events[2 + k].record()
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    for c in counters.values():
-        c.zero_()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 + len(modes))] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i, evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-
-    build_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    render_ms = {m: [e[1 + k].elapsed_time(e[2 + k]) for e in evs] for k, m in enumerate(modes)}
-    samples = {m: int(counters[m].item()) for m in modes}
+    precision = w.name == "precision"
+    if precision:
+        m = measure_steps(w, W.to_f16_normalised(raw), 1.0, tab, lights, modes, vi.VI_BF16, args, dev)
+        log("FP32 path on the same volume for comparison ...")
+        m_fp32 = measure_steps(w, raw, None, tab, lights, modes, vi.VI_F32, args, dev)
+    else:
+        m = measure_steps(w, raw, None, tab, lights, modes, vi.VI_F32, args, dev)
+    build_ms, render_ms, samples, wall = m["build_ms"], m["render_ms"], m["samples"], m["wall"]
     total_samples = sum(samples.values())
     frames = args.steps * len(modes)
 
     # roofline of the dominant kernel, algorithmic (compulsory) bytes per launch
-    vol_bytes = raw.nbytes
-    stack_bytes = w.n_slices * w.res * w.res * 4
+    vol_bytes = m["vol_bytes"]
+    stack_bytes = w.n_slices * w.res * w.res * (2 if precision else 4)
     img_bytes = Wd * Hd * 16
-    totals = {"build": sum(build_ms), **{f"render_{m}": sum(v) for m, v in render_ms.items()}}
+    totals = {"build": sum(build_ms), **{f"render_{k}": sum(v) for k, v in render_ms.items()}}
     dom = max(totals, key=totals.get)
     if dom == "build":
         per_launch, avg_ms = vol_bytes + stack_bytes, np.mean(build_ms)
@@ -312,13 +330,13 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                 "bytes_per_launch": per_launch, "avg_launch_ms": round(float(avg_ms), 4)}
-    kernels = {"volume_prepare_ms_once": round(brick_ms, 3),
+    kernels = {"volume_prepare_ms_once": round(m["prep_ms"], 3),
                "build_ms_mean": round(float(np.mean(build_ms)), 4),
                "build_hbm_frac": round((vol_bytes + stack_bytes) / (np.mean(build_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    for m, v in render_ms.items():
-        kernels[f"render_{m}_ms_mean"] = round(float(np.mean(v)), 4)
-        kernels[f"render_{m}_samples_per_frame"] = samples[m] // args.steps
-        kernels[f"render_{m}_samples_per_s"] = round(samples[m] / (sum(v) * 1e-3), 1)
+    for k, v in render_ms.items():
+        kernels[f"render_{k}_ms_mean"] = round(float(np.mean(v)), 4)
+        kernels[f"render_{k}_samples_per_frame"] = samples[k] // args.steps
+        kernels[f"render_{k}_samples_per_s"] = round(samples[k] / (sum(v) * 1e-3), 1)
 
     result = {
         "metric": "ray samples/s (build + shell + cone frames per light direction), 512^3 1080p",
@@ -331,23 +349,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16 volume, bf16 optical depth, f32 math" if precision else "f32",
         "data": "synthetic",
         "fps": round(frames / wall, 3),
-        "config": {"workload": (f"{w.name}: {w.N}^3 {raw.dtype} phantom (4x4x4 bricks, 8^3 empty-space cells), "
-                                f"{w.n_slices} slices x {w.res}^2 f32, "
+        "config": {"workload": (f"{w.name}: {w.N}^3 {'f16' if precision else raw.dtype} phantom "
+                                f"(4x4x4 bricks, 8^3 empty-space cells), "
+                                f"{w.n_slices} slices x {w.res}^2 {'bf16' if precision else 'f32'}, "
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "
                                 f"{len(lights)} light directions (one rebuild per step)"),
                    "frames_per_step": len(modes)},
         "kernels": kernels,
         "roofline": roofline,
     }
-    if not args.no_serving:
+    if precision:
+        result["fp32_path_same_volume"] = {"ms_per_step": round(m_fp32["wall"] * 1e3 / args.steps, 4),
+                                           "build_ms_mean": round(float(np.mean(m_fp32["build_ms"])), 4),
+                                           **{f"render_{k}_ms_mean": round(float(np.mean(v)), 4)
+                                              for k, v in m_fp32["render_ms"].items()}}
+    if not args.no_serving and not precision:
         log("serving leg ...")
-        del stack, imgs
         torch.cuda.empty_cache()
         result["serving"] = serving_quick("cuda:0")
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not precision:
         log("timing the oracle on a pixel sample ...")
         opts = {}
         result["cpu_baseline"] = cpu_baseline(w, raw, tab, lights[0], cam0, modes, opts, args.cpu_stride)
