@@ -267,6 +267,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving leg")
+    ap.add_argument("--modes", default=None, help="comma-separated modes to time (none, shadow, shell, cone, cone5)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -301,6 +302,8 @@ def main():
     log(f"workload {w.name}: {raw.shape} {raw.dtype} generated in {time.perf_counter() - t0:.1f} s")
     lights = w.lights()
     modes = w.modes if w.name != "medium" else ["cone5"]
+    if args.modes:
+        modes = args.modes.split(",")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cam0 = w.camera(0)
