@@ -28,12 +28,12 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     if (P.occ.mm) build_next_opaque(s_next, P.tf, P.K);
     __syncthreads();
 
-    const uint32_t tiles_x = (P.res + kBuildTile - 1) / kBuildTile;
-    const uint32_t tiles_y = tiles_x;
-    const uint32_t tile = xcd_swizzle(blockIdx.x, tiles_x * tiles_y);
+    const uint32_t tiles = (P.res + kBuildTile - 1) / kBuildTile;
+    uint32_t tx, ty;
+    if (!supertile_of(blockIdx.x, tiles, tiles, &tx, &ty)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = (int)(tile % tiles_x) * kBuildTile + (lane & 15);
-    const int j = (int)(tile / tiles_x) * kBuildTile + wave * 4 + (lane >> 4);
+    const int i = (int)tx * kBuildTile + (lane & 15);
+    const int j = (int)ty * kBuildTile + wave * 4 + (lane >> 4);
     if (i >= P.res || j >= P.res) return;
 
     // column base (slab 0 midpoint) in offset-voxel coordinates, in double
@@ -94,7 +94,7 @@ template <typename VT, int LAYOUT>
 static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
 {
     const uint32_t tiles = (uint32_t)((p.res + kBuildTile - 1) / kBuildTile);
-    dim3 grid(tiles * tiles), block(256);
+    dim3 grid(supertile_grid(tiles, tiles)), block(256);
     const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K;
     if (p.out_dtype == VI_F32)
         hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32>), grid, block, lds, s, p);

@@ -138,17 +138,38 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float x)
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// Tile index with the workgroups of each XCD given a contiguous range of
-// tiles: workgroups are dealt round-robin to the 8 XCDs, so block b runs on
-// XCD b % 8; mapping it to tile (b % 8) * per + b / 8 keeps neighbouring
-// tiles in one XCD's L2.
-__device__ __forceinline__ uint32_t xcd_swizzle(uint32_t b, uint32_t nblocks)
+// Workgroups are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8),
+// each with its own L2.  The tile grid is cut into super-tiles of 4 x 4 tiles;
+// super-tile s belongs to XCD s % 8, and the XCD's blocks walk its
+// super-tiles tile by tile.  Neighbouring tiles thus share an L2 while the
+// work of every region of the image (or light square) is spread over all
+// XCDs -- a contiguous band per XCD would leave the XCDs of empty bands idle.
+constexpr uint32_t kXcds = 8, kSuper = 4;
+__host__ __device__ inline uint32_t supertile_grid(uint32_t tiles_x, uint32_t tiles_y)
 {
-    const uint32_t X = 8;
-    uint32_t per = nblocks / X, rem = nblocks % X;
-    uint32_t x = b % X, q = b / X;
-    // XCDs 0..rem-1 own per+1 tiles, the rest own per
-    return x * per + min(x, rem) + q;
+    const uint32_t sx = (tiles_x + kSuper - 1) / kSuper, sy = (tiles_y + kSuper - 1) / kSuper;
+    return (sx * sy + kXcds - 1) / kXcds * kXcds * kSuper * kSuper;
+}
+// Returns false for padding blocks.
+__device__ __forceinline__ bool supertile_of(uint32_t b, uint32_t tiles_x, uint32_t tiles_y, uint32_t* tx,
+                                             uint32_t* ty)
+{
+    const uint32_t sx = (tiles_x + kSuper - 1) / kSuper, sy = (tiles_y + kSuper - 1) / kSuper;
+    const uint32_t x = b % kXcds, q = b / kXcds;
+    const uint32_t st = x + kXcds * (q / (kSuper * kSuper)), t = q % (kSuper * kSuper);
+    if (st >= sx * sy) return false;
+    *tx = (st % sx) * kSuper + t % kSuper;
+    *ty = (st / sx) * kSuper + t / kSuper;
+    return *tx < tiles_x && *ty < tiles_y;
+}
+// A list of n tiles: groups of 16 consecutive entries dealt round-robin to the
+// XCDs.  Returns false for padding blocks; grid = list_grid(n).
+__host__ __device__ inline uint32_t list_grid(uint32_t n) { return (n + 127) / 128 * 128; }
+__device__ __forceinline__ bool list_of(uint32_t b, uint32_t n, uint32_t* idx)
+{
+    const uint32_t G = 16, x = b % kXcds, q = b / kXcds;
+    *idx = ((q / G) * kXcds + x) * G + q % G;
+    return *idx < n;
 }
 
 }  // namespace vi

@@ -302,10 +302,11 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
     __syncthreads();
 
     const uint32_t tiles_x = (F.width + 15) / 16, tiles_y = (F.height + 15) / 16;
-    const uint32_t tile = xcd_swizzle(blockIdx.x, tiles_x * tiles_y);
+    uint32_t tx, ty;
+    if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int px = (int)(tile % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
-    const int py = (int)(tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int px = (int)tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = (int)ty * 16 + (wave >> 1) * 8 + (lane >> 3);
     uint32_t ns = 0;
     if (px < F.width && py < F.height) {
         const float4 c = render_ray<VT, LAYOUT, MODE, SDT>(F, s_tf, s_next, px, py, ns);
@@ -329,7 +330,8 @@ __global__ __launch_bounds__(256) void render_batch_kernel(const RenderFrame* __
                                                            const uint32_t* __restrict__ tiles, uint32_t ntiles)
 {
     extern __shared__ float4 s_tf[];
-    const uint32_t b = xcd_swizzle(blockIdx.x, ntiles);
+    uint32_t b;
+    if (!list_of(blockIdx.x, ntiles, &b)) return;
     const uint32_t t = tiles[b];
     const RenderFrame& F = frames[t >> 22];
     int* s_next = (int*)(s_tf + F.K);
@@ -362,8 +364,8 @@ static hipError_t launch_batch_t(const RenderFrame* d_frames, const uint32_t* d_
                                  hipStream_t s)
 {
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)maxK;
-    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT>), dim3(ntiles), dim3(256), lds, s, d_frames, d_tiles,
-                       ntiles);
+    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT>), dim3(list_grid(ntiles)), dim3(256), lds, s, d_frames,
+                       d_tiles, ntiles);
     return hipGetLastError();
 }
 
@@ -392,8 +394,7 @@ hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, const
 template <typename VT, int LAYOUT, int SDT>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
-    const uint32_t tiles = (uint32_t)(((f.width + 15) / 16) * ((f.height + 15) / 16));
-    dim3 grid(tiles), block(256);
+    dim3 grid(supertile_grid((f.width + 15) / 16, (f.height + 15) / 16)), block(256);
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K;
     switch (f.mode) {
     case VI_MODE_NONE:
