@@ -343,8 +343,8 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     vi_render_opts o;
     if (opts) o = *opts;
     else vi_default_render_opts(&o);
-    if (!(o.term_eps >= 0.0f) || !(o.ambient >= 0.0f && o.ambient <= 1.0f))
-        return fail(VI_E_INVALID_ARG, "term_eps must be >= 0 and ambient in [0,1]");
+    if (!(o.term_eps >= 0.0f && o.term_eps < 1.0f) || !(o.ambient >= 0.0f && o.ambient <= 1.0f))
+        return fail(VI_E_INVALID_ARG, "term_eps must be in [0,1) and ambient in [0,1]");
     if (mode != VI_MODE_NONE) {
         if (!sl || !sl->data) return fail(VI_E_INVALID_ARG, "mode %d needs a stack", mode);
         if (sl->dtype != VI_F32 && sl->dtype != VI_BF16) return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);

@@ -128,10 +128,41 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
     return s * F.tap_w;
 }
 
-template <typename VT, int LAYOUT, int MODE, int SDT>
+// G lanes march one ray together: lane g of the group takes segment k + g of
+// every group step, the G segments are composited front to back with a scan
+// over the group (inclusive product of (1 - alpha), then the emission of each
+// segment weighted by the transmittance in front of it), and the ray stops
+// exactly at the first segment after which 1 - alpha_dst <= term_eps.  All
+// lanes of a group carry identical ray state.  G = 1 is the plain sequential
+// march; larger G shortens the longest waves (rays of ~1000 non-empty
+// segments) and packs the G samples of a step within a couple of voxels.
+template <int G>
+__device__ __forceinline__ float group_scan_mul(float x, int g)
+{
+    for (int d = 1; d < G; d <<= 1) {
+        const float t = __shfl_up(x, d, G);
+        if (g >= d) x *= t;
+    }
+    return x;
+}
+template <int G>
+__device__ __forceinline__ float group_sum(float x)
+{
+    for (int d = G / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, G);
+    return x;
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_bits(bool p, int base)
+{
+    const unsigned long long m = __ballot(p);
+    return (uint32_t)((m >> base) & ((G == 32 ? 0xffffffffull : ((1ull << G) - 1ull))));
+}
+
+template <typename VT, int LAYOUT, int MODE, int SDT, int G>
 __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf,
                                              const int* __restrict__ s_next, int px, int py, uint32_t& nsamp)
 {
+    const int lane = threadIdx.x & 63, g = lane % G, gbase = lane - g;
     // ---- camera ray (double)
     const double xn = 2.0 * (px + 0.5) / F.width - 1.0;
     const double yn = 1.0 - 2.0 * (py + 0.5) / F.height;
@@ -209,83 +240,144 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     const VolIndex VI_ = {1u, F.vsy, F.vsz};
     const float Df = (float)D, dtf = (float)F.dt;
     const float Km1 = (float)(F.K - 1);
-    float Cr = 0.f, Cg = 0.f, Cb = 0.f, ad = 0.f;
-    // Empty-space traversal: per-axis inverse step and cell edge.  A lane in a
-    // zero-opacity cell jumps to the last segment midpoint that lies inside
-    // that cell by a margin of kEps voxels (far above the float position
-    // error), so no segment with non-zero opacity is ever skipped.
+    // C: premultiplied colour so far; T = 1 - alpha_dst, the transmittance in
+    // front of the next segment (kept as a product of exact per-segment
+    // factors, which keeps its relative precision down to term_eps).
+    float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
+    // Empty-space traversal: per-axis inverse step and cell edge.  A group whose
+    // G segments all lie in zero-opacity cells jumps to the last segment
+    // midpoint inside the cell of its last segment, by a margin of kEps voxels
+    // (far above the float position error), so no segment with non-zero
+    // opacity is ever skipped.
     const float kEps = 0.02f;
     const float ihx = hdx != 0.f ? 1.0f / hdx : 0.f, ihy = hdy != 0.f ? 1.0f / hdy : 0.f,
                 ihz = hdz != 0.f ? 1.0f / hdz : 0.f;
     const int B = 1 << F.occ.shift, last_c = (int)F.occ.nc - 1;
     uint32_t last_cell = 0xffffffffu;
     bool cell_is_empty = false;
-    int k = 0;
-    while (k < K) {
-        float len, sm, hx, hy, hz;
-        // advance over zero-opacity cells to this lane's next candidate segment
-        for (;;) {
-            const float s0 = (float)k * dtf;
-            const float s1 = fminf((float)(k + 1) * dtf, Df);
-            len = s1 - s0;
-            sm = 0.5f * (s0 + s1);
-            hx = fmaf(sm, hdx, hx0);
-            hy = fmaf(sm, hdy, hy0);
-            hz = fmaf(sm, hdz, hz0);
-            if (!F.occ.mm) break;
-            const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1), gy = clampi((int)floorf(hy) + F.M, 0, F.N - 1),
-                      gz = clampi((int)floorf(hz) + F.M, 0, F.N - 1);
-            const int cx = gx >> F.occ.shift, cy = gy >> F.occ.shift, cz = gz >> F.occ.shift;
-            const uint32_t c = ((uint32_t)cz * F.occ.nc + (uint32_t)cy) * F.occ.nc + (uint32_t)cx;
-            if (c != last_cell) {
-                last_cell = c;
-                cell_is_empty = cell_empty(F.occ.mm[c], s_next, Km1, F.K);
+    int k = 0, count = K;
+    for (;;) {
+        const int kk = k + g;
+        const bool in = kk < K;
+        float om = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;  // om = 1 - alpha of the segment
+        bool empty = true;
+        int jl = K;
+        if (in) {
+            const float s0 = (float)kk * dtf;
+            const float s1 = fminf((float)(kk + 1) * dtf, Df);
+            const float len = s1 - s0;
+            const float sm = 0.5f * (s0 + s1);
+            const float hx = fmaf(sm, hdx, hx0), hy = fmaf(sm, hdy, hy0), hz = fmaf(sm, hdz, hz0);
+            empty = false;
+            if (F.occ.mm) {
+                const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1),
+                          gy = clampi((int)floorf(hy) + F.M, 0, F.N - 1),
+                          gz = clampi((int)floorf(hz) + F.M, 0, F.N - 1);
+                const int cx = gx >> F.occ.shift, cy = gy >> F.occ.shift, cz = gz >> F.occ.shift;
+                const uint32_t c = ((uint32_t)cz * F.occ.nc + (uint32_t)cy) * F.occ.nc + (uint32_t)cx;
+                if (c != last_cell) {
+                    last_cell = c;
+                    cell_is_empty = cell_empty(F.occ.mm[c], s_next, Km1, F.K);
+                }
+                empty = cell_is_empty;
+                if (empty) {
+                    // distance along the ray to the cell's faces moved inward by
+                    // kEps (faces of edge cells toward the outside are at infinity)
+                    float se = 3.4e38f;
+                    const float lox = (float)(cx * B - F.M) + kEps, hix = (float)((cx + 1) * B - F.M) - kEps;
+                    const float loy = (float)(cy * B - F.M) + kEps, hiy = (float)((cy + 1) * B - F.M) - kEps;
+                    const float loz = (float)(cz * B - F.M) + kEps, hiz = (float)((cz + 1) * B - F.M) - kEps;
+                    if (hdx > 0.f && cx < last_c) se = fminf(se, (hix - hx0) * ihx);
+                    if (hdx < 0.f && cx > 0) se = fminf(se, (lox - hx0) * ihx);
+                    if (hdy > 0.f && cy < last_c) se = fminf(se, (hiy - hy0) * ihy);
+                    if (hdy < 0.f && cy > 0) se = fminf(se, (loy - hy0) * ihy);
+                    if (hdz > 0.f && cz < last_c) se = fminf(se, (hiz - hz0) * ihz);
+                    if (hdz < 0.f && cz > 0) se = fminf(se, (loz - hz0) * ihz);
+                    // last full segment whose midpoint (j + 1/2) dt is <= se
+                    const float jf = floorf(se / dtf - 0.5f);
+                    jl = jf >= (float)(K - 1) ? K - 1 : (int)jf;
+                }
             }
-            if (!cell_is_empty) break;
-            // distance along the ray to the cell's faces moved inward by kEps
-            // (faces of edge cells toward the outside are at infinity)
-            float se = 3.4e38f;
-            const float lox = (float)(cx * B - F.M) + kEps, hix = (float)((cx + 1) * B - F.M) - kEps;
-            const float loy = (float)(cy * B - F.M) + kEps, hiy = (float)((cy + 1) * B - F.M) - kEps;
-            const float loz = (float)(cz * B - F.M) + kEps, hiz = (float)((cz + 1) * B - F.M) - kEps;
-            if (hdx > 0.f && cx < last_c) se = fminf(se, (hix - hx0) * ihx);
-            if (hdx < 0.f && cx > 0) se = fminf(se, (lox - hx0) * ihx);
-            if (hdy > 0.f && cy < last_c) se = fminf(se, (hiy - hy0) * ihy);
-            if (hdy < 0.f && cy > 0) se = fminf(se, (loy - hy0) * ihy);
-            if (hdz > 0.f && cz < last_c) se = fminf(se, (hiz - hz0) * ihz);
-            if (hdz < 0.f && cz > 0) se = fminf(se, (loz - hz0) * ihz);
-            // last full segment whose midpoint (j + 1/2) dt is <= se
-            const float jf = floorf(se / dtf - 0.5f);
-            const int jl = jf >= (float)(K - 1) ? K - 1 : (int)jf;
-            k = (k >= K - 1) ? K : min(max(k + 1, jl + 1), K - 1);
+            if (!empty) {
+                const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz);
+                const float x = v * Km1;
+                const int e0 = min((int)x, F.K - 2);
+                const float w = x - (float)e0;
+                const float4 ta = s_tf[e0], tb = s_tf[e0 + 1];
+                const float a = clampf01(fmaf(w, tb.w - ta.w, ta.w));
+                // (1 - alpha) of a segment of length len: (1 - a)^(len / dref)
+                if (len > 0.0f && a > 0.0f) om = fast_exp2(len * F.N_f * fast_log2(1.0f - a));
+                const float alpha = 1.0f - om;
+                if (alpha > 0.0f) {
+                    float A = 1.0f;
+                    if (MODE != VI_MODE_NONE)
+                        A = gather<MODE, SDT>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
+                    const float e = alpha * fmaf(1.0f - F.ambient, A, F.ambient);
+                    cr = e * F.light[0] * fmaf(w, tb.x - ta.x, ta.x);
+                    cg = e * F.light[1] * fmaf(w, tb.y - ta.y, ta.y);
+                    cb = e * F.light[2] * fmaf(w, tb.z - ta.z, ta.z);
+                }
+            }
+        }
+        if (group_bits<G>(empty, gbase) == ((G == 32) ? 0xffffffffu : ((1u << G) - 1u))) {
+            // every segment of this step is empty (or past the exit): jump
+            const int jlast = G == 1 ? jl : __shfl(jl, gbase + G - 1);
+            k = max(k + G, jlast + 1);
             if (k >= K) break;
+            continue;
         }
+        // front-to-back over the G segments of this step (Eq. 3 in product form)
+        const float incl = group_scan_mul<G>(om, g);                  // prod_{h<=g} (1 - alpha_h)
+        const float excl = G == 1 ? 1.0f : (g == 0 ? 1.0f : __shfl_up(incl, 1, G));
+        const uint32_t tb_ = group_bits<G>(in && T * incl <= F.term_eps, gbase);
+        const int gs = tb_ ? __ffs(tb_) - 1 : G;                     // terminating segment, G if none
+        const float keep = (g <= gs) ? T * excl : 0.0f;
+        Cr += group_sum<G>(keep * cr);
+        Cg += group_sum<G>(keep * cg);
+        Cb += group_sum<G>(keep * cb);
+        const float prod = G == 1 ? incl : __shfl(incl, gbase + min(gs, G - 1));
+        T *= prod;
+        if (gs < G) {
+            count = k + gs + 1;
+            break;
+        }
+        k += G;
         if (k >= K) break;
-        const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz);
-        const float x = v * Km1;
-        const int e0 = min((int)x, F.K - 2);
-        const float w = x - (float)e0;
-        const float4 ta = s_tf[e0], tb = s_tf[e0 + 1];
-        const float a = clampf01(fmaf(w, tb.w - ta.w, ta.w));
-        float alpha = 0.0f;
-        if (len > 0.0f && a > 0.0f) alpha = 1.0f - fast_exp2(len * F.N_f * fast_log2(1.0f - a));
-        ++k;
-        if (alpha > 0.0f) {
-            float A = 1.0f;
-            if (MODE != VI_MODE_NONE)
-                A = gather<MODE, SDT>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
-            const float shade = fmaf(1.0f - F.ambient, A, F.ambient);
-            const float wgt = (1.0f - ad) * alpha * shade;
-            Cr = fmaf(wgt * F.light[0], fmaf(w, tb.x - ta.x, ta.x), Cr);
-            Cg = fmaf(wgt * F.light[1], fmaf(w, tb.y - ta.y, ta.y), Cg);
-            Cb = fmaf(wgt * F.light[2], fmaf(w, tb.z - ta.z, ta.z), Cb);
-            ad = fmaf(1.0f - ad, alpha, ad);
-            if (1.0f - ad <= F.term_eps) break;
-        }
     }
-    nsamp += (uint32_t)k;
-    const float rem = 1.0f - ad;
-    return make_float4(fmaf(rem, bg.x, Cr), fmaf(rem, bg.y, Cg), fmaf(rem, bg.z, Cb), fmaf(rem, bg.w, ad));
+    if (g == 0) nsamp += (uint32_t)min(count, K);
+    return make_float4(fmaf(T, bg.x, Cr), fmaf(T, bg.y, Cg), fmaf(T, bg.z, Cb), fmaf(T, bg.w, 1.0f - T));
+}
+
+// --------------------------------------------------------------------------
+// lane -> pixel mapping: kG lanes per ray; a wave covers WX x WY pixels, a
+// workgroup 2 x 2 waves = BX x BY pixels.
+// --------------------------------------------------------------------------
+constexpr int kG = 4;
+constexpr int kWX = (64 / kG) >= 32 ? 8 : 4, kWY = (64 / kG) / kWX;
+constexpr int kBX = 2 * kWX, kBY = 2 * kWY;
+
+__device__ __forceinline__ void block_pixel(uint32_t tx, uint32_t ty, int* px, int* py)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane / kG;
+    *px = (int)tx * kBX + (wave & 1) * kWX + r % kWX;
+    *py = (int)ty * kBY + (wave >> 1) * kWY + r / kWX;
+}
+
+template <typename VT, int LAYOUT, int MODE, int SDT>
+__device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* s_tf, const int* s_next, int px,
+                                            int py)
+{
+    uint32_t ns = 0;
+    const int lane = threadIdx.x & 63;
+    if (px < F.width && py < F.height) {
+        const float4 c = render_ray<VT, LAYOUT, MODE, SDT, kG>(F, s_tf, s_next, px, py, ns);
+        if (lane % kG == 0) F.out[(size_t)py * F.width + px] = c;
+    }
+    if (F.samples) {
+        // wave sum, one atomic per wave
+        for (int off = 32; off > 0; off >>= 1) ns += __shfl_xor(ns, off);
+        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -301,61 +393,43 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
     if (F.occ.mm) build_next_opaque(s_next, F.tf, F.K);
     __syncthreads();
 
-    const uint32_t tiles_x = (F.width + 15) / 16, tiles_y = (F.height + 15) / 16;
+    const uint32_t tiles_x = (F.width + kBX - 1) / kBX, tiles_y = (F.height + kBY - 1) / kBY;
     uint32_t tx, ty;
     if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int px = (int)tx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int py = (int)ty * 16 + (wave >> 1) * 8 + (lane >> 3);
-    uint32_t ns = 0;
-    if (px < F.width && py < F.height) {
-        const float4 c = render_ray<VT, LAYOUT, MODE, SDT>(F, s_tf, s_next, px, py, ns);
-        F.out[(size_t)py * F.width + px] = c;
-    }
-    if (F.samples) {
-        // wave sum, one atomic per wave
-        for (int off = 32; off > 0; off >>= 1) ns += __shfl_xor(ns, off);
-        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
-    }
+    int px, py;
+    block_pixel(tx, ty, &px, &py);
+    shade_pixel<VT, LAYOUT, MODE, SDT>(F, s_tf, s_next, px, py);
 }
 
 // --------------------------------------------------------------------------
-// batched kernel (serving): one workgroup per 16 x 16 tile of any frame of
-// the launch; the tile names its frame, whose parameters are read from
-// device memory.  Per pixel it runs the same render_ray as render_kernel, so
-// a frame is bit-identical alone and in a mix.
+// batched kernel (serving): the launch lists 16 x 16-pixel tiles of any frames;
+// each tile is covered by (16/BX) x (16/BY) workgroups, each reading its
+// frame's parameters from device memory.  Per pixel it runs the same
+// render_ray as render_kernel, so a frame is bit-identical alone and in a mix.
 // --------------------------------------------------------------------------
+constexpr uint32_t kSubX = 16 / kBX, kSubY = 16 / kBY, kSub = kSubX * kSubY;
+
 template <typename VT, int LAYOUT, int SDT>
 __global__ __launch_bounds__(256) void render_batch_kernel(const RenderFrame* __restrict__ frames,
                                                            const uint32_t* __restrict__ tiles, uint32_t ntiles)
 {
     extern __shared__ float4 s_tf[];
-    uint32_t b;
-    if (!list_of(blockIdx.x, ntiles, &b)) return;
-    const uint32_t t = tiles[b];
+    uint32_t q;
+    if (!list_of(blockIdx.x, ntiles * kSub, &q)) return;
+    const uint32_t t = tiles[q / kSub], sub = q % kSub;
     const RenderFrame& F = frames[t >> 22];
     int* s_next = (int*)(s_tf + F.K);
     for (int i = threadIdx.x; i < F.K; i += blockDim.x)
         s_tf[i] = make_float4(F.tf[4 * i], F.tf[4 * i + 1], F.tf[4 * i + 2], F.tf[4 * i + 3]);
     if (F.occ.mm) build_next_opaque(s_next, F.tf, F.K);
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int px = (int)(t & 2047u) * 16 + (wave & 1) * 8 + (lane & 7);
-    const int py = (int)((t >> 11) & 2047u) * 16 + (wave >> 1) * 8 + (lane >> 3);
-    uint32_t ns = 0;
-    if (px < F.width && py < F.height) {
-        float4 c;
-        switch (F.mode) {
-        case VI_MODE_NONE: c = render_ray<VT, LAYOUT, VI_MODE_NONE, SDT>(F, s_tf, s_next, px, py, ns); break;
-        case VI_MODE_SHADOW: c = render_ray<VT, LAYOUT, VI_MODE_SHADOW, SDT>(F, s_tf, s_next, px, py, ns); break;
-        case VI_MODE_SHELL: c = render_ray<VT, LAYOUT, VI_MODE_SHELL, SDT>(F, s_tf, s_next, px, py, ns); break;
-        default: c = render_ray<VT, LAYOUT, VI_MODE_CONE, SDT>(F, s_tf, s_next, px, py, ns); break;
-        }
-        F.out[(size_t)py * F.width + px] = c;
-    }
-    if (F.samples) {
-        for (int off = 32; off > 0; off >>= 1) ns += __shfl_xor(ns, off);
-        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
+    int px, py;
+    block_pixel((t & 2047u) * kSubX + sub % kSubX, ((t >> 11) & 2047u) * kSubY + sub / kSubX, &px, &py);
+    switch (F.mode) {
+    case VI_MODE_NONE: shade_pixel<VT, LAYOUT, VI_MODE_NONE, SDT>(F, s_tf, s_next, px, py); break;
+    case VI_MODE_SHADOW: shade_pixel<VT, LAYOUT, VI_MODE_SHADOW, SDT>(F, s_tf, s_next, px, py); break;
+    case VI_MODE_SHELL: shade_pixel<VT, LAYOUT, VI_MODE_SHELL, SDT>(F, s_tf, s_next, px, py); break;
+    default: shade_pixel<VT, LAYOUT, VI_MODE_CONE, SDT>(F, s_tf, s_next, px, py); break;
     }
 }
 
@@ -364,8 +438,8 @@ static hipError_t launch_batch_t(const RenderFrame* d_frames, const uint32_t* d_
                                  hipStream_t s)
 {
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)maxK;
-    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT>), dim3(list_grid(ntiles)), dim3(256), lds, s, d_frames,
-                       d_tiles, ntiles);
+    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT>), dim3(list_grid(ntiles * kSub)), dim3(256), lds, s,
+                       d_frames, d_tiles, ntiles);
     return hipGetLastError();
 }
 
@@ -394,7 +468,7 @@ hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, const
 template <typename VT, int LAYOUT, int SDT>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
-    dim3 grid(supertile_grid((f.width + 15) / 16, (f.height + 15) / 16)), block(256);
+    dim3 grid(supertile_grid((f.width + kBX - 1) / kBX, (f.height + kBY - 1) / kBY)), block(256);
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K;
     switch (f.mode) {
     case VI_MODE_NONE:
