@@ -66,6 +66,10 @@ def cpu_baseline(w, raw, tab, light, cam, modes, opts, stride, nthreads=0):
 # serving: continuous batching vs sequential plain renders, Poisson arrivals
 # ---------------------------------------------------------------------------
 
+# stack layout of every stack the bench builds (0 tiled, 1 quads; --stack-layout)
+STACK_LAYOUT = 1
+
+
 def _outputs(reqs, dev, per_size=8):
     """A small ring of output images per image size (the bench never reads them)."""
     import torch
@@ -94,7 +98,8 @@ def serve(vols, reqs, budget, max_inflight=16, tiles=8192, dev="cuda:0"):
         dt = t0 + r["arrival"] - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        t, _ = srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], r["mode"], 0.5, out=o)
+        t, _ = srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], r["mode"], 0.5, out=o,
+                          layout=STACK_LAYOUT)
         tickets.append(t)
     for t in tickets:
         rc = srv.wait(t)
@@ -130,11 +135,11 @@ def sequential(vols, reqs, budget, reuse=True, dev="cuda:0"):
         if st is not None:
             cache.move_to_end(key)
         else:
-            need = vi.slices_bytes(r["n"], r["res"])
+            need = vi.slices_bytes(r["n"], r["res"], vi.VI_F32, STACK_LAYOUT)
             while reuse and cache and used + need > budget:
                 _, old = cache.popitem(last=False)
-                used -= vi.slices_bytes(old.n, old.res)
-            st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"])
+                used -= vi.slices_bytes(old.n, old.res, vi.VI_F32, STACK_LAYOUT)
+            st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"], layout=STACK_LAYOUT)
             if reuse:
                 cache[key] = st
                 used += need
@@ -215,7 +220,7 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - tb) * 1e3
     del vol_lin
-    stack = vi.stack_buffer(w.n_slices, w.res, stack_dtype, dev)
+    stack = vi.stack_buffer(w.n_slices, w.res, stack_dtype, dev, STACK_LAYOUT)
     cam0 = w.camera(0)
     imgs = {m: torch.empty((cam0["height"], cam0["width"], 4), dtype=torch.float32, device=dev) for m in modes}
     counters = {m: torch.zeros(1, dtype=torch.int64, device=dev) for m in modes}
@@ -228,7 +233,8 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
         cam = w.camera(li)
         if events is not None:
             events[0].record()
-        st = vi.build_attenuation(vol, tf, lights[li], w.n_slices, w.res, stack_dtype, out=stack)
+        st = vi.build_attenuation(vol, tf, lights[li], w.n_slices, w.res, stack_dtype, out=stack,
+                                  layout=STACK_LAYOUT)
         if events is not None:
             events[1].record()
         for k, m in enumerate(modes):
@@ -270,9 +276,13 @@ def main():
     ap.add_argument("--modes", default=None, help="comma-separated modes to time (none, shadow, shell, cone, cone5)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
+    ap.add_argument("--stack-layout", default="quads", choices=["tiled", "quads"],
+                    help="stack layout of every stack built (quads: one 4-texel load per bilinear lookup)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    global STACK_LAYOUT
+    STACK_LAYOUT = {"tiled": 0, "quads": 1}[args.stack_layout]
     if args.copy_probe:
         import torch
         a = torch.ones(args.copy_probe * 2 ** 18, dtype=torch.float32, device="cuda:0")
@@ -357,7 +367,8 @@ def main():
         "fps": round(frames / wall, 3),
         "config": {"workload": (f"{w.name}: {w.N}^3 {'f16' if precision else raw.dtype} phantom "
                                 f"(4x4x4 bricks, 8^3 empty-space cells), "
-                                f"{w.n_slices} slices x {w.res}^2 {'bf16' if precision else 'f32'}, "
+                                f"{w.n_slices} slices x {w.res}^2 {'bf16' if precision else 'f32'} "
+                                f"({args.stack_layout}), "
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "
                                 f"{len(lights)} light directions (one rebuild per step)"),
                    "frames_per_step": len(modes)},

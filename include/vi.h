@@ -129,18 +129,32 @@ typedef struct {
     int n_entries;
 } vi_tf;
 
+/* Stack layouts.  Texel (k, j, i): layer k, row j (along V), column i
+ * (along U); T = 1 outside the res x res grid.
+ *   VI_STACK_TILED: every layer in 8 x 4 texel tiles; with R8 = res rounded
+ *     up to 8 and R4 = res rounded up to 4, texel (k, j, i) is element
+ *       k*R8*R4 + ((j/4)*(R8/8) + i/8)*32 + (j%4)*8 + i%8
+ *     (padding never read).  n*R8*R4 elements.
+ *   VI_STACK_QUADS: every layer holds, for a, b in [-1, res-1], the quad
+ *     (T(k,b,a), T(k,b,a+1), T(k,b+1,a), T(k,b+1,a+1)) -- the four texels
+ *     one bilinear lookup reads -- so a lookup is one 4-element load per
+ *     layer instead of four.  With QW = res+1 rounded up to 4, QH = res+1
+ *     rounded up to 2 and a' = a+1, b' = b+1, quad (k, b, a) is quad number
+ *       k*QW*QH + ((b'/2)*(QW/4) + a'/4)*8 + (b'%2)*4 + a'%4
+ *     (four elements each; padding never read).  About 4x the memory and
+ *     build writes of the tiled layout, for a quarter of the gather loads. */
+typedef enum { VI_STACK_TILED = 0, VI_STACK_QUADS = 1 } vi_stack_layout;
+
 /* Attenuation stack descriptor, filled by vi_build_attenuation (or by
  * vi_light_frame for the geometry alone).  `data` points at the caller's
- * buffer of vi_slices_bytes(n, res, dtype) bytes holding layer k, texel row
- * j (along V), column i (along U) in 8 x 4 texel tiles: with R8 = res
- * rounded up to 8 and R4 = res rounded up to 4, element (k, j, i) sits at
- *   k*R8*R4 + ((j/4)*(R8/8) + i/8)*32 + (j%4)*8 + i%8
- * (padding texels are never read).  F32 stores transmittance T_k; BF16
- * stores optical depth tau_k with T_k = exp(-tau_k).
+ * buffer of vi_slices_bytes(n, res, dtype, layout) bytes in `layout`.  F32
+ * stores transmittance T_k; BF16 stores optical depth tau_k with
+ * T_k = exp(-tau_k) (0 outside the grid).
  * Geometry is kept in double as computed on the host (Eq. 8). */
 typedef struct {
     void* data;
     int dtype;          /* VI_F32 or VI_BF16 */
+    int layout;         /* VI_STACK_TILED or VI_STACK_QUADS */
     int n, res;         /* slabs, texels per side */
     double L[3];        /* unit propagation direction */
     double U[3], V[3];  /* light-plane basis */
@@ -186,9 +200,9 @@ const char* vi_last_error(void);
 /* Fill `o` with the defaults listed above.  Returns VI_E_INVALID_ARG on NULL. */
 int vi_default_render_opts(vi_render_opts* o);
 
-/* Bytes of a stack buffer: n * R8 * R4 * (4 for VI_F32, 2 for VI_BF16)
- * (R8, R4: res rounded up to 8 and to 4); 0 for invalid arguments. */
-size_t vi_slices_bytes(int n_slices, int slice_res, int slice_dtype);
+/* Bytes of a stack buffer (element 4 bytes for VI_F32, 2 for VI_BF16):
+ * tiled n*R8*R4 elements, quads n*QW*QH*4 elements; 0 for invalid arguments. */
+size_t vi_slices_bytes(int n_slices, int slice_res, int slice_dtype, int slice_layout);
 
 /* Bytes of a volume of edge n, dtype and layout (0 for invalid arguments). */
 size_t vi_volume_bytes(int n, int dtype, int layout);
@@ -218,11 +232,12 @@ int vi_volume_minmax(const vi_volume* vol, int cell, float* d_minmax, vi_volume*
  * for `light_dir` (need not be unit length; finite, non-zero) and fill
  * the geometry fields of `out` (data = NULL, tag = 0).
  * 1 <= n_slices <= 4096, 1 <= slice_res <= 8192. */
-int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int slice_dtype, vi_slices* out);
+int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int slice_dtype, int slice_layout,
+                   vi_slices* out);
 
 /* Build the attenuation stack (section 3.2.1, Alg. 1) for light direction
- * `light_dir` into `d_slices` (device, vi_slices_bytes bytes, 4-byte
- * aligned) and describe it in `out_desc` (host).  One kernel launch on
+ * `light_dir` into `d_slices` (device, vi_slices_bytes bytes, 16-byte
+ * aligned, layout `slice_layout`) and describe it in `out_desc` (host).  One kernel launch on
  * `stream`.  slice_dtype: VI_F32 (transmittance, product of per-slab
  * (1-alpha)) or VI_BF16 (optical depth: the per-slab extinction summed in
  * float and rounded to bfloat16 per layer; each slab adds at most 64).
@@ -230,7 +245,7 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
  * light; VI_E_UNSUPPORTED for dtypes or sizes outside the limits above or a
  * stack of 4 GiB or more; VI_E_DEVICE if the launch fails. */
 int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n_slices,
-                         int slice_res, int slice_dtype, void* d_slices, vi_slices* out_desc,
+                         int slice_res, int slice_dtype, int slice_layout, void* d_slices, vi_slices* out_desc,
                          vi_stream_t stream);
 
 /* Ray-cast `cam` through the volume with the illumination coefficient
@@ -289,7 +304,7 @@ typedef struct {
 typedef struct {
     int vol_id;                /* from vi_server_register_volume                        */
     double light_dir[3];
-    int n_slices, slice_res, slice_dtype;
+    int n_slices, slice_res, slice_dtype, slice_layout;
     vi_camera camera;
     int mode;
     float step_vox;

@@ -101,17 +101,20 @@ void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
 }
 
 // Eq. 8 and the light projection: geometry of the stack in double.
-int fill_frame(const double l[3], int n, int res, int dt, vi_slices* f)
+int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)
 {
     if (!l || !f) return fail(VI_E_INVALID_ARG, "NULL light direction or descriptor");
     if (n < 1 || n > 4096) return fail(VI_E_INVALID_ARG, "n_slices %d outside 1..4096", n);
     if (res < 1 || res > 8192) return fail(VI_E_INVALID_ARG, "slice_res %d outside 1..8192", res);
     if (dt != VI_F32 && dt != VI_BF16) return fail(VI_E_UNSUPPORTED, "slice dtype %d not supported", dt);
+    if (sl != VI_STACK_TILED && sl != VI_STACK_QUADS) return fail(VI_E_UNSUPPORTED, "slice layout %d not supported", sl);
     if (!isfinite(l[0]) || !isfinite(l[1]) || !isfinite(l[2]))
         return fail(VI_E_INVALID_ARG, "light direction is not finite");
     const double nl = sqrt(dot3(l, l));
     if (!(nl > 0.0) || !isfinite(nl)) return fail(VI_E_INVALID_ARG, "light direction is zero");
     memset(f, 0, sizeof *f);
+    f->dtype = dt;
+    f->layout = sl;
     for (int a = 0; a < 3; ++a) f->L[a] = l[a] / nl;
     f->c[0] = f->c[1] = f->c[2] = 0.5;
     // extreme distances along L over the cube's vertices: the vertex picks
@@ -161,10 +164,15 @@ int vi_default_render_opts(vi_render_opts* o)
     return VI_OK;
 }
 
-size_t vi_slices_bytes(int n, int res, int dt)
+size_t vi_slices_bytes(int n, int res, int dt, int sl)
 {
     if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16)) return 0;
-    return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
+    if (sl == VI_STACK_TILED)
+        return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
+    if (sl == VI_STACK_QUADS)
+        return (size_t)n * vi::round_up((uint32_t)res + 1u, 4u) * vi::round_up((uint32_t)res + 1u, 2u) * 4u *
+               elem_size(dt);
+    return 0;
 }
 
 size_t vi_volume_bytes(int n, int dtype, int layout)
@@ -244,14 +252,14 @@ uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf)
     return h ? h : 1;
 }
 
-int vi_light_frame(const double light_dir[3], int n, int res, int dt, vi_slices* out)
+int vi_light_frame(const double light_dir[3], int n, int res, int dt, int sl, vi_slices* out)
 {
     clear_err();
-    return fill_frame(light_dir, n, res, dt, out);
+    return fill_frame(light_dir, n, res, dt, sl, out);
 }
 
 int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n, int res,
-                         int dt, void* d_slices, vi_slices* out_desc, vi_stream_t stream)
+                         int dt, int sl, void* d_slices, vi_slices* out_desc, vi_stream_t stream)
 {
     clear_err();
     int rc;
@@ -260,10 +268,10 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     if (!d_slices) return fail(VI_E_INVALID_ARG, "NULL stack buffer");
     if (!out_desc) return fail(VI_E_INVALID_ARG, "NULL stack descriptor");
     vi_slices f;
-    if ((rc = fill_frame(light_dir, n, res, dt, &f)) != VI_OK) return rc;
-    if (((uintptr_t)d_slices) % 4) return fail(VI_E_INVALID_ARG, "stack buffer must be 4-byte aligned");
-    if ((double)vi_slices_bytes(n, res, dt) >= 4294967296.0)
-        return fail(VI_E_UNSUPPORTED, "stack of %zu bytes exceeds 4 GiB", vi_slices_bytes(n, res, dt));
+    if ((rc = fill_frame(light_dir, n, res, dt, sl, &f)) != VI_OK) return rc;
+    if (((uintptr_t)d_slices) % 16) return fail(VI_E_INVALID_ARG, "stack buffer must be 16-byte aligned");
+    if ((double)vi_slices_bytes(n, res, dt, sl) >= 4294967296.0)
+        return fail(VI_E_UNSUPPORTED, "stack of %zu bytes exceeds 4 GiB", vi_slices_bytes(n, res, dt, sl));
 
     vi::BuildParams p;
     memset(&p, 0, sizeof p);
@@ -281,8 +289,11 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     p.out_dtype = dt;
     p.n = n;
     p.res = res;
+    p.out_layout = sl;
     p.layer = vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u);
     p.row_tiles32 = vi::round_up((uint32_t)res, 8u) * 4u;
+    p.qlayer = vi::round_up((uint32_t)res + 1u, 4u) * vi::round_up((uint32_t)res + 1u, 2u);
+    p.qrow = vi::round_up((uint32_t)res + 1u, 4u) * 2u;
     const double N = vol->n, texel = 2.0 * f.R / res, u0 = -f.R + 0.5 * texel;
     const double d0 = f.dmin + 0.5 * f.ds, Lc = dot3(f.L, f.c);
     for (int a = 0; a < 3; ++a) {
@@ -348,12 +359,15 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     if (mode != VI_MODE_NONE) {
         if (!sl || !sl->data) return fail(VI_E_INVALID_ARG, "mode %d needs a stack", mode);
         if (sl->dtype != VI_F32 && sl->dtype != VI_BF16) return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);
+        if (sl->layout != VI_STACK_TILED && sl->layout != VI_STACK_QUADS)
+            return fail(VI_E_UNSUPPORTED, "stack layout %d", sl->layout);
+        if (((uintptr_t)sl->data) % 16) return fail(VI_E_INVALID_ARG, "stack buffer must be 16-byte aligned");
         if (sl->n < 1 || sl->res < 1) return fail(VI_E_INVALID_ARG, "stack descriptor has no size");
         if (sl->vol_n != vol->n)
             return fail(VI_E_INVALID_ARG, "stack built for a volume of edge %d, rendering %d", sl->vol_n, vol->n);
         if (sl->tag != 0 && sl->tag != vi_tag(vol, tf))
             return fail(VI_E_INVALID_ARG, "stack was built from another volume or transfer function");
-        if ((double)vi_slices_bytes(sl->n, sl->res, sl->dtype) >= 4294967296.0)
+        if ((double)vi_slices_bytes(sl->n, sl->res, sl->dtype, sl->layout) >= 4294967296.0)
             return fail(VI_E_UNSUPPORTED, "stack exceeds 4 GiB");
     }
 
@@ -375,8 +389,11 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         F.stack_dtype = sl->dtype;
         F.n = sl->n;
         F.res = sl->res;
+        F.stack_layout = sl->layout;
         F.layer = vi::round_up((uint32_t)sl->res, 8u) * vi::round_up((uint32_t)sl->res, 4u);
         F.row_tiles32 = vi::round_up((uint32_t)sl->res, 8u) * 4u;
+        F.qlayer = vi::round_up((uint32_t)sl->res + 1u, 4u) * vi::round_up((uint32_t)sl->res + 1u, 2u);
+        F.qrow = vi::round_up((uint32_t)sl->res + 1u, 4u) * 2u;
         F.Mz = sl->n / 2;
         F.Mr = sl->res / 2;
         const double span = sl->dmax - sl->dmin, sc = sl->res / (2.0 * sl->R);

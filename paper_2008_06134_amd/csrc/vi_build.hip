@@ -19,7 +19,43 @@ namespace vi {
 
 constexpr int kBuildTile = 16;
 
-template <typename VT, int LAYOUT, int OUT_DTYPE>
+// Quad layout: the value of texel column (ci, cj) -- real, or a fully
+// transmitting column of the ring just outside the grid -- goes to every
+// quad (a, b) in [-1, res-1]^2 that contains it, as component
+// (ci - a) + 2 (cj - b).
+template <typename ET>
+__device__ __forceinline__ void put_quads(ET* __restrict__ out, const BuildParams& P, int k, int ci, int cj, ET v)
+{
+    const size_t base = (size_t)k * P.qlayer;
+    for (int db = 0; db < 2; ++db) {
+        const int b = cj - db;
+        if (b < -1 || b > P.res - 1) continue;
+        for (int da = 0; da < 2; ++da) {
+            const int a = ci - da;
+            if (a < -1 || a > P.res - 1) continue;
+            out[(base + quad_of(a + 1, b + 1, P.qrow)) * 4 + da + 2 * db] = v;
+        }
+    }
+}
+
+// the ring columns a lane owns: left/right of its row, above/below its
+// column, and the corner next to it
+template <typename ET>
+__device__ __forceinline__ void put_ring(ET* __restrict__ out, const BuildParams& P, int k, int i, int j, ET one)
+{
+    const int r = P.res;
+    const bool L = i == 0, Rt = i == r - 1, Bo = j == 0, To = j == r - 1;
+    if (L) put_quads(out, P, k, -1, j, one);
+    if (Rt) put_quads(out, P, k, r, j, one);
+    if (Bo) put_quads(out, P, k, i, -1, one);
+    if (To) put_quads(out, P, k, i, r, one);
+    if (L && Bo) put_quads(out, P, k, -1, -1, one);
+    if (L && To) put_quads(out, P, k, -1, r, one);
+    if (Rt && Bo) put_quads(out, P, k, r, -1, one);
+    if (Rt && To) put_quads(out, P, k, r, r, one);
+}
+
+template <typename VT, int LAYOUT, int OUT_DTYPE, int SL>
 __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 {
     extern __shared__ float s_alpha[];  // K alphas, then K next-opaque indices
@@ -81,11 +117,21 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         if (OUT_DTYPE == VI_F32) {
             // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
             T *= fast_exp2(P.e * l2);
-            ((float*)P.out)[(size_t)k * layer + col] = T;
+            if (SL == VI_STACK_QUADS) {
+                put_quads((float*)P.out, P, k, i, j, T);
+                put_ring((float*)P.out, P, k, i, j, 1.0f);
+            } else {
+                ((float*)P.out)[(size_t)k * layer + col] = T;
+            }
         } else {
             // sigma * ds = -e ln(1 - a), capped at 64 per slab
             tau += fminf(-P.e * ln2 * l2, 64.0f);
-            ((uint16_t*)P.out)[(size_t)k * layer + col] = f32_to_bf16(tau);
+            if (SL == VI_STACK_QUADS) {
+                put_quads((uint16_t*)P.out, P, k, i, j, f32_to_bf16(tau));
+                put_ring((uint16_t*)P.out, P, k, i, j, (uint16_t)0);
+            } else {
+                ((uint16_t*)P.out)[(size_t)k * layer + col] = f32_to_bf16(tau);
+            }
         }
     }
 }
@@ -96,10 +142,14 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
     const uint32_t tiles = (uint32_t)((p.res + kBuildTile - 1) / kBuildTile);
     dim3 grid(supertile_grid(tiles, tiles)), block(256);
     const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K;
-    if (p.out_dtype == VI_F32)
-        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32>), grid, block, lds, s, p);
-    else
-        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16>), grid, block, lds, s, p);
+    const bool q = p.out_layout == VI_STACK_QUADS;
+    if (p.out_dtype == VI_F32) {
+        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_QUADS>), grid, block, lds, s, p);
+        else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_TILED>), grid, block, lds, s, p);
+    } else {
+        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_QUADS>), grid, block, lds, s, p);
+        else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_TILED>), grid, block, lds, s, p);
+    }
     return hipGetLastError();
 }
 

@@ -39,7 +39,9 @@ struct BuildParams {
     void* out;
     int out_dtype;     // VI_F32 transmittance / VI_BF16 optical depth
     int n, res;
-    uint32_t layer, row_tiles32;  // stack tiling: R8*R4 per layer, (R8/8)*32 per tile row
+    int out_layout;    // VI_STACK_TILED / VI_STACK_QUADS
+    uint32_t layer, row_tiles32;  // tiled: R8*R4 per layer, (R8/8)*32 per tile row
+    uint32_t qlayer, qrow;        // quads: QW*QH quads per layer, (QW/4)*8 per tile row
     double B0[3];      // h at (i,j,k) = (0,0,0)
     double BU[3];      // d h / d i
     double BV[3];      // d h / d j
@@ -67,7 +69,9 @@ struct RenderFrame {
     const void* stack;
     int stack_dtype;
     int n, res;
+    int stack_layout;
     uint32_t layer, row_tiles32;
+    uint32_t qlayer, qrow;
     int Mz, Mr;          // integer offsets of the light-grid coordinates
     double Lq[3], Lq0;   // z = Lq . p + Lq0 - Mz       (Eq. 9 index minus one)
     double Ux[3], Ux0;   // x = Ux . p + Ux0 - Mr       (Eq. 10 texel column)
@@ -99,8 +103,9 @@ struct RenderFrame {
 // launchers (vi_build.hip / vi_render.hip / vi_layout.hip)
 hipError_t launch_build(const BuildParams& p, hipStream_t s);
 hipError_t launch_render(const RenderFrame& f, hipStream_t s);
-hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, const RenderFrame* d_frames,
-                               const uint32_t* d_tiles, uint32_t ntiles, int maxK, hipStream_t s);
+hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout,
+                               const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
+                               hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStream_t s);
 hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
                          int shift, float* out, hipStream_t s);

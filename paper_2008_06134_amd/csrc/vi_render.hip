@@ -39,12 +39,52 @@ __device__ __forceinline__ float stack_texel<VI_BF16>(const void* __restrict__ S
     return fast_exp2(-log2e * bf16_to_f32(((const uint16_t*)S)[idx]));
 }
 
+// One quad (the 2 x 2 texels of a bilinear lookup) of the quad layout.
+template <int SDT>
+__device__ __forceinline__ float4 stack_quad(const void* __restrict__ S, uint32_t q);
+template <>
+__device__ __forceinline__ float4 stack_quad<VI_F32>(const void* __restrict__ S, uint32_t q)
+{
+    return ((const float4*)S)[q];
+}
+template <>
+__device__ __forceinline__ float4 stack_quad<VI_BF16>(const void* __restrict__ S, uint32_t q)
+{
+    const uint2 u = ((const uint2*)S)[q];
+    const float log2e = 1.4426950408889634f;
+    return make_float4(fast_exp2(-log2e * __uint_as_float(u.x << 16)), fast_exp2(-log2e * __uint_as_float(u.x & 0xffff0000u)),
+                       fast_exp2(-log2e * __uint_as_float(u.y << 16)), fast_exp2(-log2e * __uint_as_float(u.y & 0xffff0000u)));
+}
+
 // Transmittance at light-grid offset coordinates (z, x, y): depth between
 // faces (layer z and z+1 in stack order, layer -1 = 1), bilinear in the
 // layer, fully transmitting outside the texel grid.
-template <int SDT>
+template <int SDT, int SL>
 __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, float x, float y)
 {
+    if (SL == VI_STACK_QUADS) {
+        z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
+        const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
+        const float wz = z - fz, wx = x - fx, wy = y - fy;
+        const int k0 = (int)fz + F.Mz;
+        const int k1 = min(k0 + 1, F.n - 1);
+        const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;
+        const bool in = a >= -1 && a <= F.res - 1 && b >= -1 && b <= F.res - 1;
+        const uint32_t qi = quad_of(clampi(a, -1, F.res - 1) + 1, clampi(b, -1, F.res - 1) + 1, F.qrow);
+        const float4 one = make_float4(1.f, 1.f, 1.f, 1.f);
+        float t0 = 1.0f;
+        if (k0 >= 0) {
+            float4 q = stack_quad<SDT>(F.stack, (uint32_t)k0 * F.qlayer + qi);
+            q = in ? q : one;
+            const float ab = fmaf(wx, q.y - q.x, q.x), cd = fmaf(wx, q.w - q.z, q.z);
+            t0 = fmaf(wy, cd - ab, ab);
+        }
+        float4 q = stack_quad<SDT>(F.stack, (uint32_t)k1 * F.qlayer + qi);
+        q = in ? q : one;
+        const float ab = fmaf(wx, q.y - q.x, q.x), cd = fmaf(wx, q.w - q.z, q.z);
+        const float t1 = fmaf(wy, cd - ab, ab);
+        return fmaf(wz, t1 - t0, t0);
+    }
     z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
     const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
     const float wz = z - fz, wx = x - fx, wy = y - fy;
@@ -95,13 +135,13 @@ struct ConeFrame {
     float px, py;  // L x B in texels per world unit
 };
 
-template <int MODE, int SDT>
+template <int MODE, int SDT, int SL>
 __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& cf, float z, float x, float y)
 {
-    if (MODE == VI_MODE_SHADOW) return stack_lookup<SDT>(F, z, x, y);
+    if (MODE == VI_MODE_SHADOW) return stack_lookup<SDT, SL>(F, z, x, y);
     if (MODE == VI_MODE_SHELL) {
         float s = 0.0f;
-        for (int t = 0; t < F.ntaps; ++t) s += stack_lookup<SDT>(F, z + F.tz[t], x + F.tx_[t], y + F.ty_[t]);
+        for (int t = 0; t < F.ntaps; ++t) s += stack_lookup<SDT, SL>(F, z + F.tz[t], x + F.tx_[t], y + F.ty_[t]);
         return s * F.tap_w;
     }
     // cone
@@ -111,7 +151,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
             const float r = (float)m * (float)F.ds * F.cone_tan;
             for (int q = 0; q < F.cone_angles; ++q) {
                 const float ca = F.cone_cos[q] * r, sa = F.cone_sin[q] * r;
-                s += stack_lookup<SDT>(F, z - (float)m, x + ca * cf.bx + sa * cf.px, y + ca * cf.by + sa * cf.py);
+                s += stack_lookup<SDT, SL>(F, z - (float)m, x + ca * cf.bx + sa * cf.px, y + ca * cf.by + sa * cf.py);
             }
         }
     } else {
@@ -121,7 +161,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
             const float a = ((float)ia - half) * rho;
             for (int ib = 0; ib < G; ++ib) {
                 const float b = ((float)ib - half) * rho;
-                s += stack_lookup<SDT>(F, z - 1.0f, x + a * cf.bx + b * cf.px, y + a * cf.by + b * cf.py);
+                s += stack_lookup<SDT, SL>(F, z - 1.0f, x + a * cf.bx + b * cf.px, y + a * cf.by + b * cf.py);
             }
         }
     }
@@ -158,7 +198,7 @@ __device__ __forceinline__ uint32_t group_bits(bool p, int base)
     return (uint32_t)((m >> base) & ((G == 32 ? 0xffffffffull : ((1ull << G) - 1ull))));
 }
 
-template <typename VT, int LAYOUT, int MODE, int SDT, int G>
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL, int G>
 __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf,
                                              const int* __restrict__ s_next, int px, int py, uint32_t& nsamp)
 {
@@ -311,7 +351,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                 if (alpha > 0.0f) {
                     float A = 1.0f;
                     if (MODE != VI_MODE_NONE)
-                        A = gather<MODE, SDT>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
+                        A = gather<MODE, SDT, SL>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
                     const float e = alpha * fmaf(1.0f - F.ambient, A, F.ambient);
                     cr = e * F.light[0] * fmaf(w, tb.x - ta.x, ta.x);
                     cg = e * F.light[1] * fmaf(w, tb.y - ta.y, ta.y);
@@ -363,14 +403,14 @@ __device__ __forceinline__ void block_pixel(uint32_t tx, uint32_t ty, int* px, i
     *py = (int)ty * kBY + (wave >> 1) * kWY + r / kWX;
 }
 
-template <typename VT, int LAYOUT, int MODE, int SDT>
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
 __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* s_tf, const int* s_next, int px,
                                             int py)
 {
     uint32_t ns = 0;
     const int lane = threadIdx.x & 63;
     if (px < F.width && py < F.height) {
-        const float4 c = render_ray<VT, LAYOUT, MODE, SDT, kG>(F, s_tf, s_next, px, py, ns);
+        const float4 c = render_ray<VT, LAYOUT, MODE, SDT, SL, kG>(F, s_tf, s_next, px, py, ns);
         if (lane % kG == 0) F.out[(size_t)py * F.width + px] = c;
     }
     if (F.samples) {
@@ -383,7 +423,7 @@ __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* 
 // --------------------------------------------------------------------------
 // single-frame kernel
 // --------------------------------------------------------------------------
-template <typename VT, int LAYOUT, int MODE, int SDT>
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
 __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
 {
     extern __shared__ float4 s_tf[];  // K entries, then K next-opaque indices
@@ -398,7 +438,7 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
     if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
     int px, py;
     block_pixel(tx, ty, &px, &py);
-    shade_pixel<VT, LAYOUT, MODE, SDT>(F, s_tf, s_next, px, py);
+    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, px, py);
 }
 
 // --------------------------------------------------------------------------
@@ -409,7 +449,7 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
 // --------------------------------------------------------------------------
 constexpr uint32_t kSubX = 16 / kBX, kSubY = 16 / kBY, kSub = kSubX * kSubY;
 
-template <typename VT, int LAYOUT, int SDT>
+template <typename VT, int LAYOUT, int SDT, int SL>
 __global__ __launch_bounds__(256) void render_batch_kernel(const RenderFrame* __restrict__ frames,
                                                            const uint32_t* __restrict__ tiles, uint32_t ntiles)
 {
@@ -426,61 +466,71 @@ __global__ __launch_bounds__(256) void render_batch_kernel(const RenderFrame* __
     int px, py;
     block_pixel((t & 2047u) * kSubX + sub % kSubX, ((t >> 11) & 2047u) * kSubY + sub / kSubX, &px, &py);
     switch (F.mode) {
-    case VI_MODE_NONE: shade_pixel<VT, LAYOUT, VI_MODE_NONE, SDT>(F, s_tf, s_next, px, py); break;
-    case VI_MODE_SHADOW: shade_pixel<VT, LAYOUT, VI_MODE_SHADOW, SDT>(F, s_tf, s_next, px, py); break;
-    case VI_MODE_SHELL: shade_pixel<VT, LAYOUT, VI_MODE_SHELL, SDT>(F, s_tf, s_next, px, py); break;
-    default: shade_pixel<VT, LAYOUT, VI_MODE_CONE, SDT>(F, s_tf, s_next, px, py); break;
+    case VI_MODE_NONE: shade_pixel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>(F, s_tf, s_next, px, py); break;
+    case VI_MODE_SHADOW: shade_pixel<VT, LAYOUT, VI_MODE_SHADOW, SDT, SL>(F, s_tf, s_next, px, py); break;
+    case VI_MODE_SHELL: shade_pixel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>(F, s_tf, s_next, px, py); break;
+    default: shade_pixel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>(F, s_tf, s_next, px, py); break;
     }
 }
 
-template <typename VT, int LAYOUT, int SDT>
+template <typename VT, int LAYOUT, int SDT, int SL>
 static hipError_t launch_batch_t(const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
                                  hipStream_t s)
 {
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)maxK;
-    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT>), dim3(list_grid(ntiles * kSub)), dim3(256), lds, s,
+    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT, SL>), dim3(list_grid(ntiles * kSub)), dim3(256), lds, s,
                        d_frames, d_tiles, ntiles);
     return hipGetLastError();
 }
 
-template <typename VT>
-static hipError_t launch_batch_vt(int layout, int sdt, const RenderFrame* f, const uint32_t* t, uint32_t n, int K,
-                                  hipStream_t s)
+template <typename VT, int LAYOUT>
+static hipError_t launch_batch_l(int sdt, int sl, const RenderFrame* f, const uint32_t* t, uint32_t n, int K,
+                                 hipStream_t s)
 {
-    if (layout == VI_LAYOUT_BRICK4)
-        return sdt == VI_BF16 ? launch_batch_t<VT, VI_LAYOUT_BRICK4, VI_BF16>(f, t, n, K, s)
-                              : launch_batch_t<VT, VI_LAYOUT_BRICK4, VI_F32>(f, t, n, K, s);
-    return sdt == VI_BF16 ? launch_batch_t<VT, VI_LAYOUT_LINEAR, VI_BF16>(f, t, n, K, s)
-                          : launch_batch_t<VT, VI_LAYOUT_LINEAR, VI_F32>(f, t, n, K, s);
+    if (sdt == VI_BF16)
+        return sl == VI_STACK_QUADS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_QUADS>(f, t, n, K, s)
+                                    : launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(f, t, n, K, s);
+    return sl == VI_STACK_QUADS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_QUADS>(f, t, n, K, s)
+                                : launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_TILED>(f, t, n, K, s);
 }
 
-hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, const RenderFrame* d_frames,
-                               const uint32_t* d_tiles, uint32_t ntiles, int maxK, hipStream_t s)
+template <typename VT>
+static hipError_t launch_batch_vt(int layout, int sdt, int sl, const RenderFrame* f, const uint32_t* t, uint32_t n,
+                                  int K, hipStream_t s)
+{
+    return layout == VI_LAYOUT_BRICK4 ? launch_batch_l<VT, VI_LAYOUT_BRICK4>(sdt, sl, f, t, n, K, s)
+                                      : launch_batch_l<VT, VI_LAYOUT_LINEAR>(sdt, sl, f, t, n, K, s);
+}
+
+hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout,
+                               const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
+                               hipStream_t s)
 {
     switch (vol_dtype) {
-    case VI_U8: return launch_batch_vt<uint8_t>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
-    case VI_U16: return launch_batch_vt<uint16_t>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
-    case VI_F16: return launch_batch_vt<__half>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
-    default: return launch_batch_vt<float>(layout, stack_dtype, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_U8: return launch_batch_vt<uint8_t>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_U16:
+        return launch_batch_vt<uint16_t>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_F16: return launch_batch_vt<__half>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
+    default: return launch_batch_vt<float>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
     }
 }
 
-template <typename VT, int LAYOUT, int SDT>
+template <typename VT, int LAYOUT, int SDT, int SL>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
     dim3 grid(supertile_grid((f.width + kBX - 1) / kBX, (f.height + kBY - 1) / kBY)), block(256);
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K;
     switch (f.mode) {
     case VI_MODE_NONE:
-        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_NONE, SDT>), grid, block, lds, s, f);
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>), grid, block, lds, s, f);
         break;
     case VI_MODE_SHADOW:
-        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHADOW, SDT>), grid, block, lds, s, f);
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHADOW, SDT, SL>), grid, block, lds, s, f);
         break;
     case VI_MODE_SHELL:
-        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT>), grid, block, lds, s, f);
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>), grid, block, lds, s, f);
         break;
-    default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_CONE, SDT>), grid, block, lds, s, f); break;
+    default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, f); break;
     }
     return hipGetLastError();
 }
@@ -488,7 +538,10 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 template <typename VT, int LAYOUT>
 static hipError_t launch_sdt(const RenderFrame& f, hipStream_t s)
 {
-    return f.stack_dtype == VI_BF16 ? launch_mode<VT, LAYOUT, VI_BF16>(f, s) : launch_mode<VT, LAYOUT, VI_F32>(f, s);
+    const bool q = f.stack_layout == VI_STACK_QUADS;
+    if (f.stack_dtype == VI_BF16)
+        return q ? launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_QUADS>(f, s) : launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(f, s);
+    return q ? launch_mode<VT, LAYOUT, VI_F32, VI_STACK_QUADS>(f, s) : launch_mode<VT, LAYOUT, VI_F32, VI_STACK_TILED>(f, s);
 }
 
 template <typename VT>

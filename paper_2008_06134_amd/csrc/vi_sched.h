@@ -104,12 +104,12 @@ public:
 private:
     using clock = std::chrono::steady_clock;
     struct Key {
-        int vol_id, n, res, dtype;
+        int vol_id, n, res, dtype, layout;
         uint64_t lx, ly, lz;
         bool operator==(const Key& o) const
         {
-            return vol_id == o.vol_id && n == o.n && res == o.res && dtype == o.dtype && lx == o.lx && ly == o.ly &&
-                   lz == o.lz;
+            return vol_id == o.vol_id && n == o.n && res == o.res && dtype == o.dtype && layout == o.layout &&
+                   lx == o.lx && ly == o.ly && lz == o.lz;
         }
     };
     struct Stack {

@@ -74,7 +74,7 @@ public:
     int validate(const vi_request& r, const sched::VolumeRec& v) override
     {
         vi_slices sl;
-        int rc = vi_light_frame(r.light_dir, r.n_slices, r.slice_res, r.slice_dtype, &sl);
+        int rc = vi_light_frame(r.light_dir, r.n_slices, r.slice_res, r.slice_dtype, r.slice_layout, &sl);
         if (rc != VI_OK) return rc;
         sl.data = pool_;  // stands in for the cached stack
         sl.vol_n = v.vol.n;
@@ -85,19 +85,19 @@ public:
 
     size_t stack_bytes(const vi_request& r) override
     {
-        return vi_slices_bytes(r.n_slices, r.slice_res, r.slice_dtype);
+        return vi_slices_bytes(r.n_slices, r.slice_res, r.slice_dtype, r.slice_layout);
     }
 
     int frame_class(const vi_request& r, const sched::VolumeRec& v) override
     {
-        return (v.vol.dtype * 4 + v.vol.layout) * 8 + r.slice_dtype;
+        return ((v.vol.dtype * 4 + v.vol.layout) * 8 + r.slice_dtype) * 2 + r.slice_layout;
     }
 
     int build(const vi_request& r, const sched::VolumeRec& v, sched::StackRef* st) override
     {
         void* dst = (char*)pool_ + st->offset;
-        int rc = vi_build_attenuation(&v.vol, &v.tf, r.light_dir, r.n_slices, r.slice_res, r.slice_dtype, dst,
-                                      &st->desc, bs_);
+        int rc = vi_build_attenuation(&v.vol, &v.tf, r.light_dir, r.n_slices, r.slice_res, r.slice_dtype,
+                                      r.slice_layout, dst, &st->desc, bs_);
         if (rc != VI_OK) return rc;
         int h = -1;
         for (size_t i = 0; i < build_events_.size(); ++i)
@@ -157,8 +157,8 @@ public:
                 e = hipStreamWaitEvent(rs_, build_events_[f.stack->build_handle], 0);
         if (e == hipSuccess) {
             const vi_volume& v0 = frames[0].vol->vol;
-            e = launch_render_batch(v0.dtype, v0.layout, frames[0].req->slice_dtype, S.d_frames, S.d_tiles,
-                                    (uint32_t)tiles.size(), maxK, rs_);
+            e = launch_render_batch(v0.dtype, v0.layout, frames[0].req->slice_dtype, frames[0].req->slice_layout,
+                                    S.d_frames, S.d_tiles, (uint32_t)tiles.size(), maxK, rs_);
         }
         if (e == hipSuccess) e = hipEventRecord(S.done, rs_);
         if (e != hipSuccess) return fail_msg(VI_E_DEVICE, hipGetErrorString(e));

@@ -29,6 +29,7 @@ class VIError(RuntimeError):
 
 
 VI_LAYOUT_LINEAR, VI_LAYOUT_BRICK4 = 0, 1
+VI_STACK_TILED, VI_STACK_QUADS = 0, 1
 
 
 class Volume_t(C.Structure):
@@ -41,7 +42,7 @@ class TF_t(C.Structure):
 
 
 class Slices_t(C.Structure):
-    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("n", C.c_int), ("res", C.c_int),
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("layout", C.c_int), ("n", C.c_int), ("res", C.c_int),
                 ("L", C.c_double * 3), ("U", C.c_double * 3), ("V", C.c_double * 3), ("c", C.c_double * 3),
                 ("dmin", C.c_double), ("dmax", C.c_double), ("ds", C.c_double), ("R", C.c_double),
                 ("vol_n", C.c_int), ("tag", C.c_uint64)]
@@ -65,7 +66,7 @@ class ServerCfg_t(C.Structure):
 
 class Request_t(C.Structure):
     _fields_ = [("vol_id", C.c_int), ("light_dir", C.c_double * 3), ("n_slices", C.c_int), ("slice_res", C.c_int),
-                ("slice_dtype", C.c_int), ("camera", Camera_t), ("mode", C.c_int), ("step_vox", C.c_float),
+                ("slice_dtype", C.c_int), ("slice_layout", C.c_int), ("camera", Camera_t), ("mode", C.c_int), ("step_vox", C.c_float),
                 ("opts", RenderOpts_t), ("d_rgba", C.c_void_p), ("d_samples", C.c_void_p)]
 
 
@@ -82,14 +83,14 @@ SIGNATURES = {
     "vi_version": ([], C.c_char_p),
     "vi_last_error": ([], C.c_char_p),
     "vi_default_render_opts": ([C.POINTER(RenderOpts_t)], C.c_int),
-    "vi_slices_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
+    "vi_slices_bytes": ([C.c_int, C.c_int, C.c_int, C.c_int], C.c_size_t),
     "vi_volume_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
     "vi_volume_to_bricks": ([C.POINTER(Volume_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_volume_minmax_bytes": ([C.c_int, C.c_int], C.c_size_t),
     "vi_volume_minmax": ([C.POINTER(Volume_t), C.c_int, C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
-    "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.POINTER(Slices_t)], C.c_int),
+    "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Slices_t)], C.c_int),
     "vi_build_attenuation": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_double), C.c_int, C.c_int,
-                              C.c_int, C.c_void_p, C.POINTER(Slices_t), C.c_void_p], C.c_int),
+                              C.c_int, C.c_int, C.c_void_p, C.POINTER(Slices_t), C.c_void_p], C.c_int),
     "vi_render": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(Slices_t), C.POINTER(Camera_t), C.c_int,
                    C.c_float, C.POINTER(RenderOpts_t), C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "vi_tag": ([C.POINTER(Volume_t), C.POINTER(TF_t)], C.c_uint64),
@@ -221,16 +222,28 @@ class TF:
 
 @dataclass
 class Slices:
-    """An attenuation stack: the device buffer (8 x 4 texel tiles per layer,
-    shaped n x R4/4 x R8/8 x 4 x 8) and its descriptor."""
+    """An attenuation stack: the device buffer and its descriptor.  Tiled:
+    8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Quads:
+    n x QH/2 x QW/4 x 2 x 4 x 4 (quad rows b' = b+1, columns a' = a+1, and
+    the four texels of each quad)."""
     data: torch.Tensor | None
     s: Slices_t
 
     def dense(self) -> torch.Tensor:
-        """The stack as an n x res x res tensor (a device copy, for inspection)."""
+        """The stack as an n x res x res tensor (a device view/copy, for inspection)."""
         n, r = self.s.n, self.s.res
         t = self.data
+        if self.s.layout == VI_STACK_QUADS:
+            q = t.permute(0, 1, 3, 2, 4, 5).reshape(n, t.shape[1] * 2, t.shape[2] * 4, 4)
+            return q[:, 1:r + 1, 1:r + 1, 0]
         return t.permute(0, 1, 3, 2, 4).reshape(n, t.shape[1] * 4, t.shape[2] * 8)[:, :r, :r]
+
+    def quads(self) -> torch.Tensor:
+        """Quad layout only: n x (res+1) x (res+1) x 4, quad (b+1, a+1) for a, b in [-1, res-1]."""
+        n, r = self.s.n, self.s.res
+        t = self.data
+        q = t.permute(0, 1, 3, 2, 4, 5).reshape(n, t.shape[1] * 2, t.shape[2] * 4, 4)
+        return q[:, :r + 1, :r + 1]
 
     @property
     def n(self):
@@ -289,14 +302,17 @@ def render_opts(opts: dict | None) -> RenderOpts_t:
 # calls
 # ---------------------------------------------------------------------------
 
-def slices_bytes(n: int, res: int, dtype: int = VI_F32) -> int:
-    return int(lib().vi_slices_bytes(n, res, dtype))
+def slices_bytes(n: int, res: int, dtype: int = VI_F32, layout: int = VI_STACK_TILED) -> int:
+    return int(lib().vi_slices_bytes(n, res, dtype, layout))
 
 
-def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda") -> torch.Tensor:
-    """An uninitialised device buffer in the stack layout (n x R4/4 x R8/8 x 4 x 8)."""
-    r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
+def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda", layout: int = VI_STACK_TILED) -> torch.Tensor:
+    """An uninitialised device buffer in a stack layout (shapes as in Slices)."""
     tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
+    if layout == VI_STACK_QUADS:
+        qw, qh = (res + 1 + 3) // 4 * 4, (res + 1 + 1) // 2 * 2
+        return torch.empty((n, qh // 2, qw // 4, 2, 4, 4), dtype=tdt, device=device)
+    r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
     return torch.empty((n, r4 // 4, r8 // 8, 4, 8), dtype=tdt, device=device)
 
 
@@ -304,24 +320,24 @@ def volume_bytes(n: int, dtype: int, layout: int) -> int:
     return int(lib().vi_volume_bytes(n, dtype, layout))
 
 
-def light_frame(light_dir, n: int, res: int, dtype: int = VI_F32) -> Slices:
+def light_frame(light_dir, n: int, res: int, dtype: int = VI_F32, layout: int = VI_STACK_TILED) -> Slices:
     s = Slices_t()
-    _check(lib().vi_light_frame(_vec3(light_dir), int(n), int(res), int(dtype), C.byref(s)))
+    _check(lib().vi_light_frame(_vec3(light_dir), int(n), int(res), int(dtype), int(layout), C.byref(s)))
     return Slices(None, s)
 
 
 def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: int, dtype: int = VI_F32,
-                      out: torch.Tensor | None = None, stream=None) -> Slices:
+                      out: torch.Tensor | None = None, stream=None, layout: int = VI_STACK_TILED) -> Slices:
     """Attenuation stack for `light_dir` (section 3.2.1, Alg. 1); returns the stack
-    (n x res x res float32 transmittance, or bfloat16 optical depth) and its descriptor."""
+    (float32 transmittance, or bfloat16 optical depth) and its descriptor."""
     if out is None:
-        out = stack_buffer(n_slices, slice_res, dtype, vol.data.device)
-    if out.numel() * out.element_size() < slices_bytes(n_slices, slice_res, dtype):
+        out = stack_buffer(n_slices, slice_res, dtype, vol.data.device, layout)
+    if out.numel() * out.element_size() < slices_bytes(n_slices, slice_res, dtype, layout):
         raise ValueError("stack buffer too small")
     s = Slices_t()
     _check(lib().vi_build_attenuation(C.byref(vol.s), C.byref(tf.s), _vec3(light_dir), int(n_slices),
-                                      int(slice_res), int(dtype), C.c_void_p(out.data_ptr()), C.byref(s),
-                                      _stream(stream)))
+                                      int(slice_res), int(dtype), int(layout), C.c_void_p(out.data_ptr()),
+                                      C.byref(s), _stream(stream)))
     return Slices(out, s)
 
 
@@ -392,7 +408,8 @@ class Server:
 
     def submit(self, vol_id: int, light_dir, n_slices: int, slice_res: int, cam: dict, mode: str,
                step_vox: float, opts: dict | None = None, out: torch.Tensor | None = None,
-               samples: torch.Tensor | None = None, dtype: int = VI_F32, device="cuda") -> tuple:
+               samples: torch.Tensor | None = None, dtype: int = VI_F32, device="cuda",
+               layout: int = VI_STACK_TILED) -> tuple:
         W, H = int(cam["width"]), int(cam["height"])
         if out is None:
             out = torch.empty((H, W, 4), dtype=torch.float32, device=device)
@@ -400,6 +417,7 @@ class Server:
         r.vol_id = int(vol_id)
         r.light_dir = _vec3(light_dir)
         r.n_slices, r.slice_res, r.slice_dtype = int(n_slices), int(slice_res), int(dtype)
+        r.slice_layout = int(layout)
         r.camera = camera(cam)
         r.mode = MODES[mode]
         r.step_vox = float(step_vox)

@@ -86,12 +86,12 @@ class _Fake:
         self.tf = vi.TF_t(0x20000, K)
 
 
-def _build(f, light=(0, 0, 1), n=8, res=8, dt=vi.VI_F32, buf=0x30000, desc=True):
+def _build(f, light=(0, 0, 1), n=8, res=8, dt=vi.VI_F32, buf=0x30000, desc=True, layout=vi.VI_STACK_TILED):
     lib = vi.lib()
     s = vi.Slices_t()
     return lib.vi_build_attenuation(C.byref(f.vol) if f.vol else None, C.byref(f.tf) if f.tf else None,
-                                    vi._vec3(light), n, res, dt, C.c_void_p(buf), C.byref(s) if desc else None,
-                                    C.c_void_p(0))
+                                    vi._vec3(light), n, res, dt, layout, C.c_void_p(buf),
+                                    C.byref(s) if desc else None, C.c_void_p(0))
 
 
 def test_build_validation_errors():
@@ -108,6 +108,8 @@ def test_build_validation_errors():
     assert _build(f) == -1
     assert _build(_Fake(), buf=0) == -1
     assert _build(_Fake(), buf=0x30002) == -1        # misaligned stack
+    assert _build(_Fake(), buf=0x30008) == -1        # stacks are 16-byte aligned
+    assert _build(_Fake(), layout=2) == -2           # unknown stack layout
     assert _build(_Fake(), light=(0, 0, 0)) == -1
     assert _build(_Fake(), dt=vi.VI_U16) == -2
     assert _build(_Fake(), desc=False) == -1
@@ -153,6 +155,12 @@ def test_render_validation_errors():
     bad = _desc(f)
     bad.tag = 12345
     assert _render(f, bad) == -1                               # stack from another volume
+    bad = _desc(f)
+    bad.layout = 3
+    assert _render(f, bad) == -2                               # unknown stack layout
+    bad = _desc(f)
+    bad.data = 0x50008
+    assert _render(f, bad) == -1                               # stack not 16-byte aligned
     cam = {"kind": "persp", "eye": [0.5, 0.5, 0.5], "target": [0.5, 0.5, 0.5], "up": [0, 0, 1], "fovy_deg": 40,
            "width": 8, "height": 8}
     assert _render(f, good, cam=cam) == -1                     # eye == target
@@ -197,6 +205,10 @@ def test_volume_bytes_and_brick_validation():
     assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -2
     # stack buffers are padded to whole 8 x 4 tiles
     assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4
+    # quads: (res+1 rounded up to 4) x (res+1 rounded up to 2) quads of 4 texels
+    assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_QUADS) == 3 * 12 * 12 * 4 * 4
+    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_QUADS) == 2 * 1028 * 1026 * 4 * 2
+    assert vi.slices_bytes(2, 8, vi.VI_F32, 5) == 0
 
 
 def test_minmax_validation():

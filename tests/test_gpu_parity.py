@@ -22,6 +22,8 @@ TOL_IMG = 1e-4      # per RGBA channel, FP32 path
 TOL_STACK = 2e-5    # transmittance, FP32 product over <= 512 slabs
 
 DEV = "cuda"
+LAYOUTS = (vi.VI_STACK_TILED, vi.VI_STACK_QUADS)
+LNAME = {vi.VI_STACK_TILED: "tiled", vi.VI_STACK_QUADS: "quads"}
 
 
 def _mode(m):
@@ -58,21 +60,22 @@ def test_small_full_image(mode):
     raw, tab = w.volume(), w.tf()
     light = w.lights()[0]
     vol, tf = gpu_inputs(raw, tab)
-    st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res)
     ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
     S = ost.export()
-    err_s = np.abs(st.dense().cpu().double().numpy() - S).max()
-    report("small stack", err_s)
-    assert err_s <= TOL_STACK
     cam = w.camera()
     m, extra = _mode(mode)
     opts = {"bg": [0.1, 0.05, 0.02, 0.3], **extra}
-    img, ns = gpu_render(vol, tf, st, cam, m, w.step_vox, opts)
     _, ref, nt, nf = O.render(O.Volume(raw), O.TF(tab), ost, cam, m, w.step_vox, opts, want_full=False)
-    err = np.abs(img - ref).max()
-    report(f"small {mode}", err)
-    assert err <= TOL_IMG
-    assert abs(ns - nt.sum()) <= 1e-3 * nt.sum() + 16
+    for lay in LAYOUTS:
+        st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res, layout=lay)
+        err_s = np.abs(st.dense().cpu().double().numpy() - S).max()
+        report(f"small stack ({LNAME[lay]})", err_s)
+        assert err_s <= TOL_STACK
+        img, ns = gpu_render(vol, tf, st, cam, m, w.step_vox, opts)
+        err = np.abs(img - ref).max()
+        report(f"small {mode} ({LNAME[lay]})", err)
+        assert err <= TOL_IMG
+        assert abs(ns - nt.sum()) <= 1e-3 * nt.sum() + 16
 
 
 # ---------------------------------------------------------------- medium / large, sampled
@@ -87,28 +90,32 @@ def _sample_pixels(W_, H_, count, seed):
 
 
 def _sampled_parity(name, raw, tab, light, n, res, cam, mode, step, opts, npix, seed, cols=1500):
+    """Both stack layouts against one oracle reference (sampled stack columns and pixels)."""
     vol, tf = gpu_inputs(raw, tab)
-    st = vi.build_attenuation(vol, tf, light, n, res)
-    torch.cuda.synchronize()
     ovol, otf = O.Volume(raw), O.TF(tab)
     ost = O.Stack(ovol, otf, light, n, res)
     rng = np.random.default_rng(seed + 1)
-    S = st.dense()
     ij = rng.integers(0, res, size=(cols, 2))
-    got = S[:, ij[:, 1], ij[:, 0]].cpu().double().numpy()
     want = np.stack([ost.column(i, j) for i, j in ij], axis=1)
-    err_s = np.abs(got - want).max()
-    report(f"{name} stack columns", err_s)
-    assert err_s <= TOL_STACK
-    img, ns = gpu_render(vol, tf, st, cam, mode, step, opts)
     pix = _sample_pixels(cam["width"], cam["height"], npix, seed)
     _, ref, nt, _ = O.render(ovol, otf, ost, cam, mode, step, opts, pixels=pix, want_full=False)
-    got = img.reshape(-1, 4)[pix]
-    err = np.abs(got - ref).max()
-    worst = pix[np.argmax(np.abs(got - ref).max(axis=1))]
-    report(f"{name} {mode} ({pix.size} px, worst pixel {worst % cam['width']},{worst // cam['width']})", err)
-    assert err <= TOL_IMG
-    return ns
+    for lay in LAYOUTS:
+        st = vi.build_attenuation(vol, tf, light, n, res, layout=lay)
+        torch.cuda.synchronize()
+        S = st.dense()
+        got = S[:, torch.as_tensor(ij[:, 1], device=DEV), torch.as_tensor(ij[:, 0], device=DEV)]
+        err_s = np.abs(got.cpu().double().numpy() - want).max()
+        report(f"{name} stack columns ({LNAME[lay]})", err_s)
+        assert err_s <= TOL_STACK
+        del S, got
+        img, ns = gpu_render(vol, tf, st, cam, mode, step, opts)
+        del st
+        got = img.reshape(-1, 4)[pix]
+        err = np.abs(got - ref).max()
+        worst = pix[np.argmax(np.abs(got - ref).max(axis=1))]
+        report(f"{name} {mode} {LNAME[lay]} ({pix.size} px, worst pixel {worst % cam['width']},"
+               f"{worst // cam['width']})", err)
+        assert err <= TOL_IMG
 
 
 @pytest.fixture(scope="module")
@@ -188,18 +195,19 @@ def test_ragged_and_degenerate_shapes(N, n, res, W_, H_, light, kind, mode):
     raw = W.sphere_u8(N, radius=N * 0.3, density=190, noise=25, seed=N)
     tab = W.tf_ramp()
     vol, tf = gpu_inputs(raw, tab)
-    st = vi.build_attenuation(vol, tf, light, n, res)
     ost = O.Stack(O.Volume(raw), O.TF(tab), light, n, res)
-    err_s = np.abs(st.dense().cpu().double().numpy() - ost.export()).max()
-    assert err_s <= TOL_STACK
     cam = W.camera_orbit(W_, H_, 0.8, 0.4, distance=1.8) if kind == "persp" else W.camera_ortho_front(W_, H_)
     m, extra = _mode(mode)
     opts = {"bg": [0.2, 0.1, 0.0, 0.5], "ambient": 0.15, **extra}
-    img, ns = gpu_render(vol, tf, st, cam, m, 0.5, opts)
     _, ref, nt, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, m, 0.5, opts, want_full=False)
-    err = np.abs(img - ref).max()
-    report(f"ragged N={N} n={n} res={res} {W_}x{H_} {mode}", err)
-    assert err <= TOL_IMG
+    for lay in LAYOUTS:
+        st = vi.build_attenuation(vol, tf, light, n, res, layout=lay)
+        err_s = np.abs(st.dense().cpu().double().numpy() - ost.export()).max()
+        assert err_s <= TOL_STACK
+        img, ns = gpu_render(vol, tf, st, cam, m, 0.5, opts)
+        err = np.abs(img - ref).max()
+        report(f"ragged N={N} n={n} res={res} {W_}x{H_} {mode} {LNAME[lay]}", err)
+        assert err <= TOL_IMG
 
 
 @pytest.mark.parametrize("dtype", [np.uint16, np.float16, np.float32])
@@ -318,3 +326,41 @@ def test_stack_is_camera_independent_and_deterministic():
     i2 = vi.render(vol, tf, a, cam, "shell", 0.5)
     torch.cuda.synchronize()
     assert torch.equal(i1, i2)
+
+
+@pytest.mark.parametrize("res", [1, 6, 19, 64])
+@pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
+def test_quad_layout_matches_its_definition(res, dtype):
+    """Quad (k, b, a) holds T(k,b,a), T(k,b,a+1), T(k,b+1,a), T(k,b+1,a+1) for
+    a, b in [-1, res-1], with the texels outside the grid fully transmitting
+    (optical depth 0); compared bit for bit with the tiled stack."""
+    raw = W.sphere_u8(30, radius=10, density=200, noise=30, seed=res)
+    vol, tf = gpu_inputs(raw, W.tf_ramp())
+    light, n = [0.3, -0.5, 0.8], 11
+    t = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_TILED)
+    q = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_QUADS)
+    torch.cuda.synchronize()
+    D = t.dense()
+    ring = torch.ones(()) if dtype == vi.VI_F32 else torch.zeros(())
+    P = torch.full((n, res + 2, res + 2), float(ring), dtype=D.dtype, device=DEV)   # padded by one texel
+    P[:, 1:res + 1, 1:res + 1] = D
+    Q = q.quads()
+    assert Q.shape == (n, res + 1, res + 1, 4)
+    for c, (da, db) in enumerate([(0, 0), (1, 0), (0, 1), (1, 1)]):
+        assert torch.equal(Q[..., c], P[:, db:db + res + 1, da:da + res + 1])
+    assert torch.equal(q.dense(), D)
+
+
+@pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
+@pytest.mark.parametrize("mode", ["shadow", "shell", "cone", "cone5"])
+def test_quad_layout_gives_bitwise_identical_images(dtype, mode):
+    raw = W.ct_phantom_u16(56, seed=6, vessels=True)
+    vol, tf = gpu_inputs(raw, W.tf_ct())
+    light = [-0.4, 0.7, 0.6]
+    m, extra = _mode(mode)
+    cam = W.camera_orbit(83, 61, 1.9, 0.45)
+    out = []
+    for lay in LAYOUTS:
+        st = vi.build_attenuation(vol, tf, light, 45, 77, dtype, layout=lay)
+        out.append(gpu_render(vol, tf, st, cam, m, 0.5, extra))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
