@@ -87,7 +87,9 @@ typedef enum {
     VI_MODE_NONE = 0,   /* coefficient 1: unlit emission-absorption        */
     VI_MODE_SHADOW = 1, /* transmittance at the sample itself (section 3)  */
     VI_MODE_SHELL = 2,  /* shell distribution (section 3.2.3)              */
-    VI_MODE_CONE = 3    /* cone distribution (section 3.2.3, Eq. 11)       */
+    VI_MODE_CONE = 3,   /* cone distribution (section 3.2.3, Eq. 11)       */
+    VI_MODE_PHONG = 4   /* local Phong model, the comparison mode of section 4:
+                           central-difference normals, no stack read       */
 } vi_mode;
 
 typedef enum { VI_CAM_ORTHO = 0, VI_CAM_PERSP = 1 } vi_camera_kind;
@@ -189,6 +191,16 @@ typedef struct {
     int cone_angles;    /* 4: taps per ring, angles 2*pi*q/angles           */
     int cone_grid;      /* 0: ring form; G in 1..7: G x G lattice one slab toward the light */
     float cone_tan;     /* 1: ring radius m*ds*cone_tan; lattice pitch ds*cone_tan/2 */
+    /* VI_MODE_PHONG: emission alpha*(sd*rgb + ss)*light_rgb with
+     * sd = phong_ka + phong_kd*max(0, n.l), ss = phong_ks*max(0, r.v)^phong_shininess,
+     * n = -g / max(|g|, grad_eps) from central differences g (value per
+     * voxel) one voxel either side along x, y, z; l = -L, v = -ray
+     * direction, r = 2(n.l)n - (n.n)l. */
+    float phong_ka;        /* 0.1 */
+    float phong_kd;        /* 0.9 */
+    float phong_ks;        /* 0.4 */
+    float phong_shininess; /* 20  */
+    float grad_eps;        /* 0.02 */
 } vi_render_opts;
 
 /* Library version string. */
@@ -253,7 +265,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
  * width*height premultiplied RGBA floats to `d_rgba` (device, 16-byte
  * aligned, row-major, y = 0 on top).  step_vox > 0 is the ray step in
  * voxels.  `opts` may be NULL (defaults).  `slices` may be NULL only for
- * VI_MODE_NONE.  If `d_samples` (device) is non-NULL the number of
+ * VI_MODE_NONE; VI_MODE_PHONG reads only its light direction, so a
+ * descriptor from vi_light_frame (data NULL) serves.  If `d_samples` (device) is non-NULL the number of
  * segments composited (stopping at termination) is ADDED to it.
  * Errors: VI_E_INVALID_ARG for NULL/misaligned pointers, bad sizes, a
  * descriptor whose vol_n differs from the volume or whose non-zero tag

@@ -11,7 +11,9 @@ What the oracle computes (paper sections in brackets):
   * ``Stack``            -- Alg. 1 attenuation stack, layer k = transmittance
                             after slab k; ``lookup`` is Eq. 9 index + Eq. 10 UV
   * ``render``           -- single-pass ray casting, Eq. 3 compositing with the
-                            Eq. 7 coefficient (direct shadow, shell, cone)
+                            Eq. 7 coefficient (direct shadow, shell, cone), or
+                            the local Phong model of the comparison in section 4
+                            (``gradient``, ``phong``)
 """
 from __future__ import annotations
 
@@ -25,7 +27,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vi_oracle.c")
 _LIB = os.path.join(_HERE, "libvi_oracle.so")
 
-MODES = {"none": 0, "shadow": 1, "shell": 2, "cone": 3}
+MODES = {"none": 0, "shadow": 1, "shell": 2, "cone": 3, "phong": 4}
+_PHONG_KEYS = ("phong_ka", "phong_kd", "phong_ks", "phong_shininess", "grad_eps")
 DTYPES = {np.dtype(np.uint8): 0, np.dtype(np.uint16): 1, np.dtype(np.float16): 2, np.dtype(np.float32): 3}
 
 
@@ -62,7 +65,9 @@ class _Camera(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("ambient", C.c_double), ("light_rgb", C.c_double * 3), ("bg", C.c_double * 4),
                 ("term_eps", C.c_double), ("shell_count", C.c_int), ("shell_h_vox", C.c_double),
-                ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_double)]
+                ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_double),
+                ("phong_ka", C.c_double), ("phong_kd", C.c_double), ("phong_ks", C.c_double),
+                ("phong_shininess", C.c_double), ("grad_eps", C.c_double)]
 
 
 _lib = None
@@ -98,6 +103,9 @@ def _load():
         lib.vio_cube_hit.argtypes = [P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)]
         lib.vio_coefficient.argtypes = [C.c_void_p, C.c_int, P(_Opts), C.c_int, P(C.c_double), P(C.c_double)]
         lib.vio_coefficient.restype = C.c_double
+        lib.vio_gradient.argtypes = [P(_Volume), P(C.c_double), P(C.c_double)]
+        lib.vio_phong.argtypes = [P(_Volume), P(_Opts), P(C.c_double), P(C.c_double), P(C.c_double),
+                                  P(C.c_double), P(C.c_double)]
         lib.vio_render.argtypes = [P(_Volume), P(_TF), C.c_void_p, P(_Camera), C.c_int, C.c_double, P(_Opts),
                                    P(C.c_int64), C.c_int64, P(C.c_double), P(C.c_double), P(C.c_int64),
                                    P(C.c_int64), C.c_int]
@@ -124,7 +132,8 @@ def default_opts() -> dict:
     _load().vio_default_opts(C.byref(o))
     return {"ambient": o.ambient, "light_rgb": list(o.light_rgb), "bg": list(o.bg), "term_eps": o.term_eps,
             "shell_count": o.shell_count, "shell_h_vox": o.shell_h_vox, "cone_rings": o.cone_rings,
-            "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan}
+            "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan,
+            **{k: getattr(o, k) for k in _PHONG_KEYS}}
 
 
 def _opts(opts: dict | None) -> _Opts:
@@ -138,6 +147,8 @@ def _opts(opts: dict | None) -> _Opts:
     o.term_eps = d["term_eps"]
     o.shell_count = int(d["shell_count"])
     o.shell_h_vox = d["shell_h_vox"]
+    for k in _PHONG_KEYS:
+        setattr(o, k, float(d[k]))
     o.cone_rings = int(d["cone_rings"])
     o.cone_angles = int(d["cone_angles"])
     o.cone_grid = int(d["cone_grid"])
@@ -179,6 +190,20 @@ def light_frame(l, n: int, res: int) -> dict:
 
 def volume_sample(vol: Volume, p) -> float:
     return _load().vio_volume_sample(C.byref(vol._s), _vec(p))
+
+
+def gradient(vol: Volume, p) -> np.ndarray:
+    """Central differences of the reconstructed field at p, value per voxel (R29)."""
+    g = (C.c_double * 3)()
+    _load().vio_gradient(C.byref(vol._s), _vec(p), g)
+    return np.array(g)
+
+
+def phong(vol: Volume, L, p, d, opts: dict | None = None):
+    """Local Phong terms (sd, ss) at p for ray direction d, light propagation direction L."""
+    sd, ss = C.c_double(), C.c_double()
+    _load().vio_phong(C.byref(vol._s), C.byref(_opts(opts)), _vec(L), _vec(p), _vec(d), C.byref(sd), C.byref(ss))
+    return sd.value, ss.value
 
 
 def tf_lookup(tf: TF, v: float) -> np.ndarray:

@@ -67,6 +67,13 @@ void vio_default_opts(vio_opts* o)
     o->cone_angles = 4;
     o->cone_grid = 0;
     o->cone_tan = 1.0;
+    /* the local-illumination comparison mode (section 4, Fig. 7 (b)):
+     * readings R29-R32 */
+    o->phong_ka = 0.1;
+    o->phong_kd = 0.9;
+    o->phong_ks = 0.4;
+    o->phong_shininess = 20.0;
+    o->grad_eps = 0.02;
 }
 
 /* ------------------------------------------------------------------ */
@@ -419,6 +426,44 @@ double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N, const d
 }
 
 /* ------------------------------------------------------------------ */
+/* Local illumination (section 4's Phong comparison mode).  The normal   */
+/* comes from central differences of the reconstructed field one voxel  */
+/* either side along each axis (R29); n = -g / max(|g|, grad_eps), so it */
+/* is a unit vector wherever the field changes by at least grad_eps per  */
+/* voxel and shrinks smoothly to zero in flat regions (R30).  Light      */
+/* vector l = -L, view vector v = -d (R31); Phong reflection            */
+/* r = 2 (n.l) n - (n.n) l, which is the mirror of l for a unit n (R32). */
+/* ------------------------------------------------------------------ */
+void vio_gradient(const vio_volume* v, const double p[3], double g[3])
+{
+    double h = 1.0 / v->N;
+    for (int a = 0; a < 3; ++a) {
+        double q1[3] = {p[0], p[1], p[2]}, q0[3] = {p[0], p[1], p[2]};
+        q1[a] += h;
+        q0[a] -= h;
+        g[a] = 0.5 * (vio_volume_sample(v, q1) - vio_volume_sample(v, q0));
+    }
+}
+
+void vio_phong(const vio_volume* v, const vio_opts* o, const double L[3], const double p[3], const double d[3],
+               double* sd, double* ss)
+{
+    double g[3], n[3], l[3], w[3], r[3];
+    vio_gradient(v, p, g);
+    double gn = norm3(g), den = gn > o->grad_eps ? gn : o->grad_eps;
+    for (int a = 0; a < 3; ++a) {
+        n[a] = -g[a] / den;
+        l[a] = -L[a];
+        w[a] = -d[a];
+    }
+    double nl = dot3(n, l), nn = dot3(n, n);
+    for (int a = 0; a < 3; ++a) r[a] = 2.0 * nl * n[a] - nn * l[a];
+    double rv = dot3(r, w);
+    *sd = o->phong_ka + o->phong_kd * (nl > 0.0 ? nl : 0.0);
+    *ss = o->phong_ks * (rv > 0.0 ? pow(rv, o->phong_shininess) : 0.0);
+}
+
+/* ------------------------------------------------------------------ */
 /* Camera rays (Eq. 10's camera matrices E_mv, E_vi; reading R27).       */
 /* ------------------------------------------------------------------ */
 int vio_camera_ray(const vio_camera* cam, int px, int py, double o[3], double d[3])
@@ -502,10 +547,19 @@ static void render_pixel(const vio_volume* v, const vio_tf* tf, vio_stack* s, co
             double alpha = vio_segment_alpha(rgba[3], len, dref);
             /* The coefficient only scales an emission that is zero when
              * alpha is zero, so it is gathered only where alpha > 0. */
-            double A = 1.0;
-            if (alpha > 0.0) A = vio_coefficient(s, mode, o, v->N, p, rd);
-            double sh = o->ambient + (1.0 - o->ambient) * A;
-            for (int c = 0; c < 3; ++c) C[c] += (1.0 - ad) * (alpha * sh * rgba[c] * o->light_rgb[c]);
+            double sd = 1.0, ss = 0.0;
+            if (alpha > 0.0) {
+                if (mode == VIO_MODE_PHONG) {
+                    vio_phong(v, o, s->f.L, p, rd, &sd, &ss);
+                } else {
+                    double A = vio_coefficient(s, mode, o, v->N, p, rd);
+                    sd = o->ambient + (1.0 - o->ambient) * A;
+                }
+            }
+            /* emission alpha (sd rgb + ss) (x) light: Eq. 7 with the
+             * coefficient, or the Phong terms (specular uncoloured) */
+            for (int c = 0; c < 3; ++c)
+                C[c] += (1.0 - ad) * (alpha * (sd * rgba[c] + ss) * o->light_rgb[c]);
             ad += (1.0 - ad) * alpha;
             if (!terminated && 1.0 - ad <= o->term_eps) {
                 terminated = 1;
@@ -536,7 +590,7 @@ int vio_render(const vio_volume* v, const vio_tf* tf, vio_stack* s, const vio_ca
                double* out_term, int64_t* samples_term, int64_t* samples_full, int nthreads)
 {
     if (!v || !tf || !cam || !o || !out_term || !(step_vox > 0.0)) return -1;
-    if (mode != VIO_MODE_NONE && !s) return -1;
+    if (mode != VIO_MODE_NONE && !s) return -1;  /* Phong takes its light from the stack's frame */
     int64_t W = cam->width;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();

@@ -37,7 +37,7 @@ extern "C" {
 #endif
 
 enum { VIO_U8 = 0, VIO_U16 = 1, VIO_F16 = 2, VIO_F32 = 3 };
-enum { VIO_MODE_NONE = 0, VIO_MODE_SHADOW = 1, VIO_MODE_SHELL = 2, VIO_MODE_CONE = 3 };
+enum { VIO_MODE_NONE = 0, VIO_MODE_SHADOW = 1, VIO_MODE_SHELL = 2, VIO_MODE_CONE = 3, VIO_MODE_PHONG = 4 };
 enum { VIO_CAM_ORTHO = 0, VIO_CAM_PERSP = 1 };
 
 typedef struct {
@@ -81,6 +81,10 @@ typedef struct {
     int cone_angles;      /* taps per ring (ring form)                    */
     int cone_grid;        /* 0: ring form, G > 0: G x G lattice form      */
     double cone_tan;      /* tan of the cone half-angle                   */
+    double phong_ka, phong_kd, phong_ks; /* local Phong model (no stack)  */
+    double phong_shininess;
+    double grad_eps;      /* gradient magnitude (per voxel) below which the
+                             normal shrinks toward zero                     */
 } vio_opts;
 
 /* Stack of light-space transmittance slices.  Columns are built on demand
@@ -112,6 +116,15 @@ int64_t    vio_stack_columns_built(const vio_stack* s);
  * if it hits the unit cube, else 0 */
 int  vio_camera_ray(const vio_camera* cam, int px, int py, double o[3], double d[3]);
 int  vio_cube_hit(const double o[3], const double d[3], double* t_in, double* t_far);
+
+/* central-difference gradient of the reconstructed field at p, in value
+ * per voxel */
+void vio_gradient(const vio_volume* v, const double p[3], double g[3]);
+/* local Phong terms at p for a ray of direction d and light propagation
+ * direction L: diffuse factor sd = ka + kd max(0, n.l) and specular term
+ * ss = ks max(0, r.v)^shininess */
+void vio_phong(const vio_volume* v, const vio_opts* o, const double L[3], const double p[3], const double d[3],
+               double* sd, double* ss);
 
 /* coefficient A at p for a ray of direction d */
 double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N,

@@ -161,6 +161,11 @@ int vi_default_render_opts(vi_render_opts* o)
     o->cone_angles = 4;
     o->cone_grid = 0;
     o->cone_tan = 1.0f;
+    o->phong_ka = 0.1f;
+    o->phong_kd = 0.9f;
+    o->phong_ks = 0.4f;
+    o->phong_shininess = 20.0f;
+    o->grad_eps = 0.02f;
     return VI_OK;
 }
 
@@ -341,7 +346,7 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     int rc;
     if ((rc = check_volume(vol)) != VI_OK) return rc;
     if ((rc = check_tf(tf)) != VI_OK) return rc;
-    if (mode < VI_MODE_NONE || mode > VI_MODE_CONE) return fail(VI_E_UNSUPPORTED, "mode %d not supported", mode);
+    if (mode < VI_MODE_NONE || mode > VI_MODE_PHONG) return fail(VI_E_UNSUPPORTED, "mode %d not supported", mode);
     if (!cam) return fail(VI_E_INVALID_ARG, "NULL camera");
     if (!d_rgba) return fail(VI_E_INVALID_ARG, "NULL output image");
     if (((uintptr_t)d_rgba) % 16) return fail(VI_E_INVALID_ARG, "output image must be 16-byte aligned");
@@ -356,7 +361,19 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     else vi_default_render_opts(&o);
     if (!(o.term_eps >= 0.0f && o.term_eps < 1.0f) || !(o.ambient >= 0.0f && o.ambient <= 1.0f))
         return fail(VI_E_INVALID_ARG, "term_eps must be in [0,1) and ambient in [0,1]");
-    if (mode != VI_MODE_NONE) {
+    const bool reads_stack = mode != VI_MODE_NONE && mode != VI_MODE_PHONG;
+    if (mode == VI_MODE_PHONG) {
+        if (!sl) return fail(VI_E_INVALID_ARG, "Phong mode needs a light frame");
+        const double l2 = dot3(sl->L, sl->L);
+        if (!(fabs(l2 - 1.0) < 1e-6)) return fail(VI_E_INVALID_ARG, "light frame has no unit direction");
+        if (!(o.phong_ka >= 0.0f && o.phong_kd >= 0.0f && o.phong_ks >= 0.0f) || !isfinite(o.phong_ka) ||
+            !isfinite(o.phong_kd) || !isfinite(o.phong_ks))
+            return fail(VI_E_INVALID_ARG, "Phong coefficients must be finite and >= 0");
+        if (!(o.phong_shininess >= 0.0f && o.phong_shininess <= 1024.0f))
+            return fail(VI_E_INVALID_ARG, "phong_shininess must be in [0, 1024]");
+        if (!(o.grad_eps > 0.0f) || !isfinite(o.grad_eps)) return fail(VI_E_INVALID_ARG, "grad_eps must be > 0");
+    }
+    if (reads_stack) {
         if (!sl || !sl->data) return fail(VI_E_INVALID_ARG, "mode %d needs a stack", mode);
         if (sl->dtype != VI_F32 && sl->dtype != VI_BF16) return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);
         if (sl->layout != VI_STACK_TILED && sl->layout != VI_STACK_QUADS)
@@ -384,7 +401,9 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     F.tf = tf->rgba;
     F.K = tf->n_entries;
     F.mode = mode;
-    if (mode != VI_MODE_NONE) {
+    if (mode == VI_MODE_PHONG)
+        for (int a = 0; a < 3; ++a) F.L[a] = sl->L[a];
+    if (reads_stack) {
         F.stack = sl->data;
         F.stack_dtype = sl->dtype;
         F.n = sl->n;
@@ -447,6 +466,11 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     for (int c = 0; c < 3; ++c) F.light[c] = o.light_rgb[c];
     for (int c = 0; c < 4; ++c) F.bg[c] = o.bg[c];
     F.term_eps = o.term_eps;
+    F.phong_ka = o.phong_ka;
+    F.phong_kd = o.phong_kd;
+    F.phong_ks = o.phong_ks;
+    F.phong_shin = o.phong_shininess;
+    F.grad_eps = o.grad_eps;
 
     if (mode == VI_MODE_SHELL) {
         if (o.shell_count < 1 || 6 * o.shell_count > vi::kMaxTaps)

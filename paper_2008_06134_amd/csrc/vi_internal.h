@@ -88,6 +88,7 @@ struct RenderFrame {
     double dt;           // step in world units
     float N_f;           // voxels per world unit (segment exponent scale)
     float ambient, light[3], bg[4], term_eps;
+    float phong_ka, phong_kd, phong_ks, phong_shin, grad_eps;
     // gather taps in light-grid units (shell: fixed; cone: per ray)
     int ntaps;
     float tap_w;

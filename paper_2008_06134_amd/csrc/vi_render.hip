@@ -249,7 +249,18 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     // light grid: depth index (Eq. 9, minus one) and texel coordinates (Eq. 10)
     float qz0 = 0.f, qx0 = 0.f, qy0 = 0.f, qdz = 0.f, qdx = 0.f, qdy = 0.f;
     ConeFrame cf = {0.f, 0.f, 0.f, 0.f};
-    if (MODE != VI_MODE_NONE) {
+    // Phong: light vector l = -L and, folded in, l.v with v = -d
+    float lx = 0.f, ly = 0.f, lz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, lv = 0.f;
+    if (MODE == VI_MODE_PHONG) {
+        lx = (float)-F.L[0];
+        ly = (float)-F.L[1];
+        lz = (float)-F.L[2];
+        vx = (float)-d[0];
+        vy = (float)-d[1];
+        vz = (float)-d[2];
+        lv = (float)(F.L[0] * d[0] + F.L[1] * d[1] + F.L[2] * d[2]);
+    }
+    if (MODE != VI_MODE_NONE && MODE != VI_MODE_PHONG) {
         qz0 = (float)(F.Lq[0] * pin[0] + F.Lq[1] * pin[1] + F.Lq[2] * pin[2] + F.Lq0 - F.Mz);
         qx0 = (float)(F.Ux[0] * pin[0] + F.Ux[1] * pin[1] + F.Ux[2] * pin[2] + F.Ux0 - F.Mr);
         qy0 = (float)(F.Vy[0] * pin[0] + F.Vy[1] * pin[1] + F.Vy[2] * pin[2] + F.Vy0 - F.Mr);
@@ -349,13 +360,37 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                 if (len > 0.0f && a > 0.0f) om = fast_exp2(len * F.N_f * fast_log2(1.0f - a));
                 const float alpha = 1.0f - om;
                 if (alpha > 0.0f) {
-                    float A = 1.0f;
-                    if (MODE != VI_MODE_NONE)
-                        A = gather<MODE, SDT, SL>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
-                    const float e = alpha * fmaf(1.0f - F.ambient, A, F.ambient);
-                    cr = e * F.light[0] * fmaf(w, tb.x - ta.x, ta.x);
-                    cg = e * F.light[1] * fmaf(w, tb.y - ta.y, ta.y);
-                    cb = e * F.light[2] * fmaf(w, tb.z - ta.z, ta.z);
+                    // emission alpha (sd rgb + ss) light: Eq. 7 with the
+                    // coefficient A, or the local Phong terms
+                    float sd, ss = 0.0f;
+                    if (MODE == VI_MODE_PHONG) {
+                        // central differences one voxel either side (exact
+                        // offsets in voxel units)
+                        const float gx = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx + 1.f, hy, hz) -
+                                                 sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx - 1.f, hy, hz));
+                        const float gy = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy + 1.f, hz) -
+                                                 sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy - 1.f, hz));
+                        const float gz = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz + 1.f) -
+                                                 sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz - 1.f));
+                        const float gn = sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+                        const float inv = -1.0f / fmaxf(gn, F.grad_eps);  // n = -g / max(|g|, eps)
+                        const float nx = gx * inv, ny = gy * inv, nz = gz * inv;
+                        const float nl = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
+                        const float nv = fmaf(nx, vx, fmaf(ny, vy, nz * vz));
+                        const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+                        const float rv = fmaf(2.0f * nl, nv, -nn * lv);   // r.v, r = 2(n.l)n - (n.n)l
+                        sd = fmaf(F.phong_kd, fmaxf(nl, 0.0f), F.phong_ka);
+                        if (rv > 0.0f) ss = F.phong_ks * fast_exp2(F.phong_shin * fast_log2(rv));
+                    } else {
+                        float A = 1.0f;
+                        if (MODE != VI_MODE_NONE)
+                            A = gather<MODE, SDT, SL>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0),
+                                                      fmaf(sm, qdy, qy0));
+                        sd = fmaf(1.0f - F.ambient, A, F.ambient);
+                    }
+                    cr = alpha * F.light[0] * fmaf(sd, fmaf(w, tb.x - ta.x, ta.x), ss);
+                    cg = alpha * F.light[1] * fmaf(sd, fmaf(w, tb.y - ta.y, ta.y), ss);
+                    cb = alpha * F.light[2] * fmaf(sd, fmaf(w, tb.z - ta.z, ta.z), ss);
                 }
             }
         }
@@ -469,7 +504,8 @@ __global__ __launch_bounds__(256) void render_batch_kernel(const RenderFrame* __
     case VI_MODE_NONE: shade_pixel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>(F, s_tf, s_next, px, py); break;
     case VI_MODE_SHADOW: shade_pixel<VT, LAYOUT, VI_MODE_SHADOW, SDT, SL>(F, s_tf, s_next, px, py); break;
     case VI_MODE_SHELL: shade_pixel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>(F, s_tf, s_next, px, py); break;
-    default: shade_pixel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>(F, s_tf, s_next, px, py); break;
+    case VI_MODE_CONE: shade_pixel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>(F, s_tf, s_next, px, py); break;
+    default: shade_pixel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>(F, s_tf, s_next, px, py); break;
     }
 }
 
@@ -530,7 +566,10 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
     case VI_MODE_SHELL:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>), grid, block, lds, s, f);
         break;
-    default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, f); break;
+    case VI_MODE_CONE:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, f);
+        break;
+    default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, f); break;
     }
     return hipGetLastError();
 }

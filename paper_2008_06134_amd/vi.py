@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvi.so")
 
 VI_U8, VI_U16, VI_F16, VI_F32, VI_BF16 = 0, 1, 2, 3, 4
-MODES = {"none": 0, "shadow": 1, "shell": 2, "cone": 3}
+MODES = {"none": 0, "shadow": 1, "shell": 2, "cone": 3, "phong": 4}
+_PHONG_KEYS = ("phong_ka", "phong_kd", "phong_ks", "phong_shininess", "grad_eps")
 ERRORS = {-1: "VI_E_INVALID_ARG", -2: "VI_E_UNSUPPORTED", -3: "VI_E_NO_MEMORY", -4: "VI_E_DEVICE",
           -5: "VI_E_BUSY", -6: "VI_E_CANCELLED"}
 
@@ -56,7 +57,9 @@ class Camera_t(C.Structure):
 class RenderOpts_t(C.Structure):
     _fields_ = [("ambient", C.c_float), ("light_rgb", C.c_float * 3), ("bg", C.c_float * 4),
                 ("term_eps", C.c_float), ("shell_count", C.c_int), ("shell_h_vox", C.c_float),
-                ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_float)]
+                ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_float),
+                ("phong_ka", C.c_float), ("phong_kd", C.c_float), ("phong_ks", C.c_float),
+                ("phong_shininess", C.c_float), ("grad_eps", C.c_float)]
 
 
 class ServerCfg_t(C.Structure):
@@ -277,7 +280,8 @@ def default_opts() -> dict:
     _check(lib().vi_default_render_opts(C.byref(o)))
     return {"ambient": o.ambient, "light_rgb": list(o.light_rgb), "bg": list(o.bg), "term_eps": o.term_eps,
             "shell_count": o.shell_count, "shell_h_vox": o.shell_h_vox, "cone_rings": o.cone_rings,
-            "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan}
+            "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan,
+            **{k: getattr(o, k) for k in _PHONG_KEYS}}
 
 
 def render_opts(opts: dict | None) -> RenderOpts_t:
@@ -295,6 +299,8 @@ def render_opts(opts: dict | None) -> RenderOpts_t:
     o.cone_angles = int(d["cone_angles"])
     o.cone_grid = int(d["cone_grid"])
     o.cone_tan = d["cone_tan"]
+    for k in _PHONG_KEYS:
+        setattr(o, k, float(d[k]))
     return o
 
 
@@ -345,7 +351,8 @@ def render(vol: Volume, tf: TF, slices: Slices | None, cam: dict, mode: str, ste
            opts: dict | None = None, out: torch.Tensor | None = None, samples: torch.Tensor | None = None,
            stream=None) -> torch.Tensor:
     """Ray-cast one frame (sections 3.2.2-3.2.3, 4); returns H x W x 4 float32
-    premultiplied RGBA.  `samples` (int64 device tensor of one element) gets the
+    premultiplied RGBA.  Mode "phong" needs only the light frame of `slices`
+    (``light_frame(...)`` serves).  `samples` (int64 device tensor of one element) gets the
     number of composited segments added to it."""
     W, H = int(cam["width"]), int(cam["height"])
     if out is None:

@@ -176,6 +176,16 @@ def test_render_validation_errors():
     assert _render(f, good, mode=3, opts={"cone_angles": 17}) == -1
     assert _render(f, good, opts={"ambient": 1.5}) == -1
     assert "ambient" in vi.lib().vi_last_error().decode()
+    # Phong: needs a light frame (not a stack), sane coefficients
+    assert _render(f, None, mode=4) == -1
+    assert _render(f, good, mode=5) == -2
+    assert _render(f, good, mode=4, opts={"grad_eps": 0.0}) == -1
+    assert _render(f, good, mode=4, opts={"phong_shininess": -1.0}) == -1
+    assert _render(f, good, mode=4, opts={"phong_kd": math.nan}) == -1
+    assert _render(f, good, mode=4, opts={"phong_ks": -0.1}) == -1
+    nolight = _desc(f)
+    nolight.L = (C.c_double * 3)(0, 0, 0)
+    assert _render(f, nolight, mode=4) == -1
 
 
 def test_tag_distinguishes_inputs():

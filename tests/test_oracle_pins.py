@@ -430,3 +430,95 @@ def test_cone_taps_invariant_under_quarter_turn_of_view(grid):
     assert 0.0 < a_x < 1.0
     # the ring radius is c_m tan(phi): a narrower cone reads a different neighbourhood
     assert st.coefficient("cone", p, [-1.0, 0.0, 0.0], {"cone_grid": grid, "cone_tan": 0.2}) != pytest.approx(a_x)
+
+
+# ------------------------------------------------------------------ P10 local Phong (comparison mode)
+
+def _linear_volume(N, c0, grad):
+    """f32 volume f = c0 + grad . (x, y, z) in voxel-index units (raw[z][y][x])."""
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    return (c0 + grad[0] * x + grad[1] * y + grad[2] * z).astype(np.float32)
+
+
+def test_p10_gradient_of_a_linear_field_is_exact():
+    """Central differences of the trilinear reconstruction of a linear field are
+    the field's own gradient (per voxel) wherever no index is clamped; distinct
+    per-axis slopes catch a swapped or mis-signed axis."""
+    N, grad = 24, (2.0 ** -7, -(2.0 ** -8), 3 * 2.0 ** -10)   # dyadic: the f32 volume is exactly linear
+    vol = O.Volume(_linear_volume(N, 0.5, grad), 1.0)
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        g_vox = rng.uniform(1.0, N - 2.0, size=3)          # voxel coords: p +- 1 voxel stays unclamped
+        p = (g_vox + 0.5) / N
+        np.testing.assert_allclose(O.gradient(vol, p), grad, rtol=0, atol=1e-14)
+
+
+PHONG = {"phong_ka": 0.1, "phong_kd": 0.7, "phong_ks": 0.4, "phong_shininess": 4.0, "grad_eps": 0.02}
+
+
+@pytest.mark.parametrize("slope,L,sd_ss", [
+    # unit normal n = -x: light along the normal -> full diffuse, reflection along -x is
+    # perpendicular to the view -> no specular
+    (2.0 ** -5, (1, 0, 0), lambda o: (o["phong_ka"] + o["phong_kd"], 0.0)),
+    # light from behind the volume toward the camera: l = -v is perpendicular to n and
+    # mirrors onto the view direction -> no diffuse, full specular
+    (2.0 ** -5, (0, -1, 0), lambda o: (o["phong_ka"], o["phong_ks"])),
+    # oblique light at 30 degrees from the normal in the x-y plane: diffuse cos 30,
+    # mirror direction at 60 degrees from the view -> specular cos(60)^s... = sin(30)^s
+    (2.0 ** -5, (math.cos(math.radians(30)), -math.sin(math.radians(30)), 0),
+     lambda o: (o["phong_ka"] + o["phong_kd"] * math.cos(math.radians(30)),
+                o["phong_ks"] * math.sin(math.radians(30)) ** o["phong_shininess"])),
+    # flat field (|g| = 2^-8 < grad_eps): the normal shrinks to |g| / grad_eps;
+    # diffuse scales with it, the mirror term with its square (r.v = 0 here)
+    (2.0 ** -8, (1, 0, 0), lambda o: (o["phong_ka"] + o["phong_kd"] * 2.0 ** -8 / o["grad_eps"], 0.0)),
+])
+def test_p10_phong_closed_form_ramp(slope, L, sd_ss):
+    """Ortho view along +y through a field linear in x with a constant TF: every
+    segment of a ray has the same normal, so a pixel is (sd rgb + ss) times the
+    chord opacity 1 - (1 - a0)^N, for rays whose samples never clamp in x."""
+    N, a0, rgb = 24, 0.04, [0.9, 0.6, 0.3]
+    raw = _linear_volume(N, 0.125, (slope, 0.0, 0.0))   # dyadic: exactly linear in f32
+    vol, tf = O.Volume(raw, 1.0), _const_tf(rgb + [a0])
+    st = O.Stack(vol, tf, L, 4, 4)                       # the light frame only (no column is built)
+    cam = W.camera_ortho_front(48, 8, half_h=0.5 * 8 / 48)   # half width 0.5: the cube spans the image
+    full, _, _, _ = O.render(vol, tf, st, cam, "phong", 0.5, PHONG)
+    sd, ss = sd_ss(PHONG)
+    a_pix = 1 - (1 - a0) ** N
+    want = np.array([(sd * c + ss) * a_pix for c in rgb] + [a_pix])
+    checked = 0
+    for px in range(48):
+        x = 0.5 + (2 * (px + 0.5) / 48 - 1) * 0.5        # world x of the column (aspect 6, half width 0.5)
+        gx = x * N - 0.5
+        if 1.0 <= gx <= N - 2.0:
+            for py in range(8):
+                np.testing.assert_allclose(full[py, px], want, rtol=1e-12, atol=1e-15)
+            checked += 1
+    assert checked > 30
+    # the direct terms agree with the render
+    p = [0.5, 0.5, 0.5]
+    assert O.phong(vol, np.asarray(L, float) / np.linalg.norm(L), p, [0, 1, 0], PHONG) == pytest.approx((sd, ss), abs=1e-14)
+
+
+def test_p10_phong_reduces_to_unlit():
+    """k_a = 1, k_d = k_s = 0 gives exactly the unlit (A = 1) image."""
+    w = W.WORKLOADS["small"]
+    vol, tf = O.Volume(w.volume()), O.TF(w.tf())
+    st = O.Stack(vol, tf, w.lights()[0], w.n_slices, w.res)
+    cam = w.camera(W=24, H=24)
+    a, _, na, _ = O.render(vol, tf, st, cam, "phong", 0.5,
+                           {"phong_ka": 1.0, "phong_kd": 0.0, "phong_ks": 0.0}, want_full=False)
+    b, _, nb, _ = O.render(vol, tf, None, cam, "none", 0.5, want_full=False)
+    assert np.array_equal(a, b) and np.array_equal(na, nb)
+
+
+def test_p10_phong_sphere_lit_side_brighter():
+    """A lit sphere: rays hitting the side facing the light are brighter than those
+    on the far side (normal orientation -g points out of a dense object)."""
+    N = 40
+    raw = W.sphere_u8(N, radius=14, density=200, noise=0, seed=1)
+    vol, tf = O.Volume(raw), O.TF(W.tf_ramp())
+    st = O.Stack(vol, tf, [1, 0, 0], 4, 4)               # light travels +x: lit side is x < 0.5
+    cam = W.camera_ortho_front(32, 32, half_h=0.5)
+    full, _, _, _ = O.render(vol, tf, st, cam, "phong", 0.5, {"phong_ks": 0.0}, want_full=True)
+    lum = full[..., :3].sum(-1)
+    assert lum[12:20, 7:11].mean() > 1.5 * lum[12:20, 21:25].mean()
