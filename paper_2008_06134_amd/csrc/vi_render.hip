@@ -403,7 +403,10 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         }
         // front-to-back over the G segments of this step (Eq. 3 in product form)
         const float incl = group_scan_mul<G>(om, g);                  // prod_{h<=g} (1 - alpha_h)
-        const float excl = G == 1 ? 1.0f : (g == 0 ? 1.0f : __shfl_up(incl, 1, G));
+        // every lane of the group takes part in the shuffle (a lane that sat
+        // out would hand its neighbour no value)
+        const float up = G == 1 ? 1.0f : __shfl_up(incl, 1, G);
+        const float excl = g == 0 ? 1.0f : up;
         const uint32_t tb_ = group_bits<G>(in && T * incl <= F.term_eps, gbase);
         const int gs = tb_ ? __ffs(tb_) - 1 : G;                     // terminating segment, G if none
         const float keep = (g <= gs) ? T * excl : 0.0f;
