@@ -255,7 +255,8 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
  * float and rounded to bfloat16 per layer; each slab adds at most 64).
  * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes or a degenerate
  * light; VI_E_UNSUPPORTED for dtypes or sizes outside the limits above or a
- * stack of 4 GiB or more; VI_E_DEVICE if the launch fails. */
+ * tiled stack of 4 GiB or more or a quad stack of 2^32 quads or more;
+ * VI_E_DEVICE if the launch fails. */
 int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n_slices,
                          int slice_res, int slice_dtype, int slice_layout, void* d_slices, vi_slices* out_desc,
                          vi_stream_t stream);

@@ -100,6 +100,16 @@ void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
     }
 }
 
+// Kernels index a tiled stack with 32-bit element offsets and a quad stack
+// with 32-bit quad offsets: tiled stacks stay below 4 GiB, quad stacks below
+// 2^32 quads.
+bool stack_size_ok(int n, int res, int dt, int sl)
+{
+    const double bytes = (double)vi_slices_bytes(n, res, dt, sl);
+    if (sl == VI_STACK_QUADS) return bytes / (4.0 * elem_size(dt)) < 4294967296.0;
+    return bytes < 4294967296.0;
+}
+
 // Eq. 8 and the light projection: geometry of the stack in double.
 int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)
 {
@@ -275,8 +285,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     vi_slices f;
     if ((rc = fill_frame(light_dir, n, res, dt, sl, &f)) != VI_OK) return rc;
     if (((uintptr_t)d_slices) % 16) return fail(VI_E_INVALID_ARG, "stack buffer must be 16-byte aligned");
-    if ((double)vi_slices_bytes(n, res, dt, sl) >= 4294967296.0)
-        return fail(VI_E_UNSUPPORTED, "stack of %zu bytes exceeds 4 GiB", vi_slices_bytes(n, res, dt, sl));
+    if (!stack_size_ok(n, res, dt, sl))
+        return fail(VI_E_UNSUPPORTED, "stack of %zu bytes exceeds the layout's limit", vi_slices_bytes(n, res, dt, sl));
 
     vi::BuildParams p;
     memset(&p, 0, sizeof p);
@@ -384,8 +394,8 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
             return fail(VI_E_INVALID_ARG, "stack built for a volume of edge %d, rendering %d", sl->vol_n, vol->n);
         if (sl->tag != 0 && sl->tag != vi_tag(vol, tf))
             return fail(VI_E_INVALID_ARG, "stack was built from another volume or transfer function");
-        if ((double)vi_slices_bytes(sl->n, sl->res, sl->dtype, sl->layout) >= 4294967296.0)
-            return fail(VI_E_UNSUPPORTED, "stack exceeds 4 GiB");
+        if (!stack_size_ok(sl->n, sl->res, sl->dtype, sl->layout))
+            return fail(VI_E_UNSUPPORTED, "stack exceeds the layout's limit");
     }
 
     vi::RenderFrame& F = *out;

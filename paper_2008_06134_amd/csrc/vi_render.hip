@@ -41,14 +41,14 @@ __device__ __forceinline__ float stack_texel<VI_BF16>(const void* __restrict__ S
 
 // One quad (the 2 x 2 texels of a bilinear lookup) of the quad layout.
 template <int SDT>
-__device__ __forceinline__ float4 stack_quad(const void* __restrict__ S, uint32_t q);
+__device__ __forceinline__ float4 stack_quad(const void* __restrict__ S, size_t q);
 template <>
-__device__ __forceinline__ float4 stack_quad<VI_F32>(const void* __restrict__ S, uint32_t q)
+__device__ __forceinline__ float4 stack_quad<VI_F32>(const void* __restrict__ S, size_t q)
 {
     return ((const float4*)S)[q];
 }
 template <>
-__device__ __forceinline__ float4 stack_quad<VI_BF16>(const void* __restrict__ S, uint32_t q)
+__device__ __forceinline__ float4 stack_quad<VI_BF16>(const void* __restrict__ S, size_t q)
 {
     const uint2 u = ((const uint2*)S)[q];
     const float log2e = 1.4426950408889634f;
@@ -74,12 +74,12 @@ __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, flo
         const float4 one = make_float4(1.f, 1.f, 1.f, 1.f);
         float t0 = 1.0f;
         if (k0 >= 0) {
-            float4 q = stack_quad<SDT>(F.stack, (uint32_t)k0 * F.qlayer + qi);
+            float4 q = stack_quad<SDT>(F.stack, (size_t)k0 * F.qlayer + qi);
             q = in ? q : one;
             const float ab = fmaf(wx, q.y - q.x, q.x), cd = fmaf(wx, q.w - q.z, q.z);
             t0 = fmaf(wy, cd - ab, ab);
         }
-        float4 q = stack_quad<SDT>(F.stack, (uint32_t)k1 * F.qlayer + qi);
+        float4 q = stack_quad<SDT>(F.stack, (size_t)k1 * F.qlayer + qi);
         q = in ? q : one;
         const float ab = fmaf(wx, q.y - q.x, q.x), cd = fmaf(wx, q.w - q.z, q.z);
         const float t1 = fmaf(wy, cd - ab, ab);

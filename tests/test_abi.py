@@ -113,7 +113,8 @@ def test_build_validation_errors():
     assert _build(_Fake(), light=(0, 0, 0)) == -1
     assert _build(_Fake(), dt=vi.VI_U16) == -2
     assert _build(_Fake(), desc=False) == -1
-    assert _build(_Fake(), n=4096, res=8192) == -2   # stack >= 4 GiB
+    assert _build(_Fake(), n=4096, res=8192) == -2   # tiled stack >= 4 GiB
+    assert _build(_Fake(), n=4096, res=8192, layout=vi.VI_STACK_QUADS) == -2   # >= 2^32 quads
     f = _Fake(n=1700, dtype=vi.VI_U8)                 # volume >= 4 GiB
     assert _build(f) == -2
     f = _Fake(dtype=vi.VI_U16)
