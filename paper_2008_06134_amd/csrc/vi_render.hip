@@ -395,9 +395,12 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
             }
         }
         if (group_bits<G>(empty, gbase) == ((G == 32) ? 0xffffffffu : ((1u << G) - 1u))) {
-            // every segment of this step is empty (or past the exit): jump
+            // every segment of this step is empty (or past the exit): jump,
+            // staying on multiples of G so that the steps group segments as a
+            // march without the map would (the products then round alike and
+            // the map changes no bit of the result)
             const int jlast = G == 1 ? jl : __shfl(jl, gbase + G - 1);
-            k = max(k + G, jlast + 1);
+            k = max(k + G, ((jlast + 1) / G) * G);
             if (k >= K) break;
             continue;
         }
