@@ -67,7 +67,7 @@ def cpu_baseline(w, raw, tab, light, cam, modes, opts, stride, nthreads=0):
 # ---------------------------------------------------------------------------
 
 # stack layout of every stack the bench builds (0 tiled, 1 quads; --stack-layout)
-STACK_LAYOUT = 1
+STACK_LAYOUT = 0
 
 
 def _outputs(reqs, dev, per_size=8):
@@ -276,8 +276,8 @@ def main():
     ap.add_argument("--modes", default=None, help="comma-separated modes to time (none, shadow, shell, cone, cone5)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
-    ap.add_argument("--stack-layout", default="quads", choices=["tiled", "quads"],
-                    help="stack layout of every stack built (quads: one 4-texel load per bilinear lookup)")
+    ap.add_argument("--stack-layout", default="tiled", choices=["tiled", "quads"],
+                    help="stack layout of every stack built (quads: one 4-texel load per lookup, 4x the memory)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
