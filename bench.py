@@ -66,7 +66,7 @@ def cpu_baseline(w, raw, tab, light, cam, modes, opts, stride, nthreads=0):
 # serving: continuous batching vs sequential plain renders, Poisson arrivals
 # ---------------------------------------------------------------------------
 
-# stack layout of every stack the bench builds (0 tiled, 1 quads; --stack-layout)
+# stack layout of every stack the bench builds (0 tiled, 1 rows; --stack-layout)
 STACK_LAYOUT = 0
 
 
@@ -276,13 +276,13 @@ def main():
     ap.add_argument("--modes", default=None, help="comma-separated modes to time (none, shadow, shell, cone, cone5)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
-    ap.add_argument("--stack-layout", default="tiled", choices=["tiled", "quads"],
-                    help="stack layout of every stack built (quads: one 4-texel load per lookup, 4x the memory)")
+    ap.add_argument("--stack-layout", default="tiled", choices=["tiled", "rows"],
+                    help="stack layout of every stack built (rows: one 8-byte load per bilinear row)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     global STACK_LAYOUT
-    STACK_LAYOUT = {"tiled": 0, "quads": 1}[args.stack_layout]
+    STACK_LAYOUT = {"tiled": 0, "rows": 1}[args.stack_layout]
     if args.copy_probe:
         import torch
         a = torch.ones(args.copy_probe * 2 ** 18, dtype=torch.float32, device="cuda:0")

@@ -137,15 +137,14 @@ typedef struct {
  *     up to 8 and R4 = res rounded up to 4, texel (k, j, i) is element
  *       k*R8*R4 + ((j/4)*(R8/8) + i/8)*32 + (j%4)*8 + i%8
  *     (padding never read).  n*R8*R4 elements.
- *   VI_STACK_QUADS: every layer holds, for a, b in [-1, res-1], the quad
- *     (T(k,b,a), T(k,b,a+1), T(k,b+1,a), T(k,b+1,a+1)) -- the four texels
- *     one bilinear lookup reads -- so a lookup is one 4-element load per
- *     layer instead of four.  With QW = res+1 rounded up to 4, QH = res+1
- *     rounded up to 2 and a' = a+1, b' = b+1, quad (k, b, a) is quad number
- *       k*QW*QH + ((b'/2)*(QW/4) + a'/4)*8 + (b'%2)*4 + a'%4
- *     (four elements each; padding never read).  About 4x the memory and
- *     build writes of the tiled layout, for a quarter of the gather loads. */
-typedef enum { VI_STACK_TILED = 0, VI_STACK_QUADS = 1 } vi_stack_layout;
+ *   VI_STACK_ROWS: every layer row-major with a border of fully
+ *     transmitting texels (T = 1, optical depth 0) around the grid, so the
+ *     two texels of a bilinear row, (k, j, i) and (k, j, i+1), are adjacent
+ *     for every i in [-1, res-1] and one 8-byte load per row reads them.
+ *     With P = res+4 rounded up to 4 (row pitch) and LS = (res+2)*P, texel
+ *     (k, j, i), i and j in [-1, res], is element k*LS + (j+1)*P + (i+1);
+ *     n*LS elements (columns res+2 .. P-1 never read as texels). */
+typedef enum { VI_STACK_TILED = 0, VI_STACK_ROWS = 1 } vi_stack_layout;
 
 /* Attenuation stack descriptor, filled by vi_build_attenuation (or by
  * vi_light_frame for the geometry alone).  `data` points at the caller's
@@ -156,7 +155,7 @@ typedef enum { VI_STACK_TILED = 0, VI_STACK_QUADS = 1 } vi_stack_layout;
 typedef struct {
     void* data;
     int dtype;          /* VI_F32 or VI_BF16 */
-    int layout;         /* VI_STACK_TILED or VI_STACK_QUADS */
+    int layout;         /* VI_STACK_TILED or VI_STACK_ROWS */
     int n, res;         /* slabs, texels per side */
     double L[3];        /* unit propagation direction */
     double U[3], V[3];  /* light-plane basis */
@@ -213,7 +212,7 @@ const char* vi_last_error(void);
 int vi_default_render_opts(vi_render_opts* o);
 
 /* Bytes of a stack buffer (element 4 bytes for VI_F32, 2 for VI_BF16):
- * tiled n*R8*R4 elements, quads n*QW*QH*4 elements; 0 for invalid arguments. */
+ * tiled n*R8*R4 elements, rows n*LS elements; 0 for invalid arguments. */
 size_t vi_slices_bytes(int n_slices, int slice_res, int slice_dtype, int slice_layout);
 
 /* Bytes of a volume of edge n, dtype and layout (0 for invalid arguments). */
@@ -255,8 +254,7 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
  * float and rounded to bfloat16 per layer; each slab adds at most 64).
  * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes or a degenerate
  * light; VI_E_UNSUPPORTED for dtypes or sizes outside the limits above or a
- * tiled stack of 4 GiB or more or a quad stack of 2^32 quads or more;
- * VI_E_DEVICE if the launch fails. */
+ * stack of 4 GiB or more; VI_E_DEVICE if the launch fails. */
 int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n_slices,
                          int slice_res, int slice_dtype, int slice_layout, void* d_slices, vi_slices* out_desc,
                          vi_stream_t stream);

@@ -100,15 +100,12 @@ void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
     }
 }
 
-// Kernels index a tiled stack with 32-bit element offsets and a quad stack
-// with 32-bit quad offsets: tiled stacks stay below 4 GiB, quad stacks below
-// 2^32 quads.
-bool stack_size_ok(int n, int res, int dt, int sl)
-{
-    const double bytes = (double)vi_slices_bytes(n, res, dt, sl);
-    if (sl == VI_STACK_QUADS) return bytes / (4.0 * elem_size(dt)) < 4294967296.0;
-    return bytes < 4294967296.0;
-}
+// Kernels index stacks with 32-bit element offsets: stacks stay below 4 GiB.
+bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_bytes(n, res, dt, sl) < 4294967296.0; }
+
+// Row layout: pitch res+4 rounded up to 4 (an 8-byte read of the bfloat16
+// pair at column res-1 stays inside the row), res+2 rows per layer.
+uint32_t row_pitch(int res) { return vi::round_up((uint32_t)res + 4u, 4u); }
 
 // Eq. 8 and the light projection: geometry of the stack in double.
 int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)
@@ -117,7 +114,7 @@ int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)
     if (n < 1 || n > 4096) return fail(VI_E_INVALID_ARG, "n_slices %d outside 1..4096", n);
     if (res < 1 || res > 8192) return fail(VI_E_INVALID_ARG, "slice_res %d outside 1..8192", res);
     if (dt != VI_F32 && dt != VI_BF16) return fail(VI_E_UNSUPPORTED, "slice dtype %d not supported", dt);
-    if (sl != VI_STACK_TILED && sl != VI_STACK_QUADS) return fail(VI_E_UNSUPPORTED, "slice layout %d not supported", sl);
+    if (sl != VI_STACK_TILED && sl != VI_STACK_ROWS) return fail(VI_E_UNSUPPORTED, "slice layout %d not supported", sl);
     if (!isfinite(l[0]) || !isfinite(l[1]) || !isfinite(l[2]))
         return fail(VI_E_INVALID_ARG, "light direction is not finite");
     const double nl = sqrt(dot3(l, l));
@@ -184,9 +181,7 @@ size_t vi_slices_bytes(int n, int res, int dt, int sl)
     if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16)) return 0;
     if (sl == VI_STACK_TILED)
         return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
-    if (sl == VI_STACK_QUADS)
-        return (size_t)n * vi::round_up((uint32_t)res + 1u, 4u) * vi::round_up((uint32_t)res + 1u, 2u) * 4u *
-               elem_size(dt);
+    if (sl == VI_STACK_ROWS) return (size_t)n * ((size_t)res + 2u) * row_pitch(res) * elem_size(dt);
     return 0;
 }
 
@@ -307,8 +302,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     p.out_layout = sl;
     p.layer = vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u);
     p.row_tiles32 = vi::round_up((uint32_t)res, 8u) * 4u;
-    p.qlayer = vi::round_up((uint32_t)res + 1u, 4u) * vi::round_up((uint32_t)res + 1u, 2u);
-    p.qrow = vi::round_up((uint32_t)res + 1u, 4u) * 2u;
+    p.rpitch = row_pitch(res);
+    p.rlayer = ((uint32_t)res + 2u) * p.rpitch;
     const double N = vol->n, texel = 2.0 * f.R / res, u0 = -f.R + 0.5 * texel;
     const double d0 = f.dmin + 0.5 * f.ds, Lc = dot3(f.L, f.c);
     for (int a = 0; a < 3; ++a) {
@@ -386,7 +381,7 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     if (reads_stack) {
         if (!sl || !sl->data) return fail(VI_E_INVALID_ARG, "mode %d needs a stack", mode);
         if (sl->dtype != VI_F32 && sl->dtype != VI_BF16) return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);
-        if (sl->layout != VI_STACK_TILED && sl->layout != VI_STACK_QUADS)
+        if (sl->layout != VI_STACK_TILED && sl->layout != VI_STACK_ROWS)
             return fail(VI_E_UNSUPPORTED, "stack layout %d", sl->layout);
         if (((uintptr_t)sl->data) % 16) return fail(VI_E_INVALID_ARG, "stack buffer must be 16-byte aligned");
         if (sl->n < 1 || sl->res < 1) return fail(VI_E_INVALID_ARG, "stack descriptor has no size");
@@ -421,8 +416,8 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         F.stack_layout = sl->layout;
         F.layer = vi::round_up((uint32_t)sl->res, 8u) * vi::round_up((uint32_t)sl->res, 4u);
         F.row_tiles32 = vi::round_up((uint32_t)sl->res, 8u) * 4u;
-        F.qlayer = vi::round_up((uint32_t)sl->res + 1u, 4u) * vi::round_up((uint32_t)sl->res + 1u, 2u);
-        F.qrow = vi::round_up((uint32_t)sl->res + 1u, 4u) * 2u;
+        F.rpitch = row_pitch(sl->res);
+        F.rlayer = ((uint32_t)sl->res + 2u) * F.rpitch;
         F.Mz = sl->n / 2;
         F.Mr = sl->res / 2;
         const double span = sl->dmax - sl->dmin, sc = sl->res / (2.0 * sl->R);

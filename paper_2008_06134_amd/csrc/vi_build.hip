@@ -19,40 +19,26 @@ namespace vi {
 
 constexpr int kBuildTile = 16;
 
-// Quad layout: the value of texel column (ci, cj) -- real, or a fully
-// transmitting column of the ring just outside the grid -- goes to every
-// quad (a, b) in [-1, res-1]^2 that contains it, as component
-// (ci - a) + 2 (cj - b).
+// Row layout: a lane stores its own texel and, on the edge of the grid, the
+// fully transmitting border texels next to it (the corners by the corner
+// lanes).
 template <typename ET>
-__device__ __forceinline__ void put_quads(ET* __restrict__ out, const BuildParams& P, int k, int ci, int cj, ET v)
-{
-    const size_t base = (size_t)k * P.qlayer;
-    for (int db = 0; db < 2; ++db) {
-        const int b = cj - db;
-        if (b < -1 || b > P.res - 1) continue;
-        for (int da = 0; da < 2; ++da) {
-            const int a = ci - da;
-            if (a < -1 || a > P.res - 1) continue;
-            out[(base + quad_of(a + 1, b + 1, P.qrow)) * 4 + da + 2 * db] = v;
-        }
-    }
-}
-
-// the ring columns a lane owns: left/right of its row, above/below its
-// column, and the corner next to it
-template <typename ET>
-__device__ __forceinline__ void put_ring(ET* __restrict__ out, const BuildParams& P, int k, int i, int j, ET one)
+__device__ __forceinline__ void put_rows(ET* __restrict__ out, const BuildParams& P, int k, int i, int j, ET v,
+                                         ET one)
 {
     const int r = P.res;
-    const bool L = i == 0, Rt = i == r - 1, Bo = j == 0, To = j == r - 1;
-    if (L) put_quads(out, P, k, -1, j, one);
-    if (Rt) put_quads(out, P, k, r, j, one);
-    if (Bo) put_quads(out, P, k, i, -1, one);
-    if (To) put_quads(out, P, k, i, r, one);
-    if (L && Bo) put_quads(out, P, k, -1, -1, one);
-    if (L && To) put_quads(out, P, k, -1, r, one);
-    if (Rt && Bo) put_quads(out, P, k, r, -1, one);
-    if (Rt && To) put_quads(out, P, k, r, r, one);
+    ET* L = out + (size_t)k * P.rlayer;
+    const uint32_t row = (uint32_t)(j + 1) * P.rpitch;
+    L[row + i + 1] = v;
+    const bool lo_i = i == 0, hi_i = i == r - 1, lo_j = j == 0, hi_j = j == r - 1;
+    if (lo_i) L[row] = one;
+    if (hi_i) L[row + r + 1] = one;
+    if (lo_j) L[i + 1] = one;
+    if (hi_j) L[(uint32_t)(r + 1) * P.rpitch + i + 1] = one;
+    if (lo_i && lo_j) L[0] = one;
+    if (hi_i && lo_j) L[r + 1] = one;
+    if (lo_i && hi_j) L[(uint32_t)(r + 1) * P.rpitch] = one;
+    if (hi_i && hi_j) L[(uint32_t)(r + 1) * P.rpitch + r + 1] = one;
 }
 
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL>
@@ -117,18 +103,16 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         if (OUT_DTYPE == VI_F32) {
             // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
             T *= fast_exp2(P.e * l2);
-            if (SL == VI_STACK_QUADS) {
-                put_quads((float*)P.out, P, k, i, j, T);
-                put_ring((float*)P.out, P, k, i, j, 1.0f);
+            if (SL == VI_STACK_ROWS) {
+                put_rows((float*)P.out, P, k, i, j, T, 1.0f);
             } else {
                 ((float*)P.out)[(size_t)k * layer + col] = T;
             }
         } else {
             // sigma * ds = -e ln(1 - a), capped at 64 per slab
             tau += fminf(-P.e * ln2 * l2, 64.0f);
-            if (SL == VI_STACK_QUADS) {
-                put_quads((uint16_t*)P.out, P, k, i, j, f32_to_bf16(tau));
-                put_ring((uint16_t*)P.out, P, k, i, j, (uint16_t)0);
+            if (SL == VI_STACK_ROWS) {
+                put_rows((uint16_t*)P.out, P, k, i, j, f32_to_bf16(tau), (uint16_t)0);
             } else {
                 ((uint16_t*)P.out)[(size_t)k * layer + col] = f32_to_bf16(tau);
             }
@@ -142,12 +126,12 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
     const uint32_t tiles = (uint32_t)((p.res + kBuildTile - 1) / kBuildTile);
     dim3 grid(supertile_grid(tiles, tiles)), block(256);
     const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K;
-    const bool q = p.out_layout == VI_STACK_QUADS;
+    const bool q = p.out_layout == VI_STACK_ROWS;
     if (p.out_dtype == VI_F32) {
-        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_QUADS>), grid, block, lds, s, p);
+        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_ROWS>), grid, block, lds, s, p);
         else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_TILED>), grid, block, lds, s, p);
     } else {
-        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_QUADS>), grid, block, lds, s, p);
+        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>), grid, block, lds, s, p);
         else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_TILED>), grid, block, lds, s, p);
     }
     return hipGetLastError();

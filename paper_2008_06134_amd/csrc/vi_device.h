@@ -101,14 +101,6 @@ __device__ __forceinline__ uint32_t stack_oj(int j, uint32_t row_tiles32)
     return ((uint32_t)j >> 2) * row_tiles32 + ((uint32_t)j & 3u) * 8u;
 }
 
-// Quad stack layout: quad (a, b), a' = a + 1, b' = b + 1 in [0, res], in
-// tiles of 4 x 2 quads (one 128-byte line in float): quad number within a
-// layer = ((b'/2)*(QW/4) + a'/4)*8 + (b'%2)*4 + a'%4; `row` = (QW/4)*8.
-__device__ __forceinline__ uint32_t quad_of(int a1, int b1, uint32_t row)
-{
-    return ((uint32_t)b1 >> 1) * row + (((uint32_t)a1 >> 2) << 3) + (((uint32_t)b1 & 1u) << 2) + ((uint32_t)a1 & 3u);
-}
-
 // Empty-space test.  s_next[e] = first transfer-function entry >= e with
 // non-zero opacity (K if none), built in LDS per workgroup.  A cell is empty
 // when no entry a value in [min, max] can interpolate between -- widened by

@@ -39,9 +39,9 @@ struct BuildParams {
     void* out;
     int out_dtype;     // VI_F32 transmittance / VI_BF16 optical depth
     int n, res;
-    int out_layout;    // VI_STACK_TILED / VI_STACK_QUADS
+    int out_layout;    // VI_STACK_TILED / VI_STACK_ROWS
     uint32_t layer, row_tiles32;  // tiled: R8*R4 per layer, (R8/8)*32 per tile row
-    uint32_t qlayer, qrow;        // quads: QW*QH quads per layer, (QW/4)*8 per tile row
+    uint32_t rlayer, rpitch;      // rows: (res+2)*P elements per layer, row pitch P
     double B0[3];      // h at (i,j,k) = (0,0,0)
     double BU[3];      // d h / d i
     double BV[3];      // d h / d j
@@ -71,7 +71,7 @@ struct RenderFrame {
     int n, res;
     int stack_layout;
     uint32_t layer, row_tiles32;
-    uint32_t qlayer, qrow;
+    uint32_t rlayer, rpitch;
     int Mz, Mr;          // integer offsets of the light-grid coordinates
     double Lq[3], Lq0;   // z = Lq . p + Lq0 - Mz       (Eq. 9 index minus one)
     double Ux[3], Ux0;   // x = Ux . p + Ux0 - Mr       (Eq. 10 texel column)

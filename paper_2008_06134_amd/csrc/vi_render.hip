@@ -39,21 +39,28 @@ __device__ __forceinline__ float stack_texel<VI_BF16>(const void* __restrict__ S
     return fast_exp2(-log2e * bf16_to_f32(((const uint16_t*)S)[idx]));
 }
 
-// One quad (the 2 x 2 texels of a bilinear lookup) of the quad layout.
+// Row layout: the two texels (i, i+1) of one bilinear row, element e and
+// e+1, with one 8-byte load (4-byte aligned for float; for bfloat16 the
+// aligned 4-element window that holds both).
+typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
 template <int SDT>
-__device__ __forceinline__ float4 stack_quad(const void* __restrict__ S, size_t q);
+__device__ __forceinline__ float2 stack_pair(const void* __restrict__ S, uint32_t e);
 template <>
-__device__ __forceinline__ float4 stack_quad<VI_F32>(const void* __restrict__ S, size_t q)
+__device__ __forceinline__ float2 stack_pair<VI_F32>(const void* __restrict__ S, uint32_t e)
 {
-    return ((const float4*)S)[q];
+    const f32x2_a4 v = *(const f32x2_a4*)((const float*)S + e);
+    return make_float2(v.x, v.y);
 }
 template <>
-__device__ __forceinline__ float4 stack_quad<VI_BF16>(const void* __restrict__ S, size_t q)
+__device__ __forceinline__ float2 stack_pair<VI_BF16>(const void* __restrict__ S, uint32_t e)
 {
-    const uint2 u = ((const uint2*)S)[q];
+    const u32x2_a4 w = *(const u32x2_a4*)((const uint16_t*)S + (e & ~1u));
+    const uint32_t lo = (e & 1u) ? (w.x >> 16) : (w.x & 0xffffu);
+    const uint32_t hi = (e & 1u) ? (w.y & 0xffffu) : (w.x >> 16);
     const float log2e = 1.4426950408889634f;
-    return make_float4(fast_exp2(-log2e * __uint_as_float(u.x << 16)), fast_exp2(-log2e * __uint_as_float(u.x & 0xffff0000u)),
-                       fast_exp2(-log2e * __uint_as_float(u.y << 16)), fast_exp2(-log2e * __uint_as_float(u.y & 0xffff0000u)));
+    return make_float2(fast_exp2(-log2e * __uint_as_float(lo << 16)), fast_exp2(-log2e * __uint_as_float(hi << 16)));
 }
 
 // Transmittance at light-grid offset coordinates (z, x, y): depth between
@@ -62,26 +69,28 @@ __device__ __forceinline__ float4 stack_quad<VI_BF16>(const void* __restrict__ S
 template <int SDT, int SL>
 __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, float x, float y)
 {
-    if (SL == VI_STACK_QUADS) {
+    if (SL == VI_STACK_ROWS) {
         z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
         const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
         const float wz = z - fz, wx = x - fx, wy = y - fy;
         const int k0 = (int)fz + F.Mz;
         const int k1 = min(k0 + 1, F.n - 1);
         const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;
+        // footprints reaching past the border read 1 everywhere
         const bool in = a >= -1 && a <= F.res - 1 && b >= -1 && b <= F.res - 1;
-        const uint32_t qi = quad_of(clampi(a, -1, F.res - 1) + 1, clampi(b, -1, F.res - 1) + 1, F.qrow);
-        const float4 one = make_float4(1.f, 1.f, 1.f, 1.f);
+        const uint32_t e = (uint32_t)(clampi(b, -1, F.res - 1) + 1) * F.rpitch + (uint32_t)(clampi(a, -1, F.res - 1) + 1);
         float t0 = 1.0f;
         if (k0 >= 0) {
-            float4 q = stack_quad<SDT>(F.stack, (size_t)k0 * F.qlayer + qi);
-            q = in ? q : one;
-            const float ab = fmaf(wx, q.y - q.x, q.x), cd = fmaf(wx, q.w - q.z, q.z);
+            const uint32_t base = (uint32_t)k0 * F.rlayer + e;
+            float2 r0 = stack_pair<SDT>(F.stack, base), r1 = stack_pair<SDT>(F.stack, base + F.rpitch);
+            if (!in) r0 = r1 = make_float2(1.0f, 1.0f);
+            const float ab = fmaf(wx, r0.y - r0.x, r0.x), cd = fmaf(wx, r1.y - r1.x, r1.x);
             t0 = fmaf(wy, cd - ab, ab);
         }
-        float4 q = stack_quad<SDT>(F.stack, (size_t)k1 * F.qlayer + qi);
-        q = in ? q : one;
-        const float ab = fmaf(wx, q.y - q.x, q.x), cd = fmaf(wx, q.w - q.z, q.z);
+        const uint32_t base = (uint32_t)k1 * F.rlayer + e;
+        float2 r0 = stack_pair<SDT>(F.stack, base), r1 = stack_pair<SDT>(F.stack, base + F.rpitch);
+        if (!in) r0 = r1 = make_float2(1.0f, 1.0f);
+        const float ab = fmaf(wx, r0.y - r0.x, r0.x), cd = fmaf(wx, r1.y - r1.x, r1.x);
         const float t1 = fmaf(wy, cd - ab, ab);
         return fmaf(wz, t1 - t0, t0);
     }
@@ -433,7 +442,18 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
 // lane -> pixel mapping: kG lanes per ray; a wave covers WX x WY pixels, a
 // workgroup 2 x 2 waves = BX x BY pixels.
 // --------------------------------------------------------------------------
-constexpr int kG = 4;
+// optional lower bound on resident waves per SIMD for the render kernels
+// (caps their registers)
+#ifdef VI_RENDER_WAVES
+#define VI_RENDER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(VI_RENDER_WAVES)))
+#else
+#define VI_RENDER_OCCUPANCY
+#endif
+#ifndef VI_RAY_LANES
+#define VI_RAY_LANES 4
+#endif
+constexpr int kG = VI_RAY_LANES;  // lanes per ray: 1, 2, 4, 8 or 16
+static_assert(kG == 1 || kG == 2 || kG == 4 || kG == 8 || kG == 16, "lanes per ray");
 constexpr int kWX = (64 / kG) >= 32 ? 8 : 4, kWY = (64 / kG) / kWX;
 constexpr int kBX = 2 * kWX, kBY = 2 * kWY;
 
@@ -465,7 +485,7 @@ __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* 
 // single-frame kernel
 // --------------------------------------------------------------------------
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
-__global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
+__global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_kernel(RenderFrame F)
 {
     extern __shared__ float4 s_tf[];  // K entries, then K next-opaque indices
     int* s_next = (int*)(s_tf + F.K);
@@ -491,7 +511,7 @@ __global__ __launch_bounds__(256) void render_kernel(RenderFrame F)
 constexpr uint32_t kSubX = 16 / kBX, kSubY = 16 / kBY, kSub = kSubX * kSubY;
 
 template <typename VT, int LAYOUT, int SDT, int SL>
-__global__ __launch_bounds__(256) void render_batch_kernel(const RenderFrame* __restrict__ frames,
+__global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_batch_kernel(const RenderFrame* __restrict__ frames,
                                                            const uint32_t* __restrict__ tiles, uint32_t ntiles)
 {
     extern __shared__ float4 s_tf[];
@@ -530,9 +550,9 @@ static hipError_t launch_batch_l(int sdt, int sl, const RenderFrame* f, const ui
                                  hipStream_t s)
 {
     if (sdt == VI_BF16)
-        return sl == VI_STACK_QUADS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_QUADS>(f, t, n, K, s)
+        return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(f, t, n, K, s)
                                     : launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(f, t, n, K, s);
-    return sl == VI_STACK_QUADS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_QUADS>(f, t, n, K, s)
+    return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(f, t, n, K, s)
                                 : launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_TILED>(f, t, n, K, s);
 }
 
@@ -583,10 +603,10 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 template <typename VT, int LAYOUT>
 static hipError_t launch_sdt(const RenderFrame& f, hipStream_t s)
 {
-    const bool q = f.stack_layout == VI_STACK_QUADS;
+    const bool q = f.stack_layout == VI_STACK_ROWS;
     if (f.stack_dtype == VI_BF16)
-        return q ? launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_QUADS>(f, s) : launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(f, s);
-    return q ? launch_mode<VT, LAYOUT, VI_F32, VI_STACK_QUADS>(f, s) : launch_mode<VT, LAYOUT, VI_F32, VI_STACK_TILED>(f, s);
+        return q ? launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(f, s) : launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(f, s);
+    return q ? launch_mode<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(f, s) : launch_mode<VT, LAYOUT, VI_F32, VI_STACK_TILED>(f, s);
 }
 
 template <typename VT>

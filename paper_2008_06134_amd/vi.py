@@ -30,7 +30,7 @@ class VIError(RuntimeError):
 
 
 VI_LAYOUT_LINEAR, VI_LAYOUT_BRICK4 = 0, 1
-VI_STACK_TILED, VI_STACK_QUADS = 0, 1
+VI_STACK_TILED, VI_STACK_ROWS = 0, 1
 
 
 class Volume_t(C.Structure):
@@ -223,12 +223,17 @@ class TF:
         return TF(torch.from_numpy(tab).to(device=device, dtype=torch.float32))
 
 
+def row_pitch(res: int) -> int:
+    """Row pitch of the row layout: res + 4 rounded up to 4."""
+    return (res + 4 + 3) // 4 * 4
+
+
 @dataclass
 class Slices:
     """An attenuation stack: the device buffer and its descriptor.  Tiled:
-    8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Quads:
-    n x QH/2 x QW/4 x 2 x 4 x 4 (quad rows b' = b+1, columns a' = a+1, and
-    the four texels of each quad)."""
+    8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Rows:
+    n x (res+2) x P, texel (k, j, i) at [k, j+1, i+1] with a border of fully
+    transmitting texels around the res x res grid."""
     data: torch.Tensor | None
     s: Slices_t
 
@@ -236,17 +241,14 @@ class Slices:
         """The stack as an n x res x res tensor (a device view/copy, for inspection)."""
         n, r = self.s.n, self.s.res
         t = self.data
-        if self.s.layout == VI_STACK_QUADS:
-            q = t.permute(0, 1, 3, 2, 4, 5).reshape(n, t.shape[1] * 2, t.shape[2] * 4, 4)
-            return q[:, 1:r + 1, 1:r + 1, 0]
+        if self.s.layout == VI_STACK_ROWS:
+            return t[:, 1:r + 1, 1:r + 1]
         return t.permute(0, 1, 3, 2, 4).reshape(n, t.shape[1] * 4, t.shape[2] * 8)[:, :r, :r]
 
-    def quads(self) -> torch.Tensor:
-        """Quad layout only: n x (res+1) x (res+1) x 4, quad (b+1, a+1) for a, b in [-1, res-1]."""
-        n, r = self.s.n, self.s.res
-        t = self.data
-        q = t.permute(0, 1, 3, 2, 4, 5).reshape(n, t.shape[1] * 2, t.shape[2] * 4, 4)
-        return q[:, :r + 1, :r + 1]
+    def padded(self) -> torch.Tensor:
+        """Row layout only: n x (res+2) x (res+2), the grid with its border."""
+        r = self.s.res
+        return self.data[:, :, :r + 2]
 
     @property
     def n(self):
@@ -315,9 +317,8 @@ def slices_bytes(n: int, res: int, dtype: int = VI_F32, layout: int = VI_STACK_T
 def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda", layout: int = VI_STACK_TILED) -> torch.Tensor:
     """An uninitialised device buffer in a stack layout (shapes as in Slices)."""
     tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
-    if layout == VI_STACK_QUADS:
-        qw, qh = (res + 1 + 3) // 4 * 4, (res + 1 + 1) // 2 * 2
-        return torch.empty((n, qh // 2, qw // 4, 2, 4, 4), dtype=tdt, device=device)
+    if layout == VI_STACK_ROWS:
+        return torch.empty((n, res + 2, row_pitch(res)), dtype=tdt, device=device)
     r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
     return torch.empty((n, r4 // 4, r8 // 8, 4, 8), dtype=tdt, device=device)
 

@@ -114,7 +114,7 @@ def test_build_validation_errors():
     assert _build(_Fake(), dt=vi.VI_U16) == -2
     assert _build(_Fake(), desc=False) == -1
     assert _build(_Fake(), n=4096, res=8192) == -2   # tiled stack >= 4 GiB
-    assert _build(_Fake(), n=4096, res=8192, layout=vi.VI_STACK_QUADS) == -2   # >= 2^32 quads
+    assert _build(_Fake(), n=4096, res=8192, layout=vi.VI_STACK_ROWS) == -2
     f = _Fake(n=1700, dtype=vi.VI_U8)                 # volume >= 4 GiB
     assert _build(f) == -2
     f = _Fake(dtype=vi.VI_U16)
@@ -216,9 +216,9 @@ def test_volume_bytes_and_brick_validation():
     assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -2
     # stack buffers are padded to whole 8 x 4 tiles
     assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4
-    # quads: (res+1 rounded up to 4) x (res+1 rounded up to 2) quads of 4 texels
-    assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_QUADS) == 3 * 12 * 12 * 4 * 4
-    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_QUADS) == 2 * 1028 * 1026 * 4 * 2
+    # rows: res+2 rows of pitch res+4 rounded up to 4
+    assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_ROWS) == 3 * 12 * 16 * 4
+    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_ROWS) == 2 * 1026 * 1028 * 2
     assert vi.slices_bytes(2, 8, vi.VI_F32, 5) == 0
 
 

@@ -22,8 +22,8 @@ TOL_IMG = 1e-4      # per RGBA channel, FP32 path
 TOL_STACK = 2e-5    # transmittance, FP32 product over <= 512 slabs
 
 DEV = "cuda"
-LAYOUTS = (vi.VI_STACK_TILED, vi.VI_STACK_QUADS)
-LNAME = {vi.VI_STACK_TILED: "tiled", vi.VI_STACK_QUADS: "quads"}
+LAYOUTS = (vi.VI_STACK_TILED, vi.VI_STACK_ROWS)
+LNAME = {vi.VI_STACK_TILED: "tiled", vi.VI_STACK_ROWS: "rows"}
 
 
 def _mode(m):
@@ -330,30 +330,27 @@ def test_stack_is_camera_independent_and_deterministic():
 
 @pytest.mark.parametrize("res", [1, 6, 19, 64])
 @pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
-def test_quad_layout_matches_its_definition(res, dtype):
-    """Quad (k, b, a) holds T(k,b,a), T(k,b,a+1), T(k,b+1,a), T(k,b+1,a+1) for
-    a, b in [-1, res-1], with the texels outside the grid fully transmitting
-    (optical depth 0); compared bit for bit with the tiled stack."""
+def test_row_layout_matches_its_definition(res, dtype):
+    """Row layout: the grid row-major with a one-texel border that transmits
+    fully (T = 1, optical depth 0); interior bit for bit equal to the tiled stack."""
     raw = W.sphere_u8(30, radius=10, density=200, noise=30, seed=res)
     vol, tf = gpu_inputs(raw, W.tf_ramp())
     light, n = [0.3, -0.5, 0.8], 11
     t = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_TILED)
-    q = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_QUADS)
+    r = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_ROWS)
     torch.cuda.synchronize()
     D = t.dense()
-    ring = torch.ones(()) if dtype == vi.VI_F32 else torch.zeros(())
-    P = torch.full((n, res + 2, res + 2), float(ring), dtype=D.dtype, device=DEV)   # padded by one texel
-    P[:, 1:res + 1, 1:res + 1] = D
-    Q = q.quads()
-    assert Q.shape == (n, res + 1, res + 1, 4)
-    for c, (da, db) in enumerate([(0, 0), (1, 0), (0, 1), (1, 1)]):
-        assert torch.equal(Q[..., c], P[:, db:db + res + 1, da:da + res + 1])
-    assert torch.equal(q.dense(), D)
+    ring = 1.0 if dtype == vi.VI_F32 else 0.0
+    want = torch.full((n, res + 2, res + 2), ring, dtype=D.dtype, device=DEV)
+    want[:, 1:res + 1, 1:res + 1] = D
+    assert r.data.shape == (n, res + 2, vi.row_pitch(res))
+    assert torch.equal(r.padded(), want)
+    assert torch.equal(r.dense(), D)
 
 
 @pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
 @pytest.mark.parametrize("mode", ["shadow", "shell", "cone", "cone5"])
-def test_quad_layout_gives_bitwise_identical_images(dtype, mode):
+def test_row_layout_gives_bitwise_identical_images(dtype, mode):
     raw = W.ct_phantom_u16(56, seed=6, vessels=True)
     vol, tf = gpu_inputs(raw, W.tf_ct())
     light = [-0.4, 0.7, 0.6]
