@@ -103,9 +103,12 @@ void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
 // Kernels index stacks with 32-bit element offsets: stacks stay below 4 GiB.
 bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_bytes(n, res, dt, sl) < 4294967296.0; }
 
-// Row layout: pitch res+4 rounded up to 4 (an 8-byte read of the bfloat16
-// pair at column res-1 stays inside the row), res+2 rows per layer.
-uint32_t row_pitch(int res) { return vi::round_up((uint32_t)res + 4u, 4u); }
+// Row layout: texel 0 of a row at element E = 128 / element size (a line
+// boundary), pitch E + res + 4 rounded up to E (an 8-byte read of the
+// bfloat16 pair at the last column stays inside the row), res+2 rows per
+// layer.
+uint32_t row_origin(int dt) { return 128u / (uint32_t)elem_size(dt); }
+uint32_t row_pitch(int res, int dt) { return vi::round_up(row_origin(dt) + (uint32_t)res + 4u, row_origin(dt)); }
 
 // Eq. 8 and the light projection: geometry of the stack in double.
 int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)
@@ -181,7 +184,7 @@ size_t vi_slices_bytes(int n, int res, int dt, int sl)
     if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16)) return 0;
     if (sl == VI_STACK_TILED)
         return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
-    if (sl == VI_STACK_ROWS) return (size_t)n * ((size_t)res + 2u) * row_pitch(res) * elem_size(dt);
+    if (sl == VI_STACK_ROWS) return (size_t)n * ((size_t)res + 2u) * row_pitch(res, dt) * elem_size(dt);
     return 0;
 }
 
@@ -302,7 +305,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     p.out_layout = sl;
     p.layer = vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u);
     p.row_tiles32 = vi::round_up((uint32_t)res, 8u) * 4u;
-    p.rpitch = row_pitch(res);
+    p.rpitch = row_pitch(res, dt);
+    p.rorg = row_origin(dt);
     p.rlayer = ((uint32_t)res + 2u) * p.rpitch;
     const double N = vol->n, texel = 2.0 * f.R / res, u0 = -f.R + 0.5 * texel;
     const double d0 = f.dmin + 0.5 * f.ds, Lc = dot3(f.L, f.c);
@@ -416,7 +420,8 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         F.stack_layout = sl->layout;
         F.layer = vi::round_up((uint32_t)sl->res, 8u) * vi::round_up((uint32_t)sl->res, 4u);
         F.row_tiles32 = vi::round_up((uint32_t)sl->res, 8u) * 4u;
-        F.rpitch = row_pitch(sl->res);
+        F.rpitch = row_pitch(sl->res, sl->dtype);
+        F.rorg = row_origin(sl->dtype);
         F.rlayer = ((uint32_t)sl->res + 2u) * F.rpitch;
         F.Mz = sl->n / 2;
         F.Mr = sl->res / 2;

@@ -9,15 +9,21 @@
 // the volume is read through the caches and the stack is written once,
 // coalesced along the texel row.
 //
-// Workgroup = 16 x 16 texels (4 waves of 16 x 4): at every slab a wave
-// stores two whole 8 x 4 texel tiles of the stack, i.e. two full 128-byte
-// lines.  The alpha column of the transfer function sits in LDS.
+// Workgroup = 16 x 16 texels (4 waves of 16 x 4) for the tiled stack: at
+// every slab a wave stores two whole 8 x 4 texel tiles, i.e. two full
+// 128-byte lines; 64 x 4 texels (a wave per 64-texel row run) for the row
+// stack.  The alpha column of the transfer function sits in LDS.
 #include "vi_device.h"
 #include "vi_internal.h"
 
 namespace vi {
 
-constexpr int kBuildTile = 16;
+// Block of texel columns per workgroup: 16 x 16 (waves of 16 x 4) for the
+// tiled layout, whose 8 x 4 tiles a wave then writes whole; 64 x 4 (waves of
+// one 64-texel row segment) for the row layout, so every slab store of a
+// wave is one contiguous 256-byte run.
+template <int SL> struct BuildBlock { static constexpr int X = 16, Y = 16; };
+template <> struct BuildBlock<VI_STACK_ROWS> { static constexpr int X = 64, Y = 4; };
 
 // Row layout: a lane stores its own texel and, on the edge of the grid, the
 // fully transmitting border texels next to it (the corners by the corner
@@ -27,18 +33,19 @@ __device__ __forceinline__ void put_rows(ET* __restrict__ out, const BuildParams
                                          ET one)
 {
     const int r = P.res;
-    ET* L = out + (size_t)k * P.rlayer;
-    const uint32_t row = (uint32_t)(j + 1) * P.rpitch;
-    L[row + i + 1] = v;
+    // texel (i, j) of this layer at row j+1, column rorg+i
+    ET* L = out + (size_t)k * P.rlayer + P.rorg;
+    const uint32_t row = (uint32_t)(j + 1) * P.rpitch, last = (uint32_t)(r + 1) * P.rpitch;
+    L[row + i] = v;
     const bool lo_i = i == 0, hi_i = i == r - 1, lo_j = j == 0, hi_j = j == r - 1;
-    if (lo_i) L[row] = one;
-    if (hi_i) L[row + r + 1] = one;
-    if (lo_j) L[i + 1] = one;
-    if (hi_j) L[(uint32_t)(r + 1) * P.rpitch + i + 1] = one;
-    if (lo_i && lo_j) L[0] = one;
-    if (hi_i && lo_j) L[r + 1] = one;
-    if (lo_i && hi_j) L[(uint32_t)(r + 1) * P.rpitch] = one;
-    if (hi_i && hi_j) L[(uint32_t)(r + 1) * P.rpitch + r + 1] = one;
+    if (lo_i) L[row - 1] = one;
+    if (hi_i) L[row + r] = one;
+    if (lo_j) L[i] = one;
+    if (hi_j) L[last + i] = one;
+    if (lo_i && lo_j) L[-1] = one;
+    if (hi_i && lo_j) L[r] = one;
+    if (lo_i && hi_j) L[last - 1] = one;
+    if (hi_i && hi_j) L[last + r] = one;
 }
 
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL>
@@ -50,12 +57,13 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     if (P.occ.mm) build_next_opaque(s_next, P.tf, P.K);
     __syncthreads();
 
-    const uint32_t tiles = (P.res + kBuildTile - 1) / kBuildTile;
+    constexpr int BX = BuildBlock<SL>::X, BY = BuildBlock<SL>::Y;
+    const uint32_t tiles_x = (P.res + BX - 1) / BX, tiles_y = (P.res + BY - 1) / BY;
     uint32_t tx, ty;
-    if (!supertile_of(blockIdx.x, tiles, tiles, &tx, &ty)) return;
+    if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = (int)tx * kBuildTile + (lane & 15);
-    const int j = (int)ty * kBuildTile + wave * 4 + (lane >> 4);
+    const int i = (int)tx * BX + (BX == 64 ? lane : (lane & 15));
+    const int j = (int)ty * BY + (BX == 64 ? wave : wave * 4 + (lane >> 4));
     if (i >= P.res || j >= P.res) return;
 
     // column base (slab 0 midpoint) in offset-voxel coordinates, in double
@@ -123,15 +131,16 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 template <typename VT, int LAYOUT>
 static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
 {
-    const uint32_t tiles = (uint32_t)((p.res + kBuildTile - 1) / kBuildTile);
-    dim3 grid(supertile_grid(tiles, tiles)), block(256);
+    const bool rows = p.out_layout == VI_STACK_ROWS;
+    const uint32_t bx = rows ? BuildBlock<VI_STACK_ROWS>::X : BuildBlock<VI_STACK_TILED>::X;
+    const uint32_t by = rows ? BuildBlock<VI_STACK_ROWS>::Y : BuildBlock<VI_STACK_TILED>::Y;
+    dim3 grid(supertile_grid(((uint32_t)p.res + bx - 1) / bx, ((uint32_t)p.res + by - 1) / by)), block(256);
     const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K;
-    const bool q = p.out_layout == VI_STACK_ROWS;
     if (p.out_dtype == VI_F32) {
-        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_ROWS>), grid, block, lds, s, p);
+        if (rows) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_ROWS>), grid, block, lds, s, p);
         else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_TILED>), grid, block, lds, s, p);
     } else {
-        if (q) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>), grid, block, lds, s, p);
+        if (rows) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>), grid, block, lds, s, p);
         else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_TILED>), grid, block, lds, s, p);
     }
     return hipGetLastError();

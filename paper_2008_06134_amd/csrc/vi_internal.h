@@ -41,7 +41,7 @@ struct BuildParams {
     int n, res;
     int out_layout;    // VI_STACK_TILED / VI_STACK_ROWS
     uint32_t layer, row_tiles32;  // tiled: R8*R4 per layer, (R8/8)*32 per tile row
-    uint32_t rlayer, rpitch;      // rows: (res+2)*P elements per layer, row pitch P
+    uint32_t rlayer, rpitch, rorg;  // rows: (res+2)*P elements per layer, pitch P, texel 0 at column rorg
     double B0[3];      // h at (i,j,k) = (0,0,0)
     double BU[3];      // d h / d i
     double BV[3];      // d h / d j
@@ -71,7 +71,7 @@ struct RenderFrame {
     int n, res;
     int stack_layout;
     uint32_t layer, row_tiles32;
-    uint32_t rlayer, rpitch;
+    uint32_t rlayer, rpitch, rorg;
     int Mz, Mr;          // integer offsets of the light-grid coordinates
     double Lq[3], Lq0;   // z = Lq . p + Lq0 - Mz       (Eq. 9 index minus one)
     double Ux[3], Ux0;   // x = Ux . p + Ux0 - Mr       (Eq. 10 texel column)

@@ -78,7 +78,7 @@ __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, flo
         const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;
         // footprints reaching past the border read 1 everywhere
         const bool in = a >= -1 && a <= F.res - 1 && b >= -1 && b <= F.res - 1;
-        const uint32_t e = (uint32_t)(clampi(b, -1, F.res - 1) + 1) * F.rpitch + (uint32_t)(clampi(a, -1, F.res - 1) + 1);
+        const uint32_t e = (uint32_t)(clampi(b, -1, F.res - 1) + 1) * F.rpitch + F.rorg + (uint32_t)clampi(a, -1, F.res - 1);
         float t0 = 1.0f;
         if (k0 >= 0) {
             const uint32_t base = (uint32_t)k0 * F.rlayer + e;

@@ -223,17 +223,23 @@ class TF:
         return TF(torch.from_numpy(tab).to(device=device, dtype=torch.float32))
 
 
-def row_pitch(res: int) -> int:
-    """Row pitch of the row layout: res + 4 rounded up to 4."""
-    return (res + 4 + 3) // 4 * 4
+def row_origin(dtype: int) -> int:
+    """Column of texel 0 in the row layout: elements per 128-byte line."""
+    return 128 // (4 if dtype == VI_F32 else 2)
+
+
+def row_pitch(res: int, dtype: int = VI_F32) -> int:
+    """Row pitch of the row layout: origin + res + 4 rounded up to the origin."""
+    e = row_origin(dtype)
+    return (e + res + 4 + e - 1) // e * e
 
 
 @dataclass
 class Slices:
     """An attenuation stack: the device buffer and its descriptor.  Tiled:
     8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Rows:
-    n x (res+2) x P, texel (k, j, i) at [k, j+1, i+1] with a border of fully
-    transmitting texels around the res x res grid."""
+    n x (res+2) x P, texel (k, j, i) at [k, j+1, E+i] (E = row_origin) with a
+    border of fully transmitting texels around the res x res grid."""
     data: torch.Tensor | None
     s: Slices_t
 
@@ -242,13 +248,14 @@ class Slices:
         n, r = self.s.n, self.s.res
         t = self.data
         if self.s.layout == VI_STACK_ROWS:
-            return t[:, 1:r + 1, 1:r + 1]
+            e = row_origin(self.s.dtype)
+            return t[:, 1:r + 1, e:e + r]
         return t.permute(0, 1, 3, 2, 4).reshape(n, t.shape[1] * 4, t.shape[2] * 8)[:, :r, :r]
 
     def padded(self) -> torch.Tensor:
         """Row layout only: n x (res+2) x (res+2), the grid with its border."""
-        r = self.s.res
-        return self.data[:, :, :r + 2]
+        r, e = self.s.res, row_origin(self.s.dtype)
+        return self.data[:, :, e - 1:e + r + 1]
 
     @property
     def n(self):
@@ -318,7 +325,7 @@ def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda", layout: i
     """An uninitialised device buffer in a stack layout (shapes as in Slices)."""
     tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
     if layout == VI_STACK_ROWS:
-        return torch.empty((n, res + 2, row_pitch(res)), dtype=tdt, device=device)
+        return torch.empty((n, res + 2, row_pitch(res, dtype)), dtype=tdt, device=device)
     r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
     return torch.empty((n, r4 // 4, r8 // 8, 4, 8), dtype=tdt, device=device)
 

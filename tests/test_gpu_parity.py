@@ -343,7 +343,7 @@ def test_row_layout_matches_its_definition(res, dtype):
     ring = 1.0 if dtype == vi.VI_F32 else 0.0
     want = torch.full((n, res + 2, res + 2), ring, dtype=D.dtype, device=DEV)
     want[:, 1:res + 1, 1:res + 1] = D
-    assert r.data.shape == (n, res + 2, vi.row_pitch(res))
+    assert r.data.shape == (n, res + 2, vi.row_pitch(res, dtype))
     assert torch.equal(r.padded(), want)
     assert torch.equal(r.dense(), D)
 
