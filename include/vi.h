@@ -141,11 +141,9 @@ typedef struct {
  *     transmitting texels (T = 1, optical depth 0) around the grid, so the
  *     two texels of a bilinear row, (k, j, i) and (k, j, i+1), are adjacent
  *     for every i in [-1, res-1] and one 8-byte load per row reads them.
- *     With E = 128 / element size (elements per 128-byte line), row pitch
- *     P = E + res + 4 rounded up to E and LS = (res+2)*P, texel (k, j, i),
- *     i and j in [-1, res], is element k*LS + (j+1)*P + E + i: every row's
- *     texel 0 starts a 128-byte line.  n*LS elements; elements outside the
- *     grid and its border are never used. */
+ *     With row pitch P = res+4 rounded up to 4 and LS = (res+2)*P, texel
+ *     (k, j, i), i and j in [-1, res], is element k*LS + (j+1)*P + (i+1);
+ *     n*LS elements (columns res+2 .. P-1 are never used). */
 typedef enum { VI_STACK_TILED = 0, VI_STACK_ROWS = 1 } vi_stack_layout;
 
 /* Attenuation stack descriptor, filled by vi_build_attenuation (or by

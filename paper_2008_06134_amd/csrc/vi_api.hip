@@ -103,12 +103,13 @@ void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
 // Kernels index stacks with 32-bit element offsets: stacks stay below 4 GiB.
 bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_bytes(n, res, dt, sl) < 4294967296.0; }
 
-// Row layout: texel 0 of a row at element E = 128 / element size (a line
-// boundary), pitch E + res + 4 rounded up to E (an 8-byte read of the
-// bfloat16 pair at the last column stays inside the row), res+2 rows per
-// layer.
-uint32_t row_origin(int dt) { return 128u / (uint32_t)elem_size(dt); }
-uint32_t row_pitch(int res, int dt) { return vi::round_up(row_origin(dt) + (uint32_t)res + 4u, row_origin(dt)); }
+// Row layout: texel 0 of a row at element 1, pitch res + 4 rounded up to 4
+// (an 8-byte read of the bfloat16 pair at the last column stays inside the
+// row), res+2 rows per layer.  (Rows aligned to 128-byte lines were measured
+// slower: a line-multiple pitch maps the rows of a footprint onto fewer
+// cache sets.)
+uint32_t row_origin(int) { return 1u; }
+uint32_t row_pitch(int res, int) { return vi::round_up((uint32_t)res + 4u, 4u); }
 
 // Eq. 8 and the light projection: geometry of the stack in double.
 int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)

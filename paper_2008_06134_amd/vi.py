@@ -223,23 +223,22 @@ class TF:
         return TF(torch.from_numpy(tab).to(device=device, dtype=torch.float32))
 
 
-def row_origin(dtype: int) -> int:
-    """Column of texel 0 in the row layout: elements per 128-byte line."""
-    return 128 // (4 if dtype == VI_F32 else 2)
+def row_origin(dtype: int = VI_F32) -> int:
+    """Column of texel 0 in the row layout (the border texel -1 precedes it)."""
+    return 1
 
 
 def row_pitch(res: int, dtype: int = VI_F32) -> int:
-    """Row pitch of the row layout: origin + res + 4 rounded up to the origin."""
-    e = row_origin(dtype)
-    return (e + res + 4 + e - 1) // e * e
+    """Row pitch of the row layout: res + 4 rounded up to 4."""
+    return (res + 4 + 3) // 4 * 4
 
 
 @dataclass
 class Slices:
     """An attenuation stack: the device buffer and its descriptor.  Tiled:
     8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Rows:
-    n x (res+2) x P, texel (k, j, i) at [k, j+1, E+i] (E = row_origin) with a
-    border of fully transmitting texels around the res x res grid."""
+    n x (res+2) x P, texel (k, j, i) at [k, j+1, i+1] with a border of fully
+    transmitting texels around the res x res grid."""
     data: torch.Tensor | None
     s: Slices_t
 

@@ -216,10 +216,9 @@ def test_volume_bytes_and_brick_validation():
     assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -2
     # stack buffers are padded to whole 8 x 4 tiles
     assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4
-    # rows: res+2 rows of pitch E+res+4 rounded up to E (E = elements per 128-byte line)
-    assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_ROWS) == 3 * 12 * 64 * 4
-    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_ROWS) == 2 * 1026 * 1152 * 2
-    assert vi.slices_bytes(2, 1024, vi.VI_F32, vi.VI_STACK_ROWS) == 2 * 1026 * 1088 * 4
+    # rows: res+2 rows of pitch res+4 rounded up to 4
+    assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_ROWS) == 3 * 12 * 16 * 4
+    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_ROWS) == 2 * 1026 * 1028 * 2
     assert vi.slices_bytes(2, 8, vi.VI_F32, 5) == 0
 
 
