@@ -67,7 +67,7 @@ def cpu_baseline(w, raw, tab, light, cam, modes, opts, stride, nthreads=0):
 # ---------------------------------------------------------------------------
 
 # stack layout of every stack the bench builds (0 tiled, 1 rows; --stack-layout)
-STACK_LAYOUT = 0
+STACK_LAYOUT = 1
 
 
 def _outputs(reqs, dev, per_size=8):
@@ -276,7 +276,7 @@ def main():
     ap.add_argument("--modes", default=None, help="comma-separated modes to time (none, shadow, shell, cone, cone5)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
-    ap.add_argument("--stack-layout", default="tiled", choices=["tiled", "rows"],
+    ap.add_argument("--stack-layout", default="rows", choices=["tiled", "rows"],
                     help="stack layout of every stack built (rows: one 8-byte load per bilinear row)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")

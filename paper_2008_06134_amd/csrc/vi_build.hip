@@ -28,6 +28,18 @@ template <> struct BuildBlock<VI_STACK_ROWS> { static constexpr int X = 64, Y = 
 // Row layout: a lane stores its own texel and, on the edge of the grid, the
 // fully transmitting border texels next to it (the corners by the corner
 // lanes).
+// stack stores: streamed past the caches (the render reads the stack long
+// after the build has moved on)
+template <typename ET>
+__device__ __forceinline__ void put(ET* p, ET v)
+{
+#ifdef VI_BUILD_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 template <typename ET>
 __device__ __forceinline__ void put_rows(ET* __restrict__ out, const BuildParams& P, int k, int i, int j, ET v,
                                          ET one)
@@ -36,7 +48,7 @@ __device__ __forceinline__ void put_rows(ET* __restrict__ out, const BuildParams
     // texel (i, j) of this layer at row j+1, column rorg+i
     ET* L = out + (size_t)k * P.rlayer + P.rorg;
     const uint32_t row = (uint32_t)(j + 1) * P.rpitch, last = (uint32_t)(r + 1) * P.rpitch;
-    L[row + i] = v;
+    put(L + row + i, v);
     const bool lo_i = i == 0, hi_i = i == r - 1, lo_j = j == 0, hi_j = j == r - 1;
     if (lo_i) L[row - 1] = one;
     if (hi_i) L[row + r] = one;
@@ -114,7 +126,7 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
             if (SL == VI_STACK_ROWS) {
                 put_rows((float*)P.out, P, k, i, j, T, 1.0f);
             } else {
-                ((float*)P.out)[(size_t)k * layer + col] = T;
+                put((float*)P.out + (size_t)k * layer + col, T);
             }
         } else {
             // sigma * ds = -e ln(1 - a), capped at 64 per slab
@@ -122,7 +134,7 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
             if (SL == VI_STACK_ROWS) {
                 put_rows((uint16_t*)P.out, P, k, i, j, f32_to_bf16(tau), (uint16_t)0);
             } else {
-                ((uint16_t*)P.out)[(size_t)k * layer + col] = f32_to_bf16(tau);
+                put((uint16_t*)P.out + (size_t)k * layer + col, f32_to_bf16(tau));
             }
         }
     }

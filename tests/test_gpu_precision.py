@@ -32,12 +32,12 @@ def _phantom(N):
     return raw, W.to_f16_normalised(raw)
 
 
-def _precision_case(N, n, res, cam, light, mode, opts, pix):
+def _precision_case(N, n, res, cam, light, mode, opts, pix, layout=vi.VI_STACK_ROWS):
     raw, f16 = _phantom(N)
     tab = W.tf_ct()
     vol = vi.Volume.from_numpy(f16, DEV, 1.0).to_bricks().with_minmax(8)
     tf = vi.TF.from_numpy(tab, DEV)
-    st = vi.build_attenuation(vol, tf, light, n, res, vi.VI_BF16)
+    st = vi.build_attenuation(vol, tf, light, n, res, vi.VI_BF16, layout=layout)
     img = vi.render(vol, tf, st, cam, mode, 0.5, opts)
     torch.cuda.synchronize()
     got = img.cpu().double().numpy().reshape(-1, 4)
@@ -66,12 +66,13 @@ def _pixels(W_, H_, stride):
     return (ys * W_ + xs).ravel().astype(np.int64)
 
 
+@pytest.mark.parametrize("layout", [vi.VI_STACK_TILED, vi.VI_STACK_ROWS])
 @pytest.mark.parametrize("mode", ["shell", "cone"])
-def test_precision_form_medium(mode):
+def test_precision_form_medium(mode, layout):
     cam = W.camera_orbit(512, 384, 1.0, math.radians(20))
     light = W.light_from_angles(0.3, math.radians(35))
-    err_T, (mu, pu), (m16, p16) = _precision_case(256, 256, 512, cam, light, mode, {}, _pixels(512, 384, 4))
-    print(f"[precision] 256^3 {mode}: stack |dT| {err_T:.2e}; vs u16 oracle max-abs {mu:.2e} PSNR {pu:.1f} dB; "
+    err_T, (mu, pu), (m16, p16) = _precision_case(256, 256, 512, cam, light, mode, {}, _pixels(512, 384, 4), layout)
+    print(f"[precision] 256^3 {mode} layout {layout}: stack |dT| {err_T:.2e}; vs u16 oracle max-abs {mu:.2e} PSNR {pu:.1f} dB; "
           f"vs f16 oracle max-abs {m16:.2e} PSNR {p16:.1f} dB", flush=True)
     assert err_T < 4e-3          # bfloat16 optical depth: |dT| <= T tau 2^-8
     assert p16 >= 50.0 and pu >= 50.0
@@ -79,7 +80,8 @@ def test_precision_form_medium(mode):
 
 @pytest.mark.parametrize("mode", ["shell", "cone"])
 def test_precision_form_full_size_sampled(mode):
-    """1024^3 FP16 volume, 512 slabs x 1024^2 bfloat16, 1920x1080 -- on a pixel sample."""
+    """1024^3 FP16 volume, 512 slabs x 1024^2 bfloat16 (row layout, as benchmarked), 1920x1080 -- on a
+    pixel sample."""
     w = W.WORKLOADS["precision"]
     cam = w.camera(0)
     light = w.lights()[0]

@@ -35,14 +35,14 @@ def _requests(vols, count, seed):
         light = W.light_from_angles(2 * math.pi * li / 3 + 0.1 * vi_, math.radians(35))
         w, h = sizes[int(rng.integers(len(sizes)))]
         cam = W.camera_orbit(w, h, float(rng.uniform(0, 2 * math.pi)), math.radians(20))
-        mode = ["shell", "cone", "cone5", "shadow"][int(rng.integers(4))]
+        mode = ["shell", "cone", "cone5", "shadow", "phong"][int(rng.integers(5))]
         reqs.append(dict(vol=vi_, light=light, n=N, res=min(2 * N, 1024), cam=cam, mode=mode))
     return reqs
 
 
-def _alone(vols, r):
+def _alone(vols, r, layout=vi.VI_STACK_TILED):
     _, v, tf = vols[r["vol"]]
-    st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"])
+    st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"], layout=layout)
     m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
     cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
     img = vi.render(v, tf, st, r["cam"], m, 0.5, extra, samples=cnt)
@@ -50,18 +50,20 @@ def _alone(vols, r):
     return img.clone(), int(cnt.item())
 
 
-def _submit(srv, ids, r, samples=None):
+def _submit(srv, ids, r, samples=None, layout=vi.VI_STACK_TILED):
     m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
-    return srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], m, 0.5, extra, samples=samples)
+    return srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], m, 0.5, extra, samples=samples,
+                      layout=layout)
 
 
-def test_mixed_burst_equals_frames_rendered_alone():
+@pytest.mark.parametrize("layout", [vi.VI_STACK_TILED, vi.VI_STACK_ROWS])
+def test_mixed_burst_equals_frames_rendered_alone(layout):
     vols = _volumes()
     reqs = _requests(vols, 40, seed=1)
     srv = vi.Server(stack_budget=256 << 20, max_inflight=12, tiles_per_launch=64)
     ids = [srv.register(v, tf) for _, v, tf in vols]
     counters = [torch.zeros(1, dtype=torch.int64, device=DEV) for _ in reqs]
-    subs = [_submit(srv, ids, r, counters[i]) for i, r in enumerate(reqs)]
+    subs = [_submit(srv, ids, r, counters[i], layout) for i, r in enumerate(reqs)]
     for t, _ in subs:
         assert srv.wait(t, 60000) == 0
     torch.cuda.synchronize()
@@ -73,7 +75,7 @@ def test_mixed_burst_equals_frames_rendered_alone():
     assert st["mean_frames_per_launch"] > 1.0          # launches really mix frames
     assert st["stack_hits"] > 0                         # the light repeats: stacks are reused
     for i, r in enumerate(reqs):
-        ref, n_ref = _alone(vols, r)
+        ref, n_ref = _alone(vols, r, layout)
         assert torch.equal(subs[i][1], ref), f"request {i} differs from its standalone render"
         assert int(counters[i].item()) == n_ref
     srv.close()
