@@ -104,7 +104,8 @@ struct RenderFrame {
 // launchers (vi_build.hip / vi_render.hip / vi_layout.hip)
 hipError_t launch_build(const BuildParams& p, hipStream_t s);
 hipError_t launch_render(const RenderFrame& f, hipStream_t s);
-hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout,
+// one launch over `ntiles` tiles whose frames all have render mode `mode`
+hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout, int mode,
                                const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
                                hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStream_t s);

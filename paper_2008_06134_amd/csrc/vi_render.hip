@@ -503,14 +503,16 @@ __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_kernel(RenderF
 }
 
 // --------------------------------------------------------------------------
-// batched kernel (serving): the launch lists 16 x 16-pixel tiles of any frames;
-// each tile is covered by (16/BX) x (16/BY) workgroups, each reading its
-// frame's parameters from device memory.  Per pixel it runs the same
-// render_ray as render_kernel, so a frame is bit-identical alone and in a mix.
+// batched kernel (serving): the launch lists 16 x 16-pixel tiles of any frames
+// of one mode; each tile is covered by (16/BX) x (16/BY) workgroups, each
+// reading its frame's parameters from device memory.  Per pixel it runs the
+// same render_ray as render_kernel, so a frame is bit-identical alone and in a
+// mix.  (One kernel per mode keeps each mode's register budget: a kernel
+// holding every mode runs all of them at the occupancy of the largest.)
 // --------------------------------------------------------------------------
 constexpr uint32_t kSubX = 16 / kBX, kSubY = 16 / kBY, kSub = kSubX * kSubY;
 
-template <typename VT, int LAYOUT, int SDT, int SL>
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
 __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_batch_kernel(const RenderFrame* __restrict__ frames,
                                                            const uint32_t* __restrict__ tiles, uint32_t ntiles)
 {
@@ -526,54 +528,70 @@ __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_batch_kernel(c
     __syncthreads();
     int px, py;
     block_pixel((t & 2047u) * kSubX + sub % kSubX, ((t >> 11) & 2047u) * kSubY + sub / kSubX, &px, &py);
-    switch (F.mode) {
-    case VI_MODE_NONE: shade_pixel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>(F, s_tf, s_next, px, py); break;
-    case VI_MODE_SHADOW: shade_pixel<VT, LAYOUT, VI_MODE_SHADOW, SDT, SL>(F, s_tf, s_next, px, py); break;
-    case VI_MODE_SHELL: shade_pixel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>(F, s_tf, s_next, px, py); break;
-    case VI_MODE_CONE: shade_pixel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>(F, s_tf, s_next, px, py); break;
-    default: shade_pixel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>(F, s_tf, s_next, px, py); break;
-    }
+    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, px, py);
 }
 
 template <typename VT, int LAYOUT, int SDT, int SL>
-static hipError_t launch_batch_t(const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
-                                 hipStream_t s)
+static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles,
+                                 int maxK, hipStream_t s)
 {
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)maxK;
-    hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, SDT, SL>), dim3(list_grid(ntiles * kSub)), dim3(256), lds, s,
-                       d_frames, d_tiles, ntiles);
+    const dim3 grid(list_grid(ntiles * kSub)), block(256);
+    switch (mode) {
+    case VI_MODE_NONE:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>), grid, block, lds, s, d_frames,
+                           d_tiles, ntiles);
+        break;
+    case VI_MODE_SHADOW:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_SHADOW, SDT, SL>), grid, block, lds, s, d_frames,
+                           d_tiles, ntiles);
+        break;
+    case VI_MODE_SHELL:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>), grid, block, lds, s, d_frames,
+                           d_tiles, ntiles);
+        break;
+    case VI_MODE_CONE:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, d_frames,
+                           d_tiles, ntiles);
+        break;
+    default:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, d_frames,
+                           d_tiles, ntiles);
+        break;
+    }
     return hipGetLastError();
 }
 
 template <typename VT, int LAYOUT>
-static hipError_t launch_batch_l(int sdt, int sl, const RenderFrame* f, const uint32_t* t, uint32_t n, int K,
-                                 hipStream_t s)
+static hipError_t launch_batch_l(int sdt, int sl, int mode, const RenderFrame* f, const uint32_t* t, uint32_t n,
+                                 int K, hipStream_t s)
 {
     if (sdt == VI_BF16)
-        return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(f, t, n, K, s)
-                                    : launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(f, t, n, K, s);
-    return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(f, t, n, K, s)
-                                : launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_TILED>(f, t, n, K, s);
+        return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(mode, f, t, n, K, s)
+                                   : launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(mode, f, t, n, K, s);
+    return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(mode, f, t, n, K, s)
+                               : launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_TILED>(mode, f, t, n, K, s);
 }
 
 template <typename VT>
-static hipError_t launch_batch_vt(int layout, int sdt, int sl, const RenderFrame* f, const uint32_t* t, uint32_t n,
-                                  int K, hipStream_t s)
+static hipError_t launch_batch_vt(int layout, int sdt, int sl, int mode, const RenderFrame* f, const uint32_t* t,
+                                  uint32_t n, int K, hipStream_t s)
 {
-    return layout == VI_LAYOUT_BRICK4 ? launch_batch_l<VT, VI_LAYOUT_BRICK4>(sdt, sl, f, t, n, K, s)
-                                      : launch_batch_l<VT, VI_LAYOUT_LINEAR>(sdt, sl, f, t, n, K, s);
+    return layout == VI_LAYOUT_BRICK4 ? launch_batch_l<VT, VI_LAYOUT_BRICK4>(sdt, sl, mode, f, t, n, K, s)
+                                      : launch_batch_l<VT, VI_LAYOUT_LINEAR>(sdt, sl, mode, f, t, n, K, s);
 }
 
-hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout,
+hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout, int mode,
                                const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
                                hipStream_t s)
 {
     switch (vol_dtype) {
-    case VI_U8: return launch_batch_vt<uint8_t>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_U8: return launch_batch_vt<uint8_t>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
     case VI_U16:
-        return launch_batch_vt<uint16_t>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
-    case VI_F16: return launch_batch_vt<__half>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
-    default: return launch_batch_vt<float>(layout, stack_dtype, stack_layout, d_frames, d_tiles, ntiles, maxK, s);
+        return launch_batch_vt<uint16_t>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_F16:
+        return launch_batch_vt<__half>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
+    default: return launch_batch_vt<float>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
     }
 }
 

@@ -146,7 +146,15 @@ public:
             maxK = std::max(maxK, v.tf.n_entries);
             cls = frame_class(r, v);
         }
-        memcpy(S.h_tiles, tiles.data(), tiles.size() * sizeof(uint32_t));
+        // tiles grouped by render mode (stable), one kernel per mode present
+        uint32_t count[VI_MODE_PHONG + 1] = {0}, start[VI_MODE_PHONG + 2] = {0};
+        for (uint32_t t : tiles) count[frames[t >> 22].req->mode]++;
+        for (int m = 0; m <= VI_MODE_PHONG; ++m) start[m + 1] = start[m] + count[m];
+        {
+            uint32_t at[VI_MODE_PHONG + 1];
+            for (int m = 0; m <= VI_MODE_PHONG; ++m) at[m] = start[m];
+            for (uint32_t t : tiles) S.h_tiles[at[frames[t >> 22].req->mode]++] = t;
+        }
         hipError_t e = hipMemcpyAsync(S.d_frames, S.h_frames, frames.size() * sizeof(RenderFrame),
                                       hipMemcpyHostToDevice, rs_);
         if (e == hipSuccess)
@@ -155,11 +163,11 @@ public:
         for (const auto& f : frames)
             if (e == hipSuccess && f.stack->build_handle >= 0)
                 e = hipStreamWaitEvent(rs_, build_events_[f.stack->build_handle], 0);
-        if (e == hipSuccess) {
-            const vi_volume& v0 = frames[0].vol->vol;
-            e = launch_render_batch(v0.dtype, v0.layout, frames[0].req->slice_dtype, frames[0].req->slice_layout,
-                                    S.d_frames, S.d_tiles, (uint32_t)tiles.size(), maxK, rs_);
-        }
+        const vi_volume& v0 = frames[0].vol->vol;
+        for (int m = 0; m <= VI_MODE_PHONG && e == hipSuccess; ++m)
+            if (count[m])
+                e = launch_render_batch(v0.dtype, v0.layout, frames[0].req->slice_dtype, frames[0].req->slice_layout,
+                                        m, S.d_frames, S.d_tiles + start[m], count[m], maxK, rs_);
         if (e == hipSuccess) e = hipEventRecord(S.done, rs_);
         if (e != hipSuccess) return fail_msg(VI_E_DEVICE, hipGetErrorString(e));
         (void)cls;
