@@ -124,7 +124,8 @@ int Scheduler::submit(const vi_request* r, uint64_t* ticket)
         return VI_E_NO_MEMORY;
     }
     q.tiles_x = (r->camera.width + kTile - 1) / kTile;
-    q.ntiles = q.tiles_x * ((r->camera.height + kTile - 1) / kTile);
+    q.tiles_y = (r->camera.height + kTile - 1) / kTile;
+    q.ntiles = q.tiles_x * q.tiles_y;
     q.submitted = clock::now();
     if (!have_first_) {
         have_first_ = true;
@@ -268,8 +269,11 @@ bool Scheduler::launch_next()
         const int take = std::min(budget, q.ntiles - q.next_tile);
         const uint32_t f = (uint32_t)frames.size();
         frames.push_back(LaunchFrame{&q.r, &vols_[q.r.vol_id], &stacks_[q.stack].ref});
-        for (int i = q.next_tile; i < q.next_tile + take; ++i)
-            tiles.push_back(pack_tile((uint32_t)(i % q.tiles_x), (uint32_t)(i / q.tiles_x), f));
+        for (int i = q.next_tile; i < q.next_tile + take; ++i) {
+            uint32_t tx, ty;
+            tile_of(i, q.tiles_x, q.tiles_y, &tx, &ty);
+            tiles.push_back(pack_tile(tx, ty, f));
+        }
         q.next_tile += take;
         budget -= take;
         L.members.push_back(t);
@@ -346,7 +350,7 @@ void Scheduler::loop()
             // nothing to do until a launch finishes or a request arrives (timed
             // against the system clock: a plain timed wait on the mutex)
             cv_work_.wait_until(lk, std::chrono::system_clock::now() +
-                                        std::chrono::microseconds(launches_.empty() ? 2000 : 50));
+                                        std::chrono::microseconds(launches_.empty() ? 2000 : 10));
         }
     }
 }

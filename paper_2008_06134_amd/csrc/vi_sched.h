@@ -45,6 +45,27 @@ struct LaunchFrame {
 // Tiles are 16 x 16 pixels; a tile entry packs x | y << 11 | frame << 22.
 constexpr int kTile = 16;
 inline uint32_t pack_tile(uint32_t tx, uint32_t ty, uint32_t f) { return tx | (ty << 11) | (f << 22); }
+// Tile i of a W x H tile grid in launch order: 2 x 2 blocks of tiles
+// (32 x 32 pixels), row pairs top to bottom; an odd last column or row is
+// taken in order.  Consecutive tiles then cover square patches, which keeps
+// the volume and stack footprint of a group of workgroups compact.
+inline void tile_of(int i, int W, int H, uint32_t* tx, uint32_t* ty)
+{
+    const int pairs = H / 2, p = i / (2 * W);
+    if (p >= pairs) {
+        *tx = (uint32_t)(i - pairs * 2 * W);
+        *ty = (uint32_t)(H - 1);
+        return;
+    }
+    const int j = i - p * 2 * W, full = 4 * (W / 2);
+    if (j < full) {
+        *tx = (uint32_t)(2 * (j / 4) + (j & 1));
+        *ty = (uint32_t)(2 * p + ((j >> 1) & 1));
+    } else {
+        *tx = (uint32_t)(W - 1);
+        *ty = (uint32_t)(2 * p + (j - full));
+    }
+}
 
 class Executor {
 public:
@@ -125,7 +146,7 @@ private:
         int cls = 0;
         size_t stack_bytes = 0;
         int stack = -1;
-        int tiles_x = 0, ntiles = 0, next_tile = 0;
+        int tiles_x = 0, tiles_y = 0, ntiles = 0, next_tile = 0;
         clock::time_point submitted;
     };
     struct Launch {

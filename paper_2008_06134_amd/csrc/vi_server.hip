@@ -37,11 +37,12 @@ public:
         if (hipStreamCreateWithFlags(&rs_, hipStreamNonBlocking) != hipSuccess ||
             hipStreamCreateWithFlags(&bs_, hipStreamNonBlocking) != hipSuccess)
             return fail_msg(VI_E_DEVICE, "cannot create streams");
+        // per slot one staging area: the launch's frames, then its tiles,
+        // copied to the device with one transfer
+        const size_t stage = sizeof(RenderFrame) * kMaxLaunchFrames + 16 + sizeof(uint32_t) * (size_t)max_tiles_;
         for (auto& s : slots_) {
-            if (hipMalloc(&s.d_frames, sizeof(RenderFrame) * kMaxLaunchFrames) != hipSuccess ||
-                hipMalloc(&s.d_tiles, sizeof(uint32_t) * (size_t)max_tiles_) != hipSuccess ||
-                hipHostMalloc(&s.h_frames, sizeof(RenderFrame) * kMaxLaunchFrames, hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc(&s.h_tiles, sizeof(uint32_t) * (size_t)max_tiles_, hipHostMallocDefault) != hipSuccess ||
+            if (hipMalloc(&s.d_stage, stage) != hipSuccess ||
+                hipHostMalloc(&s.h_stage, stage, hipHostMallocDefault) != hipSuccess ||
                 hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
                 return fail_msg(VI_E_NO_MEMORY, "cannot allocate staging buffers");
         }
@@ -54,10 +55,8 @@ public:
         if (rs_) hipStreamSynchronize(rs_);
         if (bs_) hipStreamSynchronize(bs_);
         for (auto& s : slots_) {
-            if (s.d_frames) hipFree(s.d_frames);
-            if (s.d_tiles) hipFree(s.d_tiles);
-            if (s.h_frames) hipHostFree(s.h_frames);
-            if (s.h_tiles) hipHostFree(s.h_tiles);
+            if (s.d_stage) hipFree(s.d_stage);
+            if (s.h_stage) hipHostFree(s.h_stage);
             if (s.done) hipEventDestroy(s.done);
         }
         for (hipEvent_t e : build_events_)
@@ -136,15 +135,20 @@ public:
         if (slot < 0 || (int)frames.size() > kMaxLaunchFrames || (int)tiles.size() > max_tiles_)
             return fail_msg(VI_E_BUSY, "no staging slot free");
         Slot& S = slots_[slot];
-        int maxK = 2, cls = -1;
+        // staging: this launch's frames, then its tiles (16-byte aligned)
+        RenderFrame* h_frames = (RenderFrame*)S.h_stage;
+        const size_t frames_bytes = (frames.size() * sizeof(RenderFrame) + 15) / 16 * 16;
+        uint32_t* h_tiles = (uint32_t*)((char*)S.h_stage + frames_bytes);
+        const RenderFrame* d_frames = (const RenderFrame*)S.d_stage;
+        const uint32_t* d_tiles = (const uint32_t*)((const char*)S.d_stage + frames_bytes);
+        int maxK = 2;
         for (size_t f = 0; f < frames.size(); ++f) {
             const vi_request& r = *frames[f].req;
             const sched::VolumeRec& v = *frames[f].vol;
             int rc = make_frame(&v.vol, &v.tf, &frames[f].stack->desc, &r.camera, r.mode, r.step_vox, &r.opts,
-                                r.d_rgba, r.d_samples, &S.h_frames[f]);
+                                r.d_rgba, r.d_samples, &h_frames[f]);
             if (rc != VI_OK) return rc;
             maxK = std::max(maxK, v.tf.n_entries);
-            cls = frame_class(r, v);
         }
         // tiles grouped by render mode (stable), one kernel per mode present
         uint32_t count[VI_MODE_PHONG + 1] = {0}, start[VI_MODE_PHONG + 2] = {0};
@@ -153,12 +157,10 @@ public:
         {
             uint32_t at[VI_MODE_PHONG + 1];
             for (int m = 0; m <= VI_MODE_PHONG; ++m) at[m] = start[m];
-            for (uint32_t t : tiles) S.h_tiles[at[frames[t >> 22].req->mode]++] = t;
+            for (uint32_t t : tiles) h_tiles[at[frames[t >> 22].req->mode]++] = t;
         }
-        hipError_t e = hipMemcpyAsync(S.d_frames, S.h_frames, frames.size() * sizeof(RenderFrame),
+        hipError_t e = hipMemcpyAsync(S.d_stage, S.h_stage, frames_bytes + tiles.size() * sizeof(uint32_t),
                                       hipMemcpyHostToDevice, rs_);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(S.d_tiles, S.h_tiles, tiles.size() * sizeof(uint32_t), hipMemcpyHostToDevice, rs_);
         // device-side waits on the builds of the stacks this launch reads
         for (const auto& f : frames)
             if (e == hipSuccess && f.stack->build_handle >= 0)
@@ -167,10 +169,9 @@ public:
         for (int m = 0; m <= VI_MODE_PHONG && e == hipSuccess; ++m)
             if (count[m])
                 e = launch_render_batch(v0.dtype, v0.layout, frames[0].req->slice_dtype, frames[0].req->slice_layout,
-                                        m, S.d_frames, S.d_tiles + start[m], count[m], maxK, rs_);
+                                        m, d_frames, d_tiles + start[m], count[m], maxK, rs_);
         if (e == hipSuccess) e = hipEventRecord(S.done, rs_);
         if (e != hipSuccess) return fail_msg(VI_E_DEVICE, hipGetErrorString(e));
-        (void)cls;
         S.busy = true;
         return slot;
     }
@@ -187,10 +188,8 @@ public:
 
 private:
     struct Slot {
-        RenderFrame* d_frames = nullptr;
-        uint32_t* d_tiles = nullptr;
-        RenderFrame* h_frames = nullptr;
-        uint32_t* h_tiles = nullptr;
+        void* d_stage = nullptr;  // device: frames, then tiles
+        void* h_stage = nullptr;  // pinned host mirror
         hipEvent_t done = nullptr;
         bool busy = false;
     };
