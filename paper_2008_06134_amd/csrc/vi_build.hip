@@ -22,8 +22,14 @@ namespace vi {
 // tiled layout, whose 8 x 4 tiles a wave then writes whole; 64 x 4 (waves of
 // one 64-texel row segment) for the row layout, so every slab store of a
 // wave is one contiguous 256-byte run.
-template <int SL> struct BuildBlock { static constexpr int X = 16, Y = 16; };
-template <> struct BuildBlock<VI_STACK_ROWS> { static constexpr int X = 64, Y = 4; };
+#ifndef VI_BUILD_ROW_RUN
+#define VI_BUILD_ROW_RUN 64
+#endif
+template <int SL> struct BuildBlock { static constexpr int X = 16, Y = 16, WX = 16; };
+template <> struct BuildBlock<VI_STACK_ROWS> {
+    static constexpr int WX = VI_BUILD_ROW_RUN;       // texels of a row per wave
+    static constexpr int X = WX, Y = 4 * (64 / WX);
+};
 
 // Row layout: a lane stores its own texel and, on the edge of the grid, the
 // fully transmitting border texels next to it (the corners by the corner
@@ -74,8 +80,9 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     uint32_t tx, ty;
     if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = (int)tx * BX + (BX == 64 ? lane : (lane & 15));
-    const int j = (int)ty * BY + (BX == 64 ? wave : wave * 4 + (lane >> 4));
+    constexpr int WX = BuildBlock<SL>::WX, WY = 64 / WX;  // wave footprint
+    const int i = (int)tx * BX + lane % WX;
+    const int j = (int)ty * BY + wave * WY + lane / WX;
     if (i >= P.res || j >= P.res) return;
 
     // column base (slab 0 midpoint) in offset-voxel coordinates, in double
@@ -94,6 +101,9 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     uint32_t last_cell = 0xffffffffu;
     bool cell_is_empty = false;
 
+#ifdef VI_BUILD_UNROLL
+#pragma unroll VI_BUILD_UNROLL
+#endif
     for (int k = 0; k < P.n; ++k) {
         const float kf = (float)k;
         const float hx = fmaf(kf, P.AL[0], hx0);

@@ -8,6 +8,9 @@ P6 light parallel to view: closed-form limit and convergence
 P7 stack lookup vs a dense march toward the light: second-order convergence
 P8 reductions (vanishing shell step == direct shadow)
 P9 invariants (alpha <= 1, 0 <= C <= alpha, stack monotone, termination bound)
+P11 local Phong (section 4's comparison mode): exact gradients of linear fields, closed-form
+    ramp images for diffuse-only, specular-only, oblique and flat-field lighting, the unlit
+    reduction, and the lit side of a sphere
 """
 import math
 
@@ -432,7 +435,7 @@ def test_cone_taps_invariant_under_quarter_turn_of_view(grid):
     assert st.coefficient("cone", p, [-1.0, 0.0, 0.0], {"cone_grid": grid, "cone_tan": 0.2}) != pytest.approx(a_x)
 
 
-# ------------------------------------------------------------------ P10 local Phong (comparison mode)
+# ------------------------------------------------------------------ P11 local Phong (comparison mode)
 
 def _linear_volume(N, c0, grad):
     """f32 volume f = c0 + grad . (x, y, z) in voxel-index units (raw[z][y][x])."""
@@ -440,7 +443,7 @@ def _linear_volume(N, c0, grad):
     return (c0 + grad[0] * x + grad[1] * y + grad[2] * z).astype(np.float32)
 
 
-def test_p10_gradient_of_a_linear_field_is_exact():
+def test_p11_gradient_of_a_linear_field_is_exact():
     """Central differences of the trilinear reconstruction of a linear field are
     the field's own gradient (per voxel) wherever no index is clamped; distinct
     per-axis slopes catch a swapped or mis-signed axis."""
@@ -472,7 +475,7 @@ PHONG = {"phong_ka": 0.1, "phong_kd": 0.7, "phong_ks": 0.4, "phong_shininess": 4
     # diffuse scales with it, the mirror term with its square (r.v = 0 here)
     (2.0 ** -8, (1, 0, 0), lambda o: (o["phong_ka"] + o["phong_kd"] * 2.0 ** -8 / o["grad_eps"], 0.0)),
 ])
-def test_p10_phong_closed_form_ramp(slope, L, sd_ss):
+def test_p11_phong_closed_form_ramp(slope, L, sd_ss):
     """Ortho view along +y through a field linear in x with a constant TF: every
     segment of a ray has the same normal, so a pixel is (sd rgb + ss) times the
     chord opacity 1 - (1 - a0)^N, for rays whose samples never clamp in x."""
@@ -499,7 +502,7 @@ def test_p10_phong_closed_form_ramp(slope, L, sd_ss):
     assert O.phong(vol, np.asarray(L, float) / np.linalg.norm(L), p, [0, 1, 0], PHONG) == pytest.approx((sd, ss), abs=1e-14)
 
 
-def test_p10_phong_reduces_to_unlit():
+def test_p11_phong_reduces_to_unlit():
     """k_a = 1, k_d = k_s = 0 gives exactly the unlit (A = 1) image."""
     w = W.WORKLOADS["small"]
     vol, tf = O.Volume(w.volume()), O.TF(w.tf())
@@ -511,7 +514,7 @@ def test_p10_phong_reduces_to_unlit():
     assert np.array_equal(a, b) and np.array_equal(na, nb)
 
 
-def test_p10_phong_sphere_lit_side_brighter():
+def test_p11_phong_sphere_lit_side_brighter():
     """A lit sphere: rays hitting the side facing the light are brighter than those
     on the far side (normal orientation -g points out of a dense object)."""
     N = 40
