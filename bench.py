@@ -35,7 +35,18 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
                   "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # large workload (512^3 u16 bricks, 512 x 1024^2 f32 stack in rows, 1920x1080), light 0
+    ("render_cone", "large", "rows"): {
+        "sha256": "72f4529198a92a2726b306de161297a5e0deccce9ead6d7a4c1077fadb1ba0fd",
+        "fetch_kib": 80126.4, "write_kib": 34760.0},
+    ("render_shell", "large", "rows"): {
+        "sha256": "72f4529198a92a2726b306de161297a5e0deccce9ead6d7a4c1077fadb1ba0fd",
+        "fetch_kib": 69641.1, "write_kib": 34455.8},
+    ("build", "large", "rows"): {
+        "sha256": "151b298ec9450e7b5a40f1d2391086f68db8adf02260044d9744db6451b625f3",
+        "fetch_kib": 60659.8, "write_kib": 2315410.0},
+}
 
 
 def source_sha(kind: str) -> str:
