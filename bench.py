@@ -249,6 +249,53 @@ def serving_sweep(dev, budget=48 << 30, count=2000, rates=(0.25, 0.5, 0.75, 0.9,
     return {"volumes": 64, "volume_edges": sizes, "requests_per_rate": count, "capacity_fps": cap, "rows": rows}
 
 
+def scaling_sweep(dev, slices=(64, 128, 256, 512), resolutions=(128, 256, 512, 1024), reps=5):
+    """Build and frame times over slab count x slice resolution on the large workload
+    (light 0, its camera), each the mean of `reps` HIP-event timed launches."""
+    import torch
+    from paper_2008_06134_amd import vi
+    from paper_2008_06134_amd import workloads as W
+    w = W.WORKLOADS["large"]
+    raw, tab = w.volume(), w.tf()
+    vol = vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(8)
+    tf = vi.TF.from_numpy(tab, dev)
+    light, cam = w.lights()[0], w.camera(0)
+    img = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    rows = []
+    for n in slices:
+        for res in resolutions:
+            buf = vi.stack_buffer(n, res, vi.VI_F32, dev, STACK_LAYOUT)
+            st = vi.build_attenuation(vol, tf, light, n, res, out=buf, layout=STACK_LAYOUT)
+            row = {"n": n, "res": res,
+                   "build_ms": round(timed(lambda: vi.build_attenuation(vol, tf, light, n, res, out=buf,
+                                                                       layout=STACK_LAYOUT)), 4)}
+            for m, extra in (("shell", {}), ("cone", {}), ("cone5", {"cone_grid": 5})):
+                mm = "cone" if m == "cone5" else m
+                row[f"{m}_ms"] = round(timed(lambda: vi.render(vol, tf, st, cam, mm, w.step_vox, extra, out=img)), 4)
+            log(json.dumps(row))
+            rows.append(row)
+            del buf, st
+    # the paper's flexibility claim: frame time nearly flat in the slab count
+    flat = {}
+    for res in resolutions:
+        r = [x for x in rows if x["res"] == res]
+        lo, hi = min(r, key=lambda x: x["n"]), max(r, key=lambda x: x["n"])
+        flat[str(res)] = {m: round(hi[f"{m}_ms"] / lo[f"{m}_ms"], 3) for m in ("shell", "cone", "cone5")}
+    return {"workload": "large 512^3 u16, light 0, 1920x1080", "layout": ["tiled", "rows"][STACK_LAYOUT],
+            "rows": rows, f"frame_ms_ratio_n{max(slices)}_over_n{min(slices)}": flat}
+
+
 def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     """Time `args.steps` steps (build + every mode's frame for light i) after warm-up."""
     import torch
@@ -315,6 +362,8 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving leg")
     ap.add_argument("--modes", default=None, help="comma-separated modes to time (none, shadow, shell, cone, cone5)")
+    ap.add_argument("--scaling-sweep", action="store_true",
+                    help="only run the slab-count x slice-resolution sweep (build and frame times)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
     ap.add_argument("--stack-layout", default="rows", choices=["tiled", "rows"],
@@ -345,6 +394,10 @@ def main():
     if args.serving_sweep:
         torch.cuda.set_device(0)
         print(json.dumps({"serving_sweep": serving_sweep("cuda:0")}), flush=True)
+        return
+    if args.scaling_sweep:
+        torch.cuda.set_device(0)
+        print(json.dumps({"scaling_sweep": scaling_sweep("cuda:0")}), flush=True)
         return
 
     w = W.WORKLOADS[args.workload]
