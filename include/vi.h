@@ -165,7 +165,16 @@ typedef struct {
     double R;           /* half-width of the light square, sqrt(3)/2 */
     int vol_n;          /* edge of the volume it was built from */
     uint64_t tag;       /* identity of (volume, transfer function); 0 = unchecked */
+    float darken;       /* build option it was built with (vi_build_opts) */
 } vi_slices;
+
+/* Build options; NULL means all defaults. */
+typedef struct {
+    /* 0: plain Eq. 4 product.  m > 0: the compensation of section 4 --
+     * every slab's transmitted fraction (1-alpha) is multiplied by
+     * (1+alpha)^m and capped at 1 (a slab never adds light).  0 <= m <= 64. */
+    float darken;
+} vi_build_opts;
 
 /* Camera: orthographic (view along target-eye, half image height
  * ortho_half_h in world units) or pinhole (full vertical field of view
@@ -185,6 +194,7 @@ typedef struct {
     float bg[4];        /* (0,0,0,0), premultiplied, composited last       */
     float term_eps;     /* 2^-15: stop once 1 - alpha_dst <= term_eps       */
     int shell_count;    /* 1: cuboid shells, 6 taps each                    */
+    float shell_w[8];   /* 0s: equal weights; else weight of shell r: A = sum w_r mean_r / sum w_r */
     float shell_h_vox;  /* 1: shell r samples at +-(r+1)*h voxels along x,y,z */
     int cone_rings;     /* 2: rings at m*ds toward the light, m = 1..rings  */
     int cone_angles;    /* 4: taps per ring, angles 2*pi*q/angles           */
@@ -252,12 +262,14 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
  * `stream`.  slice_dtype: VI_F32 (transmittance, product of per-slab
  * (1-alpha)) or VI_BF16 (optical depth: the per-slab extinction summed in
  * float and rounded to bfloat16 per layer; each slab adds at most 64).
- * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes or a degenerate
- * light; VI_E_UNSUPPORTED for dtypes or sizes outside the limits above or a
- * stack of 4 GiB or more; VI_E_DEVICE if the launch fails. */
+ * `opts` may be NULL (plain product).
+ * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes, a degenerate
+ * light or options out of range; VI_E_UNSUPPORTED for dtypes or sizes
+ * outside the limits above or a stack of 4 GiB or more; VI_E_DEVICE if the
+ * launch fails. */
 int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n_slices,
-                         int slice_res, int slice_dtype, int slice_layout, void* d_slices, vi_slices* out_desc,
-                         vi_stream_t stream);
+                         int slice_res, int slice_dtype, int slice_layout, const vi_build_opts* opts,
+                         void* d_slices, vi_slices* out_desc, vi_stream_t stream);
 
 /* Ray-cast `cam` through the volume with the illumination coefficient
  * `mode` gathered from `slices` (section 3.2.2 and 3.2.3) and write
@@ -317,6 +329,7 @@ typedef struct {
     int vol_id;                /* from vi_server_register_volume                        */
     double light_dir[3];
     int n_slices, slice_res, slice_dtype, slice_layout;
+    vi_build_opts build;       /* stack build options (part of the stack's identity)   */
     vi_camera camera;
     int mode;
     float step_vox;

@@ -54,7 +54,7 @@ class _TF(C.Structure):
 class _Frame(C.Structure):
     _fields_ = [("L", C.c_double * 3), ("U", C.c_double * 3), ("V", C.c_double * 3), ("c", C.c_double * 3),
                 ("dmin", C.c_double), ("dmax", C.c_double), ("ds", C.c_double), ("R", C.c_double),
-                ("n", C.c_int), ("res", C.c_int)]
+                ("n", C.c_int), ("res", C.c_int), ("darken", C.c_double)]
 
 
 class _Camera(C.Structure):
@@ -64,7 +64,8 @@ class _Camera(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("ambient", C.c_double), ("light_rgb", C.c_double * 3), ("bg", C.c_double * 4),
-                ("term_eps", C.c_double), ("shell_count", C.c_int), ("shell_h_vox", C.c_double),
+                ("term_eps", C.c_double), ("shell_count", C.c_int), ("shell_w", C.c_double * 8),
+                ("shell_h_vox", C.c_double),
                 ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_double),
                 ("phong_ka", C.c_double), ("phong_kd", C.c_double), ("phong_ks", C.c_double),
                 ("phong_shininess", C.c_double), ("grad_eps", C.c_double)]
@@ -131,7 +132,8 @@ def default_opts() -> dict:
     o = _Opts()
     _load().vio_default_opts(C.byref(o))
     return {"ambient": o.ambient, "light_rgb": list(o.light_rgb), "bg": list(o.bg), "term_eps": o.term_eps,
-            "shell_count": o.shell_count, "shell_h_vox": o.shell_h_vox, "cone_rings": o.cone_rings,
+            "shell_count": o.shell_count, "shell_w": list(o.shell_w), "shell_h_vox": o.shell_h_vox,
+            "cone_rings": o.cone_rings,
             "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan,
             **{k: getattr(o, k) for k in _PHONG_KEYS}}
 
@@ -146,6 +148,8 @@ def _opts(opts: dict | None) -> _Opts:
     o.bg = (C.c_double * 4)(*d["bg"])
     o.term_eps = d["term_eps"]
     o.shell_count = int(d["shell_count"])
+    w = list(d["shell_w"]) + [0.0] * 8
+    o.shell_w = (C.c_double * 8)(*[float(x) for x in w[:8]])
     o.shell_h_vox = d["shell_h_vox"]
     for k in _PHONG_KEYS:
         setattr(o, k, float(d[k]))
@@ -219,9 +223,10 @@ def segment_alpha(a: float, length: float, dref: float) -> float:
 class Stack:
     """Attenuation stack S[k][j][i] (Alg. 1), columns built on first use."""
 
-    def __init__(self, vol: Volume, tf: TF, light, n: int, res: int):
+    def __init__(self, vol: Volume, tf: TF, light, n: int, res: int, darken: float = 0.0):
         self.vol, self.tf = vol, tf  # keep the buffers alive
         self.frame = light_frame(light, n, res)
+        self.frame["_s"].darken = float(darken)
         self.n, self.res = n, res
         self._p = _load().vio_stack_create(C.byref(vol._s), C.byref(tf._s), C.byref(self.frame["_s"]))
         if not self._p:

@@ -88,6 +88,7 @@ int vio_light_frame(const double l[3], int n, int res, vio_frame* f)
     if (!(nl > 0.0) || !isfinite(nl) || n < 1 || res < 1) return -1;
     for (int a = 0; a < 3; ++a) f->L[a] = l[a] / nl;
     f->c[0] = f->c[1] = f->c[2] = 0.5;
+    f->darken = 0.0;
 
     /* Eq. 8: distances of the eight unit-cube vertices along L */
     f->dmin = INFINITY;
@@ -227,8 +228,16 @@ void vio_build_column(const vio_volume* v, const vio_tf* tf, const vio_frame* f,
             vio_tf_lookup(tf, vio_volume_sample(v, p), rgba);
             alpha = vio_segment_alpha(rgba[3], f->ds, dref);
         }
-        /* Eq. 4 on opacity: (1-a_dst)(1-a_src) is what stays transmitted */
-        T = T * (1.0 - alpha);
+        /* Eq. 4 on opacity: (1-a_dst)(1-a_src) is what stays transmitted;
+         * with the section 4 compensation every slab's factor is also
+         * multiplied by (1+alpha)^m, capped at 1 so that no slab adds
+         * light (R24) */
+        double f_slab = 1.0 - alpha;
+        if (f->darken > 0.0) {
+            f_slab *= pow(1.0 + alpha, f->darken);
+            if (f_slab > 1.0) f_slab = 1.0;
+        }
+        T = T * f_slab;
         col[k] = T;
     }
 }
@@ -362,19 +371,25 @@ double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N, const d
     if (mode == VIO_MODE_SHADOW) return vio_stack_lookup(s, p);
 
     if (mode == VIO_MODE_SHELL) {
-        /* Cuboid shells: the sample moved by +-(r+1) h along x, y and z,
-         * equal weights (reading R13). */
-        double h = o->shell_h_vox / N, sum = 0.0;
-        int taps = 0;
-        for (int r = 0; r < o->shell_count; ++r)
+        /* Cuboid shells: the sample moved by +-(r+1) h along x, y and z;
+         * shell r weighted w_r (section 3.2.3: each neighbourhood gets a
+         * weight), equal weights when none is given (reading R13):
+         * A = sum_r w_r mean_r / sum_r w_r. */
+        double h = o->shell_h_vox / N, num = 0.0, wsum = 0.0;
+        int weighted = 0;
+        for (int r = 0; r < o->shell_count && r < 8; ++r) weighted |= o->shell_w[r] != 0.0;
+        for (int r = 0; r < o->shell_count; ++r) {
+            double w = weighted ? o->shell_w[r] : 1.0, sum = 0.0;
             for (int a = 0; a < 3; ++a)
                 for (int sg = -1; sg <= 1; sg += 2) {
                     double q[3] = {p[0], p[1], p[2]};
                     q[a] += sg * (r + 1) * h;
                     sum += vio_stack_lookup(s, q);
-                    ++taps;
                 }
-        return sum / taps;
+            num += w * sum / 6.0;
+            wsum += w;
+        }
+        return num / wsum;
     }
 
     /* Cone: B_proj lies in the plane of sample, light and viewer: the

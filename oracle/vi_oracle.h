@@ -60,6 +60,8 @@ typedef struct {
     double ds;          /* slab thickness (dmax - dmin) / n              */
     double R;           /* half-width of the light-plane square          */
     int n, res;         /* slab count and texels per side                */
+    double darken;      /* build: exponent m of the (1+alpha)^m slab
+                           compensation of section 4 (0 = off, R24)      */
 } vio_frame;
 
 typedef struct {
@@ -76,6 +78,7 @@ typedef struct {
     double bg[4];         /* premultiplied background                     */
     double term_eps;      /* terminate once 1 - alpha_dst <= term_eps     */
     int shell_count;      /* number of cuboid shells                      */
+    double shell_w[8];    /* weight of shell r (all 0: equal weights)     */
     double shell_h_vox;   /* shell step in voxels                         */
     int cone_rings;       /* rings toward the light (ring form)           */
     int cone_angles;      /* taps per ring (ring form)                    */

@@ -172,6 +172,7 @@ int vi_default_render_opts(vi_render_opts* o)
     o->cone_angles = 4;
     o->cone_grid = 0;
     o->cone_tan = 1.0f;
+    for (int r = 0; r < 8; ++r) o->shell_w[r] = 0.0f;
     o->phong_ka = 0.1f;
     o->phong_kd = 0.9f;
     o->phong_ks = 0.4f;
@@ -273,7 +274,8 @@ int vi_light_frame(const double light_dir[3], int n, int res, int dt, int sl, vi
 }
 
 int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n, int res,
-                         int dt, int sl, void* d_slices, vi_slices* out_desc, vi_stream_t stream)
+                         int dt, int sl, const vi_build_opts* opts, void* d_slices, vi_slices* out_desc,
+                         vi_stream_t stream)
 {
     clear_err();
     int rc;
@@ -286,6 +288,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     if (((uintptr_t)d_slices) % 16) return fail(VI_E_INVALID_ARG, "stack buffer must be 16-byte aligned");
     if (!stack_size_ok(n, res, dt, sl))
         return fail(VI_E_UNSUPPORTED, "stack of %zu bytes exceeds the layout's limit", vi_slices_bytes(n, res, dt, sl));
+    const float darken = opts ? opts->darken : 0.0f;
+    if (!(darken >= 0.0f && darken <= 64.0f)) return fail(VI_E_INVALID_ARG, "darken must be in [0, 64]");
 
     vi::BuildParams p;
     memset(&p, 0, sizeof p);
@@ -319,6 +323,7 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
         p.AL[a] = (float)(f.L[a] * f.ds * N);
     }
     p.e = (float)(f.ds * N);
+    p.darken = darken;
     p.lo = (float)(-0.5 - p.M);
     p.hi = (float)(N - 0.5 - p.M);
     hipError_t e = vi::launch_build(p, (hipStream_t)stream);
@@ -326,6 +331,7 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     f.data = d_slices;
     f.vol_n = vol->n;
     f.tag = vi_tag(vol, tf);
+    f.darken = darken;
     *out_desc = f;
     return VI_OK;
 }
@@ -487,6 +493,18 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         if (o.shell_count < 1 || 6 * o.shell_count > vi::kMaxTaps)
             return fail(VI_E_INVALID_ARG, "shell_count must be 1..%d", vi::kMaxTaps / 6);
         if (!(o.shell_h_vox >= 0.0f)) return fail(VI_E_INVALID_ARG, "shell_h_vox must be >= 0");
+        // shell weights: all zero = equal; else w_r >= 0 with a positive sum
+        double wsum = 0.0;
+        bool weighted = false;
+        for (int r = 0; r < 8; ++r) {
+            if (!(o.shell_w[r] >= 0.0f) || !isfinite(o.shell_w[r]))
+                return fail(VI_E_INVALID_ARG, "shell weights must be finite and >= 0");
+            if (r < o.shell_count) {
+                weighted |= o.shell_w[r] != 0.0f;
+                wsum += o.shell_w[r];
+            }
+        }
+        if (!weighted) wsum = o.shell_count;
         const double h = (double)o.shell_h_vox / vol->n;
         int t = 0;
         for (int r = 1; r <= o.shell_count; ++r)
@@ -496,6 +514,7 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
                     F.tz[t] = (float)(off * F.Lq[a]);
                     F.tx_[t] = (float)(off * F.Ux[a]);
                     F.ty_[t] = (float)(off * F.Vy[a]);
+                    F.tw[t] = (float)((weighted ? o.shell_w[r - 1] : 1.0) / (6.0 * wsum));
                     ++t;
                 }
         F.ntaps = t;

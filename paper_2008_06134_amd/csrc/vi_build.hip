@@ -132,15 +132,21 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         }
         if (OUT_DTYPE == VI_F32) {
             // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
-            T *= fast_exp2(P.e * l2);
+            float f = fast_exp2(P.e * l2);
+            // section 4 compensation: times (1 + alpha)^m, at most 1
+            if (P.darken > 0.0f) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
+            T *= f;
             if (SL == VI_STACK_ROWS) {
                 put_rows((float*)P.out, P, k, i, j, T, 1.0f);
             } else {
                 put((float*)P.out + (size_t)k * layer + col, T);
             }
         } else {
-            // sigma * ds = -e ln(1 - a), capped at 64 per slab
-            tau += fminf(-P.e * ln2 * l2, 64.0f);
+            // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
+            // compensation subtracts m ln(1 + alpha), floored at 0
+            float dtau = -P.e * ln2 * l2;
+            if (P.darken > 0.0f) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(P.e * l2)), 0.0f);
+            tau += fminf(dtau, 64.0f);
             if (SL == VI_STACK_ROWS) {
                 put_rows((uint16_t*)P.out, P, k, i, j, f32_to_bf16(tau), (uint16_t)0);
             } else {

@@ -47,6 +47,7 @@ struct BuildParams {
     double BV[3];      // d h / d j
     float AL[3];       // d h / d k
     float e;           // slab thickness in voxels: exponent of (1-a)
+    float darken;      // exponent m of the (1+alpha)^m slab compensation, 0 = off
     float lo, hi;      // cube in h coordinates: [-1/2 - M, N - 1/2 - M]
 };
 
@@ -93,6 +94,7 @@ struct RenderFrame {
     int ntaps;
     float tap_w;
     float tz[kMaxTaps], tx_[kMaxTaps], ty_[kMaxTaps];  // shell offsets
+    float tw[kMaxTaps];                                 // shell tap weights (sum 1)
     int cone_rings, cone_angles, cone_grid;
     float cone_tan;
     float cone_cos[16], cone_sin[16];

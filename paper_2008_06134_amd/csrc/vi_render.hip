@@ -149,9 +149,11 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
 {
     if (MODE == VI_MODE_SHADOW) return stack_lookup<SDT, SL>(F, z, x, y);
     if (MODE == VI_MODE_SHELL) {
+        // weighted taps (shell r's six taps share w_r / (6 sum w))
         float s = 0.0f;
-        for (int t = 0; t < F.ntaps; ++t) s += stack_lookup<SDT, SL>(F, z + F.tz[t], x + F.tx_[t], y + F.ty_[t]);
-        return s * F.tap_w;
+        for (int t = 0; t < F.ntaps; ++t)
+            s = fmaf(F.tw[t], stack_lookup<SDT, SL>(F, z + F.tz[t], x + F.tx_[t], y + F.ty_[t]), s);
+        return s;
     }
     // cone
     float s = 0.0f;

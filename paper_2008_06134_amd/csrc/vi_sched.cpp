@@ -92,6 +92,7 @@ Scheduler::Key Scheduler::key_of(const vi_request& r) const
     k.res = r.slice_res;
     k.dtype = r.slice_dtype;
     k.layout = r.slice_layout;
+    memcpy(&k.darken, &r.build.darken, 4);
     // the light is part of the identity bit for bit
     memcpy(&k.lx, &r.light_dir[0], 8);
     memcpy(&k.ly, &r.light_dir[1], 8);

@@ -126,11 +126,12 @@ private:
     using clock = std::chrono::steady_clock;
     struct Key {
         int vol_id, n, res, dtype, layout;
+        uint32_t darken;  // build option bits
         uint64_t lx, ly, lz;
         bool operator==(const Key& o) const
         {
             return vol_id == o.vol_id && n == o.n && res == o.res && dtype == o.dtype && layout == o.layout &&
-                   lx == o.lx && ly == o.ly && lz == o.lz;
+                   darken == o.darken && lx == o.lx && ly == o.ly && lz == o.lz;
         }
     };
     struct Stack {

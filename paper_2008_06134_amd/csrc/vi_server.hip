@@ -75,6 +75,8 @@ public:
         vi_slices sl;
         int rc = vi_light_frame(r.light_dir, r.n_slices, r.slice_res, r.slice_dtype, r.slice_layout, &sl);
         if (rc != VI_OK) return rc;
+        if (!(r.build.darken >= 0.0f && r.build.darken <= 64.0f))
+            return fail_msg(VI_E_INVALID_ARG, "darken must be in [0, 64]");
         sl.data = pool_;  // stands in for the cached stack
         sl.vol_n = v.vol.n;
         sl.tag = 0;
@@ -96,7 +98,7 @@ public:
     {
         void* dst = (char*)pool_ + st->offset;
         int rc = vi_build_attenuation(&v.vol, &v.tf, r.light_dir, r.n_slices, r.slice_res, r.slice_dtype,
-                                      r.slice_layout, dst, &st->desc, bs_);
+                                      r.slice_layout, &r.build, dst, &st->desc, bs_);
         if (rc != VI_OK) return rc;
         int h = -1;
         for (size_t i = 0; i < build_events_.size(); ++i)

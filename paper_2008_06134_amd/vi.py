@@ -46,7 +46,11 @@ class Slices_t(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("layout", C.c_int), ("n", C.c_int), ("res", C.c_int),
                 ("L", C.c_double * 3), ("U", C.c_double * 3), ("V", C.c_double * 3), ("c", C.c_double * 3),
                 ("dmin", C.c_double), ("dmax", C.c_double), ("ds", C.c_double), ("R", C.c_double),
-                ("vol_n", C.c_int), ("tag", C.c_uint64)]
+                ("vol_n", C.c_int), ("tag", C.c_uint64), ("darken", C.c_float)]
+
+
+class BuildOpts_t(C.Structure):
+    _fields_ = [("darken", C.c_float)]
 
 
 class Camera_t(C.Structure):
@@ -56,7 +60,8 @@ class Camera_t(C.Structure):
 
 class RenderOpts_t(C.Structure):
     _fields_ = [("ambient", C.c_float), ("light_rgb", C.c_float * 3), ("bg", C.c_float * 4),
-                ("term_eps", C.c_float), ("shell_count", C.c_int), ("shell_h_vox", C.c_float),
+                ("term_eps", C.c_float), ("shell_count", C.c_int), ("shell_w", C.c_float * 8),
+                ("shell_h_vox", C.c_float),
                 ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_float),
                 ("phong_ka", C.c_float), ("phong_kd", C.c_float), ("phong_ks", C.c_float),
                 ("phong_shininess", C.c_float), ("grad_eps", C.c_float)]
@@ -69,7 +74,7 @@ class ServerCfg_t(C.Structure):
 
 class Request_t(C.Structure):
     _fields_ = [("vol_id", C.c_int), ("light_dir", C.c_double * 3), ("n_slices", C.c_int), ("slice_res", C.c_int),
-                ("slice_dtype", C.c_int), ("slice_layout", C.c_int), ("camera", Camera_t), ("mode", C.c_int), ("step_vox", C.c_float),
+                ("slice_dtype", C.c_int), ("slice_layout", C.c_int), ("build", BuildOpts_t), ("camera", Camera_t), ("mode", C.c_int), ("step_vox", C.c_float),
                 ("opts", RenderOpts_t), ("d_rgba", C.c_void_p), ("d_samples", C.c_void_p)]
 
 
@@ -93,7 +98,8 @@ SIGNATURES = {
     "vi_volume_minmax": ([C.POINTER(Volume_t), C.c_int, C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Slices_t)], C.c_int),
     "vi_build_attenuation": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_double), C.c_int, C.c_int,
-                              C.c_int, C.c_int, C.c_void_p, C.POINTER(Slices_t), C.c_void_p], C.c_int),
+                              C.c_int, C.c_int, C.POINTER(BuildOpts_t), C.c_void_p, C.POINTER(Slices_t),
+                              C.c_void_p], C.c_int),
     "vi_render": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(Slices_t), C.POINTER(Camera_t), C.c_int,
                    C.c_float, C.POINTER(RenderOpts_t), C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "vi_tag": ([C.POINTER(Volume_t), C.POINTER(TF_t)], C.c_uint64),
@@ -287,7 +293,8 @@ def default_opts() -> dict:
     o = RenderOpts_t()
     _check(lib().vi_default_render_opts(C.byref(o)))
     return {"ambient": o.ambient, "light_rgb": list(o.light_rgb), "bg": list(o.bg), "term_eps": o.term_eps,
-            "shell_count": o.shell_count, "shell_h_vox": o.shell_h_vox, "cone_rings": o.cone_rings,
+            "shell_count": o.shell_count, "shell_w": list(o.shell_w), "shell_h_vox": o.shell_h_vox,
+            "cone_rings": o.cone_rings,
             "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan,
             **{k: getattr(o, k) for k in _PHONG_KEYS}}
 
@@ -302,6 +309,8 @@ def render_opts(opts: dict | None) -> RenderOpts_t:
     o.bg = (C.c_float * 4)(*d["bg"])
     o.term_eps = d["term_eps"]
     o.shell_count = int(d["shell_count"])
+    w = [float(x) for x in d["shell_w"]] + [0.0] * 8
+    o.shell_w = (C.c_float * 8)(*w[:8])
     o.shell_h_vox = d["shell_h_vox"]
     o.cone_rings = int(d["cone_rings"])
     o.cone_angles = int(d["cone_angles"])
@@ -340,17 +349,19 @@ def light_frame(light_dir, n: int, res: int, dtype: int = VI_F32, layout: int = 
 
 
 def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: int, dtype: int = VI_F32,
-                      out: torch.Tensor | None = None, stream=None, layout: int = VI_STACK_TILED) -> Slices:
+                      out: torch.Tensor | None = None, stream=None, layout: int = VI_STACK_TILED,
+                      darken: float = 0.0) -> Slices:
     """Attenuation stack for `light_dir` (section 3.2.1, Alg. 1); returns the stack
-    (float32 transmittance, or bfloat16 optical depth) and its descriptor."""
+    (float32 transmittance, or bfloat16 optical depth) and its descriptor.  `darken`
+    is the exponent m of section 4's (1+alpha)^m slab compensation (0 = off)."""
     if out is None:
         out = stack_buffer(n_slices, slice_res, dtype, vol.data.device, layout)
     if out.numel() * out.element_size() < slices_bytes(n_slices, slice_res, dtype, layout):
         raise ValueError("stack buffer too small")
     s = Slices_t()
     _check(lib().vi_build_attenuation(C.byref(vol.s), C.byref(tf.s), _vec3(light_dir), int(n_slices),
-                                      int(slice_res), int(dtype), int(layout), C.c_void_p(out.data_ptr()),
-                                      C.byref(s), _stream(stream)))
+                                      int(slice_res), int(dtype), int(layout), C.byref(BuildOpts_t(float(darken))),
+                                      C.c_void_p(out.data_ptr()), C.byref(s), _stream(stream)))
     return Slices(out, s)
 
 
@@ -423,7 +434,7 @@ class Server:
     def submit(self, vol_id: int, light_dir, n_slices: int, slice_res: int, cam: dict, mode: str,
                step_vox: float, opts: dict | None = None, out: torch.Tensor | None = None,
                samples: torch.Tensor | None = None, dtype: int = VI_F32, device="cuda",
-               layout: int = VI_STACK_TILED) -> tuple:
+               layout: int = VI_STACK_TILED, darken: float = 0.0) -> tuple:
         W, H = int(cam["width"]), int(cam["height"])
         if out is None:
             out = torch.empty((H, W, 4), dtype=torch.float32, device=device)
@@ -432,6 +443,7 @@ class Server:
         r.light_dir = _vec3(light_dir)
         r.n_slices, r.slice_res, r.slice_dtype = int(n_slices), int(slice_res), int(dtype)
         r.slice_layout = int(layout)
+        r.build = BuildOpts_t(float(darken))
         r.camera = camera(cam)
         r.mode = MODES[mode]
         r.step_vox = float(step_vox)

@@ -86,11 +86,13 @@ class _Fake:
         self.tf = vi.TF_t(0x20000, K)
 
 
-def _build(f, light=(0, 0, 1), n=8, res=8, dt=vi.VI_F32, buf=0x30000, desc=True, layout=vi.VI_STACK_TILED):
+def _build(f, light=(0, 0, 1), n=8, res=8, dt=vi.VI_F32, buf=0x30000, desc=True, layout=vi.VI_STACK_TILED,
+           darken=None):
     lib = vi.lib()
     s = vi.Slices_t()
+    opts = C.byref(vi.BuildOpts_t(darken)) if darken is not None else None
     return lib.vi_build_attenuation(C.byref(f.vol) if f.vol else None, C.byref(f.tf) if f.tf else None,
-                                    vi._vec3(light), n, res, dt, layout, C.c_void_p(buf),
+                                    vi._vec3(light), n, res, dt, layout, opts, C.c_void_p(buf),
                                     C.byref(s) if desc else None, C.c_void_p(0))
 
 
@@ -110,6 +112,9 @@ def test_build_validation_errors():
     assert _build(_Fake(), buf=0x30002) == -1        # misaligned stack
     assert _build(_Fake(), buf=0x30008) == -1        # stacks are 16-byte aligned
     assert _build(_Fake(), layout=2) == -2           # unknown stack layout
+    assert _build(_Fake(), darken=-1.0) == -1        # compensation exponent out of range
+    assert _build(_Fake(), darken=math.nan) == -1
+    assert _build(_Fake(), darken=65.0) == -1
     assert _build(_Fake(), light=(0, 0, 0)) == -1
     assert _build(_Fake(), dt=vi.VI_U16) == -2
     assert _build(_Fake(), desc=False) == -1
@@ -175,6 +180,8 @@ def test_render_validation_errors():
     assert _render(f, good, mode=3, opts={"cone_grid": 8}) == -1
     assert _render(f, good, mode=3, opts={"cone_rings": 0}) == -1
     assert _render(f, good, mode=3, opts={"cone_angles": 17}) == -1
+    assert _render(f, good, mode=2, opts={"shell_w": [1, -1]}) == -1
+    assert _render(f, good, mode=2, opts={"shell_w": [math.inf]}) == -1
     assert _render(f, good, opts={"ambient": 1.5}) == -1
     assert "ambient" in vi.lib().vi_last_error().decode()
     # Phong: needs a light frame (not a stack), sane coefficients

@@ -361,3 +361,78 @@ def test_row_layout_gives_bitwise_identical_images(dtype, mode):
         st = vi.build_attenuation(vol, tf, light, 45, 77, dtype, layout=lay)
         out.append(gpu_render(vol, tf, st, cam, m, 0.5, extra))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+@pytest.mark.parametrize("darken", [0.5, 1.0, 2.5])
+def test_darkening_compensation_parity(darken):
+    """Section 4's (1+alpha)^m slab compensation in the build, both stack layouts."""
+    w = W.WORKLOADS["small"]
+    raw, tab = w.volume(), w.tf()
+    vol, tf = gpu_inputs(raw, tab)
+    light = w.lights()[0]
+    ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res, darken=darken)
+    S = ost.export()
+    cam = w.camera(W=96, H=80)
+    _, ref, _, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, "shell", w.step_vox, want_full=False)
+    for lay in LAYOUTS:
+        st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res, layout=lay, darken=darken)
+        assert st.s.darken == darken
+        err_s = np.abs(st.dense().cpu().double().numpy() - S).max()
+        img, _ = gpu_render(vol, tf, st, cam, "shell", w.step_vox)
+        err = np.abs(img - ref).max()
+        report(f"darken m={darken} {LNAME[lay]}: stack {err_s:.2e}", err)
+        assert err_s <= TOL_STACK and err <= TOL_IMG
+
+
+def test_darkening_bf16_optical_depth():
+    """bfloat16 optical depth with the compensation: exp(-tau) against the oracle's columns."""
+    w = W.WORKLOADS["medium"]
+    raw, tab = w.volume(), w.tf()
+    vol, tf = gpu_inputs(raw, tab)
+    light = w.lights()[0]
+    st = vi.build_attenuation(vol, tf, light, 64, 128, vi.VI_BF16, layout=vi.VI_STACK_ROWS, darken=1.5)
+    ost = O.Stack(O.Volume(raw), O.TF(tab), light, 64, 128, darken=1.5)
+    rng = np.random.default_rng(3)
+    ij = rng.integers(0, 128, size=(300, 2))
+    tau = st.dense()[:, torch.as_tensor(ij[:, 1], device=DEV), torch.as_tensor(ij[:, 0], device=DEV)]
+    got = np.exp(-tau.float().cpu().double().numpy())
+    want = np.stack([ost.column(i, j) for i, j in ij], axis=1)
+    err = np.abs(got - want).max()
+    report("darken bf16 stack columns", err)
+    assert err < 4e-3
+
+
+@pytest.mark.parametrize("shells,weights", [(2, [1, 0]), (2, [0.25, 1]), (3, [3, 2, 1]), (3, [])])
+def test_weighted_shells_parity(shells, weights):
+    w = W.WORKLOADS["small"]
+    raw, tab = w.volume(), w.tf()
+    vol, tf = gpu_inputs(raw, tab)
+    light = w.lights()[0]
+    ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
+    cam = w.camera(W=96, H=80)
+    opts = {"shell_count": shells, "shell_w": weights}
+    _, ref, _, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, "shell", w.step_vox, opts, want_full=False)
+    for lay in LAYOUTS:
+        st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res, layout=lay)
+        img, _ = gpu_render(vol, tf, st, cam, "shell", w.step_vox, opts)
+        err = np.abs(img - ref).max()
+        report(f"shells {shells} weights {weights} {LNAME[lay]}", err)
+        assert err <= TOL_IMG
+
+
+def test_coloured_light_parity():
+    """Light colour (R17) scales the emission per channel, every gather mode."""
+    w = W.WORKLOADS["small"]
+    raw, tab = w.volume(), w.tf()
+    vol, tf = gpu_inputs(raw, tab)
+    light = w.lights()[0]
+    ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
+    st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res, layout=vi.VI_STACK_ROWS)
+    cam = w.camera(W=80, H=64)
+    opts = {"light_rgb": [1.0, 0.7, 0.35], "ambient": 0.2}
+    for mode in ["shadow", "shell", "cone"]:
+        _, ref, _, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, mode, w.step_vox, opts, want_full=False)
+        img, _ = gpu_render(vol, tf, st, cam, mode, w.step_vox, opts)
+        err = np.abs(img - ref).max()
+        report(f"coloured light {mode}", err)
+        assert err <= TOL_IMG

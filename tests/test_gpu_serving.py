@@ -36,13 +36,14 @@ def _requests(vols, count, seed):
         w, h = sizes[int(rng.integers(len(sizes)))]
         cam = W.camera_orbit(w, h, float(rng.uniform(0, 2 * math.pi)), math.radians(20))
         mode = ["shell", "cone", "cone5", "shadow", "phong"][int(rng.integers(5))]
-        reqs.append(dict(vol=vi_, light=light, n=N, res=min(2 * N, 1024), cam=cam, mode=mode))
+        darken = 1.0 if li == 2 else 0.0          # the compensated build is part of a stack's identity
+        reqs.append(dict(vol=vi_, light=light, n=N, res=min(2 * N, 1024), cam=cam, mode=mode, darken=darken))
     return reqs
 
 
 def _alone(vols, r, layout=vi.VI_STACK_TILED):
     _, v, tf = vols[r["vol"]]
-    st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"], layout=layout)
+    st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"], layout=layout, darken=r["darken"])
     m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
     cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
     img = vi.render(v, tf, st, r["cam"], m, 0.5, extra, samples=cnt)
@@ -53,7 +54,7 @@ def _alone(vols, r, layout=vi.VI_STACK_TILED):
 def _submit(srv, ids, r, samples=None, layout=vi.VI_STACK_TILED):
     m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
     return srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], m, 0.5, extra, samples=samples,
-                      layout=layout)
+                      layout=layout, darken=r["darken"])
 
 
 @pytest.mark.parametrize("layout", [vi.VI_STACK_TILED, vi.VI_STACK_ROWS])

@@ -525,3 +525,70 @@ def test_p11_phong_sphere_lit_side_brighter():
     full, _, _, _ = O.render(vol, tf, st, cam, "phong", 0.5, {"phong_ks": 0.0}, want_full=True)
     lum = full[..., :3].sum(-1)
     assert lum[12:20, 7:11].mean() > 1.5 * lum[12:20, 21:25].mean()
+
+
+# ------------------------------------------------------------------ P12 slab compensation (1+alpha)^m (section 4)
+
+def _slab_medium(N=16, value=100):
+    raw = np.zeros((N, N, N), np.uint8)
+    raw[2:N - 2, 2:N - 2, 2:N - 2] = value
+    return raw
+
+
+def test_p12_darkening_m1_is_one_minus_alpha_squared():
+    """m = 1: every slab passes (1-alpha)(1+alpha) = 1 - alpha^2 of the light, so along an axis
+    light through a constant medium the column is (1 - alpha_s^2)^k (alpha_s the slab opacity)."""
+    N, a0 = 16, 0.1
+    vol, tf = O.Volume(_slab_medium(N)), _tf_zero_then([1, 1, 1, a0])
+    n, res = 32, 16                                   # ds = half a voxel along z
+    st = O.Stack(vol, tf, [0, 0, 1], n, res, darken=1.0)
+    plain = O.Stack(vol, tf, [0, 0, 1], n, res)
+    a_s = 1 - (1 - a0) ** 0.5
+    col, ref = st.column(res // 2, res // 2), plain.column(res // 2, res // 2)
+    # slabs whose midpoints sample the interior plateau (voxel centres 2.5 .. N-3.5 away from edges)
+    inside = [k for k in range(n) if 3.0 <= (k + 0.5) * N / n <= N - 3.0]
+    for k0, k1 in zip(inside[:-1], inside[1:]):
+        np.testing.assert_allclose(col[k1] / col[k0], 1 - a_s ** 2, rtol=1e-12)
+        np.testing.assert_allclose(ref[k1] / ref[k0], 1 - a_s, rtol=1e-12)
+
+
+def test_p12_darkening_large_m_caps_every_slab_at_one():
+    """(1-alpha)(1+alpha)^3 > 1 for alpha < 0.5...: with the cap no slab attenuates, stack == 1."""
+    vol, tf = O.Volume(_slab_medium()), _tf_zero_then([1, 1, 1, 0.05])
+    st = O.Stack(vol, tf, [0.3, -0.2, 1], 12, 10, darken=3.0)
+    assert np.all(st.export() == 1.0)
+
+
+def test_p12_darkening_is_monotone_in_m():
+    w = W.WORKLOADS["small"]
+    vol, tf = O.Volume(w.volume()), O.TF(w.tf())
+    cols = []
+    for m in (0.0, 0.5, 1.0, 2.0):
+        st = O.Stack(vol, tf, w.lights()[0], 16, 24, darken=m)
+        cols.append(st.export())
+    for a, b in zip(cols[:-1], cols[1:]):
+        assert np.all(b >= a)                          # more compensation never darkens
+        assert np.all(np.diff(b, axis=0) <= 0)         # and the stack stays monotone along the light
+
+
+# ------------------------------------------------------------------ P13 weighted shells (section 3.2.3)
+
+def test_p13_shell_weights_reduce_to_single_shells():
+    """Two shells with weights (1, 0) are the one-voxel shell; (0, 1) is the two-voxel shell,
+    i.e. one shell at twice the step; (1, 1) equals the default equal weights exactly."""
+    w = W.WORKLOADS["small"]
+    vol, tf = O.Volume(w.volume()), O.TF(w.tf())
+    st = O.Stack(vol, tf, w.lights()[0], w.n_slices, w.res)
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        p = rng.uniform(0.2, 0.8, 3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        one = st.coefficient("shell", p, d, {"shell_count": 1})
+        two = st.coefficient("shell", p, d, {"shell_count": 1, "shell_h_vox": 2.0})
+        assert st.coefficient("shell", p, d, {"shell_count": 2, "shell_w": [1, 0]}) == one
+        assert st.coefficient("shell", p, d, {"shell_count": 2, "shell_w": [0, 1]}) == two
+        eq = st.coefficient("shell", p, d, {"shell_count": 2})
+        assert st.coefficient("shell", p, d, {"shell_count": 2, "shell_w": [1, 1]}) == eq
+        assert st.coefficient("shell", p, d, {"shell_count": 2, "shell_w": [3, 1]}) == pytest.approx(
+            (3 * one + two) / 4, abs=1e-15)
