@@ -374,6 +374,9 @@ def test_darkening_compensation_parity(darken):
     S = ost.export()
     cam = w.camera(W=96, H=80)
     _, ref, _, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, "shell", w.step_vox, want_full=False)
+    plain = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
+    _, ref0, _, _ = O.render(O.Volume(raw), O.TF(tab), plain, cam, "shell", w.step_vox, want_full=False)
+    assert np.abs(ref - ref0).max() > 1e-2            # the option visibly changes the image
     for lay in LAYOUTS:
         st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res, layout=lay, darken=darken)
         assert st.s.darken == darken
@@ -412,6 +415,9 @@ def test_weighted_shells_parity(shells, weights):
     cam = w.camera(W=96, H=80)
     opts = {"shell_count": shells, "shell_w": weights}
     _, ref, _, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, "shell", w.step_vox, opts, want_full=False)
+    _, ref1, _, _ = O.render(O.Volume(raw), O.TF(tab), ost, cam, "shell", w.step_vox, want_full=False)
+    if weights != [1, 0]:                              # (1, 0) is the one-voxel shell itself
+        assert np.abs(ref - ref1).max() > 1e-2
     for lay in LAYOUTS:
         st = vi.build_attenuation(vol, tf, light, w.n_slices, w.res, layout=lay)
         img, _ = gpu_render(vol, tf, st, cam, "shell", w.step_vox, opts)
