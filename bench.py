@@ -36,14 +36,15 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
                   "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
 MEASURED_TRAFFIC = {
-    # large workload (512^3 u16 bricks, 512 x 1024^2 f32 stack in rows, 1920x1080), light 0
-    ("render_cone", "large", "rows"): {
+    # large workload (512^3 u16 bricks, 8^3 empty-space cells, 512 x 1024^2 f32 stack in rows,
+    # 1920x1080), light 0
+    ("render_cone", "large", "rows", 8): {
         "sha256": "72f4529198a92a2726b306de161297a5e0deccce9ead6d7a4c1077fadb1ba0fd",
         "fetch_kib": 80126.4, "write_kib": 34760.0},
-    ("render_shell", "large", "rows"): {
+    ("render_shell", "large", "rows", 8): {
         "sha256": "72f4529198a92a2726b306de161297a5e0deccce9ead6d7a4c1077fadb1ba0fd",
         "fetch_kib": 69641.1, "write_kib": 34455.8},
-    ("build", "large", "rows"): {
+    ("build", "large", "rows", 8): {
         "sha256": "151b298ec9450e7b5a40f1d2391086f68db8adf02260044d9744db6451b625f3",
         "fetch_kib": 60659.8, "write_kib": 2315410.0},
 }
@@ -58,9 +59,9 @@ def source_sha(kind: str) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, layout: str):
+def measured_traffic(kernel: str, workload: str, layout: str, cell: int):
     """HBM bytes per launch of `kernel` on `workload`, or None (not measured for these sources)."""
-    m = MEASURED_TRAFFIC.get((kernel, workload, layout))
+    m = MEASURED_TRAFFIC.get((kernel, workload, layout, cell))
     kind = "build" if kernel == "build" else "render"
     if not m or m["sha256"] != source_sha(kind):
         return None
@@ -200,7 +201,7 @@ def serving_inputs(vol_sizes, dev, vessels=True):
     vols = []
     for i, N in enumerate(vol_sizes):
         raw = W.serving_volume(N, i, vessels=vessels)
-        vols.append((vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(8), vi.TF.from_numpy(tab, dev)))
+        vols.append((vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(16), vi.TF.from_numpy(tab, dev)))
     return vols
 
 
@@ -257,7 +258,7 @@ def scaling_sweep(dev, slices=(64, 128, 256, 512), resolutions=(128, 256, 512, 1
     from paper_2008_06134_amd import workloads as W
     w = W.WORKLOADS["large"]
     raw, tab = w.volume(), w.tf()
-    vol = vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(8)
+    vol = vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(16)
     tf = vi.TF.from_numpy(tab, dev)
     light, cam = w.lights()[0], w.camera(0)
     img = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device=dev)
@@ -304,7 +305,7 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     tf = vi.TF.from_numpy(tab, dev)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    vol = vol_lin.to_bricks().with_minmax(8)  # one-off per volume: bricks + empty-space map
+    vol = vol_lin.to_bricks().with_minmax(args.cell)  # one-off per volume: bricks + empty-space map
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - tb) * 1e3
     del vol_lin
@@ -366,6 +367,8 @@ def main():
                     help="only run the slab-count x slice-resolution sweep (build and frame times)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
+    ap.add_argument("--cell", type=int, default=16, choices=[4, 8, 16, 32],
+                    help="edge in voxels of the empty-space map's cells")
     ap.add_argument("--stack-layout", default="rows", choices=["tiled", "rows"],
                     help="stack layout of every stack built (rows: one 8-byte load per bilinear row)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -436,7 +439,7 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(dom, w.name, args.stack_layout),
+                "traffic": measured_traffic(dom, w.name, args.stack_layout, args.cell),
                 "bytes_per_launch": per_launch, "avg_launch_ms": round(float(avg_ms), 4)}
     kernels = {"volume_prepare_ms_once": round(m["prep_ms"], 3),
                "build_ms_mean": round(float(np.mean(build_ms)), 4),
@@ -461,7 +464,7 @@ def main():
         "data": "synthetic",
         "fps": round(frames / wall, 3),
         "config": {"workload": (f"{w.name}: {w.N}^3 {'f16' if precision else raw.dtype} phantom "
-                                f"(4x4x4 bricks, 8^3 empty-space cells), "
+                                f"(4x4x4 bricks, {args.cell}^3 empty-space cells), "
                                 f"{w.n_slices} slices x {w.res}^2 {'bf16' if precision else 'f32'} "
                                 f"({args.stack_layout}), "
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "

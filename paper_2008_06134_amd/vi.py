@@ -199,7 +199,7 @@ class Volume:
         _check(lib().vi_volume_to_bricks(C.byref(self.s), C.c_void_p(out.data_ptr()), C.byref(res), _stream(stream)))
         return Volume(out, self.scale, self.n, VI_LAYOUT_BRICK4)
 
-    def with_minmax(self, cell: int = 8, out: torch.Tensor | None = None, stream=None) -> "Volume":
+    def with_minmax(self, cell: int = 16, out: torch.Tensor | None = None, stream=None) -> "Volume":
         """The same volume with an empty-space map of `cell`^3-voxel cells (vi_volume_minmax)."""
         nbytes = int(lib().vi_volume_minmax_bytes(self.n, cell))
         if nbytes == 0:

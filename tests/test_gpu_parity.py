@@ -30,9 +30,9 @@ def _mode(m):
     return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
 
 
-def gpu_inputs(raw, tab, scale=None, bricks=True, cell=8):
+def gpu_inputs(raw, tab, scale=None, bricks=True, cell=16):
     """Device volume -- by default as the benchmark runs it: 4x4x4 bricks with an
-    empty-space map of 8^3-voxel cells -- and TF."""
+    empty-space map of 16^3-voxel cells -- and TF."""
     vol = vi.Volume.from_numpy(raw, DEV, scale)
     if bricks:
         vol = vol.to_bricks()
@@ -285,7 +285,7 @@ def test_bricked_volume_gives_bitwise_identical_results(N, n, res, mode):
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("cell", [4, 8, 32])
+@pytest.mark.parametrize("cell", [4, 8, 16, 32])
 @pytest.mark.parametrize("mode", ["shell", "cone5", "none"])
 def test_empty_space_map_changes_nothing(cell, mode):
     """Skipping zero-opacity cells must give bit-identical stacks, images and counts."""

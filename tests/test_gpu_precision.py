@@ -35,7 +35,7 @@ def _phantom(N):
 def _precision_case(N, n, res, cam, light, mode, opts, pix, layout=vi.VI_STACK_ROWS):
     raw, f16 = _phantom(N)
     tab = W.tf_ct()
-    vol = vi.Volume.from_numpy(f16, DEV, 1.0).to_bricks().with_minmax(8)
+    vol = vi.Volume.from_numpy(f16, DEV, 1.0).to_bricks().with_minmax(16)
     tf = vi.TF.from_numpy(tab, DEV)
     st = vi.build_attenuation(vol, tf, light, n, res, vi.VI_BF16, layout=layout)
     img = vi.render(vol, tf, st, cam, mode, 0.5, opts)
