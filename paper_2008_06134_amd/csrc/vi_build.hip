@@ -22,51 +22,41 @@ namespace vi {
 // tiled layout, whose 8 x 4 tiles a wave then writes whole; 64 x 4 (waves of
 // one 64-texel row segment) for the row layout, so every slab store of a
 // wave is one contiguous 256-byte run.
-#ifndef VI_BUILD_ROW_RUN
-#define VI_BUILD_ROW_RUN 64
+#ifndef VI_BUILD_ROWS_X
+#define VI_BUILD_ROWS_X 64
 #endif
 template <int SL> struct BuildBlock { static constexpr int X = 16, Y = 16, WX = 16; };
 template <> struct BuildBlock<VI_STACK_ROWS> {
-    static constexpr int WX = VI_BUILD_ROW_RUN;       // texels of a row per wave
-    static constexpr int X = WX, Y = 4 * (64 / WX);
+    static constexpr int WX = 64;                     // a wave: one 64-texel row run
+    static constexpr int X = VI_BUILD_ROWS_X, Y = 4 * 64 / VI_BUILD_ROWS_X;
 };
 
-// Row layout: a lane stores its own texel and, on the edge of the grid, the
-// fully transmitting border texels next to it (the corners by the corner
-// lanes).
-// stack stores: streamed past the caches (the render reads the stack long
-// after the build has moved on)
+// Row layout: the texels of the one-texel border around the grid are the
+// same in every layer (fully transmitting: T = 1, optical depth 0), so a
+// separate small kernel writes them and the slab loop stores only its own
+// texel.  One lane per border texel and layer: rows -1 and res (res+2 texels
+// each), then columns -1 and res of rows 0..res-1.
 template <typename ET>
-__device__ __forceinline__ void put(ET* p, ET v)
+__global__ __launch_bounds__(256) void border_kernel(ET* __restrict__ out, int n, int res, uint32_t rlayer,
+                                                     uint32_t rpitch, uint32_t rorg, ET one)
 {
-#ifdef VI_BUILD_NT
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    const uint32_t per_layer = 2u * (uint32_t)(res + 2) + 2u * (uint32_t)res;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)per_layer * (size_t)n) return;
+    const uint32_t k = (uint32_t)(t / per_layer), q = (uint32_t)(t % per_layer);
+    int row, col;  // grid texel coordinates in [-1, res]
+    if (q < 2u * (uint32_t)(res + 2)) {
+        row = q < (uint32_t)(res + 2) ? -1 : res;
+        col = (int)(q % (uint32_t)(res + 2)) - 1;
+    } else {
+        const uint32_t r = q - 2u * (uint32_t)(res + 2);
+        row = (int)(r >> 1);
+        col = (r & 1u) ? res : -1;
+    }
+    out[(size_t)k * rlayer + (uint32_t)(row + 1) * rpitch + rorg + col] = one;
 }
 
-template <typename ET>
-__device__ __forceinline__ void put_rows(ET* __restrict__ out, const BuildParams& P, int k, int i, int j, ET v,
-                                         ET one)
-{
-    const int r = P.res;
-    // texel (i, j) of this layer at row j+1, column rorg+i
-    ET* L = out + (size_t)k * P.rlayer + P.rorg;
-    const uint32_t row = (uint32_t)(j + 1) * P.rpitch, last = (uint32_t)(r + 1) * P.rpitch;
-    put(L + row + i, v);
-    const bool lo_i = i == 0, hi_i = i == r - 1, lo_j = j == 0, hi_j = j == r - 1;
-    if (lo_i) L[row - 1] = one;
-    if (hi_i) L[row + r] = one;
-    if (lo_j) L[i] = one;
-    if (hi_j) L[last + i] = one;
-    if (lo_i && lo_j) L[-1] = one;
-    if (hi_i && lo_j) L[r] = one;
-    if (lo_i && hi_j) L[last - 1] = one;
-    if (hi_i && hi_j) L[last + r] = one;
-}
-
-template <typename VT, int LAYOUT, int OUT_DTYPE, int SL>
+template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool DARKEN>
 __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 {
     extern __shared__ float s_alpha[];  // K alphas, then K next-opaque indices
@@ -80,9 +70,10 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     uint32_t tx, ty;
     if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int WX = BuildBlock<SL>::WX, WY = 64 / WX;  // wave footprint
-    const int i = (int)tx * BX + lane % WX;
-    const int j = (int)ty * BY + wave * WY + lane / WX;
+    // wave footprint WX x WY; the block's waves are laid out along x first
+    constexpr int WX = BuildBlock<SL>::WX, WY = 64 / WX, NWX = BX / WX;
+    const int i = (int)tx * BX + (wave % NWX) * WX + lane % WX;
+    const int j = (int)ty * BY + (wave / NWX) * WY + lane / WX;
     if (i >= P.res || j >= P.res) return;
 
     // column base (slab 0 midpoint) in offset-voxel coordinates, in double
@@ -93,25 +84,24 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     const VT* __restrict__ vol = (const VT*)P.vol;
     const VolIndex VI_ = {1u, P.vsy, P.vsz};
     const float Km1 = (float)(P.K - 1);
-    const size_t layer = P.layer;
-    const size_t col = stack_oj(j, P.row_tiles32) + stack_oi(i);
+    // this column's texel in layer 0, and the layer stride (elements)
+    const size_t layer = SL == VI_STACK_ROWS ? (size_t)P.rlayer : (size_t)P.layer;
+    size_t at = SL == VI_STACK_ROWS ? (size_t)(j + 1) * P.rpitch + P.rorg + i
+                                    : (size_t)(stack_oj(j, P.row_tiles32) + stack_oi(i));
     float T = 1.0f;     // transmittance (F32 form)
     float tau = 0.0f;   // optical depth (BF16 form)
     const float ln2 = 0.69314718055994531f;
     uint32_t last_cell = 0xffffffffu;
     bool cell_is_empty = false;
 
-#ifdef VI_BUILD_UNROLL
-#pragma unroll VI_BUILD_UNROLL
-#endif
-    for (int k = 0; k < P.n; ++k) {
+    for (int k = 0; k < P.n; ++k, at += layer) {
         const float kf = (float)k;
         const float hx = fmaf(kf, P.AL[0], hx0);
         const float hy = fmaf(kf, P.AL[1], hy0);
         const float hz = fmaf(kf, P.AL[2], hz0);
         // log2 of the slab's (1 - alpha)/e, 0 outside the cube (empty)
         float l2 = 0.0f;
-        bool fetch = hx >= P.lo && hx <= P.hi && hy >= P.lo && hy <= P.hi && hz >= P.lo && hz <= P.hi;
+        bool fetch = (hx >= P.lo) & (hx <= P.hi) & (hy >= P.lo) & (hy <= P.hi) & (hz >= P.lo) & (hz <= P.hi);
         if (fetch && P.occ.mm) {
             // empty-space map: a zero-opacity cell leaves T unchanged exactly
             const uint32_t c = cell_of((int)floorf(hx) + P.M, (int)floorf(hy) + P.M, (int)floorf(hz) + P.M, P.N,
@@ -134,26 +124,27 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
             // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
             float f = fast_exp2(P.e * l2);
             // section 4 compensation: times (1 + alpha)^m, at most 1
-            if (P.darken > 0.0f) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
+            if (DARKEN) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
             T *= f;
-            if (SL == VI_STACK_ROWS) {
-                put_rows((float*)P.out, P, k, i, j, T, 1.0f);
-            } else {
-                put((float*)P.out + (size_t)k * layer + col, T);
-            }
+            ((float*)P.out)[at] = T;
         } else {
             // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
             // compensation subtracts m ln(1 + alpha), floored at 0
             float dtau = -P.e * ln2 * l2;
-            if (P.darken > 0.0f) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(P.e * l2)), 0.0f);
+            if (DARKEN) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(P.e * l2)), 0.0f);
             tau += fminf(dtau, 64.0f);
-            if (SL == VI_STACK_ROWS) {
-                put_rows((uint16_t*)P.out, P, k, i, j, f32_to_bf16(tau), (uint16_t)0);
-            } else {
-                put((uint16_t*)P.out + (size_t)k * layer + col, f32_to_bf16(tau));
-            }
+            ((uint16_t*)P.out)[at] = f32_to_bf16(tau);
         }
     }
+}
+
+template <typename VT, int LAYOUT, int SL, bool DARKEN>
+static void launch_build_k(const BuildParams& p, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (p.out_dtype == VI_F32)
+        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, SL, DARKEN>), grid, dim3(256), lds, s, p);
+    else
+        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, SL, DARKEN>), grid, dim3(256), lds, s, p);
 }
 
 template <typename VT, int LAYOUT>
@@ -162,14 +153,24 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
     const bool rows = p.out_layout == VI_STACK_ROWS;
     const uint32_t bx = rows ? BuildBlock<VI_STACK_ROWS>::X : BuildBlock<VI_STACK_TILED>::X;
     const uint32_t by = rows ? BuildBlock<VI_STACK_ROWS>::Y : BuildBlock<VI_STACK_TILED>::Y;
-    dim3 grid(supertile_grid(((uint32_t)p.res + bx - 1) / bx, ((uint32_t)p.res + by - 1) / by)), block(256);
+    const dim3 grid(supertile_grid(((uint32_t)p.res + bx - 1) / bx, ((uint32_t)p.res + by - 1) / by));
     const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K;
-    if (p.out_dtype == VI_F32) {
-        if (rows) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_ROWS>), grid, block, lds, s, p);
-        else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, VI_STACK_TILED>), grid, block, lds, s, p);
+    const bool dk = p.darken > 0.0f;
+    if (rows) {
+        if (dk) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds, s);
+        else launch_build_k<VT, LAYOUT, VI_STACK_ROWS, false>(p, grid, lds, s);
+        // the border, the same in every layer
+        const size_t nb = (2u * (size_t)(p.res + 2) + 2u * (size_t)p.res) * (size_t)p.n;
+        const dim3 bgrid((uint32_t)((nb + 255) / 256));
+        if (p.out_dtype == VI_F32)
+            hipLaunchKernelGGL((border_kernel<float>), bgrid, dim3(256), 0, s, (float*)p.out, p.n, p.res, p.rlayer,
+                               p.rpitch, p.rorg, 1.0f);
+        else
+            hipLaunchKernelGGL((border_kernel<uint16_t>), bgrid, dim3(256), 0, s, (uint16_t*)p.out, p.n, p.res,
+                               p.rlayer, p.rpitch, p.rorg, (uint16_t)0);
     } else {
-        if (rows) hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>), grid, block, lds, s, p);
-        else hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, VI_STACK_TILED>), grid, block, lds, s, p);
+        if (dk) launch_build_k<VT, LAYOUT, VI_STACK_TILED, true>(p, grid, lds, s);
+        else launch_build_k<VT, LAYOUT, VI_STACK_TILED, false>(p, grid, lds, s);
     }
     return hipGetLastError();
 }
