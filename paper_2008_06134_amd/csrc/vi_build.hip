@@ -118,37 +118,67 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         const int m = min(kStage, P.n - k0);
         for (int kk = 0; kk < m; ++kk) {
             const float kf = (float)(k0 + kk);
+            // The lane's columns are fetched together under wave-uniform
+            // branches (a divergent branch per column would serialise their
+            // memory round trips): map entries where a lane enters a new
+            // cell, then the trilinear footprints of every column whenever
+            // any lane of the wave has a slab with opacity.
+            float hx[CPL], hy[CPL], hz[CPL], l2[CPL];
+            bool fetch[CPL], enter[CPL];
+            uint32_t cell[CPL];
+            bool any_enter = false;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const float hx = fmaf(kf, P.AL[0], hx0[c]);
-                const float hy = fmaf(kf, P.AL[1], hy0[c]);
-                const float hz = fmaf(kf, P.AL[2], hz0[c]);
-                // log2 of the slab's (1 - alpha)/e, 0 outside the cube (empty)
-                float l2 = 0.0f;
-                bool fetch =
-                    (hx >= P.lo) & (hx <= P.hi) & (hy >= P.lo) & (hy <= P.hi) & (hz >= P.lo) & (hz <= P.hi);
-                if (fetch && P.occ.mm) {
-                    // empty-space map: a zero-opacity cell leaves T unchanged exactly
-                    const uint32_t cc = cell_of((int)floorf(hx) + P.M, (int)floorf(hy) + P.M,
-                                                (int)floorf(hz) + P.M, P.N, P.occ.shift, P.occ.nc);
-                    if (cc != last_cell[c]) {
-                        last_cell[c] = cc;
-                        cell_is_empty[c] = cell_empty(P.occ.mm[cc], s_next, Km1, P.K);
+                hx[c] = fmaf(kf, P.AL[0], hx0[c]);
+                hy[c] = fmaf(kf, P.AL[1], hy0[c]);
+                hz[c] = fmaf(kf, P.AL[2], hz0[c]);
+                l2[c] = 0.0f;  // log2 of the slab's (1 - alpha)/e: 0 outside the cube or in empty cells
+                fetch[c] = (hx[c] >= P.lo) & (hx[c] <= P.hi) & (hy[c] >= P.lo) & (hy[c] <= P.hi) &
+                           (hz[c] >= P.lo) & (hz[c] <= P.hi);
+                cell[c] = cell_of((int)floorf(hx[c]) + P.M, (int)floorf(hy[c]) + P.M, (int)floorf(hz[c]) + P.M,
+                                  P.N, P.occ.shift, P.occ.nc);
+                enter[c] = P.occ.mm && fetch[c] && cell[c] != last_cell[c];
+                any_enter |= enter[c];
+            }
+            if (__ballot(any_enter)) {
+                float2 mm[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    if (enter[c]) mm[c] = P.occ.mm[cell[c]];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    if (enter[c]) {
+                        last_cell[c] = cell[c];
+                        cell_is_empty[c] = cell_empty(mm[c], s_next, Km1, P.K);
                     }
-                    fetch = !cell_is_empty[c];
-                }
-                if (fetch) {
-                    const float v = sample_volume<VT, LAYOUT>(vol, VI_, P.N, P.M, P.scale, hx, hy, hz);
-                    const float x = v * Km1;
+            }
+            bool any_fetch = false;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                // an empty-space cell leaves T unchanged exactly
+                fetch[c] = fetch[c] && !(P.occ.mm && cell_is_empty[c]);
+                any_fetch |= fetch[c];
+            }
+            if (__ballot(any_fetch)) {
+                float v[CPL];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)  // clamped addresses: safe for every lane
+                    v[c] = sample_volume<VT, LAYOUT>(vol, VI_, P.N, P.M, P.scale, hx[c], hy[c], hz[c]);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const float x = v[c] * Km1;
                     const int e0 = min((int)x, P.K - 2);
                     const float w = x - (float)e0;
                     const float a = fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]);
-                    l2 = fast_log2(fmaxf(1.0f - a, 0.0f));  // -inf for a = 1
+                    if (fetch[c]) l2[c] = fast_log2(fmaxf(1.0f - a, 0.0f));  // -inf for a = 1
                 }
+            }
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
                 float out;
                 if (OUT_DTYPE == VI_F32) {
                     // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
-                    float f = fast_exp2(P.e * l2);
+                    float f = fast_exp2(P.e * l2[c]);
                     // section 4 compensation: times (1 + alpha)^m, at most 1
                     if (DARKEN) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
                     T[c] *= f;
@@ -156,8 +186,9 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
                 } else {
                     // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
                     // compensation subtracts m ln(1 + alpha), floored at 0
-                    float dtau = -P.e * ln2 * l2;
-                    if (DARKEN) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(P.e * l2)), 0.0f);
+                    float dtau = -P.e * ln2 * l2[c];
+                    if (DARKEN)
+                        dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(P.e * l2[c])), 0.0f);
                     tau[c] += fminf(dtau, 64.0f);
                     out = tau[c];
                 }
