@@ -36,17 +36,17 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
                   "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
 MEASURED_TRAFFIC = {
-    # large workload (512^3 u16 bricks, 8^3 empty-space cells, 512 x 1024^2 f32 stack in rows,
+    # large workload (512^3 u16 bricks, 16^3 empty-space cells, 512 x 1024^2 f32 stack in rows,
     # 1920x1080), light 0
-    ("render_cone", "large", "rows", 8): {
-        "sha256": "72f4529198a92a2726b306de161297a5e0deccce9ead6d7a4c1077fadb1ba0fd",
-        "fetch_kib": 80126.4, "write_kib": 34760.0},
-    ("render_shell", "large", "rows", 8): {
-        "sha256": "72f4529198a92a2726b306de161297a5e0deccce9ead6d7a4c1077fadb1ba0fd",
-        "fetch_kib": 69641.1, "write_kib": 34455.8},
-    ("build", "large", "rows", 8): {
-        "sha256": "151b298ec9450e7b5a40f1d2391086f68db8adf02260044d9744db6451b625f3",
-        "fetch_kib": 60659.8, "write_kib": 2315410.0},
+    ("render_cone", "large", "rows", 16): {
+        "sha256": "6769d7258d3a31ea75d89aaa88b936dcc4305607624ea41118415bb390caf52e",
+        "fetch_kib": 79213.56, "write_kib": 34595.28},
+    ("render_shell", "large", "rows", 16): {
+        "sha256": "6769d7258d3a31ea75d89aaa88b936dcc4305607624ea41118415bb390caf52e",
+        "fetch_kib": 69020.25, "write_kib": 34372.16},
+    ("build", "large", "rows", 16): {       # build kernel plus the border kernel
+        "sha256": "d7066d6d9d8ab3ab47dcdaf7d025d4cefd0a4c3065c4891b7838a955a1308c36",
+        "fetch_kib": 67545.19 + 17.5, "write_kib": 2335480.0 + 28952.75},
 }
 
 
