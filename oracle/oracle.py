@@ -54,7 +54,8 @@ class _TF(C.Structure):
 class _Frame(C.Structure):
     _fields_ = [("L", C.c_double * 3), ("U", C.c_double * 3), ("V", C.c_double * 3), ("c", C.c_double * 3),
                 ("dmin", C.c_double), ("dmax", C.c_double), ("ds", C.c_double), ("R", C.c_double),
-                ("n", C.c_int), ("res", C.c_int), ("darken", C.c_double)]
+                ("n", C.c_int), ("res", C.c_int), ("darken", C.c_double), ("positional", C.c_int),
+                ("P", C.c_double * 3)]
 
 
 class _Camera(C.Structure):
@@ -84,6 +85,7 @@ def _load():
         lib.vio_default_opts.argtypes = [P(_Opts)]
         lib.vio_threads.restype = C.c_int
         lib.vio_light_frame.argtypes = [P(C.c_double), C.c_int, C.c_int, P(_Frame)]
+        lib.vio_light_frame_point.argtypes = [P(C.c_double), C.c_int, C.c_int, P(_Frame)]
         lib.vio_volume_sample.argtypes = [P(_Volume), P(C.c_double)]
         lib.vio_volume_sample.restype = C.c_double
         lib.vio_tf_lookup.argtypes = [P(_TF), C.c_double, P(C.c_double)]
@@ -183,13 +185,19 @@ class TF:
         self._s = _TF(_dptr(self.rgba), self.rgba.shape[0])
 
 
-def light_frame(l, n: int, res: int) -> dict:
+def light_frame(l, n: int, res: int, position=None) -> dict:
+    """Light frame of a directional light `l` (propagation direction), or of a
+    point light at `position` (then `l` is ignored)."""
     f = _Frame()
-    rc = _load().vio_light_frame((C.c_double * 3)(*[float(t) for t in l]), n, res, C.byref(f))
+    if position is None:
+        rc = _load().vio_light_frame((C.c_double * 3)(*[float(t) for t in l]), n, res, C.byref(f))
+    else:
+        rc = _load().vio_light_frame_point((C.c_double * 3)(*[float(t) for t in position]), n, res, C.byref(f))
     if rc != 0:
         raise ValueError("invalid light frame arguments")
     return {"L": np.array(f.L), "U": np.array(f.U), "V": np.array(f.V), "c": np.array(f.c), "dmin": f.dmin,
-            "dmax": f.dmax, "ds": f.ds, "R": f.R, "n": f.n, "res": f.res, "_s": f}
+            "dmax": f.dmax, "ds": f.ds, "R": f.R, "n": f.n, "res": f.res, "positional": f.positional,
+            "P": np.array(f.P), "_s": f}
 
 
 def volume_sample(vol: Volume, p) -> float:
@@ -223,9 +231,9 @@ def segment_alpha(a: float, length: float, dref: float) -> float:
 class Stack:
     """Attenuation stack S[k][j][i] (Alg. 1), columns built on first use."""
 
-    def __init__(self, vol: Volume, tf: TF, light, n: int, res: int, darken: float = 0.0):
+    def __init__(self, vol: Volume, tf: TF, light, n: int, res: int, darken: float = 0.0, position=None):
         self.vol, self.tf = vol, tf  # keep the buffers alive
-        self.frame = light_frame(light, n, res)
+        self.frame = light_frame(light, n, res, position)
         self.frame["_s"].darken = float(darken)
         self.n, self.res = n, res
         self._p = _load().vio_stack_create(C.byref(vol._s), C.byref(tf._s), C.byref(self.frame["_s"]))

@@ -82,6 +82,22 @@ void vio_default_opts(vio_opts* o)
 /* R4 (L is the propagation direction), R9 (orthographic light square of */
 /* half-width sqrt(3)/2 about the cube centre), R10 (basis choice).      */
 /* ------------------------------------------------------------------ */
+/* R10: seed the plane basis with the coordinate axis least aligned with
+ * L (ties to the lowest index), Gram-Schmidt it against L. */
+static void plane_basis(vio_frame* f)
+{
+    int js = 0;
+    for (int a = 1; a < 3; ++a)
+        if (fabs(f->L[a]) < fabs(f->L[js])) js = a;
+    double e[3] = {0.0, 0.0, 0.0};
+    e[js] = 1.0;
+    double el = dot3(e, f->L);
+    double u[3] = {e[0] - el * f->L[0], e[1] - el * f->L[1], e[2] - el * f->L[2]};
+    double nu = norm3(u);
+    for (int a = 0; a < 3; ++a) f->U[a] = u[a] / nu;
+    cross3(f->L, f->U, f->V);
+}
+
 int vio_light_frame(const double l[3], int n, int res, vio_frame* f)
 {
     double nl = norm3(l);
@@ -89,6 +105,8 @@ int vio_light_frame(const double l[3], int n, int res, vio_frame* f)
     for (int a = 0; a < 3; ++a) f->L[a] = l[a] / nl;
     f->c[0] = f->c[1] = f->c[2] = 0.5;
     f->darken = 0.0;
+    f->positional = 0;
+    f->P[0] = f->P[1] = f->P[2] = 0.0;
 
     /* Eq. 8: distances of the eight unit-cube vertices along L */
     f->dmin = INFINITY;
@@ -103,21 +121,48 @@ int vio_light_frame(const double l[3], int n, int res, vio_frame* f)
     f->res = res;
     f->ds = (f->dmax - f->dmin) / n;
 
-    /* R10: seed the plane basis with the coordinate axis least aligned
-     * with L (ties to the lowest index), Gram-Schmidt it against L. */
-    int js = 0;
-    for (int a = 1; a < 3; ++a)
-        if (fabs(f->L[a]) < fabs(f->L[js])) js = a;
-    double e[3] = {0.0, 0.0, 0.0};
-    e[js] = 1.0;
-    double el = dot3(e, f->L);
-    double u[3] = {e[0] - el * f->L[0], e[1] - el * f->L[1], e[2] - el * f->L[2]};
-    double nu = norm3(u);
-    for (int a = 0; a < 3; ++a) f->U[a] = u[a] / nu;
-    cross3(f->L, f->U, f->V);
+    plane_basis(f);
 
     /* R9: the square [-R,R]^2 in the (U,V) plane covers the cube for any L */
     f->R = sqrt(3.0) / 2.0;
+    return 0;
+}
+
+/* Point light (R34-R36): the light's view looks from P at the cube centre
+ * (axis L = (c - P)/|c - P|); slabs are planes of constant depth
+ * d = L.(p - P) between the nearest and farthest cube vertices (Eq. 8 with
+ * distances measured from the light); the light projection is the
+ * perspective one onto the plane d = 1, whose square [-R,R]^2 is the
+ * smallest that holds every cube vertex's projection. */
+int vio_light_frame_point(const double pos[3], int n, int res, vio_frame* f)
+{
+    if (!isfinite(pos[0]) || !isfinite(pos[1]) || !isfinite(pos[2]) || n < 1 || res < 1) return -1;
+    f->c[0] = f->c[1] = f->c[2] = 0.5;
+    double w[3] = {f->c[0] - pos[0], f->c[1] - pos[1], f->c[2] - pos[2]};
+    double nw = norm3(w);
+    if (!(nw > 0.5 * sqrt(3.0) * 1.0001)) return -1; /* inside the circumscribed sphere */
+    for (int a = 0; a < 3; ++a) {
+        f->L[a] = w[a] / nw;
+        f->P[a] = pos[a];
+    }
+    f->darken = 0.0;
+    f->positional = 1;
+    plane_basis(f);
+    f->dmin = INFINITY;
+    f->dmax = -INFINITY;
+    f->R = 0.0;
+    for (int vtx = 0; vtx < 8; ++vtx) {
+        double V[3] = {(double)(vtx & 1) - pos[0], (double)((vtx >> 1) & 1) - pos[1], (double)((vtx >> 2) & 1) - pos[2]};
+        double d = dot3(f->L, V);
+        if (d < f->dmin) f->dmin = d;
+        if (d > f->dmax) f->dmax = d;
+        double u = fabs(dot3(f->U, V)) / d, v = fabs(dot3(f->V, V)) / d;
+        if (u > f->R) f->R = u;
+        if (v > f->R) f->R = v;
+    }
+    f->n = n;
+    f->res = res;
+    f->ds = (f->dmax - f->dmin) / n;
     return 0;
 }
 
@@ -217,16 +262,24 @@ void vio_build_column(const vio_volume* v, const vio_tf* tf, const vio_frame* f,
     double ui = -f->R + (i + 0.5) * (2.0 * f->R / f->res); /* texel centre, R9 */
     double vj = -f->R + (j + 0.5) * (2.0 * f->R / f->res);
     double Lc = dot3(f->L, f->c);
+    /* point light (R37): the column is the ray from P through the texel
+     * (u, v) of the unit-depth plane, D = L + u U + v V (L.D = 1); it meets
+     * the mid-plane of slab k at P + d_k D and crosses the slab over a
+     * length ds |D| */
+    double D[3], seg = f->ds;
+    for (int a = 0; a < 3; ++a) D[a] = f->L[a] + ui * f->U[a] + vj * f->V[a];
+    if (f->positional) seg = f->ds * norm3(D);
     double T = 1.0;
     for (int k = 0; k < f->n; ++k) {
         double dk = f->dmin + (k + 0.5) * f->ds;
         double p[3];
-        for (int a = 0; a < 3; ++a) p[a] = f->c[a] + ui * f->U[a] + vj * f->V[a] + (dk - Lc) * f->L[a];
+        for (int a = 0; a < 3; ++a)
+            p[a] = f->positional ? f->P[a] + dk * D[a] : f->c[a] + ui * f->U[a] + vj * f->V[a] + (dk - Lc) * f->L[a];
         double alpha = 0.0;
         if (inside_cube(p)) {
             double rgba[4];
             vio_tf_lookup(tf, vio_volume_sample(v, p), rgba);
-            alpha = vio_segment_alpha(rgba[3], f->ds, dref);
+            alpha = vio_segment_alpha(rgba[3], seg, dref);
         }
         /* Eq. 4 on opacity: (1-a_dst)(1-a_src) is what stays transmitted;
          * with the section 4 compensation every slab's factor is also
@@ -338,13 +391,26 @@ static double stack_ext(vio_stack* s, int k, int j, int i)
 double vio_stack_lookup(vio_stack* s, const double p[3])
 {
     const vio_frame* f = &s->f;
-    double q = f->n * (dot3(f->L, p) - f->dmin) / (f->dmax - f->dmin); /* Eq. 9 */
+    double q, x, y;
+    if (f->positional) {
+        /* R38: depth from the light and the perspective projection; a
+         * point at or behind the light's depth plane lies outside every
+         * frustum texel and is lit (R40) */
+        double r[3] = {p[0] - f->P[0], p[1] - f->P[1], p[2] - f->P[2]};
+        double d = dot3(f->L, r);
+        if (!(d > 0.0)) return 1.0;
+        q = f->n * (d - f->dmin) / (f->dmax - f->dmin); /* Eq. 9 */
+        x = (dot3(f->U, r) / d + f->R) / (2.0 * f->R) * f->res - 0.5;
+        y = (dot3(f->V, r) / d + f->R) / (2.0 * f->R) * f->res - 0.5;
+    } else {
+        q = f->n * (dot3(f->L, p) - f->dmin) / (f->dmax - f->dmin); /* Eq. 9 */
+        double r[3] = {p[0] - f->c[0], p[1] - f->c[1], p[2] - f->c[2]};
+        x = (dot3(f->U, r) + f->R) / (2.0 * f->R) * f->res - 0.5;
+        y = (dot3(f->V, r) + f->R) / (2.0 * f->R) * f->res - 0.5;
+    }
     double z = q - 1.0;
     if (z < -1.0) z = -1.0;
     if (z > f->n - 1.0) z = f->n - 1.0;
-    double r[3] = {p[0] - f->c[0], p[1] - f->c[1], p[2] - f->c[2]};
-    double x = (dot3(f->U, r) + f->R) / (2.0 * f->R) * f->res - 0.5;
-    double y = (dot3(f->V, r) + f->R) / (2.0 * f->R) * f->res - 0.5;
 
     double kf = floor(z), xf = floor(x), yf = floor(y);
     double wz = z - kf, wx = x - xf, wy = y - yf;
@@ -565,7 +631,14 @@ static void render_pixel(const vio_volume* v, const vio_tf* tf, vio_stack* s, co
             double sd = 1.0, ss = 0.0;
             if (alpha > 0.0) {
                 if (mode == VIO_MODE_PHONG) {
-                    vio_phong(v, o, s->f.L, p, rd, &sd, &ss);
+                    /* the light travels along L, or from P to p for a point light */
+                    double Lp[3] = {s->f.L[0], s->f.L[1], s->f.L[2]};
+                    if (s->f.positional) {
+                        for (int a = 0; a < 3; ++a) Lp[a] = p[a] - s->f.P[a];
+                        double nl = norm3(Lp);
+                        for (int a = 0; a < 3; ++a) Lp[a] /= nl;
+                    }
+                    vio_phong(v, o, Lp, p, rd, &sd, &ss);
                 } else {
                     double A = vio_coefficient(s, mode, o, v->N, p, rd);
                     sd = o->ambient + (1.0 - o->ambient) * A;
@@ -606,6 +679,9 @@ int vio_render(const vio_volume* v, const vio_tf* tf, vio_stack* s, const vio_ca
 {
     if (!v || !tf || !cam || !o || !out_term || !(step_vox > 0.0)) return -1;
     if (mode != VIO_MODE_NONE && !s) return -1;  /* Phong takes its light from the stack's frame */
+    /* the cone follows the light direction, which a point light does not
+     * have (R39: not defined for point lights) */
+    if (mode == VIO_MODE_CONE && s->f.positional) return -1;
     int64_t W = cam->width;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();

@@ -62,6 +62,10 @@ typedef struct {
     int n, res;         /* slab count and texels per side                */
     double darken;      /* build: exponent m of the (1+alpha)^m slab
                            compensation of section 4 (0 = off, R24)      */
+    int positional;     /* 1: point light at P (R34-R38); L is then the
+                           light's axis and R the half-width of the
+                           texel square at unit depth                    */
+    double P[3];
 } vio_frame;
 
 typedef struct {
@@ -98,6 +102,8 @@ typedef struct vio_stack vio_stack;
 int    vio_threads(void); /* OpenMP threads the oracle uses by default */
 void   vio_default_opts(vio_opts* o);
 int    vio_light_frame(const double l[3], int n, int res, vio_frame* f);
+/* point light at `pos` (outside the cube's circumscribed sphere) */
+int    vio_light_frame_point(const double pos[3], int n, int res, vio_frame* f);
 double vio_volume_sample(const vio_volume* v, const double p[3]);
 void   vio_tf_lookup(const vio_tf* tf, double value, double rgba[4]);
 double vio_segment_alpha(double a, double len, double dref);

@@ -592,3 +592,91 @@ def test_p13_shell_weights_reduce_to_single_shells():
         assert st.coefficient("shell", p, d, {"shell_count": 2, "shell_w": [1, 1]}) == eq
         assert st.coefficient("shell", p, d, {"shell_count": 2, "shell_w": [3, 1]}) == pytest.approx(
             (3 * one + two) / 4, abs=1e-15)
+
+
+# ------------------------------------------------------------------ P14 point light (perspective light frusta)
+
+def _ray_box(o, d):
+    """Parameter interval where o + t d lies in the unit cube (slab method)."""
+    t0, t1 = -np.inf, np.inf
+    for a in range(3):
+        if d[a] == 0:
+            if not 0 <= o[a] <= 1:
+                return 1.0, 0.0
+            continue
+        ta, tb = (0 - o[a]) / d[a], (1 - o[a]) / d[a]
+        t0, t1 = max(t0, min(ta, tb)), min(t1, max(ta, tb))
+    return t0, t1
+
+
+def test_p14_point_light_frame_covers_the_cube():
+    """Every cube vertex projects inside the texel square and lies between the first and last slab
+    planes; one vertex touches the square's edge (the square is the smallest)."""
+    for pos in ([0.5, 0.5, -3.0], [2.0, -1.5, 2.5], [-0.9, 1.7, 0.3]):
+        f = O.light_frame(None, 16, 32, position=pos)
+        P, L, U, V, R = np.asarray(pos), f["L"], f["U"], f["V"], f["R"]
+        np.testing.assert_allclose(L, (0.5 - P) / np.linalg.norm(0.5 - P), atol=1e-15)
+        uv = []
+        for vtx in range(8):
+            w = np.array([vtx & 1, (vtx >> 1) & 1, (vtx >> 2) & 1], float) - P
+            d = L @ w
+            assert f["dmin"] - 1e-12 <= d <= f["dmax"] + 1e-12
+            uv.append(max(abs(U @ w), abs(V @ w)) / d)
+        assert max(uv) == pytest.approx(R, abs=1e-15)
+
+
+def test_p14_point_light_constant_medium_closed_form():
+    """A constant medium filling the cube: the column of texel (i, j) is the ray from the light
+    through the texel; its layer k is (1-a)^(m_k ds |D| / dref), m_k = slabs up to k whose mid-plane
+    crossing lies in the cube -- counted here from an independent ray/box clip."""
+    N, a0 = 16, 0.03
+    raw = np.full((N, N, N), 100, np.uint8)
+    vol, tf = O.Volume(raw), _const_tf([1, 1, 1, a0])
+    pos = np.array([1.7, -0.6, 2.4])
+    n, res = 24, 12
+    st = O.Stack(vol, tf, None, n, res, position=pos)
+    f = st.frame
+    for i, j in [(0, 0), (5, 7), (11, 3), (6, 6)]:
+        u = -f["R"] + (i + 0.5) * 2 * f["R"] / res
+        v = -f["R"] + (j + 0.5) * 2 * f["R"] / res
+        D = f["L"] + u * f["U"] + v * f["V"]
+        t0, t1 = _ray_box(pos, D)                       # L.D = 1: the ray parameter is the depth
+        dk = f["dmin"] + (np.arange(n) + 0.5) * f["ds"]
+        m = np.cumsum((dk >= t0) & (dk <= t1))
+        want = (1 - a0) ** (m * f["ds"] * np.linalg.norm(D) * N)
+        np.testing.assert_allclose(st.column(i, j), want, rtol=1e-12, atol=1e-15)
+
+
+def test_p14_point_light_lookup_registers_with_the_columns():
+    """A point on a column's ray reads that column, interpolated in depth only."""
+    w = W.WORKLOADS["small"]
+    vol, tf = O.Volume(w.volume()), O.TF(w.tf())
+    pos = np.array([-1.2, 1.9, 2.2])
+    n, res = 20, 24
+    st = O.Stack(vol, tf, None, n, res, position=pos)
+    f = st.frame
+    rng = np.random.default_rng(2)
+    for _ in range(30):
+        i, j = rng.integers(0, res, 2)
+        u = -f["R"] + (i + 0.5) * 2 * f["R"] / res
+        v = -f["R"] + (j + 0.5) * 2 * f["R"] / res
+        D = f["L"] + u * f["U"] + v * f["V"]
+        d = rng.uniform(f["dmin"] + 1.5 * f["ds"], f["dmax"] - 1.5 * f["ds"])
+        p = pos + d * D
+        z = (d - f["dmin"]) / f["ds"] - 1.0                # layer coordinate (face q holds layer q-1)
+        col = st.column(int(i), int(j))
+        k0 = int(np.floor(z))
+        want = col[k0] + (z - k0) * (col[k0 + 1] - col[k0])
+        assert st.lookup(p) == pytest.approx(want, abs=1e-12)
+
+
+def test_p14_point_light_on_the_axis_keeps_the_sphere_symmetry():
+    """Light on the z axis over a centred sphere: the stack is invariant under a quarter turn of the
+    texel grid about the axis."""
+    N = 24
+    raw = W.sphere_u8(N, radius=8, density=180, noise=0, seed=1)
+    vol, tf = O.Volume(raw), O.TF(W.tf_ramp())
+    st = O.Stack(vol, tf, None, 12, 16, position=[0.5, 0.5, -2.5])
+    S = st.export()
+    np.testing.assert_allclose(S, np.rot90(S, k=1, axes=(1, 2)), atol=1e-12)
+    assert S.min() < 0.5                                  # the sphere does cast a shadow
