@@ -39,14 +39,14 @@ MEASURED_TRAFFIC = {
     # large workload (512^3 u16 bricks, 16^3 empty-space cells, 512 x 1024^2 f32 stack in rows,
     # 1920x1080), light 0
     ("render_cone", "large", "rows", 16): {
-        "sha256": "6769d7258d3a31ea75d89aaa88b936dcc4305607624ea41118415bb390caf52e",
-        "fetch_kib": 79213.56, "write_kib": 34595.28},
+        "sha256": "1d5c4c99a31317da0f18e40c1e47bbafc5de9e6682d887500e93135698bd83bd",
+        "fetch_kib": 79213.5, "write_kib": 34587.03},
     ("render_shell", "large", "rows", 16): {
-        "sha256": "6769d7258d3a31ea75d89aaa88b936dcc4305607624ea41118415bb390caf52e",
-        "fetch_kib": 69020.25, "write_kib": 34372.16},
+        "sha256": "1d5c4c99a31317da0f18e40c1e47bbafc5de9e6682d887500e93135698bd83bd",
+        "fetch_kib": 69014.75, "write_kib": 34372.97},
     ("build", "large", "rows", 16): {       # build kernel plus the border kernel
-        "sha256": "d7066d6d9d8ab3ab47dcdaf7d025d4cefd0a4c3065c4891b7838a955a1308c36",
-        "fetch_kib": 67545.19 + 17.5, "write_kib": 2335480.0 + 28952.75},
+        "sha256": "feffe886bd1cf3d7d3447d285ae881e86dd21a40ab43a2fa4ef710ed66a986ec",
+        "fetch_kib": 64654.0 + 12.5, "write_kib": 2335758.31 + 28952.78},
 }
 
 
@@ -317,13 +317,23 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     def mode_args(m):
         return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
 
+    # point lights: each at args.point_light world units up-stream of the centre
+    # along its direction
+    positions = None
+    if args.point_light:
+        positions = [[0.5 - args.point_light * c for c in l] for l in lights]
+
     def step(i, events=None):
         li = i % len(lights)
         cam = w.camera(li)
         if events is not None:
             events[0].record()
-        st = vi.build_attenuation(vol, tf, lights[li], w.n_slices, w.res, stack_dtype, out=stack,
-                                  layout=STACK_LAYOUT)
+        if positions is None:
+            st = vi.build_attenuation(vol, tf, lights[li], w.n_slices, w.res, stack_dtype, out=stack,
+                                      layout=STACK_LAYOUT)
+        else:
+            st = vi.build_attenuation(vol, tf, None, w.n_slices, w.res, stack_dtype, out=stack,
+                                      layout=STACK_LAYOUT, position=positions[li])
         if events is not None:
             events[1].record()
         for k, m in enumerate(modes):
@@ -371,6 +381,9 @@ def main():
                     help="edge in voxels of the empty-space map's cells")
     ap.add_argument("--stack-layout", default="rows", choices=["tiled", "rows"],
                     help="stack layout of every stack built (rows: one 8-byte load per bilinear row)")
+    ap.add_argument("--point-light", type=float, default=0.0, metavar="DIST",
+                    help="point lights DIST world units from the volume centre (against each light "
+                         "direction) instead of directional lights; modes shadow, shell, phong, none")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -411,6 +424,13 @@ def main():
     modes = w.modes if w.name != "medium" else ["cone5"]
     if args.modes:
         modes = args.modes.split(",")
+    if args.point_light:
+        if not args.modes:
+            modes = ["shadow", "shell"]
+        if any(m.startswith("cone") for m in modes):
+            ap.error("the cone gather is defined for directional lights only")
+        if not args.point_light > 0.8661:
+            ap.error("a point light must lie outside the sphere around the volume (DIST > 0.8661)")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cam0 = w.camera(0)
@@ -439,7 +459,8 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(dom, w.name, args.stack_layout, args.cell),
+                "traffic": None if args.point_light else measured_traffic(dom, w.name, args.stack_layout,
+                                                                           args.cell),
                 "bytes_per_launch": per_launch, "avg_launch_ms": round(float(avg_ms), 4)}
     kernels = {"volume_prepare_ms_once": round(m["prep_ms"], 3),
                "build_ms_mean": round(float(np.mean(build_ms)), 4),
@@ -468,7 +489,9 @@ def main():
                                 f"{w.n_slices} slices x {w.res}^2 {'bf16' if precision else 'f32'} "
                                 f"({args.stack_layout}), "
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "
-                                f"{len(lights)} light directions (one rebuild per step)"),
+                                + (f"{len(lights)} point lights at {args.point_light} from the centre "
+                                 if args.point_light else f"{len(lights)} light directions ")
+                                + "(one rebuild per step)"),
                    "frames_per_step": len(modes)},
         "kernels": kernels,
         "roofline": roofline,
@@ -482,7 +505,7 @@ def main():
         log("serving leg ...")
         torch.cuda.empty_cache()
         result["serving"] = serving_quick("cuda:0")
-    if not args.no_cpu_baseline and not precision:
+    if not args.no_cpu_baseline and not precision and not args.point_light:
         log("timing the oracle on a pixel sample ...")
         opts = {}
         result["cpu_baseline"] = cpu_baseline(w, raw, tab, lights[0], cam0, modes, opts, args.cpu_stride)

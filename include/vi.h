@@ -162,10 +162,12 @@ typedef struct {
     double c[3];        /* cube centre */
     double dmin, dmax;  /* Eq. 8 */
     double ds;          /* slab thickness (dmax - dmin) / n */
-    double R;           /* half-width of the light square, sqrt(3)/2 */
+    double R;           /* half-width of the light square: sqrt(3)/2, or at unit depth for a point light */
     int vol_n;          /* edge of the volume it was built from */
     uint64_t tag;       /* identity of (volume, transfer function); 0 = unchecked */
     float darken;       /* build option it was built with (vi_build_opts) */
+    int positional;     /* 1: point light at P; L is then its axis (toward the cube centre) */
+    double P[3];
 } vi_slices;
 
 /* Build options; NULL means all defaults. */
@@ -174,6 +176,14 @@ typedef struct {
      * every slab's transmitted fraction (1-alpha) is multiplied by
      * (1+alpha)^m and capped at 1 (a slab never adds light).  0 <= m <= 64. */
     float darken;
+    /* 0: directional light along `light_dir`.  1: point light at `position`
+     * (world, outside the sphere circumscribing the unit cube; `light_dir`
+     * is then ignored and may be NULL): the light's view looks at the cube
+     * centre, slabs are planes of constant depth along that axis, the light
+     * projection is perspective (section 3.2.1's L_p with a point light),
+     * and each texel column is the ray from the light through the texel. */
+    int positional;
+    double position[3];
 } vi_build_opts;
 
 /* Camera: orthographic (view along target-eye, half image height
@@ -250,11 +260,11 @@ size_t vi_volume_minmax_bytes(int n, int cell);
 int vi_volume_minmax(const vi_volume* vol, int cell, float* d_minmax, vi_volume* out, vi_stream_t stream);
 
 /* Host only: compute the light frame of Eq. 8 and the light projection
- * for `light_dir` (need not be unit length; finite, non-zero) and fill
- * the geometry fields of `out` (data = NULL, tag = 0).
- * 1 <= n_slices <= 4096, 1 <= slice_res <= 8192. */
+ * for `light_dir` (need not be unit length; finite, non-zero), or for the
+ * point light of `opts` (may be NULL), and fill the geometry fields of
+ * `out` (data = NULL, tag = 0).  1 <= n_slices <= 4096, 1 <= slice_res <= 8192. */
 int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int slice_dtype, int slice_layout,
-                   vi_slices* out);
+                   const vi_build_opts* opts, vi_slices* out);
 
 /* Build the attenuation stack (section 3.2.1, Alg. 1) for light direction
  * `light_dir` into `d_slices` (device, vi_slices_bytes bytes, 16-byte
@@ -262,7 +272,7 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
  * `stream`.  slice_dtype: VI_F32 (transmittance, product of per-slab
  * (1-alpha)) or VI_BF16 (optical depth: the per-slab extinction summed in
  * float and rounded to bfloat16 per layer; each slab adds at most 64).
- * `opts` may be NULL (plain product).
+ * `opts` may be NULL (directional light, plain product).
  * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes, a degenerate
  * light or options out of range; VI_E_UNSUPPORTED for dtypes or sizes
  * outside the limits above or a stack of 4 GiB or more; VI_E_DEVICE if the
@@ -276,9 +286,15 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
  * width*height premultiplied RGBA floats to `d_rgba` (device, 16-byte
  * aligned, row-major, y = 0 on top).  step_vox > 0 is the ray step in
  * voxels.  `opts` may be NULL (defaults).  `slices` may be NULL only for
- * VI_MODE_NONE; VI_MODE_PHONG reads only its light direction, so a
- * descriptor from vi_light_frame (data NULL) serves.  If `d_samples` (device) is non-NULL the number of
- * segments composited (stopping at termination) is ADDED to it.
+ * VI_MODE_NONE; VI_MODE_PHONG reads only its light, so a descriptor from
+ * vi_light_frame (data NULL) serves.  With a point light's descriptor
+ * every stack lookup projects through its depth from the light, and a
+ * lookup at or behind the light's depth plane reads transmittance 1;
+ * Phong's light vector points at the light from each sample.
+ * VI_MODE_CONE needs a directional light (VI_E_UNSUPPORTED for a point
+ * light's stack: its cone axis and ring offsets assume one direction).
+ * If `d_samples` (device) is non-NULL the number of segments composited
+ * (stopping at termination) is ADDED to it.
  * Errors: VI_E_INVALID_ARG for NULL/misaligned pointers, bad sizes, a
  * descriptor whose vol_n differs from the volume or whose non-zero tag
  * names another (volume, transfer function); VI_E_UNSUPPORTED for dtypes

@@ -111,14 +111,69 @@ bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_by
 uint32_t row_origin(int) { return 1u; }
 uint32_t row_pitch(int res, int) { return vi::round_up((uint32_t)res + 4u, 4u); }
 
-// Eq. 8 and the light projection: geometry of the stack in double.
-int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)
+// Light-plane basis (U from the axis least aligned with L, Gram-Schmidt;
+// V = L x U).
+void plane_basis(const double L[3], double U[3], double V[3])
 {
-    if (!l || !f) return fail(VI_E_INVALID_ARG, "NULL light direction or descriptor");
+    int js = 0;
+    for (int a = 1; a < 3; ++a)
+        if (fabs(L[a]) < fabs(L[js])) js = a;
+    double u[3] = {-L[js] * L[0], -L[js] * L[1], -L[js] * L[2]};
+    u[js] += 1.0;
+    const double nu = sqrt(dot3(u, u));
+    for (int a = 0; a < 3; ++a) U[a] = u[a] / nu;
+    cross3(L, U, V);
+}
+
+// A point light's frame: axis from the light to the cube centre, slab
+// planes of constant depth along it between the nearest and farthest cube
+// vertices, and the smallest square on the unit-depth plane that holds
+// every vertex's perspective projection.
+int fill_point_frame(const double P[3], int n, int res, int dt, int sl, vi_slices* f)
+{
+    if (!isfinite(P[0]) || !isfinite(P[1]) || !isfinite(P[2]))
+        return fail(VI_E_INVALID_ARG, "light position is not finite");
+    const double w[3] = {0.5 - P[0], 0.5 - P[1], 0.5 - P[2]};
+    const double nw = sqrt(dot3(w, w));
+    if (!(nw > 0.5 * sqrt(3.0) * 1.0001))
+        return fail(VI_E_INVALID_ARG, "a point light must lie outside the cube's circumscribed sphere");
+    memset(f, 0, sizeof *f);
+    f->dtype = dt;
+    f->layout = sl;
+    f->positional = 1;
+    for (int a = 0; a < 3; ++a) {
+        f->L[a] = w[a] / nw;
+        f->P[a] = P[a];
+        f->c[a] = 0.5;
+    }
+    plane_basis(f->L, f->U, f->V);
+    f->dmin = 1e300;
+    f->dmax = -1e300;
+    f->R = 0.0;
+    for (int vtx = 0; vtx < 8; ++vtx) {
+        const double r[3] = {(double)(vtx & 1) - P[0], (double)((vtx >> 1) & 1) - P[1], (double)((vtx >> 2) & 1) - P[2]};
+        const double d = dot3(f->L, r);
+        f->dmin = fmin(f->dmin, d);
+        f->dmax = fmax(f->dmax, d);
+        f->R = fmax(f->R, fmax(fabs(dot3(f->U, r)), fabs(dot3(f->V, r))) / d);
+    }
+    f->ds = (f->dmax - f->dmin) / n;
+    f->n = n;
+    f->res = res;
+    return VI_OK;
+}
+
+// Eq. 8 and the light projection: geometry of the stack in double.
+int fill_frame(const double l[3], int n, int res, int dt, int sl, const vi_build_opts* o, vi_slices* f)
+{
+    const bool point = o && o->positional;
+    if (o && o->positional != 0 && o->positional != 1) return fail(VI_E_INVALID_ARG, "positional must be 0 or 1");
+    if ((!l && !point) || !f) return fail(VI_E_INVALID_ARG, "NULL light direction or descriptor");
     if (n < 1 || n > 4096) return fail(VI_E_INVALID_ARG, "n_slices %d outside 1..4096", n);
     if (res < 1 || res > 8192) return fail(VI_E_INVALID_ARG, "slice_res %d outside 1..8192", res);
     if (dt != VI_F32 && dt != VI_BF16) return fail(VI_E_UNSUPPORTED, "slice dtype %d not supported", dt);
     if (sl != VI_STACK_TILED && sl != VI_STACK_ROWS) return fail(VI_E_UNSUPPORTED, "slice layout %d not supported", sl);
+    if (point) return fill_point_frame(o->position, n, res, dt, sl, f);
     if (!isfinite(l[0]) || !isfinite(l[1]) || !isfinite(l[2]))
         return fail(VI_E_INVALID_ARG, "light direction is not finite");
     const double nl = sqrt(dot3(l, l));
@@ -136,14 +191,7 @@ int fill_frame(const double l[3], int n, int res, int dt, int sl, vi_slices* f)
         else f->dmax += f->L[a];
     }
     f->ds = (f->dmax - f->dmin) / n;
-    int js = 0;
-    for (int a = 1; a < 3; ++a)
-        if (fabs(f->L[a]) < fabs(f->L[js])) js = a;
-    double u[3] = {-f->L[js] * f->L[0], -f->L[js] * f->L[1], -f->L[js] * f->L[2]};
-    u[js] += 1.0;
-    const double nu = sqrt(dot3(u, u));
-    for (int a = 0; a < 3; ++a) f->U[a] = u[a] / nu;
-    cross3(f->L, f->U, f->V);
+    plane_basis(f->L, f->U, f->V);
     f->R = sqrt(3.0) / 2.0;
     f->n = n;
     f->res = res;
@@ -267,10 +315,11 @@ uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf)
     return h ? h : 1;
 }
 
-int vi_light_frame(const double light_dir[3], int n, int res, int dt, int sl, vi_slices* out)
+int vi_light_frame(const double light_dir[3], int n, int res, int dt, int sl, const vi_build_opts* opts,
+                   vi_slices* out)
 {
     clear_err();
-    return fill_frame(light_dir, n, res, dt, sl, out);
+    return fill_frame(light_dir, n, res, dt, sl, opts, out);
 }
 
 int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double light_dir[3], int n, int res,
@@ -284,7 +333,7 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     if (!d_slices) return fail(VI_E_INVALID_ARG, "NULL stack buffer");
     if (!out_desc) return fail(VI_E_INVALID_ARG, "NULL stack descriptor");
     vi_slices f;
-    if ((rc = fill_frame(light_dir, n, res, dt, sl, &f)) != VI_OK) return rc;
+    if ((rc = fill_frame(light_dir, n, res, dt, sl, opts, &f)) != VI_OK) return rc;
     if (((uintptr_t)d_slices) % 16) return fail(VI_E_INVALID_ARG, "stack buffer must be 16-byte aligned");
     if (!stack_size_ok(n, res, dt, sl))
         return fail(VI_E_UNSUPPORTED, "stack of %zu bytes exceeds the layout's limit", vi_slices_bytes(n, res, dt, sl));
@@ -315,12 +364,27 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     p.rlayer = ((uint32_t)res + 2u) * p.rpitch;
     const double N = vol->n, texel = 2.0 * f.R / res, u0 = -f.R + 0.5 * texel;
     const double d0 = f.dmin + 0.5 * f.ds, Lc = dot3(f.L, f.c);
-    for (int a = 0; a < 3; ++a) {
-        const double p0 = f.c[a] + u0 * f.U[a] + u0 * f.V[a] + (d0 - Lc) * f.L[a];
-        p.B0[a] = p0 * N - 0.5 - p.M;
-        p.BU[a] = f.U[a] * texel * N;
-        p.BV[a] = f.V[a] * texel * N;
-        p.AL[a] = (float)(f.L[a] * f.ds * N);
+    if (f.positional) {
+        // column (i,j) is the ray P + d D(i,j), D = L + u U + v V on the
+        // unit-depth plane; slab k's mid-plane at depth d0 + k ds
+        p.point = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double D00 = f.L[a] + u0 * f.U[a] + u0 * f.V[a];
+            p.B0[a] = (f.P[a] + d0 * D00) * N - 0.5 - p.M;
+            p.BU[a] = d0 * texel * f.U[a] * N;
+            p.BV[a] = d0 * texel * f.V[a] * N;
+            p.AL0[a] = f.ds * D00 * N;
+            p.ALU[a] = f.ds * texel * f.U[a] * N;
+            p.ALV[a] = f.ds * texel * f.V[a] * N;
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            const double p0 = f.c[a] + u0 * f.U[a] + u0 * f.V[a] + (d0 - Lc) * f.L[a];
+            p.B0[a] = p0 * N - 0.5 - p.M;
+            p.BU[a] = f.U[a] * texel * N;
+            p.BV[a] = f.V[a] * texel * N;
+            p.AL[a] = (float)(f.L[a] * f.ds * N);
+        }
     }
     p.e = (float)(f.ds * N);
     p.darken = darken;
@@ -389,6 +453,15 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
             return fail(VI_E_INVALID_ARG, "phong_shininess must be in [0, 1024]");
         if (!(o.grad_eps > 0.0f) || !isfinite(o.grad_eps)) return fail(VI_E_INVALID_ARG, "grad_eps must be > 0");
     }
+    const bool point = sl && sl->positional;
+    if (point) {
+        if (mode == VI_MODE_CONE)
+            return fail(VI_E_UNSUPPORTED, "the cone gather is defined for directional lights only");
+        if (!isfinite(sl->P[0]) || !isfinite(sl->P[1]) || !isfinite(sl->P[2]))
+            return fail(VI_E_INVALID_ARG, "point light position is not finite");
+        if (reads_stack && !(sl->dmin > 0.0 && sl->R > 0.0))
+            return fail(VI_E_INVALID_ARG, "point-light frame must have dmin > 0 and R > 0");
+    }
     if (reads_stack) {
         if (!sl || !sl->data) return fail(VI_E_INVALID_ARG, "mode %d needs a stack", mode);
         if (sl->dtype != VI_F32 && sl->dtype != VI_BF16) return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);
@@ -419,6 +492,10 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     F.mode = mode;
     if (mode == VI_MODE_PHONG)
         for (int a = 0; a < 3; ++a) F.L[a] = sl->L[a];
+    if (point) {
+        F.point = 1;
+        for (int a = 0; a < 3; ++a) F.P[a] = sl->P[a];
+    }
     if (reads_stack) {
         F.stack = sl->data;
         F.stack_dtype = sl->dtype;
@@ -445,6 +522,13 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         F.Ux0 = (-dot3(sl->U, sl->c) + sl->R) * sc - 0.5;
         F.Vy0 = (-dot3(sl->V, sl->c) + sl->R) * sc - 0.5;
         F.ds = sl->ds;
+        if (point) {
+            // depth is measured from the light: d = L.p - L.P
+            F.Lq0 = -sl->n * (sl->dmin + dot3(sl->L, sl->P)) / span - 1.0;
+            F.dmin = sl->dmin;
+            F.sc = (float)sc;
+            F.xo = (float)(0.5 * sl->res - 0.5 - F.Mr);
+        }
     }
     // camera basis
     double fwd[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1], cam->target[2] - cam->eye[2]};
@@ -512,8 +596,15 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
                 for (int sg = -1; sg <= 1; sg += 2) {
                     const double off = sg * r * h;
                     F.tz[t] = (float)(off * F.Lq[a]);
-                    F.tx_[t] = (float)(off * F.Ux[a]);
-                    F.ty_[t] = (float)(off * F.Vy[a]);
+                    if (point) {
+                        // world-frame offsets: the projection divides by depth per tap
+                        F.td_[t] = (float)(off * F.L[a]);
+                        F.tx_[t] = (float)(off * F.U[a]);
+                        F.ty_[t] = (float)(off * F.V[a]);
+                    } else {
+                        F.tx_[t] = (float)(off * F.Ux[a]);
+                        F.ty_[t] = (float)(off * F.Vy[a]);
+                    }
                     F.tw[t] = (float)((weighted ? o.shell_w[r - 1] : 1.0) / (6.0 * wsum));
                     ++t;
                 }

@@ -76,6 +76,18 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     const float hx0 = (float)(P.B0[0] + i * P.BU[0] + j * P.BV[0]);
     const float hy0 = (float)(P.B0[1] + i * P.BU[1] + j * P.BV[1]);
     const float hz0 = (float)(P.B0[2] + i * P.BU[2] + j * P.BV[2]);
+    // step per slab, and the slab exponent (its length in voxels); a point
+    // light's column is its own ray from the light
+    float alx = P.AL[0], aly = P.AL[1], alz = P.AL[2], e = P.e;
+    if (P.point) {
+        const double ax = P.AL0[0] + i * P.ALU[0] + j * P.ALV[0];
+        const double ay = P.AL0[1] + i * P.ALU[1] + j * P.ALV[1];
+        const double az = P.AL0[2] + i * P.ALU[2] + j * P.ALV[2];
+        alx = (float)ax;
+        aly = (float)ay;
+        alz = (float)az;
+        e = (float)sqrt(ax * ax + ay * ay + az * az);
+    }
 
     const VT* __restrict__ vol = (const VT*)P.vol;
     const VolIndex VI_ = {1u, P.vsy, P.vsz};
@@ -92,9 +104,9 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 
     for (int k = 0; k < P.n; ++k, at += layer) {
         const float kf = (float)k;
-        const float hx = fmaf(kf, P.AL[0], hx0);
-        const float hy = fmaf(kf, P.AL[1], hy0);
-        const float hz = fmaf(kf, P.AL[2], hz0);
+        const float hx = fmaf(kf, alx, hx0);
+        const float hy = fmaf(kf, aly, hy0);
+        const float hz = fmaf(kf, alz, hz0);
         // log2 of the slab's (1 - alpha)/e, 0 outside the cube (empty)
         float l2 = 0.0f;
         bool fetch = (hx >= P.lo) & (hx <= P.hi) & (hy >= P.lo) & (hy <= P.hi) & (hz >= P.lo) & (hz <= P.hi);
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         }
         if (OUT_DTYPE == VI_F32) {
             // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
-            float f = fast_exp2(P.e * l2);
+            float f = fast_exp2(e * l2);
             // section 4 compensation: times (1 + alpha)^m, at most 1
             if (DARKEN) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
             T *= f;
@@ -126,8 +138,8 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         } else {
             // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
             // compensation subtracts m ln(1 + alpha), floored at 0
-            float dtau = -P.e * ln2 * l2;
-            if (DARKEN) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(P.e * l2)), 0.0f);
+            float dtau = -e * ln2 * l2;
+            if (DARKEN) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
             tau += fminf(dtau, 64.0f);
             ((uint16_t*)P.out)[at] = f32_to_bf16(tau);
         }

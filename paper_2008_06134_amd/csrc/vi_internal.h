@@ -49,6 +49,11 @@ struct BuildParams {
     float e;           // slab thickness in voxels: exponent of (1-a)
     float darken;      // exponent m of the (1+alpha)^m slab compensation, 0 = off
     float lo, hi;      // cube in h coordinates: [-1/2 - M, N - 1/2 - M]
+    // point light: column (i,j) advances by AL0 + i ALU + j ALV per slab,
+    // and its slab exponent is that step's length (the ray crosses the
+    // slab obliquely)
+    int point;
+    double AL0[3], ALU[3], ALV[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -79,6 +84,11 @@ struct RenderFrame {
     double Vy[3], Vy0;   // y = Vy . p + Vy0 - Mr
     double L[3], U[3], V[3];
     double ds;
+    // point light: depth d = L.(p - P) and lateral u = U.(p - P), v = V.(p - P)
+    // map to z = (d - dmin) zs - 1 - Mz, x = (u / d) sc + xo, y = (v / d) sc + yo
+    int point;
+    double P[3], dmin;
+    float zs, sc, xo;
     // camera
     int cam_kind;
     int width, height;
@@ -95,6 +105,8 @@ struct RenderFrame {
     float tap_w;
     float tz[kMaxTaps], tx_[kMaxTaps], ty_[kMaxTaps];  // shell offsets
     float tw[kMaxTaps];                                 // shell tap weights (sum 1)
+    float td_[kMaxTaps];                                // point light: depth offsets (tx_, ty_ then
+                                                        // hold world-frame lateral offsets)
     int cone_rings, cone_angles, cone_grid;
     float cone_tan;
     float cone_cos[16], cone_sin[16];
@@ -106,13 +118,25 @@ struct RenderFrame {
 // launchers (vi_build.hip / vi_render.hip / vi_layout.hip)
 hipError_t launch_build(const BuildParams& p, hipStream_t s);
 hipError_t launch_render(const RenderFrame& f, hipStream_t s);
-// one launch over `ntiles` tiles whose frames all have render mode `mode`
+// one launch over `ntiles` tiles whose frames all have kernel_mode() `mode`
 hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout, int mode,
                                const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
                                hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStream_t s);
 hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
                          int shift, float* out, hipStream_t s);
+
+// Kernel variants of the modes for a point light: the light grid is a
+// perspective frustum (every stack lookup divides by its depth), and Phong's
+// light vector points at the light from each sample.
+constexpr int kModePointShadow = 5, kModePointShell = 6, kModePointPhong = 7, kKernelModes = 8;
+inline int kernel_mode(const RenderFrame& f)
+{
+    if (f.point && f.mode == VI_MODE_SHADOW) return kModePointShadow;
+    if (f.point && f.mode == VI_MODE_SHELL) return kModePointShell;
+    if (f.point && f.mode == VI_MODE_PHONG) return kModePointPhong;
+    return f.mode;
+}
 
 // host helpers shared by the API and the server
 int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const vi_camera* cam, int mode,

@@ -179,6 +179,34 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
     return s * F.tap_w;
 }
 
+// Point light: the light grid is a frustum with its apex at P.  A lookup at
+// depth d = L.(p - P) and lateral offsets (u, v) = (U, V).(p - P) reads texel
+// column (u / d) sc + xo; a point at or behind the apex's plane (d <= 0) lies
+// outside every texel, where the stack reads 1.  The column is clamped to a
+// band just outside the grid, which keeps huge quotients finite.
+__device__ __forceinline__ float frustum_col(const RenderFrame& F, float u, float rd, bool ahead)
+{
+    const float x = ahead ? fmaf(u * rd, F.sc, F.xo) : -3.0e38f;
+    return fminf(fmaxf(x, (float)(-2 - F.Mr)), (float)(F.res + 1 - F.Mr));
+}
+
+template <int MODE, int SDT, int SL>
+__device__ __forceinline__ float gather_point(const RenderFrame& F, float z, float d, float u, float v)
+{
+    if (MODE == kModePointShadow) {
+        const float rd = __builtin_amdgcn_rcpf(d);
+        return stack_lookup<SDT, SL>(F, z, frustum_col(F, u, rd, d > 0.0f), frustum_col(F, v, rd, d > 0.0f));
+    }
+    // shell taps: world-frame offsets, each projected through its own depth
+    float s = 0.0f;
+    for (int t = 0; t < F.ntaps; ++t) {
+        const float dt = d + F.td_[t], rd = __builtin_amdgcn_rcpf(dt);
+        const float x = frustum_col(F, u + F.tx_[t], rd, dt > 0.0f), y = frustum_col(F, v + F.ty_[t], rd, dt > 0.0f);
+        s = fmaf(F.tw[t], stack_lookup<SDT, SL>(F, z + F.tz[t], x, y), s);
+    }
+    return s;
+}
+
 // G lanes march one ray together: lane g of the group takes segment k + g of
 // every group step, the G segments are composited front to back with a scan
 // over the group (inclusive product of (1 - alpha), then the emission of each
@@ -258,11 +286,16 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                 hz0 = (float)(pin[2] * Nd - 0.5 - F.M);
     const float hdx = (float)(d[0] * Nd), hdy = (float)(d[1] * Nd), hdz = (float)(d[2] * Nd);
     // light grid: depth index (Eq. 9, minus one) and texel coordinates (Eq. 10)
-    float qz0 = 0.f, qx0 = 0.f, qy0 = 0.f, qdz = 0.f, qdx = 0.f, qdy = 0.f;
+    // (point light: qx / qy hold the lateral offsets U.(p - P), V.(p - P) and
+    // pd the depth L.(p - P), all affine along the ray)
+    constexpr bool PT = MODE == kModePointShadow || MODE == kModePointShell;
+    constexpr bool PTP = MODE == kModePointPhong, PHONG = MODE == VI_MODE_PHONG || PTP;
+    float qz0 = 0.f, qx0 = 0.f, qy0 = 0.f, qdz = 0.f, qdx = 0.f, qdy = 0.f, pd0 = 0.f, pdd = 0.f;
     ConeFrame cf = {0.f, 0.f, 0.f, 0.f};
     // Phong: light vector l = -L and, folded in, l.v with v = -d
+    // (point light: l is taken per sample toward P, and lx, ly, lz hold pin - P)
     float lx = 0.f, ly = 0.f, lz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, lv = 0.f;
-    if (MODE == VI_MODE_PHONG) {
+    if (PHONG) {
         lx = (float)-F.L[0];
         ly = (float)-F.L[1];
         lz = (float)-F.L[2];
@@ -270,14 +303,29 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         vy = (float)-d[1];
         vz = (float)-d[2];
         lv = (float)(F.L[0] * d[0] + F.L[1] * d[1] + F.L[2] * d[2]);
+        if (PTP) {
+            lx = (float)(pin[0] - F.P[0]);
+            ly = (float)(pin[1] - F.P[1]);
+            lz = (float)(pin[2] - F.P[2]);
+        }
     }
-    if (MODE != VI_MODE_NONE && MODE != VI_MODE_PHONG) {
+    if (MODE != VI_MODE_NONE && !PHONG) {
         qz0 = (float)(F.Lq[0] * pin[0] + F.Lq[1] * pin[1] + F.Lq[2] * pin[2] + F.Lq0 - F.Mz);
-        qx0 = (float)(F.Ux[0] * pin[0] + F.Ux[1] * pin[1] + F.Ux[2] * pin[2] + F.Ux0 - F.Mr);
-        qy0 = (float)(F.Vy[0] * pin[0] + F.Vy[1] * pin[1] + F.Vy[2] * pin[2] + F.Vy0 - F.Mr);
         qdz = (float)(F.Lq[0] * d[0] + F.Lq[1] * d[1] + F.Lq[2] * d[2]);
-        qdx = (float)(F.Ux[0] * d[0] + F.Ux[1] * d[1] + F.Ux[2] * d[2]);
-        qdy = (float)(F.Vy[0] * d[0] + F.Vy[1] * d[1] + F.Vy[2] * d[2]);
+        if (PT) {
+            const double r[3] = {pin[0] - F.P[0], pin[1] - F.P[1], pin[2] - F.P[2]};
+            pd0 = (float)(F.L[0] * r[0] + F.L[1] * r[1] + F.L[2] * r[2]);
+            pdd = (float)(F.L[0] * d[0] + F.L[1] * d[1] + F.L[2] * d[2]);
+            qx0 = (float)(F.U[0] * r[0] + F.U[1] * r[1] + F.U[2] * r[2]);
+            qdx = (float)(F.U[0] * d[0] + F.U[1] * d[1] + F.U[2] * d[2]);
+            qy0 = (float)(F.V[0] * r[0] + F.V[1] * r[1] + F.V[2] * r[2]);
+            qdy = (float)(F.V[0] * d[0] + F.V[1] * d[1] + F.V[2] * d[2]);
+        } else {
+            qx0 = (float)(F.Ux[0] * pin[0] + F.Ux[1] * pin[1] + F.Ux[2] * pin[2] + F.Ux0 - F.Mr);
+            qy0 = (float)(F.Vy[0] * pin[0] + F.Vy[1] * pin[1] + F.Vy[2] * pin[2] + F.Vy0 - F.Mr);
+            qdx = (float)(F.Ux[0] * d[0] + F.Ux[1] * d[1] + F.Ux[2] * d[2]);
+            qdy = (float)(F.Vy[0] * d[0] + F.Vy[1] * d[1] + F.Vy[2] * d[2]);
+        }
         if (MODE == VI_MODE_CONE) {
             // B: direction toward the viewer with its L component removed
             double w[3] = {-d[0], -d[1], -d[2]};
@@ -374,7 +422,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                     // emission alpha (sd rgb + ss) light: Eq. 7 with the
                     // coefficient A, or the local Phong terms
                     float sd, ss = 0.0f;
-                    if (MODE == VI_MODE_PHONG) {
+                    if (PHONG) {
                         // central differences one voxel either side (exact
                         // offsets in voxel units)
                         const float gx = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx + 1.f, hy, hz) -
@@ -386,15 +434,28 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                         const float gn = sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
                         const float inv = -1.0f / fmaxf(gn, F.grad_eps);  // n = -g / max(|g|, eps)
                         const float nx = gx * inv, ny = gy * inv, nz = gz * inv;
-                        const float nl = fmaf(nx, lx, fmaf(ny, ly, nz * lz));
+                        float llx = lx, lly = ly, llz = lz, llv = lv;
+                        if (PTP) {
+                            // l = (P - p) / |P - p|
+                            const float rx = fmaf(sm, -vx, lx), ry = fmaf(sm, -vy, ly), rz = fmaf(sm, -vz, lz);
+                            const float ir = -__builtin_amdgcn_rsqf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+                            llx = rx * ir;
+                            lly = ry * ir;
+                            llz = rz * ir;
+                            llv = fmaf(llx, vx, fmaf(lly, vy, llz * vz));
+                        }
+                        const float nl = fmaf(nx, llx, fmaf(ny, lly, nz * llz));
                         const float nv = fmaf(nx, vx, fmaf(ny, vy, nz * vz));
                         const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-                        const float rv = fmaf(2.0f * nl, nv, -nn * lv);   // r.v, r = 2(n.l)n - (n.n)l
+                        const float rv = fmaf(2.0f * nl, nv, -nn * llv);  // r.v, r = 2(n.l)n - (n.n)l
                         sd = fmaf(F.phong_kd, fmaxf(nl, 0.0f), F.phong_ka);
                         if (rv > 0.0f) ss = F.phong_ks * fast_exp2(F.phong_shin * fast_log2(rv));
                     } else {
                         float A = 1.0f;
-                        if (MODE != VI_MODE_NONE)
+                        if (PT)
+                            A = gather_point<MODE, SDT, SL>(F, fmaf(sm, qdz, qz0), fmaf(sm, pdd, pd0),
+                                                            fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
+                        else if (MODE != VI_MODE_NONE)
                             A = gather<MODE, SDT, SL>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0),
                                                       fmaf(sm, qdy, qy0));
                         sd = fmaf(1.0f - F.ambient, A, F.ambient);
@@ -556,6 +617,18 @@ static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const ui
         hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, d_frames,
                            d_tiles, ntiles);
         break;
+    case kModePointShadow:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, kModePointShadow, SDT, SL>), grid, block, lds, s,
+                           d_frames, d_tiles, ntiles);
+        break;
+    case kModePointShell:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, kModePointShell, SDT, SL>), grid, block, lds, s,
+                           d_frames, d_tiles, ntiles);
+        break;
+    case kModePointPhong:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, kModePointPhong, SDT, SL>), grid, block, lds, s,
+                           d_frames, d_tiles, ntiles);
+        break;
     default:
         hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, d_frames,
                            d_tiles, ntiles);
@@ -602,7 +675,7 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
     dim3 grid(supertile_grid((f.width + kBX - 1) / kBX, (f.height + kBY - 1) / kBY)), block(256);
     const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K;
-    switch (f.mode) {
+    switch (kernel_mode(f)) {
     case VI_MODE_NONE:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>), grid, block, lds, s, f);
         break;
@@ -614,6 +687,15 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
         break;
     case VI_MODE_CONE:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, f);
+        break;
+    case kModePointShadow:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, kModePointShadow, SDT, SL>), grid, block, lds, s, f);
+        break;
+    case kModePointShell:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, kModePointShell, SDT, SL>), grid, block, lds, s, f);
+        break;
+    case kModePointPhong:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, kModePointPhong, SDT, SL>), grid, block, lds, s, f);
         break;
     default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, f); break;
     }

@@ -93,10 +93,13 @@ Scheduler::Key Scheduler::key_of(const vi_request& r) const
     k.dtype = r.slice_dtype;
     k.layout = r.slice_layout;
     memcpy(&k.darken, &r.build.darken, 4);
-    // the light is part of the identity bit for bit
-    memcpy(&k.lx, &r.light_dir[0], 8);
-    memcpy(&k.ly, &r.light_dir[1], 8);
-    memcpy(&k.lz, &r.light_dir[2], 8);
+    // the light is part of the identity bit for bit: its direction, or for
+    // a point light its position
+    k.positional = r.build.positional ? 1 : 0;
+    const double* l = k.positional ? r.build.position : r.light_dir;
+    memcpy(&k.lx, &l[0], 8);
+    memcpy(&k.ly, &l[1], 8);
+    memcpy(&k.lz, &l[2], 8);
     return k;
 }
 

@@ -127,11 +127,12 @@ private:
     struct Key {
         int vol_id, n, res, dtype, layout;
         uint32_t darken;  // build option bits
+        int positional;   // lx, ly, lz: direction bits, or position bits when set
         uint64_t lx, ly, lz;
         bool operator==(const Key& o) const
         {
             return vol_id == o.vol_id && n == o.n && res == o.res && dtype == o.dtype && layout == o.layout &&
-                   darken == o.darken && lx == o.lx && ly == o.ly && lz == o.lz;
+                   darken == o.darken && positional == o.positional && lx == o.lx && ly == o.ly && lz == o.lz;
         }
     };
     struct Stack {

@@ -73,7 +73,7 @@ public:
     int validate(const vi_request& r, const sched::VolumeRec& v) override
     {
         vi_slices sl;
-        int rc = vi_light_frame(r.light_dir, r.n_slices, r.slice_res, r.slice_dtype, r.slice_layout, &sl);
+        int rc = vi_light_frame(r.light_dir, r.n_slices, r.slice_res, r.slice_dtype, r.slice_layout, &r.build, &sl);
         if (rc != VI_OK) return rc;
         if (!(r.build.darken >= 0.0f && r.build.darken <= 64.0f))
             return fail_msg(VI_E_INVALID_ARG, "darken must be in [0, 64]");
@@ -152,14 +152,15 @@ public:
             if (rc != VI_OK) return rc;
             maxK = std::max(maxK, v.tf.n_entries);
         }
-        // tiles grouped by render mode (stable), one kernel per mode present
-        uint32_t count[VI_MODE_PHONG + 1] = {0}, start[VI_MODE_PHONG + 2] = {0};
-        for (uint32_t t : tiles) count[frames[t >> 22].req->mode]++;
-        for (int m = 0; m <= VI_MODE_PHONG; ++m) start[m + 1] = start[m] + count[m];
+        // tiles grouped by kernel mode (stable), one kernel per mode present
+        constexpr int kModes = kKernelModes;
+        uint32_t count[kModes] = {0}, start[kModes + 1] = {0};
+        for (uint32_t t : tiles) count[kernel_mode(h_frames[t >> 22])]++;
+        for (int m = 0; m < kModes; ++m) start[m + 1] = start[m] + count[m];
         {
-            uint32_t at[VI_MODE_PHONG + 1];
-            for (int m = 0; m <= VI_MODE_PHONG; ++m) at[m] = start[m];
-            for (uint32_t t : tiles) h_tiles[at[frames[t >> 22].req->mode]++] = t;
+            uint32_t at[kModes];
+            for (int m = 0; m < kModes; ++m) at[m] = start[m];
+            for (uint32_t t : tiles) h_tiles[at[kernel_mode(h_frames[t >> 22])]++] = t;
         }
         hipError_t e = hipMemcpyAsync(S.d_stage, S.h_stage, frames_bytes + tiles.size() * sizeof(uint32_t),
                                       hipMemcpyHostToDevice, rs_);
@@ -168,7 +169,7 @@ public:
             if (e == hipSuccess && f.stack->build_handle >= 0)
                 e = hipStreamWaitEvent(rs_, build_events_[f.stack->build_handle], 0);
         const vi_volume& v0 = frames[0].vol->vol;
-        for (int m = 0; m <= VI_MODE_PHONG && e == hipSuccess; ++m)
+        for (int m = 0; m < kModes && e == hipSuccess; ++m)
             if (count[m])
                 e = launch_render_batch(v0.dtype, v0.layout, frames[0].req->slice_dtype, frames[0].req->slice_layout,
                                         m, d_frames, d_tiles + start[m], count[m], maxK, rs_);

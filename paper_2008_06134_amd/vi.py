@@ -46,11 +46,22 @@ class Slices_t(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("layout", C.c_int), ("n", C.c_int), ("res", C.c_int),
                 ("L", C.c_double * 3), ("U", C.c_double * 3), ("V", C.c_double * 3), ("c", C.c_double * 3),
                 ("dmin", C.c_double), ("dmax", C.c_double), ("ds", C.c_double), ("R", C.c_double),
-                ("vol_n", C.c_int), ("tag", C.c_uint64), ("darken", C.c_float)]
+                ("vol_n", C.c_int), ("tag", C.c_uint64), ("darken", C.c_float), ("positional", C.c_int),
+                ("P", C.c_double * 3)]
 
 
 class BuildOpts_t(C.Structure):
-    _fields_ = [("darken", C.c_float)]
+    _fields_ = [("darken", C.c_float), ("positional", C.c_int), ("position", C.c_double * 3)]
+
+
+def build_opts(darken: float = 0.0, position=None) -> BuildOpts_t:
+    """Build options: `position` (world xyz) makes the light a point light."""
+    o = BuildOpts_t()
+    o.darken = float(darken)
+    if position is not None:
+        o.positional = 1
+        o.position = _vec3(position)
+    return o
 
 
 class Camera_t(C.Structure):
@@ -96,7 +107,8 @@ SIGNATURES = {
     "vi_volume_to_bricks": ([C.POINTER(Volume_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_volume_minmax_bytes": ([C.c_int, C.c_int], C.c_size_t),
     "vi_volume_minmax": ([C.POINTER(Volume_t), C.c_int, C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
-    "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Slices_t)], C.c_int),
+    "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(BuildOpts_t),
+                        C.POINTER(Slices_t)], C.c_int),
     "vi_build_attenuation": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_double), C.c_int, C.c_int,
                               C.c_int, C.c_int, C.POINTER(BuildOpts_t), C.c_void_p, C.POINTER(Slices_t),
                               C.c_void_p], C.c_int),
@@ -273,7 +285,7 @@ class Slices:
     def frame(self) -> dict:
         s = self.s
         return {"L": list(s.L), "U": list(s.U), "V": list(s.V), "c": list(s.c), "dmin": s.dmin, "dmax": s.dmax,
-                "ds": s.ds, "R": s.R, "n": s.n, "res": s.res}
+                "ds": s.ds, "R": s.R, "n": s.n, "res": s.res, "positional": s.positional, "P": list(s.P)}
 
 
 def camera(cam: dict) -> Camera_t:
@@ -342,25 +354,31 @@ def volume_bytes(n: int, dtype: int, layout: int) -> int:
     return int(lib().vi_volume_bytes(n, dtype, layout))
 
 
-def light_frame(light_dir, n: int, res: int, dtype: int = VI_F32, layout: int = VI_STACK_TILED) -> Slices:
+def light_frame(light_dir, n: int, res: int, dtype: int = VI_F32, layout: int = VI_STACK_TILED,
+                position=None) -> Slices:
     s = Slices_t()
-    _check(lib().vi_light_frame(_vec3(light_dir), int(n), int(res), int(dtype), int(layout), C.byref(s)))
+    ld = _vec3(light_dir) if light_dir is not None else None
+    _check(lib().vi_light_frame(ld, int(n), int(res), int(dtype), int(layout), C.byref(build_opts(0.0, position)),
+                                C.byref(s)))
     return Slices(None, s)
 
 
 def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: int, dtype: int = VI_F32,
                       out: torch.Tensor | None = None, stream=None, layout: int = VI_STACK_TILED,
-                      darken: float = 0.0) -> Slices:
+                      darken: float = 0.0, position=None) -> Slices:
     """Attenuation stack for `light_dir` (section 3.2.1, Alg. 1); returns the stack
     (float32 transmittance, or bfloat16 optical depth) and its descriptor.  `darken`
-    is the exponent m of section 4's (1+alpha)^m slab compensation (0 = off)."""
+    is the exponent m of section 4's (1+alpha)^m slab compensation (0 = off);
+    `position` (world xyz) builds for a point light there instead (`light_dir`
+    is then ignored and may be None)."""
     if out is None:
         out = stack_buffer(n_slices, slice_res, dtype, vol.data.device, layout)
     if out.numel() * out.element_size() < slices_bytes(n_slices, slice_res, dtype, layout):
         raise ValueError("stack buffer too small")
     s = Slices_t()
-    _check(lib().vi_build_attenuation(C.byref(vol.s), C.byref(tf.s), _vec3(light_dir), int(n_slices),
-                                      int(slice_res), int(dtype), int(layout), C.byref(BuildOpts_t(float(darken))),
+    ld = _vec3(light_dir) if light_dir is not None else None
+    _check(lib().vi_build_attenuation(C.byref(vol.s), C.byref(tf.s), ld, int(n_slices),
+                                      int(slice_res), int(dtype), int(layout), C.byref(build_opts(darken, position)),
                                       C.c_void_p(out.data_ptr()), C.byref(s), _stream(stream)))
     return Slices(out, s)
 
@@ -434,16 +452,16 @@ class Server:
     def submit(self, vol_id: int, light_dir, n_slices: int, slice_res: int, cam: dict, mode: str,
                step_vox: float, opts: dict | None = None, out: torch.Tensor | None = None,
                samples: torch.Tensor | None = None, dtype: int = VI_F32, device="cuda",
-               layout: int = VI_STACK_TILED, darken: float = 0.0) -> tuple:
+               layout: int = VI_STACK_TILED, darken: float = 0.0, position=None) -> tuple:
         W, H = int(cam["width"]), int(cam["height"])
         if out is None:
             out = torch.empty((H, W, 4), dtype=torch.float32, device=device)
         r = Request_t()
         r.vol_id = int(vol_id)
-        r.light_dir = _vec3(light_dir)
+        r.light_dir = _vec3(light_dir if light_dir is not None else (0.0, 0.0, 1.0))
         r.n_slices, r.slice_res, r.slice_dtype = int(n_slices), int(slice_res), int(dtype)
         r.slice_layout = int(layout)
-        r.build = BuildOpts_t(float(darken))
+        r.build = build_opts(darken, position)
         r.camera = camera(cam)
         r.mode = MODES[mode]
         r.step_vox = float(step_vox)

@@ -49,6 +49,25 @@ def test_light_frame_matches_oracle(light):
         assert f[k] == pytest.approx(g[k], abs=4e-16)
 
 
+@pytest.mark.parametrize("pos", [[0.5, 0.5, 2.5], [-1.2, 0.3, 1.9], [3.0, -2.0, -1.0], [0.5, 1.37, 0.5]])
+def test_point_light_frame_matches_oracle(pos):
+    """Point light (section 3.2.1's L_p with a light position): the descriptor
+    the library computes equals the oracle's frame."""
+    f = vi.light_frame(None, 17, 33, position=pos).frame()
+    g = O.light_frame(None, 17, 33, position=pos)
+    assert f["positional"] == 1 and g["positional"] == 1
+    for k in ("L", "U", "V", "c", "P"):
+        np.testing.assert_allclose(f[k], g[k], atol=4e-16)
+    for k in ("dmin", "dmax", "ds", "R"):
+        assert f[k] == pytest.approx(g[k], rel=1e-14, abs=1e-15)
+
+
+@pytest.mark.parametrize("pos", [[0.5, 0.5, 0.5], [0.5, 0.5, 1.3], [1.0, 1.0, 1.0], [math.nan, 0, 3],
+                                 [math.inf, 0, 0]])
+def test_point_light_inside_or_invalid_rejected(pos):
+    assert _err(lambda: vi.light_frame(None, 8, 8, position=pos)) == -1
+
+
 def test_slices_bytes():
     assert vi.slices_bytes(512, 1024, vi.VI_F32) == 512 * 1024 * 1024 * 4
     assert vi.slices_bytes(512, 1024, vi.VI_BF16) == 512 * 1024 * 1024 * 2
@@ -116,6 +135,14 @@ def test_build_validation_errors():
     assert _build(_Fake(), darken=math.nan) == -1
     assert _build(_Fake(), darken=65.0) == -1
     assert _build(_Fake(), light=(0, 0, 0)) == -1
+    lib, s = vi.lib(), vi.Slices_t()
+    inside = vi.build_opts(0.0, (0.5, 0.5, 1.2))              # point light inside the cube's sphere
+    assert lib.vi_build_attenuation(C.byref(f.vol), C.byref(f.tf), None, 8, 8, vi.VI_F32, vi.VI_STACK_ROWS,
+                                    C.byref(inside), C.c_void_p(0x30000), C.byref(s), C.c_void_p(0)) == -1
+    bad = vi.build_opts(0.0, (0.5, 0.5, 3.0))
+    bad.positional = 2
+    assert lib.vi_build_attenuation(C.byref(f.vol), C.byref(f.tf), None, 8, 8, vi.VI_F32, vi.VI_STACK_ROWS,
+                                    C.byref(bad), C.c_void_p(0x30000), C.byref(s), C.c_void_p(0)) == -1
     assert _build(_Fake(), dt=vi.VI_U16) == -2
     assert _build(_Fake(), desc=False) == -1
     assert _build(_Fake(), n=4096, res=8192) == -2   # tiled stack >= 4 GiB
@@ -194,6 +221,18 @@ def test_render_validation_errors():
     nolight = _desc(f)
     nolight.L = (C.c_double * 3)(0, 0, 0)
     assert _render(f, nolight, mode=4) == -1
+    # point light: the cone gather is defined for directional lights only
+    pt = vi.light_frame(None, 8, 8, position=[0.5, 0.5, 3.0]).s
+    pt.data, pt.vol_n, pt.tag = 0x50000, f.vol.n, 0
+    assert _render(f, pt, mode=3) == -2
+    assert "directional" in vi.lib().vi_last_error().decode()
+    bad = vi.light_frame(None, 8, 8, position=[0.5, 0.5, 3.0]).s
+    bad.data, bad.vol_n, bad.tag = 0x50000, f.vol.n, 0
+    bad.P = (C.c_double * 3)(math.nan, 0, 0)
+    assert _render(f, bad, mode=1) == -1
+    bad.P = (C.c_double * 3)(0.5, 0.5, 3.0)
+    bad.dmin = 0.0
+    assert _render(f, bad, mode=2) == -1
 
 
 def test_tag_distinguishes_inputs():

@@ -37,13 +37,20 @@ def _requests(vols, count, seed):
         cam = W.camera_orbit(w, h, float(rng.uniform(0, 2 * math.pi)), math.radians(20))
         mode = ["shell", "cone", "cone5", "shadow", "phong"][int(rng.integers(5))]
         darken = 1.0 if li == 2 else 0.0          # the compensated build is part of a stack's identity
-        reqs.append(dict(vol=vi_, light=light, n=N, res=min(2 * N, 1024), cam=cam, mode=mode, darken=darken))
+        # light 0 becomes a point light two units up-stream of the centre
+        # where the mode is defined for one (not the cone)
+        pos = None
+        if li == 0 and mode in ("shell", "shadow", "phong"):
+            pos = [0.5 - 2.0 * c for c in light]
+        reqs.append(dict(vol=vi_, light=light, n=N, res=min(2 * N, 1024), cam=cam, mode=mode, darken=darken,
+                         pos=pos))
     return reqs
 
 
 def _alone(vols, r, layout=vi.VI_STACK_TILED):
     _, v, tf = vols[r["vol"]]
-    st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"], layout=layout, darken=r["darken"])
+    st = vi.build_attenuation(v, tf, r["light"], r["n"], r["res"], layout=layout, darken=r["darken"],
+                              position=r["pos"])
     m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
     cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
     img = vi.render(v, tf, st, r["cam"], m, 0.5, extra, samples=cnt)
@@ -54,7 +61,7 @@ def _alone(vols, r, layout=vi.VI_STACK_TILED):
 def _submit(srv, ids, r, samples=None, layout=vi.VI_STACK_TILED):
     m, extra = ("cone", {"cone_grid": 5}) if r["mode"] == "cone5" else (r["mode"], {})
     return srv.submit(ids[r["vol"]], r["light"], r["n"], r["res"], r["cam"], m, 0.5, extra, samples=samples,
-                      layout=layout, darken=r["darken"])
+                      layout=layout, darken=r["darken"], position=r["pos"])
 
 
 @pytest.mark.parametrize("layout", [vi.VI_STACK_TILED, vi.VI_STACK_ROWS])
@@ -75,6 +82,7 @@ def test_mixed_burst_equals_frames_rendered_alone(layout):
     assert st["completed"] == len(reqs)
     assert st["mean_frames_per_launch"] > 1.0          # launches really mix frames
     assert st["stack_hits"] > 0                         # the light repeats: stacks are reused
+    assert any(r["pos"] is not None for r in reqs) and any(r["pos"] is None for r in reqs)
     for i, r in enumerate(reqs):
         ref, n_ref = _alone(vols, r, layout)
         assert torch.equal(subs[i][1], ref), f"request {i} differs from its standalone render"
