@@ -36,17 +36,17 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
                   "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
 MEASURED_TRAFFIC = {
-    # large workload (512^3 u16 bricks, 16^3 empty-space cells, 512 x 1024^2 f32 stack in rows,
-    # 1920x1080), light 0
-    ("render_cone", "large", "rows", 16): {
-        "sha256": "1d5c4c99a31317da0f18e40c1e47bbafc5de9e6682d887500e93135698bd83bd",
-        "fetch_kib": 79213.5, "write_kib": 34587.03},
-    ("render_shell", "large", "rows", 16): {
-        "sha256": "1d5c4c99a31317da0f18e40c1e47bbafc5de9e6682d887500e93135698bd83bd",
-        "fetch_kib": 69014.75, "write_kib": 34372.97},
-    ("build", "large", "rows", 16): {       # build kernel plus the border kernel
-        "sha256": "feffe886bd1cf3d7d3447d285ae881e86dd21a40ab43a2fa4ef710ed66a986ec",
-        "fetch_kib": 64654.0 + 12.5, "write_kib": 2335758.31 + 28952.78},
+    # large workload (512^3 u16 in the quad layout, 16^3 empty-space cells, 512 x 1024^2 f32 stack in
+    # rows, 1920x1080), light 0
+    ("render_cone", "large", "rows", 16, "quads"): {
+        "sha256": "4ddaa76dcb691aed4be35c602e2c908db21d39188a723419fa578bd94520692c",
+        "fetch_kib": 125650.31, "write_kib": 34832.34},
+    ("render_shell", "large", "rows", 16, "quads"): {
+        "sha256": "4ddaa76dcb691aed4be35c602e2c908db21d39188a723419fa578bd94520692c",
+        "fetch_kib": 113624.25, "write_kib": 34579.47},
+    ("build", "large", "rows", 16, "quads"): {       # build kernel plus the border kernel
+        "sha256": "04ecfc298e988099158c26cc3bbddd349614a429c2a27ce32912ef86d3427e5e",
+        "fetch_kib": 198002.25 + 16.5, "write_kib": 2332031.41 + 28953.44},
 }
 
 
@@ -59,9 +59,9 @@ def source_sha(kind: str) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, layout: str, cell: int):
+def measured_traffic(kernel: str, workload: str, layout: str, cell: int, vol_layout: str):
     """HBM bytes per launch of `kernel` on `workload`, or None (not measured for these sources)."""
-    m = MEASURED_TRAFFIC.get((kernel, workload, layout, cell))
+    m = MEASURED_TRAFFIC.get((kernel, workload, layout, cell, vol_layout))
     kind = "build" if kernel == "build" else "render"
     if not m or m["sha256"] != source_sha(kind):
         return None
@@ -201,7 +201,7 @@ def serving_inputs(vol_sizes, dev, vessels=True):
     vols = []
     for i, N in enumerate(vol_sizes):
         raw = W.serving_volume(N, i, vessels=vessels)
-        vols.append((vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(16), vi.TF.from_numpy(tab, dev)))
+        vols.append((vi.Volume.from_numpy(raw, dev).to_quads().with_minmax(16), vi.TF.from_numpy(tab, dev)))
     return vols
 
 
@@ -225,7 +225,7 @@ def serving_quick(dev, budget=16 << 30, count=300):
     rate = 0.9 * cap
     reqs = W.serving_requests(count, sizes, rate, seed=5)
     serve(vols, reqs[:30], budget)                 # warm-up
-    out = {"volumes": "8 resident u16 phantoms 128^3-320^3 (bricks + empty-space map)",
+    out = {"volumes": "8 resident u16 phantoms 128^3-320^3 (quad layout + empty-space map)",
            "requests": count, "rate_hz": round(rate, 2), "sequential_capacity_fps": cap,
            "served": serve(vols, reqs, budget), "sequential": sequential(vols, reqs, budget)}
     return out
@@ -258,7 +258,7 @@ def scaling_sweep(dev, slices=(64, 128, 256, 512), resolutions=(128, 256, 512, 1
     from paper_2008_06134_amd import workloads as W
     w = W.WORKLOADS["large"]
     raw, tab = w.volume(), w.tf()
-    vol = vi.Volume.from_numpy(raw, dev).to_bricks().with_minmax(16)
+    vol = vi.Volume.from_numpy(raw, dev).to_quads().with_minmax(16)
     tf = vi.TF.from_numpy(tab, dev)
     light, cam = w.lights()[0], w.camera(0)
     img = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device=dev)
@@ -305,7 +305,8 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     tf = vi.TF.from_numpy(tab, dev)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    vol = vol_lin.to_bricks().with_minmax(args.cell)  # one-off per volume: bricks + empty-space map
+    # one-off per volume: brick or quad layout + empty-space map
+    vol = (vol_lin.to_quads() if args.volume_layout == "quads" else vol_lin.to_bricks()).with_minmax(args.cell)
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - tb) * 1e3
     del vol_lin
@@ -381,6 +382,10 @@ def main():
                     help="edge in voxels of the empty-space map's cells")
     ap.add_argument("--stack-layout", default="rows", choices=["tiled", "rows"],
                     help="stack layout of every stack built (rows: one 8-byte load per bilinear row)")
+    ap.add_argument("--volume-layout", default="auto", choices=["auto", "bricks", "quads"],
+                    help="4x4x4 bricks, or quads (each slot its voxel's 2x2 x/y neighbourhood: 4x the bytes, "
+                         "two loads per trilinear footprint); auto = quads, except bricks for the 1024^3 "
+                         "precision workload (where quads measured slower)")
     ap.add_argument("--point-light", type=float, default=0.0, metavar="DIST",
                     help="point lights DIST world units from the volume centre (against each light "
                          "direction) instead of directional lights; modes shadow, shell, phong, none")
@@ -389,6 +394,8 @@ def main():
     args = ap.parse_args()
     global STACK_LAYOUT
     STACK_LAYOUT = {"tiled": 0, "rows": 1}[args.stack_layout]
+    if args.volume_layout == "auto":
+        args.volume_layout = "bricks" if args.workload == "precision" else "quads"
     if args.copy_probe:
         import torch
         a = torch.ones(args.copy_probe * 2 ** 18, dtype=torch.float32, device="cuda:0")
@@ -460,7 +467,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": None if args.point_light else measured_traffic(dom, w.name, args.stack_layout,
-                                                                           args.cell),
+                                                                           args.cell, args.volume_layout),
                 "bytes_per_launch": per_launch, "avg_launch_ms": round(float(avg_ms), 4)}
     kernels = {"volume_prepare_ms_once": round(m["prep_ms"], 3),
                "build_ms_mean": round(float(np.mean(build_ms)), 4),
@@ -485,7 +492,8 @@ def main():
         "data": "synthetic",
         "fps": round(frames / wall, 3),
         "config": {"workload": (f"{w.name}: {w.N}^3 {'f16' if precision else raw.dtype} phantom "
-                                f"(4x4x4 bricks, {args.cell}^3 empty-space cells), "
+                                f"({'4x4x4 bricks' if args.volume_layout == 'bricks' else '4x4x4 bricks of 2x2 quads'}, "
+                                f"{args.cell}^3 empty-space cells), "
                                 f"{w.n_slices} slices x {w.res}^2 {'bf16' if precision else 'f32'} "
                                 f"({args.stack_layout}), "
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "

@@ -101,8 +101,14 @@ typedef enum { VI_CAM_ORTHO = 0, VI_CAM_PERSP = 1 } vi_camera_kind;
  *     at ((z/4)*nb*nb + (y/4)*nb + x/4)*64 + (z%4)*16 + (y%4)*4 + x%4,
  *     NP^3 elements (padding never read).  A trilinear footprint then
  *     touches one to eight 64-element bricks instead of four rows, which is
- *     what the gathers of both passes pay for. */
-typedef enum { VI_LAYOUT_LINEAR = 0, VI_LAYOUT_BRICK4 = 1 } vi_layout;
+ *     what the gathers of both passes pay for.
+ *   VI_LAYOUT_QUAD4: the slots of VI_LAYOUT_BRICK4, each holding the 2x2
+ *     neighbourhood of its voxel in one 4-element unit: slot (x,y,z) =
+ *     { v(x,y,z), v(x+1,y,z), v(x,y+1,z), v(x+1,y+1,z) } with indices
+ *     clamped to N-1, at elements 4*brick_offset(x,y,z) + 0..3 (4*NP^3
+ *     elements, 4x the bytes).  A trilinear footprint is then two loads (one
+ *     per z) instead of eight; results are the same bit for bit. */
+typedef enum { VI_LAYOUT_LINEAR = 0, VI_LAYOUT_BRICK4 = 1, VI_LAYOUT_QUAD4 = 2 } vi_layout;
 
 /* A cubic volume in device memory.  `scale` maps raw values to [0,1]
  * (u8: 1/255, u16 12-bit data: 1/4095, f16/f32 normalised: 1).
@@ -117,9 +123,9 @@ typedef enum { VI_LAYOUT_LINEAR = 0, VI_LAYOUT_BRICK4 = 1 } vi_layout;
 typedef struct {
     const void* data;
     int dtype;  /* VI_U8, VI_U16, VI_F16 or VI_F32 */
-    int n;      /* edge length N >= 2; storage < 4 GiB */
+    int n;      /* edge length N >= 2; < 2^32 bytes per copy of the voxels */
     float scale;
-    int layout; /* VI_LAYOUT_LINEAR (0) or VI_LAYOUT_BRICK4 */
+    int layout; /* VI_LAYOUT_LINEAR (0), VI_LAYOUT_BRICK4 or VI_LAYOUT_QUAD4 */
     const float* minmax; /* NULL, or ceil(n/cell)^3 (min, max) float pairs, cells x fastest */
     int cell;            /* cell edge in voxels (4, 8, 16 or 32) when minmax is set */
 } vi_volume;
@@ -246,6 +252,14 @@ size_t vi_volume_bytes(int n, int dtype, int layout);
  * Errors: VI_E_INVALID_ARG for NULL pointers or a source that is not
  * linear; VI_E_UNSUPPORTED for sizes beyond the limits; VI_E_DEVICE. */
 int vi_volume_to_bricks(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream);
+
+/* Copy a linear volume into the quad layout (VI_LAYOUT_QUAD4): `d_dst`
+ * (device, vi_volume_bytes(n, dtype, VI_LAYOUT_QUAD4) bytes, aligned to
+ * 4 elements, caller-owned) receives every voxel's 2x2 neighbourhood and
+ * `out` describes it.  One kernel launch on `stream`; results computed from
+ * it equal those from the linear volume bit for bit.  Errors as
+ * vi_volume_to_bricks. */
+int vi_volume_to_quads(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream);
 
 /* Bytes of the empty-space map of a volume of edge n with cells of `cell`
  * voxels: ceil(n/cell)^3 * 8 (0 for invalid arguments). */

@@ -41,10 +41,22 @@ size_t elem_size(int dt)
     }
 }
 
+bool known_layout(int layout)
+{
+    return layout == VI_LAYOUT_LINEAR || layout == VI_LAYOUT_BRICK4 || layout == VI_LAYOUT_QUAD4;
+}
+
+// bytes of one copy of the voxels (the quad layout stores four copies):
+// kernels index voxels (quad slots) with 32-bit offsets, so this stays
+// below 4 GiB
+double voxel_storage(int n, int dtype, int layout)
+{
+    const double e = (double)(layout == VI_LAYOUT_LINEAR ? (uint32_t)n : vi::round_up((uint32_t)n, 4u));
+    return e * e * e * (double)elem_size(dtype);
+}
 double volume_storage(int n, int dtype, int layout)
 {
-    const double e = (double)(layout == VI_LAYOUT_BRICK4 ? vi::round_up((uint32_t)n, 4u) : (uint32_t)n);
-    return e * e * e * (double)elem_size(dtype);
+    return voxel_storage(n, dtype, layout) * (layout == VI_LAYOUT_QUAD4 ? 4.0 : 1.0);
 }
 
 int check_volume(const vi_volume* v)
@@ -52,12 +64,12 @@ int check_volume(const vi_volume* v)
     if (!v || !v->data) return fail(VI_E_INVALID_ARG, "volume or its data pointer is NULL");
     if (v->dtype != VI_U8 && v->dtype != VI_U16 && v->dtype != VI_F16 && v->dtype != VI_F32)
         return fail(VI_E_UNSUPPORTED, "volume dtype %d not supported", v->dtype);
-    if (v->layout != VI_LAYOUT_LINEAR && v->layout != VI_LAYOUT_BRICK4)
-        return fail(VI_E_UNSUPPORTED, "volume layout %d not supported", v->layout);
+    if (!known_layout(v->layout)) return fail(VI_E_UNSUPPORTED, "volume layout %d not supported", v->layout);
     if (v->n < 2) return fail(VI_E_INVALID_ARG, "volume edge %d < 2", v->n);
-    const double bytes = volume_storage(v->n, v->dtype, v->layout);
+    const double bytes = voxel_storage(v->n, v->dtype, v->layout);
     if (bytes >= 4294967296.0) return fail(VI_E_UNSUPPORTED, "volume of %.0f bytes exceeds 4 GiB", bytes);
-    if (((uintptr_t)v->data) % elem_size(v->dtype)) return fail(VI_E_INVALID_ARG, "volume pointer misaligned");
+    const size_t align = elem_size(v->dtype) * (v->layout == VI_LAYOUT_QUAD4 ? 4 : 1);
+    if (((uintptr_t)v->data) % align) return fail(VI_E_INVALID_ARG, "volume pointer misaligned");
     if (!(v->scale > 0.0f) || !isfinite(v->scale)) return fail(VI_E_INVALID_ARG, "volume scale must be > 0");
     if (v->minmax) {
         if (v->cell != 4 && v->cell != 8 && v->cell != 16 && v->cell != 32)
@@ -90,7 +102,7 @@ int check_tf(const vi_tf* tf)
 // per-axis offset strides of a volume layout (y, z)
 void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
 {
-    if (v->layout == VI_LAYOUT_BRICK4) {
+    if (v->layout != VI_LAYOUT_LINEAR) {  // bricks, or quads in brick order
         const uint32_t nb = vi::round_up((uint32_t)v->n, 4u) / 4u;
         *sy = nb * 64u;
         *sz = nb * nb * 64u;
@@ -241,26 +253,39 @@ size_t vi_slices_bytes(int n, int res, int dt, int sl)
 size_t vi_volume_bytes(int n, int dtype, int layout)
 {
     if (n < 2 || elem_size(dtype) == 0 || dtype == VI_BF16) return 0;
-    if (layout != VI_LAYOUT_LINEAR && layout != VI_LAYOUT_BRICK4) return 0;
+    if (!known_layout(layout)) return 0;
     return (size_t)volume_storage(n, dtype, layout);
 }
 
-int vi_volume_to_bricks(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream)
+static int relayout(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream, int layout)
 {
     clear_err();
     int rc;
     if ((rc = check_volume(src)) != VI_OK) return rc;
     if (src->layout != VI_LAYOUT_LINEAR) return fail(VI_E_INVALID_ARG, "source volume is not linear");
     if (!d_dst || !out) return fail(VI_E_INVALID_ARG, "NULL destination or descriptor");
-    if (((uintptr_t)d_dst) % elem_size(src->dtype)) return fail(VI_E_INVALID_ARG, "destination misaligned");
-    if (volume_storage(src->n, src->dtype, VI_LAYOUT_BRICK4) >= 4294967296.0)
-        return fail(VI_E_UNSUPPORTED, "bricked volume exceeds 4 GiB");
-    hipError_t e = vi::launch_to_bricks(src->data, d_dst, src->dtype, src->n, (hipStream_t)stream);
-    if (e != hipSuccess) return fail(VI_E_DEVICE, "brick launch failed: %s", hipGetErrorString(e));
+    const size_t align = elem_size(src->dtype) * (layout == VI_LAYOUT_QUAD4 ? 4 : 1);
+    if (((uintptr_t)d_dst) % align) return fail(VI_E_INVALID_ARG, "destination misaligned");
+    if (voxel_storage(src->n, src->dtype, layout) >= 4294967296.0)
+        return fail(VI_E_UNSUPPORTED, "bricked volume exceeds 4 GiB per copy of the voxels");
+    hipError_t e = layout == VI_LAYOUT_QUAD4
+                       ? vi::launch_to_quads(src->data, d_dst, src->dtype, src->n, (hipStream_t)stream)
+                       : vi::launch_to_bricks(src->data, d_dst, src->dtype, src->n, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VI_E_DEVICE, "layout launch failed: %s", hipGetErrorString(e));
     *out = *src;
     out->data = d_dst;
-    out->layout = VI_LAYOUT_BRICK4;
+    out->layout = layout;
     return VI_OK;
+}
+
+int vi_volume_to_bricks(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream)
+{
+    return relayout(src, d_dst, out, stream, VI_LAYOUT_BRICK4);
+}
+
+int vi_volume_to_quads(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream_t stream)
+{
+    return relayout(src, d_dst, out, stream, VI_LAYOUT_QUAD4);
 }
 
 size_t vi_volume_minmax_bytes(int n, int cell)

@@ -186,6 +186,7 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
 template <typename VT>
 static hipError_t launch_build_l(const BuildParams& p, hipStream_t s)
 {
+    if (p.vol_layout == VI_LAYOUT_QUAD4) return launch_build_t<VT, VI_LAYOUT_QUAD4>(p, s);
     return p.vol_layout == VI_LAYOUT_BRICK4 ? launch_build_t<VT, VI_LAYOUT_BRICK4>(p, s)
                                             : launch_build_t<VT, VI_LAYOUT_LINEAR>(p, s);
 }

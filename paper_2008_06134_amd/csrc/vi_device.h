@@ -52,20 +52,54 @@ struct VolIndex {
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t vol_ox(const VolIndex& I, int x)
 {
-    if (LAYOUT == VI_LAYOUT_BRICK4) return ((uint32_t)x >> 2) * 64u + ((uint32_t)x & 3u);
+    if (LAYOUT != VI_LAYOUT_LINEAR) return ((uint32_t)x >> 2) * 64u + ((uint32_t)x & 3u);
     return (uint32_t)x;
 }
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t vol_oy(const VolIndex& I, int y)
 {
-    if (LAYOUT == VI_LAYOUT_BRICK4) return ((uint32_t)y >> 2) * I.sy + ((uint32_t)y & 3u) * 4u;
+    if (LAYOUT != VI_LAYOUT_LINEAR) return ((uint32_t)y >> 2) * I.sy + ((uint32_t)y & 3u) * 4u;
     return (uint32_t)y * I.sy;
 }
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t vol_oz(const VolIndex& I, int z)
 {
-    if (LAYOUT == VI_LAYOUT_BRICK4) return ((uint32_t)z >> 2) * I.sz + ((uint32_t)z & 3u) * 16u;
+    if (LAYOUT != VI_LAYOUT_LINEAR) return ((uint32_t)z >> 2) * I.sz + ((uint32_t)z & 3u) * 16u;
     return (uint32_t)z * I.sz;
+}
+
+// The four normalised values of quad slot `q` (VI_LAYOUT_QUAD4): one load
+// of 4 elements, each converted exactly as voxel_norm converts it.
+template <typename VT>
+__device__ __forceinline__ float4 quad_norm(const VT* __restrict__ v, uint32_t q, float scale);
+template <>
+__device__ __forceinline__ float4 quad_norm<uint8_t>(const uint8_t* __restrict__ v, uint32_t q, float scale)
+{
+    const uint32_t w = ((const uint32_t*)v)[q];
+    return make_float4(clampf01((float)(w & 0xffu) * scale), clampf01((float)((w >> 8) & 0xffu) * scale),
+                       clampf01((float)((w >> 16) & 0xffu) * scale), clampf01((float)(w >> 24) * scale));
+}
+template <>
+__device__ __forceinline__ float4 quad_norm<uint16_t>(const uint16_t* __restrict__ v, uint32_t q, float scale)
+{
+    const uint2 w = ((const uint2*)v)[q];
+    return make_float4(clampf01((float)(w.x & 0xffffu) * scale), clampf01((float)(w.x >> 16) * scale),
+                       clampf01((float)(w.y & 0xffffu) * scale), clampf01((float)(w.y >> 16) * scale));
+}
+template <>
+__device__ __forceinline__ float4 quad_norm<__half>(const __half* __restrict__ v, uint32_t q, float scale)
+{
+    const uint2 w = ((const uint2*)v)[q];
+    return make_float4(clampf01(__half2float(__ushort_as_half((unsigned short)(w.x & 0xffffu))) * scale),
+                       clampf01(__half2float(__ushort_as_half((unsigned short)(w.x >> 16))) * scale),
+                       clampf01(__half2float(__ushort_as_half((unsigned short)(w.y & 0xffffu))) * scale),
+                       clampf01(__half2float(__ushort_as_half((unsigned short)(w.y >> 16))) * scale));
+}
+template <>
+__device__ __forceinline__ float4 quad_norm<float>(const float* __restrict__ v, uint32_t q, float scale)
+{
+    const float4 w = ((const float4*)v)[q];
+    return make_float4(clampf01(w.x * scale), clampf01(w.y * scale), clampf01(w.z * scale), clampf01(w.w * scale));
 }
 
 // Trilinear sample at offset-voxel coordinates h = g - M (g = p*N - 1/2),
@@ -77,6 +111,20 @@ __device__ __forceinline__ float sample_volume(const VT* __restrict__ vol, const
     float fx = floorf(hx), fy = floorf(hy), fz = floorf(hz);
     float wx = hx - fx, wy = hy - fy, wz = hz - fz;
     int x0 = (int)fx + M, y0 = (int)fy + M, z0 = (int)fz + M;
+    if (LAYOUT == VI_LAYOUT_QUAD4) {
+        // the slot of the clamped lower corner holds the x/y neighbours,
+        // themselves clamped; below the first voxel both x (or y) corners
+        // clamp to voxel 0, which a zero weight reproduces exactly
+        const uint32_t xy = vol_ox<LAYOUT>(I, clampi(x0, 0, N - 1)) + vol_oy<LAYOUT>(I, clampi(y0, 0, N - 1));
+        const float4 a = quad_norm(vol, vol_oz<LAYOUT>(I, clampi(z0, 0, N - 1)) + xy, scale);
+        const float4 b = quad_norm(vol, vol_oz<LAYOUT>(I, clampi(z0 + 1, 0, N - 1)) + xy, scale);
+        if (x0 < 0) wx = 0.0f;
+        if (y0 < 0) wy = 0.0f;
+        const float c00 = fmaf(wx, a.y - a.x, a.x), c01 = fmaf(wx, a.w - a.z, a.z);
+        const float c10 = fmaf(wx, b.y - b.x, b.x), c11 = fmaf(wx, b.w - b.z, b.z);
+        const float c0 = fmaf(wy, c01 - c00, c00), c1 = fmaf(wy, c11 - c10, c10);
+        return fmaf(wz, c1 - c0, c0);
+    }
     const uint32_t xa = vol_ox<LAYOUT>(I, clampi(x0, 0, N - 1)), xb = vol_ox<LAYOUT>(I, clampi(x0 + 1, 0, N - 1));
     const uint32_t ya = vol_oy<LAYOUT>(I, clampi(y0, 0, N - 1)), yb = vol_oy<LAYOUT>(I, clampi(y0 + 1, 0, N - 1));
     const uint32_t za = vol_oz<LAYOUT>(I, clampi(z0, 0, N - 1)), zb = vol_oz<LAYOUT>(I, clampi(z0 + 1, 0, N - 1));

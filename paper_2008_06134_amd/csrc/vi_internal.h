@@ -123,6 +123,7 @@ hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int s
                                const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
                                hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStream_t s);
+hipError_t launch_to_quads(const void* src, void* dst, int dtype, int N, hipStream_t s);
 hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
                          int shift, float* out, hipStream_t s);
 

@@ -1,5 +1,6 @@
 // vi_layout.hip -- volume layout conversion: linear raw[z][y][x] -> 4x4x4
-// bricks (one 64-element brick = one 128-byte line at 16 bits).  One thread
+// bricks (one 64-element brick = one 128-byte line at 16 bits), or the quad
+// layout (brick order, every slot holding its voxel's 2x2 x/y neighbourhood).  One thread
 // per destination element, so the stores are fully coalesced; each run of
 // four source elements along x is contiguous.  A bit-exact copy: results
 // computed from the bricked volume equal those from the linear one.
@@ -43,6 +44,52 @@ hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStr
     }
 }
 
+// Quad layout: one thread per slot (brick order as above); the slot holds
+// its voxel's 2x2 neighbourhood in x and y, indices clamped to N-1, stored
+// with one 4-element store.  Padding slots hold zeros (never read).
+template <typename T, typename T4>
+__global__ __launch_bounds__(256) void to_quads_kernel(const T* __restrict__ src, T4* __restrict__ dst, int N,
+                                                       uint32_t nb, uint64_t total)
+{
+    const uint64_t idx = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    if (idx >= total) return;
+    const uint32_t b = (uint32_t)(idx >> 6), w = (uint32_t)(idx & 63u);
+    const uint32_t bx = b % nb, by = (b / nb) % nb, bz = b / (nb * nb);
+    const int x = (int)(bx * 4u + (w & 3u)), y = (int)(by * 4u + ((w >> 2) & 3u)), z = (int)(bz * 4u + (w >> 4));
+    T4 q;
+    q.x = q.y = q.z = q.w = T(0);
+    if (x < N && y < N && z < N) {
+        const int x1 = min(x + 1, N - 1), y1 = min(y + 1, N - 1);
+        const size_t r0 = ((size_t)z * N + y) * N, r1 = ((size_t)z * N + y1) * N;
+        q.x = src[r0 + x];
+        q.y = src[r0 + x1];
+        q.z = src[r1 + x];
+        q.w = src[r1 + x1];
+    }
+    dst[idx] = q;
+}
+
+template <typename T, typename T4>
+static hipError_t launch_q(const void* src, void* dst, int N, hipStream_t s)
+{
+    const uint32_t NP = round_up((uint32_t)N, 4u), nb = NP / 4u;
+    const uint64_t total = (uint64_t)NP * NP * NP;
+    const uint64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL((to_quads_kernel<T, T4>), dim3((uint32_t)blocks), dim3(256), 0, s, (const T*)src, (T4*)dst,
+                       N, nb, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_quads(const void* src, void* dst, int dtype, int N, hipStream_t s)
+{
+    switch (dtype) {
+    case VI_U8: return launch_q<uint8_t, uchar4>(src, dst, N, s);
+    case VI_U16:
+    case VI_F16: return launch_q<uint16_t, ushort4>(src, dst, N, s);
+    default: return launch_q<uint32_t, uint4>(src, dst, N, s);
+    }
+}
+
 // Empty-space map: one thread per cell, min/max of the normalised voxel
 // values over the cell's voxels plus one more along each axis (clamped).
 template <typename VT, int LAYOUT>
@@ -61,7 +108,10 @@ __global__ __launch_bounds__(256) void minmax_kernel(const VT* __restrict__ vol,
         for (int y = y0; y <= y1; ++y) {
             const uint32_t oy = oz + vol_oy<LAYOUT>(I, y);
             for (int x = x0; x <= x1; ++x) {
-                const float v = voxel_norm(vol, oy + vol_ox<LAYOUT>(I, x), scale);
+                // a quad slot's first element is its own voxel
+                const uint32_t o = oy + vol_ox<LAYOUT>(I, x);
+                const float v = LAYOUT == VI_LAYOUT_QUAD4 ? voxel_norm(vol + 4 * (size_t)o, 0u, scale)
+                                                          : voxel_norm(vol, o, scale);
                 lo = fminf(lo, v);
                 hi = fmaxf(hi, v);
             }
@@ -77,7 +127,10 @@ static hipError_t launch_mm(const void* vol, int layout, VolIndex I, int N, floa
     const uint32_t nc = ((uint32_t)N + (1u << shift) - 1) >> shift;
     const uint32_t cells = nc * nc * nc;
     dim3 grid((cells + 255) / 256), block(256);
-    if (layout == VI_LAYOUT_BRICK4)
+    if (layout == VI_LAYOUT_QUAD4)
+        hipLaunchKernelGGL((minmax_kernel<VT, VI_LAYOUT_QUAD4>), grid, block, 0, s, (const VT*)vol, I, N, scale,
+                           shift, nc, (float2*)out);
+    else if (layout == VI_LAYOUT_BRICK4)
         hipLaunchKernelGGL((minmax_kernel<VT, VI_LAYOUT_BRICK4>), grid, block, 0, s, (const VT*)vol, I, N, scale,
                            shift, nc, (float2*)out);
     else

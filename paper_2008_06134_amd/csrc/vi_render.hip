@@ -652,6 +652,7 @@ template <typename VT>
 static hipError_t launch_batch_vt(int layout, int sdt, int sl, int mode, const RenderFrame* f, const uint32_t* t,
                                   uint32_t n, int K, hipStream_t s)
 {
+    if (layout == VI_LAYOUT_QUAD4) return launch_batch_l<VT, VI_LAYOUT_QUAD4>(sdt, sl, mode, f, t, n, K, s);
     return layout == VI_LAYOUT_BRICK4 ? launch_batch_l<VT, VI_LAYOUT_BRICK4>(sdt, sl, mode, f, t, n, K, s)
                                       : launch_batch_l<VT, VI_LAYOUT_LINEAR>(sdt, sl, mode, f, t, n, K, s);
 }
@@ -714,6 +715,7 @@ static hipError_t launch_sdt(const RenderFrame& f, hipStream_t s)
 template <typename VT>
 static hipError_t launch_vt(const RenderFrame& f, hipStream_t s)
 {
+    if (f.vol_layout == VI_LAYOUT_QUAD4) return launch_sdt<VT, VI_LAYOUT_QUAD4>(f, s);
     return f.vol_layout == VI_LAYOUT_BRICK4 ? launch_sdt<VT, VI_LAYOUT_BRICK4>(f, s)
                                             : launch_sdt<VT, VI_LAYOUT_LINEAR>(f, s);
 }

@@ -29,7 +29,7 @@ class VIError(RuntimeError):
         self.code = code
 
 
-VI_LAYOUT_LINEAR, VI_LAYOUT_BRICK4 = 0, 1
+VI_LAYOUT_LINEAR, VI_LAYOUT_BRICK4, VI_LAYOUT_QUAD4 = 0, 1, 2
 VI_STACK_TILED, VI_STACK_ROWS = 0, 1
 
 
@@ -105,6 +105,7 @@ SIGNATURES = {
     "vi_slices_bytes": ([C.c_int, C.c_int, C.c_int, C.c_int], C.c_size_t),
     "vi_volume_bytes": ([C.c_int, C.c_int, C.c_int], C.c_size_t),
     "vi_volume_to_bricks": ([C.POINTER(Volume_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
+    "vi_volume_to_quads": ([C.POINTER(Volume_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_volume_minmax_bytes": ([C.c_int, C.c_int], C.c_size_t),
     "vi_volume_minmax": ([C.POINTER(Volume_t), C.c_int, C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(BuildOpts_t),
@@ -171,7 +172,8 @@ _DEFAULT_SCALE = {VI_U8: 1.0 / 255.0, VI_U16: 1.0 / 4095.0, VI_F16: 1.0, VI_F32:
 class Volume:
     """A device-resident cubic volume (u8, u16 -- stored as uint16 or its int16 bit
     pattern --, f16 or f32) and the scale mapping raw values to [0,1].  `data` is
-    raw[z][y][x] (linear layout) or the 4x4x4 brick layout of `to_bricks()`."""
+    raw[z][y][x] (linear layout), the 4x4x4 brick layout of `to_bricks()` or the quad
+    layout of `to_quads()`."""
 
     def __init__(self, data: torch.Tensor, scale: float | None = None, n: int | None = None,
                  layout: int = VI_LAYOUT_LINEAR):
@@ -200,16 +202,25 @@ class Volume:
             t = torch.from_numpy(raw).to(device)
         return Volume(t, scale)
 
-    def to_bricks(self, out: torch.Tensor | None = None, stream=None) -> "Volume":
-        """Copy into the 4x4x4 brick layout (vi_volume_to_bricks)."""
-        nbytes = int(lib().vi_volume_bytes(self.n, self.dtype, VI_LAYOUT_BRICK4))
+    def _relayout(self, layout: int, fn: str, out: torch.Tensor | None, stream) -> "Volume":
+        nbytes = int(lib().vi_volume_bytes(self.n, self.dtype, layout))
         if out is None:
             out = torch.empty(nbytes // self.data.element_size(), dtype=self.data.dtype, device=self.data.device)
         if out.numel() * out.element_size() < nbytes:
-            raise ValueError("brick buffer too small")
+            raise ValueError("layout buffer too small")
         res = Volume_t()
-        _check(lib().vi_volume_to_bricks(C.byref(self.s), C.c_void_p(out.data_ptr()), C.byref(res), _stream(stream)))
-        return Volume(out, self.scale, self.n, VI_LAYOUT_BRICK4)
+        _check(getattr(lib(), fn)(C.byref(self.s), C.c_void_p(out.data_ptr()), C.byref(res), _stream(stream)))
+        return Volume(out, self.scale, self.n, layout)
+
+    def to_bricks(self, out: torch.Tensor | None = None, stream=None) -> "Volume":
+        """Copy into the 4x4x4 brick layout (vi_volume_to_bricks)."""
+        return self._relayout(VI_LAYOUT_BRICK4, "vi_volume_to_bricks", out, stream)
+
+    def to_quads(self, out: torch.Tensor | None = None, stream=None) -> "Volume":
+        """Copy into the quad layout: brick order, each slot its voxel's 2x2 x/y
+        neighbourhood (vi_volume_to_quads); 4x the bytes, two loads per trilinear
+        footprint."""
+        return self._relayout(VI_LAYOUT_QUAD4, "vi_volume_to_quads", out, stream)
 
     def with_minmax(self, cell: int = 16, out: torch.Tensor | None = None, stream=None) -> "Volume":
         """The same volume with an empty-space map of `cell`^3-voxel cells (vi_volume_minmax)."""

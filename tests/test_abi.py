@@ -260,6 +260,21 @@ def test_volume_bytes_and_brick_validation():
     assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20001), C.byref(out), None) == -1
     src.layout = 7
     assert lib.vi_volume_to_bricks(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -2
+    # quads: four values per slot, aligned to a whole slot
+    assert vi.volume_bytes(33, vi.VI_U16, vi.VI_LAYOUT_QUAD4) == 4 * 36 ** 3 * 2
+    assert vi.volume_bytes(16, vi.VI_F32, vi.VI_LAYOUT_QUAD4) == 4 * 16 ** 3 * 4
+    src.layout = vi.VI_LAYOUT_QUAD4
+    assert lib.vi_volume_to_quads(C.byref(src), C.c_void_p(0x20000), C.byref(out), None) == -1  # not linear
+    src.layout = vi.VI_LAYOUT_LINEAR
+    assert lib.vi_volume_to_quads(C.byref(src), C.c_void_p(0x20004), C.byref(out), None) == -1  # 8-byte slots
+    assert lib.vi_volume_to_quads(C.byref(src), None, C.byref(out), None) == -1
+    big = vi.Volume_t(0x10000, vi.VI_U8, 1700, 1 / 255, vi.VI_LAYOUT_LINEAR)
+    assert lib.vi_volume_to_quads(C.byref(big), C.c_void_p(0x20000), C.byref(out), None) == -2  # >= 4 GiB of slots
+    # a quad volume whose pointer is not slot-aligned is rejected by the passes
+    f = _Fake(dtype=vi.VI_U16)
+    f.vol.layout = vi.VI_LAYOUT_QUAD4
+    f.vol.data = 0x10004
+    assert _build(f) == -1
     # stack buffers are padded to whole 8 x 4 tiles
     assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4
     # rows: res+2 rows of pitch res+4 rounded up to 4

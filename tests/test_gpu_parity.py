@@ -30,12 +30,13 @@ def _mode(m):
     return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
 
 
-def gpu_inputs(raw, tab, scale=None, bricks=True, cell=16):
-    """Device volume -- by default as the benchmark runs it: 4x4x4 bricks with an
-    empty-space map of 16^3-voxel cells -- and TF."""
+def gpu_inputs(raw, tab, scale=None, quads=True, cell=16):
+    """Device volume -- by default as the benchmark runs it: the quad layout
+    (4x4x4 bricks of 2x2 neighbourhoods) with an empty-space map of 16^3-voxel
+    cells -- and TF."""
     vol = vi.Volume.from_numpy(raw, DEV, scale)
-    if bricks:
-        vol = vol.to_bricks()
+    if quads:
+        vol = vol.to_quads()
     if cell:
         vol = vol.with_minmax(cell)
     return vol, vi.TF.from_numpy(tab, DEV)
@@ -264,25 +265,68 @@ def test_brick_layout_matches_its_definition(N):
     assert np.array_equal(got[off], raw)
 
 
+@pytest.mark.parametrize("N", [64, 33, 6])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float16, np.float32])
+def test_quad_layout_matches_its_definition(N, dtype):
+    """Slot (x,y,z) of the quad layout holds v(x,y,z), v(x+1,y,z), v(x,y+1,z),
+    v(x+1,y+1,z) (indices clamped to N-1) at 4 * brick offset."""
+    rng = np.random.default_rng(N + 7)
+    raw = rng.integers(0, 4096 if dtype == np.uint16 else 256, size=(N, N, N)).astype(dtype)
+    q = vi.Volume.from_numpy(raw, DEV).to_quads()
+    torch.cuda.synchronize()
+    NP = (N + 3) // 4 * 4
+    nb = NP // 4
+    got = q.data.cpu().numpy().view(raw.dtype)
+    assert got.size == 4 * NP ** 3
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    off = 4 * (((z // 4) * nb * nb + (y // 4) * nb + x // 4) * 64 + (z % 4) * 16 + (y % 4) * 4 + x % 4)
+    x1, y1 = np.minimum(x + 1, N - 1), np.minimum(y + 1, N - 1)
+    for c, (yy, xx) in enumerate([(y, x), (y, x1), (y1, x), (y1, x1)]):
+        assert np.array_equal(got[off + c], raw[z, yy, xx])
+
+
 @pytest.mark.parametrize("N,n,res", [(64, 32, 64), (33, 7, 50)])
-@pytest.mark.parametrize("mode", ["shell", "cone", "cone5"])
+@pytest.mark.parametrize("mode", ["shell", "cone", "cone5", "phong"])
 def test_bricked_volume_gives_bitwise_identical_results(N, n, res, mode):
+    """Linear, brick and quad layouts: identical stacks, images and sample counts."""
     raw = W.sphere_u8(N, radius=N * 0.35, density=180, noise=30, seed=N + 1)
     tab = W.tf_ramp()
-    lin, tf = gpu_inputs(raw, tab, bricks=False, cell=0)
-    br = lin.to_bricks()
+    lin, tf = gpu_inputs(raw, tab, quads=False, cell=0)
     light = [0.6, -0.3, -0.74]
     s1 = vi.build_attenuation(lin, tf, light, n, res)
-    s2 = vi.build_attenuation(br, tf, light, n, res)
-    torch.cuda.synchronize()
-    assert torch.equal(s1.dense(), s2.dense())   # padding texels of the tiles are never written
     m, extra = _mode(mode)
     cam = W.camera_orbit(70, 50, 2.2, 0.5)
-    a = vi.render(lin, tf, s1, cam, m, 0.5, extra)
-    s2.s.tag = 0  # stack built from the bricked copy, rendered with either
-    b = vi.render(br, tf, s2, cam, m, 0.5, extra)
+    a, na = gpu_render(lin, tf, s1, cam, m, 0.5, extra)
+    for other in (lin.to_bricks(), lin.to_quads(), lin.to_quads().with_minmax(8)):
+        s2 = vi.build_attenuation(other, tf, light, n, res)
+        torch.cuda.synchronize()
+        assert torch.equal(s1.dense(), s2.dense())   # padding texels of the tiles are never written
+        s2.s.tag = 0  # stack built from the other copy, rendered with either
+        b, nb = gpu_render(other, tf, s2, cam, m, 0.5, extra)
+        assert np.array_equal(a, b) and na == nb
+
+
+def test_quad_layout_point_light_and_map():
+    """The quad layout under a point light and with its own empty-space map
+    (which equals the linear volume's map)."""
+    raw = W.ct_phantom_u16(40, seed=9, vessels=True)
+    tab = W.tf_ct()
+    lin, tf = gpu_inputs(raw, tab, quads=False, cell=0)
+    q = lin.to_quads()
+    ml, mq = lin.with_minmax(8), q.with_minmax(8)
     torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    assert torch.equal(ml.minmax, mq.minmax)
+    pos = [1.8, 0.2, 1.5]
+    s1 = vi.build_attenuation(ml, tf, None, 30, 48, position=pos)
+    s2 = vi.build_attenuation(mq, tf, None, 30, 48, position=pos)
+    torch.cuda.synchronize()
+    assert torch.equal(s1.dense(), s2.dense())
+    cam = W.camera_orbit(64, 48, 0.9, 0.4)
+    s1.s.tag = 0  # one stack, rendered with either copy of the volume
+    for m in ("shadow", "shell"):
+        a, na = gpu_render(ml, tf, s1, cam, m, 0.5)
+        b, nb = gpu_render(mq, tf, s1, cam, m, 0.5)
+        assert np.array_equal(a, b) and na == nb
 
 
 @pytest.mark.parametrize("cell", [4, 8, 16, 32])

@@ -16,7 +16,7 @@ TOL_IMG = 1e-4
 
 
 def _inputs(raw, tab, scale=None):
-    vol = vi.Volume.from_numpy(raw, DEV, scale).to_bricks().with_minmax(16)
+    vol = vi.Volume.from_numpy(raw, DEV, scale).to_quads().with_minmax(16)
     return vol, vi.TF.from_numpy(tab, DEV)
 
 

@@ -27,7 +27,7 @@ POSITIONS = [[0.5, 0.5, 2.5], [-1.1, 1.7, 1.4], [2.2, -0.4, 0.3], [1.35, 1.35, 1
 
 
 def _inputs(raw, tab, cell=16):
-    vol = vi.Volume.from_numpy(raw, DEV).to_bricks()
+    vol = vi.Volume.from_numpy(raw, DEV).to_quads()
     if cell:
         vol = vol.with_minmax(cell)
     return vol, vi.TF.from_numpy(tab, DEV)

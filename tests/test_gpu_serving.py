@@ -19,7 +19,7 @@ def _volumes():
     vols = []
     for k, N in enumerate([48, 64, 80, 96]):
         raw = W.ct_phantom_u16(N, seed=100 + k, vessels=(k % 2 == 1))
-        v = vi.Volume.from_numpy(raw, DEV).to_bricks().with_minmax(16)
+        v = vi.Volume.from_numpy(raw, DEV).to_quads().with_minmax(16)
         vols.append((N, v, vi.TF.from_numpy(W.tf_ct(), DEV)))
     return vols
 
