@@ -52,13 +52,19 @@ __global__ __launch_bounds__(256) void border_kernel(ET* __restrict__ out, int n
     out[(size_t)k * rlayer + (uint32_t)(row + 1) * rpitch + rorg + col] = one;
 }
 
+// slabs per batch of the build loop
+#ifndef VI_BUILD_BATCH
+#define VI_BUILD_BATCH 4
+#endif
+constexpr int kBatch = VI_BUILD_BATCH;
+
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool DARKEN>
 __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 {
     extern __shared__ float s_alpha[];  // K alphas, then K next-opaque indices
     int* s_next = (int*)(s_alpha + P.K);
     for (int t = threadIdx.x; t < P.K; t += blockDim.x) s_alpha[t] = P.tf[4 * t + 3];
-    if (P.occ.mm) build_next_opaque(s_next, P.tf, P.K);
+    build_next_opaque(s_next, P.tf, P.K);  // read by every batch (unused without a map)
     __syncthreads();
 
     constexpr int BX = BuildBlock<SL>::X, BY = BuildBlock<SL>::Y;
@@ -101,47 +107,87 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     const float ln2 = 0.69314718055994531f;
     uint32_t last_cell = 0xffffffffu;
     bool cell_is_empty = false;
+    const bool use_map = P.occ.mm != nullptr;
 
-    for (int k = 0; k < P.n; ++k, at += layer) {
-        const float kf = (float)k;
-        const float hx = fmaf(kf, alx, hx0);
-        const float hy = fmaf(kf, aly, hy0);
-        const float hz = fmaf(kf, alz, hz0);
-        // log2 of the slab's (1 - alpha)/e, 0 outside the cube (empty)
-        float l2 = 0.0f;
-        bool fetch = (hx >= P.lo) & (hx <= P.hi) & (hy >= P.lo) & (hy <= P.hi) & (hz >= P.lo) & (hz <= P.hi);
-        if (fetch && P.occ.mm) {
-            // empty-space map: a zero-opacity cell leaves T unchanged exactly
-            const uint32_t c = cell_of((int)floorf(hx) + P.M, (int)floorf(hy) + P.M, (int)floorf(hz) + P.M, P.N,
-                                       P.occ.shift, P.occ.nc);
-            if (c != last_cell) {
-                last_cell = c;
-                cell_is_empty = cell_empty(P.occ.mm[c], s_next, Km1, P.K);
+    // The slabs go in batches of kBatch: first every slab's position and the
+    // map entries of newly entered cells (loaded together), then the
+    // empty-space verdicts, then the volume loads of all slabs that need one,
+    // and only then the arithmetic, the running product and the stores -- so
+    // a column waits on one round trip per batch instead of one per slab.
+    // Each slab's arithmetic is the same as one at a time.
+    for (int k0 = 0; k0 < P.n; k0 += kBatch) {
+        float hx[kBatch], hy[kBatch], hz[kBatch];
+        bool fetch[kBatch];
+        uint32_t cell[kBatch];
+        float2 mm[kBatch];
+        uint32_t cur = last_cell;  // cell of the latest slab inside the cube
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const float kf = (float)(k0 + u);
+            hx[u] = fmaf(kf, alx, hx0);
+            hy[u] = fmaf(kf, aly, hy0);
+            hz[u] = fmaf(kf, alz, hz0);
+            fetch[u] = (k0 + u < P.n) & (hx[u] >= P.lo) & (hx[u] <= P.hi) & (hy[u] >= P.lo) & (hy[u] <= P.hi) &
+                       (hz[u] >= P.lo) & (hz[u] <= P.hi);
+            cell[u] = 0xffffffffu;
+            mm[u] = make_float2(0.0f, 0.0f);
+            if (fetch[u] && use_map) {
+                cell[u] = cell_of((int)floorf(hx[u]) + P.M, (int)floorf(hy[u]) + P.M, (int)floorf(hz[u]) + P.M, P.N,
+                                  P.occ.shift, P.occ.nc);
+                if (cell[u] != cur) {
+                    mm[u] = P.occ.mm[cell[u]];  // a newly entered cell
+                    cur = cell[u];
+                }
             }
-            fetch = !cell_is_empty;
         }
-        if (fetch) {
-            const float v = sample_volume<VT, LAYOUT>(vol, VI_, P.N, P.M, P.scale, hx, hy, hz);
-            const float x = v * Km1;
-            const int e0 = min((int)x, P.K - 2);
-            const float w = x - (float)e0;
-            const float a = fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]);
-            l2 = fast_log2(fmaxf(1.0f - a, 0.0f));  // -inf for a = 1
+        // Empty-space verdicts: a zero-opacity cell leaves T unchanged
+        // exactly.  Every entry's verdict is taken, on every path and with
+        // selects rather than branches (entries not loaded hold zeros and
+        // their verdicts are not used; without a map none is), so no map
+        // load is left in flight behind the volume loads below.  The cell
+        // sequence is the one above, so an entry is loaded wherever its
+        // verdict is used.
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const bool empty = cell_empty(mm[u], s_next, Km1, P.K);
+            const bool entered = use_map && fetch[u] && cell[u] != last_cell;
+            cell_is_empty = entered ? empty : cell_is_empty;
+            last_cell = entered ? cell[u] : last_cell;
+            fetch[u] = fetch[u] && !cell_is_empty;
         }
-        if (OUT_DTYPE == VI_F32) {
-            // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
-            float f = fast_exp2(e * l2);
-            // section 4 compensation: times (1 + alpha)^m, at most 1
-            if (DARKEN) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
-            T *= f;
-            ((float*)P.out)[at] = T;
-        } else {
-            // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
-            // compensation subtracts m ln(1 + alpha), floored at 0
-            float dtau = -e * ln2 * l2;
-            if (DARKEN) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
-            tau += fminf(dtau, 64.0f);
-            ((uint16_t*)P.out)[at] = f32_to_bf16(tau);
+        RawFoot<VT, LAYOUT> raw[kBatch];
+        float wx[kBatch], wy[kBatch], wz[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (fetch[u]) foot_load<VT, LAYOUT>(raw[u], wx[u], wy[u], wz[u], vol, VI_, P.N, P.M, hx[u], hy[u], hz[u]);
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u, at += layer) {
+            if (k0 + u >= P.n) break;
+            // log2 of the slab's (1 - alpha)/e, 0 outside the cube or in empty cells
+            float l2 = 0.0f;
+            if (fetch[u]) {
+                const float v = foot_value<VT, LAYOUT>(raw[u], wx[u], wy[u], wz[u], P.scale);
+                const float x = v * Km1;
+                const int e0 = min((int)x, P.K - 2);
+                const float w = x - (float)e0;
+                const float a = fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]);
+                l2 = fast_log2(fmaxf(1.0f - a, 0.0f));  // -inf for a = 1
+            }
+            if (OUT_DTYPE == VI_F32) {
+                // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
+                float f = fast_exp2(e * l2);
+                // section 4 compensation: times (1 + alpha)^m, at most 1
+                if (DARKEN) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
+                T *= f;
+                ((float*)P.out)[at] = T;
+            } else {
+                // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
+                // compensation subtracts m ln(1 + alpha), floored at 0
+                float dtau = -e * ln2 * l2;
+                if (DARKEN) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
+                tau += fminf(dtau, 64.0f);
+                ((uint16_t*)P.out)[at] = f32_to_bf16(tau);
+            }
         }
     }
 }

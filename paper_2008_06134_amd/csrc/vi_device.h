@@ -102,6 +102,96 @@ __device__ __forceinline__ float4 quad_norm<float>(const float* __restrict__ v, 
     return make_float4(clampf01(w.x * scale), clampf01(w.y * scale), clampf01(w.z * scale), clampf01(w.w * scale));
 }
 
+// A trilinear footprint split into its loads and its arithmetic, so that a
+// caller can issue the loads of several footprints before it needs any of
+// them.  RawFoot holds the raw elements (eight voxels, or the two quad slots
+// at z and z+1); foot_value converts and interpolates them exactly as
+// sample_volume does.
+template <typename VT> struct QuadRaw { using T = uint2; };           // 16-bit voxels
+template <> struct QuadRaw<uint8_t> { using T = uint32_t; };
+template <> struct QuadRaw<float> { using T = float4; };
+template <typename VT, int LAYOUT> struct RawFoot { VT v[8]; };
+template <typename VT> struct RawFoot<VT, VI_LAYOUT_QUAD4> { typename QuadRaw<VT>::T a, b; };
+
+__device__ __forceinline__ float norm1(uint8_t x, float scale) { return clampf01((float)x * scale); }
+__device__ __forceinline__ float norm1(uint16_t x, float scale) { return clampf01((float)x * scale); }
+__device__ __forceinline__ float norm1(__half x, float scale) { return clampf01(__half2float(x) * scale); }
+__device__ __forceinline__ float norm1(float x, float scale) { return clampf01(x * scale); }
+
+__device__ __forceinline__ float4 quad_decode(uint32_t w, float scale, uint8_t)
+{
+    return make_float4(clampf01((float)(w & 0xffu) * scale), clampf01((float)((w >> 8) & 0xffu) * scale),
+                       clampf01((float)((w >> 16) & 0xffu) * scale), clampf01((float)(w >> 24) * scale));
+}
+__device__ __forceinline__ float4 quad_decode(uint2 w, float scale, uint16_t)
+{
+    return make_float4(clampf01((float)(w.x & 0xffffu) * scale), clampf01((float)(w.x >> 16) * scale),
+                       clampf01((float)(w.y & 0xffffu) * scale), clampf01((float)(w.y >> 16) * scale));
+}
+__device__ __forceinline__ float4 quad_decode(uint2 w, float scale, __half)
+{
+    return make_float4(clampf01(__half2float(__ushort_as_half((unsigned short)(w.x & 0xffffu))) * scale),
+                       clampf01(__half2float(__ushort_as_half((unsigned short)(w.x >> 16))) * scale),
+                       clampf01(__half2float(__ushort_as_half((unsigned short)(w.y & 0xffffu))) * scale),
+                       clampf01(__half2float(__ushort_as_half((unsigned short)(w.y >> 16))) * scale));
+}
+__device__ __forceinline__ float4 quad_decode(float4 w, float scale, float)
+{
+    return make_float4(clampf01(w.x * scale), clampf01(w.y * scale), clampf01(w.z * scale), clampf01(w.w * scale));
+}
+
+// Issue the loads of the footprint at offset-voxel coordinates h and return
+// its weights (a quad footprint below the first voxel in x or y takes a zero
+// weight there: both of its corners clamp to voxel 0).
+template <typename VT, int LAYOUT>
+__device__ __forceinline__ void foot_load(RawFoot<VT, LAYOUT>& r, float& wx, float& wy, float& wz,
+                                          const VT* __restrict__ vol, const VolIndex& I, int N, int M, float hx,
+                                          float hy, float hz)
+{
+    const float fx = floorf(hx), fy = floorf(hy), fz = floorf(hz);
+    wx = hx - fx;
+    wy = hy - fy;
+    wz = hz - fz;
+    const int x0 = (int)fx + M, y0 = (int)fy + M, z0 = (int)fz + M;
+    const uint32_t za = vol_oz<LAYOUT>(I, clampi(z0, 0, N - 1)), zb = vol_oz<LAYOUT>(I, clampi(z0 + 1, 0, N - 1));
+    if constexpr (LAYOUT == VI_LAYOUT_QUAD4) {
+        using Q = typename QuadRaw<VT>::T;
+        const uint32_t xy = vol_ox<LAYOUT>(I, clampi(x0, 0, N - 1)) + vol_oy<LAYOUT>(I, clampi(y0, 0, N - 1));
+        r.a = ((const Q*)vol)[za + xy];
+        r.b = ((const Q*)vol)[zb + xy];
+        if (x0 < 0) wx = 0.0f;
+        if (y0 < 0) wy = 0.0f;
+    } else {
+        const uint32_t xa = vol_ox<LAYOUT>(I, clampi(x0, 0, N - 1)), xb = vol_ox<LAYOUT>(I, clampi(x0 + 1, 0, N - 1));
+        const uint32_t ya = vol_oy<LAYOUT>(I, clampi(y0, 0, N - 1)), yb = vol_oy<LAYOUT>(I, clampi(y0 + 1, 0, N - 1));
+        r.v[0] = vol[za + ya + xa];
+        r.v[1] = vol[za + ya + xb];
+        r.v[2] = vol[za + yb + xa];
+        r.v[3] = vol[za + yb + xb];
+        r.v[4] = vol[zb + ya + xa];
+        r.v[5] = vol[zb + ya + xb];
+        r.v[6] = vol[zb + yb + xa];
+        r.v[7] = vol[zb + yb + xb];
+    }
+}
+
+template <typename VT, int LAYOUT>
+__device__ __forceinline__ float foot_value(const RawFoot<VT, LAYOUT>& r, float wx, float wy, float wz, float scale)
+{
+    float4 a, b;
+    if constexpr (LAYOUT == VI_LAYOUT_QUAD4) {
+        a = quad_decode(r.a, scale, VT());
+        b = quad_decode(r.b, scale, VT());
+    } else {
+        a = make_float4(norm1(r.v[0], scale), norm1(r.v[1], scale), norm1(r.v[2], scale), norm1(r.v[3], scale));
+        b = make_float4(norm1(r.v[4], scale), norm1(r.v[5], scale), norm1(r.v[6], scale), norm1(r.v[7], scale));
+    }
+    const float c00 = fmaf(wx, a.y - a.x, a.x), c01 = fmaf(wx, a.w - a.z, a.z);
+    const float c10 = fmaf(wx, b.y - b.x, b.x), c11 = fmaf(wx, b.w - b.z, b.z);
+    const float c0 = fmaf(wy, c01 - c00, c00), c1 = fmaf(wy, c11 - c10, c10);
+    return fmaf(wz, c1 - c0, c0);
+}
+
 // Trilinear sample at offset-voxel coordinates h = g - M (g = p*N - 1/2),
 // clamp to edge.  M is an integer so floor/fraction are taken on h exactly.
 template <typename VT, int LAYOUT>

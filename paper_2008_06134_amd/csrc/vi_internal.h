@@ -127,15 +127,19 @@ hipError_t launch_to_quads(const void* src, void* dst, int dtype, int N, hipStre
 hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
                          int shift, float* out, hipStream_t s);
 
-// Kernel variants of the modes for a point light: the light grid is a
-// perspective frustum (every stack lookup divides by its depth), and Phong's
-// light vector points at the light from each sample.
-constexpr int kModePointShadow = 5, kModePointShell = 6, kModePointPhong = 7, kKernelModes = 8;
+// Kernel variants beyond the public modes: for a point light the light grid
+// is a perspective frustum (every stack lookup divides by its depth) and
+// Phong's light vector points at the light from each sample; the cone's
+// lattice form is a kernel of its own (its best tap batching and register
+// budget differ from the ring form's).
+constexpr int kModePointShadow = 5, kModePointShell = 6, kModePointPhong = 7, kModeConeGrid = 8,
+              kKernelModes = 9;
 inline int kernel_mode(const RenderFrame& f)
 {
     if (f.point && f.mode == VI_MODE_SHADOW) return kModePointShadow;
     if (f.point && f.mode == VI_MODE_SHELL) return kModePointShell;
     if (f.point && f.mode == VI_MODE_PHONG) return kModePointPhong;
+    if (f.mode == VI_MODE_CONE && f.cone_grid > 0) return kModeConeGrid;
     return f.mode;
 }
 

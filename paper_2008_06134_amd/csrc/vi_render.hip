@@ -45,22 +45,84 @@ __device__ __forceinline__ float stack_texel<VI_BF16>(const void* __restrict__ S
 typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 
+// The load and the conversion are separate steps (PairRaw holds the loaded
+// bits), so that a gather can issue the loads of several taps before it
+// converts any of them.
+template <int SDT> struct PairRaw;
+template <> struct PairRaw<VI_F32> { f32x2_a4 v; };
+template <> struct PairRaw<VI_BF16> { u32x2_a4 w; uint32_t odd; };
+
 template <int SDT>
-__device__ __forceinline__ float2 stack_pair(const void* __restrict__ S, uint32_t e);
+__device__ __forceinline__ PairRaw<SDT> pair_load(const void* __restrict__ S, uint32_t e);
 template <>
-__device__ __forceinline__ float2 stack_pair<VI_F32>(const void* __restrict__ S, uint32_t e)
+__device__ __forceinline__ PairRaw<VI_F32> pair_load<VI_F32>(const void* __restrict__ S, uint32_t e)
 {
-    const f32x2_a4 v = *(const f32x2_a4*)((const float*)S + e);
-    return make_float2(v.x, v.y);
+    return PairRaw<VI_F32>{*(const f32x2_a4*)((const float*)S + e)};
 }
 template <>
-__device__ __forceinline__ float2 stack_pair<VI_BF16>(const void* __restrict__ S, uint32_t e)
+__device__ __forceinline__ PairRaw<VI_BF16> pair_load<VI_BF16>(const void* __restrict__ S, uint32_t e)
 {
-    const u32x2_a4 w = *(const u32x2_a4*)((const uint16_t*)S + (e & ~1u));
-    const uint32_t lo = (e & 1u) ? (w.x >> 16) : (w.x & 0xffffu);
-    const uint32_t hi = (e & 1u) ? (w.y & 0xffffu) : (w.x >> 16);
+    return PairRaw<VI_BF16>{*(const u32x2_a4*)((const uint16_t*)S + (e & ~1u)), e & 1u};
+}
+__device__ __forceinline__ float2 pair_value(const PairRaw<VI_F32>& r) { return make_float2(r.v.x, r.v.y); }
+__device__ __forceinline__ float2 pair_value(const PairRaw<VI_BF16>& r)
+{
+    const uint32_t lo = r.odd ? (r.w.x >> 16) : (r.w.x & 0xffffu);
+    const uint32_t hi = r.odd ? (r.w.y & 0xffffu) : (r.w.x >> 16);
     const float log2e = 1.4426950408889634f;
     return make_float2(fast_exp2(-log2e * __uint_as_float(lo << 16)), fast_exp2(-log2e * __uint_as_float(hi << 16)));
+}
+template <int SDT>
+__device__ __forceinline__ float2 stack_pair(const void* __restrict__ S, uint32_t e)
+{
+    return pair_value(pair_load<SDT>(S, e));
+}
+
+// One row-layout lookup split into its four loads (rows j, j+1 of layers k0
+// and k1) and its arithmetic.  Layer k0 = -1 (in front of the first face)
+// loads layer 0 and reads 1 instead, so the four loads go out together.
+template <int SDT>
+struct RowTap {
+    PairRaw<SDT> a0, a1, b0, b1;  // layer k0 rows j, j+1; layer k1 rows j, j+1
+    float wx, wy, wz;
+    bool in, front;
+};
+template <int SDT>
+__device__ __forceinline__ void rowtap_load(const RenderFrame& F, float z, float x, float y, RowTap<SDT>& t)
+{
+    z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
+    const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
+    t.wz = z - fz;
+    t.wx = x - fx;
+    t.wy = y - fy;
+    const int k0 = (int)fz + F.Mz;
+    const int k1 = min(k0 + 1, F.n - 1);
+    const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;
+    // footprints reaching past the border read 1 everywhere
+    t.in = a >= -1 && a <= F.res - 1 && b >= -1 && b <= F.res - 1;
+    t.front = k0 < 0;
+    const uint32_t e = (uint32_t)(clampi(b, -1, F.res - 1) + 1) * F.rpitch + F.rorg + (uint32_t)clampi(a, -1, F.res - 1);
+    const uint32_t base0 = (uint32_t)max(k0, 0) * F.rlayer + e, base1 = (uint32_t)k1 * F.rlayer + e;
+    t.a0 = pair_load<SDT>(F.stack, base0);
+    t.a1 = pair_load<SDT>(F.stack, base0 + F.rpitch);
+    t.b0 = pair_load<SDT>(F.stack, base1);
+    t.b1 = pair_load<SDT>(F.stack, base1 + F.rpitch);
+}
+template <int SDT>
+__device__ __forceinline__ float rowtap_value(const RowTap<SDT>& t)
+{
+    float t0 = 1.0f;
+    if (!t.front) {
+        float2 r0 = pair_value(t.a0), r1 = pair_value(t.a1);
+        if (!t.in) r0 = r1 = make_float2(1.0f, 1.0f);
+        const float ab = fmaf(t.wx, r0.y - r0.x, r0.x), cd = fmaf(t.wx, r1.y - r1.x, r1.x);
+        t0 = fmaf(t.wy, cd - ab, ab);
+    }
+    float2 r0 = pair_value(t.b0), r1 = pair_value(t.b1);
+    if (!t.in) r0 = r1 = make_float2(1.0f, 1.0f);
+    const float ab = fmaf(t.wx, r0.y - r0.x, r0.x), cd = fmaf(t.wx, r1.y - r1.x, r1.x);
+    const float t1 = fmaf(t.wy, cd - ab, ab);
+    return fmaf(t.wz, t1 - t0, t0);
 }
 
 // Transmittance at light-grid offset coordinates (z, x, y): depth between
@@ -70,29 +132,9 @@ template <int SDT, int SL>
 __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, float x, float y)
 {
     if (SL == VI_STACK_ROWS) {
-        z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
-        const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
-        const float wz = z - fz, wx = x - fx, wy = y - fy;
-        const int k0 = (int)fz + F.Mz;
-        const int k1 = min(k0 + 1, F.n - 1);
-        const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;
-        // footprints reaching past the border read 1 everywhere
-        const bool in = a >= -1 && a <= F.res - 1 && b >= -1 && b <= F.res - 1;
-        const uint32_t e = (uint32_t)(clampi(b, -1, F.res - 1) + 1) * F.rpitch + F.rorg + (uint32_t)clampi(a, -1, F.res - 1);
-        float t0 = 1.0f;
-        if (k0 >= 0) {
-            const uint32_t base = (uint32_t)k0 * F.rlayer + e;
-            float2 r0 = stack_pair<SDT>(F.stack, base), r1 = stack_pair<SDT>(F.stack, base + F.rpitch);
-            if (!in) r0 = r1 = make_float2(1.0f, 1.0f);
-            const float ab = fmaf(wx, r0.y - r0.x, r0.x), cd = fmaf(wx, r1.y - r1.x, r1.x);
-            t0 = fmaf(wy, cd - ab, ab);
-        }
-        const uint32_t base = (uint32_t)k1 * F.rlayer + e;
-        float2 r0 = stack_pair<SDT>(F.stack, base), r1 = stack_pair<SDT>(F.stack, base + F.rpitch);
-        if (!in) r0 = r1 = make_float2(1.0f, 1.0f);
-        const float ab = fmaf(wx, r0.y - r0.x, r0.x), cd = fmaf(wx, r1.y - r1.x, r1.x);
-        const float t1 = fmaf(wy, cd - ab, ab);
-        return fmaf(wz, t1 - t0, t0);
+        RowTap<SDT> t;
+        rowtap_load<SDT>(F, z, x, y, t);
+        return rowtap_value<SDT>(t);
     }
     z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
     const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
@@ -144,35 +186,98 @@ struct ConeFrame {
     float px, py;  // L x B in texels per world unit
 };
 
+// NB stack lookups at once: all their loads are issued before any of them
+// is converted (row layout; the tiled layout looks up one at a time), so a
+// gather waits on one round trip per batch of taps.  Larger batches keep
+// more loads in flight per wave but take registers, i.e. resident waves;
+// measured on the 512^3 workload: the ring cone runs fastest with two taps
+// per batch, the shell and the 5 x 5 lattice with one (four loads).
+template <int MODE>
+constexpr int tap_batch()
+{
+    return MODE == VI_MODE_CONE ? 2 : 1;
+}
+
+template <int SDT, int SL, int NB>
+__device__ __forceinline__ void lookup_batch(const RenderFrame& F, const float (&z)[NB], const float (&x)[NB],
+                                             const float (&y)[NB], float (&out)[NB])
+{
+    if constexpr (SL == VI_STACK_ROWS) {
+        RowTap<SDT> t[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) rowtap_load<SDT>(F, z[u], x[u], y[u], t[u]);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) out[u] = rowtap_value<SDT>(t[u]);
+    } else {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) out[u] = stack_lookup<SDT, SL>(F, z[u], x[u], y[u]);
+    }
+}
+
 template <int MODE, int SDT, int SL>
 __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& cf, float z, float x, float y)
 {
     if (MODE == VI_MODE_SHADOW) return stack_lookup<SDT, SL>(F, z, x, y);
+    // Taps go in batches; a batch running past the last tap repeats it and
+    // leaves the sum alone for the repeats, so every tap is added once, in
+    // order, as a one-at-a-time loop adds it.
+    constexpr int NB = tap_batch<MODE>();
+    float zz[NB], xx[NB], yy[NB], v[NB];
     if (MODE == VI_MODE_SHELL) {
         // weighted taps (shell r's six taps share w_r / (6 sum w))
         float s = 0.0f;
-        for (int t = 0; t < F.ntaps; ++t)
-            s = fmaf(F.tw[t], stack_lookup<SDT, SL>(F, z + F.tz[t], x + F.tx_[t], y + F.ty_[t]), s);
+        for (int t = 0; t < F.ntaps; t += NB) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int i = min(t + u, F.ntaps - 1);
+                zz[u] = z + F.tz[i];
+                xx[u] = x + F.tx_[i];
+                yy[u] = y + F.ty_[i];
+            }
+            lookup_batch<SDT, SL>(F, zz, xx, yy, v);
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                if (t + u < F.ntaps) s = fmaf(F.tw[t + u], v[u], s);
+        }
         return s;
     }
-    // cone
+    // cone: rings (Eq. 11), or the lattice form in a kernel of its own
     float s = 0.0f;
-    if (F.cone_grid <= 0) {
+    if (MODE == VI_MODE_CONE) {
         for (int m = 1; m <= F.cone_rings; ++m) {
             const float r = (float)m * (float)F.ds * F.cone_tan;
-            for (int q = 0; q < F.cone_angles; ++q) {
-                const float ca = F.cone_cos[q] * r, sa = F.cone_sin[q] * r;
-                s += stack_lookup<SDT, SL>(F, z - (float)m, x + ca * cf.bx + sa * cf.px, y + ca * cf.by + sa * cf.py);
+            for (int q = 0; q < F.cone_angles; q += NB) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int i = min(q + u, F.cone_angles - 1);
+                    const float ca = F.cone_cos[i] * r, sa = F.cone_sin[i] * r;
+                    zz[u] = z - (float)m;
+                    xx[u] = x + ca * cf.bx + sa * cf.px;
+                    yy[u] = y + ca * cf.by + sa * cf.py;
+                }
+                lookup_batch<SDT, SL>(F, zz, xx, yy, v);
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    if (q + u < F.cone_angles) s += v[u];
             }
         }
-    } else {
+    } else if (MODE == kModeConeGrid) {
         const int G = F.cone_grid;
         const float rho = (float)F.ds * F.cone_tan * 0.5f, half = 0.5f * (float)(G - 1);
         for (int ia = 0; ia < G; ++ia) {
             const float a = ((float)ia - half) * rho;
-            for (int ib = 0; ib < G; ++ib) {
-                const float b = ((float)ib - half) * rho;
-                s += stack_lookup<SDT, SL>(F, z - 1.0f, x + a * cf.bx + b * cf.px, y + a * cf.by + b * cf.py);
+            for (int ib = 0; ib < G; ib += NB) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const float b = ((float)min(ib + u, G - 1) - half) * rho;
+                    zz[u] = z - 1.0f;
+                    xx[u] = x + a * cf.bx + b * cf.px;
+                    yy[u] = y + a * cf.by + b * cf.py;
+                }
+                lookup_batch<SDT, SL>(F, zz, xx, yy, v);
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    if (ib + u < G) s += v[u];
             }
         }
     }
@@ -198,11 +303,23 @@ __device__ __forceinline__ float gather_point(const RenderFrame& F, float z, flo
         return stack_lookup<SDT, SL>(F, z, frustum_col(F, u, rd, d > 0.0f), frustum_col(F, v, rd, d > 0.0f));
     }
     // shell taps: world-frame offsets, each projected through its own depth
+    // (batched as in gather())
     float s = 0.0f;
-    for (int t = 0; t < F.ntaps; ++t) {
-        const float dt = d + F.td_[t], rd = __builtin_amdgcn_rcpf(dt);
-        const float x = frustum_col(F, u + F.tx_[t], rd, dt > 0.0f), y = frustum_col(F, v + F.ty_[t], rd, dt > 0.0f);
-        s = fmaf(F.tw[t], stack_lookup<SDT, SL>(F, z + F.tz[t], x, y), s);
+    constexpr int NB = tap_batch<MODE>();
+    float zz[NB], xx[NB], yy[NB], val[NB];
+    for (int t = 0; t < F.ntaps; t += NB) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int i = min(t + q, F.ntaps - 1);
+            const float dt = d + F.td_[i], rd = __builtin_amdgcn_rcpf(dt);
+            zz[q] = z + F.tz[i];
+            xx[q] = frustum_col(F, u + F.tx_[i], rd, dt > 0.0f);
+            yy[q] = frustum_col(F, v + F.ty_[i], rd, dt > 0.0f);
+        }
+        lookup_batch<SDT, SL>(F, zz, xx, yy, val);
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (t + q < F.ntaps) s = fmaf(F.tw[t + q], val[q], s);
     }
     return s;
 }
@@ -326,7 +443,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
             qdx = (float)(F.Ux[0] * d[0] + F.Ux[1] * d[1] + F.Ux[2] * d[2]);
             qdy = (float)(F.Vy[0] * d[0] + F.Vy[1] * d[1] + F.Vy[2] * d[2]);
         }
-        if (MODE == VI_MODE_CONE) {
+        if (MODE == VI_MODE_CONE || MODE == kModeConeGrid) {
             // B: direction toward the viewer with its L component removed
             double w[3] = {-d[0], -d[1], -d[2]};
             const double wl = w[0] * F.L[0] + w[1] * F.L[1] + w[2] * F.L[2];
@@ -629,6 +746,10 @@ static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const ui
         hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, kModePointPhong, SDT, SL>), grid, block, lds, s,
                            d_frames, d_tiles, ntiles);
         break;
+    case kModeConeGrid:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, kModeConeGrid, SDT, SL>), grid, block, lds, s,
+                           d_frames, d_tiles, ntiles);
+        break;
     default:
         hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, d_frames,
                            d_tiles, ntiles);
@@ -697,6 +818,9 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
         break;
     case kModePointPhong:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, kModePointPhong, SDT, SL>), grid, block, lds, s, f);
+        break;
+    case kModeConeGrid:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, kModeConeGrid, SDT, SL>), grid, block, lds, s, f);
         break;
     default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, f); break;
     }
