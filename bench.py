@@ -201,7 +201,8 @@ def serving_inputs(vol_sizes, dev, vessels=True):
     vols = []
     for i, N in enumerate(vol_sizes):
         raw = W.serving_volume(N, i, vessels=vessels)
-        vols.append((vi.Volume.from_numpy(raw, dev).to_quads().with_minmax(16), vi.TF.from_numpy(tab, dev)))
+        tf = vi.TF.from_numpy(tab, dev)
+        vols.append((vi.Volume.from_numpy(raw, dev).to_quads().with_minmax(16).with_occupancy(tf), tf))
     return vols
 
 
@@ -225,7 +226,7 @@ def serving_quick(dev, budget=16 << 30, count=300):
     rate = 0.9 * cap
     reqs = W.serving_requests(count, sizes, rate, seed=5)
     serve(vols, reqs[:30], budget)                 # warm-up
-    out = {"volumes": "8 resident u16 phantoms 128^3-320^3 (quad layout + empty-space map)",
+    out = {"volumes": "8 resident u16 phantoms 128^3-320^3 (quad layout + empty-space map + occupancy bits)",
            "requests": count, "rate_hz": round(rate, 2), "sequential_capacity_fps": cap,
            "served": serve(vols, reqs, budget), "sequential": sequential(vols, reqs, budget)}
     return out
@@ -258,8 +259,8 @@ def scaling_sweep(dev, slices=(64, 128, 256, 512), resolutions=(128, 256, 512, 1
     from paper_2008_06134_amd import workloads as W
     w = W.WORKLOADS["large"]
     raw, tab = w.volume(), w.tf()
-    vol = vi.Volume.from_numpy(raw, dev).to_quads().with_minmax(16)
     tf = vi.TF.from_numpy(tab, dev)
+    vol = vi.Volume.from_numpy(raw, dev).to_quads().with_minmax(16).with_occupancy(tf)
     light, cam = w.lights()[0], w.camera(0)
     img = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device=dev)
 
@@ -307,6 +308,8 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     tb = time.perf_counter()
     # one-off per volume: brick or quad layout + empty-space map
     vol = (vol_lin.to_quads() if args.volume_layout == "quads" else vol_lin.to_bricks()).with_minmax(args.cell)
+    if not args.no_occupancy:
+        vol = vol.with_occupancy(tf)  # per (volume, TF): one bit per empty-space cell
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - tb) * 1e3
     del vol_lin
@@ -386,6 +389,8 @@ def main():
                     help="4x4x4 bricks, or quads (each slot its voxel's 2x2 x/y neighbourhood: 4x the bytes, "
                          "two loads per trilinear footprint); auto = quads, except bricks for the 1024^3 "
                          "precision workload (where quads measured slower)")
+    ap.add_argument("--no-occupancy", action="store_true",
+                    help="decide empty space from the min/max map and the TF per cell instead of occupancy bits")
     ap.add_argument("--point-light", type=float, default=0.0, metavar="DIST",
                     help="point lights DIST world units from the volume centre (against each light "
                          "direction) instead of directional lights; modes shadow, shell, phong, none")
@@ -493,7 +498,7 @@ def main():
         "fps": round(frames / wall, 3),
         "config": {"workload": (f"{w.name}: {w.N}^3 {'f16' if precision else raw.dtype} phantom "
                                 f"({'4x4x4 bricks' if args.volume_layout == 'bricks' else '4x4x4 bricks of 2x2 quads'}, "
-                                f"{args.cell}^3 empty-space cells), "
+                                f"{args.cell}^3 empty-space cells{'' if args.no_occupancy else ' + occupancy bits'}), "
                                 f"{w.n_slices} slices x {w.res}^2 {'bf16' if precision else 'f32'} "
                                 f"({args.stack_layout}), "
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "

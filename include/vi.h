@@ -128,6 +128,8 @@ typedef struct {
     int layout; /* VI_LAYOUT_LINEAR (0), VI_LAYOUT_BRICK4 or VI_LAYOUT_QUAD4 */
     const float* minmax; /* NULL, or ceil(n/cell)^3 (min, max) float pairs, cells x fastest */
     int cell;            /* cell edge in voxels (4, 8, 16 or 32) when minmax is set */
+    const uint32_t* occ; /* NULL, or occupancy bits from vi_volume_occupancy (needs minmax) */
+    uint64_t occ_tag;    /* identity of the (volume, map, transfer function) the bits were made for */
 } vi_volume;
 
 /* Transfer function: `n_entries` x 4 floats (r,g,b,a) in device memory,
@@ -272,6 +274,26 @@ size_t vi_volume_minmax_bytes(int n, int cell);
  * function is applied when rendering, so one map serves every TF.
  * Errors: VI_E_INVALID_ARG for NULL pointers or a bad cell size. */
 int vi_volume_minmax(const vi_volume* vol, int cell, float* d_minmax, vi_volume* out, vi_stream_t stream);
+
+/* Bytes of the occupancy bits of a volume of edge n with cells of `cell`
+ * voxels: ceil(ceil(n/cell)^3 / 32) * 4 (0 for invalid arguments). */
+size_t vi_volume_occupancy_bytes(int n, int cell);
+
+/* For a volume with an empty-space map and one transfer function, write to
+ * `d_bits` (device, vi_volume_occupancy_bytes bytes, 4-byte aligned,
+ * caller-owned) one bit per cell -- bit c%32 of word c/32 is 1 where the
+ * cell may hold opacity under `tf`, i.e. the negation of the map's
+ * emptiness test -- and return in `out` a copy of `vol` that refers to them.
+ * Both passes then answer the empty-space question with one bit, held in
+ * LDS when the bits fit in 8 KiB (65536 cells), instead of a map entry and a
+ * transfer-function table lookup: a shorter chain of dependent reads per
+ * cell; results are unchanged bit for bit.  The passes accept the bits only
+ * with the transfer function (and map) they were made for.  One kernel
+ * launch on `stream`.
+ * Errors: VI_E_INVALID_ARG for NULL pointers, a volume without a map or a
+ * misaligned buffer; VI_E_DEVICE. */
+int vi_volume_occupancy(const vi_volume* vol, const vi_tf* tf, uint32_t* d_bits, vi_volume* out,
+                        vi_stream_t stream);
 
 /* Host only: compute the light frame of Eq. 8 and the light projection
  * for `light_dir` (need not be unit length; finite, non-zero), or for the

@@ -76,10 +76,20 @@ int check_volume(const vi_volume* v)
             return fail(VI_E_INVALID_ARG, "empty-space cell %d must be 4, 8, 16 or 32", v->cell);
         if (((uintptr_t)v->minmax) % 8) return fail(VI_E_INVALID_ARG, "empty-space map misaligned");
     }
+    if (v->occ) {
+        if (!v->minmax) return fail(VI_E_INVALID_ARG, "occupancy bits without an empty-space map");
+        if (((uintptr_t)v->occ) % 4) return fail(VI_E_INVALID_ARG, "occupancy bits misaligned");
+    }
     return VI_OK;
 }
 
 int cell_shift(int cell) { return cell == 4 ? 2 : cell == 8 ? 3 : cell == 16 ? 4 : 5; }
+
+uint32_t cells_of(int n, int cell)
+{
+    const uint32_t nc = ((uint32_t)n + (uint32_t)cell - 1) / (uint32_t)cell;
+    return nc * nc * nc;
+}
 
 vi::OccMap occ_of(const vi_volume* v)
 {
@@ -87,7 +97,31 @@ vi::OccMap occ_of(const vi_volume* v)
     o.mm = v->minmax ? (const float2*)v->minmax : nullptr;
     o.shift = v->minmax ? cell_shift(v->cell) : 0;
     o.nc = v->minmax ? ((uint32_t)v->n + (uint32_t)v->cell - 1) / (uint32_t)v->cell : 0;
+    const uint32_t words = v->minmax ? (cells_of(v->n, v->cell) + 31u) / 32u : 0;
+    // bits that do not fit in LDS are not used: the map decides instead
+    o.bits = v->minmax && v->occ && words <= vi::kMaxLdsOccWords ? v->occ : nullptr;
+    o.words = o.bits ? words : 0;
     return o;
+}
+
+// Identity of the (volume, map, transfer function) occupancy bits belong to.
+uint64_t occ_tag_of(const vi_volume* v, const vi_tf* tf)
+{
+    uint64_t h = vi_tag(v, tf);
+    const uint64_t parts[2] = {(uint64_t)(uintptr_t)v->minmax, (uint64_t)v->cell};
+    for (uint64_t x : parts)
+        for (int b = 0; b < 8; ++b) {
+            h ^= (x >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    return h ? h : 1;
+}
+
+int check_occ(const vi_volume* v, const vi_tf* tf)
+{
+    if (v->occ && v->occ_tag != occ_tag_of(v, tf))
+        return fail(VI_E_INVALID_ARG, "occupancy bits were made for another transfer function or map");
+    return VI_OK;
 }
 
 int check_tf(const vi_tf* tf)
@@ -275,6 +309,8 @@ static int relayout(const vi_volume* src, void* d_dst, vi_volume* out, vi_stream
     *out = *src;
     out->data = d_dst;
     out->layout = layout;
+    out->occ = nullptr;  // bits are tied to the source's identity (the map stays valid)
+    out->occ_tag = 0;
     return VI_OK;
 }
 
@@ -295,6 +331,31 @@ size_t vi_volume_minmax_bytes(int n, int cell)
     return nc * nc * nc * 8;
 }
 
+size_t vi_volume_occupancy_bytes(int n, int cell)
+{
+    if (n < 2 || (cell != 4 && cell != 8 && cell != 16 && cell != 32)) return 0;
+    return ((size_t)cells_of(n, cell) + 31) / 32 * 4;
+}
+
+int vi_volume_occupancy(const vi_volume* vol, const vi_tf* tf, uint32_t* d_bits, vi_volume* out,
+                        vi_stream_t stream)
+{
+    clear_err();
+    int rc;
+    if ((rc = check_volume(vol)) != VI_OK) return rc;
+    if ((rc = check_tf(tf)) != VI_OK) return rc;
+    if (!vol->minmax) return fail(VI_E_INVALID_ARG, "the volume has no empty-space map");
+    if (!d_bits || !out) return fail(VI_E_INVALID_ARG, "NULL bits or descriptor");
+    if (((uintptr_t)d_bits) % 4) return fail(VI_E_INVALID_ARG, "bits pointer must be 4-byte aligned");
+    hipError_t e = vi::launch_occupancy(vol->minmax, cells_of(vol->n, vol->cell), tf->rgba, tf->n_entries, d_bits,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return fail(VI_E_DEVICE, "occupancy launch failed: %s", hipGetErrorString(e));
+    *out = *vol;
+    out->occ = d_bits;
+    out->occ_tag = occ_tag_of(vol, tf);
+    return VI_OK;
+}
+
 int vi_volume_minmax(const vi_volume* vol, int cell, float* d_minmax, vi_volume* out, vi_stream_t stream)
 {
     clear_err();
@@ -312,6 +373,8 @@ int vi_volume_minmax(const vi_volume* vol, int cell, float* d_minmax, vi_volume*
     *out = *vol;
     out->minmax = d_minmax;
     out->cell = cell;
+    out->occ = nullptr;  // bits belong to the previous map
+    out->occ_tag = 0;
     return VI_OK;
 }
 
@@ -355,6 +418,7 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     int rc;
     if ((rc = check_volume(vol)) != VI_OK) return rc;
     if ((rc = check_tf(tf)) != VI_OK) return rc;
+    if ((rc = check_occ(vol, tf)) != VI_OK) return rc;
     if (!d_slices) return fail(VI_E_INVALID_ARG, "NULL stack buffer");
     if (!out_desc) return fail(VI_E_INVALID_ARG, "NULL stack descriptor");
     vi_slices f;
@@ -451,6 +515,7 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     int rc;
     if ((rc = check_volume(vol)) != VI_OK) return rc;
     if ((rc = check_tf(tf)) != VI_OK) return rc;
+    if ((rc = check_occ(vol, tf)) != VI_OK) return rc;
     if (mode < VI_MODE_NONE || mode > VI_MODE_PHONG) return fail(VI_E_UNSUPPORTED, "mode %d not supported", mode);
     if (!cam) return fail(VI_E_INVALID_ARG, "NULL camera");
     if (!d_rgba) return fail(VI_E_INVALID_ARG, "NULL output image");

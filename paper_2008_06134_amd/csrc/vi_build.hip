@@ -13,6 +13,8 @@
 // every slab a wave stores two whole 8 x 4 texel tiles, i.e. two full
 // 128-byte lines; 64 x 4 texels (a wave per 64-texel row run) for the row
 // stack.  The alpha column of the transfer function sits in LDS.
+#include <algorithm>
+
 #include "vi_device.h"
 #include "vi_internal.h"
 
@@ -59,12 +61,14 @@ __global__ __launch_bounds__(256) void border_kernel(ET* __restrict__ out, int n
 constexpr int kBatch = VI_BUILD_BATCH;
 
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool DARKEN>
-__global__ __launch_bounds__(256) void build_kernel(BuildParams P)
+__device__ __forceinline__ void build_columns(const BuildParams& P)
 {
-    extern __shared__ float s_alpha[];  // K alphas, then K next-opaque indices
+    extern __shared__ float s_alpha[];  // K alphas, K next-opaque indices, then the occupancy bits
     int* s_next = (int*)(s_alpha + P.K);
+    uint32_t* s_bits = (uint32_t*)(s_next + P.K);
     for (int t = threadIdx.x; t < P.K; t += blockDim.x) s_alpha[t] = P.tf[4 * t + 3];
     build_next_opaque(s_next, P.tf, P.K);  // read by every batch (unused without a map)
+    stage_occupancy(P.occ, s_bits);
     __syncthreads();
 
     constexpr int BX = BuildBlock<SL>::X, BY = BuildBlock<SL>::Y;
@@ -108,6 +112,7 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     uint32_t last_cell = 0xffffffffu;
     bool cell_is_empty = false;
     const bool use_map = P.occ.mm != nullptr;
+    const bool use_bits = P.occ.bits != nullptr;  // verdicts from the occupancy bits, no map loads
 
     // The slabs go in batches of kBatch: first every slab's position and the
     // map entries of newly entered cells (loaded together), then the
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
                 cell[u] = cell_of((int)floorf(hx[u]) + P.M, (int)floorf(hy[u]) + P.M, (int)floorf(hz[u]) + P.M, P.N,
                                   P.occ.shift, P.occ.nc);
                 if (cell[u] != cur) {
-                    mm[u] = P.occ.mm[cell[u]];  // a newly entered cell
+                    if (!use_bits) mm[u] = P.occ.mm[cell[u]];  // a newly entered cell
                     cur = cell[u];
                 }
             }
@@ -149,7 +154,13 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
         // verdict is used.
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const bool empty = cell_empty(mm[u], s_next, Km1, P.K);
+            // Both verdicts are taken and one is selected (slabs outside the
+            // cube, and runs without bits, read word 0 of the bits: always
+            // allocated, unused then)
+            const uint32_t cq = (cell[u] == 0xffffffffu || !use_bits) ? 0u : cell[u];
+            const bool empty_bit = !occupancy_bit(s_bits, cq);
+            const bool empty_map = cell_empty(mm[u], s_next, Km1, P.K);
+            const bool empty = use_bits ? empty_bit : empty_map;
             const bool entered = use_map && fetch[u] && cell[u] != last_cell;
             cell_is_empty = entered ? empty : cell_is_empty;
             last_cell = entered ? cell[u] : last_cell;
@@ -192,11 +203,33 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
     }
 }
 
+// The kernel.  With the quad layout of 8- and 16-bit voxels a batch's
+// footprints take few registers, and five resident waves per SIMD (at most
+// 96 VGPRs, no spills) measured faster than the compiler's choice of four;
+// the other cases (eight voxels per footprint, 32-bit quads, the
+// compensation) keep the compiler's budget.
+template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool DARKEN>
+__global__ __launch_bounds__(256) void build_kernel(BuildParams P)
+{
+    build_columns<VT, LAYOUT, OUT_DTYPE, SL, DARKEN>(P);
+}
+template <typename VT, int OUT_DTYPE, int SL, bool DARKEN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void build_kernel_quads(BuildParams P)
+{
+    build_columns<VT, VI_LAYOUT_QUAD4, OUT_DTYPE, SL, DARKEN>(P);
+}
+
 template <typename VT, int LAYOUT, int SL, bool DARKEN>
 static void launch_build_k(const BuildParams& p, dim3 grid, size_t lds, hipStream_t s)
 {
+    constexpr bool kFive = LAYOUT == VI_LAYOUT_QUAD4 && sizeof(VT) <= 2 && !DARKEN;
     if (p.out_dtype == VI_F32)
-        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, SL, DARKEN>), grid, dim3(256), lds, s, p);
+        if constexpr (kFive)
+            hipLaunchKernelGGL((build_kernel_quads<VT, VI_F32, SL, DARKEN>), grid, dim3(256), lds, s, p);
+        else
+            hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, SL, DARKEN>), grid, dim3(256), lds, s, p);
+    else if constexpr (kFive)
+        hipLaunchKernelGGL((build_kernel_quads<VT, VI_BF16, SL, DARKEN>), grid, dim3(256), lds, s, p);
     else
         hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, SL, DARKEN>), grid, dim3(256), lds, s, p);
 }
@@ -208,7 +241,8 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
     const uint32_t bx = rows ? BuildBlock<VI_STACK_ROWS>::X : BuildBlock<VI_STACK_TILED>::X;
     const uint32_t by = rows ? BuildBlock<VI_STACK_ROWS>::Y : BuildBlock<VI_STACK_TILED>::Y;
     const dim3 grid(supertile_grid(((uint32_t)p.res + bx - 1) / bx, ((uint32_t)p.res + by - 1) / by));
-    const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K;
+    // (at least one word of bits, which the slab loop reads even without them)
+    const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K + sizeof(uint32_t) * std::max(p.occ.words, 1u);
     const bool dk = p.darken > 0.0f;
     if (rows) {
         if (dk) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds, s);

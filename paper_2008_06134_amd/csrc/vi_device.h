@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/vi.h"
+#include "vi_internal.h"
 
 namespace vi {
 
@@ -257,6 +258,25 @@ __device__ __forceinline__ bool cell_empty(const float2 m, const int* s_next, fl
     const int hi = min((int)(m.y * Km1) + 2, K - 1);
     return s_next[lo] > hi;
 }
+// Whether cell c may hold opacity: its occupancy bit (the LDS copy
+// `s_bits`), or the map entry against the transfer function.
+__device__ __forceinline__ bool cell_occupied(const OccMap& o, const uint32_t* s_bits, uint32_t c,
+                                              const int* s_next, float Km1, int K)
+{
+    if (o.bits) return (s_bits[c >> 5] >> (c & 31u)) & 1u;
+    return !cell_empty(o.mm[c], s_next, Km1, K);
+}
+__device__ __forceinline__ bool occupancy_bit(const uint32_t* s_bits, uint32_t c)
+{
+    return (s_bits[c >> 5] >> (c & 31u)) & 1u;
+}
+// Stage the occupancy bits in LDS (call before the workgroup's barrier).
+__device__ __forceinline__ void stage_occupancy(const OccMap& o, uint32_t* s_bits)
+{
+    if (o.bits)
+        for (uint32_t w = threadIdx.x; w < o.words; w += blockDim.x) s_bits[w] = o.bits[w];
+}
+
 // Cell index of a trilinear footprint whose lower corner is voxel (x0,y0,z0)
 // (before clamping).
 __device__ __forceinline__ uint32_t cell_of(int x0, int y0, int z0, int N, int shift, uint32_t nc)

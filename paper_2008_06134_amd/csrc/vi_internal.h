@@ -20,11 +20,17 @@ constexpr int kMaxTaps = 49;     // largest gather (7 x 7 lattice)
 // ---------------------------------------------------------------------------
 // Empty-space map: per cell of 2^shift voxels, (min, max) of the normalised
 // values over the cell's voxels and the next one along each axis.
+// Optional occupancy bits for the frame's transfer function: one bit per
+// cell (1 = may hold opacity), staged in LDS by every workgroup.  Used only
+// when they fit in kMaxLdsOccWords; larger maps are decided from mm.
 struct OccMap {
     const float2* mm;   // nullptr: no skipping
     int shift;
     uint32_t nc;        // cells per axis
+    const uint32_t* bits;  // nullptr: decide from mm and the transfer function
+    uint32_t words;        // 32-bit words of bits
 };
+constexpr uint32_t kMaxLdsOccWords = 2048;  // 8 KiB of bits (65536 cells)
 
 struct BuildParams {
     const void* vol;
@@ -119,13 +125,17 @@ struct RenderFrame {
 hipError_t launch_build(const BuildParams& p, hipStream_t s);
 hipError_t launch_render(const RenderFrame& f, hipStream_t s);
 // one launch over `ntiles` tiles whose frames all have kernel_mode() `mode`
+// (maxK / max_occ_words: the largest transfer function and LDS occupancy
+// bits of the frames, which size the launch's LDS)
 hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout, int mode,
                                const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
-                               hipStream_t s);
+                               uint32_t max_occ_words, hipStream_t s);
 hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStream_t s);
 hipError_t launch_to_quads(const void* src, void* dst, int dtype, int N, hipStream_t s);
 hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
                          int shift, float* out, hipStream_t s);
+hipError_t launch_occupancy(const float* minmax, uint32_t cells, const float* tf, int K, uint32_t* bits,
+                            hipStream_t s);
 
 // Kernel variants beyond the public modes: for a point light the light grid
 // is a perspective frustum (every stack lookup divides by its depth) and

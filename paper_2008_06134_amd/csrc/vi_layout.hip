@@ -151,4 +151,34 @@ hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, u
     }
 }
 
+// Occupancy bits for one transfer function: one thread per 32-cell word,
+// bit i = cell 32w+i may hold opacity (the negation of the map's emptiness
+// test against the table's next-opaque indices, built in LDS per block).
+__global__ __launch_bounds__(256) void occupancy_kernel(const float2* __restrict__ mm, uint32_t cells,
+                                                        const float* __restrict__ tf, int K, uint32_t* __restrict__ bits)
+{
+    extern __shared__ int s_next[];
+    build_next_opaque(s_next, tf, K);
+    __syncthreads();
+    const uint32_t w = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t words = (cells + 31u) / 32u;
+    if (w >= words) return;
+    const float Km1 = (float)(K - 1);
+    uint32_t b = 0;
+    for (uint32_t i = 0; i < 32u; ++i) {
+        const uint32_t c = w * 32u + i;
+        if (c < cells && !cell_empty(mm[c], s_next, Km1, K)) b |= 1u << i;
+    }
+    bits[w] = b;
+}
+
+hipError_t launch_occupancy(const float* minmax, uint32_t cells, const float* tf, int K, uint32_t* bits,
+                            hipStream_t s)
+{
+    const uint32_t words = (cells + 31u) / 32u;
+    hipLaunchKernelGGL(occupancy_kernel, dim3((words + 255u) / 256u), dim3(256), sizeof(int) * (size_t)K, s,
+                       (const float2*)minmax, cells, tf, K, bits);
+    return hipGetLastError();
+}
+
 }  // namespace vi

@@ -356,7 +356,8 @@ __device__ __forceinline__ uint32_t group_bits(bool p, int base)
 
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL, int G>
 __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf,
-                                             const int* __restrict__ s_next, int px, int py, uint32_t& nsamp)
+                                             const int* __restrict__ s_next, const uint32_t* __restrict__ s_bits,
+                                             int px, int py, uint32_t& nsamp)
 {
     const int lane = threadIdx.x & 63, g = lane % G, gbase = lane - g;
     // ---- camera ray (double)
@@ -504,7 +505,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                 const uint32_t c = ((uint32_t)cz * F.occ.nc + (uint32_t)cy) * F.occ.nc + (uint32_t)cx;
                 if (c != last_cell) {
                     last_cell = c;
-                    cell_is_empty = cell_empty(F.occ.mm[c], s_next, Km1, F.K);
+                    cell_is_empty = !cell_occupied(F.occ, s_bits, c, s_next, Km1, F.K);
                 }
                 empty = cell_is_empty;
                 if (empty) {
@@ -645,13 +646,13 @@ __device__ __forceinline__ void block_pixel(uint32_t tx, uint32_t ty, int* px, i
 }
 
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
-__device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* s_tf, const int* s_next, int px,
-                                            int py)
+__device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* s_tf, const int* s_next,
+                                            const uint32_t* s_bits, int px, int py)
 {
     uint32_t ns = 0;
     const int lane = threadIdx.x & 63;
     if (px < F.width && py < F.height) {
-        const float4 c = render_ray<VT, LAYOUT, MODE, SDT, SL, kG>(F, s_tf, s_next, px, py, ns);
+        const float4 c = render_ray<VT, LAYOUT, MODE, SDT, SL, kG>(F, s_tf, s_next, s_bits, px, py, ns);
         if (lane % kG == 0) F.out[(size_t)py * F.width + px] = c;
     }
     if (F.samples) {
@@ -667,11 +668,13 @@ __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* 
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
 __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_kernel(RenderFrame F)
 {
-    extern __shared__ float4 s_tf[];  // K entries, then K next-opaque indices
+    extern __shared__ float4 s_tf[];  // K entries, K next-opaque indices, then the occupancy bits
     int* s_next = (int*)(s_tf + F.K);
+    uint32_t* s_bits = (uint32_t*)(s_next + F.K);
     for (int t = threadIdx.x; t < F.K; t += blockDim.x)
         s_tf[t] = make_float4(F.tf[4 * t], F.tf[4 * t + 1], F.tf[4 * t + 2], F.tf[4 * t + 3]);
-    if (F.occ.mm) build_next_opaque(s_next, F.tf, F.K);
+    if (F.occ.mm && !F.occ.bits) build_next_opaque(s_next, F.tf, F.K);
+    stage_occupancy(F.occ, s_bits);
     __syncthreads();
 
     const uint32_t tiles_x = (F.width + kBX - 1) / kBX, tiles_y = (F.height + kBY - 1) / kBY;
@@ -679,7 +682,7 @@ __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_kernel(RenderF
     if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
     int px, py;
     block_pixel(tx, ty, &px, &py);
-    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, px, py);
+    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, px, py);
 }
 
 // --------------------------------------------------------------------------
@@ -702,20 +705,22 @@ __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_batch_kernel(c
     const uint32_t t = tiles[q / kSub], sub = q % kSub;
     const RenderFrame& F = frames[t >> 22];
     int* s_next = (int*)(s_tf + F.K);
+    uint32_t* s_bits = (uint32_t*)(s_next + F.K);
     for (int i = threadIdx.x; i < F.K; i += blockDim.x)
         s_tf[i] = make_float4(F.tf[4 * i], F.tf[4 * i + 1], F.tf[4 * i + 2], F.tf[4 * i + 3]);
-    if (F.occ.mm) build_next_opaque(s_next, F.tf, F.K);
+    if (F.occ.mm && !F.occ.bits) build_next_opaque(s_next, F.tf, F.K);
+    stage_occupancy(F.occ, s_bits);
     __syncthreads();
     int px, py;
     block_pixel((t & 2047u) * kSubX + sub % kSubX, ((t >> 11) & 2047u) * kSubY + sub / kSubX, &px, &py);
-    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, px, py);
+    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, px, py);
 }
 
 template <typename VT, int LAYOUT, int SDT, int SL>
 static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles,
-                                 int maxK, hipStream_t s)
+                                 int maxK, uint32_t occ_words, hipStream_t s)
 {
-    const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)maxK;
+    const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)maxK + sizeof(uint32_t) * (size_t)occ_words;
     const dim3 grid(list_grid(ntiles * kSub)), block(256);
     switch (mode) {
     case VI_MODE_NONE:
@@ -760,35 +765,36 @@ static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const ui
 
 template <typename VT, int LAYOUT>
 static hipError_t launch_batch_l(int sdt, int sl, int mode, const RenderFrame* f, const uint32_t* t, uint32_t n,
-                                 int K, hipStream_t s)
+                                 int K, uint32_t w, hipStream_t s)
 {
     if (sdt == VI_BF16)
-        return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(mode, f, t, n, K, s)
-                                   : launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(mode, f, t, n, K, s);
-    return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(mode, f, t, n, K, s)
-                               : launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_TILED>(mode, f, t, n, K, s);
+        return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(mode, f, t, n, K, w, s)
+                                   : launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(mode, f, t, n, K, w, s);
+    return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(mode, f, t, n, K, w, s)
+                               : launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_TILED>(mode, f, t, n, K, w, s);
 }
 
 template <typename VT>
 static hipError_t launch_batch_vt(int layout, int sdt, int sl, int mode, const RenderFrame* f, const uint32_t* t,
-                                  uint32_t n, int K, hipStream_t s)
+                                  uint32_t n, int K, uint32_t w, hipStream_t s)
 {
-    if (layout == VI_LAYOUT_QUAD4) return launch_batch_l<VT, VI_LAYOUT_QUAD4>(sdt, sl, mode, f, t, n, K, s);
-    return layout == VI_LAYOUT_BRICK4 ? launch_batch_l<VT, VI_LAYOUT_BRICK4>(sdt, sl, mode, f, t, n, K, s)
-                                      : launch_batch_l<VT, VI_LAYOUT_LINEAR>(sdt, sl, mode, f, t, n, K, s);
+    if (layout == VI_LAYOUT_QUAD4) return launch_batch_l<VT, VI_LAYOUT_QUAD4>(sdt, sl, mode, f, t, n, K, w, s);
+    return layout == VI_LAYOUT_BRICK4 ? launch_batch_l<VT, VI_LAYOUT_BRICK4>(sdt, sl, mode, f, t, n, K, w, s)
+                                      : launch_batch_l<VT, VI_LAYOUT_LINEAR>(sdt, sl, mode, f, t, n, K, w, s);
 }
 
 hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int stack_layout, int mode,
                                const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles, int maxK,
-                               hipStream_t s)
+                               uint32_t max_occ_words, hipStream_t s)
 {
+    const uint32_t w = max_occ_words;
     switch (vol_dtype) {
-    case VI_U8: return launch_batch_vt<uint8_t>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
+    case VI_U8: return launch_batch_vt<uint8_t>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, w, s);
     case VI_U16:
-        return launch_batch_vt<uint16_t>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
+        return launch_batch_vt<uint16_t>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, w, s);
     case VI_F16:
-        return launch_batch_vt<__half>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
-    default: return launch_batch_vt<float>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, s);
+        return launch_batch_vt<__half>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, w, s);
+    default: return launch_batch_vt<float>(layout, stack_dtype, stack_layout, mode, d_frames, d_tiles, ntiles, maxK, w, s);
     }
 }
 
@@ -796,7 +802,7 @@ template <typename VT, int LAYOUT, int SDT, int SL>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
     dim3 grid(supertile_grid((f.width + kBX - 1) / kBX, (f.height + kBY - 1) / kBY)), block(256);
-    const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K;
+    const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K + (f.occ.bits ? sizeof(uint32_t) * f.occ.words : 0);
     switch (kernel_mode(f)) {
     case VI_MODE_NONE:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>), grid, block, lds, s, f);

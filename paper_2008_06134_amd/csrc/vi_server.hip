@@ -144,6 +144,7 @@ public:
         const RenderFrame* d_frames = (const RenderFrame*)S.d_stage;
         const uint32_t* d_tiles = (const uint32_t*)((const char*)S.d_stage + frames_bytes);
         int maxK = 2;
+        uint32_t occ_words = 0;  // LDS occupancy bits of the largest frame
         for (size_t f = 0; f < frames.size(); ++f) {
             const vi_request& r = *frames[f].req;
             const sched::VolumeRec& v = *frames[f].vol;
@@ -151,6 +152,7 @@ public:
                                 r.d_rgba, r.d_samples, &h_frames[f]);
             if (rc != VI_OK) return rc;
             maxK = std::max(maxK, v.tf.n_entries);
+            if (h_frames[f].occ.bits) occ_words = std::max(occ_words, h_frames[f].occ.words);
         }
         // tiles grouped by kernel mode (stable), one kernel per mode present
         constexpr int kModes = kKernelModes;
@@ -172,7 +174,7 @@ public:
         for (int m = 0; m < kModes && e == hipSuccess; ++m)
             if (count[m])
                 e = launch_render_batch(v0.dtype, v0.layout, frames[0].req->slice_dtype, frames[0].req->slice_layout,
-                                        m, d_frames, d_tiles + start[m], count[m], maxK, rs_);
+                                        m, d_frames, d_tiles + start[m], count[m], maxK, occ_words, rs_);
         if (e == hipSuccess) e = hipEventRecord(S.done, rs_);
         if (e != hipSuccess) return fail_msg(VI_E_DEVICE, hipGetErrorString(e));
         S.busy = true;

@@ -35,7 +35,8 @@ VI_STACK_TILED, VI_STACK_ROWS = 0, 1
 
 class Volume_t(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int), ("n", C.c_int), ("scale", C.c_float),
-                ("layout", C.c_int), ("minmax", C.c_void_p), ("cell", C.c_int)]
+                ("layout", C.c_int), ("minmax", C.c_void_p), ("cell", C.c_int), ("occ", C.c_void_p),
+                ("occ_tag", C.c_uint64)]
 
 
 class TF_t(C.Structure):
@@ -108,6 +109,9 @@ SIGNATURES = {
     "vi_volume_to_quads": ([C.POINTER(Volume_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
     "vi_volume_minmax_bytes": ([C.c_int, C.c_int], C.c_size_t),
     "vi_volume_minmax": ([C.POINTER(Volume_t), C.c_int, C.c_void_p, C.POINTER(Volume_t), C.c_void_p], C.c_int),
+    "vi_volume_occupancy_bytes": ([C.c_int, C.c_int], C.c_size_t),
+    "vi_volume_occupancy": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.c_void_p, C.POINTER(Volume_t), C.c_void_p],
+                            C.c_int),
     "vi_light_frame": ([C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(BuildOpts_t),
                         C.POINTER(Slices_t)], C.c_int),
     "vi_build_attenuation": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_double), C.c_int, C.c_int,
@@ -234,6 +238,24 @@ class Volume:
                                       _stream(stream)))
         v = Volume(self.data, self.scale, self.n, self.layout)
         v.minmax = out
+        v.s = res
+        return v
+
+    def with_occupancy(self, tf: "TF", out: torch.Tensor | None = None, stream=None) -> "Volume":
+        """The same volume with occupancy bits for `tf` (vi_volume_occupancy): one
+        bit per empty-space cell, which the passes read instead of the map.  The
+        volume must have a map (with_minmax) and is then rendered with `tf` only."""
+        if self.minmax is None:
+            raise ValueError("occupancy bits need an empty-space map (with_minmax)")
+        nbytes = int(lib().vi_volume_occupancy_bytes(self.n, int(self.s.cell)))
+        if out is None:
+            out = torch.empty(max(nbytes // 4, 1), dtype=torch.int32, device=self.data.device)
+        res = Volume_t()
+        _check(lib().vi_volume_occupancy(C.byref(self.s), C.byref(tf.s), C.c_void_p(out.data_ptr()), C.byref(res),
+                                         _stream(stream)))
+        v = Volume(self.data, self.scale, self.n, self.layout)
+        v.minmax = self.minmax
+        v.occ = out
         v.s = res
         return v
 

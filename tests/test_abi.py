@@ -283,6 +283,27 @@ def test_volume_bytes_and_brick_validation():
     assert vi.slices_bytes(2, 8, vi.VI_F32, 5) == 0
 
 
+def test_occupancy_validation():
+    lib = vi.lib()
+    assert lib.vi_volume_occupancy_bytes(512, 16) == 32 ** 3 // 32 * 4
+    assert lib.vi_volume_occupancy_bytes(33, 8) == (5 ** 3 + 31) // 32 * 4
+    assert lib.vi_volume_occupancy_bytes(33, 5) == 0 and lib.vi_volume_occupancy_bytes(1, 8) == 0
+    f = _Fake()
+    out = vi.Volume_t()
+    assert lib.vi_volume_occupancy(C.byref(f.vol), C.byref(f.tf), C.c_void_p(0x60000), C.byref(out), None) == -1
+    assert "map" in lib.vi_last_error().decode()                 # no empty-space map
+    f.vol.minmax, f.vol.cell = 0x70000, 8
+    assert lib.vi_volume_occupancy(C.byref(f.vol), C.byref(f.tf), C.c_void_p(0x60002), C.byref(out), None) == -1
+    assert lib.vi_volume_occupancy(C.byref(f.vol), C.byref(f.tf), None, C.byref(out), None) == -1
+    # the passes take bits only with the transfer function (and map) they were made for
+    f.vol.occ, f.vol.occ_tag = 0x60000, 12345
+    assert _build(f) == -1
+    assert "occupancy" in lib.vi_last_error().decode()
+    assert _render(f, _desc(f), mode=2) == -1
+    f.vol.minmax = None                                            # bits without a map
+    assert _build(f) == -1
+
+
 def test_minmax_validation():
     lib = vi.lib()
     assert lib.vi_volume_minmax_bytes(512, 8) == 64 ** 3 * 8

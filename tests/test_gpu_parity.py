@@ -486,3 +486,82 @@ def test_coloured_light_parity():
         err = np.abs(img - ref).max()
         report(f"coloured light {mode}", err)
         assert err <= TOL_IMG
+
+
+# ---------------------------------------------------------------- occupancy bits
+
+def _occupancy_reference(mm, tab):
+    """Bit per cell: some transfer-function entry the cell's value range can
+    interpolate (widened by one entry each side) has non-zero opacity."""
+    K = tab.shape[0]
+    lo = np.maximum((mm[:, 0].astype(np.float32) * np.float32(K - 1)).astype(np.int64) - 1, 0)
+    hi = np.minimum((mm[:, 1].astype(np.float32) * np.float32(K - 1)).astype(np.int64) + 2, K - 1)
+    opaque = np.flatnonzero(tab[:, 3] > 0)
+    occ = np.zeros(mm.shape[0], bool)
+    for c in range(mm.shape[0]):
+        occ[c] = np.any((opaque >= lo[c]) & (opaque <= hi[c]))
+    return occ
+
+
+@pytest.mark.parametrize("cell", [4, 8, 16])
+def test_occupancy_bits_match_their_definition(cell):
+    raw = W.ct_phantom_u16(48, seed=12, vessels=True)
+    tab = W.tf_ct()
+    vol, tf = gpu_inputs(raw, tab, cell=cell)
+    occ = vol.with_occupancy(tf)
+    torch.cuda.synchronize()
+    mm = vol.minmax.view(-1, 2).cpu().numpy()
+    words = occ.occ.cpu().numpy().view(np.uint32)
+    bits = ((words[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)[:mm.shape[0]].astype(bool)
+    want = _occupancy_reference(mm, tab)
+    assert np.array_equal(bits, want)
+    assert want.any()
+    if cell <= 8:                                  # 27 cells of 16^3 are all occupied here
+        assert not want.all()
+
+
+@pytest.mark.parametrize("N,cell", [(64, 8), (168, 4)])   # bits in LDS; 74088 cells: bits read from memory
+@pytest.mark.parametrize("mode", ["none", "shadow", "shell", "cone", "cone5", "phong"])
+def test_occupancy_bits_change_nothing(N, cell, mode):
+    """Stacks, images and sample counts with the bits equal those with the map alone, bit for bit."""
+    raw = W.ct_phantom_u16(N, seed=13, vessels=True)
+    tab = W.tf_ct()
+    mapped, tf = gpu_inputs(raw, tab, cell=cell)
+    bits = mapped.with_occupancy(tf)
+    light = [0.35, -0.5, -0.79]
+    n, res = N // 2, N
+    s1 = vi.build_attenuation(mapped, tf, light, n, res, layout=vi.VI_STACK_ROWS)
+    s2 = vi.build_attenuation(bits, tf, light, n, res, layout=vi.VI_STACK_ROWS)
+    torch.cuda.synchronize()
+    assert torch.equal(s1.dense(), s2.dense())
+    m, extra = _mode(mode)
+    cam = W.camera_orbit(96, 72, 1.1, 0.35)
+    a, na = gpu_render(mapped, tf, s1, cam, m, 0.5, extra)
+    b, nb = gpu_render(bits, tf, s1, cam, m, 0.5, extra)
+    assert np.array_equal(a, b) and na == nb
+
+
+def test_occupancy_bits_point_light():
+    raw = W.ct_phantom_u16(56, seed=14, vessels=True)
+    tab = W.tf_ct()
+    mapped, tf = gpu_inputs(raw, tab, cell=8)
+    bits = mapped.with_occupancy(tf)
+    pos = [-0.9, 1.6, 1.3]
+    s1 = vi.build_attenuation(mapped, tf, None, 40, 64, position=pos)
+    s2 = vi.build_attenuation(bits, tf, None, 40, 64, position=pos)
+    torch.cuda.synchronize()
+    assert torch.equal(s1.dense(), s2.dense())
+    cam = W.camera_orbit(80, 64, 2.0, 0.3)
+    for m in ("shadow", "shell", "phong"):
+        a, na = gpu_render(mapped, tf, s1, cam, m, 0.5)
+        b, nb = gpu_render(bits, tf, s1, cam, m, 0.5)
+        assert np.array_equal(a, b) and na == nb
+
+
+def test_occupancy_bits_refuse_another_transfer_function():
+    raw = W.ct_phantom_u16(32, seed=15)
+    vol, tf = gpu_inputs(raw, W.tf_ct(), cell=8)
+    bits = vol.with_occupancy(tf)
+    other = vi.TF.from_numpy(W.tf_ramp(), DEV)
+    with pytest.raises(vi.VIError):
+        vi.build_attenuation(bits, other, [0, 0, 1], 16, 32)

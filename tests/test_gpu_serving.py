@@ -20,7 +20,10 @@ def _volumes():
     for k, N in enumerate([48, 64, 80, 96]):
         raw = W.ct_phantom_u16(N, seed=100 + k, vessels=(k % 2 == 1))
         v = vi.Volume.from_numpy(raw, DEV).to_quads().with_minmax(16)
-        vols.append((N, v, vi.TF.from_numpy(W.tf_ct(), DEV)))
+        tf = vi.TF.from_numpy(W.tf_ct(), DEV)
+        if k % 2 == 0:
+            v = v.with_occupancy(tf)     # a launch mixes frames with and without occupancy bits
+        vols.append((N, v, tf))
     return vols
 
 
