@@ -36,17 +36,17 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
                   "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
 MEASURED_TRAFFIC = {
-    # large workload (512^3 u16 in the quad layout, 16^3 empty-space cells, 512 x 1024^2 f32 stack in
-    # rows, 1920x1080), light 0
+    # large workload (512^3 u16 in the quad layout, 16^3 empty-space cells with occupancy bits, 512 x
+    # 1024^2 f32 stack in rows, 1920x1080), light 0
     ("render_cone", "large", "rows", 16, "quads"): {
-        "sha256": "4ddaa76dcb691aed4be35c602e2c908db21d39188a723419fa578bd94520692c",
-        "fetch_kib": 125650.31, "write_kib": 34832.34},
+        "sha256": "41286ad49ffde1fe4ddb2334386d62a055c40864fabed42d16bab36239158198",
+        "fetch_kib": 124871.75, "write_kib": 34851.84},
     ("render_shell", "large", "rows", 16, "quads"): {
-        "sha256": "4ddaa76dcb691aed4be35c602e2c908db21d39188a723419fa578bd94520692c",
-        "fetch_kib": 113624.25, "write_kib": 34579.47},
+        "sha256": "41286ad49ffde1fe4ddb2334386d62a055c40864fabed42d16bab36239158198",
+        "fetch_kib": 113817.94, "write_kib": 34809.78},
     ("build", "large", "rows", 16, "quads"): {       # build kernel plus the border kernel
-        "sha256": "04ecfc298e988099158c26cc3bbddd349614a429c2a27ce32912ef86d3427e5e",
-        "fetch_kib": 198002.25 + 16.5, "write_kib": 2332031.41 + 28953.44},
+        "sha256": "531e58676c8192bae79444b29bd3e670583aa1cbdf958e8503bf22bac7ea830b",
+        "fetch_kib": 201830.62 + 12.5, "write_kib": 2262495.31 + 28953.72},
 }
 
 
@@ -471,8 +471,8 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": None if args.point_light else measured_traffic(dom, w.name, args.stack_layout,
-                                                                           args.cell, args.volume_layout),
+                "traffic": None if (args.point_light or args.no_occupancy) else
+                measured_traffic(dom, w.name, args.stack_layout, args.cell, args.volume_layout),
                 "bytes_per_launch": per_launch, "avg_launch_ms": round(float(avg_ms), 4)}
     kernels = {"volume_prepare_ms_once": round(m["prep_ms"], 3),
                "build_ms_mean": round(float(np.mean(build_ms)), 4),
