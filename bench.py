@@ -381,8 +381,9 @@ def main():
                     help="only run the slab-count x slice-resolution sweep (build and frame times)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only run the full serving sweep (64 volumes, 6 arrival rates, 2000 requests each)")
-    ap.add_argument("--cell", type=int, default=16, choices=[4, 8, 16, 32],
-                    help="edge in voxels of the empty-space map's cells")
+    ap.add_argument("--cell", type=int, default=0, choices=[0, 4, 8, 16, 32],
+                    help="edge in voxels of the empty-space map's cells; 0 = the smallest of 16 and 32 whose "
+                         "occupancy bits fit in LDS (at most 65536 cells): 16 at 512^3, 32 at 1024^3")
     ap.add_argument("--stack-layout", default="rows", choices=["tiled", "rows"],
                     help="stack layout of every stack built (rows: one 8-byte load per bilinear row)")
     ap.add_argument("--volume-layout", default="auto", choices=["auto", "bricks", "quads"],
@@ -429,6 +430,8 @@ def main():
         return
 
     w = W.WORKLOADS[args.workload]
+    if args.cell == 0:
+        args.cell = 16 if -(-w.N // 16) ** 3 <= 65536 else 32
     t0 = time.perf_counter()
     raw, tab = w.volume(), w.tf()
     log(f"workload {w.name}: {raw.shape} {raw.dtype} generated in {time.perf_counter() - t0:.1f} s")
