@@ -30,16 +30,19 @@ def _mode(m):
     return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
 
 
-def gpu_inputs(raw, tab, scale=None, quads=True, cell=16):
-    """Device volume -- by default as the benchmark runs it: the quad layout
-    (4x4x4 bricks of 2x2 neighbourhoods) with an empty-space map of 16^3-voxel
-    cells -- and TF."""
+def gpu_inputs(raw, tab, scale=None, quads=True, cell=16, bits=False):
+    """Device volume -- with quads=True and bits=True as the benchmark runs it:
+    the quad layout (4x4x4 bricks of 2x2 neighbourhoods) with an empty-space
+    map of 16^3-voxel cells and its occupancy bits for the TF -- and TF."""
     vol = vi.Volume.from_numpy(raw, DEV, scale)
     if quads:
         vol = vol.to_quads()
+    tf = vi.TF.from_numpy(tab, DEV)
     if cell:
         vol = vol.with_minmax(cell)
-    return vol, vi.TF.from_numpy(tab, DEV)
+        if bits:
+            vol = vol.with_occupancy(tf)
+    return vol, tf
 
 
 def gpu_render(vol, tf, st, cam, mode, step, opts=None):
@@ -60,7 +63,7 @@ def test_small_full_image(mode):
     w = W.WORKLOADS["small"]
     raw, tab = w.volume(), w.tf()
     light = w.lights()[0]
-    vol, tf = gpu_inputs(raw, tab)
+    vol, tf = gpu_inputs(raw, tab, bits=True)
     ost = O.Stack(O.Volume(raw), O.TF(tab), light, w.n_slices, w.res)
     S = ost.export()
     cam = w.camera()
@@ -91,8 +94,9 @@ def _sample_pixels(W_, H_, count, seed):
 
 
 def _sampled_parity(name, raw, tab, light, n, res, cam, mode, step, opts, npix, seed, cols=1500):
-    """Both stack layouts against one oracle reference (sampled stack columns and pixels)."""
-    vol, tf = gpu_inputs(raw, tab)
+    """Both stack layouts against one oracle reference (sampled stack columns and pixels), with the
+    volume as the benchmark prepares it (quads, map, occupancy bits)."""
+    vol, tf = gpu_inputs(raw, tab, bits=True)
     ovol, otf = O.Volume(raw), O.TF(tab)
     ost = O.Stack(ovol, otf, light, n, res)
     rng = np.random.default_rng(seed + 1)

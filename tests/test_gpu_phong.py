@@ -16,8 +16,10 @@ TOL_IMG = 1e-4
 
 
 def _inputs(raw, tab, scale=None):
-    vol = vi.Volume.from_numpy(raw, DEV, scale).to_quads().with_minmax(16)
-    return vol, vi.TF.from_numpy(tab, DEV)
+    """As the benchmark prepares a volume: quads, empty-space map, occupancy bits."""
+    tf = vi.TF.from_numpy(tab, DEV)
+    vol = vi.Volume.from_numpy(raw, DEV, scale).to_quads().with_minmax(16).with_occupancy(tf)
+    return vol, tf
 
 
 def _render(vol, tf, light, cam, opts=None, step=0.5):

@@ -27,10 +27,12 @@ POSITIONS = [[0.5, 0.5, 2.5], [-1.1, 1.7, 1.4], [2.2, -0.4, 0.3], [1.35, 1.35, 1
 
 
 def _inputs(raw, tab, cell=16):
+    """As the benchmark prepares a volume: quads, empty-space map, occupancy bits."""
+    tf = vi.TF.from_numpy(tab, DEV)
     vol = vi.Volume.from_numpy(raw, DEV).to_quads()
     if cell:
-        vol = vol.with_minmax(cell)
-    return vol, vi.TF.from_numpy(tab, DEV)
+        vol = vol.with_minmax(cell).with_occupancy(tf)
+    return vol, tf
 
 
 def _render(vol, tf, st, cam, mode, step, opts=None):

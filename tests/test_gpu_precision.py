@@ -35,8 +35,10 @@ def _phantom(N):
 def _precision_case(N, n, res, cam, light, mode, opts, pix, layout=vi.VI_STACK_ROWS):
     raw, f16 = _phantom(N)
     tab = W.tf_ct()
-    vol = vi.Volume.from_numpy(f16, DEV, 1.0).to_bricks().with_minmax(16)
+    # as the benchmark prepares the precision volume: bricks, the cell size whose occupancy bits fit in LDS
     tf = vi.TF.from_numpy(tab, DEV)
+    cell = 16 if N <= 640 else 32
+    vol = vi.Volume.from_numpy(f16, DEV, 1.0).to_bricks().with_minmax(cell).with_occupancy(tf)
     st = vi.build_attenuation(vol, tf, light, n, res, vi.VI_BF16, layout=layout)
     img = vi.render(vol, tf, st, cam, mode, 0.5, opts)
     torch.cuda.synchronize()
