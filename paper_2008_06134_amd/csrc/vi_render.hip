@@ -190,12 +190,14 @@ struct ConeFrame {
 // is converted (row layout; the tiled layout looks up one at a time), so a
 // gather waits on one round trip per batch of taps.  Larger batches keep
 // more loads in flight per wave but take registers, i.e. resident waves;
-// measured on the 512^3 workload: the ring cone runs fastest with two taps
-// per batch, the shell and the 5 x 5 lattice with one (four loads).
-template <int MODE>
+// measured on the 512^3 workload: the ring cone and the float-stack shell
+// (the latter held to six waves per SIMD) run fastest with two taps per
+// batch, the 5 x 5 lattice with one (four loads); the bfloat16 shell, whose
+// decoding takes more registers, keeps one.
+template <int MODE, int SDT>
 constexpr int tap_batch()
 {
-    return MODE == VI_MODE_CONE ? 2 : 1;
+    return (MODE == VI_MODE_CONE || (MODE == VI_MODE_SHELL && SDT == VI_F32)) ? 2 : 1;
 }
 
 template <int SDT, int SL, int NB>
@@ -221,7 +223,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
     // Taps go in batches; a batch running past the last tap repeats it and
     // leaves the sum alone for the repeats, so every tap is added once, in
     // order, as a one-at-a-time loop adds it.
-    constexpr int NB = tap_batch<MODE>();
+    constexpr int NB = tap_batch<MODE, SDT>();
     float zz[NB], xx[NB], yy[NB], v[NB];
     if (MODE == VI_MODE_SHELL) {
         // weighted taps (shell r's six taps share w_r / (6 sum w))
@@ -305,7 +307,7 @@ __device__ __forceinline__ float gather_point(const RenderFrame& F, float z, flo
     // shell taps: world-frame offsets, each projected through its own depth
     // (batched as in gather())
     float s = 0.0f;
-    constexpr int NB = tap_batch<MODE>();
+    constexpr int NB = tap_batch<MODE, SDT>();
     float zz[NB], xx[NB], yy[NB], val[NB];
     for (int t = 0; t < F.ntaps; t += NB) {
 #pragma unroll
@@ -666,7 +668,7 @@ __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* 
 // single-frame kernel
 // --------------------------------------------------------------------------
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
-__global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_kernel(RenderFrame F)
+__device__ __forceinline__ void render_frame(const RenderFrame& F)
 {
     extern __shared__ float4 s_tf[];  // K entries, K next-opaque indices, then the occupancy bits
     int* s_next = (int*)(s_tf + F.K);
@@ -696,8 +698,8 @@ __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_kernel(RenderF
 constexpr uint32_t kSubX = 16 / kBX, kSubY = 16 / kBY, kSub = kSubX * kSubY;
 
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
-__global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_batch_kernel(const RenderFrame* __restrict__ frames,
-                                                           const uint32_t* __restrict__ tiles, uint32_t ntiles)
+__device__ __forceinline__ void render_tiles(const RenderFrame* __restrict__ frames, const uint32_t* __restrict__ tiles,
+                                             uint32_t ntiles)
 {
     extern __shared__ float4 s_tf[];
     uint32_t q;
@@ -716,6 +718,33 @@ __global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_batch_kernel(c
     shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, px, py);
 }
 
+// The kernels.  The float-stack shell's two-tap batches fit six waves per
+// SIMD (at most 80 VGPRs, no spills), which measured faster than the five
+// the compiler picks for them; the other cases keep the compiler's budget.
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
+__global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_kernel(RenderFrame F)
+{
+    render_frame<VT, LAYOUT, MODE, SDT, SL>(F);
+}
+template <typename VT, int LAYOUT, int SDT, int SL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void render_kernel_shell(RenderFrame F)
+{
+    render_frame<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>(F);
+}
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
+__global__ __launch_bounds__(256) VI_RENDER_OCCUPANCY void render_batch_kernel(const RenderFrame* __restrict__ frames,
+                                                                               const uint32_t* __restrict__ tiles,
+                                                                               uint32_t ntiles)
+{
+    render_tiles<VT, LAYOUT, MODE, SDT, SL>(frames, tiles, ntiles);
+}
+template <typename VT, int LAYOUT, int SDT, int SL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void render_batch_kernel_shell(
+    const RenderFrame* __restrict__ frames, const uint32_t* __restrict__ tiles, uint32_t ntiles)
+{
+    render_tiles<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>(frames, tiles, ntiles);
+}
+
 template <typename VT, int LAYOUT, int SDT, int SL>
 static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const uint32_t* d_tiles, uint32_t ntiles,
                                  int maxK, uint32_t occ_words, hipStream_t s)
@@ -732,8 +761,12 @@ static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const ui
                            d_tiles, ntiles);
         break;
     case VI_MODE_SHELL:
-        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>), grid, block, lds, s, d_frames,
-                           d_tiles, ntiles);
+        if constexpr (SDT == VI_F32)
+            hipLaunchKernelGGL((render_batch_kernel_shell<VT, LAYOUT, SDT, SL>), grid, block, lds, s, d_frames,
+                               d_tiles, ntiles);
+        else
+            hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>), grid, block, lds, s,
+                               d_frames, d_tiles, ntiles);
         break;
     case VI_MODE_CONE:
         hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, d_frames,
@@ -811,7 +844,10 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHADOW, SDT, SL>), grid, block, lds, s, f);
         break;
     case VI_MODE_SHELL:
-        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>), grid, block, lds, s, f);
+        if constexpr (SDT == VI_F32)
+            hipLaunchKernelGGL((render_kernel_shell<VT, LAYOUT, SDT, SL>), grid, block, lds, s, f);
+        else
+            hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_SHELL, SDT, SL>), grid, block, lds, s, f);
         break;
     case VI_MODE_CONE:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_CONE, SDT, SL>), grid, block, lds, s, f);
