@@ -39,14 +39,14 @@ MEASURED_TRAFFIC = {
     # large workload (512^3 u16 in the quad layout, 16^3 empty-space cells with occupancy bits, 512 x
     # 1024^2 f32 stack in rows, 1920x1080), light 0
     ("render_cone", "large", "rows", 16, "quads"): {
-        "sha256": "41286ad49ffde1fe4ddb2334386d62a055c40864fabed42d16bab36239158198",
-        "fetch_kib": 124871.75, "write_kib": 34851.84},
+        "sha256": "8a5108c8d0916c75c0f61051da9ff4414132c58cfe7f2e9c12abc5117ab272bd",
+        "fetch_kib": 124401.62, "write_kib": 34834.91},
     ("render_shell", "large", "rows", 16, "quads"): {
-        "sha256": "41286ad49ffde1fe4ddb2334386d62a055c40864fabed42d16bab36239158198",
-        "fetch_kib": 113817.94, "write_kib": 34809.78},
+        "sha256": "8a5108c8d0916c75c0f61051da9ff4414132c58cfe7f2e9c12abc5117ab272bd",
+        "fetch_kib": 113958.81, "write_kib": 34822.78},
     ("build", "large", "rows", 16, "quads"): {       # build kernel plus the border kernel
         "sha256": "531e58676c8192bae79444b29bd3e670583aa1cbdf958e8503bf22bac7ea830b",
-        "fetch_kib": 201830.62 + 12.5, "write_kib": 2262495.31 + 28953.72},
+        "fetch_kib": 202240.88 + 12.5, "write_kib": 2262386.47 + 28953.56},
 }
 
 
