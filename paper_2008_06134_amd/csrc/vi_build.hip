@@ -213,8 +213,12 @@ __global__ __launch_bounds__(256) void build_kernel(BuildParams P)
 {
     build_columns<VT, LAYOUT, OUT_DTYPE, SL, DARKEN>(P);
 }
+#ifndef VI_BUILD_QUAD_WAVES
+#define VI_BUILD_QUAD_WAVES 5
+#endif
 template <typename VT, int OUT_DTYPE, int SL, bool DARKEN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void build_kernel_quads(BuildParams P)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VI_BUILD_QUAD_WAVES))) void build_kernel_quads(
+    BuildParams P)
 {
     build_columns<VT, VI_LAYOUT_QUAD4, OUT_DTYPE, SL, DARKEN>(P);
 }
