@@ -484,6 +484,10 @@ def main():
         kernels[f"render_{k}_ms_mean"] = round(float(np.mean(v)), 4)
         kernels[f"render_{k}_samples_per_frame"] = samples[k] // args.steps
         kernels[f"render_{k}_samples_per_s"] = round(samples[k] / (sum(v) * 1e-3), 1)
+    # spread of the per-launch HIP-event times (each step renders a different light and camera)
+    kernels["ms_p10_p50_p90"] = {name: [round(float(x), 4) for x in np.percentile(v, [10, 50, 90])]
+                                 for name, v in [("build", build_ms)] + [(f"render_{k}", v)
+                                                                         for k, v in render_ms.items()]}
 
     result = {
         "metric": "ray samples/s (build + shell + cone frames per light direction), 512^3 1080p",
