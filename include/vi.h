@@ -133,10 +133,17 @@ typedef struct {
 } vi_volume;
 
 /* Transfer function: `n_entries` x 4 floats (r,g,b,a) in device memory,
- * 2 <= n_entries <= 1024. */
+ * 2 <= n_entries <= 1024.  Opacities outside [0, 1] are clamped to it.
+ * `tag` names the table's contents: vi_tf_tag() of the same table in host
+ * memory, set by the caller whenever it writes the table.  Stacks and
+ * occupancy bits made with one table are then refused with another, also
+ * one that reuses the device address of a freed table.  tag = 0 leaves the
+ * table identified by its device pointer alone (a table rewritten in place
+ * then goes undetected). */
 typedef struct {
     const float* rgba;
     int n_entries;
+    uint64_t tag;
 } vi_tf;
 
 /* Stack layouts.  Texel (k, j, i): layer k, row j (along V), column i
@@ -339,8 +346,15 @@ int vi_render(const vi_volume* vol, const vi_tf* tf, const vi_slices* slices, co
               float step_vox, const vi_render_opts* opts, float* d_rgba, unsigned long long* d_samples,
               vi_stream_t stream);
 
-/* Identity tag vi_build_attenuation stores in vi_slices.tag for (vol, tf). */
+/* Identity tag vi_build_attenuation stores in vi_slices.tag for (vol, tf):
+ * a hash of the volume's pointer, edge, dtype and scale and of the table's
+ * content tag (its pointer when the tag is 0) and size. */
 uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf);
+
+/* Content tag of a transfer function: FNV-1a over the bytes of the
+ * n_entries x 4 floats at `host_rgba` (HOST memory) and n_entries; never 0.
+ * Returns 0 for a NULL table or n_entries < 1. */
+uint64_t vi_tf_tag(const float* host_rgba, int n_entries);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.

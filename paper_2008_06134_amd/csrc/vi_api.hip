@@ -157,6 +157,18 @@ bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_by
 uint32_t row_origin(int) { return 1u; }
 uint32_t row_pitch(int res, int) { return vi::round_up((uint32_t)res + 4u, 4u); }
 
+// A position or step in voxels as a Q40 fixed-point number (the build's
+// slab positions): |x| < 2^23 voxels, rounded to the nearest 2^-40 voxel.
+int64_t to_q40(double x) { return (int64_t)llround(ldexp(x, vi::kQBits)); }
+
+// A double as a float pair: hi = x rounded to float, lo = the remainder
+// rounded to float (together about 48 significant bits).
+void split_float(double x, float* hi, float* lo)
+{
+    *hi = (float)x;
+    *lo = (float)(x - (double)*hi);
+}
+
 // Light-plane basis (U from the axis least aligned with L, Gram-Schmidt;
 // V = L x U).
 void plane_basis(const double L[3], double U[3], double V[3])
@@ -397,8 +409,24 @@ uint64_t vi_tag(const vi_volume* vol, const vi_tf* tf)
         mix(sb);
     }
     if (tf) {
-        mix((uint64_t)(uintptr_t)tf->rgba);
+        mix(tf->tag ? tf->tag : (uint64_t)(uintptr_t)tf->rgba);
         mix((uint64_t)tf->n_entries);
+    }
+    return h ? h : 1;
+}
+
+uint64_t vi_tf_tag(const float* host_rgba, int n_entries)
+{
+    if (!host_rgba || n_entries < 1) return 0;
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* b = (const unsigned char*)host_rgba;
+    for (size_t i = 0; i < (size_t)n_entries * 4u * sizeof(float); ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    for (int k = 0; k < 4; ++k) {
+        h ^= ((uint32_t)n_entries >> (8 * k)) & 0xffu;
+        h *= 1099511628211ull;
     }
     return h ? h : 1;
 }
@@ -459,26 +487,26 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
         p.point = 1;
         for (int a = 0; a < 3; ++a) {
             const double D00 = f.L[a] + u0 * f.U[a] + u0 * f.V[a];
-            p.B0[a] = (f.P[a] + d0 * D00) * N - 0.5 - p.M;
-            p.BU[a] = d0 * texel * f.U[a] * N;
-            p.BV[a] = d0 * texel * f.V[a] * N;
-            p.AL0[a] = f.ds * D00 * N;
-            p.ALU[a] = f.ds * texel * f.U[a] * N;
-            p.ALV[a] = f.ds * texel * f.V[a] * N;
+            p.B0q[a] = to_q40((f.P[a] + d0 * D00) * N - 0.5 - p.M);
+            p.BUq[a] = to_q40(d0 * texel * f.U[a] * N);
+            p.BVq[a] = to_q40(d0 * texel * f.V[a] * N);
+            p.ALq[a] = to_q40(f.ds * D00 * N);
+            p.ALUq[a] = to_q40(f.ds * texel * f.U[a] * N);
+            p.ALVq[a] = to_q40(f.ds * texel * f.V[a] * N);
         }
     } else {
         for (int a = 0; a < 3; ++a) {
             const double p0 = f.c[a] + u0 * f.U[a] + u0 * f.V[a] + (d0 - Lc) * f.L[a];
-            p.B0[a] = p0 * N - 0.5 - p.M;
-            p.BU[a] = f.U[a] * texel * N;
-            p.BV[a] = f.V[a] * texel * N;
-            p.AL[a] = (float)(f.L[a] * f.ds * N);
+            p.B0q[a] = to_q40(p0 * N - 0.5 - p.M);
+            p.BUq[a] = to_q40(f.U[a] * texel * N);
+            p.BVq[a] = to_q40(f.V[a] * texel * N);
+            p.ALq[a] = to_q40(f.L[a] * f.ds * N);
         }
     }
     p.e = (float)(f.ds * N);
     p.darken = darken;
-    p.lo = (float)(-0.5 - p.M);
-    p.hi = (float)(N - 0.5 - p.M);
+    p.loq = to_q40(-0.5 - p.M);
+    p.hiq = to_q40(N - 0.5 - p.M);
     hipError_t e = vi::launch_build(p, (hipStream_t)stream);
     if (e != hipSuccess) return fail(VI_E_DEVICE, "build launch failed: %s", hipGetErrorString(e));
     f.data = d_slices;
@@ -580,12 +608,17 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     F.tf = tf->rgba;
     F.K = tf->n_entries;
     F.mode = mode;
+    // Geometry is derived in double here and handed to the kernels as float
+    // affine coefficients of the offset-voxel position h = p N - 1/2 - M
+    // (p = (h + 1/2 + M) / N), so that no GPU step needs double.
+    const double Nd = vol->n, hoff = 0.5 + F.M;
     if (mode == VI_MODE_PHONG)
-        for (int a = 0; a < 3; ++a) F.L[a] = sl->L[a];
+        for (int a = 0; a < 3; ++a) F.L[a] = (float)sl->L[a];
     if (point) {
         F.point = 1;
-        for (int a = 0; a < 3; ++a) F.P[a] = sl->P[a];
+        for (int a = 0; a < 3; ++a) split_float(sl->P[a] * Nd - hoff, &F.Ph[a], &F.Phl[a]);
     }
+    double Lq[3] = {0, 0, 0}, Ux[3] = {0, 0, 0}, Vy[3] = {0, 0, 0};  // per world unit
     if (reads_stack) {
         F.stack = sl->data;
         F.stack_dtype = sl->dtype;
@@ -601,21 +634,32 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         F.Mr = sl->res / 2;
         const double span = sl->dmax - sl->dmin, sc = sl->res / (2.0 * sl->R);
         for (int a = 0; a < 3; ++a) {
-            F.Lq[a] = sl->n * sl->L[a] / span;
-            F.Ux[a] = sl->U[a] * sc;
-            F.Vy[a] = sl->V[a] * sc;
-            F.L[a] = sl->L[a];
-            F.U[a] = sl->U[a];
-            F.V[a] = sl->V[a];
+            Lq[a] = sl->n * sl->L[a] / span;
+            Ux[a] = sl->U[a] * sc;
+            Vy[a] = sl->V[a] * sc;
+            split_float(sl->L[a], &F.L[a], &F.Ll[a]);
+            split_float(sl->U[a], &F.U[a], &F.Ul[a]);
+            split_float(sl->V[a], &F.V[a], &F.Vl[a]);
         }
-        F.Lq0 = -sl->n * sl->dmin / span - 1.0;  // index of Eq. 9 minus one
-        F.Ux0 = (-dot3(sl->U, sl->c) + sl->R) * sc - 0.5;
-        F.Vy0 = (-dot3(sl->V, sl->c) + sl->R) * sc - 0.5;
-        F.ds = sl->ds;
+        // world-unit offsets of the three maps (Eq. 9 index minus one; a
+        // point light's depth is measured from the light: d = L.p - L.P)
+        double Lq0 = point ? -sl->n * (sl->dmin + dot3(sl->L, sl->P)) / span - 1.0 : -sl->n * sl->dmin / span - 1.0;
+        double Ux0 = (-dot3(sl->U, sl->c) + sl->R) * sc - 0.5;
+        double Vy0 = (-dot3(sl->V, sl->c) + sl->R) * sc - 0.5;
+        // the same maps of h, less the integer offsets Mz, Mr
+        for (int a = 0; a < 3; ++a) {
+            Lq0 += Lq[a] * hoff / Nd;
+            Ux0 += Ux[a] * hoff / Nd;
+            Vy0 += Vy[a] * hoff / Nd;
+            split_float(Lq[a] / Nd, &F.Lq[a], &F.Lql[a]);
+            split_float(Ux[a] / Nd, &F.Ux[a], &F.Uxl[a]);
+            split_float(Vy[a] / Nd, &F.Vy[a], &F.Vyl[a]);
+        }
+        split_float(Lq0 - F.Mz, &F.Lq0, &F.Lq0l);
+        split_float(Ux0 - F.Mr, &F.Ux0, &F.Ux0l);
+        split_float(Vy0 - F.Mr, &F.Vy0, &F.Vy0l);
+        F.ds = (float)(sl->ds * Nd);
         if (point) {
-            // depth is measured from the light: d = L.p - L.P
-            F.Lq0 = -sl->n * (sl->dmin + dot3(sl->L, sl->P)) / span - 1.0;
-            F.dmin = sl->dmin;
             F.sc = (float)sc;
             F.xo = (float)(0.5 * sl->res - 0.5 - F.Mr);
         }
@@ -634,25 +678,32 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     F.cam_kind = cam->kind;
     F.width = cam->width;
     F.height = cam->height;
-    for (int a = 0; a < 3; ++a) {
-        F.eye[a] = cam->eye[a];
-        F.fwd[a] = fwd[a];
-        F.right[a] = right[a];
-        F.up[a] = up2[a];
-    }
     const double aspect = (double)cam->width / cam->height;
+    double tx, ty;
     if (cam->kind == VI_CAM_PERSP) {
         if (!(cam->fovy_deg > 0.0 && cam->fovy_deg < 180.0)) return fail(VI_E_INVALID_ARG, "fovy outside (0,180)");
         const double th = tan(0.5 * cam->fovy_deg * M_PI / 180.0);
-        F.tx = th * aspect;
-        F.ty = th;
+        tx = th * aspect;
+        ty = th;
     } else {
         if (!(cam->ortho_half_h > 0.0)) return fail(VI_E_INVALID_ARG, "ortho_half_h must be > 0");
-        F.tx = cam->ortho_half_h * aspect;
-        F.ty = cam->ortho_half_h;
+        // the image plane's extent in voxels
+        tx = cam->ortho_half_h * aspect * Nd;
+        ty = cam->ortho_half_h * Nd;
     }
-    F.dt = (double)step_vox / vol->n;
-    F.N_f = (float)vol->n;
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(cam->eye[a])) return fail(VI_E_INVALID_ARG, "camera eye is not finite");
+        split_float(cam->eye[a] * Nd - hoff, &F.cam_o[a], &F.cam_ol[a]);
+        split_float(fwd[a], &F.cam_f[a], &F.cam_fl[a]);
+        split_float(right[a] * tx, &F.cam_r[a], &F.cam_rl[a]);
+        split_float(up2[a] * ty, &F.cam_u[a], &F.cam_ul[a]);
+    }
+    F.lo = (float)(-hoff);
+    F.hi = (float)(Nd - hoff);
+    // segments per ray stay below 2^24, where float segment positions are exact
+    if (sqrt(3.0) * Nd / step_vox > 16777216.0)
+        return fail(VI_E_INVALID_ARG, "step_vox %g gives more than 2^24 segments per ray", (double)step_vox);
+    F.dt = step_vox;
     F.ambient = o.ambient;
     for (int c = 0; c < 3; ++c) F.light[c] = o.light_rgb[c];
     for (int c = 0; c < 4; ++c) F.bg[c] = o.bg[c];
@@ -679,21 +730,22 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
             }
         }
         if (!weighted) wsum = o.shell_count;
-        const double h = (double)o.shell_h_vox / vol->n;
+        const double h = (double)o.shell_h_vox / vol->n;  // world units
         int t = 0;
         for (int r = 1; r <= o.shell_count; ++r)
             for (int a = 0; a < 3; ++a)
                 for (int sg = -1; sg <= 1; sg += 2) {
                     const double off = sg * r * h;
-                    F.tz[t] = (float)(off * F.Lq[a]);
+                    F.tz[t] = (float)(off * Lq[a]);
                     if (point) {
-                        // world-frame offsets: the projection divides by depth per tap
-                        F.td_[t] = (float)(off * F.L[a]);
-                        F.tx_[t] = (float)(off * F.U[a]);
-                        F.ty_[t] = (float)(off * F.V[a]);
+                        // world-frame offsets in voxels: the projection
+                        // divides by depth per tap
+                        F.td_[t] = (float)(off * Nd * sl->L[a]);
+                        F.tx_[t] = (float)(off * Nd * sl->U[a]);
+                        F.ty_[t] = (float)(off * Nd * sl->V[a]);
                     } else {
-                        F.tx_[t] = (float)(off * F.Ux[a]);
-                        F.ty_[t] = (float)(off * F.Vy[a]);
+                        F.tx_[t] = (float)(off * Ux[a]);
+                        F.ty_[t] = (float)(off * Vy[a]);
                     }
                     F.tw[t] = (float)((weighted ? o.shell_w[r - 1] : 1.0) / (6.0 * wsum));
                     ++t;

@@ -1,33 +1,40 @@
 // vi_build.hip -- light-space attenuation build (section 3.2.1, Alg. 1).
 //
-// One lane owns one texel column of the light square and scans the n slabs
-// from the light (Eq. 8 ordering): per slab it samples the volume at the slab
-// midpoint, looks up the transfer-function opacity, corrects it to the slab
-// thickness (extinction form, Eq. 6) and multiplies the running
-// transmittance by (1 - alpha) -- Eq. 4 applied to opacity.  Every layer is
-// written as soon as it is known, so the pass is a single streaming sweep:
-// the volume is read through the caches and the stack is written once,
-// coalesced along the texel row.
+// Every texel column of the light square is scanned over the n slabs from
+// the light (Eq. 8 ordering): per slab the volume is sampled at the slab
+// midpoint, the transfer-function opacity is looked up and corrected to the
+// slab thickness (extinction form, Eq. 6), and the running transmittance is
+// multiplied by (1 - alpha) -- Eq. 4 applied to opacity.  Every layer is
+// written as soon as it is known, so the pass is one streaming sweep: the
+// volume is read through the caches and the stack is written once.
 //
-// Workgroup = 16 x 16 texels (4 waves of 16 x 4) for the tiled stack: at
-// every slab a wave stores two whole 8 x 4 texel tiles, i.e. two full
-// 128-byte lines; 64 x 4 texels (a wave per 64-texel row run) for the row
-// stack.  The alpha column of the transfer function sits in LDS.
+// Mapping: one workgroup per run of NT * C texels of one stack row, lane l
+// owning columns l, l + NT, ..., l + NT (C - 1) of the run.  At every slab a
+// workgroup stores its run as one contiguous stretch of the layer (4 KiB for
+// a 1024-texel row); many short runs spread over the layer (64 x 4 texel
+// tiles per workgroup) measured at half that write rate.  For a fixed c the
+// 64 lanes of a wave hold 64 neighbouring columns, so each volume gather of
+// a wave stays compact.
+//
+// Per column the slabs whose midpoints lie in the cube form one interval
+// [k_in, k_out], found once by exact integer division; a wave stores the
+// unattenuated layers in front of its columns' union of intervals and the
+// final transmittance behind it without touching the volume, and runs the
+// full per-slab work (fetch, transfer function, Eq. 6 correction, product)
+// only inside.  Empty-space verdicts come from the occupancy bits in LDS
+// (without bits every slab in the cube is fetched).
+//
+// Slab-midpoint positions are fixed-point numbers (h * 2^40 in an int64, h
+// the offset-voxel coordinate), so stepping from slab to slab is an exact
+// integer add and the voxel index and trilinear weight are exact bit fields
+// of the position: no rounding accumulates over the 512 slabs, and a float
+// would resolve |h| ~ N/2 only to 2^-16 voxel.
 #include <algorithm>
 
 #include "vi_device.h"
 #include "vi_internal.h"
 
 namespace vi {
-
-// Block of texel columns per workgroup: 16 x 16 (waves of 16 x 4) for the
-// tiled layout, whose 8 x 4 tiles a wave then writes whole; 64 x 4 (waves of
-// one 64-texel row segment) for the row layout, so every slab store of a
-// wave is one contiguous 256-byte run.
-template <int SL> struct BuildBlock { static constexpr int X = 16, Y = 16, WX = 16; };
-template <> struct BuildBlock<VI_STACK_ROWS> {
-    static constexpr int WX = 64, X = 64, Y = 4;  // a wave: one 64-texel row run
-};
 
 // Row layout: the texels of the one-texel border around the grid are the
 // same in every layer (fully transmitting: T = 1, optical depth 0), so a
@@ -54,202 +61,312 @@ __global__ __launch_bounds__(256) void border_kernel(ET* __restrict__ out, int n
     out[(size_t)k * rlayer + (uint32_t)(row + 1) * rpitch + rorg + col] = one;
 }
 
-// slabs per batch of the build loop
-#ifndef VI_BUILD_BATCH
-#define VI_BUILD_BATCH 4
-#endif
-constexpr int kBatch = VI_BUILD_BATCH;
-
-template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool DARKEN>
-__device__ __forceinline__ void build_columns(const BuildParams& P)
+// Workgroup b -> (row, run): rows are dealt to the 8 XCDs in groups of 4
+// consecutive rows (neighbouring rows sample the same voxels and share an
+// L2), the groups of an XCD spread over the whole light square.
+constexpr uint32_t kRowGroup = 4;
+__device__ __forceinline__ bool row_run_of(uint32_t b, uint32_t rows, uint32_t runs, uint32_t* row, uint32_t* run)
 {
-    extern __shared__ float s_alpha[];  // K alphas, K next-opaque indices, then the occupancy bits
-    int* s_next = (int*)(s_alpha + P.K);
-    uint32_t* s_bits = (uint32_t*)(s_next + P.K);
+    const uint32_t x = b % kXcds, q = b / kXcds;  // XCD, index within it
+    const uint32_t unit = q / runs, r = q % runs;
+    const uint32_t grp = unit / kRowGroup, within = unit % kRowGroup;
+    *row = (grp * kXcds + x) * kRowGroup + within;
+    *run = r;
+    return *row < rows;
+}
+inline uint32_t row_run_grid(uint32_t rows, uint32_t runs)
+{
+    const uint32_t groups = (rows + kRowGroup - 1) / kRowGroup;
+    return (groups + kXcds - 1) / kXcds * kRowGroup * runs * kXcds;
+}
+
+// Q40 positions: floor(h) and the trilinear weight h - floor(h) (its top 24
+// bits, exact in a float).
+__device__ __forceinline__ int q_floor(int64_t H) { return (int)(H >> kQBits); }
+__device__ __forceinline__ float q_frac(int64_t H)
+{
+    return (float)((uint32_t)((uint64_t)H >> (kQBits - 24)) & 0xFFFFFFu) * (1.0f / 16777216.0f);
+}
+__device__ __forceinline__ float q_to_float(int64_t H) { return (float)H * (1.0f / 1099511627776.0f); }
+
+// (NT, C, B): threads per workgroup, columns per lane, slabs per batch;
+// a lane's C columns are NT apart (CONSEC = 0: each store instruction of a
+// wave covers 64 neighbouring texels) or adjacent (CONSEC = 1: one
+// C-element store per lane)
+#ifndef VI_BUILD_NT
+#define VI_BUILD_NT 1024
+#endif
+#ifndef VI_BUILD_C
+#define VI_BUILD_C 1
+#endif
+#ifndef VI_BUILD_BATCH
+#define VI_BUILD_BATCH 2
+#endif
+#ifndef VI_BUILD_CONSEC
+#define VI_BUILD_CONSEC 0
+#endif
+constexpr int kBuildNT = VI_BUILD_NT, kBuildC = VI_BUILD_C, kBuildB = VI_BUILD_BATCH;
+constexpr bool kBuildConsec = VI_BUILD_CONSEC != 0;
+
+// The slabs of a column whose midpoints lie in the cube: k in [k_in, k_out]
+// (empty when k_in > k_out), exactly as the per-slab test lo <= h_k <= hi
+// on all three axes decides it: per axis a half-line or interval of k from
+// an exact integer division of Q40 values.
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+__device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
+__device__ __forceinline__ void slab_range(const int64_t H[3], const int64_t A[3], int n, int64_t lo, int64_t hi,
+                                           int* k_in, int* k_out)
+{
+    int64_t kl = 0, kh = n - 1;
+    for (int a = 0; a < 3; ++a) {
+        if (A[a] == 0) {
+            if (H[a] < lo || H[a] > hi) kl = n;  // never inside along this axis
+        } else if (A[a] > 0) {
+            kl = max(kl, ceil_div(lo - H[a], A[a]));
+            kh = min(kh, floor_div(hi - H[a], A[a]));
+        } else {
+            kl = max(kl, ceil_div(hi - H[a], A[a]));
+            kh = min(kh, floor_div(lo - H[a], A[a]));
+        }
+    }
+    if (kl > kh) {
+        *k_in = n;
+        *k_out = -1;
+    } else {
+        *k_in = (int)kl;
+        *k_out = (int)kh;
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+// One stack texel: transmittance, or (BF16 form) optical depth.
+template <int OUT_DTYPE>
+__device__ __forceinline__ void put_texel(void* out, uint32_t at, float T, float tau)
+{
+    if (OUT_DTYPE == VI_F32) ((float*)out)[at] = T;
+    else ((uint16_t*)out)[at] = f32_to_bf16(tau);
+}
+
+template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool PT>
+__device__ __forceinline__ void build_run(const BuildParams& P)
+{
+    constexpr int NT = kBuildNT, C = kBuildC, B = kBuildB;
+    constexpr int CS = kBuildConsec ? 1 : NT;  // stride between a lane's columns
+    extern __shared__ float s_alpha[];  // K alphas, then the occupancy bits
+    uint32_t* s_bits = (uint32_t*)(s_alpha + P.K);
     for (int t = threadIdx.x; t < P.K; t += blockDim.x) s_alpha[t] = P.tf[4 * t + 3];
-    build_next_opaque(s_next, P.tf, P.K);  // read by every batch (unused without a map)
-    stage_occupancy(P.occ, s_bits);
+    // Empty-space verdicts come from the occupancy bits in LDS; without them
+    // one set bit stands for "every cell may hold opacity" (cell index 0).
+    const bool use_bits = P.occ.bits != nullptr;
+    if (use_bits) stage_occupancy(P.occ, s_bits);
+    else if (threadIdx.x == 0) s_bits[0] = 1u;
+    const int cshift = use_bits ? P.occ.shift : 30;
+    const uint32_t cnc = use_bits ? P.occ.nc : 1u;
     __syncthreads();
 
-    constexpr int BX = BuildBlock<SL>::X, BY = BuildBlock<SL>::Y;
-    const uint32_t tiles_x = (P.res + BX - 1) / BX, tiles_y = (P.res + BY - 1) / BY;
-    uint32_t tx, ty;
-    if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // wave footprint WX x WY; the block's waves are laid out along x first
-    constexpr int WX = BuildBlock<SL>::WX, WY = 64 / WX, NWX = BX / WX;
-    const int i = (int)tx * BX + (wave % NWX) * WX + lane % WX;
-    const int j = (int)ty * BY + (wave / NWX) * WY + lane / WX;
-    if (i >= P.res || j >= P.res) return;
+    const uint32_t runs = ((uint32_t)P.res + NT * C - 1) / (NT * C);
+    uint32_t row, run;
+    if (!row_run_of(blockIdx.x, (uint32_t)P.res, runs, &row, &run)) return;
+    const int j = (int)row;
+    const int i0 = (int)(run * NT * C) + (kBuildConsec ? C * (int)threadIdx.x : (int)threadIdx.x);
 
-    // column base (slab 0 midpoint) in offset-voxel coordinates, in double
-    const float hx0 = (float)(P.B0[0] + i * P.BU[0] + j * P.BV[0]);
-    const float hy0 = (float)(P.B0[1] + i * P.BU[1] + j * P.BV[1]);
-    const float hz0 = (float)(P.B0[2] + i * P.BU[2] + j * P.BV[2]);
-    // step per slab, and the slab exponent (its length in voxels); a point
-    // light's column is its own ray from the light
-    float alx = P.AL[0], aly = P.AL[1], alz = P.AL[2], e = P.e;
-    if (P.point) {
-        const double ax = P.AL0[0] + i * P.ALU[0] + j * P.ALV[0];
-        const double ay = P.AL0[1] + i * P.ALU[1] + j * P.ALV[1];
-        const double az = P.AL0[2] + i * P.ALU[2] + j * P.ALV[2];
-        alx = (float)ax;
-        aly = (float)ay;
-        alz = (float)az;
-        e = (float)sqrt(ax * ax + ay * ay + az * az);
+    // per column: the slab-0 midpoint and (point light) the step, in Q40;
+    // the slabs inside the cube; the texel's element in layer 0
+    int64_t Hx[C], Hy[C], Hz[C];
+    int64_t Ax[PT ? C : 1], Ay[PT ? C : 1], Az[PT ? C : 1];
+    float ex[PT ? C : 1];
+    int kin[C], kout[C];
+    uint32_t at[C];
+    int kmin = P.n, kmax = -1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int i = i0 + CS * c;
+        const int q = PT ? c : 0;
+        Hx[c] = P.B0q[0] + (int64_t)i * P.BUq[0] + (int64_t)j * P.BVq[0];
+        Hy[c] = P.B0q[1] + (int64_t)i * P.BUq[1] + (int64_t)j * P.BVq[1];
+        Hz[c] = P.B0q[2] + (int64_t)i * P.BUq[2] + (int64_t)j * P.BVq[2];
+        if constexpr (PT) {
+            Ax[c] = P.ALq[0] + (int64_t)i * P.ALUq[0] + (int64_t)j * P.ALVq[0];
+            Ay[c] = P.ALq[1] + (int64_t)i * P.ALUq[1] + (int64_t)j * P.ALVq[1];
+            Az[c] = P.ALq[2] + (int64_t)i * P.ALUq[2] + (int64_t)j * P.ALVq[2];
+            const float ax = q_to_float(Ax[c]), ay = q_to_float(Ay[c]), az = q_to_float(Az[c]);
+            ex[c] = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));  // the step's length, voxels
+        } else if (c == 0) {
+            Ax[0] = P.ALq[0], Ay[0] = P.ALq[1], Az[0] = P.ALq[2];
+            ex[0] = P.e;
+        }
+        if (i < P.res) {
+            const int64_t H3[3] = {Hx[c], Hy[c], Hz[c]}, A3[3] = {Ax[q], Ay[q], Az[q]};
+            slab_range(H3, A3, P.n, P.loq, P.hiq, &kin[c], &kout[c]);
+        } else {
+            kin[c] = P.n;  // not a column of the grid: no slab, no store
+            kout[c] = -1;
+        }
+        kmin = min(kmin, kin[c]);
+        kmax = max(kmax, kout[c]);
+        at[c] = SL == VI_STACK_ROWS ? (uint32_t)(j + 1) * P.rpitch + P.rorg + (uint32_t)i
+                                    : stack_oj(j, P.row_tiles32) + stack_oi(i);
+    }
+    bool col[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) col[c] = i0 + CS * c < P.res;
+    // the wave's slabs with any midpoint in the cube: [kmin, kmax]
+    kmin = __builtin_amdgcn_readfirstlane(wave_min(kmin));
+    kmax = __builtin_amdgcn_readfirstlane(wave_max(kmax));
+    const uint32_t layer = SL == VI_STACK_ROWS ? P.rlayer : P.layer;
+
+    // slabs in front of the cube: the light arrives unattenuated
+    {
+        const int k1 = min(kmin, P.n);
+        for (int k = 0; k < k1; ++k)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c], 1.0f, 0.0f);
+                at[c] += layer;
+            }
     }
 
     const VT* __restrict__ vol = (const VT*)P.vol;
     const VolIndex VI_ = {1u, P.vsy, P.vsz};
     const float Km1 = (float)(P.K - 1);
-    // this column's texel in layer 0, and the layer stride (elements)
-    const size_t layer = SL == VI_STACK_ROWS ? (size_t)P.rlayer : (size_t)P.layer;
-    size_t at = SL == VI_STACK_ROWS ? (size_t)(j + 1) * P.rpitch + P.rorg + i
-                                    : (size_t)(stack_oj(j, P.row_tiles32) + stack_oi(i));
-    float T = 1.0f;     // transmittance (F32 form)
-    float tau = 0.0f;   // optical depth (BF16 form)
+    float T[C], tau[C];  // transmittance (F32 form), optical depth (BF16 form)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T[c] = 1.0f, tau[c] = 0.0f;
+        // positions at the first slab of the wave's range
+        const int q = PT ? c : 0;
+        const int k0 = kmin < P.n ? kmin : 0;
+        Hx[c] += (int64_t)k0 * Ax[q];
+        Hy[c] += (int64_t)k0 * Ay[q];
+        Hz[c] += (int64_t)k0 * Az[q];
+    }
     const float ln2 = 0.69314718055994531f;
-    uint32_t last_cell = 0xffffffffu;
-    bool cell_is_empty = false;
-    const bool use_map = P.occ.mm != nullptr;
-    const bool use_bits = P.occ.bits != nullptr;  // verdicts from the occupancy bits, no map loads
+    // the section 4 compensation (1 + alpha)^m; m = 0 leaves every factor
+    // unchanged exactly (f * 2^0 = f, min(f, 1) = f)
+    const bool darken = P.darken > 0.0f;
 
-    // The slabs go in batches of kBatch: first every slab's position and the
-    // map entries of newly entered cells (loaded together), then the
-    // empty-space verdicts, then the volume loads of all slabs that need one,
-    // and only then the arithmetic, the running product and the stores -- so
-    // a column waits on one round trip per batch instead of one per slab.
-    // Each slab's arithmetic is the same as one at a time.
-    for (int k0 = 0; k0 < P.n; k0 += kBatch) {
-        float hx[kBatch], hy[kBatch], hz[kBatch];
-        bool fetch[kBatch];
-        uint32_t cell[kBatch];
-        float2 mm[kBatch];
-        uint32_t cur = last_cell;  // cell of the latest slab inside the cube
+    // The wave's range in batches of B slabs for all C columns: positions and
+    // empty-space verdicts, then every volume load of the batch, and only then
+    // the arithmetic and the stores -- one wait per batch, with C * B
+    // footprints in flight.
+    for (int k0 = kmin; k0 <= kmax; k0 += B) {
+        bool fetch[C][B];
+        int gx[C][B], gy[C][B], gz[C][B];
+        float wx[C][B], wy[C][B], wz[C][B];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const float kf = (float)(k0 + u);
-            hx[u] = fmaf(kf, alx, hx0);
-            hy[u] = fmaf(kf, aly, hy0);
-            hz[u] = fmaf(kf, alz, hz0);
-            fetch[u] = (k0 + u < P.n) & (hx[u] >= P.lo) & (hx[u] <= P.hi) & (hy[u] >= P.lo) & (hy[u] <= P.hi) &
-                       (hz[u] >= P.lo) & (hz[u] <= P.hi);
-            cell[u] = 0xffffffffu;
-            mm[u] = make_float2(0.0f, 0.0f);
-            if (fetch[u] && use_map) {
-                cell[u] = cell_of((int)floorf(hx[u]) + P.M, (int)floorf(hy[u]) + P.M, (int)floorf(hz[u]) + P.M, P.N,
-                                  P.occ.shift, P.occ.nc);
-                if (cell[u] != cur) {
-                    if (!use_bits) mm[u] = P.occ.mm[cell[u]];  // a newly entered cell
-                    cur = cell[u];
+        for (int c = 0; c < C; ++c) {
+            const int q = PT ? c : 0;
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                // slab k0 + u: H0 + (k0 + u) A, exact
+                const int64_t hx = Hx[c] + (int64_t)u * Ax[q], hy = Hy[c] + (int64_t)u * Ay[q],
+                              hz = Hz[c] + (int64_t)u * Az[q];
+                const int k = k0 + u;
+                gx[c][u] = q_floor(hx) + P.M;
+                gy[c][u] = q_floor(hy) + P.M;
+                gz[c][u] = q_floor(hz) + P.M;
+                wx[c][u] = q_frac(hx);
+                wy[c][u] = q_frac(hy);
+                wz[c][u] = q_frac(hz);
+                const uint32_t cell = cell_of(gx[c][u], gy[c][u], gz[c][u], P.N, cshift, cnc);
+                // a zero-opacity cell leaves T unchanged exactly
+                fetch[c][u] = k >= kin[c] && k <= kout[c] && occupancy_bit(s_bits, cell);
+            }
+            Hx[c] += (int64_t)B * Ax[q];
+            Hy[c] += (int64_t)B * Ay[q];
+            Hz[c] += (int64_t)B * Az[q];
+        }
+        RawFoot<VT, LAYOUT> raw[C][B];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (fetch[c][u])
+                    foot_load_g<VT, LAYOUT>(raw[c][u], wx[c][u], wy[c][u], vol, VI_, P.N, gx[c][u], gy[c][u],
+                                            gz[c][u]);
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (k0 + u > kmax) break;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (fetch[c][u]) {
+                    const float v = foot_value<VT, LAYOUT>(raw[c][u], wx[c][u], wy[c][u], wz[c][u], P.scale);
+                    const float x = v * Km1;
+                    const int e0 = min((int)x, P.K - 2);
+                    const float w = x - (float)e0;
+                    // the table's opacity clamped to [0, 1], as the render clamps it
+                    const float a = clampf01(fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]));
+                    const float l2 = fast_log2(1.0f - a);  // -inf for a = 1
+                    const float e = ex[PT ? c : 0];
+                    if (OUT_DTYPE == VI_F32) {
+                        // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
+                        float f = fast_exp2(e * l2);
+                        // section 4 compensation: times (1 + alpha)^m, at most 1
+                        if (darken) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
+                        T[c] *= f;
+                    } else {
+                        // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
+                        // compensation subtracts m ln(1 + alpha), floored at 0
+                        float dtau = -e * ln2 * l2;
+                        if (darken)
+                            dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
+                        tau[c] += fminf(dtau, 64.0f);
+                    }
                 }
-            }
-        }
-        // Empty-space verdicts: a zero-opacity cell leaves T unchanged
-        // exactly.  Every entry's verdict is taken, on every path and with
-        // selects rather than branches (entries not loaded hold zeros and
-        // their verdicts are not used; without a map none is), so no map
-        // load is left in flight behind the volume loads below.  The cell
-        // sequence is the one above, so an entry is loaded wherever its
-        // verdict is used.
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            // Both verdicts are taken and one is selected (slabs outside the
-            // cube, and runs without bits, read word 0 of the bits: always
-            // allocated, unused then)
-            const uint32_t cq = (cell[u] == 0xffffffffu || !use_bits) ? 0u : cell[u];
-            const bool empty_bit = !occupancy_bit(s_bits, cq);
-            const bool empty_map = cell_empty(mm[u], s_next, Km1, P.K);
-            const bool empty = use_bits ? empty_bit : empty_map;
-            const bool entered = use_map && fetch[u] && cell[u] != last_cell;
-            cell_is_empty = entered ? empty : cell_is_empty;
-            last_cell = entered ? cell[u] : last_cell;
-            fetch[u] = fetch[u] && !cell_is_empty;
-        }
-        RawFoot<VT, LAYOUT> raw[kBatch];
-        float wx[kBatch], wy[kBatch], wz[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u)
-            if (fetch[u]) foot_load<VT, LAYOUT>(raw[u], wx[u], wy[u], wz[u], vol, VI_, P.N, P.M, hx[u], hy[u], hz[u]);
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u, at += layer) {
-            if (k0 + u >= P.n) break;
-            // log2 of the slab's (1 - alpha)/e, 0 outside the cube or in empty cells
-            float l2 = 0.0f;
-            if (fetch[u]) {
-                const float v = foot_value<VT, LAYOUT>(raw[u], wx[u], wy[u], wz[u], P.scale);
-                const float x = v * Km1;
-                const int e0 = min((int)x, P.K - 2);
-                const float w = x - (float)e0;
-                const float a = fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]);
-                l2 = fast_log2(fmaxf(1.0f - a, 0.0f));  // -inf for a = 1
-            }
-            if (OUT_DTYPE == VI_F32) {
-                // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
-                float f = fast_exp2(e * l2);
-                // section 4 compensation: times (1 + alpha)^m, at most 1
-                if (DARKEN) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
-                T *= f;
-                ((float*)P.out)[at] = T;
-            } else {
-                // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
-                // compensation subtracts m ln(1 + alpha), floored at 0
-                float dtau = -e * ln2 * l2;
-                if (DARKEN) dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
-                tau += fminf(dtau, 64.0f);
-                ((uint16_t*)P.out)[at] = f32_to_bf16(tau);
+                if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c], T[c], tau[c]);
+                at[c] += layer;
             }
         }
     }
+
+    // slabs behind the cube: the transmittance stays as it left the cube
+    for (int k = max(kmax + 1, kmin < P.n ? kmin : P.n); k < P.n; ++k)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c], T[c], tau[c]);
+            at[c] += layer;
+        }
 }
 
-// The kernel.  With the quad layout of 8- and 16-bit voxels a batch's
-// footprints take few registers, and five resident waves per SIMD (at most
-// 96 VGPRs, no spills) measured faster than the compiler's choice of four;
-// the other cases (eight voxels per footprint, 32-bit quads, the
-// compensation) keep the compiler's budget.
-template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool DARKEN>
-__global__ __launch_bounds__(256) void build_kernel(BuildParams P)
+template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool PT>
+__global__ __launch_bounds__(kBuildNT) void build_kernel(BuildParams P)
 {
-    build_columns<VT, LAYOUT, OUT_DTYPE, SL, DARKEN>(P);
-}
-#ifndef VI_BUILD_QUAD_WAVES
-#define VI_BUILD_QUAD_WAVES 5
-#endif
-template <typename VT, int OUT_DTYPE, int SL, bool DARKEN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VI_BUILD_QUAD_WAVES))) void build_kernel_quads(
-    BuildParams P)
-{
-    build_columns<VT, VI_LAYOUT_QUAD4, OUT_DTYPE, SL, DARKEN>(P);
+    build_run<VT, LAYOUT, OUT_DTYPE, SL, PT>(P);
 }
 
-template <typename VT, int LAYOUT, int SL, bool DARKEN>
+template <typename VT, int LAYOUT, int SL, bool PT>
 static void launch_build_k(const BuildParams& p, dim3 grid, size_t lds, hipStream_t s)
 {
-    constexpr bool kFive = LAYOUT == VI_LAYOUT_QUAD4 && sizeof(VT) <= 2 && !DARKEN;
     if (p.out_dtype == VI_F32)
-        if constexpr (kFive)
-            hipLaunchKernelGGL((build_kernel_quads<VT, VI_F32, SL, DARKEN>), grid, dim3(256), lds, s, p);
-        else
-            hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, SL, DARKEN>), grid, dim3(256), lds, s, p);
-    else if constexpr (kFive)
-        hipLaunchKernelGGL((build_kernel_quads<VT, VI_BF16, SL, DARKEN>), grid, dim3(256), lds, s, p);
+        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, SL, PT>), grid, dim3(kBuildNT), lds, s, p);
     else
-        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, SL, DARKEN>), grid, dim3(256), lds, s, p);
+        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, SL, PT>), grid, dim3(kBuildNT), lds, s, p);
 }
 
 template <typename VT, int LAYOUT>
 static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
 {
-    const bool rows = p.out_layout == VI_STACK_ROWS;
-    const uint32_t bx = rows ? BuildBlock<VI_STACK_ROWS>::X : BuildBlock<VI_STACK_TILED>::X;
-    const uint32_t by = rows ? BuildBlock<VI_STACK_ROWS>::Y : BuildBlock<VI_STACK_TILED>::Y;
-    const dim3 grid(supertile_grid(((uint32_t)p.res + bx - 1) / bx, ((uint32_t)p.res + by - 1) / by));
-    // (at least one word of bits, which the slab loop reads even without them)
-    const size_t lds = (sizeof(float) + sizeof(int)) * (size_t)p.K + sizeof(uint32_t) * std::max(p.occ.words, 1u);
-    const bool dk = p.darken > 0.0f;
-    if (rows) {
-        if (dk) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds, s);
+    const uint32_t runs = ((uint32_t)p.res + kBuildNT * kBuildC - 1) / (kBuildNT * kBuildC);
+    const dim3 grid(row_run_grid((uint32_t)p.res, runs));
+    // (at least one word of bits: without them word 0 says "occupied")
+    const size_t lds = sizeof(float) * (size_t)p.K + sizeof(uint32_t) * std::max(p.occ.words, 1u);
+    if (p.out_layout == VI_STACK_ROWS) {
+        if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds, s);
         else launch_build_k<VT, LAYOUT, VI_STACK_ROWS, false>(p, grid, lds, s);
         // the border, the same in every layer
         const size_t nb = (2u * (size_t)(p.res + 2) + 2u * (size_t)p.res) * (size_t)p.n;
@@ -261,7 +378,7 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
             hipLaunchKernelGGL((border_kernel<uint16_t>), bgrid, dim3(256), 0, s, (uint16_t*)p.out, p.n, p.res,
                                p.rlayer, p.rpitch, p.rorg, (uint16_t)0);
     } else {
-        if (dk) launch_build_k<VT, LAYOUT, VI_STACK_TILED, true>(p, grid, lds, s);
+        if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_TILED, true>(p, grid, lds, s);
         else launch_build_k<VT, LAYOUT, VI_STACK_TILED, false>(p, grid, lds, s);
     }
     return hipGetLastError();

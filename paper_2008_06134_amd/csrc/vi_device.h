@@ -15,7 +15,72 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
+
+// Knuth's two-sum: s = fl(a + b) and the exact error e = (a + b) - s, for
+// the float pairs below.  The error term holds only for separately rounded
+// operations, so contraction of products and sums into FMAs is off here.
+__device__ __forceinline__ float two_sum(float a, float b, float* e)
+{
+#pragma clang fp contract(off)
+    const float s = a + b, t = s - a;
+    *e = (a - (s - t)) + (b - t);
+    return s;
+}
 __device__ __forceinline__ float clampf01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// Float pairs: a value held as hi + lo with |lo| <= ulp(hi) / 2, about 48
+// significant bits from FP32 operations alone (Dekker's product via FMA,
+// Knuth's two-sum).  The per-ray set-up of the render uses them where a
+// single float would misplace a ray entering the cube ~10^3 voxels from the
+// eye by ~10^-4 voxel.  Contraction stays off: every error term assumes
+// separately rounded operations.
+struct F2 {
+    float hi, lo;
+};
+__device__ __forceinline__ F2 f2(float a) { return F2{a, 0.0f}; }
+__device__ __forceinline__ F2 f2_fast(float a, float b)  // |a| >= |b|
+{
+#pragma clang fp contract(off)
+    const float s = a + b;
+    return F2{s, b - (s - a)};
+}
+__device__ __forceinline__ F2 f2_add(F2 a, F2 b)
+{
+#pragma clang fp contract(off)
+    float e;
+    const float s = two_sum(a.hi, b.hi, &e);
+    return f2_fast(s, e + (a.lo + b.lo));
+}
+__device__ __forceinline__ F2 f2_neg(F2 a) { return F2{-a.hi, -a.lo}; }
+__device__ __forceinline__ F2 f2_sub(F2 a, F2 b) { return f2_add(a, f2_neg(b)); }
+__device__ __forceinline__ F2 f2_mul(F2 a, F2 b)
+{
+#pragma clang fp contract(off)
+    const float p = a.hi * b.hi;
+    const float e = fmaf(a.hi, b.hi, -p) + (a.hi * b.lo + a.lo * b.hi);
+    return f2_fast(p, e);
+}
+__device__ __forceinline__ F2 f2_div(F2 a, F2 b)
+{
+#pragma clang fp contract(off)
+    const float q = a.hi / b.hi;
+    const F2 r = f2_sub(a, f2_mul(f2(q), b));  // a - q b
+    return f2_fast(q, r.hi / b.hi);
+}
+__device__ __forceinline__ F2 f2_sqrt(F2 a)  // a > 0
+{
+#pragma clang fp contract(off)
+    const float s = sqrtf(a.hi);
+    const F2 r = f2_sub(a, f2_mul(f2(s), f2(s)));
+    return f2_fast(s, r.hi / (2.0f * s));
+}
+__device__ __forceinline__ bool f2_lt(F2 a, F2 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+__device__ __forceinline__ F2 f2_max(F2 a, F2 b) { return f2_lt(a, b) ? b : a; }
+__device__ __forceinline__ F2 f2_min(F2 a, F2 b) { return f2_lt(a, b) ? a : b; }
+__device__ __forceinline__ F2 f2_dot3(const F2* a, const F2* b)
+{
+    return f2_add(f2_add(f2_mul(a[0], b[0]), f2_mul(a[1], b[1])), f2_mul(a[2], b[2]));
+}
 
 // One voxel, normalised and clamped to [0,1] before interpolation.
 template <typename VT>
@@ -141,19 +206,13 @@ __device__ __forceinline__ float4 quad_decode(float4 w, float scale, float)
     return make_float4(clampf01(w.x * scale), clampf01(w.y * scale), clampf01(w.z * scale), clampf01(w.w * scale));
 }
 
-// Issue the loads of the footprint at offset-voxel coordinates h and return
-// its weights (a quad footprint below the first voxel in x or y takes a zero
-// weight there: both of its corners clamp to voxel 0).
+// Issue the loads of the footprint whose lower corner is voxel (x0, y0, z0)
+// (before clamping to the volume); a quad footprint below the first voxel in
+// x or y takes a zero weight there (both of its corners clamp to voxel 0).
 template <typename VT, int LAYOUT>
-__device__ __forceinline__ void foot_load(RawFoot<VT, LAYOUT>& r, float& wx, float& wy, float& wz,
-                                          const VT* __restrict__ vol, const VolIndex& I, int N, int M, float hx,
-                                          float hy, float hz)
+__device__ __forceinline__ void foot_load_g(RawFoot<VT, LAYOUT>& r, float& wx, float& wy, const VT* __restrict__ vol,
+                                            const VolIndex& I, int N, int x0, int y0, int z0)
 {
-    const float fx = floorf(hx), fy = floorf(hy), fz = floorf(hz);
-    wx = hx - fx;
-    wy = hy - fy;
-    wz = hz - fz;
-    const int x0 = (int)fx + M, y0 = (int)fy + M, z0 = (int)fz + M;
     const uint32_t za = vol_oz<LAYOUT>(I, clampi(z0, 0, N - 1)), zb = vol_oz<LAYOUT>(I, clampi(z0 + 1, 0, N - 1));
     if constexpr (LAYOUT == VI_LAYOUT_QUAD4) {
         using Q = typename QuadRaw<VT>::T;

@@ -15,9 +15,13 @@ constexpr int kMaxTaps = 49;     // largest gather (7 x 7 lattice)
 // Build pass parameters.  Positions are carried in "offset voxel"
 // coordinates h = p*N - 1/2 - M, with M = floor(N/2) an integer, so that
 // floor/fraction of the voxel index g = h + M are exact and |h| <= ~0.9 N.
-// Column (i,j) at slab k sits at h = B(i,j) + k * AL, with B evaluated in
-// double on the device once per column.
+// Column (i,j) at slab k sits at h = B(i,j) + k * AL.  The build carries h as
+// a fixed-point number h * 2^kQBits in an int64 (Q40: |h| < 2^23 voxels,
+// resolution 2^-40 voxel); the host derives the light frame (Eq. 8, Eq. 10)
+// in double and rounds every coefficient to Q40 once.
 // ---------------------------------------------------------------------------
+constexpr int kQBits = 40;
+
 // Empty-space map: per cell of 2^shift voxels, (min, max) of the normalised
 // values over the cell's voxels and the next one along each axis.
 // Optional occupancy bits for the frame's transfer function: one bit per
@@ -48,18 +52,18 @@ struct BuildParams {
     int out_layout;    // VI_STACK_TILED / VI_STACK_ROWS
     uint32_t layer, row_tiles32;  // tiled: R8*R4 per layer, (R8/8)*32 per tile row
     uint32_t rlayer, rpitch, rorg;  // rows: (res+2)*P elements per layer, pitch P, texel 0 at column rorg
-    double B0[3];      // h at (i,j,k) = (0,0,0)
-    double BU[3];      // d h / d i
-    double BV[3];      // d h / d j
-    float AL[3];       // d h / d k
+    int64_t B0q[3];    // h at (i,j,k) = (0,0,0), Q40
+    int64_t BUq[3];    // d h / d i
+    int64_t BVq[3];    // d h / d j
+    int64_t ALq[3];    // d h / d k (point light: at column (0,0))
     float e;           // slab thickness in voxels: exponent of (1-a)
     float darken;      // exponent m of the (1+alpha)^m slab compensation, 0 = off
-    float lo, hi;      // cube in h coordinates: [-1/2 - M, N - 1/2 - M]
-    // point light: column (i,j) advances by AL0 + i ALU + j ALV per slab,
+    int64_t loq, hiq;  // cube in h coordinates: [-1/2 - M, N - 1/2 - M], Q40
+    // point light: column (i,j) advances by ALq + i ALUq + j ALVq per slab,
     // and its slab exponent is that step's length (the ray crosses the
     // slab obliquely)
     int point;
-    double AL0[3], ALU[3], ALV[3];
+    int64_t ALUq[3], ALVq[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -85,25 +89,31 @@ struct RenderFrame {
     uint32_t layer, row_tiles32;
     uint32_t rlayer, rpitch, rorg;
     int Mz, Mr;          // integer offsets of the light-grid coordinates
-    double Lq[3], Lq0;   // z = Lq . p + Lq0 - Mz       (Eq. 9 index minus one)
-    double Ux[3], Ux0;   // x = Ux . p + Ux0 - Mr       (Eq. 10 texel column)
-    double Vy[3], Vy0;   // y = Vy . p + Vy0 - Mr
-    double L[3], U[3], V[3];
-    double ds;
-    // point light: depth d = L.(p - P) and lateral u = U.(p - P), v = V.(p - P)
-    // map to z = (d - dmin) zs - 1 - Mz, x = (u / d) sc + xo, y = (v / d) sc + yo
+    // Light grid as affine maps of the offset-voxel position h; every
+    // coefficient is a float pair (value, remainder), so that the per-ray
+    // offsets are as accurate as a double set-up would make them:
+    float Lq[3], Lql[3], Lq0, Lq0l;  // z = Lq . h + Lq0   (Eq. 9 index minus one, minus Mz)
+    float Ux[3], Uxl[3], Ux0, Ux0l;  // x = Ux . h + Ux0   (Eq. 10 texel column minus Mr)
+    float Vy[3], Vyl[3], Vy0, Vy0l;  // y = Vy . h + Vy0
+    float L[3], U[3], V[3];
+    float Ll[3], Ul[3], Vl[3];
+    float ds;            // slab thickness in voxels (cone ring radii)
+    // point light: depth d = L.(h - Ph) and lateral u = U.(h - Ph),
+    // v = V.(h - Ph) (voxels) map to x = (u / d) sc + xo, y = (v / d) sc + xo
     int point;
-    double P[3], dmin;
-    float zs, sc, xo;
-    // camera
+    float Ph[3], Phl[3]; // light position in offset-voxel coordinates
+    float sc, xo;
+    // camera, in offset-voxel coordinates (float pairs): a pinhole ray leaves
+    // cam_o along cam_f + xn cam_r + yn cam_u (normalised); an orthographic
+    // ray leaves cam_o + xn cam_r + yn cam_u along cam_f (xn, yn in [-1, 1]
+    // across the image)
     int cam_kind;
     int width, height;
-    double eye[3], fwd[3], right[3], up[3];
-    double tx, ty;       // persp: tan(fovy/2)*W/H, tan(fovy/2); ortho: h*W/H, h
+    float cam_o[3], cam_ol[3], cam_f[3], cam_fl[3], cam_r[3], cam_rl[3], cam_u[3], cam_ul[3];
+    float lo, hi;        // the cube in h coordinates: [-1/2 - M, N - 1/2 - M]
     // march
     int mode;
-    double dt;           // step in world units
-    float N_f;           // voxels per world unit (segment exponent scale)
+    float dt;            // step in voxels (= the reference length of Eq. 6's exponent)
     float ambient, light[3], bg[4], term_eps;
     float phong_ka, phong_kd, phong_ks, phong_shin, grad_eps;
     // gather taps in light-grid units (shell: fixed; cone: per ray)
@@ -112,7 +122,7 @@ struct RenderFrame {
     float tz[kMaxTaps], tx_[kMaxTaps], ty_[kMaxTaps];  // shell offsets
     float tw[kMaxTaps];                                 // shell tap weights (sum 1)
     float td_[kMaxTaps];                                // point light: depth offsets (tx_, ty_ then
-                                                        // hold world-frame lateral offsets)
+                                                        // hold lateral offsets), voxels
     int cone_rings, cone_angles, cone_grid;
     float cone_tan;
     float cone_cos[16], cone_sin[16];

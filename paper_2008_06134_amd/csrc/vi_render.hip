@@ -1,20 +1,21 @@
 // vi_render.hip -- eye-space ray march with the slice-based illumination
 // coefficient (sections 3.2.2, 3.2.3 and 4).
 //
-// One lane marches one ray.  Per ray (double precision, once): the camera
-// ray, the slab test against the unit cube, the entry point in volume and
-// light-grid coordinates and the per-unit-length increments of both; for the
-// cone, the per-ray frame (B, L x B) in texel units.  Per segment (float):
-// position = entry + s * direction in offset coordinates (so the fraction of
-// every interpolation is taken on small magnitudes), trilinear fetch,
-// transfer function from LDS, extinction-corrected opacity, and -- only when
-// the opacity is non-zero -- the coefficient gather from the stack, then the
-// front-to-back update (Eq. 3) with the coefficient weighting the emission
-// (Eq. 7).  The lane leaves the loop when its ray exits or its remaining
+// Four lanes march one ray together (each takes every fourth segment; the
+// four segments of a step are composited by an in-group scan).  Per ray, once
+// (float): the camera ray, the slab test against the unit cube, the entry
+// point in volume and light-grid coordinates and the increments of both per
+// voxel of path; for the cone, the per-ray frame (B, L x B) in texel units.
+// Per segment: position = entry + s * direction in offset coordinates (so
+// the fraction of every interpolation is taken on small magnitudes),
+// trilinear fetch, transfer function from LDS, extinction-corrected opacity,
+// and -- only when the opacity is non-zero -- the coefficient gather from the
+// stack, then the front-to-back update (Eq. 3) with the coefficient weighting
+// the emission (Eq. 7).  A ray stops when it exits the cube or its remaining
 // transmittance drops to term_eps.
 //
-// Workgroup = 16 x 16 pixels, each wave an 8 x 8 pixel block so the rays of a
-// wave sample neighbouring voxels and texels.
+// A wave covers 4 x 4 pixels (16 rays x 4 lanes), a workgroup 8 x 8 pixels,
+// so the rays of a wave sample neighbouring voxels and texels.
 #include "vi_device.h"
 #include "vi_internal.h"
 
@@ -247,7 +248,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
     float s = 0.0f;
     if (MODE == VI_MODE_CONE) {
         for (int m = 1; m <= F.cone_rings; ++m) {
-            const float r = (float)m * (float)F.ds * F.cone_tan;
+            const float r = (float)m * F.ds * F.cone_tan;
             for (int q = 0; q < F.cone_angles; q += NB) {
 #pragma unroll
                 for (int u = 0; u < NB; ++u) {
@@ -265,7 +266,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
         }
     } else if (MODE == kModeConeGrid) {
         const int G = F.cone_grid;
-        const float rho = (float)F.ds * F.cone_tan * 0.5f, half = 0.5f * (float)(G - 1);
+        const float rho = F.ds * F.cone_tan * 0.5f, half = 0.5f * (float)(G - 1);
         for (int ia = 0; ia < G; ++ia) {
             const float a = ((float)ia - half) * rho;
             for (int ib = 0; ib < G; ib += NB) {
@@ -362,113 +363,140 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                                              int px, int py, uint32_t& nsamp)
 {
     const int lane = threadIdx.x & 63, g = lane % G, gbase = lane - g;
-    // ---- camera ray (double)
-    const double xn = 2.0 * (px + 0.5) / F.width - 1.0;
-    const double yn = 1.0 - 2.0 * (py + 0.5) / F.height;
-    double o[3], d[3];
-    if (F.cam_kind == VI_CAM_PERSP) {
-        for (int a = 0; a < 3; ++a) {
-            o[a] = F.eye[a];
-            d[a] = F.fwd[a] + xn * F.tx * F.right[a] + yn * F.ty * F.up[a];
-        }
-        const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        for (int a = 0; a < 3; ++a) d[a] *= inv;
-    } else {
-        for (int a = 0; a < 3; ++a) {
-            d[a] = F.fwd[a];
-            o[a] = F.eye[a] + xn * F.tx * F.right[a] + yn * F.ty * F.up[a];
+    // ---- camera ray, in offset-voxel coordinates, in float pairs (the
+    // host folded the camera and the light grid into float-pair
+    // coefficients of h; see F2)
+    F2 xn, yn;
+    {
+        // xn = (2 px + 1 - W) / W, yn = (H - 2 py - 1) / H: exact numerators
+        const float W = (float)F.width, H = (float)F.height;
+        xn = f2_div(f2(2.0f * (float)px + 1.0f - W), f2(W));
+        yn = f2_div(f2(H - 2.0f * (float)py - 1.0f), f2(H));
+    }
+    F2 o[3], d[3];
+    for (int a = 0; a < 3; ++a) {
+        const F2 r = F2{F.cam_r[a], F.cam_rl[a]}, u = F2{F.cam_u[a], F.cam_ul[a]};
+        const F2 f = F2{F.cam_f[a], F.cam_fl[a]}, e = F2{F.cam_o[a], F.cam_ol[a]};
+        const F2 lat = f2_add(f2_mul(xn, r), f2_mul(yn, u));
+        if (F.cam_kind == VI_CAM_PERSP) {
+            o[a] = e;
+            d[a] = f2_add(f, lat);
+        } else {
+            o[a] = f2_add(e, lat);
+            d[a] = f;
         }
     }
-    // ---- slab test (double)
-    double tn = -1e300, tf = 1e300;
+    if (F.cam_kind == VI_CAM_PERSP) {
+        const F2 inv = f2_div(f2(1.0f), f2_sqrt(f2_dot3(d, d)));
+        for (int a = 0; a < 3; ++a) d[a] = f2_mul(d[a], inv);
+    }
+    // ---- slab test against the cube [lo, hi]^3 (distances in voxels)
+    F2 tn = f2(-3.0e38f), tf = f2(3.0e38f);
     bool hit = true;
     for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0) {
-            if (o[a] < 0.0 || o[a] > 1.0) hit = false;
+        if (d[a].hi == 0.0f) {
+            if (o[a].hi < F.lo || o[a].hi > F.hi) hit = false;
             continue;
         }
-        const double t1 = (0.0 - o[a]) / d[a], t2 = (1.0 - o[a]) / d[a];
-        tn = fmax(tn, fmin(t1, t2));
-        tf = fmin(tf, fmax(t1, t2));
+        const F2 t1 = f2_div(f2_sub(f2(F.lo), o[a]), d[a]), t2 = f2_div(f2_sub(f2(F.hi), o[a]), d[a]);
+        tn = f2_max(tn, f2_min(t1, t2));
+        tf = f2_min(tf, f2_max(t1, t2));
     }
-    const double ti = fmax(tn, 0.0);
+    const F2 ti = f2_max(tn, f2(0.0f));
     float4 bg = make_float4(F.bg[0], F.bg[1], F.bg[2], F.bg[3]);
-    if (!hit || !(tf > ti)) return bg;
+    if (!hit || !f2_lt(ti, tf)) return bg;
 
-    const double D = tf - ti;
-    const int K = (int)ceil(D / F.dt);
-    double pin[3];
-    for (int a = 0; a < 3; ++a) pin[a] = o[a] + ti * d[a];
-
-    // volume: offset-voxel coordinates at the entry and per unit length
-    const double Nd = (double)F.N;
-    const float hx0 = (float)(pin[0] * Nd - 0.5 - F.M), hy0 = (float)(pin[1] * Nd - 0.5 - F.M),
-                hz0 = (float)(pin[2] * Nd - 0.5 - F.M);
-    const float hdx = (float)(d[0] * Nd), hdy = (float)(d[1] * Nd), hdz = (float)(d[2] * Nd);
+    const F2 Dc = f2_sub(tf, ti);  // chord length, voxels
+    const float Df = Dc.hi;
+    int K;
+    {
+        // K = ceil(D / dt), decided on the pair
+        const F2 q = f2_div(Dc, f2(F.dt));
+        float c = ceilf(q.hi);
+        if (c == q.hi && q.lo > 0.0f) c += 1.0f;
+        else if (c - 1.0f - q.hi >= q.lo) c -= 1.0f;
+        K = (int)c;
+    }
+    // volume: entry point (value, remainder) and direction (value, remainder)
+    F2 pin[3];
+    for (int a = 0; a < 3; ++a) pin[a] = f2_add(o[a], f2_mul(ti, d[a]));
+    const float hx0 = pin[0].hi, hy0 = pin[1].hi, hz0 = pin[2].hi;
+    const float hxl = pin[0].lo, hyl = pin[1].lo, hzl = pin[2].lo;
+    const float hdx = d[0].hi, hdy = d[1].hi, hdz = d[2].hi;
+    const float hdxl = d[0].lo, hdyl = d[1].lo, hdzl = d[2].lo;
     // light grid: depth index (Eq. 9, minus one) and texel coordinates (Eq. 10)
-    // (point light: qx / qy hold the lateral offsets U.(p - P), V.(p - P) and
-    // pd the depth L.(p - P), all affine along the ray)
+    // (point light: qx / qy hold the lateral offsets U.(h - Ph), V.(h - Ph)
+    // and pd the depth L.(h - Ph), all affine along the ray)
     constexpr bool PT = MODE == kModePointShadow || MODE == kModePointShell;
     constexpr bool PTP = MODE == kModePointPhong, PHONG = MODE == VI_MODE_PHONG || PTP;
     float qz0 = 0.f, qx0 = 0.f, qy0 = 0.f, qdz = 0.f, qdx = 0.f, qdy = 0.f, pd0 = 0.f, pdd = 0.f;
     ConeFrame cf = {0.f, 0.f, 0.f, 0.f};
     // Phong: light vector l = -L and, folded in, l.v with v = -d
-    // (point light: l is taken per sample toward P, and lx, ly, lz hold pin - P)
+    // (point light: l is taken per sample toward P, and lx, ly, lz hold h_in - Ph)
     float lx = 0.f, ly = 0.f, lz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, lv = 0.f;
     if (PHONG) {
-        lx = (float)-F.L[0];
-        ly = (float)-F.L[1];
-        lz = (float)-F.L[2];
-        vx = (float)-d[0];
-        vy = (float)-d[1];
-        vz = (float)-d[2];
-        lv = (float)(F.L[0] * d[0] + F.L[1] * d[1] + F.L[2] * d[2]);
+        lx = -F.L[0];
+        ly = -F.L[1];
+        lz = -F.L[2];
+        vx = -hdx;
+        vy = -hdy;
+        vz = -hdz;
+        lv = fmaf(F.L[0], hdx, fmaf(F.L[1], hdy, F.L[2] * hdz));
         if (PTP) {
-            lx = (float)(pin[0] - F.P[0]);
-            ly = (float)(pin[1] - F.P[1]);
-            lz = (float)(pin[2] - F.P[2]);
+            lx = f2_sub(pin[0], F2{F.Ph[0], F.Phl[0]}).hi;
+            ly = f2_sub(pin[1], F2{F.Ph[1], F.Phl[1]}).hi;
+            lz = f2_sub(pin[2], F2{F.Ph[2], F.Phl[2]}).hi;
         }
     }
     if (MODE != VI_MODE_NONE && !PHONG) {
-        qz0 = (float)(F.Lq[0] * pin[0] + F.Lq[1] * pin[1] + F.Lq[2] * pin[2] + F.Lq0 - F.Mz);
-        qdz = (float)(F.Lq[0] * d[0] + F.Lq[1] * d[1] + F.Lq[2] * d[2]);
+        const F2 Lq[3] = {F2{F.Lq[0], F.Lql[0]}, F2{F.Lq[1], F.Lql[1]}, F2{F.Lq[2], F.Lql[2]}};
+        qz0 = f2_add(f2_dot3(Lq, pin), F2{F.Lq0, F.Lq0l}).hi;
+        qdz = f2_dot3(Lq, d).hi;
         if (PT) {
-            const double r[3] = {pin[0] - F.P[0], pin[1] - F.P[1], pin[2] - F.P[2]};
-            pd0 = (float)(F.L[0] * r[0] + F.L[1] * r[1] + F.L[2] * r[2]);
-            pdd = (float)(F.L[0] * d[0] + F.L[1] * d[1] + F.L[2] * d[2]);
-            qx0 = (float)(F.U[0] * r[0] + F.U[1] * r[1] + F.U[2] * r[2]);
-            qdx = (float)(F.U[0] * d[0] + F.U[1] * d[1] + F.U[2] * d[2]);
-            qy0 = (float)(F.V[0] * r[0] + F.V[1] * r[1] + F.V[2] * r[2]);
-            qdy = (float)(F.V[0] * d[0] + F.V[1] * d[1] + F.V[2] * d[2]);
+            const F2 r[3] = {f2_sub(pin[0], F2{F.Ph[0], F.Phl[0]}), f2_sub(pin[1], F2{F.Ph[1], F.Phl[1]}),
+                             f2_sub(pin[2], F2{F.Ph[2], F.Phl[2]})};
+            const F2 L[3] = {F2{F.L[0], F.Ll[0]}, F2{F.L[1], F.Ll[1]}, F2{F.L[2], F.Ll[2]}};
+            const F2 U[3] = {F2{F.U[0], F.Ul[0]}, F2{F.U[1], F.Ul[1]}, F2{F.U[2], F.Ul[2]}};
+            const F2 V[3] = {F2{F.V[0], F.Vl[0]}, F2{F.V[1], F.Vl[1]}, F2{F.V[2], F.Vl[2]}};
+            pd0 = f2_dot3(L, r).hi;
+            pdd = f2_dot3(L, d).hi;
+            qx0 = f2_dot3(U, r).hi;
+            qdx = f2_dot3(U, d).hi;
+            qy0 = f2_dot3(V, r).hi;
+            qdy = f2_dot3(V, d).hi;
         } else {
-            qx0 = (float)(F.Ux[0] * pin[0] + F.Ux[1] * pin[1] + F.Ux[2] * pin[2] + F.Ux0 - F.Mr);
-            qy0 = (float)(F.Vy[0] * pin[0] + F.Vy[1] * pin[1] + F.Vy[2] * pin[2] + F.Vy0 - F.Mr);
-            qdx = (float)(F.Ux[0] * d[0] + F.Ux[1] * d[1] + F.Ux[2] * d[2]);
-            qdy = (float)(F.Vy[0] * d[0] + F.Vy[1] * d[1] + F.Vy[2] * d[2]);
+            const F2 Ux[3] = {F2{F.Ux[0], F.Uxl[0]}, F2{F.Ux[1], F.Uxl[1]}, F2{F.Ux[2], F.Uxl[2]}};
+            const F2 Vy[3] = {F2{F.Vy[0], F.Vyl[0]}, F2{F.Vy[1], F.Vyl[1]}, F2{F.Vy[2], F.Vyl[2]}};
+            qx0 = f2_add(f2_dot3(Ux, pin), F2{F.Ux0, F.Ux0l}).hi;
+            qy0 = f2_add(f2_dot3(Vy, pin), F2{F.Vy0, F.Vy0l}).hi;
+            qdx = f2_dot3(Ux, d).hi;
+            qdy = f2_dot3(Vy, d).hi;
         }
         if (MODE == VI_MODE_CONE || MODE == kModeConeGrid) {
             // B: direction toward the viewer with its L component removed
-            double w[3] = {-d[0], -d[1], -d[2]};
-            const double wl = w[0] * F.L[0] + w[1] * F.L[1] + w[2] * F.L[2];
-            double B[3] = {w[0] - wl * F.L[0], w[1] - wl * F.L[1], w[2] - wl * F.L[2]};
-            const double nb = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
-            if (nb < 1e-6) {
+            // (U when the view runs along L)
+            const float wl = -fmaf(hdx, F.L[0], fmaf(hdy, F.L[1], hdz * F.L[2]));
+            float B[3] = {fmaf(-wl, F.L[0], -hdx), fmaf(-wl, F.L[1], -hdy), fmaf(-wl, F.L[2], -hdz)};
+            const float nb = sqrtf(fmaf(B[0], B[0], fmaf(B[1], B[1], B[2] * B[2])));
+            if (nb < 1e-6f) {
                 for (int a = 0; a < 3; ++a) B[a] = F.U[a];
             } else {
-                for (int a = 0; a < 3; ++a) B[a] /= nb;
+                const float inb = 1.0f / nb;
+                for (int a = 0; a < 3; ++a) B[a] *= inb;
             }
-            const double P[3] = {F.L[1] * B[2] - F.L[2] * B[1], F.L[2] * B[0] - F.L[0] * B[2],
-                                 F.L[0] * B[1] - F.L[1] * B[0]};
-            cf.bx = (float)(F.Ux[0] * B[0] + F.Ux[1] * B[1] + F.Ux[2] * B[2]);
-            cf.by = (float)(F.Vy[0] * B[0] + F.Vy[1] * B[1] + F.Vy[2] * B[2]);
-            cf.px = (float)(F.Ux[0] * P[0] + F.Ux[1] * P[1] + F.Ux[2] * P[2]);
-            cf.py = (float)(F.Vy[0] * P[0] + F.Vy[1] * P[1] + F.Vy[2] * P[2]);
+            const float P[3] = {F.L[1] * B[2] - F.L[2] * B[1], F.L[2] * B[0] - F.L[0] * B[2],
+                                F.L[0] * B[1] - F.L[1] * B[0]};
+            // B and L x B in texels per voxel
+            cf.bx = fmaf(F.Ux[0], B[0], fmaf(F.Ux[1], B[1], F.Ux[2] * B[2]));
+            cf.by = fmaf(F.Vy[0], B[0], fmaf(F.Vy[1], B[1], F.Vy[2] * B[2]));
+            cf.px = fmaf(F.Ux[0], P[0], fmaf(F.Ux[1], P[1], F.Ux[2] * P[2]));
+            cf.py = fmaf(F.Vy[0], P[0], fmaf(F.Vy[1], P[1], F.Vy[2] * P[2]));
         }
     }
 
     const VT* __restrict__ vol = (const VT*)F.vol;
     const VolIndex VI_ = {1u, F.vsy, F.vsz};
-    const float Df = (float)D, dtf = (float)F.dt;
+    const float dtf = F.dt;
     const float Km1 = (float)(F.K - 1);
     // C: premultiplied colour so far; T = 1 - alpha_dst, the transmittance in
     // front of the next segment (kept as a product of exact per-segment
@@ -497,7 +525,11 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
             const float s1 = fminf((float)(kk + 1) * dtf, Df);
             const float len = s1 - s0;
             const float sm = 0.5f * (s0 + s1);
-            const float hx = fmaf(sm, hdx, hx0), hy = fmaf(sm, hdy, hy0), hz = fmaf(sm, hdz, hz0);
+            // entry + sm d on the pairs: the high parts in one FMA, the
+            // remainders added
+            const float hx = fmaf(sm, hdx, hx0) + fmaf(sm, hdxl, hxl);
+            const float hy = fmaf(sm, hdy, hy0) + fmaf(sm, hdyl, hyl);
+            const float hz = fmaf(sm, hdz, hz0) + fmaf(sm, hdzl, hzl);
             empty = false;
             if (F.occ.mm) {
                 const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1),
@@ -536,7 +568,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                 const float4 ta = s_tf[e0], tb = s_tf[e0 + 1];
                 const float a = clampf01(fmaf(w, tb.w - ta.w, ta.w));
                 // (1 - alpha) of a segment of length len: (1 - a)^(len / dref)
-                if (len > 0.0f && a > 0.0f) om = fast_exp2(len * F.N_f * fast_log2(1.0f - a));
+                if (len > 0.0f && a > 0.0f) om = fast_exp2(len * fast_log2(1.0f - a));
                 const float alpha = 1.0f - om;
                 if (alpha > 0.0f) {
                     // emission alpha (sd rgb + ss) light: Eq. 7 with the

@@ -40,7 +40,7 @@ class Volume_t(C.Structure):
 
 
 class TF_t(C.Structure):
-    _fields_ = [("rgba", C.c_void_p), ("n_entries", C.c_int)]
+    _fields_ = [("rgba", C.c_void_p), ("n_entries", C.c_int), ("tag", C.c_uint64)]
 
 
 class Slices_t(C.Structure):
@@ -120,6 +120,7 @@ SIGNATURES = {
     "vi_render": ([C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(Slices_t), C.POINTER(Camera_t), C.c_int,
                    C.c_float, C.POINTER(RenderOpts_t), C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "vi_tag": ([C.POINTER(Volume_t), C.POINTER(TF_t)], C.c_uint64),
+    "vi_tf_tag": ([C.c_void_p, C.c_int], C.c_uint64),
     "vi_server_create": ([C.POINTER(ServerCfg_t), C.POINTER(C.c_void_p)], C.c_int),
     "vi_server_register_volume": ([C.c_void_p, C.POINTER(Volume_t), C.POINTER(TF_t), C.POINTER(C.c_int)], C.c_int),
     "vi_server_submit": ([C.c_void_p, C.POINTER(Request_t), C.POINTER(C.c_uint64)], C.c_int),
@@ -267,7 +268,9 @@ class TF:
         if rgba.dim() != 2 or rgba.shape[1] != 4:
             raise ValueError("transfer function must be K x 4")
         self.data = rgba.to(torch.float32).contiguous()
-        self.s = TF_t(self.data.data_ptr(), int(self.data.shape[0]))
+        # the table's content tag, from a host copy taken once here
+        host = self.data.detach().to("cpu").contiguous()
+        self.s = TF_t(self.data.data_ptr(), int(self.data.shape[0]), tf_tag(host))
 
     @staticmethod
     def from_numpy(tab, device="cuda") -> "TF":
@@ -438,6 +441,12 @@ def render(vol: Volume, tf: TF, slices: Slices | None, cam: dict, mode: str, ste
 
 def tag(vol: Volume, tf: TF) -> int:
     return int(lib().vi_tag(C.byref(vol.s), C.byref(tf.s)))
+
+
+def tf_tag(host_rgba: torch.Tensor) -> int:
+    """Content tag of a K x 4 float32 table held in host memory."""
+    t = host_rgba.to(torch.float32).contiguous()
+    return int(lib().vi_tf_tag(C.c_void_p(t.data_ptr()), int(t.shape[0])))
 
 
 def version() -> str:

@@ -319,3 +319,38 @@ def test_minmax_validation():
     f = _Fake()
     f.vol = v
     assert _build(f) == -1
+
+
+def test_tf_identity_is_its_contents():
+    """Two tables at the same device address (a freed table's address reused
+    by the allocator) with different contents name different stacks and
+    occupancy bits; the same contents name the same."""
+    import numpy as np
+    import torch
+    lib = vi.lib()
+    ramp = np.linspace(0, 1, 256 * 4, dtype=np.float32).reshape(256, 4)
+    other = ramp.copy()
+    other[100, 3] = 0.5
+    ta = vi.tf_tag(torch.from_numpy(ramp))
+    tb = vi.tf_tag(torch.from_numpy(other))
+    assert ta != 0 and tb != 0 and ta != tb
+    assert ta == vi.tf_tag(torch.from_numpy(ramp.copy()))
+    assert lib.vi_tf_tag(None, 4) == 0
+    a, b = _Fake(), _Fake()
+    a.tf.tag, b.tf.tag = ta, tb                       # same pointer 0x20000, other contents
+    assert lib.vi_tag(C.byref(a.vol), C.byref(a.tf)) != lib.vi_tag(C.byref(b.vol), C.byref(b.tf))
+    # a stack built with table a is refused with table b
+    sa = _desc(a)
+    assert _render(b, sa, mode=2) == -1
+    assert "another volume or transfer function" in lib.vi_last_error().decode()
+    # (occupancy bits carry the same identity: tests/test_gpu_parity.py makes
+    # bits with one table and has them refused with a rewritten one)
+
+
+def test_step_bound_keeps_segments_below_2_24():
+    """step_vox so small that a chord of sqrt(3) N voxels would hold more than
+    2^24 segments is refused before any launch."""
+    f = _Fake(n=16)
+    good = _desc(f)
+    assert _render(f, good, step=1e-6) == -1
+    assert "2^24" in vi.lib().vi_last_error().decode()

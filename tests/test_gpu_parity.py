@@ -569,3 +569,23 @@ def test_occupancy_bits_refuse_another_transfer_function():
     other = vi.TF.from_numpy(W.tf_ramp(), DEV)
     with pytest.raises(vi.VIError):
         vi.build_attenuation(bits, other, [0, 0, 1], 16, 32)
+
+
+def test_rewritten_transfer_function_is_refused():
+    """A table rewritten in place (same device address, new contents) names
+    another identity: occupancy bits and stacks made with the old contents
+    are refused, not silently reused."""
+    raw = W.ct_phantom_u16(32, seed=16)
+    vol, tf = gpu_inputs(raw, W.tf_ct(), cell=8)
+    bits = vol.with_occupancy(tf)
+    st = vi.build_attenuation(bits, tf, [0, 0, 1], 16, 32)
+    torch.cuda.synchronize()
+    tf.data.copy_(torch.from_numpy(W.tf_ramp()).to(DEV))   # same pointer, other table
+    again = vi.TF(tf.data)
+    assert again.data.data_ptr() == tf.data.data_ptr()
+    with pytest.raises(vi.VIError):
+        vi.build_attenuation(bits, again, [0, 0, 1], 16, 32)
+    cam = {"kind": "ortho", "eye": [0.5, -2.0, 0.5], "target": [0.5, 0.5, 0.5], "up": [0, 0, 1],
+           "ortho_half_h": 0.75, "width": 16, "height": 16}
+    with pytest.raises(vi.VIError):
+        vi.render(vol, again, st, cam, "shell", 0.5)
