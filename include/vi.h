@@ -152,13 +152,17 @@ typedef struct {
  *     up to 8 and R4 = res rounded up to 4, texel (k, j, i) is element
  *       k*R8*R4 + ((j/4)*(R8/8) + i/8)*32 + (j%4)*8 + i%8
  *     (padding never read).  n*R8*R4 elements.
- *   VI_STACK_ROWS: every layer row-major with a border of fully
- *     transmitting texels (T = 1, optical depth 0) around the grid, so the
- *     two texels of a bilinear row, (k, j, i) and (k, j, i+1), are adjacent
- *     for every i in [-1, res-1] and one 8-byte load per row reads them.
- *     With row pitch P = res+4 rounded up to 4 and LS = (res+2)*P, texel
- *     (k, j, i), i and j in [-1, res], is element k*LS + (j+1)*P + (i+1);
- *     n*LS elements (columns res+2 .. P-1 are never used). */
+ *   VI_STACK_ROWS: every layer row-major with a border two texels wide of
+ *     fully transmitting texels (T = 1, optical depth 0) around the grid,
+ *     and one leading layer k = -1 that transmits fully everywhere (face 0
+ *     of the depth index of Eq. 9).  The two texels of a bilinear row,
+ *     (k, j, i) and (k, j, i+1), are adjacent, so one 8-byte load per row
+ *     reads them, and every footprint of a lookup, clamped to i, j in
+ *     [-2, res] and k in [-1, n-1], reads stored texels only.  With row
+ *     pitch P = res+4 (bfloat16: res+6) rounded up to 4 and LS = (res+4)*P,
+ *     texel (k, j, i), k in [-1, n-1], i and j in [-2, res+1], is element
+ *     (k+1)*LS + (j+2)*P + (i+2); (n+1)*LS elements (columns res+4 .. P-1
+ *     are never used). */
 typedef enum { VI_STACK_TILED = 0, VI_STACK_ROWS = 1 } vi_stack_layout;
 
 /* Attenuation stack descriptor, filled by vi_build_attenuation (or by

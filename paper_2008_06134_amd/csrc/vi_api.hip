@@ -149,13 +149,18 @@ void volume_strides(const vi_volume* v, uint32_t* sy, uint32_t* sz)
 // Kernels index stacks with 32-bit element offsets: stacks stay below 4 GiB.
 bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_bytes(n, res, dt, sl) < 4294967296.0; }
 
-// Row layout: texel 0 of a row at element 1, pitch res + 4 rounded up to 4
-// (an 8-byte read of the bfloat16 pair at the last column stays inside the
-// row), res+2 rows per layer.  (Rows aligned to 128-byte lines were measured
-// slower: a line-multiple pitch maps the rows of a footprint onto fewer
-// cache sets.)
-uint32_t row_origin(int) { return 1u; }
-uint32_t row_pitch(int res, int) { return vi::round_up((uint32_t)res + 4u, 4u); }
+// Row layout: every layer has rows -2 .. res+1 and columns -2 .. res+1 of
+// texels, the two outermost rings a fully transmitting border; one extra
+// leading layer (-1, face 0 of Eq. 9's index) transmits fully too.  The
+// pitch is res + 4 rounded up to 4 (res + 6 for bfloat16, whose pair reads
+// take the aligned 4-element window holding the pair, so that the window of
+// the last pair stays inside its row).  (Rows aligned to 128-byte lines were
+// measured slower: a line-multiple pitch maps the rows of a footprint onto
+// fewer cache sets.)
+uint32_t row_pitch(int res, int dt) { return vi::round_up((uint32_t)res + (dt == VI_BF16 ? 6u : 4u), 4u); }
+uint32_t row_layer(int res, int dt) { return ((uint32_t)res + 4u) * row_pitch(res, dt); }
+// element of texel (k, j, i) = (0, 0, 0): past the front layer, two rows and two columns of border
+uint32_t row_origin(int res, int dt) { return row_layer(res, dt) + 2u * row_pitch(res, dt) + 2u; }
 
 // A position or step in voxels as a Q40 fixed-point number (the build's
 // slab positions): |x| < 2^23 voxels, rounded to the nearest 2^-40 voxel.
@@ -292,7 +297,7 @@ size_t vi_slices_bytes(int n, int res, int dt, int sl)
     if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16)) return 0;
     if (sl == VI_STACK_TILED)
         return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
-    if (sl == VI_STACK_ROWS) return (size_t)n * ((size_t)res + 2u) * row_pitch(res, dt) * elem_size(dt);
+    if (sl == VI_STACK_ROWS) return ((size_t)n + 1u) * row_layer(res, dt) * elem_size(dt);
     return 0;
 }
 
@@ -477,8 +482,8 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
     p.layer = vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u);
     p.row_tiles32 = vi::round_up((uint32_t)res, 8u) * 4u;
     p.rpitch = row_pitch(res, dt);
-    p.rorg = row_origin(dt);
-    p.rlayer = ((uint32_t)res + 2u) * p.rpitch;
+    p.rorg = row_origin(res, dt);
+    p.rlayer = row_layer(res, dt);
     const double N = vol->n, texel = 2.0 * f.R / res, u0 = -f.R + 0.5 * texel;
     const double d0 = f.dmin + 0.5 * f.ds, Lc = dot3(f.L, f.c);
     if (f.positional) {
@@ -628,8 +633,8 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         F.layer = vi::round_up((uint32_t)sl->res, 8u) * vi::round_up((uint32_t)sl->res, 4u);
         F.row_tiles32 = vi::round_up((uint32_t)sl->res, 8u) * 4u;
         F.rpitch = row_pitch(sl->res, sl->dtype);
-        F.rorg = row_origin(sl->dtype);
-        F.rlayer = ((uint32_t)sl->res + 2u) * F.rpitch;
+        F.rorg = row_origin(sl->res, sl->dtype);
+        F.rlayer = row_layer(sl->res, sl->dtype);
         F.Mz = sl->n / 2;
         F.Mr = sl->res / 2;
         const double span = sl->dmax - sl->dmin, sc = sl->res / (2.0 * sl->R);
@@ -691,12 +696,19 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         tx = cam->ortho_half_h * aspect * Nd;
         ty = cam->ortho_half_h * Nd;
     }
+    // pixel (px, py): xn = (2 px + 1 - W) / W, yn = (H - 2 py - 1) / H, and
+    // b = base + xn R + yn U (base: the eye, or for a pinhole the forward
+    // direction) = (base + R (1 - W) / W + U (H - 1) / H) + px (2 R / W) - py (2 U / H)
+    const double Wd = cam->width, Hd = cam->height;
     for (int a = 0; a < 3; ++a) {
         if (!isfinite(cam->eye[a])) return fail(VI_E_INVALID_ARG, "camera eye is not finite");
-        split_float(cam->eye[a] * Nd - hoff, &F.cam_o[a], &F.cam_ol[a]);
+        const double eye_h = cam->eye[a] * Nd - hoff, R = right[a] * tx, U = up2[a] * ty;
+        const double base = cam->kind == VI_CAM_PERSP ? fwd[a] : eye_h;
+        split_float(eye_h, &F.cam_o[a], &F.cam_ol[a]);
         split_float(fwd[a], &F.cam_f[a], &F.cam_fl[a]);
-        split_float(right[a] * tx, &F.cam_r[a], &F.cam_rl[a]);
-        split_float(up2[a] * ty, &F.cam_u[a], &F.cam_ul[a]);
+        split_float(base + R * (1.0 - Wd) / Wd + U * (Hd - 1.0) / Hd, &F.cam_b[a], &F.cam_bl[a]);
+        split_float(2.0 * R / Wd, &F.cam_sx[a], &F.cam_sxl[a]);
+        split_float(-2.0 * U / Hd, &F.cam_sy[a], &F.cam_syl[a]);
     }
     F.lo = (float)(-hoff);
     F.hi = (float)(Nd - hoff);
@@ -704,6 +716,7 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     if (sqrt(3.0) * Nd / step_vox > 16777216.0)
         return fail(VI_E_INVALID_ARG, "step_vox %g gives more than 2^24 segments per ray", (double)step_vox);
     F.dt = step_vox;
+    split_float(1.0 / (double)step_vox, &F.idt, &F.idtl);
     F.ambient = o.ambient;
     for (int c = 0; c < 3; ++c) F.light[c] = o.light_rgb[c];
     for (int c = 0; c < 4; ++c) F.bg[c] = o.bg[c];

@@ -36,29 +36,33 @@
 
 namespace vi {
 
-// Row layout: the texels of the one-texel border around the grid are the
-// same in every layer (fully transmitting: T = 1, optical depth 0), so a
-// separate small kernel writes them and the slab loop stores only its own
-// texel.  One lane per border texel and layer: rows -1 and res (res+2 texels
-// each), then columns -1 and res of rows 0..res-1.
+// Row layout: the texels of the two-texel border around the grid are the
+// same in every layer, and so is the whole leading layer -1 (fully
+// transmitting: T = 1, optical depth 0), so a separate small kernel writes
+// the border rings of layers -1 .. n-1 and the slab loop stores only its own
+// texels (layer -1 included).  One lane per border texel and layer: rows -2,
+// -1, res, res+1 (res+4 texels each), then columns -2, -1, res, res+1 of rows
+// 0..res-1.
 template <typename ET>
 __global__ __launch_bounds__(256) void border_kernel(ET* __restrict__ out, int n, int res, uint32_t rlayer,
                                                      uint32_t rpitch, uint32_t rorg, ET one)
 {
-    const uint32_t per_layer = 2u * (uint32_t)(res + 2) + 2u * (uint32_t)res;
+    const uint32_t W = (uint32_t)res + 4u, per_layer = 4u * W + 4u * (uint32_t)res;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (size_t)per_layer * (size_t)n) return;
-    const uint32_t k = (uint32_t)(t / per_layer), q = (uint32_t)(t % per_layer);
-    int row, col;  // grid texel coordinates in [-1, res]
-    if (q < 2u * (uint32_t)(res + 2)) {
-        row = q < (uint32_t)(res + 2) ? -1 : res;
-        col = (int)(q % (uint32_t)(res + 2)) - 1;
+    if (t >= (size_t)per_layer * ((size_t)n + 1u)) return;
+    const int k = (int)(t / per_layer) - 1;
+    const uint32_t q = (uint32_t)(t % per_layer);
+    int row, col;  // grid texel coordinates in [-2, res+1]
+    if (q < 4u * W) {
+        const uint32_t r = q / W;  // 0, 1, 2, 3 -> rows -2, -1, res, res+1
+        row = r < 2u ? (int)r - 2 : res + (int)r - 2;
+        col = (int)(q % W) - 2;
     } else {
-        const uint32_t r = q - 2u * (uint32_t)(res + 2);
-        row = (int)(r >> 1);
-        col = (r & 1u) ? res : -1;
+        const uint32_t r = q - 4u * W, c = r & 3u;
+        row = (int)(r >> 2);
+        col = c < 2u ? (int)c - 2 : res + (int)c - 2;
     }
-    out[(size_t)k * rlayer + (uint32_t)(row + 1) * rpitch + rorg + col] = one;
+    out[(int64_t)rorg + (int64_t)k * rlayer + (int64_t)row * rpitch + col] = one;
 }
 
 // Workgroup b -> (row, run): rows are dealt to the 8 XCDs in groups of 4
@@ -219,7 +223,7 @@ __device__ __forceinline__ void build_run(const BuildParams& P)
         }
         kmin = min(kmin, kin[c]);
         kmax = max(kmax, kout[c]);
-        at[c] = SL == VI_STACK_ROWS ? (uint32_t)(j + 1) * P.rpitch + P.rorg + (uint32_t)i
+        at[c] = SL == VI_STACK_ROWS ? P.rorg + (uint32_t)j * P.rpitch + (uint32_t)i
                                     : stack_oj(j, P.row_tiles32) + stack_oi(i);
     }
     bool col[C];
@@ -229,6 +233,11 @@ __device__ __forceinline__ void build_run(const BuildParams& P)
     kmin = __builtin_amdgcn_readfirstlane(wave_min(kmin));
     kmax = __builtin_amdgcn_readfirstlane(wave_max(kmax));
     const uint32_t layer = SL == VI_STACK_ROWS ? P.rlayer : P.layer;
+    // row layout: the leading layer -1 (face 0) transmits fully
+    if (SL == VI_STACK_ROWS)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c] - layer, 1.0f, 0.0f);
 
     // slabs in front of the cube: the light arrives unattenuated
     {
@@ -369,7 +378,7 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
         if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds, s);
         else launch_build_k<VT, LAYOUT, VI_STACK_ROWS, false>(p, grid, lds, s);
         // the border, the same in every layer
-        const size_t nb = (2u * (size_t)(p.res + 2) + 2u * (size_t)p.res) * (size_t)p.n;
+        const size_t nb = (4u * (size_t)(p.res + 4) + 4u * (size_t)p.res) * ((size_t)p.n + 1u);
         const dim3 bgrid((uint32_t)((nb + 255) / 256));
         if (p.out_dtype == VI_F32)
             hipLaunchKernelGGL((border_kernel<float>), bgrid, dim3(256), 0, s, (float*)p.out, p.n, p.res, p.rlayer,

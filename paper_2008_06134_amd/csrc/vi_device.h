@@ -60,19 +60,26 @@ __device__ __forceinline__ F2 f2_mul(F2 a, F2 b)
     const float e = fmaf(a.hi, b.hi, -p) + (a.hi * b.lo + a.lo * b.hi);
     return f2_fast(p, e);
 }
+// a / b: a quotient from the hardware reciprocal, corrected once by the
+// pair residual a - q b (the reciprocal's error enters squared)
 __device__ __forceinline__ F2 f2_div(F2 a, F2 b)
 {
 #pragma clang fp contract(off)
-    const float q = a.hi / b.hi;
-    const F2 r = f2_sub(a, f2_mul(f2(q), b));  // a - q b
-    return f2_fast(q, r.hi / b.hi);
+    const float r = __builtin_amdgcn_rcpf(b.hi);
+    const float q = a.hi * r;
+    const F2 e = f2_sub(a, f2_mul(f2(q), b));  // a - q b
+    const float q2 = e.hi * r;
+    const F2 e2 = f2_sub(e, f2_mul(f2(q2), b));
+    return f2_add(f2_fast(q, q2), f2(e2.hi * r));
 }
-__device__ __forceinline__ F2 f2_sqrt(F2 a)  // a > 0
+// 1 / sqrt(a), a > 0: the hardware estimate and one Newton step on the pair
+__device__ __forceinline__ F2 f2_rsqrt(F2 a)
 {
 #pragma clang fp contract(off)
-    const float s = sqrtf(a.hi);
-    const F2 r = f2_sub(a, f2_mul(f2(s), f2(s)));
-    return f2_fast(s, r.hi / (2.0f * s));
+    const float r = __builtin_amdgcn_rsqf(a.hi);
+    const F2 y = f2_mul(f2_mul(a, f2(r)), f2(r));           // a r^2, about 1
+    const F2 h = f2_sub(f2(1.5f), f2_mul(f2(0.5f), y));      // (3 - a r^2) / 2
+    return f2_mul(f2(r), h);
 }
 __device__ __forceinline__ bool f2_lt(F2 a, F2 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
 __device__ __forceinline__ F2 f2_max(F2 a, F2 b) { return f2_lt(a, b) ? b : a; }

@@ -51,7 +51,7 @@ struct BuildParams {
     int n, res;
     int out_layout;    // VI_STACK_TILED / VI_STACK_ROWS
     uint32_t layer, row_tiles32;  // tiled: R8*R4 per layer, (R8/8)*32 per tile row
-    uint32_t rlayer, rpitch, rorg;  // rows: (res+2)*P elements per layer, pitch P, texel 0 at column rorg
+    uint32_t rlayer, rpitch, rorg;  // rows: elements per layer, pitch P, element of texel (0,0,0)
     int64_t B0q[3];    // h at (i,j,k) = (0,0,0), Q40
     int64_t BUq[3];    // d h / d i
     int64_t BVq[3];    // d h / d j
@@ -87,7 +87,7 @@ struct RenderFrame {
     int n, res;
     int stack_layout;
     uint32_t layer, row_tiles32;
-    uint32_t rlayer, rpitch, rorg;
+    uint32_t rlayer, rpitch, rorg;  // rows: elements per layer, pitch, element of texel (0,0,0)
     int Mz, Mr;          // integer offsets of the light-grid coordinates
     // Light grid as affine maps of the offset-voxel position h; every
     // coefficient is a float pair (value, remainder), so that the per-ray
@@ -103,17 +103,18 @@ struct RenderFrame {
     int point;
     float Ph[3], Phl[3]; // light position in offset-voxel coordinates
     float sc, xo;
-    // camera, in offset-voxel coordinates (float pairs): a pinhole ray leaves
-    // cam_o along cam_f + xn cam_r + yn cam_u (normalised); an orthographic
-    // ray leaves cam_o + xn cam_r + yn cam_u along cam_f (xn, yn in [-1, 1]
-    // across the image)
+    // camera, in offset-voxel coordinates (float pairs): pixel (px, py)
+    // maps to b = cam_b + px cam_sx + py cam_sy; a pinhole ray leaves cam_o
+    // along b (normalised), an orthographic ray leaves b along cam_f
     int cam_kind;
     int width, height;
-    float cam_o[3], cam_ol[3], cam_f[3], cam_fl[3], cam_r[3], cam_rl[3], cam_u[3], cam_ul[3];
+    float cam_o[3], cam_ol[3], cam_f[3], cam_fl[3];
+    float cam_b[3], cam_bl[3], cam_sx[3], cam_sxl[3], cam_sy[3], cam_syl[3];
     float lo, hi;        // the cube in h coordinates: [-1/2 - M, N - 1/2 - M]
     // march
     int mode;
     float dt;            // step in voxels (= the reference length of Eq. 6's exponent)
+    float idt, idtl;     // 1 / dt as a float pair
     float ambient, light[3], bg[4], term_eps;
     float phong_ka, phong_kd, phong_ks, phong_shin, grad_eps;
     // gather taps in light-grid units (shell: fixed; cone: per ray)

@@ -80,30 +80,30 @@ __device__ __forceinline__ float2 stack_pair(const void* __restrict__ S, uint32_
 }
 
 // One row-layout lookup split into its four loads (rows j, j+1 of layers k0
-// and k1) and its arithmetic.  Layer k0 = -1 (in front of the first face)
-// loads layer 0 and reads 1 instead, so the four loads go out together.
+// and k1) and its arithmetic.  The layout makes every footprint a plain read:
+// layer -1 (face 0) transmits fully, so a depth index in front of the first
+// face needs no test, and the two-texel border lets a footprint that reaches
+// past the grid clamp onto border texels only (a column a < -2 reads the
+// pair (-2, -1), a > res the pair (res, res+1): both 1).  No selects, no
+// branches; the four loads go out together.
 template <int SDT>
 struct RowTap {
     PairRaw<SDT> a0, a1, b0, b1;  // layer k0 rows j, j+1; layer k1 rows j, j+1
     float wx, wy, wz;
-    bool in, front;
 };
 template <int SDT>
 __device__ __forceinline__ void rowtap_load(const RenderFrame& F, float z, float x, float y, RowTap<SDT>& t)
 {
-    z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
+    z = __builtin_amdgcn_fmed3f(z, (float)(-1 - F.Mz), (float)(F.n - 1 - F.Mz));
     const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
     t.wz = z - fz;
     t.wx = x - fx;
     t.wy = y - fy;
-    const int k0 = (int)fz + F.Mz;
+    const int k0 = (int)fz + F.Mz;                 // -1 .. n-1
     const int k1 = min(k0 + 1, F.n - 1);
-    const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;
-    // footprints reaching past the border read 1 everywhere
-    t.in = a >= -1 && a <= F.res - 1 && b >= -1 && b <= F.res - 1;
-    t.front = k0 < 0;
-    const uint32_t e = (uint32_t)(clampi(b, -1, F.res - 1) + 1) * F.rpitch + F.rorg + (uint32_t)clampi(a, -1, F.res - 1);
-    const uint32_t base0 = (uint32_t)max(k0, 0) * F.rlayer + e, base1 = (uint32_t)k1 * F.rlayer + e;
+    const int a = min(max((int)fx + F.Mr, -2), F.res), b = min(max((int)fy + F.Mr, -2), F.res);
+    const uint32_t e = (uint32_t)((int)F.rorg + b * (int)F.rpitch + a);
+    const uint32_t base0 = e + (uint32_t)(k0 * (int)F.rlayer), base1 = e + (uint32_t)(k1 * (int)F.rlayer);
     t.a0 = pair_load<SDT>(F.stack, base0);
     t.a1 = pair_load<SDT>(F.stack, base0 + F.rpitch);
     t.b0 = pair_load<SDT>(F.stack, base1);
@@ -112,16 +112,13 @@ __device__ __forceinline__ void rowtap_load(const RenderFrame& F, float z, float
 template <int SDT>
 __device__ __forceinline__ float rowtap_value(const RowTap<SDT>& t)
 {
-    float t0 = 1.0f;
-    if (!t.front) {
-        float2 r0 = pair_value(t.a0), r1 = pair_value(t.a1);
-        if (!t.in) r0 = r1 = make_float2(1.0f, 1.0f);
-        const float ab = fmaf(t.wx, r0.y - r0.x, r0.x), cd = fmaf(t.wx, r1.y - r1.x, r1.x);
-        t0 = fmaf(t.wy, cd - ab, ab);
-    }
-    float2 r0 = pair_value(t.b0), r1 = pair_value(t.b1);
-    if (!t.in) r0 = r1 = make_float2(1.0f, 1.0f);
-    const float ab = fmaf(t.wx, r0.y - r0.x, r0.x), cd = fmaf(t.wx, r1.y - r1.x, r1.x);
+    float2 r0 = pair_value(t.a0), r1 = pair_value(t.a1);
+    float ab = fmaf(t.wx, r0.y - r0.x, r0.x), cd = fmaf(t.wx, r1.y - r1.x, r1.x);
+    const float t0 = fmaf(t.wy, cd - ab, ab);
+    r0 = pair_value(t.b0);
+    r1 = pair_value(t.b1);
+    ab = fmaf(t.wx, r0.y - r0.x, r0.x);
+    cd = fmaf(t.wx, r1.y - r1.x, r1.x);
     const float t1 = fmaf(t.wy, cd - ab, ab);
     return fmaf(t.wz, t1 - t0, t0);
 }
@@ -295,7 +292,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
 __device__ __forceinline__ float frustum_col(const RenderFrame& F, float u, float rd, bool ahead)
 {
     const float x = ahead ? fmaf(u * rd, F.sc, F.xo) : -3.0e38f;
-    return fminf(fmaxf(x, (float)(-2 - F.Mr)), (float)(F.res + 1 - F.Mr));
+    return fminf(fmaxf(x, (float)(-3 - F.Mr)), (float)(F.res + 2 - F.Mr));
 }
 
 template <int MODE, int SDT, int SL>
@@ -365,53 +362,56 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     const int lane = threadIdx.x & 63, g = lane % G, gbase = lane - g;
     // ---- camera ray, in offset-voxel coordinates, in float pairs (the
     // host folded the camera and the light grid into float-pair
-    // coefficients of h; see F2)
-    F2 xn, yn;
-    {
-        // xn = (2 px + 1 - W) / W, yn = (H - 2 py - 1) / H: exact numerators
-        const float W = (float)F.width, H = (float)F.height;
-        xn = f2_div(f2(2.0f * (float)px + 1.0f - W), f2(W));
-        yn = f2_div(f2(H - 2.0f * (float)py - 1.0f), f2(H));
-    }
+    // coefficients of h; see F2): pixel (px, py) -> b = base + px sx + py sy
     F2 o[3], d[3];
-    for (int a = 0; a < 3; ++a) {
-        const F2 r = F2{F.cam_r[a], F.cam_rl[a]}, u = F2{F.cam_u[a], F.cam_ul[a]};
-        const F2 f = F2{F.cam_f[a], F.cam_fl[a]}, e = F2{F.cam_o[a], F.cam_ol[a]};
-        const F2 lat = f2_add(f2_mul(xn, r), f2_mul(yn, u));
+    {
+        const F2 fx = f2((float)px), fy = f2((float)py);
+        for (int a = 0; a < 3; ++a) {
+            const F2 b = f2_add(F2{F.cam_b[a], F.cam_bl[a]},
+                                f2_add(f2_mul(fx, F2{F.cam_sx[a], F.cam_sxl[a]}), f2_mul(fy, F2{F.cam_sy[a], F.cam_syl[a]})));
+            if (F.cam_kind == VI_CAM_PERSP) {
+                o[a] = F2{F.cam_o[a], F.cam_ol[a]};
+                d[a] = b;
+            } else {
+                o[a] = b;
+                d[a] = F2{F.cam_f[a], F.cam_fl[a]};
+            }
+        }
         if (F.cam_kind == VI_CAM_PERSP) {
-            o[a] = e;
-            d[a] = f2_add(f, lat);
-        } else {
-            o[a] = f2_add(e, lat);
-            d[a] = f;
+            const F2 inv = f2_rsqrt(f2_dot3(d, d));
+            for (int a = 0; a < 3; ++a) d[a] = f2_mul(d[a], inv);
         }
     }
-    if (F.cam_kind == VI_CAM_PERSP) {
-        const F2 inv = f2_div(f2(1.0f), f2_sqrt(f2_dot3(d, d)));
-        for (int a = 0; a < 3; ++a) d[a] = f2_mul(d[a], inv);
-    }
-    // ---- slab test against the cube [lo, hi]^3 (distances in voxels)
-    F2 tn = f2(-3.0e38f), tf = f2(3.0e38f);
+    // ---- slab test against the cube [lo, hi]^3 (distances in voxels): the
+    // entry and exit faces are picked in float, their distances then taken on
+    // the pairs
+    float tn = -3.0e38f, tf_ = 3.0e38f, bn = 0.0f, bf = 0.0f;
+    int an = -1, af = -1;
     bool hit = true;
     for (int a = 0; a < 3; ++a) {
         if (d[a].hi == 0.0f) {
             if (o[a].hi < F.lo || o[a].hi > F.hi) hit = false;
             continue;
         }
-        const F2 t1 = f2_div(f2_sub(f2(F.lo), o[a]), d[a]), t2 = f2_div(f2_sub(f2(F.hi), o[a]), d[a]);
-        tn = f2_max(tn, f2_min(t1, t2));
-        tf = f2_min(tf, f2_max(t1, t2));
+        const float r = __builtin_amdgcn_rcpf(d[a].hi);
+        const float near = d[a].hi > 0.0f ? F.lo : F.hi, far = d[a].hi > 0.0f ? F.hi : F.lo;
+        const float t1 = (near - o[a].hi) * r, t2 = (far - o[a].hi) * r;
+        if (t1 > tn) tn = t1, an = a, bn = near;
+        if (t2 < tf_) tf_ = t2, af = a, bf = far;
     }
-    const F2 ti = f2_max(tn, f2(0.0f));
     float4 bg = make_float4(F.bg[0], F.bg[1], F.bg[2], F.bg[3]);
-    if (!hit || !f2_lt(ti, tf)) return bg;
+    if (!hit || af < 0 || !(tf_ > fmaxf(tn, 0.0f))) return bg;
+    const auto pick = [&](const F2* v, int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); };
+    const F2 ti = (an >= 0 && tn > 0.0f) ? f2_div(f2_sub(f2(bn), pick(o, an)), pick(d, an)) : f2(0.0f);
+    const F2 tf = f2_div(f2_sub(f2(bf), pick(o, af)), pick(d, af));
+    if (!f2_lt(ti, tf)) return bg;
 
     const F2 Dc = f2_sub(tf, ti);  // chord length, voxels
     const float Df = Dc.hi;
     int K;
     {
         // K = ceil(D / dt), decided on the pair
-        const F2 q = f2_div(Dc, f2(F.dt));
+        const F2 q = f2_mul(Dc, F2{F.idt, F.idtl});
         float c = ceilf(q.hi);
         if (c == q.hi && q.lo > 0.0f) c += 1.0f;
         else if (c - 1.0f - q.hi >= q.lo) c -= 1.0f;
@@ -421,9 +421,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     F2 pin[3];
     for (int a = 0; a < 3; ++a) pin[a] = f2_add(o[a], f2_mul(ti, d[a]));
     const float hx0 = pin[0].hi, hy0 = pin[1].hi, hz0 = pin[2].hi;
-    const float hxl = pin[0].lo, hyl = pin[1].lo, hzl = pin[2].lo;
     const float hdx = d[0].hi, hdy = d[1].hi, hdz = d[2].hi;
-    const float hdxl = d[0].lo, hdyl = d[1].lo, hdzl = d[2].lo;
     // light grid: depth index (Eq. 9, minus one) and texel coordinates (Eq. 10)
     // (point light: qx / qy hold the lateral offsets U.(h - Ph), V.(h - Ph)
     // and pd the depth L.(h - Ph), all affine along the ray)
@@ -451,7 +449,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     if (MODE != VI_MODE_NONE && !PHONG) {
         const F2 Lq[3] = {F2{F.Lq[0], F.Lql[0]}, F2{F.Lq[1], F.Lql[1]}, F2{F.Lq[2], F.Lql[2]}};
         qz0 = f2_add(f2_dot3(Lq, pin), F2{F.Lq0, F.Lq0l}).hi;
-        qdz = f2_dot3(Lq, d).hi;
+        qdz = fmaf(F.Lq[0], hdx, fmaf(F.Lq[1], hdy, F.Lq[2] * hdz));
         if (PT) {
             const F2 r[3] = {f2_sub(pin[0], F2{F.Ph[0], F.Phl[0]}), f2_sub(pin[1], F2{F.Ph[1], F.Phl[1]}),
                              f2_sub(pin[2], F2{F.Ph[2], F.Phl[2]})};
@@ -459,18 +457,18 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
             const F2 U[3] = {F2{F.U[0], F.Ul[0]}, F2{F.U[1], F.Ul[1]}, F2{F.U[2], F.Ul[2]}};
             const F2 V[3] = {F2{F.V[0], F.Vl[0]}, F2{F.V[1], F.Vl[1]}, F2{F.V[2], F.Vl[2]}};
             pd0 = f2_dot3(L, r).hi;
-            pdd = f2_dot3(L, d).hi;
+            pdd = fmaf(F.L[0], hdx, fmaf(F.L[1], hdy, F.L[2] * hdz));
             qx0 = f2_dot3(U, r).hi;
-            qdx = f2_dot3(U, d).hi;
+            qdx = fmaf(F.U[0], hdx, fmaf(F.U[1], hdy, F.U[2] * hdz));
             qy0 = f2_dot3(V, r).hi;
-            qdy = f2_dot3(V, d).hi;
+            qdy = fmaf(F.V[0], hdx, fmaf(F.V[1], hdy, F.V[2] * hdz));
         } else {
             const F2 Ux[3] = {F2{F.Ux[0], F.Uxl[0]}, F2{F.Ux[1], F.Uxl[1]}, F2{F.Ux[2], F.Uxl[2]}};
             const F2 Vy[3] = {F2{F.Vy[0], F.Vyl[0]}, F2{F.Vy[1], F.Vyl[1]}, F2{F.Vy[2], F.Vyl[2]}};
             qx0 = f2_add(f2_dot3(Ux, pin), F2{F.Ux0, F.Ux0l}).hi;
             qy0 = f2_add(f2_dot3(Vy, pin), F2{F.Vy0, F.Vy0l}).hi;
-            qdx = f2_dot3(Ux, d).hi;
-            qdy = f2_dot3(Vy, d).hi;
+            qdx = fmaf(F.Ux[0], hdx, fmaf(F.Ux[1], hdy, F.Ux[2] * hdz));
+            qdy = fmaf(F.Vy[0], hdx, fmaf(F.Vy[1], hdy, F.Vy[2] * hdz));
         }
         if (MODE == VI_MODE_CONE || MODE == kModeConeGrid) {
             // B: direction toward the viewer with its L component removed
@@ -525,11 +523,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
             const float s1 = fminf((float)(kk + 1) * dtf, Df);
             const float len = s1 - s0;
             const float sm = 0.5f * (s0 + s1);
-            // entry + sm d on the pairs: the high parts in one FMA, the
-            // remainders added
-            const float hx = fmaf(sm, hdx, hx0) + fmaf(sm, hdxl, hxl);
-            const float hy = fmaf(sm, hdy, hy0) + fmaf(sm, hdyl, hyl);
-            const float hz = fmaf(sm, hdz, hz0) + fmaf(sm, hdzl, hzl);
+            const float hx = fmaf(sm, hdx, hx0), hy = fmaf(sm, hdy, hy0), hz = fmaf(sm, hdz, hz0);
             empty = false;
             if (F.occ.mm) {
                 const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1),

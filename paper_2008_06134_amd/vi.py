@@ -278,21 +278,21 @@ class TF:
 
 
 def row_origin(dtype: int = VI_F32) -> int:
-    """Column of texel 0 in the row layout (the border texel -1 precedes it)."""
-    return 1
+    """Column of texel 0 in a row of the row layout (two border texels precede it)."""
+    return 2
 
 
 def row_pitch(res: int, dtype: int = VI_F32) -> int:
-    """Row pitch of the row layout: res + 4 rounded up to 4."""
-    return (res + 4 + 3) // 4 * 4
+    """Row pitch of the row layout: res + 4 (bfloat16: res + 6) rounded up to 4."""
+    return (res + (6 if dtype == VI_BF16 else 4) + 3) // 4 * 4
 
 
 @dataclass
 class Slices:
     """An attenuation stack: the device buffer and its descriptor.  Tiled:
     8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Rows:
-    n x (res+2) x P, texel (k, j, i) at [k, j+1, i+1] with a border of fully
-    transmitting texels around the res x res grid."""
+    (n+1) x (res+4) x P, texel (k, j, i) at [k+1, j+2, i+2]: a leading layer
+    and a two-texel border around the res x res grid, all fully transmitting."""
     data: torch.Tensor | None
     s: Slices_t
 
@@ -302,13 +302,14 @@ class Slices:
         t = self.data
         if self.s.layout == VI_STACK_ROWS:
             e = row_origin(self.s.dtype)
-            return t[:, 1:r + 1, e:e + r]
+            return t[1:, 2:r + 2, e:e + r]
         return t.permute(0, 1, 3, 2, 4).reshape(n, t.shape[1] * 4, t.shape[2] * 8)[:, :r, :r]
 
     def padded(self) -> torch.Tensor:
-        """Row layout only: n x (res+2) x (res+2), the grid with its border."""
+        """Row layout only: (n+1) x (res+4) x (res+4), the grid with its border
+        and the leading layer."""
         r, e = self.s.res, row_origin(self.s.dtype)
-        return self.data[:, :, e - 1:e + r + 1]
+        return self.data[:, :, e - 2:e + r + 2]
 
     @property
     def n(self):
@@ -381,7 +382,7 @@ def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda", layout: i
     """An uninitialised device buffer in a stack layout (shapes as in Slices)."""
     tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
     if layout == VI_STACK_ROWS:
-        return torch.empty((n, res + 2, row_pitch(res, dtype)), dtype=tdt, device=device)
+        return torch.empty((n + 1, res + 4, row_pitch(res, dtype)), dtype=tdt, device=device)
     r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
     return torch.empty((n, r4 // 4, r8 // 8, 4, 8), dtype=tdt, device=device)
 

@@ -379,8 +379,9 @@ def test_stack_is_camera_independent_and_deterministic():
 @pytest.mark.parametrize("res", [1, 6, 19, 64])
 @pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
 def test_row_layout_matches_its_definition(res, dtype):
-    """Row layout: the grid row-major with a one-texel border that transmits
-    fully (T = 1, optical depth 0); interior bit for bit equal to the tiled stack."""
+    """Row layout: the grid row-major with a two-texel border and a leading
+    layer that transmit fully (T = 1, optical depth 0); interior bit for bit
+    equal to the tiled stack."""
     raw = W.sphere_u8(30, radius=10, density=200, noise=30, seed=res)
     vol, tf = gpu_inputs(raw, W.tf_ramp())
     light, n = [0.3, -0.5, 0.8], 11
@@ -389,9 +390,9 @@ def test_row_layout_matches_its_definition(res, dtype):
     torch.cuda.synchronize()
     D = t.dense()
     ring = 1.0 if dtype == vi.VI_F32 else 0.0
-    want = torch.full((n, res + 2, res + 2), ring, dtype=D.dtype, device=DEV)
-    want[:, 1:res + 1, 1:res + 1] = D
-    assert r.data.shape == (n, res + 2, vi.row_pitch(res, dtype))
+    want = torch.full((n + 1, res + 4, res + 4), ring, dtype=D.dtype, device=DEV)
+    want[1:, 2:res + 2, 2:res + 2] = D
+    assert r.data.shape == (n + 1, res + 4, vi.row_pitch(res, dtype))
     assert torch.equal(r.padded(), want)
     assert torch.equal(r.dense(), D)
 
