@@ -98,9 +98,12 @@ vi::OccMap occ_of(const vi_volume* v)
     o.shift = v->minmax ? cell_shift(v->cell) : 0;
     o.nc = v->minmax ? ((uint32_t)v->n + (uint32_t)v->cell - 1) / (uint32_t)v->cell : 0;
     const uint32_t words = v->minmax ? (cells_of(v->n, v->cell) + 31u) / 32u : 0;
+    const uint32_t snc = (o.nc + 3u) / 4u, swords = v->minmax ? (snc * snc * snc + 31u) / 32u : 0;
     // bits that do not fit in LDS are not used: the map decides instead
-    o.bits = v->minmax && v->occ && words <= vi::kMaxLdsOccWords ? v->occ : nullptr;
+    o.bits = v->minmax && v->occ && words + swords <= vi::kMaxLdsOccWords ? v->occ : nullptr;
     o.words = o.bits ? words : 0;
+    o.snc = o.bits ? snc : 0;
+    o.swords = o.bits ? swords : 0;
     return o;
 }
 
@@ -351,7 +354,8 @@ size_t vi_volume_minmax_bytes(int n, int cell)
 size_t vi_volume_occupancy_bytes(int n, int cell)
 {
     if (n < 2 || (cell != 4 && cell != 8 && cell != 16 && cell != 32)) return 0;
-    return ((size_t)cells_of(n, cell) + 31) / 32 * 4;
+    const size_t nc = ((size_t)n + cell - 1) / cell, snc = (nc + 3) / 4;
+    return ((size_t)cells_of(n, cell) + 31) / 32 * 4 + (snc * snc * snc + 31) / 32 * 4;
 }
 
 int vi_volume_occupancy(const vi_volume* vol, const vi_tf* tf, uint32_t* d_bits, vi_volume* out,
@@ -364,8 +368,8 @@ int vi_volume_occupancy(const vi_volume* vol, const vi_tf* tf, uint32_t* d_bits,
     if (!vol->minmax) return fail(VI_E_INVALID_ARG, "the volume has no empty-space map");
     if (!d_bits || !out) return fail(VI_E_INVALID_ARG, "NULL bits or descriptor");
     if (((uintptr_t)d_bits) % 4) return fail(VI_E_INVALID_ARG, "bits pointer must be 4-byte aligned");
-    hipError_t e = vi::launch_occupancy(vol->minmax, cells_of(vol->n, vol->cell), tf->rgba, tf->n_entries, d_bits,
-                                        (hipStream_t)stream);
+    const uint32_t nc = ((uint32_t)vol->n + (uint32_t)vol->cell - 1u) / (uint32_t)vol->cell;
+    hipError_t e = vi::launch_occupancy(vol->minmax, nc, tf->rgba, tf->n_entries, d_bits, (hipStream_t)stream);
     if (e != hipSuccess) return fail(VI_E_DEVICE, "occupancy launch failed: %s", hipGetErrorString(e));
     *out = *vol;
     out->occ = d_bits;

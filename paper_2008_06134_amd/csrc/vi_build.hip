@@ -373,7 +373,7 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
     const uint32_t runs = ((uint32_t)p.res + kBuildNT * kBuildC - 1) / (kBuildNT * kBuildC);
     const dim3 grid(row_run_grid((uint32_t)p.res, runs));
     // (at least one word of bits: without them word 0 says "occupied")
-    const size_t lds = sizeof(float) * (size_t)p.K + sizeof(uint32_t) * std::max(p.occ.words, 1u);
+    const size_t lds = sizeof(float) * (size_t)p.K + sizeof(uint32_t) * std::max(p.occ.words + p.occ.swords, 1u);
     if (p.out_layout == VI_STACK_ROWS) {
         if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds, s);
         else launch_build_k<VT, LAYOUT, VI_STACK_ROWS, false>(p, grid, lds, s);

@@ -340,7 +340,7 @@ __device__ __forceinline__ bool occupancy_bit(const uint32_t* s_bits, uint32_t c
 __device__ __forceinline__ void stage_occupancy(const OccMap& o, uint32_t* s_bits)
 {
     if (o.bits)
-        for (uint32_t w = threadIdx.x; w < o.words; w += blockDim.x) s_bits[w] = o.bits[w];
+        for (uint32_t w = threadIdx.x; w < o.words + o.swords; w += blockDim.x) s_bits[w] = o.bits[w];
 }
 
 // Cell index of a trilinear footprint whose lower corner is voxel (x0,y0,z0)

@@ -27,14 +27,19 @@ constexpr int kQBits = 40;
 // Optional occupancy bits for the frame's transfer function: one bit per
 // cell (1 = may hold opacity), staged in LDS by every workgroup.  Used only
 // when they fit in kMaxLdsOccWords; larger maps are decided from mm.
+// Behind the cell bits lie the bits of the super-cells (4 x 4 x 4 cells):
+// set where any of their cells is set, so a ray in empty space can jump a
+// whole empty super-cell at once.
 struct OccMap {
     const float2* mm;   // nullptr: no skipping
     int shift;
     uint32_t nc;        // cells per axis
     const uint32_t* bits;  // nullptr: decide from mm and the transfer function
-    uint32_t words;        // 32-bit words of bits
+    uint32_t words;        // 32-bit words of cell bits (the super-cell bits follow)
+    uint32_t snc;          // super-cells per axis, ceil(nc / 4)
+    uint32_t swords;       // 32-bit words of super-cell bits
 };
-constexpr uint32_t kMaxLdsOccWords = 2048;  // 8 KiB of bits (65536 cells)
+constexpr uint32_t kMaxLdsOccWords = 2304;  // 9 KiB of bits (65536 cells and their super-cells)
 
 struct BuildParams {
     const void* vol;
@@ -145,7 +150,7 @@ hipError_t launch_to_bricks(const void* src, void* dst, int dtype, int N, hipStr
 hipError_t launch_to_quads(const void* src, void* dst, int dtype, int N, hipStream_t s);
 hipError_t launch_minmax(const void* vol, int dtype, int layout, uint32_t vsy, uint32_t vsz, int N, float scale,
                          int shift, float* out, hipStream_t s);
-hipError_t launch_occupancy(const float* minmax, uint32_t cells, const float* tf, int K, uint32_t* bits,
+hipError_t launch_occupancy(const float* minmax, uint32_t nc, const float* tf, int K, uint32_t* bits,
                             hipStream_t s);
 
 // Kernel variants beyond the public modes: for a point light the light grid

@@ -500,15 +500,18 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     // front of the next segment (kept as a product of exact per-segment
     // factors, which keeps its relative precision down to term_eps).
     float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
-    // Empty-space traversal: per-axis inverse step and cell edge.  A group whose
-    // G segments all lie in zero-opacity cells jumps to the last segment
-    // midpoint inside the cell of its last segment, by a margin of kEps voxels
-    // (far above the float position error), so no segment with non-zero
-    // opacity is ever skipped.
+    // Empty-space traversal.  A group whose G segments all lie in
+    // zero-opacity cells jumps to the last segment midpoint inside the empty
+    // box around its last segment -- the segment's cell, or the cell's
+    // super-cell (4 x 4 x 4 cells) when that is empty too -- with the box's
+    // faces moved inward by kEps voxels (far above the float position
+    // error), so no segment with non-zero opacity is ever skipped.  Faces of
+    // boxes at the volume's edge toward the outside are at infinity (edge
+    // cells also hold the clamped positions beyond the last voxel centre).
     const float kEps = 0.02f;
-    const float ihx = hdx != 0.f ? 1.0f / hdx : 0.f, ihy = hdy != 0.f ? 1.0f / hdy : 0.f,
-                ihz = hdz != 0.f ? 1.0f / hdz : 0.f;
-    const int B = 1 << F.occ.shift, last_c = (int)F.occ.nc - 1;
+    const float ihx = hdx != 0.f ? __builtin_amdgcn_rcpf(hdx) : 0.f, ihy = hdy != 0.f ? __builtin_amdgcn_rcpf(hdy) : 0.f,
+                ihz = hdz != 0.f ? __builtin_amdgcn_rcpf(hdz) : 0.f;
+    const float Mf = (float)F.M;
     uint32_t last_cell = 0xffffffffu;
     bool cell_is_empty = false;
     int k = 0, count = K;
@@ -517,7 +520,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         const bool in = kk < K;
         float om = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;  // om = 1 - alpha of the segment
         bool empty = true;
-        int jl = K;
+        int cx = 0, cy = 0, cz = 0;  // the segment's cell
         if (in) {
             const float s0 = (float)kk * dtf;
             const float s1 = fminf((float)(kk + 1) * dtf, Df);
@@ -529,30 +532,13 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                 const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1),
                           gy = clampi((int)floorf(hy) + F.M, 0, F.N - 1),
                           gz = clampi((int)floorf(hz) + F.M, 0, F.N - 1);
-                const int cx = gx >> F.occ.shift, cy = gy >> F.occ.shift, cz = gz >> F.occ.shift;
-                const uint32_t c = ((uint32_t)cz * F.occ.nc + (uint32_t)cy) * F.occ.nc + (uint32_t)cx;
+                cx = gx >> F.occ.shift, cy = gy >> F.occ.shift, cz = gz >> F.occ.shift;
+                const uint32_t c = __umul24(__umul24((uint32_t)cz, F.occ.nc) + (uint32_t)cy, F.occ.nc) + (uint32_t)cx;
                 if (c != last_cell) {
                     last_cell = c;
                     cell_is_empty = !cell_occupied(F.occ, s_bits, c, s_next, Km1, F.K);
                 }
                 empty = cell_is_empty;
-                if (empty) {
-                    // distance along the ray to the cell's faces moved inward by
-                    // kEps (faces of edge cells toward the outside are at infinity)
-                    float se = 3.4e38f;
-                    const float lox = (float)(cx * B - F.M) + kEps, hix = (float)((cx + 1) * B - F.M) - kEps;
-                    const float loy = (float)(cy * B - F.M) + kEps, hiy = (float)((cy + 1) * B - F.M) - kEps;
-                    const float loz = (float)(cz * B - F.M) + kEps, hiz = (float)((cz + 1) * B - F.M) - kEps;
-                    if (hdx > 0.f && cx < last_c) se = fminf(se, (hix - hx0) * ihx);
-                    if (hdx < 0.f && cx > 0) se = fminf(se, (lox - hx0) * ihx);
-                    if (hdy > 0.f && cy < last_c) se = fminf(se, (hiy - hy0) * ihy);
-                    if (hdy < 0.f && cy > 0) se = fminf(se, (loy - hy0) * ihy);
-                    if (hdz > 0.f && cz < last_c) se = fminf(se, (hiz - hz0) * ihz);
-                    if (hdz < 0.f && cz > 0) se = fminf(se, (loz - hz0) * ihz);
-                    // last full segment whose midpoint (j + 1/2) dt is <= se
-                    const float jf = floorf(se / dtf - 0.5f);
-                    jl = jf >= (float)(K - 1) ? K - 1 : (int)jf;
-                }
             }
             if (!empty) {
                 const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz);
@@ -616,7 +602,35 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
             // every segment of this step is empty (or past the exit): jump,
             // staying on multiples of G so that the steps group segments as a
             // march without the map would (the products then round alike and
-            // the map changes no bit of the result)
+            // the map changes no bit of the result).  Each lane finds the
+            // last segment inside the empty box around its own segment; the
+            // group takes its last lane's.
+            int jl = K;
+            if (in && F.occ.mm) {
+                int sh = F.occ.shift, bx = cx, by = cy, bz = cz, last = (int)F.occ.nc - 1;
+                if (F.occ.bits) {
+                    const int sx = cx >> 2, sy = cy >> 2, sz = cz >> 2;
+                    const uint32_t sc =
+                        __umul24(__umul24((uint32_t)sz, F.occ.snc) + (uint32_t)sy, F.occ.snc) + (uint32_t)sx;
+                    if (!occupancy_bit(s_bits + F.occ.words, sc)) {
+                        sh += 2;
+                        bx = sx, by = sy, bz = sz;
+                        last = (int)F.occ.snc - 1;
+                    }
+                }
+                // distance along the ray to the box's exit faces, moved inward
+                const float edge = (float)(1 << sh) - kEps;
+                float se = 3.4e38f;
+                if (hdx > 0.f && bx < last) se = fminf(se, ((float)(bx << sh) - Mf + edge - hx0) * ihx);
+                if (hdx < 0.f && bx > 0) se = fminf(se, ((float)(bx << sh) - Mf + kEps - hx0) * ihx);
+                if (hdy > 0.f && by < last) se = fminf(se, ((float)(by << sh) - Mf + edge - hy0) * ihy);
+                if (hdy < 0.f && by > 0) se = fminf(se, ((float)(by << sh) - Mf + kEps - hy0) * ihy);
+                if (hdz > 0.f && bz < last) se = fminf(se, ((float)(bz << sh) - Mf + edge - hz0) * ihz);
+                if (hdz < 0.f && bz > 0) se = fminf(se, ((float)(bz << sh) - Mf + kEps - hz0) * ihz);
+                // last full segment whose midpoint (j + 1/2) dt is <= se
+                const float jf = floorf(fmaf(se, F.idt, -0.5f));
+                jl = jf >= (float)(K - 1) ? K - 1 : (int)jf;
+            }
             const int jlast = G == 1 ? jl : __shfl(jl, gbase + G - 1);
             k = max(k + G, ((jlast + 1) / G) * G);
             if (k >= K) break;
@@ -861,7 +875,8 @@ template <typename VT, int LAYOUT, int SDT, int SL>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
     dim3 grid(supertile_grid((f.width + kBX - 1) / kBX, (f.height + kBY - 1) / kBY)), block(256);
-    const size_t lds = (sizeof(float4) + sizeof(int)) * (size_t)f.K + (f.occ.bits ? sizeof(uint32_t) * f.occ.words : 0);
+    const size_t lds =
+        (sizeof(float4) + sizeof(int)) * (size_t)f.K + (f.occ.bits ? sizeof(uint32_t) * (f.occ.words + f.occ.swords) : 0);
     switch (kernel_mode(f)) {
     case VI_MODE_NONE:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_NONE, SDT, SL>), grid, block, lds, s, f);

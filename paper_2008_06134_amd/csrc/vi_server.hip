@@ -152,7 +152,8 @@ public:
                                 r.d_rgba, r.d_samples, &h_frames[f]);
             if (rc != VI_OK) return rc;
             maxK = std::max(maxK, v.tf.n_entries);
-            if (h_frames[f].occ.bits) occ_words = std::max(occ_words, h_frames[f].occ.words);
+            if (h_frames[f].occ.bits)
+                occ_words = std::max(occ_words, h_frames[f].occ.words + h_frames[f].occ.swords);
         }
         // tiles grouped by kernel mode (stable), one kernel per mode present
         constexpr int kModes = kKernelModes;

@@ -286,8 +286,9 @@ def test_volume_bytes_and_brick_validation():
 
 def test_occupancy_validation():
     lib = vi.lib()
-    assert lib.vi_volume_occupancy_bytes(512, 16) == 32 ** 3 // 32 * 4
-    assert lib.vi_volume_occupancy_bytes(33, 8) == (5 ** 3 + 31) // 32 * 4
+    # cell bits, then the bits of the 4 x 4 x 4-cell super-cells
+    assert lib.vi_volume_occupancy_bytes(512, 16) == 32 ** 3 // 32 * 4 + 8 ** 3 // 32 * 4
+    assert lib.vi_volume_occupancy_bytes(33, 8) == (5 ** 3 + 31) // 32 * 4 + 4
     assert lib.vi_volume_occupancy_bytes(33, 5) == 0 and lib.vi_volume_occupancy_bytes(1, 8) == 0
     f = _Fake()
     out = vi.Volume_t()

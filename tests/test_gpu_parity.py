@@ -521,6 +521,19 @@ def test_occupancy_bits_match_their_definition(cell):
     want = _occupancy_reference(mm, tab)
     assert np.array_equal(bits, want)
     assert want.any()
+    # super-cells: 4 x 4 x 4 cells each, set where any of their cells is
+    nc = -(-48 // cell)
+    snc = -(-nc // 4)
+    ncw = -(-mm.shape[0] // 32)
+    sw = words[ncw:]
+    sbits = ((sw[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).reshape(-1)[:snc ** 3].astype(bool)
+    cells = want.reshape(nc, nc, nc)  # z, y, x
+    swant = np.zeros((snc, snc, snc), dtype=bool)
+    for Z in range(snc):
+        for Y in range(snc):
+            for X in range(snc):
+                swant[Z, Y, X] = cells[4 * Z:4 * Z + 4, 4 * Y:4 * Y + 4, 4 * X:4 * X + 4].any()
+    assert np.array_equal(sbits, swant.reshape(-1))
     if cell <= 8:                                  # 27 cells of 16^3 are all occupied here
         assert not want.all()
 
