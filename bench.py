@@ -25,28 +25,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# HBM bytes per launch of a kernel, from two rocprofv3 --pmc runs of this bench
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
-# counters read for a plain 1 GiB device copy (bench.py --copy-probe 1024:
-# FETCH_SIZE reads half the bytes copied, WRITE_SIZE all of them).  Each entry
-# holds the sha256 of the sources the kernel is built from at the time the
-# counters were taken; once those sources change the entry no longer applies
-# and the bench reports traffic as null.  Commands and raw figures: profiles/.
+# Hardware counters of a kernel on a workload, from rocprofv3 --pmc runs of
+# this bench (one counter set per run; commands and raw figures: profiles/).
+# HBM bytes per launch are FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+# scaled by what the same counters read for a plain 1 GiB device copy (bench.py
+# --copy-probe 1024: FETCH_SIZE reads half the bytes copied, WRITE_SIZE all of
+# them).  valu_insts (SQ_INSTS_VALU, wave instructions) and gui_cycles
+# (GRBM_GUI_ACTIVE summed over the 8 XCDs) give the VALU issue fraction: a
+# wave64 instruction occupies one of the 1024 SIMDs for 4 cycles (16 lanes per
+# cycle; packed FP32 is not used).  ta_busy (TA_TA_BUSY_sum over the 256
+# address units) gives the vector-memory address unit's busy fraction.  Each
+# entry holds the sha256 of the sources the kernel is built from when the
+# counters were taken; once those change the entry no longer applies and the
+# bench reports the figures as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+N_SIMDS, N_TAS, N_XCDS = 1024, 256, 8
 KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
                   "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
-MEASURED_TRAFFIC = {
+MEASURED = {
     # large workload (512^3 u16 in the quad layout, 16^3 empty-space cells with occupancy bits, 512 x
-    # 1024^2 f32 stack in rows, 1920x1080), light 0
-    ("render_cone", "large", "rows", 16, "quads"): {
-        "sha256": "8a5108c8d0916c75c0f61051da9ff4414132c58cfe7f2e9c12abc5117ab272bd",
-        "fetch_kib": 124401.62, "write_kib": 34834.91},
-    ("render_shell", "large", "rows", 16, "quads"): {
-        "sha256": "8a5108c8d0916c75c0f61051da9ff4414132c58cfe7f2e9c12abc5117ab272bd",
-        "fetch_kib": 113958.81, "write_kib": 34822.78},
-    ("build", "large", "rows", 16, "quads"): {       # build kernel plus the border kernel
-        "sha256": "531e58676c8192bae79444b29bd3e670583aa1cbdf958e8503bf22bac7ea830b",
-        "fetch_kib": 202240.88 + 12.5, "write_kib": 2262386.47 + 28953.56},
+    # 1024^2 f32 stack in rows, 1920x1080), lights 0..2 (bench --steps 2 --warmup 1)
 }
 
 
@@ -59,24 +57,56 @@ def source_sha(kind: str) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, layout: str, cell: int, vol_layout: str):
-    """HBM bytes per launch of `kernel` on `workload`, or None (not measured for these sources)."""
-    m = MEASURED_TRAFFIC.get((kernel, workload, layout, cell, vol_layout))
+def measured(kernel: str, workload: str, layout: str, cell: int, vol_layout: str):
+    """Recorded counters of `kernel` on `workload` for the current sources, or None."""
+    m = MEASURED.get((kernel, workload, layout, cell, vol_layout))
     kind = "build" if kernel == "build" else "render"
     if not m or m["sha256"] != source_sha(kind):
         return None
+    return m
+
+
+def traffic_bytes(m) -> int | None:
+    if not m:
+        return None
     return int(m["fetch_kib"] * 1024 * FETCH_SCALE + m["write_kib"] * 1024 * WRITE_SCALE)
+
+
+# Algorithmic FP32 operations of the method per composited segment (one with
+# non-zero opacity; an FMA counts 2): its position (6), the trilinear fetch
+# (8 normalisations, 7 lerps: 29), the transfer function (14), the Eq. 6
+# opacity correction (4), the emission (21) and the front-to-back update (9)
+# = 83, plus the coefficient gather: the sample's light-grid coordinates (6)
+# and per tap its offset and a depth-linear bilinear lookup (24 for a shell
+# or the shadow tap, 32 for a ring-cone tap, 30 for a lattice tap) and its
+# weighting.  Skipped segments cost no arithmetic of the method.
+FLOPS_PER_SAMPLE = {"none": 83, "shadow": 83 + 6 + 24, "shell": 83 + 6 + 6 * 24 + 12,
+                    "cone": 83 + 6 + 8 * 32 + 9, "cone5": 83 + 6 + 25 * 30 + 26, "phong": 83 + 6 * 29 + 40}
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32, published (packed FP32; 78.6 without packing)
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, raw, tab, light, cam, modes, opts, stride, nthreads=0):
     """The FP64 oracle timed on the host cores on one step of the same workload:
     the full attenuation build, then the step's frames on a stratified pixel
     sample (every `stride`-th row and column); the frame time is scaled up by
-    the sampled fraction.  Rate = step samples / step time."""
+    the sampled fraction.  Rate = step samples / step time.  Beside it, one
+    thread on the small workload (its whole step) and on a sample of the
+    medium one."""
     from oracle import oracle as O
     ovol, otf = O.Volume(raw), O.TF(tab)
     Wd, Hd = cam["width"], cam["height"]
@@ -97,11 +127,45 @@ def cpu_baseline(w, raw, tab, light, cam, modes, opts, stride, nthreads=0):
     t_render = time.perf_counter() - t0
     step_time = t_build + t_render / frac
     return {"value": round(samples / frac / step_time, 1), "unit": "samples/s", "cores": O.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": (f"light 0 of the large workload: full FP64 build of {w.res}^2 columns x {w.n_slices} slabs "
-                       f"in {t_build:.1f} s, then the {'+'.join(modes)} frames on {pix.size} of {Wd * Hd} pixels "
-                       f"(every {stride}th row and column, {samples} samples) in {t_render:.1f} s; the frame time "
-                       f"is scaled by 1/{frac:.3f}: {step_time:.1f} s per step")}
+                       f"in {t_build * 1e3:.0f} ms, then the {'+'.join(modes)} frames on {pix.size} of {Wd * Hd} "
+                       f"pixels (every {stride}th row and column, {samples} samples) in {t_render * 1e3:.0f} ms; "
+                       f"the frame time is scaled by 1/{frac:.3f}: {step_time * 1e3:.0f} ms per step"),
+            "build_ms": round(t_build * 1e3, 1), "frames_ms_sampled": round(t_render * 1e3, 1),
+            "single_thread": single_thread_baselines()}
+
+
+def single_thread_baselines():
+    """The oracle on one thread: the small workload's whole step (build + shell
+    frame, 256^2) and the medium workload's build plus its cone 5x5 frame on
+    every 8th row and column (scaled up)."""
+    from oracle import oracle as O
+    from paper_2008_06134_amd import workloads as W
+    out = {}
+    for name, stride in (("small", 1), ("medium", 8)):
+        w = W.WORKLOADS[name]
+        raw, tab = w.volume(), w.tf()
+        ovol, otf = O.Volume(raw), O.TF(tab)
+        cam = w.camera()
+        Wd, Hd = cam["width"], cam["height"]
+        ys, xs = np.meshgrid(np.arange(stride // 2, Hd, stride), np.arange(stride // 2, Wd, stride), indexing="ij")
+        pix = (ys * Wd + xs).ravel().astype(np.int64)
+        frac = pix.size / (Wd * Hd)
+        st = O.Stack(ovol, otf, w.lights()[0], w.n_slices, w.res)
+        t0 = time.perf_counter()
+        st.fill(1)
+        tb = time.perf_counter() - t0
+        mode = w.modes[0]
+        t0 = time.perf_counter()
+        _, _, nt, _ = O.render(ovol, otf, st, cam, mode, w.step_vox, w.opts, pixels=pix, want_full=False, nthreads=1)
+        tr = time.perf_counter() - t0
+        n = int(nt.sum()) / frac
+        step = tb + tr / frac
+        out[name] = {"build_ms": round(tb * 1e3, 1), "frame_ms": round(tr / frac * 1e3, 1),
+                     "samples_per_s": round(n / step, 1),
+                     "frame_sample": f"{pix.size} of {Wd * Hd} pixels" + ("" if stride == 1 else ", scaled")}
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -216,19 +280,22 @@ def serving_capacity(vols, vol_sizes, budget, count=200, seed=99):
     return sequential(vols, reqs, budget)["frames_per_s"]
 
 
-def serving_quick(dev, budget=16 << 30, count=300):
-    """The default bench's serving leg: 8 resident volumes 128^3-320^3, Poisson
-    arrivals at 0.9x the sequential capacity."""
+def serving_quick(dev, budget=24 << 30, count=300):
+    """The default bench's serving leg, on inputs of the serving configuration:
+    8 resident u16 phantoms 128^3-512^3 with vessels, images 512^2-1920x1080,
+    shell/cone 50/50, lights changing every 1-10 frames; Poisson arrivals at
+    0.9x and 1.2x the sequential capacity, against sequential plain renders."""
     from paper_2008_06134_amd import workloads as W
-    sizes = [128, 192, 256, 320, 128, 192, 256, 320]
-    vols = serving_inputs(sizes, dev, vessels=False)
+    sizes = [128, 192, 256, 320, 384, 448, 512, 256]
+    vols = serving_inputs(sizes, dev, vessels=True)
     cap = serving_capacity(vols, sizes, budget)
-    rate = 0.9 * cap
-    reqs = W.serving_requests(count, sizes, rate, seed=5)
-    serve(vols, reqs[:30], budget)                 # warm-up
-    out = {"volumes": "8 resident u16 phantoms 128^3-320^3 (quad layout + empty-space map + occupancy bits)",
-           "requests": count, "rate_hz": round(rate, 2), "sequential_capacity_fps": cap,
-           "served": serve(vols, reqs, budget), "sequential": sequential(vols, reqs, budget)}
+    out = {"volumes": "8 resident u16 phantoms 128^3-512^3 with vessels (quad layout + empty-space map + "
+                      "occupancy bits)", "requests_per_rate": count, "sequential_capacity_fps": cap, "rates": []}
+    for f in (0.9, 1.2):
+        reqs = W.serving_requests(count, sizes, f * cap, seed=5 + int(10 * f))
+        serve(vols, reqs[:30], budget)                 # warm-up
+        out["rates"].append({"rate_x": f, "rate_hz": round(f * cap, 2), "served": serve(vols, reqs, budget),
+                             "sequential": sequential(vols, reqs, budget)})
     return out
 
 
@@ -316,7 +383,7 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     stack = vi.stack_buffer(w.n_slices, w.res, stack_dtype, dev, STACK_LAYOUT)
     cam0 = w.camera(0)
     imgs = {m: torch.empty((cam0["height"], cam0["width"], 4), dtype=torch.float32, device=dev) for m in modes}
-    counters = {m: torch.zeros(1, dtype=torch.int64, device=dev) for m in modes}
+    counters = {m: torch.zeros(2, dtype=torch.int64, device=dev) for m in modes}
 
     def mode_args(m):
         return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
@@ -360,7 +427,8 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     wall = time.perf_counter() - t_start
     out = {"build_ms": [e[0].elapsed_time(e[1]) for e in evs],
            "render_ms": {m: [e[1 + k].elapsed_time(e[2 + k]) for e in evs] for k, m in enumerate(modes)},
-           "samples": {m: int(counters[m].item()) for m in modes}, "wall": wall, "prep_ms": prep_ms,
+           "samples": {m: int(counters[m][0].item()) for m in modes},
+           "opaque": {m: int(counters[m][1].item()) for m in modes}, "wall": wall, "prep_ms": prep_ms,
            "vol_bytes": raw.nbytes}
     del vol, stack, imgs
     torch.cuda.empty_cache()
@@ -461,29 +529,69 @@ def main():
     total_samples = sum(samples.values())
     frames = args.steps * len(modes)
 
-    # roofline of the dominant kernel, algorithmic (compulsory) bytes per launch
+    # Roofline of the dominant kernel (the most time per step).  A frame is
+    # bound by vector-ALU instruction issue (the counters put its VALU issue
+    # near the SIMDs' capacity while HBM moves a fraction of the compulsory
+    # bytes), so its roof is the FP32 ALU: achieved = the method's algorithmic
+    # FP32 operations per launch (FLOPS_PER_SAMPLE x composited segments) over
+    # the launch's mean HIP-event time.  The HBM view (compulsory bytes, and
+    # the bytes the counters saw) and the counters' VALU-issue and
+    # address-unit fractions stand beside it.  The build is a write stream:
+    # its roof is HBM.
     vol_bytes = m["vol_bytes"]
     stack_bytes = w.n_slices * w.res * w.res * (2 if precision else 4)
     img_bytes = Wd * Hd * 16
+    opaque = m["opaque"]
     totals = {"build": sum(build_ms), **{f"render_{k}": sum(v) for k, v in render_ms.items()}}
     dom = max(totals, key=totals.get)
+    rec = None if (args.point_light or args.no_occupancy) else \
+        measured(dom, w.name, args.stack_layout, args.cell, args.volume_layout)
+
+    def counter_fracs(r, ms):
+        if not r:
+            return None, None
+        cycles = r["gui_cycles"] / N_XCDS  # per XCD = per SIMD
+        return (round(r["valu_insts"] * 4.0 / (N_SIMDS * cycles), 4),
+                round(r["ta_busy"] / (N_TAS * cycles), 4))
+
     if dom == "build":
-        per_launch, avg_ms = vol_bytes + stack_bytes, np.mean(build_ms)
+        per_launch, avg_ms = vol_bytes + stack_bytes, float(np.mean(build_ms))
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        tb = traffic_bytes(rec)
+        roofline = {"bound": "hbm", "kernel": "build", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": tb,
+                    "bytes_per_launch": per_launch, "avg_launch_ms": round(avg_ms, 4)}
     else:
-        per_launch, avg_ms = vol_bytes + stack_bytes + img_bytes, np.mean(render_ms[dom[len("render_"):]])
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": None if (args.point_light or args.no_occupancy) else
-                measured_traffic(dom, w.name, args.stack_layout, args.cell, args.volume_layout),
-                "bytes_per_launch": per_launch, "avg_launch_ms": round(float(avg_ms), 4)}
+        mode = dom[len("render_"):]
+        avg_ms = float(np.mean(render_ms[mode]))
+        flops = FLOPS_PER_SAMPLE[mode] * opaque[mode] / args.steps
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        tb = traffic_bytes(rec)
+        valu, ta = counter_fracs(rec, avg_ms)
+        ideal = vol_bytes + stack_bytes + img_bytes
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": tb,
+                    "flops_per_launch": int(flops), "flops_per_composited_segment": FLOPS_PER_SAMPLE[mode],
+                    "avg_launch_ms": round(avg_ms, 4),
+                    "valu_issue_frac": valu, "address_unit_busy_frac": ta,
+                    "hbm": {"compulsory_bytes": ideal,
+                            "compulsory_gbs": round(ideal / (avg_ms * 1e-3) / 1e9, 2),
+                            "compulsory_frac": round(ideal / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                            "measured_gbs": None if tb is None else round(tb / (avg_ms * 1e-3) / 1e9, 2)}}
+    build_ms_mean = float(np.mean(build_ms))
+    brec = None if (args.point_light or args.no_occupancy) else \
+        measured("build", w.name, args.stack_layout, args.cell, args.volume_layout)
+    btb = traffic_bytes(brec)
     kernels = {"volume_prepare_ms_once": round(m["prep_ms"], 3),
-               "build_ms_mean": round(float(np.mean(build_ms)), 4),
-               "build_hbm_frac": round((vol_bytes + stack_bytes) / (np.mean(build_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+               "build_ms_mean": round(build_ms_mean, 4),
+               "build_hbm_frac": round((vol_bytes + stack_bytes) / (build_ms_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "build_hbm_measured_gbs": None if btb is None else round(btb / (build_ms_mean * 1e-3) / 1e9, 2)}
     for k, v in render_ms.items():
         kernels[f"render_{k}_ms_mean"] = round(float(np.mean(v)), 4)
         kernels[f"render_{k}_samples_per_frame"] = samples[k] // args.steps
+        kernels[f"render_{k}_composited_per_frame"] = opaque[k] // args.steps
         kernels[f"render_{k}_samples_per_s"] = round(samples[k] / (sum(v) * 1e-3), 1)
+        kernels[f"render_{k}_composited_per_s"] = round(opaque[k] / (sum(v) * 1e-3), 1)
     # spread of the per-launch HIP-event times (each step renders a different light and camera)
     kernels["ms_p10_p50_p90"] = {name: [round(float(x), 4) for x in np.percentile(v, [10, 50, 90])]
                                  for name, v in [("build", build_ms)] + [(f"render_{k}", v)
@@ -492,6 +600,7 @@ def main():
     result = {
         "metric": "ray samples/s (build + shell + cone frames per light direction), 512^3 1080p",
         "value": round(total_samples / wall, 1),
+        "composited_samples_per_s": round(sum(m["opaque"].values()) / wall, 1),
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,

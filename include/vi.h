@@ -239,6 +239,9 @@ typedef struct {
     float phong_ks;        /* 0.4 */
     float phong_shininess; /* 20  */
     float grad_eps;        /* 0.02 */
+    int samples_opaque;    /* 0: d_samples of vi_render is one counter; 1: two, [0] as
+                              described there and [1] the segments composited with
+                              non-zero opacity (those whose coefficient is gathered) */
 } vi_render_opts;
 
 /* Library version string. */
@@ -341,7 +344,10 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
  * VI_MODE_CONE needs a directional light (VI_E_UNSUPPORTED for a point
  * light's stack: its cone axis and ring offsets assume one direction).
  * If `d_samples` (device) is non-NULL the number of segments composited
- * (stopping at termination) is ADDED to it.
+ * (stopping at termination; segments that empty-space skipping steps over
+ * count too) is ADDED to d_samples[0]; with opts->samples_opaque = 1 the
+ * number of those segments whose opacity is non-zero is added to
+ * d_samples[1] as well.
  * Errors: VI_E_INVALID_ARG for NULL/misaligned pointers, bad sizes, a
  * descriptor whose vol_n differs from the volume or whose non-zero tag
  * names another (volume, transfer function); VI_E_UNSUPPORTED for dtypes

@@ -134,7 +134,8 @@ struct RenderFrame {
     float cone_cos[16], cone_sin[16];
     // output
     float4* out;
-    unsigned long long* samples;
+    unsigned long long* samples;  // [0] segments marched, [1] (count_opaque) segments composited with alpha > 0
+    int count_opaque;
 };
 
 // launchers (vi_build.hip / vi_render.hip / vi_layout.hip)

@@ -357,7 +357,7 @@ __device__ __forceinline__ uint32_t group_bits(bool p, int base)
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL, int G>
 __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf,
                                              const int* __restrict__ s_next, const uint32_t* __restrict__ s_bits,
-                                             int px, int py, uint32_t& nsamp)
+                                             int px, int py, uint32_t& nsamp, uint32_t& nop)
 {
     const int lane = threadIdx.x & 63, g = lane % G, gbase = lane - g;
     // ---- camera ray, in offset-voxel coordinates, in float pairs (the
@@ -645,6 +645,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         const uint32_t tb_ = group_bits<G>(in && T * incl <= F.term_eps, gbase);
         const int gs = tb_ ? __ffs(tb_) - 1 : G;                     // terminating segment, G if none
         const float keep = (g <= gs) ? T * excl : 0.0f;
+        nop += (in && g <= gs && om < 1.0f) ? 1u : 0u;  // composited with non-zero opacity
         Cr += group_sum<G>(keep * cr);
         Cg += group_sum<G>(keep * cg);
         Cb += group_sum<G>(keep * cb);
@@ -691,16 +692,20 @@ template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
 __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* s_tf, const int* s_next,
                                             const uint32_t* s_bits, int px, int py)
 {
-    uint32_t ns = 0;
+    uint32_t ns = 0, nop = 0;
     const int lane = threadIdx.x & 63;
     if (px < F.width && py < F.height) {
-        const float4 c = render_ray<VT, LAYOUT, MODE, SDT, SL, kG>(F, s_tf, s_next, s_bits, px, py, ns);
+        const float4 c = render_ray<VT, LAYOUT, MODE, SDT, SL, kG>(F, s_tf, s_next, s_bits, px, py, ns, nop);
         if (lane % kG == 0) F.out[(size_t)py * F.width + px] = c;
     }
     if (F.samples) {
-        // wave sum, one atomic per wave
-        for (int off = 32; off > 0; off >>= 1) ns += __shfl_xor(ns, off);
+        // wave sums, one atomic per wave and counter
+        for (int off = 32; off > 0; off >>= 1) {
+            ns += __shfl_xor(ns, off);
+            nop += __shfl_xor(nop, off);
+        }
         if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
+        if (lane == 0 && nop && F.count_opaque) atomicAdd(F.samples + 1, (unsigned long long)nop);
     }
 }
 

@@ -76,7 +76,7 @@ class RenderOpts_t(C.Structure):
                 ("shell_h_vox", C.c_float),
                 ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_float),
                 ("phong_ka", C.c_float), ("phong_kd", C.c_float), ("phong_ks", C.c_float),
-                ("phong_shininess", C.c_float), ("grad_eps", C.c_float)]
+                ("phong_shininess", C.c_float), ("grad_eps", C.c_float), ("samples_opaque", C.c_int)]
 
 
 class ServerCfg_t(C.Structure):
@@ -345,7 +345,7 @@ def default_opts() -> dict:
             "shell_count": o.shell_count, "shell_w": list(o.shell_w), "shell_h_vox": o.shell_h_vox,
             "cone_rings": o.cone_rings,
             "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan,
-            **{k: getattr(o, k) for k in _PHONG_KEYS}}
+            **{k: getattr(o, k) for k in _PHONG_KEYS}, "samples_opaque": o.samples_opaque}
 
 
 def render_opts(opts: dict | None) -> RenderOpts_t:
@@ -367,6 +367,7 @@ def render_opts(opts: dict | None) -> RenderOpts_t:
     o.cone_tan = d["cone_tan"]
     for k in _PHONG_KEYS:
         setattr(o, k, float(d[k]))
+    o.samples_opaque = int(d["samples_opaque"])
     return o
 
 
@@ -425,7 +426,8 @@ def render(vol: Volume, tf: TF, slices: Slices | None, cam: dict, mode: str, ste
            stream=None) -> torch.Tensor:
     """Ray-cast one frame (sections 3.2.2-3.2.3, 4); returns H x W x 4 float32
     premultiplied RGBA.  Mode "phong" needs only the light frame of `slices`
-    (``light_frame(...)`` serves).  `samples` (int64 device tensor of one element) gets the
+    (``light_frame(...)`` serves).  `samples` (int64 device tensor of one element, or two: the
+    second then gets the segments composited with non-zero opacity) gets the
     number of composited segments added to it."""
     W, H = int(cam["width"]), int(cam["height"])
     if out is None:
@@ -433,6 +435,8 @@ def render(vol: Volume, tf: TF, slices: Slices | None, cam: dict, mode: str, ste
     if out.numel() < W * H * 4 or out.dtype != torch.float32 or not out.is_contiguous():
         raise ValueError("output must be a contiguous float32 tensor of H*W*4 elements")
     o = render_opts(opts)
+    if samples is not None and samples.numel() >= 2:
+        o.samples_opaque = 1
     sp = C.byref(slices.s) if slices is not None else None
     _check(lib().vi_render(C.byref(vol.s), C.byref(tf.s), sp, C.byref(camera(cam)), MODES[mode],
                            C.c_float(step_vox), C.byref(o), C.c_void_p(out.data_ptr()),

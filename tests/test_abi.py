@@ -349,6 +349,12 @@ def test_tf_identity_is_its_contents():
     # bits with one table and has them refused with a rewritten one)
 
 
+def test_samples_opaque_flag_validated():
+    f = _Fake()
+    assert _render(f, _desc(f), mode=2, opts={"samples_opaque": 2}) == -1
+    assert "samples_opaque" in vi.lib().vi_last_error().decode()
+
+
 def test_step_bound_keeps_segments_below_2_24():
     """step_vox so small that a chord of sqrt(3) N voxels would hold more than
     2^24 segments is refused before any launch."""

@@ -80,6 +80,14 @@ def test_small_full_image(mode):
         report(f"small {mode} ({LNAME[lay]})", err)
         assert err <= TOL_IMG
         assert abs(ns - nt.sum()) <= 1e-3 * nt.sum() + 16
+        # the second counter: segments composited with non-zero opacity (a
+        # subset of those marched; the same count again in the same launch)
+        cnt = torch.zeros(2, dtype=torch.int64, device=DEV)
+        img2 = vi.render(vol, tf, st, cam, m, w.step_vox, opts, samples=cnt)
+        torch.cuda.synchronize()
+        n2, nop = int(cnt[0].item()), int(cnt[1].item())
+        assert n2 == ns and 0 < nop <= n2
+        assert torch.equal(img2.cpu().double(), torch.from_numpy(img))
 
 
 # ---------------------------------------------------------------- medium / large, sampled
