@@ -106,6 +106,8 @@ def _load():
         lib.vio_cube_hit.argtypes = [P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)]
         lib.vio_coefficient.argtypes = [C.c_void_p, C.c_int, P(_Opts), C.c_int, P(C.c_double), P(C.c_double)]
         lib.vio_coefficient.restype = C.c_double
+        lib.vio_cone_taps.argtypes = [C.c_void_p, P(_Opts), P(C.c_double), P(C.c_double), P(C.c_double)]
+        lib.vio_cone_taps.restype = C.c_int
         lib.vio_gradient.argtypes = [P(_Volume), P(C.c_double), P(C.c_double)]
         lib.vio_phong.argtypes = [P(_Volume), P(_Opts), P(C.c_double), P(C.c_double), P(C.c_double),
                                   P(C.c_double), P(C.c_double)]
@@ -266,6 +268,13 @@ class Stack:
     def coefficient(self, mode: str, p, d, opts: dict | None = None) -> float:
         o = _opts(opts)
         return _load().vio_coefficient(self._p, MODES[mode], C.byref(o), self.vol.N, _vec(p), _vec(d))
+
+    def cone_taps(self, p, d, opts: dict | None = None) -> np.ndarray:
+        """World positions of the cone's taps at sample p for view direction d."""
+        o = _opts(opts)
+        out = np.zeros((128, 3))
+        n = _load().vio_cone_taps(self._p, C.byref(o), _vec(p), _vec(d), _dptr(out))
+        return out[:n].copy()
 
 
 def _camera(cam: dict) -> _Camera:

@@ -432,7 +432,6 @@ double vio_stack_lookup(vio_stack* s, const double p[3])
 /* ------------------------------------------------------------------ */
 double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N, const double p[3], const double d[3])
 {
-    const vio_frame* f = &s->f;
     if (mode == VIO_MODE_NONE) return 1.0;
     if (mode == VIO_MODE_SHADOW) return vio_stack_lookup(s, p);
 
@@ -458,52 +457,76 @@ double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N, const d
         return num / wsum;
     }
 
-    /* Cone: B_proj lies in the plane of sample, light and viewer: the
-     * direction toward the viewer with its component along L removed
-     * (reading R14); fall back to U when the view is parallel to L. */
+    double taps[VIO_MAX_CONE_TAPS][3];
+    int nt = vio_cone_taps(s, o, p, d, taps);
+    if (nt == 0) return 1.0;
+    double sum = 0.0;
+    for (int t = 0; t < nt; ++t) sum += vio_stack_lookup(s, taps[t]);
+    return sum / nt;
+}
+
+/* Cone tap positions at sample p viewed along d (section 3.2.3, Eq. 11).
+ * The light at p travels along L_s: the stack's direction L for a
+ * directional light; for a point light (reading R39) the direction from the
+ * light to p, L_s = (p - P)/|p - P|.  B_proj lies in the plane of sample,
+ * light and viewer: the direction toward the viewer with its component
+ * along L_s removed (reading R14); when the view runs along L_s it is U with
+ * its L_s component removed.  Ring m lies toward the light along L_s, at the
+ * point t_m whose depth is m slabs less than p's: t_m = m ds / (L . L_s)
+ * (= m ds for a directional light); its radius is t_m tan(phi), its axis
+ * B_proj rotated about L_s by theta (Rodrigues, Eq. 11).  The lattice form
+ * (R15) puts G x G points one slab toward the light, spacing t_1 tan(phi)/2
+ * in the (B_proj, L_s x B_proj) plane.  Returns the tap count. */
+int vio_cone_taps(vio_stack* s, const vio_opts* o, const double p[3], const double d[3],
+                  double taps[][3])
+{
+    const vio_frame* f = &s->f;
+    double Ls[3] = {f->L[0], f->L[1], f->L[2]};
+    if (f->positional) {
+        double r[3] = {p[0] - f->P[0], p[1] - f->P[1], p[2] - f->P[2]};
+        double nr = norm3(r);
+        for (int a = 0; a < 3; ++a) Ls[a] = r[a] / nr;
+    }
+    /* t_1: one slab toward the light along L_s */
+    double step = f->positional ? f->ds / dot3(f->L, Ls) : f->ds;
     double wv[3] = {-d[0], -d[1], -d[2]};
-    double wl = dot3(wv, f->L);
-    double B[3] = {wv[0] - wl * f->L[0], wv[1] - wl * f->L[1], wv[2] - wl * f->L[2]};
+    double wl = dot3(wv, Ls);
+    double B[3] = {wv[0] - wl * Ls[0], wv[1] - wl * Ls[1], wv[2] - wl * Ls[2]};
     double nb = norm3(B);
     if (nb < 1e-6) {
-        for (int a = 0; a < 3; ++a) B[a] = f->U[a];
-    } else {
-        for (int a = 0; a < 3; ++a) B[a] /= nb;
+        double ul = dot3(f->U, Ls);
+        for (int a = 0; a < 3; ++a) B[a] = f->U[a] - ul * Ls[a];
+        nb = norm3(B);
     }
+    for (int a = 0; a < 3; ++a) B[a] /= nb;
     double LxB[3];
-    cross3(f->L, B, LxB);
-    double LdotB = dot3(f->L, B);
-    double sum = 0.0;
-    int taps = 0;
+    cross3(Ls, B, LxB);
+    double LdotB = dot3(Ls, B);
+    int nt = 0;
     if (o->cone_grid <= 0) {
-        /* Rings at distance c_m = m ds toward the light with radius
-         * r_m = c_m tan(phi); on each ring the axis A_proj is B_proj rotated
-         * about L by theta (Rodrigues, Eq. 11). */
+        if (o->cone_rings * o->cone_angles > VIO_MAX_CONE_TAPS) return 0;
         for (int m = 1; m <= o->cone_rings; ++m) {
-            double cm = m * f->ds, rm = cm * o->cone_tan;
+            double cm = m * step, rm = cm * o->cone_tan;
             for (int qa = 0; qa < o->cone_angles; ++qa) {
                 double th = 2.0 * VIO_PI * qa / o->cone_angles;
-                double ct = cos(th), st = sin(th), Ap[3], q[3];
-                for (int a = 0; a < 3; ++a) Ap[a] = B[a] * ct + LxB[a] * st + LdotB * f->L[a] * (1.0 - ct);
-                for (int a = 0; a < 3; ++a) q[a] = p[a] - cm * f->L[a] + rm * Ap[a];
-                sum += vio_stack_lookup(s, q);
-                ++taps;
+                double ct = cos(th), st = sin(th), Ap[3];
+                for (int a = 0; a < 3; ++a) Ap[a] = B[a] * ct + LxB[a] * st + LdotB * Ls[a] * (1.0 - ct);
+                for (int a = 0; a < 3; ++a) taps[nt][a] = p[a] - cm * Ls[a] + rm * Ap[a];
+                ++nt;
             }
         }
     } else {
-        /* Lattice form (reading R15): G x G points one slab toward the
-         * light, spacing rho = ds tan(phi) / 2 in the (B, L x B) plane. */
         int G = o->cone_grid;
-        double rho = f->ds * o->cone_tan / 2.0, half = (G - 1) / 2.0;
+        if (G * G > VIO_MAX_CONE_TAPS) return 0;
+        double rho = step * o->cone_tan / 2.0, half = (G - 1) / 2.0;
         for (int ia = 0; ia < G; ++ia)
             for (int ib = 0; ib < G; ++ib) {
-                double a_ = ia - half, b_ = ib - half, q[3];
-                for (int a = 0; a < 3; ++a) q[a] = p[a] - f->ds * f->L[a] + a_ * rho * B[a] + b_ * rho * LxB[a];
-                sum += vio_stack_lookup(s, q);
-                ++taps;
+                double a_ = ia - half, b_ = ib - half;
+                for (int a = 0; a < 3; ++a) taps[nt][a] = p[a] - step * Ls[a] + a_ * rho * B[a] + b_ * rho * LxB[a];
+                ++nt;
             }
     }
-    return sum / taps;
+    return nt;
 }
 
 /* ------------------------------------------------------------------ */
@@ -679,9 +702,6 @@ int vio_render(const vio_volume* v, const vio_tf* tf, vio_stack* s, const vio_ca
 {
     if (!v || !tf || !cam || !o || !out_term || !(step_vox > 0.0)) return -1;
     if (mode != VIO_MODE_NONE && !s) return -1;  /* Phong takes its light from the stack's frame */
-    /* the cone follows the light direction, which a point light does not
-     * have (R39: not defined for point lights) */
-    if (mode == VIO_MODE_CONE && s->f.positional) return -1;
     int64_t W = cam->width;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();

@@ -136,6 +136,11 @@ void vio_phong(const vio_volume* v, const vio_opts* o, const double L[3], const 
                double* sd, double* ss);
 
 /* coefficient A at p for a ray of direction d */
+/* Cone tap positions at sample p for view direction d (reading R14, R15,
+ * R39): at most VIO_MAX_CONE_TAPS rows of world xyz; returns the count. */
+#define VIO_MAX_CONE_TAPS 128
+int vio_cone_taps(vio_stack* s, const vio_opts* o, const double p[3], const double d[3], double taps[][3]);
+
 double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N,
                        const double p[3], const double d[3]);
 

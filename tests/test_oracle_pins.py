@@ -680,3 +680,81 @@ def test_p14_point_light_on_the_axis_keeps_the_sphere_symmetry():
     S = st.export()
     np.testing.assert_allclose(S, np.rot90(S, k=1, axes=(1, 2)), atol=1e-12)
     assert S.min() < 0.5                                  # the sphere does cast a shadow
+
+
+# ------------------------------------------------------------------ P15 cone under a point light (R39)
+
+def test_p15_point_cone_taps_geometry():
+    """Cone under a point light: ring m of the default cone (2 rings x 4 angles) is centred on the
+    line from the light through the sample, at t_m = m ds / (L . L_s) toward the light (m slabs of
+    depth), in the plane across L_s, radius t_m tan(phi), the first tap along the view direction
+    with its L_s part removed and the four taps a quarter turn apart about L_s.  Catches
+    the axis direction L taken for L_s, t_m without the obliquity, a radial axis not
+    perpendicular to L_s, a misrotated ring."""
+    w = W.WORKLOADS["small"]
+    vol, tf = O.Volume(w.volume()), O.TF(w.tf())
+    pos = np.array([-1.4, 2.1, 1.9])
+    st = O.Stack(vol, tf, None, 20, 24, position=pos)
+    f = st.frame
+    L = np.asarray(f["L"])
+    rng = np.random.default_rng(7)
+    for _ in range(12):
+        p = rng.uniform(0.2, 0.8, 3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        taps = st.cone_taps(p, d)
+        assert taps.shape == (8, 3)
+        Ls = (p - pos) / np.linalg.norm(p - pos)
+        wv = -d - (-d @ Ls) * Ls
+        Bp = wv / np.linalg.norm(wv)
+        for m in (1, 2):
+            ring = taps[4 * (m - 1):4 * m]
+            tm = m * f["ds"] / (L @ Ls)
+            centre = p - tm * Ls
+            # the ring's centre lies on the light ray through p, exactly m slabs of depth nearer the light
+            np.testing.assert_allclose(ring.mean(axis=0), centre, atol=1e-12)
+            np.testing.assert_allclose(L @ (centre - pos), L @ (p - pos) - m * f["ds"], atol=1e-12)
+            off = ring - centre
+            np.testing.assert_allclose(off @ Ls, 0.0, atol=1e-12)
+            np.testing.assert_allclose(np.linalg.norm(off, axis=1), tm, rtol=1e-12)   # tan(phi) = 1
+            np.testing.assert_allclose(off[0] / tm, Bp, atol=1e-12)
+            np.testing.assert_allclose(off[1] / tm, np.cross(Ls, Bp), atol=1e-12)
+            np.testing.assert_allclose(off[2], -off[0], atol=1e-12)
+            np.testing.assert_allclose(off[3], -off[1], atol=1e-12)
+    # directional light: t_m = m ds along L exactly (the rings of section 3.2.3)
+    sd = O.Stack(vol, tf, w.lights()[0], 20, 24)
+    p, d = np.array([0.5, 0.45, 0.55]), np.array([0.0, 1.0, 0.0])
+    taps = sd.cone_taps(p, d)
+    Ld = np.asarray(sd.frame["L"])
+    np.testing.assert_allclose((taps - p) @ Ld, np.repeat([-1, -2], 4) * sd.frame["ds"], atol=1e-14)
+
+
+def test_p15_point_cone_tends_to_the_directional_cone():
+    """A point light receding along -L gives the directional cone in the limit: tap positions
+    approach the directional cone's about as 1/distance, so the coefficient, read from one stack,
+    does too (ring and lattice); and the coefficient is the mean stack value over its taps (Eq. 11).
+    Two stacks are not compared with each other: their grids differ, and so do their bilinear
+    reconstructions near sharp shadow edges."""
+    w = W.WORKLOADS["small"]
+    vol, tf = O.Volume(w.volume()), O.TF(w.tf())
+    L = np.array([1.0, 1.0, -1.0]) / np.sqrt(3.0)
+    n, res = 24, 32
+    sd = O.Stack(vol, tf, L, n, res)
+    rng = np.random.default_rng(11)
+    pts = [(rng.uniform(0.3, 0.7, 3), rng.normal(size=3)) for _ in range(16)]
+    pts = [(p, d / np.linalg.norm(d)) for p, d in pts]
+    for opts in ({}, {"cone_grid": 5}):
+        geo, coef = [], []
+        for D in (40.0, 400.0, 4000.0):
+            sp = O.Stack(vol, tf, None, n, res, position=0.5 - D * L)
+            g = c = 0.0
+            for p, d in pts:
+                tp, td = sp.cone_taps(p, d, opts), sd.cone_taps(p, d, opts)
+                g = max(g, float(np.abs(tp - td).max()))
+                cp = sp.coefficient("cone", p, d, opts)
+                assert abs(cp - np.mean([sp.lookup(t) for t in tp])) < 1e-14
+                c = max(c, abs(cp - np.mean([sp.lookup(t) for t in td])))
+            geo.append(g)
+            coef.append(c)
+        assert geo[2] < 1e-4 and geo[1] < geo[0] / 6 and geo[2] < geo[1] / 6, geo
+        assert coef[2] < 1e-4 and coef[2] < coef[0] / 6, coef
