@@ -462,7 +462,7 @@ def main():
                     help="decide empty space from the min/max map and the TF per cell instead of occupancy bits")
     ap.add_argument("--point-light", type=float, default=0.0, metavar="DIST",
                     help="point lights DIST world units from the volume centre (against each light "
-                         "direction) instead of directional lights; modes shadow, shell, phong, none")
+                         "direction) instead of directional lights")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -508,10 +508,6 @@ def main():
     if args.modes:
         modes = args.modes.split(",")
     if args.point_light:
-        if not args.modes:
-            modes = ["shadow", "shell"]
-        if any(m.startswith("cone") for m in modes):
-            ap.error("the cone gather is defined for directional lights only")
         if not args.point_light > 0.8661:
             ap.error("a point light must lie outside the sphere around the volume (DIST > 0.8661)")
     dev = torch.device("cuda:0")

@@ -225,7 +225,7 @@ typedef struct {
     int shell_count;    /* 1: cuboid shells, 6 taps each                    */
     float shell_w[8];   /* 0s: equal weights; else weight of shell r: A = sum w_r mean_r / sum w_r */
     float shell_h_vox;  /* 1: shell r samples at +-(r+1)*h voxels along x,y,z */
-    int cone_rings;     /* 2: rings at m*ds toward the light, m = 1..rings  */
+    int cone_rings;     /* 2: rings m = 1..rings, m slabs toward the light (ds each along L) */
     int cone_angles;    /* 4: taps per ring, angles 2*pi*q/angles           */
     int cone_grid;      /* 0: ring form; G in 1..7: G x G lattice one slab toward the light */
     float cone_tan;     /* 1: ring radius m*ds*cone_tan; lattice pitch ds*cone_tan/2 */
@@ -340,9 +340,11 @@ int vi_build_attenuation(const vi_volume* vol, const vi_tf* tf, const double lig
  * vi_light_frame (data NULL) serves.  With a point light's descriptor
  * every stack lookup projects through its depth from the light, and a
  * lookup at or behind the light's depth plane reads transmittance 1;
- * Phong's light vector points at the light from each sample.
- * VI_MODE_CONE needs a directional light (VI_E_UNSUPPORTED for a point
- * light's stack: its cone axis and ring offsets assume one direction).
+ * Phong's light vector points at the light from each sample, and the
+ * cone's axis is the light's direction at each sample, L_s = (p - P)/|p - P|:
+ * ring m is centred on that line m slabs of depth toward the light, in the
+ * plane across L_s, radius (that distance) * cone_tan; the lattice lies one
+ * slab toward the light in the same way.
  * If `d_samples` (device) is non-NULL the number of segments composited
  * (stopping at termination; segments that empty-space skipping steps over
  * count too) is ADDED to d_samples[0]; with opts->samples_opaque = 1 the

@@ -583,8 +583,6 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     }
     const bool point = sl && sl->positional;
     if (point) {
-        if (mode == VI_MODE_CONE)
-            return fail(VI_E_UNSUPPORTED, "the cone gather is defined for directional lights only");
         if (!isfinite(sl->P[0]) || !isfinite(sl->P[1]) || !isfinite(sl->P[2]))
             return fail(VI_E_INVALID_ARG, "point light position is not finite");
         if (reads_stack && !(sl->dmin > 0.0 && sl->R > 0.0))
@@ -669,6 +667,7 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         split_float(Ux0 - F.Mr, &F.Ux0, &F.Ux0l);
         split_float(Vy0 - F.Mr, &F.Vy0, &F.Vy0l);
         F.ds = (float)(sl->ds * Nd);
+        F.ids = (float)(1.0 / (sl->ds * Nd));
         if (point) {
             F.sc = (float)sc;
             F.xo = (float)(0.5 * sl->res - 0.5 - F.Mr);

@@ -102,7 +102,7 @@ struct RenderFrame {
     float Vy[3], Vyl[3], Vy0, Vy0l;  // y = Vy . h + Vy0
     float L[3], U[3], V[3];
     float Ll[3], Ul[3], Vl[3];
-    float ds;            // slab thickness in voxels (cone ring radii)
+    float ds, ids;       // slab thickness in voxels (cone ring radii) and its inverse
     // point light: depth d = L.(h - Ph) and lateral u = U.(h - Ph),
     // v = V.(h - Ph) (voxels) map to x = (u / d) sc + xo, y = (v / d) sc + xo
     int point;
@@ -155,17 +155,19 @@ hipError_t launch_occupancy(const float* minmax, uint32_t nc, const float* tf, i
                             hipStream_t s);
 
 // Kernel variants beyond the public modes: for a point light the light grid
-// is a perspective frustum (every stack lookup divides by its depth) and
-// Phong's light vector points at the light from each sample; the cone's
-// lattice form is a kernel of its own (its best tap batching and register
-// budget differ from the ring form's).
+// is a perspective frustum (every stack lookup divides by its depth),
+// Phong's light vector points at the light from each sample and the cone's
+// axis is the light's direction at each sample (ring and lattice forms in
+// one kernel); the directional cone's lattice form is a kernel of its own
+// (its best tap batching and register budget differ from the ring form's).
 constexpr int kModePointShadow = 5, kModePointShell = 6, kModePointPhong = 7, kModeConeGrid = 8,
-              kKernelModes = 9;
+              kModePointCone = 9, kKernelModes = 10;
 inline int kernel_mode(const RenderFrame& f)
 {
     if (f.point && f.mode == VI_MODE_SHADOW) return kModePointShadow;
     if (f.point && f.mode == VI_MODE_SHELL) return kModePointShell;
     if (f.point && f.mode == VI_MODE_PHONG) return kModePointPhong;
+    if (f.point && f.mode == VI_MODE_CONE) return kModePointCone;
     if (f.mode == VI_MODE_CONE && f.cone_grid > 0) return kModeConeGrid;
     return f.mode;
 }

@@ -295,13 +295,94 @@ __device__ __forceinline__ float frustum_col(const RenderFrame& F, float u, floa
     return fminf(fmaxf(x, (float)(-3 - F.Mr)), (float)(F.res + 2 - F.Mr));
 }
 
+// Cone (Eq. 11) about the light's direction at the sample.  With r = (d, u,
+// v) the sample's offset from the light in the light frame (voxels), the
+// axis is L_s = r / |r|, and one slab of depth toward the light lies
+// S = ds |r| / d along it.  Tap (c, a, b) sits at
+//   r - c S L_s + S (a B + b L_s x B) = r (1 - c ds / d) + S (a B + b L_s x B),
+// B the view vector w = (wd, wu, wv) with its L_s part removed (U's, when w
+// runs along L_s), of unit length; ring m has c = m and (a, b) = m tan phi
+// (cos, sin) theta, the lattice c = 1 and (a, b) on a grid of spacing
+// tan phi / 2.  The tap's slab index moves with its depth: c slabs, plus
+// the depth part of the lateral offset.  Taps are summed in the order rings
+// (or lattice rows), then angles (or columns), in batches as in gather().
+template <int SDT, int SL>
+__device__ __forceinline__ float gather_point_cone(const RenderFrame& F, float z, float d, float u, float v, float wd,
+                                                   float wu, float wv)
+{
+    const float r2 = fmaf(d, d, fmaf(u, u, v * v)), ir = __builtin_amdgcn_rsqf(r2);
+    const float ld = d * ir, lu = u * ir, lv = v * ir;
+    const float wl = fmaf(wd, ld, fmaf(wu, lu, wv * lv));
+    float bd = fmaf(-wl, ld, wd), bu = fmaf(-wl, lu, wu), bv = fmaf(-wl, lv, wv);
+    float nb = fmaf(bd, bd, fmaf(bu, bu, bv * bv));
+    if (nb < 1e-12f) {
+        // U is (0, 1, 0) in the light frame
+        bd = -lu * ld;
+        bu = fmaf(-lu, lu, 1.0f);
+        bv = -lu * lv;
+        nb = fmaf(bd, bd, fmaf(bu, bu, bv * bv));
+    }
+    const float q = F.ds * __builtin_amdgcn_rcpf(d);                  // ds / d
+    const float sb = (q * r2 * ir) * __builtin_amdgcn_rsqf(nb);       // S / |B|
+    bd *= sb;
+    bu *= sb;
+    bv *= sb;
+    const float cd = fmaf(lu, bv, -lv * bu), cu = fmaf(lv, bd, -ld * bv), cv = fmaf(ld, bu, -lu * bd);
+    const auto tap = [&](float c, float a, float b, float& zz, float& xx, float& yy) {
+        const float k = fmaf(-c, q, 1.0f);
+        const float od = fmaf(a, bd, b * cd);
+        const float dd = fmaf(d, k, od);
+        const float rd = __builtin_amdgcn_rcpf(dd);
+        zz = fmaf(od, F.ids, z - c);
+        xx = frustum_col(F, fmaf(u, k, fmaf(a, bu, b * cu)), rd, dd > 0.0f);
+        yy = frustum_col(F, fmaf(v, k, fmaf(a, bv, b * cv)), rd, dd > 0.0f);
+    };
+    constexpr int NB = 2;
+    float zz[NB], xx[NB], yy[NB], val[NB];
+    float s = 0.0f;
+    if (F.cone_grid == 0) {
+        for (int m = 1; m <= F.cone_rings; ++m) {
+            const float c = (float)m, r = c * F.cone_tan;
+            for (int t = 0; t < F.cone_angles; t += NB) {
+#pragma unroll
+                for (int w = 0; w < NB; ++w) {
+                    const int i = min(t + w, F.cone_angles - 1);
+                    tap(c, F.cone_cos[i] * r, F.cone_sin[i] * r, zz[w], xx[w], yy[w]);
+                }
+                lookup_batch<SDT, SL>(F, zz, xx, yy, val);
+#pragma unroll
+                for (int w = 0; w < NB; ++w)
+                    if (t + w < F.cone_angles) s += val[w];
+            }
+        }
+    } else {
+        const int G = F.cone_grid;
+        const float rho = 0.5f * F.cone_tan, half = 0.5f * (float)(G - 1);
+        for (int ia = 0; ia < G; ++ia) {
+            const float a = ((float)ia - half) * rho;
+            for (int ib = 0; ib < G; ib += NB) {
+#pragma unroll
+                for (int w = 0; w < NB; ++w)
+                    tap(1.0f, a, ((float)min(ib + w, G - 1) - half) * rho, zz[w], xx[w], yy[w]);
+                lookup_batch<SDT, SL>(F, zz, xx, yy, val);
+#pragma unroll
+                for (int w = 0; w < NB; ++w)
+                    if (ib + w < G) s += val[w];
+            }
+        }
+    }
+    return s * F.tap_w;
+}
+
 template <int MODE, int SDT, int SL>
-__device__ __forceinline__ float gather_point(const RenderFrame& F, float z, float d, float u, float v)
+__device__ __forceinline__ float gather_point(const RenderFrame& F, float z, float d, float u, float v, float wd,
+                                              float wu, float wv)
 {
     if (MODE == kModePointShadow) {
         const float rd = __builtin_amdgcn_rcpf(d);
         return stack_lookup<SDT, SL>(F, z, frustum_col(F, u, rd, d > 0.0f), frustum_col(F, v, rd, d > 0.0f));
     }
+    if constexpr (MODE == kModePointCone) return gather_point_cone<SDT, SL>(F, z, d, u, v, wd, wu, wv);
     // shell taps: world-frame offsets, each projected through its own depth
     // (batched as in gather())
     float s = 0.0f;
@@ -425,7 +506,7 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     // light grid: depth index (Eq. 9, minus one) and texel coordinates (Eq. 10)
     // (point light: qx / qy hold the lateral offsets U.(h - Ph), V.(h - Ph)
     // and pd the depth L.(h - Ph), all affine along the ray)
-    constexpr bool PT = MODE == kModePointShadow || MODE == kModePointShell;
+    constexpr bool PT = MODE == kModePointShadow || MODE == kModePointShell || MODE == kModePointCone;
     constexpr bool PTP = MODE == kModePointPhong, PHONG = MODE == VI_MODE_PHONG || PTP;
     float qz0 = 0.f, qx0 = 0.f, qy0 = 0.f, qdz = 0.f, qdx = 0.f, qdy = 0.f, pd0 = 0.f, pdd = 0.f;
     ConeFrame cf = {0.f, 0.f, 0.f, 0.f};
@@ -586,7 +667,8 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                         float A = 1.0f;
                         if (PT)
                             A = gather_point<MODE, SDT, SL>(F, fmaf(sm, qdz, qz0), fmaf(sm, pdd, pd0),
-                                                            fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0));
+                                                            fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0), -pdd, -qdx,
+                                                            -qdy);
                         else if (MODE != VI_MODE_NONE)
                             A = gather<MODE, SDT, SL>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0),
                                                       fmaf(sm, qdy, qy0));
@@ -833,6 +915,10 @@ static hipError_t launch_batch_t(int mode, const RenderFrame* d_frames, const ui
         hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, kModeConeGrid, SDT, SL>), grid, block, lds, s,
                            d_frames, d_tiles, ntiles);
         break;
+    case kModePointCone:
+        hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, kModePointCone, SDT, SL>), grid, block, lds, s,
+                           d_frames, d_tiles, ntiles);
+        break;
     default:
         hipLaunchKernelGGL((render_batch_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, d_frames,
                            d_tiles, ntiles);
@@ -909,6 +995,9 @@ static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
         break;
     case kModeConeGrid:
         hipLaunchKernelGGL((render_kernel<VT, LAYOUT, kModeConeGrid, SDT, SL>), grid, block, lds, s, f);
+        break;
+    case kModePointCone:
+        hipLaunchKernelGGL((render_kernel<VT, LAYOUT, kModePointCone, SDT, SL>), grid, block, lds, s, f);
         break;
     default: hipLaunchKernelGGL((render_kernel<VT, LAYOUT, VI_MODE_PHONG, SDT, SL>), grid, block, lds, s, f); break;
     }

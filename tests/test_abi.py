@@ -221,11 +221,12 @@ def test_render_validation_errors():
     nolight = _desc(f)
     nolight.L = (C.c_double * 3)(0, 0, 0)
     assert _render(f, nolight, mode=4) == -1
-    # point light: the cone gather is defined for directional lights only
+    # point light: the cone is accepted (its axis follows the light per sample) and its options checked
     pt = vi.light_frame(None, 8, 8, position=[0.5, 0.5, 3.0]).s
     pt.data, pt.vol_n, pt.tag = 0x50000, f.vol.n, 0
-    assert _render(f, pt, mode=3) == -2
-    assert "directional" in vi.lib().vi_last_error().decode()
+    assert _render(f, pt, mode=3, opts={"cone_tan": -1.0}) == -1
+    assert "cone_tan" in vi.lib().vi_last_error().decode()
+    assert _render(f, pt, mode=3, opts={"cone_grid": 9}) == -1
     bad = vi.light_frame(None, 8, 8, position=[0.5, 0.5, 3.0]).s
     bad.data, bad.vol_n, bad.tag = 0x50000, f.vol.n, 0
     bad.P = (C.c_double * 3)(math.nan, 0, 0)

@@ -108,7 +108,7 @@ def test_cone_fallback_when_view_runs_along_the_light(sign):
 
 def test_point_light_large_sampled(large):
     """A point light 2.0 from the centre at the large size: sampled frustum
-    columns and shadow / shell pixels against the oracle."""
+    columns and shadow / shell / cone pixels against the oracle."""
     w, raw, tab, vol, tf, ovol, otf = large
     d = np.array(w.lights()[3])
     pos = (np.array([0.5, 0.5, 0.5]) - 2.0 * d).tolist()
@@ -127,7 +127,7 @@ def test_point_light_large_sampled(large):
     assert err_s <= TOL_STACK
     pix = np.unique(np.concatenate([rng.choice(cam["width"] * cam["height"], 3000, replace=False),
                                     (cam["height"] // 2) * cam["width"] + np.arange(cam["width"])]))
-    for mode in ("shadow", "shell"):
+    for mode in ("shadow", "shell", "cone"):
         img, _ = _frame(vol, tf, st, cam, mode, w.step_vox, {})
         _, ref, _, _ = O.render(ovol, otf, ost, cam, mode, w.step_vox, {}, pixels=pix, want_full=False)
         err = float(np.abs(img.reshape(-1, 4)[pix] - ref).max())

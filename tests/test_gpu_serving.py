@@ -44,9 +44,8 @@ def _requests(vols, count, seed):
         mode = ["shell", "cone", "cone5", "shadow", "phong"][int(rng.integers(5))]
         darken = 1.0 if li == 2 else 0.0          # the compensated build is part of a stack's identity
         # light 0 becomes a point light two units up-stream of the centre
-        # where the mode is defined for one (not the cone)
         pos = None
-        if li == 0 and mode in ("shell", "shadow", "phong"):
+        if li == 0:
             pos = [0.5 - 2.0 * c for c in light]
         reqs.append(dict(vol=vi_, light=light, n=N, res=min(2 * N, 1024), cam=cam, mode=mode, darken=darken,
                          pos=pos))
