@@ -69,7 +69,8 @@ class _Opts(C.Structure):
                 ("shell_h_vox", C.c_double),
                 ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_double),
                 ("phong_ka", C.c_double), ("phong_kd", C.c_double), ("phong_ks", C.c_double),
-                ("phong_shininess", C.c_double), ("grad_eps", C.c_double)]
+                ("phong_shininess", C.c_double), ("grad_eps", C.c_double),
+                ("nearest_layer", C.c_int), ("nearest_shift", C.c_double)]
 
 
 _lib = None
@@ -100,6 +101,8 @@ def _load():
         lib.vio_stack_column.restype = P(C.c_double)
         lib.vio_stack_lookup.argtypes = [C.c_void_p, P(C.c_double)]
         lib.vio_stack_lookup.restype = C.c_double
+        lib.vio_stack_lookup_layer.argtypes = [C.c_void_p, P(C.c_double), C.c_int, C.c_double]
+        lib.vio_stack_lookup_layer.restype = C.c_double
         lib.vio_stack_columns_built.argtypes = [C.c_void_p]
         lib.vio_stack_columns_built.restype = C.c_int64
         lib.vio_camera_ray.argtypes = [P(_Camera), C.c_int, C.c_int, P(C.c_double), P(C.c_double)]
@@ -139,6 +142,7 @@ def default_opts() -> dict:
             "shell_count": o.shell_count, "shell_w": list(o.shell_w), "shell_h_vox": o.shell_h_vox,
             "cone_rings": o.cone_rings,
             "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan,
+            "nearest_layer": o.nearest_layer, "nearest_shift": o.nearest_shift,
             **{k: getattr(o, k) for k in _PHONG_KEYS}}
 
 
@@ -161,6 +165,8 @@ def _opts(opts: dict | None) -> _Opts:
     o.cone_angles = int(d["cone_angles"])
     o.cone_grid = int(d["cone_grid"])
     o.cone_tan = d["cone_tan"]
+    o.nearest_layer = int(d["nearest_layer"])
+    o.nearest_shift = float(d["nearest_shift"])
     return o
 
 
@@ -259,7 +265,10 @@ class Stack:
         ptr = _load().vio_stack_column(self._p, int(i), int(j))
         return np.ctypeslib.as_array(ptr, shape=(self.n,)).copy()
 
-    def lookup(self, p) -> float:
+    def lookup(self, p, nearest: bool = False, shift: float = 0.0) -> float:
+        """Transmittance at world point p: continuous in depth, or the nearest layer."""
+        if nearest:
+            return _load().vio_stack_lookup_layer(self._p, _vec(p), 1, float(shift))
         return _load().vio_stack_lookup(self._p, _vec(p))
 
     def columns_built(self) -> int:

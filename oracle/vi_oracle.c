@@ -74,6 +74,9 @@ void vio_default_opts(vio_opts* o)
     o->phong_ks = 0.4;
     o->phong_shininess = 20.0;
     o->grad_eps = 0.02;
+    /* continuous depth (R11); the nearest-layer reading R25 is an option */
+    o->nearest_layer = 0;
+    o->nearest_shift = 0.0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -388,7 +391,16 @@ static double stack_ext(vio_stack* s, int k, int j, int i)
  * (reading R11: the index q lies between faces q-1 and q, so the lookup
  * interpolates layers S[q-1] ... with S[-1] = 1), bilinear in the slice,
  * clamped beyond the last face (R12). */
-double vio_stack_lookup(vio_stack* s, const double p[3])
+double vio_stack_lookup(vio_stack* s, const double p[3]) { return vio_stack_lookup_layer(s, p, 0, 0.0); }
+
+/* The same lookup, or with nearest = 1 the nearest-layer reading R25 of
+ * Eq. 9: the index q picks one layer of the texture array, the face nearest
+ * to q, f = floor(q + 1/2 + shift) clamped to 0..n (face 0 = 1, face f holds
+ * S[f-1]), read bilinearly in that layer.  shift = 0 is the reading; a
+ * small non-zero shift moves every rounding boundary, which the tests use
+ * to tell which results depend on a depth index lying within |shift| of a
+ * half-integer. */
+double vio_stack_lookup_layer(vio_stack* s, const double p[3], int nearest, double shift)
 {
     const vio_frame* f = &s->f;
     double q, x, y;
@@ -409,6 +421,7 @@ double vio_stack_lookup(vio_stack* s, const double p[3])
         y = (dot3(f->V, r) + f->R) / (2.0 * f->R) * f->res - 0.5;
     }
     double z = q - 1.0;
+    if (nearest) z = floor(q + 0.5 + shift) - 1.0;
     if (z < -1.0) z = -1.0;
     if (z > f->n - 1.0) z = f->n - 1.0;
 
@@ -433,7 +446,7 @@ double vio_stack_lookup(vio_stack* s, const double p[3])
 double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N, const double p[3], const double d[3])
 {
     if (mode == VIO_MODE_NONE) return 1.0;
-    if (mode == VIO_MODE_SHADOW) return vio_stack_lookup(s, p);
+    if (mode == VIO_MODE_SHADOW) return vio_stack_lookup_layer(s, p, o->nearest_layer, o->nearest_shift);
 
     if (mode == VIO_MODE_SHELL) {
         /* Cuboid shells: the sample moved by +-(r+1) h along x, y and z;
@@ -449,7 +462,7 @@ double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N, const d
                 for (int sg = -1; sg <= 1; sg += 2) {
                     double q[3] = {p[0], p[1], p[2]};
                     q[a] += sg * (r + 1) * h;
-                    sum += vio_stack_lookup(s, q);
+                    sum += vio_stack_lookup_layer(s, q, o->nearest_layer, o->nearest_shift);
                 }
             num += w * sum / 6.0;
             wsum += w;
@@ -461,7 +474,7 @@ double vio_coefficient(vio_stack* s, int mode, const vio_opts* o, int N, const d
     int nt = vio_cone_taps(s, o, p, d, taps);
     if (nt == 0) return 1.0;
     double sum = 0.0;
-    for (int t = 0; t < nt; ++t) sum += vio_stack_lookup(s, taps[t]);
+    for (int t = 0; t < nt; ++t) sum += vio_stack_lookup_layer(s, taps[t], o->nearest_layer, o->nearest_shift);
     return sum / nt;
 }
 

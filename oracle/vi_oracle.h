@@ -92,6 +92,8 @@ typedef struct {
     double phong_shininess;
     double grad_eps;      /* gradient magnitude (per voxel) below which the
                              normal shrinks toward zero                     */
+    int nearest_layer;    /* 1: lookups read the layer nearest Eq. 9's index (R25) */
+    double nearest_shift; /* moves the nearest-layer rounding boundary (tests) */
 } vio_opts;
 
 /* Stack of light-space transmittance slices.  Columns are built on demand
@@ -119,6 +121,7 @@ void       vio_stack_export(vio_stack* s, double* out, int nthreads);
 /* column (i,j): n transmittances, built on first use */
 const double* vio_stack_column(vio_stack* s, int i, int j);
 double     vio_stack_lookup(vio_stack* s, const double p[3]);
+double     vio_stack_lookup_layer(vio_stack* s, const double p[3], int nearest, double shift);
 int64_t    vio_stack_columns_built(const vio_stack* s);
 
 /* camera ray through pixel (px,py); returns 1 and the entry/exit distances

@@ -758,3 +758,86 @@ def test_p15_point_cone_tends_to_the_directional_cone():
             coef.append(c)
         assert geo[2] < 1e-4 and geo[1] < geo[0] / 6 and geo[2] < geo[1] / 6, geo
         assert coef[2] < 1e-4 and coef[2] < coef[0] / 6, coef
+
+
+# ------------------------------------------------------------------ P16 nearest-layer lookup (R25)
+
+def _face_point(st, p, f, frame):
+    """p moved to depth index q = f without changing its texel coordinates: along L for a
+    directional light, along the ray from the light for a point light."""
+    L = np.asarray(frame["L"])
+    span = frame["dmax"] - frame["dmin"]
+    if frame.get("positional"):
+        P = np.asarray(frame["P"])
+        d = L @ (p - P)
+        df = frame["dmin"] + f * span / frame["n"]
+        return P + (df / d) * (p - P)
+    q = frame["n"] * (L @ p - frame["dmin"]) / span
+    return p + (f - q) * span / frame["n"] * L
+
+
+def test_p16_nearest_layer_reads_the_nearest_face():
+    """Nearest-layer lookup (R25): at any point it equals the continuous lookup (R11) at the
+    same texel coordinates on face f = floor(q + 1/2 + shift), clamped to 0..n (face 0 reads 1),
+    for a directional and a point light.  Catches rounding down instead of to nearest, the
+    face/layer offset (face f holds layer f - 1), a missing clamp."""
+    w = W.WORKLOADS["small"]
+    vol, tf = O.Volume(w.volume()), O.TF(w.tf())
+    rng = np.random.default_rng(5)
+    for light, pos in (([0.3, -0.5, 0.81], None), (None, [1.9, -0.6, 1.3])):
+        st = O.Stack(vol, tf, light, 20, 28, position=pos)
+        f = st.frame
+        L = np.asarray(f["L"])
+        differs = 0
+        for _ in range(300):
+            p = rng.uniform(-0.05, 1.05, 3)
+            shift = 0.0 if rng.random() < 0.5 else float(rng.uniform(-0.45, 0.45))
+            if f.get("positional"):
+                q = f["n"] * (L @ (p - np.asarray(f["P"])) - f["dmin"]) / (f["dmax"] - f["dmin"])
+            else:
+                q = f["n"] * (L @ p - f["dmin"]) / (f["dmax"] - f["dmin"])
+            face = int(min(max(math.floor(q + 0.5 + shift), 0), f["n"]))
+            got = st.lookup(p, nearest=True, shift=shift)
+            want = 1.0 if face == 0 else st.lookup(_face_point(st, p, face, f))
+            assert abs(got - want) < 1e-12, (p, q, shift, got, want)
+            differs += abs(got - st.lookup(p)) > 1e-6
+        assert differs >= 20          # the two readings really differ (where the stack is not 1)
+
+
+def test_p16_nearest_layer_converges_at_first_order():
+    """Against the dense light march of P7: the nearest layer's error falls in proportion to
+    the slab thickness (first order), the continuous reading's with its square."""
+    N = 16
+    g = (np.arange(N) + 0.5) / N
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    field = np.exp(-(((X - 0.45) ** 2 + (Y - 0.55) ** 2 + (Z - 0.5) ** 2) / (2 * 0.18 ** 2)))
+    vol = O.Volume((0.6 * field).astype(np.float32), scale=1.0)
+    tab = np.zeros((256, 4))
+    tab[:, 3] = 0.25 * np.linspace(0, 1, 256)
+    tf = O.TF(tab)
+    light = np.array([0.4, -0.3, 0.85])
+    L = light / np.linalg.norm(light)
+    rng = np.random.default_rng(7)
+    pts = rng.uniform(0.3, 0.7, size=(40, 3))
+
+    def dense(p):
+        s_max = min(((0.0 - p[a]) / -L[a]) if -L[a] < 0 else ((1.0 - p[a]) / -L[a]) for a in range(3))
+        M = 4000
+        ds = s_max / M
+        tau = 0.0
+        for m in range(M):
+            q = p - (m + 0.5) * ds * L
+            a = O.tf_lookup(tf, O.volume_sample(vol, q))[3]
+            tau += -math.log(1 - a) * N * ds
+        return math.exp(-tau)
+
+    ref = np.array([dense(p) for p in pts])
+    near, cont = [], []
+    for n in [12, 24, 48, 96]:
+        st = O.Stack(vol, tf, light, n, 4 * n)
+        near.append(np.abs(np.array([st.lookup(p, nearest=True) for p in pts]) - ref).max())
+        cont.append(np.abs(np.array([st.lookup(p) for p in pts]) - ref).max())
+    # over an 8x refinement first order gains ~8 (the max over points is noisy per step),
+    # second order ~64
+    assert 4.0 < near[0] / near[-1] < 14.0, near
+    assert cont[0] / cont[-1] > 25.0 and near[-1] > 5 * cont[-1], (near, cont)
