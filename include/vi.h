@@ -242,6 +242,11 @@ typedef struct {
     int samples_opaque;    /* 0: d_samples of vi_render is one counter; 1: two, [0] as
                               described there and [1] the segments composited with
                               non-zero opacity (those whose coefficient is gathered) */
+    int nearest_layer;     /* 0: depth-continuous lookups (the index q of Eq. 9 lies
+                              between faces floor(q) and ceil(q), linear between them);
+                              1: each lookup reads the single layer of the face nearest
+                              to q, floor(q + 1/2) (face 0 = 1, face f = layer f-1), as a
+                              texture array indexed by Eq. 9 would, bilinear within it */
 } vi_render_opts;
 
 /* Library version string. */

@@ -293,6 +293,7 @@ int vi_default_render_opts(vi_render_opts* o)
     o->phong_shininess = 20.0f;
     o->grad_eps = 0.02f;
     o->samples_opaque = 0;
+    o->nearest_layer = 0;
     return VI_OK;
 }
 
@@ -732,6 +733,8 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     F.grad_eps = o.grad_eps;
     if (o.samples_opaque != 0 && o.samples_opaque != 1) return fail(VI_E_INVALID_ARG, "samples_opaque must be 0 or 1");
     F.count_opaque = o.samples_opaque;
+    if (o.nearest_layer != 0 && o.nearest_layer != 1) return fail(VI_E_INVALID_ARG, "nearest_layer must be 0 or 1");
+    F.nearest = o.nearest_layer;
 
     if (mode == VI_MODE_SHELL) {
         if (o.shell_count < 1 || 6 * o.shell_count > vi::kMaxTaps)

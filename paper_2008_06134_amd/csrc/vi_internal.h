@@ -94,6 +94,7 @@ struct RenderFrame {
     uint32_t layer, row_tiles32;
     uint32_t rlayer, rpitch, rorg;  // rows: elements per layer, pitch, element of texel (0,0,0)
     int Mz, Mr;          // integer offsets of the light-grid coordinates
+    int nearest;         // 1: every lookup reads the face nearest its depth index
     // Light grid as affine maps of the offset-voxel position h; every
     // coefficient is a float pair (value, remainder), so that the per-ray
     // offsets are as accurate as a double set-up would make them:

@@ -91,9 +91,10 @@ struct RowTap {
     PairRaw<SDT> a0, a1, b0, b1;  // layer k0 rows j, j+1; layer k1 rows j, j+1
     float wx, wy, wz;
 };
-template <int SDT>
+template <int SDT, bool NEAR>
 __device__ __forceinline__ void rowtap_load(const RenderFrame& F, float z, float x, float y, RowTap<SDT>& t)
 {
+    if (NEAR) z = floorf(z + 0.5f);
     z = __builtin_amdgcn_fmed3f(z, (float)(-1 - F.Mz), (float)(F.n - 1 - F.Mz));
     const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
     t.wz = z - fz;
@@ -126,14 +127,15 @@ __device__ __forceinline__ float rowtap_value(const RowTap<SDT>& t)
 // Transmittance at light-grid offset coordinates (z, x, y): depth between
 // faces (layer z and z+1 in stack order, layer -1 = 1), bilinear in the
 // layer, fully transmitting outside the texel grid.
-template <int SDT, int SL>
+template <int SDT, int SL, bool NEAR>
 __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, float x, float y)
 {
     if (SL == VI_STACK_ROWS) {
         RowTap<SDT> t;
-        rowtap_load<SDT>(F, z, x, y, t);
+        rowtap_load<SDT, NEAR>(F, z, x, y, t);
         return rowtap_value<SDT>(t);
     }
+    if (NEAR) z = floorf(z + 0.5f);
     z = fminf(fmaxf(z, (float)(-1 - F.Mz)), (float)(F.n - 1 - F.Mz));
     const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
     const float wz = z - fz, wx = x - fx, wy = y - fy;
@@ -198,26 +200,26 @@ constexpr int tap_batch()
     return (MODE == VI_MODE_CONE || (MODE == VI_MODE_SHELL && SDT == VI_F32)) ? 2 : 1;
 }
 
-template <int SDT, int SL, int NB>
+template <int SDT, int SL, bool NEAR, int NB>
 __device__ __forceinline__ void lookup_batch(const RenderFrame& F, const float (&z)[NB], const float (&x)[NB],
                                              const float (&y)[NB], float (&out)[NB])
 {
     if constexpr (SL == VI_STACK_ROWS) {
         RowTap<SDT> t[NB];
 #pragma unroll
-        for (int u = 0; u < NB; ++u) rowtap_load<SDT>(F, z[u], x[u], y[u], t[u]);
+        for (int u = 0; u < NB; ++u) rowtap_load<SDT, NEAR>(F, z[u], x[u], y[u], t[u]);
 #pragma unroll
         for (int u = 0; u < NB; ++u) out[u] = rowtap_value<SDT>(t[u]);
     } else {
 #pragma unroll
-        for (int u = 0; u < NB; ++u) out[u] = stack_lookup<SDT, SL>(F, z[u], x[u], y[u]);
+        for (int u = 0; u < NB; ++u) out[u] = stack_lookup<SDT, SL, NEAR>(F, z[u], x[u], y[u]);
     }
 }
 
-template <int MODE, int SDT, int SL>
+template <int MODE, int SDT, int SL, bool NEAR>
 __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& cf, float z, float x, float y)
 {
-    if (MODE == VI_MODE_SHADOW) return stack_lookup<SDT, SL>(F, z, x, y);
+    if (MODE == VI_MODE_SHADOW) return stack_lookup<SDT, SL, NEAR>(F, z, x, y);
     // Taps go in batches; a batch running past the last tap repeats it and
     // leaves the sum alone for the repeats, so every tap is added once, in
     // order, as a one-at-a-time loop adds it.
@@ -234,7 +236,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
                 xx[u] = x + F.tx_[i];
                 yy[u] = y + F.ty_[i];
             }
-            lookup_batch<SDT, SL>(F, zz, xx, yy, v);
+            lookup_batch<SDT, SL, NEAR>(F, zz, xx, yy, v);
 #pragma unroll
             for (int u = 0; u < NB; ++u)
                 if (t + u < F.ntaps) s = fmaf(F.tw[t + u], v[u], s);
@@ -255,7 +257,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
                     xx[u] = x + ca * cf.bx + sa * cf.px;
                     yy[u] = y + ca * cf.by + sa * cf.py;
                 }
-                lookup_batch<SDT, SL>(F, zz, xx, yy, v);
+                lookup_batch<SDT, SL, NEAR>(F, zz, xx, yy, v);
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
                     if (q + u < F.cone_angles) s += v[u];
@@ -274,7 +276,7 @@ __device__ __forceinline__ float gather(const RenderFrame& F, const ConeFrame& c
                     xx[u] = x + a * cf.bx + b * cf.px;
                     yy[u] = y + a * cf.by + b * cf.py;
                 }
-                lookup_batch<SDT, SL>(F, zz, xx, yy, v);
+                lookup_batch<SDT, SL, NEAR>(F, zz, xx, yy, v);
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
                     if (ib + u < G) s += v[u];
@@ -306,7 +308,7 @@ __device__ __forceinline__ float frustum_col(const RenderFrame& F, float u, floa
 // tan phi / 2.  The tap's slab index moves with its depth: c slabs, plus
 // the depth part of the lateral offset.  Taps are summed in the order rings
 // (or lattice rows), then angles (or columns), in batches as in gather().
-template <int SDT, int SL>
+template <int SDT, int SL, bool NEAR>
 __device__ __forceinline__ float gather_point_cone(const RenderFrame& F, float z, float d, float u, float v, float wd,
                                                    float wu, float wv)
 {
@@ -349,7 +351,7 @@ __device__ __forceinline__ float gather_point_cone(const RenderFrame& F, float z
                     const int i = min(t + w, F.cone_angles - 1);
                     tap(c, F.cone_cos[i] * r, F.cone_sin[i] * r, zz[w], xx[w], yy[w]);
                 }
-                lookup_batch<SDT, SL>(F, zz, xx, yy, val);
+                lookup_batch<SDT, SL, NEAR>(F, zz, xx, yy, val);
 #pragma unroll
                 for (int w = 0; w < NB; ++w)
                     if (t + w < F.cone_angles) s += val[w];
@@ -364,7 +366,7 @@ __device__ __forceinline__ float gather_point_cone(const RenderFrame& F, float z
 #pragma unroll
                 for (int w = 0; w < NB; ++w)
                     tap(1.0f, a, ((float)min(ib + w, G - 1) - half) * rho, zz[w], xx[w], yy[w]);
-                lookup_batch<SDT, SL>(F, zz, xx, yy, val);
+                lookup_batch<SDT, SL, NEAR>(F, zz, xx, yy, val);
 #pragma unroll
                 for (int w = 0; w < NB; ++w)
                     if (ib + w < G) s += val[w];
@@ -374,15 +376,15 @@ __device__ __forceinline__ float gather_point_cone(const RenderFrame& F, float z
     return s * F.tap_w;
 }
 
-template <int MODE, int SDT, int SL>
+template <int MODE, int SDT, int SL, bool NEAR>
 __device__ __forceinline__ float gather_point(const RenderFrame& F, float z, float d, float u, float v, float wd,
                                               float wu, float wv)
 {
     if (MODE == kModePointShadow) {
         const float rd = __builtin_amdgcn_rcpf(d);
-        return stack_lookup<SDT, SL>(F, z, frustum_col(F, u, rd, d > 0.0f), frustum_col(F, v, rd, d > 0.0f));
+        return stack_lookup<SDT, SL, NEAR>(F, z, frustum_col(F, u, rd, d > 0.0f), frustum_col(F, v, rd, d > 0.0f));
     }
-    if constexpr (MODE == kModePointCone) return gather_point_cone<SDT, SL>(F, z, d, u, v, wd, wu, wv);
+    if constexpr (MODE == kModePointCone) return gather_point_cone<SDT, SL, NEAR>(F, z, d, u, v, wd, wu, wv);
     // shell taps: world-frame offsets, each projected through its own depth
     // (batched as in gather())
     float s = 0.0f;
@@ -397,7 +399,7 @@ __device__ __forceinline__ float gather_point(const RenderFrame& F, float z, flo
             xx[q] = frustum_col(F, u + F.tx_[i], rd, dt > 0.0f);
             yy[q] = frustum_col(F, v + F.ty_[i], rd, dt > 0.0f);
         }
-        lookup_batch<SDT, SL>(F, zz, xx, yy, val);
+        lookup_batch<SDT, SL, NEAR>(F, zz, xx, yy, val);
 #pragma unroll
         for (int q = 0; q < NB; ++q)
             if (t + q < F.ntaps) s = fmaf(F.tw[t + q], val[q], s);
@@ -664,14 +666,18 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
                         sd = fmaf(F.phong_kd, fmaxf(nl, 0.0f), F.phong_ka);
                         if (rv > 0.0f) ss = F.phong_ks * fast_exp2(F.phong_shin * fast_log2(rv));
                     } else {
+                        // (the nearest-face form is a second copy of the
+                        // gather behind a branch that is uniform per frame)
                         float A = 1.0f;
-                        if (PT)
-                            A = gather_point<MODE, SDT, SL>(F, fmaf(sm, qdz, qz0), fmaf(sm, pdd, pd0),
-                                                            fmaf(sm, qdx, qx0), fmaf(sm, qdy, qy0), -pdd, -qdx,
-                                                            -qdy);
-                        else if (MODE != VI_MODE_NONE)
-                            A = gather<MODE, SDT, SL>(F, cf, fmaf(sm, qdz, qz0), fmaf(sm, qdx, qx0),
-                                                      fmaf(sm, qdy, qy0));
+                        const float qz = fmaf(sm, qdz, qz0), qx = fmaf(sm, qdx, qx0), qy = fmaf(sm, qdy, qy0);
+                        if (PT) {
+                            const float pd = fmaf(sm, pdd, pd0);
+                            A = F.nearest ? gather_point<MODE, SDT, SL, true>(F, qz, pd, qx, qy, -pdd, -qdx, -qdy)
+                                          : gather_point<MODE, SDT, SL, false>(F, qz, pd, qx, qy, -pdd, -qdx, -qdy);
+                        } else if (MODE != VI_MODE_NONE) {
+                            A = F.nearest ? gather<MODE, SDT, SL, true>(F, cf, qz, qx, qy)
+                                          : gather<MODE, SDT, SL, false>(F, cf, qz, qx, qy);
+                        }
                         sd = fmaf(1.0f - F.ambient, A, F.ambient);
                     }
                     cr = alpha * F.light[0] * fmaf(sd, fmaf(w, tb.x - ta.x, ta.x), ss);

@@ -76,7 +76,8 @@ class RenderOpts_t(C.Structure):
                 ("shell_h_vox", C.c_float),
                 ("cone_rings", C.c_int), ("cone_angles", C.c_int), ("cone_grid", C.c_int), ("cone_tan", C.c_float),
                 ("phong_ka", C.c_float), ("phong_kd", C.c_float), ("phong_ks", C.c_float),
-                ("phong_shininess", C.c_float), ("grad_eps", C.c_float), ("samples_opaque", C.c_int)]
+                ("phong_shininess", C.c_float), ("grad_eps", C.c_float), ("samples_opaque", C.c_int),
+                ("nearest_layer", C.c_int)]
 
 
 class ServerCfg_t(C.Structure):
@@ -345,7 +346,8 @@ def default_opts() -> dict:
             "shell_count": o.shell_count, "shell_w": list(o.shell_w), "shell_h_vox": o.shell_h_vox,
             "cone_rings": o.cone_rings,
             "cone_angles": o.cone_angles, "cone_grid": o.cone_grid, "cone_tan": o.cone_tan,
-            **{k: getattr(o, k) for k in _PHONG_KEYS}, "samples_opaque": o.samples_opaque}
+            **{k: getattr(o, k) for k in _PHONG_KEYS}, "samples_opaque": o.samples_opaque,
+            "nearest_layer": o.nearest_layer}
 
 
 def render_opts(opts: dict | None) -> RenderOpts_t:
@@ -368,6 +370,7 @@ def render_opts(opts: dict | None) -> RenderOpts_t:
     for k in _PHONG_KEYS:
         setattr(o, k, float(d[k]))
     o.samples_opaque = int(d["samples_opaque"])
+    o.nearest_layer = int(d["nearest_layer"])
     return o
 
 
