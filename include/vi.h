@@ -80,7 +80,7 @@ typedef enum {
     VI_U16 = 1,  /* volume: unsigned 16-bit                             */
     VI_F16 = 2,  /* volume: IEEE half                                   */
     VI_F32 = 3,  /* volume: float; stack: float transmittance           */
-    VI_BF16 = 4  /* stack: bfloat16 optical depth (precision form)      */
+    VI_BF16 = 4  /* stack: bfloat16 optical depth -log2 T (precision form) */
 } vi_dtype;
 
 typedef enum {
@@ -168,8 +168,8 @@ typedef enum { VI_STACK_TILED = 0, VI_STACK_ROWS = 1 } vi_stack_layout;
 /* Attenuation stack descriptor, filled by vi_build_attenuation (or by
  * vi_light_frame for the geometry alone).  `data` points at the caller's
  * buffer of vi_slices_bytes(n, res, dtype, layout) bytes in `layout`.  F32
- * stores transmittance T_k; BF16 stores optical depth tau_k with
- * T_k = exp(-tau_k) (0 outside the grid).
+ * stores transmittance T_k; BF16 stores optical depth in base-2 units,
+ * tau_k = -log2 T_k, so T_k = 2^-tau_k (0 outside the grid).
  * Geometry is kept in double as computed on the host (Eq. 8). */
 typedef struct {
     void* data;
@@ -325,8 +325,9 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
  * `light_dir` into `d_slices` (device, vi_slices_bytes bytes, 16-byte
  * aligned, layout `slice_layout`) and describe it in `out_desc` (host).  One kernel launch on
  * `stream`.  slice_dtype: VI_F32 (transmittance, product of per-slab
- * (1-alpha)) or VI_BF16 (optical depth: the per-slab extinction summed in
- * float and rounded to bfloat16 per layer; each slab adds at most 64).
+ * (1-alpha)) or VI_BF16 (optical depth in base-2 units, -log2 T: the
+ * per-slab extinction over ln 2 summed in float and rounded to bfloat16 per
+ * layer; each slab adds at most 64 / ln 2, a factor e^-64).
  * `opts` may be NULL (directional light, plain product).
  * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes, a degenerate
  * light or options out of range; VI_E_UNSUPPORTED for dtypes or sizes

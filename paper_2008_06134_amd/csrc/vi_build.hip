@@ -158,7 +158,8 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// One stack texel: transmittance, or (BF16 form) optical depth.
+// One stack texel: transmittance, or (BF16 form) optical depth in base-2
+// units, -log2 T.
 template <int OUT_DTYPE>
 __device__ __forceinline__ void put_texel(void* out, uint32_t at, float T, float tau)
 {
@@ -264,7 +265,6 @@ __device__ __forceinline__ void build_run(const BuildParams& P)
         Hy[c] += (int64_t)k0 * Ay[q];
         Hz[c] += (int64_t)k0 * Az[q];
     }
-    const float ln2 = 0.69314718055994531f;
     // the section 4 compensation (1 + alpha)^m; m = 0 leaves every factor
     // unchanged exactly (f * 2^0 = f, min(f, 1) = f)
     const bool darken = P.darken > 0.0f;
@@ -329,12 +329,13 @@ __device__ __forceinline__ void build_run(const BuildParams& P)
                         if (darken) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
                         T[c] *= f;
                     } else {
-                        // sigma * ds = -e ln(1 - a), capped at 64 per slab; the
-                        // compensation subtracts m ln(1 + alpha), floored at 0
-                        float dtau = -e * ln2 * l2;
-                        if (darken)
-                            dtau = fmaxf(dtau - P.darken * ln2 * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
-                        tau[c] += fminf(dtau, 64.0f);
+                        // optical depth in base-2 units: sigma ds / ln 2 =
+                        // -e log2(1 - a), capped at 64 / ln 2 per slab (a factor
+                        // e^-64); the compensation subtracts m log2(1 + alpha),
+                        // floored at 0
+                        float dtau = -e * l2;
+                        if (darken) dtau = fmaxf(dtau - P.darken * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
+                        tau[c] += fminf(dtau, 92.332482616893656f);
                     }
                 }
                 if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c], T[c], tau[c]);

@@ -24,6 +24,10 @@ namespace vi {
 // --------------------------------------------------------------------------
 // stack access
 // --------------------------------------------------------------------------
+// A float stack holds transmittance T; a bfloat16 stack holds optical depth
+// in base-2 units, tau2 = -log2 T (Eq. 6's exponent summed over the slabs in
+// front, over ln 2), so that each texel converts to T = 2^-tau2 with one
+// exponential before the interpolation.
 template <int SDT>
 __device__ __forceinline__ float stack_texel(const void* __restrict__ S, uint32_t idx);
 
@@ -35,23 +39,21 @@ __device__ __forceinline__ float stack_texel<VI_F32>(const void* __restrict__ S,
 template <>
 __device__ __forceinline__ float stack_texel<VI_BF16>(const void* __restrict__ S, uint32_t idx)
 {
-    // optical depth -> transmittance per texel, before interpolation
-    const float log2e = 1.4426950408889634f;
-    return fast_exp2(-log2e * bf16_to_f32(((const uint16_t*)S)[idx]));
+    return fast_exp2(-bf16_to_f32(((const uint16_t*)S)[idx]));
 }
 
 // Row layout: the two texels (i, i+1) of one bilinear row, element e and
-// e+1, with one 8-byte load (4-byte aligned for float; for bfloat16 the
-// aligned 4-element window that holds both).
+// e+1, with one load: 8 bytes (4-byte aligned) for float, 4 bytes (2-byte
+// aligned, which global loads allow) for bfloat16.
 typedef float f32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
-typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32_a2 __attribute__((aligned(2)));
 
 // The load and the conversion are separate steps (PairRaw holds the loaded
 // bits), so that a gather can issue the loads of several taps before it
 // converts any of them.
 template <int SDT> struct PairRaw;
 template <> struct PairRaw<VI_F32> { f32x2_a4 v; };
-template <> struct PairRaw<VI_BF16> { u32x2_a4 w; uint32_t odd; };
+template <> struct PairRaw<VI_BF16> { uint32_t w; };
 
 template <int SDT>
 __device__ __forceinline__ PairRaw<SDT> pair_load(const void* __restrict__ S, uint32_t e);
@@ -63,20 +65,13 @@ __device__ __forceinline__ PairRaw<VI_F32> pair_load<VI_F32>(const void* __restr
 template <>
 __device__ __forceinline__ PairRaw<VI_BF16> pair_load<VI_BF16>(const void* __restrict__ S, uint32_t e)
 {
-    return PairRaw<VI_BF16>{*(const u32x2_a4*)((const uint16_t*)S + (e & ~1u)), e & 1u};
+    return PairRaw<VI_BF16>{*(const u32_a2*)((const uint16_t*)S + e)};
 }
 __device__ __forceinline__ float2 pair_value(const PairRaw<VI_F32>& r) { return make_float2(r.v.x, r.v.y); }
 __device__ __forceinline__ float2 pair_value(const PairRaw<VI_BF16>& r)
 {
-    const uint32_t lo = r.odd ? (r.w.x >> 16) : (r.w.x & 0xffffu);
-    const uint32_t hi = r.odd ? (r.w.y & 0xffffu) : (r.w.x >> 16);
-    const float log2e = 1.4426950408889634f;
-    return make_float2(fast_exp2(-log2e * __uint_as_float(lo << 16)), fast_exp2(-log2e * __uint_as_float(hi << 16)));
-}
-template <int SDT>
-__device__ __forceinline__ float2 stack_pair(const void* __restrict__ S, uint32_t e)
-{
-    return pair_value(pair_load<SDT>(S, e));
+    // element e in the low half, e + 1 in the high half (little-endian)
+    return make_float2(fast_exp2(-__uint_as_float(r.w << 16)), fast_exp2(-__uint_as_float(r.w & 0xffff0000u)));
 }
 
 // One row-layout lookup split into its four loads (rows j, j+1 of layers k0
@@ -149,16 +144,17 @@ __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, flo
     const uint32_t oj0 = stack_oj(clampi(j0, 0, res - 1), F.row_tiles32);
     const uint32_t oj1 = stack_oj(clampi(j0 + 1, 0, res - 1), F.row_tiles32);
 
-    float t0 = 1.0f;
+    constexpr float one = 1.0f;
+    float t0 = one;
     if (k0 >= 0) {
         const uint32_t base = (uint32_t)k0 * F.layer;
         const uint32_t r0 = base + oj0, r1 = base + oj1;
         float a = stack_texel<SDT>(F.stack, r0 + oi0), b = stack_texel<SDT>(F.stack, r0 + oi1);
         float c = stack_texel<SDT>(F.stack, r1 + oi0), d = stack_texel<SDT>(F.stack, r1 + oi1);
-        a = (vi0 && vj0) ? a : 1.0f;
-        b = (vi1 && vj0) ? b : 1.0f;
-        c = (vi0 && vj1) ? c : 1.0f;
-        d = (vi1 && vj1) ? d : 1.0f;
+        a = (vi0 && vj0) ? a : one;
+        b = (vi1 && vj0) ? b : one;
+        c = (vi0 && vj1) ? c : one;
+        d = (vi1 && vj1) ? d : one;
         const float ab = fmaf(wx, b - a, a), cd = fmaf(wx, d - c, c);
         t0 = fmaf(wy, cd - ab, ab);
     }
@@ -168,10 +164,10 @@ __device__ __forceinline__ float stack_lookup(const RenderFrame& F, float z, flo
         const uint32_t r0 = base + oj0, r1 = base + oj1;
         float a = stack_texel<SDT>(F.stack, r0 + oi0), b = stack_texel<SDT>(F.stack, r0 + oi1);
         float c = stack_texel<SDT>(F.stack, r1 + oi0), d = stack_texel<SDT>(F.stack, r1 + oi1);
-        a = (vi0 && vj0) ? a : 1.0f;
-        b = (vi1 && vj0) ? b : 1.0f;
-        c = (vi0 && vj1) ? c : 1.0f;
-        d = (vi1 && vj1) ? d : 1.0f;
+        a = (vi0 && vj0) ? a : one;
+        b = (vi1 && vj0) ? b : one;
+        c = (vi0 && vj1) ? c : one;
+        d = (vi1 && vj1) ? d : one;
         const float ab = fmaf(wx, b - a, a), cd = fmaf(wx, d - c, c);
         t1 = fmaf(wy, cd - ab, ab);
     }

@@ -408,7 +408,7 @@ def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: 
                       out: torch.Tensor | None = None, stream=None, layout: int = VI_STACK_TILED,
                       darken: float = 0.0, position=None) -> Slices:
     """Attenuation stack for `light_dir` (section 3.2.1, Alg. 1); returns the stack
-    (float32 transmittance, or bfloat16 optical depth) and its descriptor.  `darken`
+    (float32 transmittance, or bfloat16 optical depth -log2 T) and its descriptor.  `darken`
     is the exponent m of section 4's (1+alpha)^m slab compensation (0 = off);
     `position` (world xyz) builds for a point light there instead (`light_dir`
     is then ignored and may be None)."""

@@ -52,8 +52,8 @@ def _precision_case(N, n, res, cam, light, mode, opts, pix, layout=vi.VI_STACK_R
     otf = O.TF(tab)
     o_u16, o_f16 = O.Volume(raw), O.Volume(f16, 1.0)
     s16 = O.Stack(o_f16, otf, light, n, res)
-    # stack: exp(-tau) against the oracle's transmittance, sampled columns
-    T_gpu = np.exp(-tau)
+    # stack: 2^-tau (base-2 optical depth) against the oracle's transmittance, sampled columns
+    T_gpu = np.exp2(-tau)
     T_ref = np.stack([s16.column(i, j) for i, j in ij], axis=1)
     err_T = float(np.abs(T_gpu - T_ref).max())
     _, ref16, _, _ = O.render(o_f16, otf, s16, cam, mode, 0.5, opts, pixels=pix, want_full=False)
