@@ -31,9 +31,14 @@ def hipcc() -> str:
 
 
 def flags() -> list:
+    # VI_BUILD_DEFINES: extra -D options for experiments with the kernels'
+    # compile-time switches (e.g. "-DVI_RENDER_COMPACT=1"); empty by default
+    extra = os.environ.get("VI_BUILD_DEFINES", "").split()
+    if any(not e.startswith("-D") for e in extra):
+        raise RuntimeError("VI_BUILD_DEFINES takes -D options only")
     return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-function",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(ROOT, "include")]
+            "-I", os.path.join(ROOT, "include"), *extra]
 
 
 def build(verbose: bool = False) -> str:

@@ -433,12 +433,33 @@ __device__ __forceinline__ uint32_t group_bits(bool p, int base)
     return (uint32_t)((m >> base) & ((G == 32 ? 0xffffffffull : ((1ull << G) - 1ull))));
 }
 
-template <typename VT, int LAYOUT, int MODE, int SDT, int SL, int G>
-__device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf,
-                                             const int* __restrict__ s_next, const uint32_t* __restrict__ s_bits,
-                                             int px, int py, uint32_t& nsamp, uint32_t& nop)
+// Per-ray march state (identical in the G lanes of a ray's group): the ray
+// in offset-voxel coordinates, its light-grid maps, the cone basis or Phong
+// vectors, the empty-space cache and the compositing state.
+struct RayState {
+    float hx0, hy0, hz0, hdx, hdy, hdz;  // entry point and direction
+    float Df;                            // chord length, voxels
+    int K;                               // segments
+    float qz0, qx0, qy0, qdz, qdx, qdy, pd0, pdd;
+    ConeFrame cf;
+    float lx, ly, lz, vx, vy, vz, lv;
+    float ihx, ihy, ihz;
+    float Cr, Cg, Cb, T;
+    uint32_t last_cell;
+    bool cell_is_empty;
+    int k, count;
+};
+
+constexpr bool is_point_gather(int mode)
 {
-    const int lane = threadIdx.x & 63, g = lane % G, gbase = lane - g;
+    return mode == kModePointShadow || mode == kModePointShell || mode == kModePointCone;
+}
+
+// Ray set-up for pixel (px, py): false if the ray misses the cube (the pixel
+// is then the background).
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL, int G>
+__device__ __forceinline__ bool ray_setup(const RenderFrame& F, int px, int py, RayState& S)
+{
     // ---- camera ray, in offset-voxel coordinates, in float pairs (the
     // host folded the camera and the light grid into float-pair
     // coefficients of h; see F2): pixel (px, py) -> b = base + px sx + py sy
@@ -478,15 +499,22 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         if (t1 > tn) tn = t1, an = a, bn = near;
         if (t2 < tf_) tf_ = t2, af = a, bf = far;
     }
-    float4 bg = make_float4(F.bg[0], F.bg[1], F.bg[2], F.bg[3]);
-    if (!hit || af < 0 || !(tf_ > fmaxf(tn, 0.0f))) return bg;
-    const auto pick = [&](const F2* v, int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); };
-    const F2 ti = (an >= 0 && tn > 0.0f) ? f2_div(f2_sub(f2(bn), pick(o, an)), pick(d, an)) : f2(0.0f);
-    const F2 tf = f2_div(f2_sub(f2(bf), pick(o, af)), pick(d, af));
-    if (!f2_lt(ti, tf)) return bg;
+    if (!hit || af < 0 || !(tf_ > fmaxf(tn, 0.0f))) return false;
+    // the chosen faces' numerators and denominators, gathered with constant
+    // indices (a variable index would put o and d in scratch memory)
+    F2 on = f2(0.0f), dn = f2(1.0f), of = f2(0.0f), df = f2(1.0f);
+    for (int a = 0; a < 3; ++a) {
+        on = a == an ? o[a] : on;
+        dn = a == an ? d[a] : dn;
+        of = a == af ? o[a] : of;
+        df = a == af ? d[a] : df;
+    }
+    const F2 ti = (an >= 0 && tn > 0.0f) ? f2_div(f2_sub(f2(bn), on), dn) : f2(0.0f);
+    const F2 tf = f2_div(f2_sub(f2(bf), of), df);
+    if (!f2_lt(ti, tf)) return false;
 
     const F2 Dc = f2_sub(tf, ti);  // chord length, voxels
-    const float Df = Dc.hi;
+    S.Df = Dc.hi;
     int K;
     {
         // K = ceil(D / dt), decided on the pair
@@ -495,22 +523,29 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         if (c == q.hi && q.lo > 0.0f) c += 1.0f;
         else if (c - 1.0f - q.hi >= q.lo) c -= 1.0f;
         K = (int)c;
+        S.K = K;
     }
     // volume: entry point (value, remainder) and direction (value, remainder)
     F2 pin[3];
     for (int a = 0; a < 3; ++a) pin[a] = f2_add(o[a], f2_mul(ti, d[a]));
-    const float hx0 = pin[0].hi, hy0 = pin[1].hi, hz0 = pin[2].hi;
+    S.hx0 = pin[0].hi, S.hy0 = pin[1].hi, S.hz0 = pin[2].hi;
     const float hdx = d[0].hi, hdy = d[1].hi, hdz = d[2].hi;
+    S.hdx = hdx, S.hdy = hdy, S.hdz = hdz;
     // light grid: depth index (Eq. 9, minus one) and texel coordinates (Eq. 10)
     // (point light: qx / qy hold the lateral offsets U.(h - Ph), V.(h - Ph)
     // and pd the depth L.(h - Ph), all affine along the ray)
-    constexpr bool PT = MODE == kModePointShadow || MODE == kModePointShell || MODE == kModePointCone;
+    constexpr bool PT = is_point_gather(MODE);
     constexpr bool PTP = MODE == kModePointPhong, PHONG = MODE == VI_MODE_PHONG || PTP;
-    float qz0 = 0.f, qx0 = 0.f, qy0 = 0.f, qdz = 0.f, qdx = 0.f, qdy = 0.f, pd0 = 0.f, pdd = 0.f;
-    ConeFrame cf = {0.f, 0.f, 0.f, 0.f};
+    float& qz0 = S.qz0; float& qx0 = S.qx0; float& qy0 = S.qy0; float& qdz = S.qdz; float& qdx = S.qdx;
+    float& qdy = S.qdy; float& pd0 = S.pd0; float& pdd = S.pdd;
+    ConeFrame& cf = S.cf;
+    qz0 = qx0 = qy0 = qdz = qdx = qdy = pd0 = pdd = 0.f;
+    cf = ConeFrame{0.f, 0.f, 0.f, 0.f};
     // Phong: light vector l = -L and, folded in, l.v with v = -d
     // (point light: l is taken per sample toward P, and lx, ly, lz hold h_in - Ph)
-    float lx = 0.f, ly = 0.f, lz = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, lv = 0.f;
+    float& lx = S.lx; float& ly = S.ly; float& lz = S.lz; float& vx = S.vx; float& vy = S.vy; float& vz = S.vz;
+    float& lv = S.lv;
+    lx = ly = lz = vx = vy = vz = lv = 0.f;
     if (PHONG) {
         lx = -F.L[0];
         ly = -F.L[1];
@@ -571,14 +606,47 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
         }
     }
 
+    // C: premultiplied colour so far; T = 1 - alpha_dst, the transmittance in
+    // front of the next segment (kept as a product of exact per-segment
+    // factors, which keeps its relative precision down to term_eps).
+    S.Cr = S.Cg = S.Cb = 0.f;
+    S.T = 1.0f;
+    S.ihx = hdx != 0.f ? __builtin_amdgcn_rcpf(hdx) : 0.f;
+    S.ihy = hdy != 0.f ? __builtin_amdgcn_rcpf(hdy) : 0.f;
+    S.ihz = hdz != 0.f ? __builtin_amdgcn_rcpf(hdz) : 0.f;
+    S.last_cell = 0xffffffffu;
+    S.cell_is_empty = false;
+    S.k = 0;
+    S.count = K;
+    return true;
+}
+
+// One step of G segments of the ray's march (the G lanes of its group take
+// one segment each); true once the ray is done.
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL, int G>
+__device__ __forceinline__ bool ray_step(const RenderFrame& F, const float4* __restrict__ s_tf,
+                                         const int* __restrict__ s_next, const uint32_t* __restrict__ s_bits,
+                                         RayState& S, uint32_t& nop)
+{
+    const int lane = threadIdx.x & 63, g = lane % G, gbase = lane - g;
+    constexpr bool PT = is_point_gather(MODE);
+    constexpr bool PTP = MODE == kModePointPhong, PHONG = MODE == VI_MODE_PHONG || PTP;
+    const float hx0 = S.hx0, hy0 = S.hy0, hz0 = S.hz0, hdx = S.hdx, hdy = S.hdy, hdz = S.hdz;
+    const float qz0 = S.qz0, qx0 = S.qx0, qy0 = S.qy0, qdz = S.qdz, qdx = S.qdx, qdy = S.qdy, pd0 = S.pd0,
+                pdd = S.pdd;
+    const ConeFrame cf = S.cf;
+    const float lx = S.lx, ly = S.ly, lz = S.lz, vx = S.vx, vy = S.vy, vz = S.vz, lv = S.lv;
+    const float Df = S.Df, ihx = S.ihx, ihy = S.ihy, ihz = S.ihz;
+    const int K = S.K;
+    float& Cr = S.Cr; float& Cg = S.Cg; float& Cb = S.Cb; float& T = S.T;
+    uint32_t& last_cell = S.last_cell;
+    bool& cell_is_empty = S.cell_is_empty;
+    int& k = S.k;
+    int& count = S.count;
     const VT* __restrict__ vol = (const VT*)F.vol;
     const VolIndex VI_ = {1u, F.vsy, F.vsz};
     const float dtf = F.dt;
     const float Km1 = (float)(F.K - 1);
-    // C: premultiplied colour so far; T = 1 - alpha_dst, the transmittance in
-    // front of the next segment (kept as a product of exact per-segment
-    // factors, which keeps its relative precision down to term_eps).
-    float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
     // Empty-space traversal.  A group whose G segments all lie in
     // zero-opacity cells jumps to the last segment midpoint inside the empty
     // box around its last segment -- the segment's cell, or the cell's
@@ -588,162 +656,174 @@ __device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4*
     // boxes at the volume's edge toward the outside are at infinity (edge
     // cells also hold the clamped positions beyond the last voxel centre).
     const float kEps = 0.02f;
-    const float ihx = hdx != 0.f ? __builtin_amdgcn_rcpf(hdx) : 0.f, ihy = hdy != 0.f ? __builtin_amdgcn_rcpf(hdy) : 0.f,
-                ihz = hdz != 0.f ? __builtin_amdgcn_rcpf(hdz) : 0.f;
     const float Mf = (float)F.M;
-    uint32_t last_cell = 0xffffffffu;
-    bool cell_is_empty = false;
-    int k = 0, count = K;
-    for (;;) {
-        const int kk = k + g;
-        const bool in = kk < K;
-        float om = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;  // om = 1 - alpha of the segment
-        bool empty = true;
-        int cx = 0, cy = 0, cz = 0;  // the segment's cell
-        if (in) {
-            const float s0 = (float)kk * dtf;
-            const float s1 = fminf((float)(kk + 1) * dtf, Df);
-            const float len = s1 - s0;
-            const float sm = 0.5f * (s0 + s1);
-            const float hx = fmaf(sm, hdx, hx0), hy = fmaf(sm, hdy, hy0), hz = fmaf(sm, hdz, hz0);
-            empty = false;
-            if (F.occ.mm) {
-                const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1),
-                          gy = clampi((int)floorf(hy) + F.M, 0, F.N - 1),
-                          gz = clampi((int)floorf(hz) + F.M, 0, F.N - 1);
-                cx = gx >> F.occ.shift, cy = gy >> F.occ.shift, cz = gz >> F.occ.shift;
-                const uint32_t c = __umul24(__umul24((uint32_t)cz, F.occ.nc) + (uint32_t)cy, F.occ.nc) + (uint32_t)cx;
-                if (c != last_cell) {
-                    last_cell = c;
-                    cell_is_empty = !cell_occupied(F.occ, s_bits, c, s_next, Km1, F.K);
-                }
-                empty = cell_is_empty;
+    const int kk = k + g;
+    const bool in = kk < K;
+    float om = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;  // om = 1 - alpha of the segment
+    bool empty = true;
+    int cx = 0, cy = 0, cz = 0;  // the segment's cell
+    if (in) {
+        const float s0 = (float)kk * dtf;
+        const float s1 = fminf((float)(kk + 1) * dtf, Df);
+        const float len = s1 - s0;
+        const float sm = 0.5f * (s0 + s1);
+        const float hx = fmaf(sm, hdx, hx0), hy = fmaf(sm, hdy, hy0), hz = fmaf(sm, hdz, hz0);
+        empty = false;
+        if (F.occ.mm) {
+            const int gx = clampi((int)floorf(hx) + F.M, 0, F.N - 1),
+                      gy = clampi((int)floorf(hy) + F.M, 0, F.N - 1),
+                      gz = clampi((int)floorf(hz) + F.M, 0, F.N - 1);
+            cx = gx >> F.occ.shift, cy = gy >> F.occ.shift, cz = gz >> F.occ.shift;
+            const uint32_t c = __umul24(__umul24((uint32_t)cz, F.occ.nc) + (uint32_t)cy, F.occ.nc) + (uint32_t)cx;
+            if (c != last_cell) {
+                last_cell = c;
+                cell_is_empty = !cell_occupied(F.occ, s_bits, c, s_next, Km1, F.K);
             }
-            if (!empty) {
-                const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz);
-                const float x = v * Km1;
-                const int e0 = min((int)x, F.K - 2);
-                const float w = x - (float)e0;
-                const float4 ta = s_tf[e0], tb = s_tf[e0 + 1];
-                const float a = clampf01(fmaf(w, tb.w - ta.w, ta.w));
-                // (1 - alpha) of a segment of length len: (1 - a)^(len / dref)
-                if (len > 0.0f && a > 0.0f) om = fast_exp2(len * fast_log2(1.0f - a));
-                const float alpha = 1.0f - om;
-                if (alpha > 0.0f) {
-                    // emission alpha (sd rgb + ss) light: Eq. 7 with the
-                    // coefficient A, or the local Phong terms
-                    float sd, ss = 0.0f;
-                    if (PHONG) {
-                        // central differences one voxel either side (exact
-                        // offsets in voxel units)
-                        const float gx = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx + 1.f, hy, hz) -
-                                                 sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx - 1.f, hy, hz));
-                        const float gy = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy + 1.f, hz) -
-                                                 sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy - 1.f, hz));
-                        const float gz = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz + 1.f) -
-                                                 sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz - 1.f));
-                        const float gn = sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
-                        const float inv = -1.0f / fmaxf(gn, F.grad_eps);  // n = -g / max(|g|, eps)
-                        const float nx = gx * inv, ny = gy * inv, nz = gz * inv;
-                        float llx = lx, lly = ly, llz = lz, llv = lv;
-                        if (PTP) {
-                            // l = (P - p) / |P - p|
-                            const float rx = fmaf(sm, -vx, lx), ry = fmaf(sm, -vy, ly), rz = fmaf(sm, -vz, lz);
-                            const float ir = -__builtin_amdgcn_rsqf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
-                            llx = rx * ir;
-                            lly = ry * ir;
-                            llz = rz * ir;
-                            llv = fmaf(llx, vx, fmaf(lly, vy, llz * vz));
-                        }
-                        const float nl = fmaf(nx, llx, fmaf(ny, lly, nz * llz));
-                        const float nv = fmaf(nx, vx, fmaf(ny, vy, nz * vz));
-                        const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-                        const float rv = fmaf(2.0f * nl, nv, -nn * llv);  // r.v, r = 2(n.l)n - (n.n)l
-                        sd = fmaf(F.phong_kd, fmaxf(nl, 0.0f), F.phong_ka);
-                        if (rv > 0.0f) ss = F.phong_ks * fast_exp2(F.phong_shin * fast_log2(rv));
-                    } else {
-                        // (the nearest-face form is a second copy of the
-                        // gather behind a branch that is uniform per frame)
-                        float A = 1.0f;
-                        const float qz = fmaf(sm, qdz, qz0), qx = fmaf(sm, qdx, qx0), qy = fmaf(sm, qdy, qy0);
-                        if (PT) {
-                            const float pd = fmaf(sm, pdd, pd0);
-                            A = F.nearest ? gather_point<MODE, SDT, SL, true>(F, qz, pd, qx, qy, -pdd, -qdx, -qdy)
-                                          : gather_point<MODE, SDT, SL, false>(F, qz, pd, qx, qy, -pdd, -qdx, -qdy);
-                        } else if (MODE != VI_MODE_NONE) {
-                            A = F.nearest ? gather<MODE, SDT, SL, true>(F, cf, qz, qx, qy)
-                                          : gather<MODE, SDT, SL, false>(F, cf, qz, qx, qy);
-                        }
-                        sd = fmaf(1.0f - F.ambient, A, F.ambient);
+            empty = cell_is_empty;
+        }
+        if (!empty) {
+            const float v = sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz);
+            const float x = v * Km1;
+            const int e0 = min((int)x, F.K - 2);
+            const float w = x - (float)e0;
+            const float4 ta = s_tf[e0], tb = s_tf[e0 + 1];
+            const float a = clampf01(fmaf(w, tb.w - ta.w, ta.w));
+            // (1 - alpha) of a segment of length len: (1 - a)^(len / dref)
+            if (len > 0.0f && a > 0.0f) om = fast_exp2(len * fast_log2(1.0f - a));
+            const float alpha = 1.0f - om;
+            if (alpha > 0.0f) {
+                // emission alpha (sd rgb + ss) light: Eq. 7 with the
+                // coefficient A, or the local Phong terms
+                float sd, ss = 0.0f;
+                if (PHONG) {
+                    // central differences one voxel either side (exact
+                    // offsets in voxel units)
+                    const float gx = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx + 1.f, hy, hz) -
+                                             sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx - 1.f, hy, hz));
+                    const float gy = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy + 1.f, hz) -
+                                             sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy - 1.f, hz));
+                    const float gz = 0.5f * (sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz + 1.f) -
+                                             sample_volume<VT, LAYOUT>(vol, VI_, F.N, F.M, F.scale, hx, hy, hz - 1.f));
+                    const float gn = sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+                    const float inv = -1.0f / fmaxf(gn, F.grad_eps);  // n = -g / max(|g|, eps)
+                    const float nx = gx * inv, ny = gy * inv, nz = gz * inv;
+                    float llx = lx, lly = ly, llz = lz, llv = lv;
+                    if (PTP) {
+                        // l = (P - p) / |P - p|
+                        const float rx = fmaf(sm, -vx, lx), ry = fmaf(sm, -vy, ly), rz = fmaf(sm, -vz, lz);
+                        const float ir = -__builtin_amdgcn_rsqf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+                        llx = rx * ir;
+                        lly = ry * ir;
+                        llz = rz * ir;
+                        llv = fmaf(llx, vx, fmaf(lly, vy, llz * vz));
                     }
-                    cr = alpha * F.light[0] * fmaf(sd, fmaf(w, tb.x - ta.x, ta.x), ss);
-                    cg = alpha * F.light[1] * fmaf(sd, fmaf(w, tb.y - ta.y, ta.y), ss);
-                    cb = alpha * F.light[2] * fmaf(sd, fmaf(w, tb.z - ta.z, ta.z), ss);
-                }
-            }
-        }
-        if (group_bits<G>(empty, gbase) == ((G == 32) ? 0xffffffffu : ((1u << G) - 1u))) {
-            // every segment of this step is empty (or past the exit): jump,
-            // staying on multiples of G so that the steps group segments as a
-            // march without the map would (the products then round alike and
-            // the map changes no bit of the result).  Each lane finds the
-            // last segment inside the empty box around its own segment; the
-            // group takes its last lane's.
-            int jl = K;
-            if (in && F.occ.mm) {
-                int sh = F.occ.shift, bx = cx, by = cy, bz = cz, last = (int)F.occ.nc - 1;
-                if (F.occ.bits) {
-                    const int sx = cx >> 2, sy = cy >> 2, sz = cz >> 2;
-                    const uint32_t sc =
-                        __umul24(__umul24((uint32_t)sz, F.occ.snc) + (uint32_t)sy, F.occ.snc) + (uint32_t)sx;
-                    if (!occupancy_bit(s_bits + F.occ.words, sc)) {
-                        sh += 2;
-                        bx = sx, by = sy, bz = sz;
-                        last = (int)F.occ.snc - 1;
+                    const float nl = fmaf(nx, llx, fmaf(ny, lly, nz * llz));
+                    const float nv = fmaf(nx, vx, fmaf(ny, vy, nz * vz));
+                    const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+                    const float rv = fmaf(2.0f * nl, nv, -nn * llv);  // r.v, r = 2(n.l)n - (n.n)l
+                    sd = fmaf(F.phong_kd, fmaxf(nl, 0.0f), F.phong_ka);
+                    if (rv > 0.0f) ss = F.phong_ks * fast_exp2(F.phong_shin * fast_log2(rv));
+                } else {
+                    // (the nearest-face form is a second copy of the
+                    // gather behind a branch that is uniform per frame)
+                    float A = 1.0f;
+                    const float qz = fmaf(sm, qdz, qz0), qx = fmaf(sm, qdx, qx0), qy = fmaf(sm, qdy, qy0);
+                    if (PT) {
+                        const float pd = fmaf(sm, pdd, pd0);
+                        A = F.nearest ? gather_point<MODE, SDT, SL, true>(F, qz, pd, qx, qy, -pdd, -qdx, -qdy)
+                                      : gather_point<MODE, SDT, SL, false>(F, qz, pd, qx, qy, -pdd, -qdx, -qdy);
+                    } else if (MODE != VI_MODE_NONE) {
+                        A = F.nearest ? gather<MODE, SDT, SL, true>(F, cf, qz, qx, qy)
+                                      : gather<MODE, SDT, SL, false>(F, cf, qz, qx, qy);
                     }
+                    sd = fmaf(1.0f - F.ambient, A, F.ambient);
                 }
-                // distance along the ray to the box's exit faces, moved inward
-                const float edge = (float)(1 << sh) - kEps;
-                float se = 3.4e38f;
-                if (hdx > 0.f && bx < last) se = fminf(se, ((float)(bx << sh) - Mf + edge - hx0) * ihx);
-                if (hdx < 0.f && bx > 0) se = fminf(se, ((float)(bx << sh) - Mf + kEps - hx0) * ihx);
-                if (hdy > 0.f && by < last) se = fminf(se, ((float)(by << sh) - Mf + edge - hy0) * ihy);
-                if (hdy < 0.f && by > 0) se = fminf(se, ((float)(by << sh) - Mf + kEps - hy0) * ihy);
-                if (hdz > 0.f && bz < last) se = fminf(se, ((float)(bz << sh) - Mf + edge - hz0) * ihz);
-                if (hdz < 0.f && bz > 0) se = fminf(se, ((float)(bz << sh) - Mf + kEps - hz0) * ihz);
-                // last full segment whose midpoint (j + 1/2) dt is <= se
-                const float jf = floorf(fmaf(se, F.idt, -0.5f));
-                jl = jf >= (float)(K - 1) ? K - 1 : (int)jf;
+                cr = alpha * F.light[0] * fmaf(sd, fmaf(w, tb.x - ta.x, ta.x), ss);
+                cg = alpha * F.light[1] * fmaf(sd, fmaf(w, tb.y - ta.y, ta.y), ss);
+                cb = alpha * F.light[2] * fmaf(sd, fmaf(w, tb.z - ta.z, ta.z), ss);
             }
-            const int jlast = G == 1 ? jl : __shfl(jl, gbase + G - 1);
-            k = max(k + G, ((jlast + 1) / G) * G);
-            if (k >= K) break;
-            continue;
         }
-        // front-to-back over the G segments of this step (Eq. 3 in product form)
-        const float incl = group_scan_mul<G>(om, g);                  // prod_{h<=g} (1 - alpha_h)
-        // every lane of the group takes part in the shuffle (a lane that sat
-        // out would hand its neighbour no value)
-        const float up = G == 1 ? 1.0f : __shfl_up(incl, 1, G);
-        const float excl = g == 0 ? 1.0f : up;
-        const uint32_t tb_ = group_bits<G>(in && T * incl <= F.term_eps, gbase);
-        const int gs = tb_ ? __ffs(tb_) - 1 : G;                     // terminating segment, G if none
-        const float keep = (g <= gs) ? T * excl : 0.0f;
-        nop += (in && g <= gs && om < 1.0f) ? 1u : 0u;  // composited with non-zero opacity
-        Cr += group_sum<G>(keep * cr);
-        Cg += group_sum<G>(keep * cg);
-        Cb += group_sum<G>(keep * cb);
-        const float prod = G == 1 ? incl : __shfl(incl, gbase + min(gs, G - 1));
-        T *= prod;
-        if (gs < G) {
-            count = k + gs + 1;
-            break;
-        }
-        k += G;
-        if (k >= K) break;
     }
-    if (g == 0) nsamp += (uint32_t)min(count, K);
-    return make_float4(fmaf(T, bg.x, Cr), fmaf(T, bg.y, Cg), fmaf(T, bg.z, Cb), fmaf(T, bg.w, 1.0f - T));
+    if (group_bits<G>(empty, gbase) == ((G == 32) ? 0xffffffffu : ((1u << G) - 1u))) {
+        // every segment of this step is empty (or past the exit): jump,
+        // staying on multiples of G so that the steps group segments as a
+        // march without the map would (the products then round alike and
+        // the map changes no bit of the result).  Each lane finds the
+        // last segment inside the empty box around its own segment; the
+        // group takes its last lane's.
+        int jl = K;
+        if (in && F.occ.mm) {
+            int sh = F.occ.shift, bx = cx, by = cy, bz = cz, last = (int)F.occ.nc - 1;
+            if (F.occ.bits) {
+                const int sx = cx >> 2, sy = cy >> 2, sz = cz >> 2;
+                const uint32_t sc =
+                    __umul24(__umul24((uint32_t)sz, F.occ.snc) + (uint32_t)sy, F.occ.snc) + (uint32_t)sx;
+                if (!occupancy_bit(s_bits + F.occ.words, sc)) {
+                    sh += 2;
+                    bx = sx, by = sy, bz = sz;
+                    last = (int)F.occ.snc - 1;
+                }
+            }
+            // distance along the ray to the box's exit faces, moved inward
+            const float edge = (float)(1 << sh) - kEps;
+            float se = 3.4e38f;
+            if (hdx > 0.f && bx < last) se = fminf(se, ((float)(bx << sh) - Mf + edge - hx0) * ihx);
+            if (hdx < 0.f && bx > 0) se = fminf(se, ((float)(bx << sh) - Mf + kEps - hx0) * ihx);
+            if (hdy > 0.f && by < last) se = fminf(se, ((float)(by << sh) - Mf + edge - hy0) * ihy);
+            if (hdy < 0.f && by > 0) se = fminf(se, ((float)(by << sh) - Mf + kEps - hy0) * ihy);
+            if (hdz > 0.f && bz < last) se = fminf(se, ((float)(bz << sh) - Mf + edge - hz0) * ihz);
+            if (hdz < 0.f && bz > 0) se = fminf(se, ((float)(bz << sh) - Mf + kEps - hz0) * ihz);
+            // last full segment whose midpoint (j + 1/2) dt is <= se
+            const float jf = floorf(fmaf(se, F.idt, -0.5f));
+            jl = jf >= (float)(K - 1) ? K - 1 : (int)jf;
+        }
+        const int jlast = G == 1 ? jl : __shfl(jl, gbase + G - 1);
+        k = max(k + G, ((jlast + 1) / G) * G);
+        if (k >= K) return true;
+        return false;
+    }
+    // front-to-back over the G segments of this step (Eq. 3 in product form)
+    const float incl = group_scan_mul<G>(om, g);                  // prod_{h<=g} (1 - alpha_h)
+    // every lane of the group takes part in the shuffle (a lane that sat
+    // out would hand its neighbour no value)
+    const float up = G == 1 ? 1.0f : __shfl_up(incl, 1, G);
+    const float excl = g == 0 ? 1.0f : up;
+    const uint32_t tb_ = group_bits<G>(in && T * incl <= F.term_eps, gbase);
+    const int gs = tb_ ? __ffs(tb_) - 1 : G;                     // terminating segment, G if none
+    const float keep = (g <= gs) ? T * excl : 0.0f;
+    nop += (in && g <= gs && om < 1.0f) ? 1u : 0u;  // composited with non-zero opacity
+    Cr += group_sum<G>(keep * cr);
+    Cg += group_sum<G>(keep * cg);
+    Cb += group_sum<G>(keep * cb);
+    const float prod = G == 1 ? incl : __shfl(incl, gbase + min(gs, G - 1));
+    T *= prod;
+    if (gs < G) {
+        count = k + gs + 1;
+        return true;
+    }
+    k += G;
+    return k >= K;
+}
+
+// The finished ray's colour over the background, and its segment count.
+__device__ __forceinline__ float4 ray_result(const RenderFrame& F, const RayState& S)
+{
+    return make_float4(fmaf(S.T, F.bg[0], S.Cr), fmaf(S.T, F.bg[1], S.Cg), fmaf(S.T, F.bg[2], S.Cb),
+                       fmaf(S.T, F.bg[3], 1.0f - S.T));
+}
+
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL, int G>
+__device__ __forceinline__ float4 render_ray(const RenderFrame& F, const float4* __restrict__ s_tf,
+                                             const int* __restrict__ s_next, const uint32_t* __restrict__ s_bits,
+                                             int px, int py, uint32_t& nsamp, uint32_t& nop)
+{
+    RayState S;
+    if (!ray_setup<VT, LAYOUT, MODE, SDT, SL, G>(F, px, py, S))
+        return make_float4(F.bg[0], F.bg[1], F.bg[2], F.bg[3]);
+    while (!ray_step<VT, LAYOUT, MODE, SDT, SL, G>(F, s_tf, s_next, s_bits, S, nop)) {
+    }
+    if ((threadIdx.x & 63) % G == 0) nsamp += (uint32_t)min(S.count, S.K);
+    return ray_result(F, S);
 }
 
 // --------------------------------------------------------------------------
@@ -793,6 +873,70 @@ __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* 
     }
 }
 
+// Ray compaction (VI_RENDER_COMPACT = 1): a wave owns four blocks of
+// (64 / kG) rays and its groups take the next ray of the wave's list as they
+// finish, a refill at a time once at least VI_COMPACT_REFILL groups are idle
+// (a refill runs the set-up code for the whole wave, so one per finished
+// ray would cost more than the idle lanes it saves).  The per-ray
+// arithmetic is unchanged, so the image and counts are the same bits as
+// with one block per wave.
+#ifndef VI_RENDER_COMPACT
+#define VI_RENDER_COMPACT 0
+#endif
+#ifndef VI_COMPACT_REFILL
+#define VI_COMPACT_REFILL 8
+#endif
+constexpr bool kCompact = VI_RENDER_COMPACT != 0;
+
+template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
+__device__ __forceinline__ void shade_region_compact(const RenderFrame& F, const float4* s_tf, const int* s_next,
+                                                     const uint32_t* s_bits, int x0, int y0)
+{
+    constexpr int kGroups = 64 / kG, kRays = 4 * kGroups;
+    const int lane = threadIdx.x & 63, g = lane % kG, grp = lane / kG;
+    RayState S;
+    bool live = false;
+    int px = 0, py = 0, next = 0;  // next: the wave's next ray (uniform)
+    uint32_t ns = 0, nop = 0;
+    for (;;) {
+        const uint64_t idle = __ballot(!live && g == 0);
+        const int nidle = __popcll(idle);
+        if (next < kRays && (nidle >= VI_COMPACT_REFILL || nidle == kGroups)) {
+            if (!live) {
+                const int r = next + __popcll(idle & ((1ull << (grp * kG)) - 1ull));
+                if (r < kRays) {
+                    const int b = r / kGroups, i = r % kGroups;
+                    px = x0 + (b & 1) * kWX + i % kWX;
+                    py = y0 + (b >> 1) * kWY + i / kWX;
+                    if (px < F.width && py < F.height) {
+                        live = ray_setup<VT, LAYOUT, MODE, SDT, SL, kG>(F, px, py, S);
+                        if (!live && g == 0)
+                            F.out[(size_t)py * F.width + px] = make_float4(F.bg[0], F.bg[1], F.bg[2], F.bg[3]);
+                    }
+                }
+            }
+            next += nidle;
+            continue;
+        }
+        if (nidle == kGroups) break;  // nothing live, nothing left
+        if (live && ray_step<VT, LAYOUT, MODE, SDT, SL, kG>(F, s_tf, s_next, s_bits, S, nop)) {
+            if (g == 0) {
+                ns += (uint32_t)min(S.count, S.K);
+                F.out[(size_t)py * F.width + px] = ray_result(F, S);
+            }
+            live = false;
+        }
+    }
+    if (F.samples) {
+        for (int off = 32; off > 0; off >>= 1) {
+            ns += __shfl_xor(ns, off);
+            nop += __shfl_xor(nop, off);
+        }
+        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
+        if (lane == 0 && nop && F.count_opaque) atomicAdd(F.samples + 1, (unsigned long long)nop);
+    }
+}
+
 // --------------------------------------------------------------------------
 // single-frame kernel
 // --------------------------------------------------------------------------
@@ -808,12 +952,23 @@ __device__ __forceinline__ void render_frame(const RenderFrame& F)
     stage_occupancy(F.occ, s_bits);
     __syncthreads();
 
-    const uint32_t tiles_x = (F.width + kBX - 1) / kBX, tiles_y = (F.height + kBY - 1) / kBY;
-    uint32_t tx, ty;
-    if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
-    int px, py;
-    block_pixel(tx, ty, &px, &py);
-    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, px, py);
+    if constexpr (kCompact) {
+        // workgroup tile of 2 x 2 waves, each 2 x 2 blocks of kWX x kWY pixels
+        const uint32_t tiles_x = (F.width + 4 * kWX - 1) / (4 * kWX), tiles_y = (F.height + 4 * kWY - 1) / (4 * kWY);
+        uint32_t tx, ty;
+        if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
+        const int wave = threadIdx.x >> 6;
+        shade_region_compact<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits,
+                                                        (int)tx * 4 * kWX + (wave & 1) * 2 * kWX,
+                                                        (int)ty * 4 * kWY + (wave >> 1) * 2 * kWY);
+    } else {
+        const uint32_t tiles_x = (F.width + kBX - 1) / kBX, tiles_y = (F.height + kBY - 1) / kBY;
+        uint32_t tx, ty;
+        if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
+        int px, py;
+        block_pixel(tx, ty, &px, &py);
+        shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, px, py);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -967,7 +1122,8 @@ hipError_t launch_render_batch(int vol_dtype, int layout, int stack_dtype, int s
 template <typename VT, int LAYOUT, int SDT, int SL>
 static hipError_t launch_mode(const RenderFrame& f, hipStream_t s)
 {
-    dim3 grid(supertile_grid((f.width + kBX - 1) / kBX, (f.height + kBY - 1) / kBY)), block(256);
+    const uint32_t tw = kCompact ? 4 * kWX : kBX, th = kCompact ? 4 * kWY : kBY;
+    dim3 grid(supertile_grid((f.width + tw - 1) / tw, (f.height + th - 1) / th)), block(256);
     const size_t lds =
         (sizeof(float4) + sizeof(int)) * (size_t)f.K + (f.occ.bits ? sizeof(uint32_t) * (f.occ.words + f.occ.swords) : 0);
     switch (kernel_mode(f)) {
