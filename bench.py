@@ -516,7 +516,13 @@ def main():
     Wd, Hd = cam0["width"], cam0["height"]
     precision = w.name == "precision"
     if precision:
-        m = measure_steps(w, W.to_f16_normalised(raw), 1.0, tab, lights, modes, vi.VI_BF16, args, dev)
+        f16 = W.to_f16_normalised(raw)
+        m = measure_steps(w, f16, 1.0, tab, lights, modes, vi.VI_BF16, args, dev)
+        m_half = None
+        if STACK_LAYOUT == vi.VI_STACK_ROWS:
+            log("half-precision transmittance stack on the same FP16 volume ...")
+            m_half = measure_steps(w, f16, 1.0, tab, lights, modes, vi.VI_F16, args, dev)
+        del f16
         log("FP32 path on the same volume for comparison ...")
         m_fp32 = measure_steps(w, raw, None, tab, lights, modes, vi.VI_F32, args, dev)
     else:
@@ -622,10 +628,15 @@ def main():
         "roofline": roofline,
     }
     if precision:
-        result["fp32_path_same_volume"] = {"ms_per_step": round(m_fp32["wall"] * 1e3 / args.steps, 4),
-                                           "build_ms_mean": round(float(np.mean(m_fp32["build_ms"])), 4),
-                                           **{f"render_{k}_ms_mean": round(float(np.mean(v)), 4)
-                                              for k, v in m_fp32["render_ms"].items()}}
+        def leg(mm):
+            return {"ms_per_step": round(mm["wall"] * 1e3 / args.steps, 4),
+                    "build_ms_mean": round(float(np.mean(mm["build_ms"])), 4),
+                    **{f"render_{k}_ms_mean": round(float(np.mean(v)), 4) for k, v in mm["render_ms"].items()}}
+        result["fp32_path_same_volume"] = leg(m_fp32)
+        if m_half is not None:
+            # the same FP16 volume with a half-precision transmittance stack
+            # (optical depth summed in float, stored as 2^-tau): no exponential per texel
+            result["half_stack_same_volume"] = leg(m_half)
     if not args.no_serving and not precision:
         log("serving leg ...")
         torch.cuda.empty_cache()

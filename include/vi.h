@@ -78,7 +78,7 @@ typedef void* vi_stream_t; /* a hipStream_t */
 typedef enum {
     VI_U8 = 0,   /* volume: unsigned 8-bit                              */
     VI_U16 = 1,  /* volume: unsigned 16-bit                             */
-    VI_F16 = 2,  /* volume: IEEE half                                   */
+    VI_F16 = 2,  /* volume: IEEE half; stack: half transmittance (rows)  */
     VI_F32 = 3,  /* volume: float; stack: float transmittance           */
     VI_BF16 = 4  /* stack: bfloat16 optical depth -log2 T (precision form) */
 } vi_dtype;
@@ -156,10 +156,10 @@ typedef struct {
  *     fully transmitting texels (T = 1, optical depth 0) around the grid,
  *     and one leading layer k = -1 that transmits fully everywhere (face 0
  *     of the depth index of Eq. 9).  The two texels of a bilinear row,
- *     (k, j, i) and (k, j, i+1), are adjacent, so one 8-byte load per row
+ *     (k, j, i) and (k, j, i+1), are adjacent, so one load per row
  *     reads them, and every footprint of a lookup, clamped to i, j in
  *     [-2, res] and k in [-1, n-1], reads stored texels only.  With row
- *     pitch P = res+4 (bfloat16: res+6) rounded up to 4 and LS = (res+4)*P,
+ *     pitch P = res+4 rounded up to 4 and LS = (res+4)*P,
  *     texel (k, j, i), k in [-1, n-1], i and j in [-2, res+1], is element
  *     (k+1)*LS + (j+2)*P + (i+2); (n+1)*LS elements (columns res+4 .. P-1
  *     are never used). */
@@ -173,7 +173,7 @@ typedef enum { VI_STACK_TILED = 0, VI_STACK_ROWS = 1 } vi_stack_layout;
  * Geometry is kept in double as computed on the host (Eq. 8). */
 typedef struct {
     void* data;
-    int dtype;          /* VI_F32 or VI_BF16 */
+    int dtype;          /* VI_F32, VI_BF16 or VI_F16 (VI_F16: row layout only) */
     int layout;         /* VI_STACK_TILED or VI_STACK_ROWS */
     int n, res;         /* slabs, texels per side */
     double L[3];        /* unit propagation direction */
@@ -258,8 +258,9 @@ const char* vi_last_error(void);
 /* Fill `o` with the defaults listed above.  Returns VI_E_INVALID_ARG on NULL. */
 int vi_default_render_opts(vi_render_opts* o);
 
-/* Bytes of a stack buffer (element 4 bytes for VI_F32, 2 for VI_BF16):
- * tiled n*R8*R4 elements, rows n*LS elements; 0 for invalid arguments. */
+/* Bytes of a stack buffer (element 4 bytes for VI_F32, 2 for VI_BF16 and
+ * VI_F16): tiled n*R8*R4 elements, rows (n+1)*LS elements; 0 for invalid
+ * arguments (VI_F16 with the tiled layout included). */
 size_t vi_slices_bytes(int n_slices, int slice_res, int slice_dtype, int slice_layout);
 
 /* Bytes of a volume of edge n, dtype and layout (0 for invalid arguments). */
@@ -325,9 +326,12 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
  * `light_dir` into `d_slices` (device, vi_slices_bytes bytes, 16-byte
  * aligned, layout `slice_layout`) and describe it in `out_desc` (host).  One kernel launch on
  * `stream`.  slice_dtype: VI_F32 (transmittance, product of per-slab
- * (1-alpha)) or VI_BF16 (optical depth in base-2 units, -log2 T: the
+ * (1-alpha)), VI_BF16 (optical depth in base-2 units, -log2 T: the
  * per-slab extinction over ln 2 summed in float and rounded to bfloat16 per
- * layer; each slab adds at most 64 / ln 2, a factor e^-64).
+ * layer; each slab adds at most 64 / ln 2, a factor e^-64) or VI_F16 (row
+ * layout only: the same float optical depth stored as its transmittance
+ * 2^-tau rounded to half precision, so that lookups need no exponential;
+ * transmittances below 2^-24 round to 0).
  * `opts` may be NULL (directional light, plain product).
  * Errors: VI_E_INVALID_ARG for NULL pointers, bad sizes, a degenerate
  * light or options out of range; VI_E_UNSUPPORTED for dtypes or sizes

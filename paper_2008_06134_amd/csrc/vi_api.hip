@@ -155,12 +155,10 @@ bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_by
 // Row layout: every layer has rows -2 .. res+1 and columns -2 .. res+1 of
 // texels, the two outermost rings a fully transmitting border; one extra
 // leading layer (-1, face 0 of Eq. 9's index) transmits fully too.  The
-// pitch is res + 4 rounded up to 4 (res + 6 for bfloat16, whose pair reads
-// take the aligned 4-element window holding the pair, so that the window of
-// the last pair stays inside its row).  (Rows aligned to 128-byte lines were
+// pitch is res + 4 rounded up to 4.  (Rows aligned to 128-byte lines were
 // measured slower: a line-multiple pitch maps the rows of a footprint onto
 // fewer cache sets.)
-uint32_t row_pitch(int res, int dt) { return vi::round_up((uint32_t)res + (dt == VI_BF16 ? 6u : 4u), 4u); }
+uint32_t row_pitch(int res, int) { return vi::round_up((uint32_t)res + 4u, 4u); }
 uint32_t row_layer(int res, int dt) { return ((uint32_t)res + 4u) * row_pitch(res, dt); }
 // element of texel (k, j, i) = (0, 0, 0): past the front layer, two rows and two columns of border
 uint32_t row_origin(int res, int dt) { return row_layer(res, dt) + 2u * row_pitch(res, dt) + 2u; }
@@ -237,8 +235,9 @@ int fill_frame(const double l[3], int n, int res, int dt, int sl, const vi_build
     if ((!l && !point) || !f) return fail(VI_E_INVALID_ARG, "NULL light direction or descriptor");
     if (n < 1 || n > 4096) return fail(VI_E_INVALID_ARG, "n_slices %d outside 1..4096", n);
     if (res < 1 || res > 8192) return fail(VI_E_INVALID_ARG, "slice_res %d outside 1..8192", res);
-    if (dt != VI_F32 && dt != VI_BF16) return fail(VI_E_UNSUPPORTED, "slice dtype %d not supported", dt);
+    if (dt != VI_F32 && dt != VI_BF16 && dt != VI_F16) return fail(VI_E_UNSUPPORTED, "slice dtype %d not supported", dt);
     if (sl != VI_STACK_TILED && sl != VI_STACK_ROWS) return fail(VI_E_UNSUPPORTED, "slice layout %d not supported", sl);
+    if (dt == VI_F16 && sl != VI_STACK_ROWS) return fail(VI_E_UNSUPPORTED, "a half-precision stack needs the row layout");
     if (point) return fill_point_frame(o->position, n, res, dt, sl, f);
     if (!isfinite(l[0]) || !isfinite(l[1]) || !isfinite(l[2]))
         return fail(VI_E_INVALID_ARG, "light direction is not finite");
@@ -299,7 +298,8 @@ int vi_default_render_opts(vi_render_opts* o)
 
 size_t vi_slices_bytes(int n, int res, int dt, int sl)
 {
-    if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16)) return 0;
+    if (n < 1 || res < 1 || (dt != VI_F32 && dt != VI_BF16 && dt != VI_F16)) return 0;
+    if (sl == VI_STACK_TILED && dt == VI_F16) return 0;
     if (sl == VI_STACK_TILED)
         return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
     if (sl == VI_STACK_ROWS) return ((size_t)n + 1u) * row_layer(res, dt) * elem_size(dt);
@@ -591,9 +591,12 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
     }
     if (reads_stack) {
         if (!sl || !sl->data) return fail(VI_E_INVALID_ARG, "mode %d needs a stack", mode);
-        if (sl->dtype != VI_F32 && sl->dtype != VI_BF16) return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);
+        if (sl->dtype != VI_F32 && sl->dtype != VI_BF16 && sl->dtype != VI_F16)
+            return fail(VI_E_UNSUPPORTED, "stack dtype %d", sl->dtype);
         if (sl->layout != VI_STACK_TILED && sl->layout != VI_STACK_ROWS)
             return fail(VI_E_UNSUPPORTED, "stack layout %d", sl->layout);
+        if (sl->dtype == VI_F16 && sl->layout != VI_STACK_ROWS)
+            return fail(VI_E_UNSUPPORTED, "a half-precision stack needs the row layout");
         if (((uintptr_t)sl->data) % 16) return fail(VI_E_INVALID_ARG, "stack buffer must be 16-byte aligned");
         if (sl->n < 1 || sl->res < 1) return fail(VI_E_INVALID_ARG, "stack descriptor has no size");
         if (sl->vol_n != vol->n)

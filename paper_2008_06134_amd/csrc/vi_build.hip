@@ -158,13 +158,15 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// One stack texel: transmittance, or (BF16 form) optical depth in base-2
-// units, -log2 T.
+// One stack texel: transmittance (F32), optical depth in base-2 units
+// -log2 T (BF16), or the transmittance 2^-tau of the float optical depth
+// rounded to half precision (F16).
 template <int OUT_DTYPE>
 __device__ __forceinline__ void put_texel(void* out, uint32_t at, float T, float tau)
 {
     if (OUT_DTYPE == VI_F32) ((float*)out)[at] = T;
-    else ((uint16_t*)out)[at] = f32_to_bf16(tau);
+    else if (OUT_DTYPE == VI_BF16) ((uint16_t*)out)[at] = f32_to_bf16(tau);
+    else ((__half*)out)[at] = __float2half_rn(fast_exp2(-tau));
 }
 
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool PT>
@@ -364,8 +366,10 @@ static void launch_build_k(const BuildParams& p, dim3 grid, size_t lds, hipStrea
 {
     if (p.out_dtype == VI_F32)
         hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F32, SL, PT>), grid, dim3(kBuildNT), lds, s, p);
-    else
+    else if (p.out_dtype == VI_BF16)
         hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_BF16, SL, PT>), grid, dim3(kBuildNT), lds, s, p);
+    else if constexpr (SL == VI_STACK_ROWS)
+        hipLaunchKernelGGL((build_kernel<VT, LAYOUT, VI_F16, SL, PT>), grid, dim3(kBuildNT), lds, s, p);
 }
 
 template <typename VT, int LAYOUT>
@@ -384,9 +388,9 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
         if (p.out_dtype == VI_F32)
             hipLaunchKernelGGL((border_kernel<float>), bgrid, dim3(256), 0, s, (float*)p.out, p.n, p.res, p.rlayer,
                                p.rpitch, p.rorg, 1.0f);
-        else
+        else  // bfloat16 optical depth 0, or half-precision transmittance 1
             hipLaunchKernelGGL((border_kernel<uint16_t>), bgrid, dim3(256), 0, s, (uint16_t*)p.out, p.n, p.res,
-                               p.rlayer, p.rpitch, p.rorg, (uint16_t)0);
+                               p.rlayer, p.rpitch, p.rorg, (uint16_t)(p.out_dtype == VI_F16 ? 0x3c00u : 0u));
     } else {
         if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_TILED, true>(p, grid, lds, s);
         else launch_build_k<VT, LAYOUT, VI_STACK_TILED, false>(p, grid, lds, s);

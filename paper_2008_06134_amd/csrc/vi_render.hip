@@ -27,7 +27,8 @@ namespace vi {
 // A float stack holds transmittance T; a bfloat16 stack holds optical depth
 // in base-2 units, tau2 = -log2 T (Eq. 6's exponent summed over the slabs in
 // front, over ln 2), so that each texel converts to T = 2^-tau2 with one
-// exponential before the interpolation.
+// exponential before the interpolation; a half-precision stack holds T
+// (from the float optical depth), converted with no exponential.
 template <int SDT>
 __device__ __forceinline__ float stack_texel(const void* __restrict__ S, uint32_t idx);
 
@@ -40,6 +41,11 @@ template <>
 __device__ __forceinline__ float stack_texel<VI_BF16>(const void* __restrict__ S, uint32_t idx)
 {
     return fast_exp2(-bf16_to_f32(((const uint16_t*)S)[idx]));
+}
+template <>
+__device__ __forceinline__ float stack_texel<VI_F16>(const void* __restrict__ S, uint32_t idx)
+{
+    return __half2float(((const __half*)S)[idx]);
 }
 
 // Row layout: the two texels (i, i+1) of one bilinear row, element e and
@@ -54,6 +60,7 @@ typedef uint32_t u32_a2 __attribute__((aligned(2)));
 template <int SDT> struct PairRaw;
 template <> struct PairRaw<VI_F32> { f32x2_a4 v; };
 template <> struct PairRaw<VI_BF16> { uint32_t w; };
+template <> struct PairRaw<VI_F16> { uint32_t w; };
 
 template <int SDT>
 __device__ __forceinline__ PairRaw<SDT> pair_load(const void* __restrict__ S, uint32_t e);
@@ -67,7 +74,17 @@ __device__ __forceinline__ PairRaw<VI_BF16> pair_load<VI_BF16>(const void* __res
 {
     return PairRaw<VI_BF16>{*(const u32_a2*)((const uint16_t*)S + e)};
 }
+template <>
+__device__ __forceinline__ PairRaw<VI_F16> pair_load<VI_F16>(const void* __restrict__ S, uint32_t e)
+{
+    return PairRaw<VI_F16>{*(const u32_a2*)((const uint16_t*)S + e)};
+}
 __device__ __forceinline__ float2 pair_value(const PairRaw<VI_F32>& r) { return make_float2(r.v.x, r.v.y); }
+__device__ __forceinline__ float2 pair_value(const PairRaw<VI_F16>& r)
+{
+    return make_float2(__half2float(__ushort_as_half((unsigned short)(r.w & 0xffffu))),
+                       __half2float(__ushort_as_half((unsigned short)(r.w >> 16))));
+}
 __device__ __forceinline__ float2 pair_value(const PairRaw<VI_BF16>& r)
 {
     // element e in the low half, e + 1 in the high half (little-endian)
@@ -1091,6 +1108,8 @@ static hipError_t launch_batch_l(int sdt, int sl, int mode, const RenderFrame* f
     if (sdt == VI_BF16)
         return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(mode, f, t, n, K, w, s)
                                    : launch_batch_t<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(mode, f, t, n, K, w, s);
+    if (sdt == VI_F16)  // row layout only
+        return launch_batch_t<VT, LAYOUT, VI_F16, VI_STACK_ROWS>(mode, f, t, n, K, w, s);
     return sl == VI_STACK_ROWS ? launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(mode, f, t, n, K, w, s)
                                : launch_batch_t<VT, LAYOUT, VI_F32, VI_STACK_TILED>(mode, f, t, n, K, w, s);
 }
@@ -1168,6 +1187,8 @@ static hipError_t launch_sdt(const RenderFrame& f, hipStream_t s)
     const bool q = f.stack_layout == VI_STACK_ROWS;
     if (f.stack_dtype == VI_BF16)
         return q ? launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_ROWS>(f, s) : launch_mode<VT, LAYOUT, VI_BF16, VI_STACK_TILED>(f, s);
+    if (f.stack_dtype == VI_F16)  // row layout only
+        return launch_mode<VT, LAYOUT, VI_F16, VI_STACK_ROWS>(f, s);
     return q ? launch_mode<VT, LAYOUT, VI_F32, VI_STACK_ROWS>(f, s) : launch_mode<VT, LAYOUT, VI_F32, VI_STACK_TILED>(f, s);
 }
 

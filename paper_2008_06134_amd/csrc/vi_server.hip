@@ -19,7 +19,7 @@ namespace {
 constexpr int kSlots = 4;           // staging slots (> launches in flight)
 constexpr int kMaxLaunchFrames = 64;
 
-int slice_elem(int dt) { return dt == VI_BF16 ? 2 : 4; }
+int slice_elem(int dt) { return dt == VI_F32 ? 4 : 2; }
 
 class HipExecutor final : public sched::Executor {
 public:

@@ -284,8 +284,8 @@ def row_origin(dtype: int = VI_F32) -> int:
 
 
 def row_pitch(res: int, dtype: int = VI_F32) -> int:
-    """Row pitch of the row layout: res + 4 (bfloat16: res + 6) rounded up to 4."""
-    return (res + (6 if dtype == VI_BF16 else 4) + 3) // 4 * 4
+    """Row pitch of the row layout: res + 4 rounded up to 4 (every stack dtype)."""
+    return (res + 4 + 3) // 4 * 4
 
 
 @dataclass
@@ -384,7 +384,7 @@ def slices_bytes(n: int, res: int, dtype: int = VI_F32, layout: int = VI_STACK_T
 
 def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda", layout: int = VI_STACK_TILED) -> torch.Tensor:
     """An uninitialised device buffer in a stack layout (shapes as in Slices)."""
-    tdt = torch.float32 if dtype == VI_F32 else torch.bfloat16
+    tdt = {VI_F32: torch.float32, VI_BF16: torch.bfloat16, VI_F16: torch.float16}[dtype]
     if layout == VI_STACK_ROWS:
         return torch.empty((n + 1, res + 4, row_pitch(res, dtype)), dtype=tdt, device=device)
     r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
@@ -408,7 +408,7 @@ def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: 
                       out: torch.Tensor | None = None, stream=None, layout: int = VI_STACK_TILED,
                       darken: float = 0.0, position=None) -> Slices:
     """Attenuation stack for `light_dir` (section 3.2.1, Alg. 1); returns the stack
-    (float32 transmittance, or bfloat16 optical depth -log2 T) and its descriptor.  `darken`
+    (float32 transmittance, bfloat16 optical depth -log2 T, or float16 transmittance) and its descriptor.  `darken`
     is the exponent m of section 4's (1+alpha)^m slab compensation (0 = off);
     `position` (world xyz) builds for a point light there instead (`light_dir`
     is then ignored and may be None)."""

@@ -280,7 +280,9 @@ def test_volume_bytes_and_brick_validation():
     assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4
     # rows: n+1 layers of res+4 rows, pitch res+4 (bfloat16 res+6) rounded up to 4
     assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_ROWS) == 4 * 14 * 16 * 4
-    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_ROWS) == 3 * 1028 * 1032 * 2
+    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_ROWS) == 3 * 1028 * 1028 * 2
+    assert vi.slices_bytes(2, 1024, vi.VI_F16, vi.VI_STACK_ROWS) == 3 * 1028 * 1028 * 2
+    assert vi.slices_bytes(2, 1024, vi.VI_F16, vi.VI_STACK_TILED) == 0
     assert vi.slices_bytes(2, 1024, vi.VI_F32, vi.VI_STACK_ROWS) == 3 * 1028 * 1028 * 4
     assert vi.slices_bytes(2, 8, vi.VI_F32, 5) == 0
 

@@ -405,6 +405,31 @@ def test_row_layout_matches_its_definition(res, dtype):
     assert torch.equal(r.dense(), D)
 
 
+@pytest.mark.parametrize("res", [1, 19, 64])
+def test_half_stack_matches_its_definition(res):
+    """Half-precision stack (row layout only): border and leading layer hold 1, every texel
+    is the float stack's transmittance within half precision's rounding (relative 2^-11,
+    plus the float optical depth's own rounding), and the tiled layout is refused."""
+    raw = W.sphere_u8(30, radius=10, density=200, noise=30, seed=res)
+    vol, tf = gpu_inputs(raw, W.tf_ramp())
+    light, n = [0.3, -0.5, 0.8], 11
+    f = vi.build_attenuation(vol, tf, light, n, res, vi.VI_F32, layout=vi.VI_STACK_ROWS)
+    h = vi.build_attenuation(vol, tf, light, n, res, vi.VI_F16, layout=vi.VI_STACK_ROWS)
+    torch.cuda.synchronize()
+    assert h.data.dtype == torch.float16 and h.data.shape == (n + 1, res + 4, vi.row_pitch(res, vi.VI_F16))
+    P = h.padded().float()
+    ring = torch.ones_like(P)
+    ring[1:, 2:res + 2, 2:res + 2] = 0.0
+    assert torch.all(P[ring > 0] == 1.0)
+    T32, T16 = f.dense().double(), h.dense().double()
+    err = float(((T16 - T32).abs() - T32 * 2.0 ** -11).max())
+    report(f"half stack res {res} vs float stack (beyond 2^-11 T)", err)
+    assert err <= 2e-6
+    with pytest.raises(vi.VIError) as e:
+        vi.build_attenuation(vol, tf, light, n, res, vi.VI_F16, layout=vi.VI_STACK_TILED)
+    assert e.value.code == -2
+
+
 @pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
 @pytest.mark.parametrize("mode", ["shadow", "shell", "cone", "cone5"])
 def test_row_layout_gives_bitwise_identical_images(dtype, mode):

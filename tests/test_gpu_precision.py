@@ -32,14 +32,14 @@ def _phantom(N):
     return raw, W.to_f16_normalised(raw)
 
 
-def _precision_case(N, n, res, cam, light, mode, opts, pix, layout=vi.VI_STACK_ROWS):
+def _precision_case(N, n, res, cam, light, mode, opts, pix, layout=vi.VI_STACK_ROWS, sdt=vi.VI_BF16):
     raw, f16 = _phantom(N)
     tab = W.tf_ct()
     # as the benchmark prepares the precision volume: bricks, the cell size whose occupancy bits fit in LDS
     tf = vi.TF.from_numpy(tab, DEV)
     cell = 16 if N <= 640 else 32
     vol = vi.Volume.from_numpy(f16, DEV, 1.0).to_bricks().with_minmax(cell).with_occupancy(tf)
-    st = vi.build_attenuation(vol, tf, light, n, res, vi.VI_BF16, layout=layout)
+    st = vi.build_attenuation(vol, tf, light, n, res, sdt, layout=layout)
     img = vi.render(vol, tf, st, cam, mode, 0.5, opts)
     torch.cuda.synchronize()
     got = img.cpu().double().numpy().reshape(-1, 4)
@@ -53,7 +53,7 @@ def _precision_case(N, n, res, cam, light, mode, opts, pix, layout=vi.VI_STACK_R
     o_u16, o_f16 = O.Volume(raw), O.Volume(f16, 1.0)
     s16 = O.Stack(o_f16, otf, light, n, res)
     # stack: 2^-tau (base-2 optical depth) against the oracle's transmittance, sampled columns
-    T_gpu = np.exp2(-tau)
+    T_gpu = np.exp2(-tau) if sdt == vi.VI_BF16 else tau      # (half stacks hold T itself)
     T_ref = np.stack([s16.column(i, j) for i, j in ij], axis=1)
     err_T = float(np.abs(T_gpu - T_ref).max())
     _, ref16, _, _ = O.render(o_f16, otf, s16, cam, mode, 0.5, opts, pixels=pix, want_full=False)
@@ -92,4 +92,26 @@ def test_precision_form_full_size_sampled(mode):
     print(f"[precision] 1024^3 {mode}: stack |dT| {err_T:.2e}; vs u16 oracle max-abs {mu:.2e} PSNR {pu:.1f} dB; "
           f"vs f16 oracle max-abs {m16:.2e} PSNR {p16:.1f} dB", flush=True)
     assert err_T < 4e-3
+    assert p16 >= 50.0 and pu >= 50.0
+
+
+@pytest.mark.parametrize("mode", ["shell", "cone"])
+def test_half_transmittance_stack(mode):
+    """The half-precision transmittance stack (optical depth summed in float, stored as
+    2^-tau in half precision): 256^3 in full on a pixel grid and 1024^3 sampled."""
+    cam = W.camera_orbit(512, 384, 1.0, math.radians(20))
+    light = W.light_from_angles(0.3, math.radians(35))
+    err_T, (mu, pu), (m16, p16) = _precision_case(256, 256, 512, cam, light, mode, {}, _pixels(512, 384, 4),
+                                                  sdt=vi.VI_F16)
+    print(f"[precision] half stack 256^3 {mode}: stack |dT| {err_T:.2e}; vs u16 oracle max-abs {mu:.2e} "
+          f"PSNR {pu:.1f} dB; vs f16 oracle max-abs {m16:.2e} PSNR {p16:.1f} dB", flush=True)
+    assert err_T < 1e-3          # half precision: |dT| <= T 2^-11 (+ float optical depth)
+    assert p16 >= 50.0 and pu >= 50.0
+    w = W.WORKLOADS["precision"]
+    cam = w.camera(0)
+    err_T, (mu, pu), (m16, p16) = _precision_case(w.N, w.n_slices, w.res, cam, w.lights()[0], mode, {},
+                                                  _pixels(cam["width"], cam["height"], 16), sdt=vi.VI_F16)
+    print(f"[precision] half stack 1024^3 {mode}: stack |dT| {err_T:.2e}; vs u16 oracle max-abs {mu:.2e} "
+          f"PSNR {pu:.1f} dB; vs f16 oracle max-abs {m16:.2e} PSNR {p16:.1f} dB", flush=True)
+    assert err_T < 1e-3
     assert p16 >= 50.0 and pu >= 50.0
