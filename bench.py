@@ -44,7 +44,12 @@ KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
                   "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
 MEASURED = {
     # large workload (512^3 u16 in the quad layout, 16^3 empty-space cells with occupancy bits, 512 x
-    # 1024^2 f32 stack in rows, 1920x1080), lights 0..2 (bench --steps 2 --warmup 1)
+    # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1
+    # (lights 0, 0, 1); per launch: FETCH_SIZE / WRITE_SIZE in KiB, SQ_INSTS_VALU, GRBM_GUI_ACTIVE
+    # (summed over the 8 XCDs), TA_TA_BUSY_sum and the other SQ counters of the same passes
+    ("build", "large", "rows", 16, "quads"): {"sha256": "85223c81a6738a8ac52602b65030514320eff770fd9bea223bbf47019ea57a86", "fetch_kib": 309563.9, "write_kib": 2326962.5, "valu_insts": 153875669, "gui_cycles": 19733623, "ta_busy": 445316094, "vmem_rd": 1229360, "vmem_wr": 8404992, "waves": 16384, "wave_cycles": 2439104670, "busy_cycles": 78051113, "wait_inst_any": 1176047523, "lds_insts": 2803424, "salu_insts": 59472493, "tcp_accesses": 83333396},
+    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "e1c9f48912e9cc4b9d9d400914217ba28ed51a0ee1bfe95d334a530e80635ab8", "fetch_kib": 108743.6, "write_kib": 35181.3, "valu_insts": 564175220, "gui_cycles": 22835991, "ta_busy": 380755027, "vmem_rd": 17659382, "vmem_wr": 205020, "waves": 130560, "wave_cycles": 2821976676, "busy_cycles": 82035853, "wait_inst_any": 427929436, "lds_insts": 16353531, "salu_insts": 113265714, "tcp_accesses": 448550948},
+    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "e1c9f48912e9cc4b9d9d400914217ba28ed51a0ee1bfe95d334a530e80635ab8", "fetch_kib": 120427.9, "write_kib": 35278.1, "valu_insts": 622770674, "gui_cycles": 25366729, "ta_busy": 459075382, "vmem_rd": 22669024, "vmem_wr": 205020, "waves": 130560, "wave_cycles": 2545333462, "busy_cycles": 85923833, "wait_inst_any": 557543318, "lds_insts": 16353531, "salu_insts": 135583891, "tcp_accesses": 579458706},
 }
 
 
@@ -386,7 +391,10 @@ def measure_steps(w, raw, scale, tab, lights, modes, stack_dtype, args, dev):
     counters = {m: torch.zeros(2, dtype=torch.int64, device=dev) for m in modes}
 
     def mode_args(m):
-        return ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
+        mm, extra = ("cone", {"cone_grid": 5}) if m == "cone5" else (m, {})
+        if args.nearest_layer:
+            extra = {**extra, "nearest_layer": 1}
+        return mm, extra
 
     # point lights: each at args.point_light world units up-stream of the centre
     # along its direction
@@ -463,6 +471,8 @@ def main():
     ap.add_argument("--point-light", type=float, default=0.0, metavar="DIST",
                     help="point lights DIST world units from the volume centre (against each light "
                          "direction) instead of directional lights")
+    ap.add_argument("--nearest-layer", action="store_true",
+                    help="stack lookups read the layer nearest each depth index instead of interpolating in depth")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -546,7 +556,7 @@ def main():
     opaque = m["opaque"]
     totals = {"build": sum(build_ms), **{f"render_{k}": sum(v) for k, v in render_ms.items()}}
     dom = max(totals, key=totals.get)
-    rec = None if (args.point_light or args.no_occupancy) else \
+    rec = None if (args.point_light or args.no_occupancy or args.nearest_layer) else \
         measured(dom, w.name, args.stack_layout, args.cell, args.volume_layout)
 
     def counter_fracs(r, ms):
@@ -581,7 +591,7 @@ def main():
                             "compulsory_frac": round(ideal / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
                             "measured_gbs": None if tb is None else round(tb / (avg_ms * 1e-3) / 1e9, 2)}}
     build_ms_mean = float(np.mean(build_ms))
-    brec = None if (args.point_light or args.no_occupancy) else \
+    brec = None if (args.point_light or args.no_occupancy or args.nearest_layer) else \
         measured("build", w.name, args.stack_layout, args.cell, args.volume_layout)
     btb = traffic_bytes(brec)
     kernels = {"volume_prepare_ms_once": round(m["prep_ms"], 3),
@@ -622,7 +632,8 @@ def main():
                                 f"{Wd}x{Hd}, step {w.step_vox} voxel, modes {'+'.join(modes)}, "
                                 + (f"{len(lights)} point lights at {args.point_light} from the centre "
                                  if args.point_light else f"{len(lights)} light directions ")
-                                + "(one rebuild per step)"),
+                                + "(one rebuild per step)"
+                                + (", nearest-layer lookups" if args.nearest_layer else "")),
                    "frames_per_step": len(modes)},
         "kernels": kernels,
         "roofline": roofline,
@@ -641,7 +652,7 @@ def main():
         log("serving leg ...")
         torch.cuda.empty_cache()
         result["serving"] = serving_quick("cuda:0")
-    if not args.no_cpu_baseline and not precision and not args.point_light:
+    if not args.no_cpu_baseline and not precision and not args.point_light and not args.nearest_layer:
         log("timing the oracle on a pixel sample ...")
         opts = {}
         result["cpu_baseline"] = cpu_baseline(w, raw, tab, lights[0], cam0, modes, opts, args.cpu_stride)

@@ -173,28 +173,26 @@ __global__ __launch_bounds__(256) void occupancy_kernel(const float2* __restrict
 }
 
 // Super-cell bits: super-cell (X, Y, Z) covers cells 4X .. 4X+3 (and so on,
-// clipped at nc) and is set when any of them is.  One lane per word.
+// clipped at nc) and is set when any of them is.  One lane per super-cell;
+// each half-wave's ballot is one word.
 __global__ __launch_bounds__(256) void super_kernel(const uint32_t* __restrict__ bits, uint32_t nc,
                                                     uint32_t* __restrict__ sbits)
 {
     const uint32_t snc = (nc + 3u) / 4u, scells = snc * snc * snc;
-    const uint32_t w = blockIdx.x * 256u + threadIdx.x;
-    if (w >= (scells + 31u) / 32u) return;
-    uint32_t b = 0;
-    for (uint32_t i = 0; i < 32u; ++i) {
-        const uint32_t sc = w * 32u + i;
-        if (sc >= scells) break;
+    const uint32_t sc = blockIdx.x * 256u + threadIdx.x;
+    bool any = false;
+    if (sc < scells) {
         const uint32_t X = sc % snc, Y = (sc / snc) % snc, Z = sc / (snc * snc);
-        bool any = false;
         for (uint32_t z = 4u * Z; z < min(4u * Z + 4u, nc); ++z)
             for (uint32_t y = 4u * Y; y < min(4u * Y + 4u, nc); ++y)
                 for (uint32_t x = 4u * X; x < min(4u * X + 4u, nc); ++x) {
                     const uint32_t c = (z * nc + y) * nc + x;
                     any = any || ((bits[c >> 5] >> (c & 31u)) & 1u);
                 }
-        if (any) b |= 1u << i;
     }
-    sbits[w] = b;
+    const uint64_t m = __ballot(any);
+    const uint32_t lane = threadIdx.x & 63u;
+    if ((lane & 31u) == 0u && sc < scells) sbits[sc >> 5] = (uint32_t)(lane ? (m >> 32) : m);
 }
 
 hipError_t launch_occupancy(const float* minmax, uint32_t nc, const float* tf, int K, uint32_t* bits,
@@ -203,9 +201,9 @@ hipError_t launch_occupancy(const float* minmax, uint32_t nc, const float* tf, i
     const uint32_t cells = nc * nc * nc, words = (cells + 31u) / 32u;
     hipLaunchKernelGGL(occupancy_kernel, dim3((words + 255u) / 256u), dim3(256), sizeof(int) * (size_t)K, s,
                        (const float2*)minmax, cells, tf, K, bits);
-    const uint32_t snc = (nc + 3u) / 4u, swords = (snc * snc * snc + 31u) / 32u;
-    hipLaunchKernelGGL(super_kernel, dim3((swords + 255u) / 256u), dim3(256), 0, s, (const uint32_t*)bits, nc,
-                       bits + words);
+    const uint32_t snc = (nc + 3u) / 4u;
+    hipLaunchKernelGGL(super_kernel, dim3((snc * snc * snc + 255u) / 256u), dim3(256), 0, s, (const uint32_t*)bits,
+                       nc, bits + words);
     return hipGetLastError();
 }
 
