@@ -272,6 +272,8 @@ def serving_inputs(vol_sizes, dev, vessels=True):
         raw = W.serving_volume(N, i, vessels=vessels)
         tf = vi.TF.from_numpy(tab, dev)
         vols.append((vi.Volume.from_numpy(raw, dev).to_quads().with_minmax(16).with_occupancy(tf), tf))
+        if len(vol_sizes) > 16 and i % 8 == 7:
+            log(f"{i + 1} of {len(vol_sizes)} serving volumes resident")
     return vols
 
 
