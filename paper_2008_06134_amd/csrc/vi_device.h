@@ -90,28 +90,39 @@ __device__ __forceinline__ F2 f2_dot3(const F2* a, const F2* b)
 }
 
 // One voxel, normalised and clamped to [0,1] before interpolation.
+// Element idx of an array below 4 GiB, addressed with a 32-bit byte offset
+// (the load then takes the base from scalar registers: no 64-bit address
+// arithmetic per load).  Stacks and one copy of a volume's voxels are
+// refused at 4 GiB and above; the quad layout, four copies, is not (it keeps
+// 64-bit addressing).
+template <typename T>
+__device__ __forceinline__ T ld32(const void* __restrict__ base, uint32_t idx)
+{
+    return *(const T*)((const char*)base + idx * (uint32_t)sizeof(T));
+}
+
 template <typename VT>
 __device__ __forceinline__ float voxel_norm(const VT* __restrict__ v, uint32_t idx, float scale);
 
 template <>
 __device__ __forceinline__ float voxel_norm<uint8_t>(const uint8_t* __restrict__ v, uint32_t idx, float scale)
 {
-    return clampf01((float)v[idx] * scale);
+    return clampf01((float)ld32<uint8_t>(v, idx) * scale);
 }
 template <>
 __device__ __forceinline__ float voxel_norm<uint16_t>(const uint16_t* __restrict__ v, uint32_t idx, float scale)
 {
-    return clampf01((float)v[idx] * scale);
+    return clampf01((float)ld32<uint16_t>(v, idx) * scale);
 }
 template <>
 __device__ __forceinline__ float voxel_norm<__half>(const __half* __restrict__ v, uint32_t idx, float scale)
 {
-    return clampf01(__half2float(v[idx]) * scale);
+    return clampf01(__half2float(ld32<__half>(v, idx)) * scale);
 }
 template <>
 __device__ __forceinline__ float voxel_norm<float>(const float* __restrict__ v, uint32_t idx, float scale)
 {
-    return clampf01(v[idx] * scale);
+    return clampf01(ld32<float>(v, idx) * scale);
 }
 
 // Element offsets of the two volume layouts, separable per axis so the
@@ -224,6 +235,8 @@ __device__ __forceinline__ void foot_load_g(RawFoot<VT, LAYOUT>& r, float& wx, f
     if constexpr (LAYOUT == VI_LAYOUT_QUAD4) {
         using Q = typename QuadRaw<VT>::T;
         const uint32_t xy = vol_ox<LAYOUT>(I, clampi(x0, 0, N - 1)) + vol_oy<LAYOUT>(I, clampi(y0, 0, N - 1));
+        // (a quad volume holds four copies of the voxels and may pass 4 GiB:
+        // 64-bit addressing)
         r.a = ((const Q*)vol)[za + xy];
         r.b = ((const Q*)vol)[zb + xy];
         if (x0 < 0) wx = 0.0f;
@@ -231,14 +244,14 @@ __device__ __forceinline__ void foot_load_g(RawFoot<VT, LAYOUT>& r, float& wx, f
     } else {
         const uint32_t xa = vol_ox<LAYOUT>(I, clampi(x0, 0, N - 1)), xb = vol_ox<LAYOUT>(I, clampi(x0 + 1, 0, N - 1));
         const uint32_t ya = vol_oy<LAYOUT>(I, clampi(y0, 0, N - 1)), yb = vol_oy<LAYOUT>(I, clampi(y0 + 1, 0, N - 1));
-        r.v[0] = vol[za + ya + xa];
-        r.v[1] = vol[za + ya + xb];
-        r.v[2] = vol[za + yb + xa];
-        r.v[3] = vol[za + yb + xb];
-        r.v[4] = vol[zb + ya + xa];
-        r.v[5] = vol[zb + ya + xb];
-        r.v[6] = vol[zb + yb + xa];
-        r.v[7] = vol[zb + yb + xb];
+        r.v[0] = ld32<VT>(vol, za + ya + xa);
+        r.v[1] = ld32<VT>(vol, za + ya + xb);
+        r.v[2] = ld32<VT>(vol, za + yb + xa);
+        r.v[3] = ld32<VT>(vol, za + yb + xb);
+        r.v[4] = ld32<VT>(vol, zb + ya + xa);
+        r.v[5] = ld32<VT>(vol, zb + ya + xb);
+        r.v[6] = ld32<VT>(vol, zb + yb + xa);
+        r.v[7] = ld32<VT>(vol, zb + yb + xb);
     }
 }
 

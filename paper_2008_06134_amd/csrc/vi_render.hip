@@ -64,20 +64,23 @@ template <> struct PairRaw<VI_F16> { uint32_t w; };
 
 template <int SDT>
 __device__ __forceinline__ PairRaw<SDT> pair_load(const void* __restrict__ S, uint32_t e);
+// (Byte offsets are formed in 32 bits -- a stack is below 4 GiB -- so that
+// each load takes the stack's base from scalar registers and a 32-bit
+// offset, with no 64-bit address arithmetic per load.)
 template <>
 __device__ __forceinline__ PairRaw<VI_F32> pair_load<VI_F32>(const void* __restrict__ S, uint32_t e)
 {
-    return PairRaw<VI_F32>{*(const f32x2_a4*)((const float*)S + e)};
+    return PairRaw<VI_F32>{*(const f32x2_a4*)((const char*)S + (e << 2))};
 }
 template <>
 __device__ __forceinline__ PairRaw<VI_BF16> pair_load<VI_BF16>(const void* __restrict__ S, uint32_t e)
 {
-    return PairRaw<VI_BF16>{*(const u32_a2*)((const uint16_t*)S + e)};
+    return PairRaw<VI_BF16>{*(const u32_a2*)((const char*)S + (e << 1))};
 }
 template <>
 __device__ __forceinline__ PairRaw<VI_F16> pair_load<VI_F16>(const void* __restrict__ S, uint32_t e)
 {
-    return PairRaw<VI_F16>{*(const u32_a2*)((const uint16_t*)S + e)};
+    return PairRaw<VI_F16>{*(const u32_a2*)((const char*)S + (e << 1))};
 }
 __device__ __forceinline__ float2 pair_value(const PairRaw<VI_F32>& r) { return make_float2(r.v.x, r.v.y); }
 __device__ __forceinline__ float2 pair_value(const PairRaw<VI_F16>& r)
@@ -869,9 +872,45 @@ __device__ __forceinline__ void block_pixel(uint32_t tx, uint32_t ty, int* px, i
     *py = (int)ty * kBY + (wave >> 1) * kWY + r / kWX;
 }
 
+// Segment counters: a wave sums its lanes' counts, the workgroup's waves add
+// theirs in LDS, and the last wave to finish adds the workgroup's totals to
+// the frame's counters -- one global atomic per workgroup and counter (one
+// per wave measured up to twice the unlit frame's time: every wave of the
+// frame hits the same two words).  No barrier: finished waves still leave.
+struct GroupCount {
+    unsigned long long ns, nop;
+    uint32_t waves_done;
+};
+__device__ __forceinline__ void group_count_init(GroupCount* g)
+{
+    if (threadIdx.x == 0) {
+        g->ns = 0;
+        g->nop = 0;
+        g->waves_done = 0;
+    }
+}
+__device__ __forceinline__ void group_count_add(const RenderFrame& F, GroupCount* g, uint32_t ns, uint32_t nop)
+{
+    if (!F.samples) return;
+    for (int off = 32; off > 0; off >>= 1) {
+        ns += __shfl_xor(ns, off);
+        nop += __shfl_xor(nop, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&g->ns, (unsigned long long)ns);
+        atomicAdd(&g->nop, (unsigned long long)nop);
+        __threadfence_block();
+        if (atomicAdd(&g->waves_done, 1u) == blockDim.x / 64u - 1u) {
+            const unsigned long long tn = atomicAdd(&g->ns, 0ull), to = atomicAdd(&g->nop, 0ull);
+            if (tn) atomicAdd(F.samples, tn);
+            if (to && F.count_opaque) atomicAdd(F.samples + 1, to);
+        }
+    }
+}
+
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
 __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* s_tf, const int* s_next,
-                                            const uint32_t* s_bits, int px, int py)
+                                            const uint32_t* s_bits, GroupCount* gc, int px, int py)
 {
     uint32_t ns = 0, nop = 0;
     const int lane = threadIdx.x & 63;
@@ -879,15 +918,7 @@ __device__ __forceinline__ void shade_pixel(const RenderFrame& F, const float4* 
         const float4 c = render_ray<VT, LAYOUT, MODE, SDT, SL, kG>(F, s_tf, s_next, s_bits, px, py, ns, nop);
         if (lane % kG == 0) F.out[(size_t)py * F.width + px] = c;
     }
-    if (F.samples) {
-        // wave sums, one atomic per wave and counter
-        for (int off = 32; off > 0; off >>= 1) {
-            ns += __shfl_xor(ns, off);
-            nop += __shfl_xor(nop, off);
-        }
-        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
-        if (lane == 0 && nop && F.count_opaque) atomicAdd(F.samples + 1, (unsigned long long)nop);
-    }
+    group_count_add(F, gc, ns, nop);
 }
 
 // Ray compaction (VI_RENDER_COMPACT = 1): a wave owns four blocks of
@@ -907,7 +938,7 @@ constexpr bool kCompact = VI_RENDER_COMPACT != 0;
 
 template <typename VT, int LAYOUT, int MODE, int SDT, int SL>
 __device__ __forceinline__ void shade_region_compact(const RenderFrame& F, const float4* s_tf, const int* s_next,
-                                                     const uint32_t* s_bits, int x0, int y0)
+                                                     const uint32_t* s_bits, GroupCount* gc, int x0, int y0)
 {
     constexpr int kGroups = 64 / kG, kRays = 4 * kGroups;
     const int lane = threadIdx.x & 63, g = lane % kG, grp = lane / kG;
@@ -944,14 +975,7 @@ __device__ __forceinline__ void shade_region_compact(const RenderFrame& F, const
             live = false;
         }
     }
-    if (F.samples) {
-        for (int off = 32; off > 0; off >>= 1) {
-            ns += __shfl_xor(ns, off);
-            nop += __shfl_xor(nop, off);
-        }
-        if (lane == 0 && ns) atomicAdd(F.samples, (unsigned long long)ns);
-        if (lane == 0 && nop && F.count_opaque) atomicAdd(F.samples + 1, (unsigned long long)nop);
-    }
+    group_count_add(F, gc, ns, nop);
 }
 
 // --------------------------------------------------------------------------
@@ -963,6 +987,8 @@ __device__ __forceinline__ void render_frame(const RenderFrame& F)
     extern __shared__ float4 s_tf[];  // K entries, K next-opaque indices, then the occupancy bits
     int* s_next = (int*)(s_tf + F.K);
     uint32_t* s_bits = (uint32_t*)(s_next + F.K);
+    __shared__ GroupCount gc;
+    group_count_init(&gc);
     for (int t = threadIdx.x; t < F.K; t += blockDim.x)
         s_tf[t] = make_float4(F.tf[4 * t], F.tf[4 * t + 1], F.tf[4 * t + 2], F.tf[4 * t + 3]);
     if (F.occ.mm && !F.occ.bits) build_next_opaque(s_next, F.tf, F.K);
@@ -975,7 +1001,7 @@ __device__ __forceinline__ void render_frame(const RenderFrame& F)
         uint32_t tx, ty;
         if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
         const int wave = threadIdx.x >> 6;
-        shade_region_compact<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits,
+        shade_region_compact<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, &gc,
                                                         (int)tx * 4 * kWX + (wave & 1) * 2 * kWX,
                                                         (int)ty * 4 * kWY + (wave >> 1) * 2 * kWY);
     } else {
@@ -984,7 +1010,7 @@ __device__ __forceinline__ void render_frame(const RenderFrame& F)
         if (!supertile_of(blockIdx.x, tiles_x, tiles_y, &tx, &ty)) return;
         int px, py;
         block_pixel(tx, ty, &px, &py);
-        shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, px, py);
+        shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, &gc, px, py);
     }
 }
 
@@ -1009,6 +1035,8 @@ __device__ __forceinline__ void render_tiles(const RenderFrame* __restrict__ fra
     const RenderFrame& F = frames[t >> 22];
     int* s_next = (int*)(s_tf + F.K);
     uint32_t* s_bits = (uint32_t*)(s_next + F.K);
+    __shared__ GroupCount gc;
+    group_count_init(&gc);
     for (int i = threadIdx.x; i < F.K; i += blockDim.x)
         s_tf[i] = make_float4(F.tf[4 * i], F.tf[4 * i + 1], F.tf[4 * i + 2], F.tf[4 * i + 3]);
     if (F.occ.mm && !F.occ.bits) build_next_opaque(s_next, F.tf, F.K);
@@ -1016,7 +1044,7 @@ __device__ __forceinline__ void render_tiles(const RenderFrame* __restrict__ fra
     __syncthreads();
     int px, py;
     block_pixel((t & 2047u) * kSubX + sub % kSubX, ((t >> 11) & 2047u) * kSubY + sub / kSubX, &px, &py);
-    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, px, py);
+    shade_pixel<VT, LAYOUT, MODE, SDT, SL>(F, s_tf, s_next, s_bits, &gc, px, py);
 }
 
 // The kernels.  The float-stack shell's two-tap batches fit six waves per

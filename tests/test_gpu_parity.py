@@ -636,3 +636,32 @@ def test_rewritten_transfer_function_is_refused():
            "ortho_half_h": 0.75, "width": 16, "height": 16}
     with pytest.raises(vi.VIError):
         vi.render(vol, again, st, cam, "shell", 0.5)
+
+
+@pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
+def test_out_of_range_tf_opacity_is_clamped(dtype):
+    """A table whose opacity runs from -0.1 to 1.1: the build and the render both take the
+    interpolated opacity clamped to [0, 1] (a <= 0 transmits, a >= 1 is opaque), as the oracle does;
+    stack and image against the oracle, occupancy bits on."""
+    raw = W.sphere_u8(48, radius=18, density=150, noise=60, seed=12)
+    tab = W.tf_ramp().copy()
+    tab[:, 3] = np.linspace(-0.1, 1.1, tab.shape[0])
+    vol, tf = gpu_inputs(raw, tab, bits=True)
+    light, n, res = [0.3, -0.4, 0.87], 40, 72
+    ovol, otf = O.Volume(raw), O.TF(tab)
+    ost = O.Stack(ovol, otf, light, n, res)
+    st = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_ROWS)
+    torch.cuda.synchronize()
+    S = st.dense().float().cpu().double().numpy()
+    T = S if dtype == vi.VI_F32 else np.exp2(-S)
+    err_s = float(np.abs(T - ost.export()).max())
+    assert float(ost.export().min()) < 1e-3            # some columns are fully shadowed
+    cam = W.camera_orbit(80, 64, 0.7, 0.35)
+    _, ref, _, _ = O.render(ovol, otf, ost, cam, "shell", 0.5, want_full=False)
+    img, _ = gpu_render(vol, tf, st, cam, "shell", 0.5)
+    err = float(np.abs(img - ref).max())
+    report(f"out-of-range TF opacity ({'f32' if dtype == vi.VI_F32 else 'bf16'}), stack {err_s:.2e}", err)
+    if dtype == vi.VI_F32:
+        assert err_s <= TOL_STACK and err <= TOL_IMG
+    else:
+        assert err_s < 4e-3 and err < 5e-3
