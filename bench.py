@@ -47,9 +47,9 @@ MEASURED = {
     # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1
     # (lights 0, 0, 1); per launch: FETCH_SIZE / WRITE_SIZE in KiB, SQ_INSTS_VALU, GRBM_GUI_ACTIVE
     # (summed over the 8 XCDs), TA_TA_BUSY_sum and the other SQ counters of the same passes
-    ("build", "large", "rows", 16, "quads"): {"sha256": "85223c81a6738a8ac52602b65030514320eff770fd9bea223bbf47019ea57a86", "fetch_kib": 309563.9, "write_kib": 2326962.5, "valu_insts": 153875669, "gui_cycles": 19733623, "ta_busy": 445316094, "vmem_rd": 1229360, "vmem_wr": 8404992, "waves": 16384, "wave_cycles": 2439104670, "busy_cycles": 78051113, "wait_inst_any": 1176047523, "lds_insts": 2803424, "salu_insts": 59472493, "tcp_accesses": 83333396},
-    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "e1c9f48912e9cc4b9d9d400914217ba28ed51a0ee1bfe95d334a530e80635ab8", "fetch_kib": 108743.6, "write_kib": 35181.3, "valu_insts": 564175220, "gui_cycles": 22835991, "ta_busy": 380755027, "vmem_rd": 17659382, "vmem_wr": 205020, "waves": 130560, "wave_cycles": 2821976676, "busy_cycles": 82035853, "wait_inst_any": 427929436, "lds_insts": 16353531, "salu_insts": 113265714, "tcp_accesses": 448550948},
-    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "e1c9f48912e9cc4b9d9d400914217ba28ed51a0ee1bfe95d334a530e80635ab8", "fetch_kib": 120427.9, "write_kib": 35278.1, "valu_insts": 622770674, "gui_cycles": 25366729, "ta_busy": 459075382, "vmem_rd": 22669024, "vmem_wr": 205020, "waves": 130560, "wave_cycles": 2545333462, "busy_cycles": 85923833, "wait_inst_any": 557543318, "lds_insts": 16353531, "salu_insts": 135583891, "tcp_accesses": 579458706},
+    ("build", "large", "rows", 16, "quads"): {"sha256": "60a925d0adaee6452ae28e34dabe8cd97ef64ccadae0e8d8217d3cf755a35387", "fetch_kib": 310577.0, "write_kib": 2324977.6, "valu_insts": 151067640, "gui_cycles": 19818776, "ta_busy": 442224221, "vmem_rd": 1229360, "vmem_wr": 8404992, "waves": 16384, "wave_cycles": 2417801311, "busy_cycles": 78172547, "wait_inst_any": 1193627674, "lds_insts": 2803424, "salu_insts": 59573447, "tcp_accesses": 83333396},
+    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "4e3edbc1f79ab746fde8b106035751aea42dba3cf15319b68af4f5c6db98149c", "fetch_kib": 108710.3, "write_kib": 33394.2, "valu_insts": 551565403, "gui_cycles": 20609846, "ta_busy": 369097631, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2494958500, "busy_cycles": 73585077, "wait_inst_any": 420817146, "lds_insts": 16872411, "salu_insts": 116260385, "tcp_accesses": 448494575},
+    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "4e3edbc1f79ab746fde8b106035751aea42dba3cf15319b68af4f5c6db98149c", "fetch_kib": 120320.1, "write_kib": 33493.1, "valu_insts": 610734737, "gui_cycles": 23362731, "ta_busy": 451344948, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2342726930, "busy_cycles": 79983727, "wait_inst_any": 556156233, "lds_insts": 16872411, "salu_insts": 138578562, "tcp_accesses": 579402332},
 }
 
 

@@ -161,12 +161,14 @@ __device__ __forceinline__ int wave_max(int v)
 // One stack texel: transmittance (F32), optical depth in base-2 units
 // -log2 T (BF16), or the transmittance 2^-tau of the float optical depth
 // rounded to half precision (F16).
+// (The stack is below 4 GiB: byte offsets in 32 bits, so a store takes the
+// stack's base from scalar registers.)
 template <int OUT_DTYPE>
 __device__ __forceinline__ void put_texel(void* out, uint32_t at, float T, float tau)
 {
-    if (OUT_DTYPE == VI_F32) ((float*)out)[at] = T;
-    else if (OUT_DTYPE == VI_BF16) ((uint16_t*)out)[at] = f32_to_bf16(tau);
-    else ((__half*)out)[at] = __float2half_rn(fast_exp2(-tau));
+    if (OUT_DTYPE == VI_F32) *(float*)((char*)out + (at << 2)) = T;
+    else if (OUT_DTYPE == VI_BF16) *(uint16_t*)((char*)out + (at << 1)) = f32_to_bf16(tau);
+    else *(__half*)((char*)out + (at << 1)) = __float2half_rn(fast_exp2(-tau));
 }
 
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool PT>

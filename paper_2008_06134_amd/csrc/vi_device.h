@@ -139,17 +139,20 @@ __device__ __forceinline__ uint32_t vol_ox(const VolIndex& I, int x)
     if (LAYOUT != VI_LAYOUT_LINEAR) return ((uint32_t)x >> 2) * 64u + ((uint32_t)x & 3u);
     return (uint32_t)x;
 }
+// (Products in 24-bit multiplies, full rate where a 32-bit multiply is
+// quarter rate: a volume below 4 GiB has N < 2^11, so the coordinates and
+// the strides N, N^2, (N/4)*64 and (N/4)^2*64 all stay below 2^24.)
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t vol_oy(const VolIndex& I, int y)
 {
-    if (LAYOUT != VI_LAYOUT_LINEAR) return ((uint32_t)y >> 2) * I.sy + ((uint32_t)y & 3u) * 4u;
-    return (uint32_t)y * I.sy;
+    if (LAYOUT != VI_LAYOUT_LINEAR) return __umul24((uint32_t)y >> 2, I.sy) + ((uint32_t)y & 3u) * 4u;
+    return __umul24((uint32_t)y, I.sy);
 }
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t vol_oz(const VolIndex& I, int z)
 {
-    if (LAYOUT != VI_LAYOUT_LINEAR) return ((uint32_t)z >> 2) * I.sz + ((uint32_t)z & 3u) * 16u;
-    return (uint32_t)z * I.sz;
+    if (LAYOUT != VI_LAYOUT_LINEAR) return __umul24((uint32_t)z >> 2, I.sz) + ((uint32_t)z & 3u) * 16u;
+    return __umul24((uint32_t)z, I.sz);
 }
 
 // The four normalised values of quad slot `q` (VI_LAYOUT_QUAD4): one load
