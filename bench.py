@@ -47,9 +47,9 @@ MEASURED = {
     # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1
     # (lights 0, 0, 1); per launch: FETCH_SIZE / WRITE_SIZE in KiB, SQ_INSTS_VALU, GRBM_GUI_ACTIVE
     # (summed over the 8 XCDs), TA_TA_BUSY_sum and the other SQ counters of the same passes
-    ("build", "large", "rows", 16, "quads"): {"sha256": "60a925d0adaee6452ae28e34dabe8cd97ef64ccadae0e8d8217d3cf755a35387", "fetch_kib": 310577.0, "write_kib": 2324977.6, "valu_insts": 151067640, "gui_cycles": 19818776, "ta_busy": 442224221, "vmem_rd": 1229360, "vmem_wr": 8404992, "waves": 16384, "wave_cycles": 2417801311, "busy_cycles": 78172547, "wait_inst_any": 1193627674, "lds_insts": 2803424, "salu_insts": 59573447, "tcp_accesses": 83333396},
-    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "4e3edbc1f79ab746fde8b106035751aea42dba3cf15319b68af4f5c6db98149c", "fetch_kib": 108710.3, "write_kib": 33394.2, "valu_insts": 551565403, "gui_cycles": 20609846, "ta_busy": 369097631, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2494958500, "busy_cycles": 73585077, "wait_inst_any": 420817146, "lds_insts": 16872411, "salu_insts": 116260385, "tcp_accesses": 448494575},
-    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "4e3edbc1f79ab746fde8b106035751aea42dba3cf15319b68af4f5c6db98149c", "fetch_kib": 120320.1, "write_kib": 33493.1, "valu_insts": 610734737, "gui_cycles": 23362731, "ta_busy": 451344948, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2342726930, "busy_cycles": 79983727, "wait_inst_any": 556156233, "lds_insts": 16872411, "salu_insts": 138578562, "tcp_accesses": 579402332},
+    ("build", "large", "rows", 16, "quads"): {"sha256": "60a925d0adaee6452ae28e34dabe8cd97ef64ccadae0e8d8217d3cf755a35387", "fetch_kib": 311391.4, "write_kib": 2323506.6, "valu_insts": 151067640, "gui_cycles": 19848809, "ta_busy": 442732980, "vmem_rd": 1229360, "vmem_wr": 8404992, "waves": 16384, "wave_cycles": 2417193486, "busy_cycles": 78017670, "wait_inst_any": 1194736821, "lds_insts": 2803424, "salu_insts": 59573447, "tcp_accesses": 83333396},
+    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "139aa270919f7515964588b0b188ff3395f8c1deadf550038a218f948c04b793", "fetch_kib": 108679.5, "write_kib": 33389.0, "valu_insts": 541556037, "gui_cycles": 20403040, "ta_busy": 368592803, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2472088470, "busy_cycles": 73104390, "wait_inst_any": 401286993, "lds_insts": 16872411, "salu_insts": 116432238, "tcp_accesses": 448494575},
+    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "139aa270919f7515964588b0b188ff3395f8c1deadf550038a218f948c04b793", "fetch_kib": 120285.0, "write_kib": 33491.1, "valu_insts": 595820378, "gui_cycles": 23190306, "ta_busy": 450709008, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2326198305, "busy_cycles": 79679379, "wait_inst_any": 531290148, "lds_insts": 16872411, "salu_insts": 138750415, "tcp_accesses": 579402332},
 }
 
 

@@ -110,14 +110,19 @@ template <int SDT, bool NEAR>
 __device__ __forceinline__ void rowtap_load(const RenderFrame& F, float z, float x, float y, RowTap<SDT>& t)
 {
     if (NEAR) z = floorf(z + 0.5f);
+    // clamping the coordinates (not the texel indices) keeps every footprint
+    // on stored texels: beyond the grid both texels of a row are border
+    // texels (1), so the value is the same 1 whatever the weight
     z = __builtin_amdgcn_fmed3f(z, (float)(-1 - F.Mz), (float)(F.n - 1 - F.Mz));
+    x = __builtin_amdgcn_fmed3f(x, (float)(-2 - F.Mr), (float)(F.res - F.Mr));
+    y = __builtin_amdgcn_fmed3f(y, (float)(-2 - F.Mr), (float)(F.res - F.Mr));
     const float fz = floorf(z), fx = floorf(x), fy = floorf(y);
     t.wz = z - fz;
     t.wx = x - fx;
     t.wy = y - fy;
     const int k0 = (int)fz + F.Mz;                 // -1 .. n-1
     const int k1 = min(k0 + 1, F.n - 1);
-    const int a = min(max((int)fx + F.Mr, -2), F.res), b = min(max((int)fy + F.Mr, -2), F.res);
+    const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;  // -2 .. res
     const uint32_t e = (uint32_t)((int)F.rorg + b * (int)F.rpitch + a);
     const uint32_t base0 = e + (uint32_t)(k0 * (int)F.rlayer), base1 = e + (uint32_t)(k1 * (int)F.rlayer);
     t.a0 = pair_load<SDT>(F.stack, base0);
