@@ -40,8 +40,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # bench reports the figures as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 N_SIMDS, N_TAS, N_XCDS = 1024, 256, 8
-KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h"],
-                  "build": ["vi_build.hip", "vi_device.h", "vi_internal.h"]}
+# (vi_api.hip fixes the stack layout both kernels address)
+KERNEL_SOURCES = {"render": ["vi_render.hip", "vi_device.h", "vi_internal.h", "vi_api.hip"],
+                  "build": ["vi_build.hip", "vi_device.h", "vi_internal.h", "vi_api.hip"]}
 MEASURED = {
     # large workload (512^3 u16 in the quad layout, 16^3 empty-space cells with occupancy bits, 512 x
     # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1

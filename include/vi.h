@@ -159,10 +159,16 @@ typedef struct {
  *     (k, j, i) and (k, j, i+1), are adjacent, so one load per row
  *     reads them, and every footprint of a lookup, clamped to i, j in
  *     [-2, res] and k in [-1, n-1], reads stored texels only.  With row
- *     pitch P = res+4 rounded up to 4 and LS = (res+4)*P,
- *     texel (k, j, i), k in [-1, n-1], i and j in [-2, res+1], is element
- *     (k+1)*LS + (j+2)*P + (i+2); (n+1)*LS elements (columns res+4 .. P-1
- *     are never used). */
+ *     pitch P = res+4 rounded up to 4 and LS = the least odd multiple of h
+ *     from (res+4)*P up, h = 16 for VI_F32 and 32 for the 2-byte dtypes
+ *     (half a 128-byte line), texel (k, j, i), k in [-1, n-1], i and j in
+ *     [-2, res+1], is element (k+1)*LS + (j+2)*P + (i+2); (n+1)*LS elements
+ *     (columns res+4 .. P-1 and a layer's last LS - (res+4)*P elements are
+ *     never read).  The same texel of neighbouring layers lies half a line
+ *     apart; in a buffer aligned to 128 bytes every other layer starts on a
+ *     line and the build writes whole lines but for two half-lines per
+ *     workgroup and layer (any 16-byte aligned buffer is correct, more
+ *     slowly). */
 typedef enum { VI_STACK_TILED = 0, VI_STACK_ROWS = 1 } vi_stack_layout;
 
 /* Attenuation stack descriptor, filled by vi_build_attenuation (or by
@@ -324,8 +330,10 @@ int vi_light_frame(const double light_dir[3], int n_slices, int slice_res, int s
 
 /* Build the attenuation stack (section 3.2.1, Alg. 1) for light direction
  * `light_dir` into `d_slices` (device, vi_slices_bytes bytes, 16-byte
- * aligned, layout `slice_layout`) and describe it in `out_desc` (host).  One kernel launch on
- * `stream`.  slice_dtype: VI_F32 (transmittance, product of per-slab
+ * aligned -- 128-byte aligned for whole-line writes in the row layout --,
+ * layout `slice_layout`) and describe it in `out_desc` (host).  One kernel
+ * launch on `stream`, which writes every element of the row layout that a
+ * lookup can read (the border and the leading layer included).  slice_dtype: VI_F32 (transmittance, product of per-slab
  * (1-alpha)), VI_BF16 (optical depth in base-2 units, -log2 T: the
  * per-slab extinction over ln 2 summed in float and rounded to bfloat16 per
  * layer; each slab adds at most 64 / ln 2, a factor e^-64) or VI_F16 (row

@@ -8,21 +8,23 @@
 // written as soon as it is known, so the pass is one streaming sweep: the
 // volume is read through the caches and the stack is written once.
 //
-// Mapping: one workgroup per run of NT * C texels of one stack row, lane l
-// owning columns l, l + NT, ..., l + NT (C - 1) of the run.  At every slab a
-// workgroup stores its run as one contiguous stretch of the layer (4 KiB for
-// a 1024-texel row); many short runs spread over the layer (64 x 4 texel
-// tiles per workgroup) measured at half that write rate.  For a fixed c the
-// 64 lanes of a wave hold 64 neighbouring columns, so each volume gather of
-// a wave stays compact.
+// Mapping: one workgroup per run of consecutive elements of a layer, one
+// column per lane (in the tiled layout optionally C columns).  In the row
+// layout a run is a stretch of the layer's element range, border included
+// (build_rows); in the tiled layout a run of one stack row (build_tiled).
+// At every slab a workgroup stores its run as one contiguous stretch of the
+// layer (4 KiB for 1024 float texels); many short runs spread over the layer
+// (64 x 4 texel tiles per workgroup) measured at half that write rate.  The
+// 64 lanes of a wave hold 64 neighbouring columns (of at most two rows), so
+// each volume gather of a wave stays compact.
 //
 // Per column the slabs whose midpoints lie in the cube form one interval
-// [k_in, k_out], found once by exact integer division; a wave stores the
-// unattenuated layers in front of its columns' union of intervals and the
-// final transmittance behind it without touching the volume, and runs the
-// full per-slab work (fetch, transfer function, Eq. 6 correction, product)
-// only inside.  Empty-space verdicts come from the occupancy bits in LDS
-// (without bits every slab in the cube is fetched).
+// [k_in, k_out], found once by exact integer division; a wave runs the full
+// per-slab work (fetch, transfer function, Eq. 6 correction, product) only
+// for slabs in its columns' union of intervals, and otherwise only stores
+// (the unattenuated value in front, the final transmittance behind).
+// Empty-space verdicts come from the occupancy bits in LDS (without bits
+// every slab in the cube is fetched).
 //
 // Slab-midpoint positions are fixed-point numbers (h * 2^40 in an int64, h
 // the offset-voxel coordinate), so stepping from slab to slab is an exact
@@ -36,37 +38,9 @@
 
 namespace vi {
 
-// Row layout: the texels of the two-texel border around the grid are the
-// same in every layer, and so is the whole leading layer -1 (fully
-// transmitting: T = 1, optical depth 0), so a separate small kernel writes
-// the border rings of layers -1 .. n-1 and the slab loop stores only its own
-// texels (layer -1 included).  One lane per border texel and layer: rows -2,
-// -1, res, res+1 (res+4 texels each), then columns -2, -1, res, res+1 of rows
-// 0..res-1.
-template <typename ET>
-__global__ __launch_bounds__(256) void border_kernel(ET* __restrict__ out, int n, int res, uint32_t rlayer,
-                                                     uint32_t rpitch, uint32_t rorg, ET one)
-{
-    const uint32_t W = (uint32_t)res + 4u, per_layer = 4u * W + 4u * (uint32_t)res;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (size_t)per_layer * ((size_t)n + 1u)) return;
-    const int k = (int)(t / per_layer) - 1;
-    const uint32_t q = (uint32_t)(t % per_layer);
-    int row, col;  // grid texel coordinates in [-2, res+1]
-    if (q < 4u * W) {
-        const uint32_t r = q / W;  // 0, 1, 2, 3 -> rows -2, -1, res, res+1
-        row = r < 2u ? (int)r - 2 : res + (int)r - 2;
-        col = (int)(q % W) - 2;
-    } else {
-        const uint32_t r = q - 4u * W, c = r & 3u;
-        row = (int)(r >> 2);
-        col = c < 2u ? (int)c - 2 : res + (int)c - 2;
-    }
-    out[(int64_t)rorg + (int64_t)k * rlayer + (int64_t)row * rpitch + col] = one;
-}
-
-// Workgroup b -> (row, run): rows are dealt to the 8 XCDs in groups of 4
-// consecutive rows (neighbouring rows sample the same voxels and share an
+// Workgroup b -> (row, run): rows (in the row layout, runs of about a row
+// of the layer's element range) are dealt to the 8 XCDs in groups of 4
+// consecutive ones (neighbouring rows sample the same voxels and share an
 // L2), the groups of an XCD spread over the whole light square.
 constexpr uint32_t kRowGroup = 4;
 __device__ __forceinline__ bool row_run_of(uint32_t b, uint32_t rows, uint32_t runs, uint32_t* row, uint32_t* run)
@@ -171,19 +145,115 @@ __device__ __forceinline__ void put_texel(void* out, uint32_t at, float T, float
     else *(__half*)((char*)out + (at << 1)) = __float2half_rn(fast_exp2(-tau));
 }
 
-template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool PT>
-__device__ __forceinline__ void build_run(const BuildParams& P)
+// Shared set-up of both layouts: the TF's opacities and the occupancy bits
+// in LDS.  Empty-space verdicts come from the bits; without them one set bit
+// stands for "every cell may hold opacity" (cell index 0).  Returns the
+// number of 32-bit words the bits take.
+__device__ __forceinline__ uint32_t stage_build_tables(const BuildParams& P, float* s_alpha, uint32_t* s_bits)
+{
+    for (int t = threadIdx.x; t < P.K; t += blockDim.x) s_alpha[t] = P.tf[4 * t + 3];
+    if (P.occ.bits != nullptr) {
+        stage_occupancy(P.occ, s_bits);
+        return P.occ.words + P.occ.swords;
+    }
+    if (threadIdx.x == 0) s_bits[0] = 1u;
+    return 1u;
+}
+
+// The slab-0 midpoint of column (i, j) and (point light) its step, in Q40,
+// the step's length in voxels, and the column's slabs inside the cube.
+template <bool PT>
+__device__ __forceinline__ void column_setup(const BuildParams& P, int i, int j, bool grid, int64_t H[3], int64_t A[3],
+                                             float* e, int* kin, int* kout)
+{
+    for (int a = 0; a < 3; ++a) H[a] = P.B0q[a] + (int64_t)i * P.BUq[a] + (int64_t)j * P.BVq[a];
+    if constexpr (PT) {
+        for (int a = 0; a < 3; ++a) A[a] = P.ALq[a] + (int64_t)i * P.ALUq[a] + (int64_t)j * P.ALVq[a];
+        const float ax = q_to_float(A[0]), ay = q_to_float(A[1]), az = q_to_float(A[2]);
+        *e = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));
+    } else {
+        for (int a = 0; a < 3; ++a) A[a] = P.ALq[a];
+        *e = P.e;
+    }
+    if (grid) {
+        slab_range(H, A, P.n, P.loq, P.hiq, kin, kout);
+    } else {
+        *kin = P.n;  // border, padding or past the grid: no slab
+        *kout = -1;
+    }
+}
+
+// A slab midpoint in Q40: its footprint's lower voxel, trilinear weights and
+// whether it must be fetched (slab k inside the column's cube interval and
+// its cell possibly opaque; a zero-opacity cell leaves T unchanged exactly).
+struct SlabProbe {
+    int gx, gy, gz;
+    float wx, wy, wz;
+    bool fetch;
+};
+__device__ __forceinline__ SlabProbe probe_slab(const BuildParams& P, int64_t hx, int64_t hy, int64_t hz, int k, int kin,
+                                                int kout, const uint32_t* s_bits, int cshift, uint32_t cnc)
+{
+    SlabProbe s;
+    s.gx = q_floor(hx) + P.M;
+    s.gy = q_floor(hy) + P.M;
+    s.gz = q_floor(hz) + P.M;
+    s.wx = q_frac(hx);
+    s.wy = q_frac(hy);
+    s.wz = q_frac(hz);
+    const uint32_t cell = cell_of(s.gx, s.gy, s.gz, P.N, cshift, cnc);
+    s.fetch = k >= kin && k <= kout && occupancy_bit(s_bits, cell);
+    return s;
+}
+
+// One slab of a column (Alg. 1): the volume value at the slab midpoint, the
+// TF opacity clamped to [0, 1] as the render clamps it, corrected to the
+// slab thickness (Eq. 6, extinction form: e = ds / dref), applied to the
+// transmittance T (F32) or added to the optical depth tau in base-2 units
+// (2-byte stacks).  `darken` applies the section 4 compensation
+// (1 + alpha)^m; m = 0 leaves every factor unchanged exactly.
+template <typename VT, int LAYOUT, int OUT_DTYPE>
+__device__ __forceinline__ void slab_step(const BuildParams& P, const float* s_alpha, const RawFoot<VT, LAYOUT>& raw,
+                                          const SlabProbe& s, float e, bool darken, float& T, float& tau)
+{
+    const float v = foot_value<VT, LAYOUT>(raw, s.wx, s.wy, s.wz, P.scale);
+    const float x = v * (float)(P.K - 1);
+    const int e0 = min((int)x, P.K - 2);
+    const float w = x - (float)e0;
+    const float a = clampf01(fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]));
+    const float l2 = fast_log2(1.0f - a);  // -inf for a = 1
+    if (OUT_DTYPE == VI_F32) {
+        // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
+        float f = fast_exp2(e * l2);
+        // section 4 compensation: times (1 + alpha)^m, at most 1
+        if (darken) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
+        T *= f;
+    } else {
+        // optical depth in base-2 units: sigma ds / ln 2 = -e log2(1 - a),
+        // capped at 64 / ln 2 per slab (a factor e^-64); the compensation
+        // subtracts m log2(1 + alpha), floored at 0
+        float dtau = -e * l2;
+        if (darken) dtau = fmaxf(dtau - P.darken * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
+        tau += fminf(dtau, 92.332482616893656f);
+    }
+}
+
+// Tiled layout: one workgroup per run of NT * C texels of one stack row,
+// lane l owning columns l, l + NT, ..., l + NT (C - 1) of the run (or C
+// adjacent ones).  Slabs in front of a wave's columns' union of cube
+// intervals and behind it are stored without touching the volume; inside,
+// batches of B slabs: positions and empty-space verdicts, then every volume
+// load of the batch, and only then the arithmetic and the stores -- one
+// wait per batch, with C * B footprints in flight.
+template <typename VT, int LAYOUT, int OUT_DTYPE, bool PT>
+__device__ __forceinline__ void build_tiled(const BuildParams& P)
 {
     constexpr int NT = kBuildNT, C = kBuildC, B = kBuildB;
     constexpr int CS = kBuildConsec ? 1 : NT;  // stride between a lane's columns
     extern __shared__ float s_alpha[];  // K alphas, then the occupancy bits
     uint32_t* s_bits = (uint32_t*)(s_alpha + P.K);
-    for (int t = threadIdx.x; t < P.K; t += blockDim.x) s_alpha[t] = P.tf[4 * t + 3];
-    // Empty-space verdicts come from the occupancy bits in LDS; without them
-    // one set bit stands for "every cell may hold opacity" (cell index 0).
+    stage_build_tables(P, s_alpha, s_bits);
     const bool use_bits = P.occ.bits != nullptr;
-    if (use_bits) stage_occupancy(P.occ, s_bits);
-    else if (threadIdx.x == 0) s_bits[0] = 1u;
     const int cshift = use_bits ? P.occ.shift : 30;
     const uint32_t cnc = use_bits ? P.occ.nc : 1u;
     __syncthreads();
@@ -191,157 +261,73 @@ __device__ __forceinline__ void build_run(const BuildParams& P)
     const uint32_t runs = ((uint32_t)P.res + NT * C - 1) / (NT * C);
     uint32_t row, run;
     if (!row_run_of(blockIdx.x, (uint32_t)P.res, runs, &row, &run)) return;
-    const int j = (int)row;
     const int i0 = (int)(run * NT * C) + (kBuildConsec ? C * (int)threadIdx.x : (int)threadIdx.x);
+    const int j = (int)row;
 
-    // per column: the slab-0 midpoint and (point light) the step, in Q40;
-    // the slabs inside the cube; the texel's element in layer 0
-    int64_t Hx[C], Hy[C], Hz[C];
-    int64_t Ax[PT ? C : 1], Ay[PT ? C : 1], Az[PT ? C : 1];
-    float ex[PT ? C : 1];
+    int64_t H[C][3], A[C][3];
+    float ex[C];
     int kin[C], kout[C];
+    bool col[C];
     uint32_t at[C];
     int kmin = P.n, kmax = -1;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int i = i0 + CS * c;
-        const int q = PT ? c : 0;
-        Hx[c] = P.B0q[0] + (int64_t)i * P.BUq[0] + (int64_t)j * P.BVq[0];
-        Hy[c] = P.B0q[1] + (int64_t)i * P.BUq[1] + (int64_t)j * P.BVq[1];
-        Hz[c] = P.B0q[2] + (int64_t)i * P.BUq[2] + (int64_t)j * P.BVq[2];
-        if constexpr (PT) {
-            Ax[c] = P.ALq[0] + (int64_t)i * P.ALUq[0] + (int64_t)j * P.ALVq[0];
-            Ay[c] = P.ALq[1] + (int64_t)i * P.ALUq[1] + (int64_t)j * P.ALVq[1];
-            Az[c] = P.ALq[2] + (int64_t)i * P.ALUq[2] + (int64_t)j * P.ALVq[2];
-            const float ax = q_to_float(Ax[c]), ay = q_to_float(Ay[c]), az = q_to_float(Az[c]);
-            ex[c] = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));  // the step's length, voxels
-        } else if (c == 0) {
-            Ax[0] = P.ALq[0], Ay[0] = P.ALq[1], Az[0] = P.ALq[2];
-            ex[0] = P.e;
-        }
-        if (i < P.res) {
-            const int64_t H3[3] = {Hx[c], Hy[c], Hz[c]}, A3[3] = {Ax[q], Ay[q], Az[q]};
-            slab_range(H3, A3, P.n, P.loq, P.hiq, &kin[c], &kout[c]);
-        } else {
-            kin[c] = P.n;  // not a column of the grid: no slab, no store
-            kout[c] = -1;
-        }
+        col[c] = i < P.res;
+        column_setup<PT>(P, i, j, col[c], H[c], A[c], &ex[c], &kin[c], &kout[c]);
+        at[c] = stack_oj(j, P.row_tiles32) + stack_oi(i);
         kmin = min(kmin, kin[c]);
         kmax = max(kmax, kout[c]);
-        at[c] = SL == VI_STACK_ROWS ? P.rorg + (uint32_t)j * P.rpitch + (uint32_t)i
-                                    : stack_oj(j, P.row_tiles32) + stack_oi(i);
     }
-    bool col[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) col[c] = i0 + CS * c < P.res;
     // the wave's slabs with any midpoint in the cube: [kmin, kmax]
     kmin = __builtin_amdgcn_readfirstlane(wave_min(kmin));
     kmax = __builtin_amdgcn_readfirstlane(wave_max(kmax));
-    const uint32_t layer = SL == VI_STACK_ROWS ? P.rlayer : P.layer;
-    // row layout: the leading layer -1 (face 0) transmits fully
-    if (SL == VI_STACK_ROWS)
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c] - layer, 1.0f, 0.0f);
+    const uint32_t layer = P.layer;
 
     // slabs in front of the cube: the light arrives unattenuated
-    {
-        const int k1 = min(kmin, P.n);
-        for (int k = 0; k < k1; ++k)
+    for (int k = 0; k < min(kmin, P.n); ++k)
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c], 1.0f, 0.0f);
-                at[c] += layer;
-            }
-    }
+        for (int c = 0; c < C; ++c) {
+            if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c], 1.0f, 0.0f);
+            at[c] += layer;
+        }
 
     const VT* __restrict__ vol = (const VT*)P.vol;
     const VolIndex VI_ = {1u, P.vsy, P.vsz};
-    const float Km1 = (float)(P.K - 1);
-    float T[C], tau[C];  // transmittance (F32 form), optical depth (BF16 form)
+    float T[C], tau[C];
+    const int kstart = kmin < P.n ? kmin : 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         T[c] = 1.0f, tau[c] = 0.0f;
-        // positions at the first slab of the wave's range
-        const int q = PT ? c : 0;
-        const int k0 = kmin < P.n ? kmin : 0;
-        Hx[c] += (int64_t)k0 * Ax[q];
-        Hy[c] += (int64_t)k0 * Ay[q];
-        Hz[c] += (int64_t)k0 * Az[q];
+        for (int a = 0; a < 3; ++a) H[c][a] += (int64_t)kstart * A[c][a];  // positions at slab kmin
     }
-    // the section 4 compensation (1 + alpha)^m; m = 0 leaves every factor
-    // unchanged exactly (f * 2^0 = f, min(f, 1) = f)
     const bool darken = P.darken > 0.0f;
 
-    // The wave's range in batches of B slabs for all C columns: positions and
-    // empty-space verdicts, then every volume load of the batch, and only then
-    // the arithmetic and the stores -- one wait per batch, with C * B
-    // footprints in flight.
     for (int k0 = kmin; k0 <= kmax; k0 += B) {
-        bool fetch[C][B];
-        int gx[C][B], gy[C][B], gz[C][B];
-        float wx[C][B], wy[C][B], wz[C][B];
+        SlabProbe sp[C][B];
+        RawFoot<VT, LAYOUT> raw[C][B];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int q = PT ? c : 0;
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                // slab k0 + u: H0 + (k0 + u) A, exact
-                const int64_t hx = Hx[c] + (int64_t)u * Ax[q], hy = Hy[c] + (int64_t)u * Ay[q],
-                              hz = Hz[c] + (int64_t)u * Az[q];
-                const int k = k0 + u;
-                gx[c][u] = q_floor(hx) + P.M;
-                gy[c][u] = q_floor(hy) + P.M;
-                gz[c][u] = q_floor(hz) + P.M;
-                wx[c][u] = q_frac(hx);
-                wy[c][u] = q_frac(hy);
-                wz[c][u] = q_frac(hz);
-                const uint32_t cell = cell_of(gx[c][u], gy[c][u], gz[c][u], P.N, cshift, cnc);
-                // a zero-opacity cell leaves T unchanged exactly
-                fetch[c][u] = k >= kin[c] && k <= kout[c] && occupancy_bit(s_bits, cell);
-            }
-            Hx[c] += (int64_t)B * Ax[q];
-            Hy[c] += (int64_t)B * Ay[q];
-            Hz[c] += (int64_t)B * Az[q];
+            for (int u = 0; u < B; ++u)
+                sp[c][u] = probe_slab(P, H[c][0] + (int64_t)u * A[c][0], H[c][1] + (int64_t)u * A[c][1],
+                                      H[c][2] + (int64_t)u * A[c][2], k0 + u, kin[c], kout[c], s_bits, cshift, cnc);
+            for (int a = 0; a < 3; ++a) H[c][a] += (int64_t)B * A[c][a];
         }
-        RawFoot<VT, LAYOUT> raw[C][B];
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
             for (int u = 0; u < B; ++u)
-                if (fetch[c][u])
-                    foot_load_g<VT, LAYOUT>(raw[c][u], wx[c][u], wy[c][u], vol, VI_, P.N, gx[c][u], gy[c][u],
-                                            gz[c][u]);
+                if (sp[c][u].fetch)
+                    foot_load_g<VT, LAYOUT>(raw[c][u], sp[c][u].wx, sp[c][u].wy, vol, VI_, P.N, sp[c][u].gx,
+                                            sp[c][u].gy, sp[c][u].gz);
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             if (k0 + u > kmax) break;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                if (fetch[c][u]) {
-                    const float v = foot_value<VT, LAYOUT>(raw[c][u], wx[c][u], wy[c][u], wz[c][u], P.scale);
-                    const float x = v * Km1;
-                    const int e0 = min((int)x, P.K - 2);
-                    const float w = x - (float)e0;
-                    // the table's opacity clamped to [0, 1], as the render clamps it
-                    const float a = clampf01(fmaf(w, s_alpha[e0 + 1] - s_alpha[e0], s_alpha[e0]));
-                    const float l2 = fast_log2(1.0f - a);  // -inf for a = 1
-                    const float e = ex[PT ? c : 0];
-                    if (OUT_DTYPE == VI_F32) {
-                        // (1 - alpha(ds)) = (1 - a)^(ds / dref) = 2^(e log2(1 - a))
-                        float f = fast_exp2(e * l2);
-                        // section 4 compensation: times (1 + alpha)^m, at most 1
-                        if (darken) f = fminf(f * fast_exp2(P.darken * fast_log2(2.0f - f)), 1.0f);
-                        T[c] *= f;
-                    } else {
-                        // optical depth in base-2 units: sigma ds / ln 2 =
-                        // -e log2(1 - a), capped at 64 / ln 2 per slab (a factor
-                        // e^-64); the compensation subtracts m log2(1 + alpha),
-                        // floored at 0
-                        float dtau = -e * l2;
-                        if (darken) dtau = fmaxf(dtau - P.darken * fast_log2(2.0f - fast_exp2(e * l2)), 0.0f);
-                        tau[c] += fminf(dtau, 92.332482616893656f);
-                    }
-                }
+                if (sp[c][u].fetch) slab_step<VT, LAYOUT, OUT_DTYPE>(P, s_alpha, raw[c][u], sp[c][u], ex[c], darken,
+                                                                     T[c], tau[c]);
                 if (col[c]) put_texel<OUT_DTYPE>(P.out, at[c], T[c], tau[c]);
                 at[c] += layer;
             }
@@ -357,10 +343,106 @@ __device__ __forceinline__ void build_run(const BuildParams& P)
         }
 }
 
+// Row layout.  A layer, border and padding included, is one run of LS
+// elements, LS times the element size an odd multiple of 64 bytes: the same
+// texel of two neighbouring layers lies half a 128-byte line apart, as the
+// render's lookups need (the lanes of a ray group read neighbouring layers
+// at one texel position in the same load instruction; a whole-line layer
+// stride made those reads collide in the L1 tags, 6-8 % slower frames).  In
+// a buffer aligned to 128 bytes layers -1, 1, 3, ... then start on a line
+// and layers 0, 2, 4, ... half a line past one.
+//
+// The workgroup owns NT consecutive elements of a layer's run, one column
+// per lane; border and padding lanes store the fully transmitting value
+// without touching the volume.  It walks the slabs two at a time, in step
+// across the workgroup: layer k0 + 1 (on the line grid) is stored by the
+// lane that owns each element, layer k0 (half a line off) goes through LDS
+// rotated by half a line, so that every wave's store there starts on a line
+// too; only the two half-lines at the ends of the workgroup's run are
+// written in part.  (Stores straddling lines measured at half the write
+// rate.)  One barrier per pair of slabs, reached by every wave the same
+// number of times; a wave with no slab inside the cube in a pair only
+// stores.
+template <typename VT, int LAYOUT, int OUT_DTYPE, bool PT>
+__device__ __forceinline__ void build_rows(const BuildParams& P)
+{
+    static_assert(kBuildC == 1 && !kBuildConsec, "the row-layout build runs one column per lane");
+    constexpr uint32_t NT = kBuildNT;
+    constexpr uint32_t HALF = OUT_DTYPE == VI_F32 ? 16u : 32u;  // half a 128-byte line, in elements
+    extern __shared__ float s_alpha[];  // K alphas, the occupancy bits, then two exchange rows of NT
+    uint32_t* s_bits = (uint32_t*)(s_alpha + P.K);
+    float* s_x = (float*)(s_bits + stage_build_tables(P, s_alpha, s_bits));
+    const bool use_bits = P.occ.bits != nullptr;
+    const int cshift = use_bits ? P.occ.shift : 30;
+    const uint32_t cnc = use_bits ? P.occ.nc : 1u;
+    __syncthreads();
+
+    const uint32_t span = P.rlayer;
+    uint32_t unit, one;
+    if (!row_run_of(blockIdx.x, (span + NT - 1) / NT, 1u, &unit, &one)) return;  // uniform per workgroup
+    const uint32_t t = threadIdx.x, f = unit * NT + t;
+    // in layers half a line off, lane t stores the element of lane tr
+    const uint32_t tr = (t + HALF) % NT, fr = unit * NT + tr;
+    const int i = (int)(f % P.rpitch) - 2, j = (int)(f / P.rpitch) - 2;
+    const bool col = f < span, col_r = fr < span;
+    const bool grid = col && i >= 0 && i < P.res && j >= 0 && j < P.res;
+
+    int64_t H[3], A[3];
+    float ex;
+    int kin, kout;
+    column_setup<PT>(P, i, j, grid, H, A, &ex, &kin, &kout);
+    // the wave's slabs with any midpoint in the cube: [kmin, kmax]
+    const int kmin = __builtin_amdgcn_readfirstlane(wave_min(kin));
+    const int kmax = __builtin_amdgcn_readfirstlane(wave_max(kout));
+    const uint32_t layer = P.rlayer;
+    uint32_t at = layer + f, at_r = layer + fr;  // elements of layer 0
+
+    // the leading layer -1 (face 0) transmits fully
+    if (col) put_texel<OUT_DTYPE>(P.out, f, 1.0f, 0.0f);
+
+    const VT* __restrict__ vol = (const VT*)P.vol;
+    const VolIndex VI_ = {1u, P.vsy, P.vsz};
+    const bool darken = P.darken > 0.0f;
+    float T = 1.0f, tau = 0.0f;  // transmittance (float stack), optical depth (2-byte stacks)
+    for (int k0 = 0; k0 < P.n; k0 += 2) {
+        float v0;  // the value of layer k0: T or tau
+        if (k0 + 1 >= kmin && k0 <= kmax) {  // uniform per wave
+            SlabProbe sp[2];
+            RawFoot<VT, LAYOUT> raw[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                sp[u] = probe_slab(P, H[0] + (int64_t)u * A[0], H[1] + (int64_t)u * A[1], H[2] + (int64_t)u * A[2],
+                                   k0 + u, kin, kout, s_bits, cshift, cnc);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (sp[u].fetch)
+                    foot_load_g<VT, LAYOUT>(raw[u], sp[u].wx, sp[u].wy, vol, VI_, P.N, sp[u].gx, sp[u].gy, sp[u].gz);
+            if (sp[0].fetch) slab_step<VT, LAYOUT, OUT_DTYPE>(P, s_alpha, raw[0], sp[0], ex, darken, T, tau);
+            v0 = OUT_DTYPE == VI_F32 ? T : tau;
+            if (sp[1].fetch) slab_step<VT, LAYOUT, OUT_DTYPE>(P, s_alpha, raw[1], sp[1], ex, darken, T, tau);
+        } else {
+            v0 = OUT_DTYPE == VI_F32 ? T : tau;
+        }
+        for (int a = 0; a < 3; ++a) H[a] += 2 * A[a];
+        // layer k0 + 1, on the line grid: its own lane
+        if (k0 + 1 < P.n && col) put_texel<OUT_DTYPE>(P.out, at + layer, T, tau);
+        // layer k0, half a line off: rotated through LDS (two rows in turn,
+        // so one barrier per pair of slabs keeps writes and reads apart)
+        float* x = s_x + ((uint32_t)(k0 >> 1) & 1u) * NT;
+        x[t] = v0;
+        __syncthreads();
+        const float w = x[tr];
+        if (col_r) put_texel<OUT_DTYPE>(P.out, at_r, w, w);
+        at += 2 * layer;
+        at_r += 2 * layer;
+    }
+}
+
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool PT>
 __global__ __launch_bounds__(kBuildNT) void build_kernel(BuildParams P)
 {
-    build_run<VT, LAYOUT, OUT_DTYPE, SL, PT>(P);
+    if constexpr (SL == VI_STACK_ROWS) build_rows<VT, LAYOUT, OUT_DTYPE, PT>(P);
+    else build_tiled<VT, LAYOUT, OUT_DTYPE, PT>(P);
 }
 
 template <typename VT, int LAYOUT, int SL, bool PT>
@@ -377,23 +459,19 @@ static void launch_build_k(const BuildParams& p, dim3 grid, size_t lds, hipStrea
 template <typename VT, int LAYOUT>
 static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
 {
-    const uint32_t runs = ((uint32_t)p.res + kBuildNT * kBuildC - 1) / (kBuildNT * kBuildC);
-    const dim3 grid(row_run_grid((uint32_t)p.res, runs));
+    constexpr uint32_t per_group = (uint32_t)kBuildNT * kBuildC;
     // (at least one word of bits: without them word 0 says "occupied")
     const size_t lds = sizeof(float) * (size_t)p.K + sizeof(uint32_t) * std::max(p.occ.words + p.occ.swords, 1u);
     if (p.out_layout == VI_STACK_ROWS) {
-        if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds, s);
-        else launch_build_k<VT, LAYOUT, VI_STACK_ROWS, false>(p, grid, lds, s);
-        // the border, the same in every layer
-        const size_t nb = (4u * (size_t)(p.res + 4) + 4u * (size_t)p.res) * ((size_t)p.n + 1u);
-        const dim3 bgrid((uint32_t)((nb + 255) / 256));
-        if (p.out_dtype == VI_F32)
-            hipLaunchKernelGGL((border_kernel<float>), bgrid, dim3(256), 0, s, (float*)p.out, p.n, p.res, p.rlayer,
-                               p.rpitch, p.rorg, 1.0f);
-        else  // bfloat16 optical depth 0, or half-precision transmittance 1
-            hipLaunchKernelGGL((border_kernel<uint16_t>), bgrid, dim3(256), 0, s, (uint16_t*)p.out, p.n, p.res,
-                               p.rlayer, p.rpitch, p.rorg, (uint16_t)(p.out_dtype == VI_F16 ? 0x3c00u : 0u));
+        // runs of a layer's element range, border and padding included; two
+        // exchange rows of floats
+        const dim3 grid(row_run_grid((p.rlayer + per_group - 1) / per_group, 1u));
+        const size_t lds_rows = lds + 2 * sizeof(float) * (size_t)kBuildNT;
+        if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds_rows, s);
+        else launch_build_k<VT, LAYOUT, VI_STACK_ROWS, false>(p, grid, lds_rows, s);
     } else {
+        const uint32_t runs = ((uint32_t)p.res + per_group - 1) / per_group;
+        const dim3 grid(row_run_grid((uint32_t)p.res, runs));
         if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_TILED, true>(p, grid, lds, s);
         else launch_build_k<VT, LAYOUT, VI_STACK_TILED, false>(p, grid, lds, s);
     }

@@ -288,12 +288,21 @@ def row_pitch(res: int, dtype: int = VI_F32) -> int:
     return (res + 4 + 3) // 4 * 4
 
 
+def row_layer(res: int, dtype: int = VI_F32) -> int:
+    """Elements per layer of the row layout: the least odd multiple of half a
+    128-byte line (16 floats, 32 two-byte texels) from (res + 4) x pitch up."""
+    half = 16 if dtype == VI_F32 else 32
+    m = -(-(res + 4) * row_pitch(res, dtype) // half)
+    return (m | 1) * half
+
+
 @dataclass
 class Slices:
     """An attenuation stack: the device buffer and its descriptor.  Tiled:
     8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Rows:
-    (n+1) x (res+4) x P, texel (k, j, i) at [k+1, j+2, i+2]: a leading layer
-    and a two-texel border around the res x res grid, all fully transmitting."""
+    (n+1) x (res+4) x P with layer stride row_layer(res), texel (k, j, i) at
+    [k+1, j+2, i+2]: a leading layer and a two-texel border around the
+    res x res grid, all fully transmitting."""
     data: torch.Tensor | None
     s: Slices_t
 
@@ -386,7 +395,10 @@ def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda", layout: i
     """An uninitialised device buffer in a stack layout (shapes as in Slices)."""
     tdt = {VI_F32: torch.float32, VI_BF16: torch.bfloat16, VI_F16: torch.float16}[dtype]
     if layout == VI_STACK_ROWS:
-        return torch.empty((n + 1, res + 4, row_pitch(res, dtype)), dtype=tdt, device=device)
+        # (n+1) x (res+4) x P over layers of row_layer elements
+        ls, p = row_layer(res, dtype), row_pitch(res, dtype)
+        flat = torch.empty((n + 1) * ls, dtype=tdt, device=device)
+        return flat.as_strided((n + 1, res + 4, p), (ls, p, 1))
     r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
     return torch.empty((n, r4 // 4, r8 // 8, 4, 8), dtype=tdt, device=device)
 
@@ -414,7 +426,10 @@ def build_attenuation(vol: Volume, tf: TF, light_dir, n_slices: int, slice_res: 
     is then ignored and may be None)."""
     if out is None:
         out = stack_buffer(n_slices, slice_res, dtype, vol.data.device, layout)
-    if out.numel() * out.element_size() < slices_bytes(n_slices, slice_res, dtype, layout):
+    # (a row-layout stack is a strided view whose layers may end in padding:
+    # count the bytes of its storage from the view's first element)
+    avail = out.untyped_storage().nbytes() - out.storage_offset() * out.element_size()
+    if avail < slices_bytes(n_slices, slice_res, dtype, layout):
         raise ValueError("stack buffer too small")
     s = Slices_t()
     ld = _vec3(light_dir) if light_dir is not None else None
