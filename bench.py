@@ -48,9 +48,9 @@ MEASURED = {
     # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1
     # (lights 0, 0, 1); per launch: FETCH_SIZE / WRITE_SIZE in KiB, SQ_INSTS_VALU, GRBM_GUI_ACTIVE
     # (summed over the 8 XCDs), TA_TA_BUSY_sum and the other SQ counters of the same passes
-    ("build", "large", "rows", 16, "quads"): {"sha256": "60a925d0adaee6452ae28e34dabe8cd97ef64ccadae0e8d8217d3cf755a35387", "fetch_kib": 311391.4, "write_kib": 2323506.6, "valu_insts": 151067640, "gui_cycles": 19848809, "ta_busy": 442732980, "vmem_rd": 1229360, "vmem_wr": 8404992, "waves": 16384, "wave_cycles": 2417193486, "busy_cycles": 78017670, "wait_inst_any": 1194736821, "lds_insts": 2803424, "salu_insts": 59573447, "tcp_accesses": 83333396},
-    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "139aa270919f7515964588b0b188ff3395f8c1deadf550038a218f948c04b793", "fetch_kib": 108679.5, "write_kib": 33389.0, "valu_insts": 541556037, "gui_cycles": 20403040, "ta_busy": 368592803, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2472088470, "busy_cycles": 73104390, "wait_inst_any": 401286993, "lds_insts": 16872411, "salu_insts": 116432238, "tcp_accesses": 448494575},
-    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "139aa270919f7515964588b0b188ff3395f8c1deadf550038a218f948c04b793", "fetch_kib": 120285.0, "write_kib": 33491.1, "valu_insts": 595820378, "gui_cycles": 23190306, "ta_busy": 450709008, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2326198305, "busy_cycles": 79679379, "wait_inst_any": 531290148, "lds_insts": 16872411, "salu_insts": 138750415, "tcp_accesses": 579402332},
+    ("build", "large", "rows", 16, "quads"): {"sha256": "045643794df170f2a57c0169edd8adcdefb440a1779889200a976fcdb17bd381", "fetch_kib": 273494.5, "write_kib": 2119779.0, "valu_insts": 168741141, "gui_cycles": 14170968, "ta_busy": 274163419, "vmem_rd": 1226619, "vmem_wr": 8471169, "waves": 16896, "wave_cycles": 3230758005, "busy_cycles": 55746904, "wait_inst_any": 565919262, "lds_insts": 11275370, "salu_insts": 108490483, "tcp_accesses": 66792582},
+    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "fd38f1e60ce1e2ca63263618a3afc68a0635c5f55f774db985b58da8f64f3834", "fetch_kib": 108651.7, "write_kib": 33397.9, "valu_insts": 541556037, "gui_cycles": 20337362, "ta_busy": 368415554, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2477481161, "busy_cycles": 72908618, "wait_inst_any": 400610812, "lds_insts": 16872411, "salu_insts": 116432238, "tcp_accesses": 448494575},
+    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "fd38f1e60ce1e2ca63263618a3afc68a0635c5f55f774db985b58da8f64f3834", "fetch_kib": 120346.1, "write_kib": 33494.8, "valu_insts": 595820378, "gui_cycles": 23067013, "ta_busy": 450340420, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2313563150, "busy_cycles": 79751580, "wait_inst_any": 534150019, "lds_insts": 16872411, "salu_insts": 138750415, "tcp_accesses": 579402332},
 }
 
 
