@@ -154,15 +154,17 @@ typedef struct {
  *     (padding never read).  n*R8*R4 elements.
  *   VI_STACK_ROWS: every layer row-major with a border two texels wide of
  *     fully transmitting texels (T = 1, optical depth 0) around the grid,
- *     and one leading layer k = -1 that transmits fully everywhere (face 0
- *     of the depth index of Eq. 9).  The two texels of a bilinear row,
- *     (k, j, i) and (k, j, i+1), are adjacent, so one load per row
- *     reads them, and every footprint of a lookup, clamped to i, j in
- *     [-2, res] and k in [-1, n-1], reads stored texels only.  With row
- *     pitch P = res+4 rounded up to 4 and LS = the least odd multiple of h
- *     from (res+4)*P up, h = 16 for VI_F32 and 32 for the 2-byte dtypes
- *     (half a 128-byte line), texel (k, j, i), k in [-1, n-1], i and j in
- *     [-2, res+1], is element (k+1)*LS + (j+2)*P + (i+2); (n+1)*LS elements
+ *     one leading layer k = -1 that transmits fully everywhere (face 0 of
+ *     the depth index of Eq. 9), and one trailing layer k = n equal to
+ *     layer n-1 (the light leaving the last slab).  The two texels of a
+ *     bilinear row, (k, j, i) and (k, j, i+1), are adjacent, so one load
+ *     per row reads them, and every footprint of a lookup, clamped to i, j
+ *     in [-2, res] and k in [-1, n-1] (with its second layer k+1), reads
+ *     stored texels only.  With row pitch P = res+4 rounded up to 4 and
+ *     LS = the least odd multiple of h from (res+4)*P up, h = 16 for VI_F32
+ *     and 32 for the 2-byte dtypes (half a 128-byte line), texel (k, j, i),
+ *     k in [-1, n], i and j in [-2, res+1], is element
+ *     (k+1)*LS + (j+2)*P + (i+2); (n+2)*LS elements
  *     (columns res+4 .. P-1 and a layer's last LS - (res+4)*P elements are
  *     never read).  The same texel of neighbouring layers lies half a line
  *     apart; in a buffer aligned to 128 bytes every other layer starts on a
@@ -265,7 +267,7 @@ const char* vi_last_error(void);
 int vi_default_render_opts(vi_render_opts* o);
 
 /* Bytes of a stack buffer (element 4 bytes for VI_F32, 2 for VI_BF16 and
- * VI_F16): tiled n*R8*R4 elements, rows (n+1)*LS elements; 0 for invalid
+ * VI_F16): tiled n*R8*R4 elements, rows (n+2)*LS elements; 0 for invalid
  * arguments (VI_F16 with the tiled layout included). */
 size_t vi_slices_bytes(int n_slices, int slice_res, int slice_dtype, int slice_layout);
 

@@ -154,7 +154,9 @@ bool stack_size_ok(int n, int res, int dt, int sl) { return (double)vi_slices_by
 
 // Row layout: every layer has rows -2 .. res+1 and columns -2 .. res+1 of
 // texels, the two outermost rings a fully transmitting border; one extra
-// leading layer (-1, face 0 of Eq. 9's index) transmits fully too.  The
+// leading layer (-1, face 0 of Eq. 9's index) transmits fully too, and one
+// trailing layer n repeats layer n - 1 (the light leaving the last slab), so
+// that a lookup's second layer k0 + 1 needs no clamp.  The
 // pitch P is res + 4 rounded up to 4.  A layer holds the least number of
 // elements from (res + 4) P up that is an odd multiple of half a 128-byte
 // line (16 floats, 32 two-byte texels): the same texel of two neighbouring
@@ -311,7 +313,7 @@ size_t vi_slices_bytes(int n, int res, int dt, int sl)
     if (sl == VI_STACK_TILED && dt == VI_F16) return 0;
     if (sl == VI_STACK_TILED)
         return (size_t)n * vi::round_up((uint32_t)res, 8u) * vi::round_up((uint32_t)res, 4u) * elem_size(dt);
-    if (sl == VI_STACK_ROWS) return ((size_t)n + 1u) * row_layer(res, dt) * elem_size(dt);
+    if (sl == VI_STACK_ROWS) return ((size_t)n + 2u) * row_layer(res, dt) * elem_size(dt);
     return 0;
 }
 
@@ -653,6 +655,12 @@ int make_frame(const vi_volume* vol, const vi_tf* tf, const vi_slices* sl, const
         F.rlayer = row_layer(sl->res, sl->dtype);
         F.Mz = sl->n / 2;
         F.Mr = sl->res / 2;
+        // rows: the shifted bases and the element of light-grid cell (0, 0, 0)
+        const size_t es = elem_size(sl->dtype);
+        F.stack_r1 = (const char*)sl->data + (size_t)F.rpitch * es;
+        F.stack_l1 = (const char*)sl->data + (size_t)F.rlayer * es;
+        F.stack_l1r1 = (const char*)sl->data + ((size_t)F.rlayer + F.rpitch) * es;
+        F.rbase = F.rorg + (uint32_t)F.Mr * F.rpitch + (uint32_t)F.Mr + (uint32_t)F.Mz * F.rlayer;
         const double span = sl->dmax - sl->dmin, sc = sl->res / (2.0 * sl->R);
         for (int a = 0; a < 3; ++a) {
             Lq[a] = sl->n * sl->L[a] / span;

@@ -358,8 +358,9 @@ __device__ __forceinline__ void build_tiled(const BuildParams& P)
 // and layers 0, 2, 4, ... half a line past one.
 //
 // The workgroup owns NT consecutive elements of a layer's run, one column
-// per lane; border and padding lanes store the fully transmitting value
-// without touching the volume.  It walks the slabs two at a time, in step
+// per lane, in every layer from the leading layer -1 to the trailing layer n
+// (a copy of layer n - 1); border and padding lanes store the fully
+// transmitting value without touching the volume.  It walks the slabs two at a time, in step
 // across the workgroup: layer k0 + 1 (on the line grid) is stored by the
 // lane that owns each element, layer k0 (half a line off) goes through LDS
 // rotated by half a line, so that every wave's store there starts on a line
@@ -457,6 +458,8 @@ __device__ __forceinline__ void build_rows(const BuildParams& P)
             at_r += 2 * layer;
         }
     }
+    // the trailing layer n repeats layer n - 1
+    if (col) put_texel<OUT_DTYPE>(P.out, (uint32_t)(P.n + 1) * layer + f, T, tau);
 }
 
 template <typename VT, int LAYOUT, int OUT_DTYPE, int SL, bool PT>

@@ -88,6 +88,12 @@ struct RenderFrame {
     int K;
     // stack
     const void* stack;
+    // rows: the stack advanced by one row, one layer, and one layer and one
+    // row, so that the four loads of a lookup share one offset
+    const void* stack_r1;
+    const void* stack_l1;
+    const void* stack_l1r1;
+    uint32_t rbase;  // rows: element of light-grid cell (iz, iy, ix) = rbase + iz rlayer + iy rpitch + ix
     int stack_dtype;
     int n, res;
     int stack_layout;

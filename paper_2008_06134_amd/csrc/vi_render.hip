@@ -120,15 +120,16 @@ __device__ __forceinline__ void rowtap_load(const RenderFrame& F, float z, float
     t.wz = z - fz;
     t.wx = x - fx;
     t.wy = y - fy;
-    const int k0 = (int)fz + F.Mz;                 // -1 .. n-1
-    const int k1 = min(k0 + 1, F.n - 1);
-    const int a = (int)fx + F.Mr, b = (int)fy + F.Mr;  // -2 .. res
-    const uint32_t e = (uint32_t)((int)F.rorg + b * (int)F.rpitch + a);
-    const uint32_t base0 = e + (uint32_t)(k0 * (int)F.rlayer), base1 = e + (uint32_t)(k1 * (int)F.rlayer);
-    t.a0 = pair_load<SDT>(F.stack, base0);
-    t.a1 = pair_load<SDT>(F.stack, base0 + F.rpitch);
-    t.b0 = pair_load<SDT>(F.stack, base1);
-    t.b1 = pair_load<SDT>(F.stack, base1 + F.rpitch);
+    // texel (k0, b, a) of the footprint, k0 = iz + Mz in -1 .. n-1 and
+    // a, b = ix, iy + Mr in -2 .. res: one offset for all four loads, whose
+    // next row and next layer come from the shifted bases (layer n repeats
+    // layer n-1, so k0 + 1 needs no clamp)
+    const int iz = (int)fz, ix = (int)fx, iy = (int)fy;
+    const uint32_t e = F.rbase + (uint32_t)(iz * (int)F.rlayer) + (uint32_t)__mul24(iy, (int)F.rpitch) + (uint32_t)ix;
+    t.a0 = pair_load<SDT>(F.stack, e);
+    t.a1 = pair_load<SDT>(F.stack_r1, e);
+    t.b0 = pair_load<SDT>(F.stack_l1, e);
+    t.b1 = pair_load<SDT>(F.stack_l1r1, e);
 }
 template <int SDT>
 __device__ __forceinline__ float rowtap_value(const RowTap<SDT>& t)

@@ -300,9 +300,10 @@ def row_layer(res: int, dtype: int = VI_F32) -> int:
 class Slices:
     """An attenuation stack: the device buffer and its descriptor.  Tiled:
     8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Rows:
-    (n+1) x (res+4) x P with layer stride row_layer(res), texel (k, j, i) at
+    (n+2) x (res+4) x P with layer stride row_layer(res), texel (k, j, i) at
     [k+1, j+2, i+2]: a leading layer and a two-texel border around the
-    res x res grid, all fully transmitting."""
+    res x res grid, all fully transmitting, and a trailing layer equal to
+    the last."""
     data: torch.Tensor | None
     s: Slices_t
 
@@ -312,12 +313,12 @@ class Slices:
         t = self.data
         if self.s.layout == VI_STACK_ROWS:
             e = row_origin(self.s.dtype)
-            return t[1:, 2:r + 2, e:e + r]
+            return t[1:n + 1, 2:r + 2, e:e + r]
         return t.permute(0, 1, 3, 2, 4).reshape(n, t.shape[1] * 4, t.shape[2] * 8)[:, :r, :r]
 
     def padded(self) -> torch.Tensor:
-        """Row layout only: (n+1) x (res+4) x (res+4), the grid with its border
-        and the leading layer."""
+        """Row layout only: (n+2) x (res+4) x (res+4), the grid with its border,
+        the leading layer and the trailing layer."""
         r, e = self.s.res, row_origin(self.s.dtype)
         return self.data[:, :, e - 2:e + r + 2]
 
@@ -395,10 +396,10 @@ def stack_buffer(n: int, res: int, dtype: int = VI_F32, device="cuda", layout: i
     """An uninitialised device buffer in a stack layout (shapes as in Slices)."""
     tdt = {VI_F32: torch.float32, VI_BF16: torch.bfloat16, VI_F16: torch.float16}[dtype]
     if layout == VI_STACK_ROWS:
-        # (n+1) x (res+4) x P over layers of row_layer elements
+        # (n+2) x (res+4) x P over layers of row_layer elements
         ls, p = row_layer(res, dtype), row_pitch(res, dtype)
-        flat = torch.empty((n + 1) * ls, dtype=tdt, device=device)
-        return flat.as_strided((n + 1, res + 4, p), (ls, p, 1))
+        flat = torch.empty((n + 2) * ls, dtype=tdt, device=device)
+        return flat.as_strided((n + 2, res + 4, p), (ls, p, 1))
     r8, r4 = (res + 7) // 8 * 8, (res + 3) // 4 * 4
     return torch.empty((n, r4 // 4, r8 // 8, 4, 8), dtype=tdt, device=device)
 

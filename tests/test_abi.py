@@ -278,14 +278,14 @@ def test_volume_bytes_and_brick_validation():
     assert _build(f) == -1
     # stack buffers are padded to whole 8 x 4 tiles
     assert vi.slices_bytes(3, 10, vi.VI_F32) == 3 * 16 * 12 * 4
-    # rows: n+1 layers of res+4 rows of pitch res+4 rounded up to 4, a layer's
+    # rows: n+2 layers of res+4 rows of pitch res+4 rounded up to 4, a layer's
     # size the least odd multiple of half a 128-byte line from there up
-    assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_ROWS) == 4 * 240 * 4  # 14 x 16 = 224 -> 15 x 16
-    assert vi.slices_bytes(3, 10, vi.VI_BF16, vi.VI_STACK_ROWS) == 4 * 224 * 2  # 7 x 32
-    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_ROWS) == 3 * 1056800 * 2  # 1028^2 -> 33025 x 32
-    assert vi.slices_bytes(2, 1024, vi.VI_F16, vi.VI_STACK_ROWS) == 3 * 1056800 * 2
+    assert vi.slices_bytes(3, 10, vi.VI_F32, vi.VI_STACK_ROWS) == 5 * 240 * 4  # 14 x 16 = 224 -> 15 x 16
+    assert vi.slices_bytes(3, 10, vi.VI_BF16, vi.VI_STACK_ROWS) == 5 * 224 * 2  # 7 x 32
+    assert vi.slices_bytes(2, 1024, vi.VI_BF16, vi.VI_STACK_ROWS) == 4 * 1056800 * 2  # 1028^2 -> 33025 x 32
+    assert vi.slices_bytes(2, 1024, vi.VI_F16, vi.VI_STACK_ROWS) == 4 * 1056800 * 2
     assert vi.slices_bytes(2, 1024, vi.VI_F16, vi.VI_STACK_TILED) == 0
-    assert vi.slices_bytes(2, 1024, vi.VI_F32, vi.VI_STACK_ROWS) == 3 * 1028 * 1028 * 4  # 66049 x 16
+    assert vi.slices_bytes(2, 1024, vi.VI_F32, vi.VI_STACK_ROWS) == 4 * 1028 * 1028 * 4  # 66049 x 16
     assert vi.slices_bytes(2, 8, vi.VI_F32, 5) == 0
 
 
@@ -302,7 +302,7 @@ def test_row_layer_rule():
             ls = vi.row_layer(res, dt)
             assert (ls * es) % 128 == 64 and w * p <= ls < w * p + 2 * 128 // es
             assert not any((q * es) % 128 == 64 for q in range(w * p, ls))  # the least such
-            assert vi.slices_bytes(5, res, dt, vi.VI_STACK_ROWS) == 6 * ls * es
+            assert vi.slices_bytes(5, res, dt, vi.VI_STACK_ROWS) == 7 * ls * es
 
 
 def test_occupancy_validation():

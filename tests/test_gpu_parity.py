@@ -388,8 +388,8 @@ def test_stack_is_camera_independent_and_deterministic():
 @pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
 def test_row_layout_matches_its_definition(res, dtype):
     """Row layout: the grid row-major with a two-texel border and a leading
-    layer that transmit fully (T = 1, optical depth 0); interior bit for bit
-    equal to the tiled stack."""
+    layer that transmit fully (T = 1, optical depth 0) and a trailing layer
+    equal to the last; interior bit for bit equal to the tiled stack."""
     raw = W.sphere_u8(30, radius=10, density=200, noise=30, seed=res)
     vol, tf = gpu_inputs(raw, W.tf_ramp())
     light, n = [0.3, -0.5, 0.8], 11
@@ -398,9 +398,10 @@ def test_row_layout_matches_its_definition(res, dtype):
     torch.cuda.synchronize()
     D = t.dense()
     ring = 1.0 if dtype == vi.VI_F32 else 0.0
-    want = torch.full((n + 1, res + 4, res + 4), ring, dtype=D.dtype, device=DEV)
-    want[1:, 2:res + 2, 2:res + 2] = D
-    assert r.data.shape == (n + 1, res + 4, vi.row_pitch(res, dtype))
+    want = torch.full((n + 2, res + 4, res + 4), ring, dtype=D.dtype, device=DEV)
+    want[1:n + 1, 2:res + 2, 2:res + 2] = D
+    want[n + 1] = want[n]      # the trailing layer repeats the last
+    assert r.data.shape == (n + 2, res + 4, vi.row_pitch(res, dtype))
     assert torch.equal(r.padded(), want)
     assert torch.equal(r.dense(), D)
 
@@ -416,11 +417,12 @@ def test_half_stack_matches_its_definition(res):
     f = vi.build_attenuation(vol, tf, light, n, res, vi.VI_F32, layout=vi.VI_STACK_ROWS)
     h = vi.build_attenuation(vol, tf, light, n, res, vi.VI_F16, layout=vi.VI_STACK_ROWS)
     torch.cuda.synchronize()
-    assert h.data.dtype == torch.float16 and h.data.shape == (n + 1, res + 4, vi.row_pitch(res, vi.VI_F16))
+    assert h.data.dtype == torch.float16 and h.data.shape == (n + 2, res + 4, vi.row_pitch(res, vi.VI_F16))
     P = h.padded().float()
     ring = torch.ones_like(P)
     ring[1:, 2:res + 2, 2:res + 2] = 0.0
     assert torch.all(P[ring > 0] == 1.0)
+    assert torch.equal(P[n + 1], P[n])      # the trailing layer repeats the last
     T32, T16 = f.dense().double(), h.dense().double()
     err = float(((T16 - T32).abs() - T32 * 2.0 ** -11).max())
     report(f"half stack res {res} vs float stack (beyond 2^-11 T)", err)
