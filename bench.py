@@ -48,9 +48,9 @@ MEASURED = {
     # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1
     # (lights 0, 0, 1); per launch: FETCH_SIZE / WRITE_SIZE in KiB, SQ_INSTS_VALU, GRBM_GUI_ACTIVE
     # (summed over the 8 XCDs), TA_TA_BUSY_sum and the other SQ counters of the same passes
-    ("build", "large", "rows", 16, "quads"): {"sha256": "045643794df170f2a57c0169edd8adcdefb440a1779889200a976fcdb17bd381", "fetch_kib": 273494.5, "write_kib": 2119779.0, "valu_insts": 168741141, "gui_cycles": 14170968, "ta_busy": 274163419, "vmem_rd": 1226619, "vmem_wr": 8471169, "waves": 16896, "wave_cycles": 3230758005, "busy_cycles": 55746904, "wait_inst_any": 565919262, "lds_insts": 11275370, "salu_insts": 108490483, "tcp_accesses": 66792582},
-    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "fd38f1e60ce1e2ca63263618a3afc68a0635c5f55f774db985b58da8f64f3834", "fetch_kib": 108651.7, "write_kib": 33397.9, "valu_insts": 541556037, "gui_cycles": 20337362, "ta_busy": 368415554, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2477481161, "busy_cycles": 72908618, "wait_inst_any": 400610812, "lds_insts": 16872411, "salu_insts": 116432238, "tcp_accesses": 448494575},
-    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "fd38f1e60ce1e2ca63263618a3afc68a0635c5f55f774db985b58da8f64f3834", "fetch_kib": 120346.1, "write_kib": 33494.8, "valu_insts": 595820378, "gui_cycles": 23067013, "ta_busy": 450340420, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2313563150, "busy_cycles": 79751580, "wait_inst_any": 534150019, "lds_insts": 16872411, "salu_insts": 138750415, "tcp_accesses": 579402332},
+    ("build", "large", "rows", 16, "quads"): {"sha256": "ad1989fbc00877495db2fb9ede2db7b5baa4ea8c32229fe1dea82110b4b2039f", "fetch_kib": 273281.2, "write_kib": 2123926.3, "valu_insts": 168757654, "gui_cycles": 14160771, "ta_busy": 274514049, "vmem_rd": 1226619, "vmem_wr": 8487682, "waves": 16896, "wave_cycles": 3220942155, "busy_cycles": 55494959, "wait_inst_any": 565325487, "lds_insts": 11275370, "salu_insts": 108540037, "tcp_accesses": 66858631},
+    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 108673.1, "write_kib": 33389.4, "valu_insts": 511498181, "gui_cycles": 20254768, "ta_busy": 366516519, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2426670527, "busy_cycles": 71604580, "wait_inst_any": 364281201, "lds_insts": 16872411, "salu_insts": 116374954, "tcp_accesses": 448494575},
+    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 120844.3, "write_kib": 33485.0, "valu_insts": 561198279, "gui_cycles": 22594079, "ta_busy": 448467834, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2285667767, "busy_cycles": 78952778, "wait_inst_any": 536788524, "lds_insts": 16872411, "salu_insts": 138693131, "tcp_accesses": 579402332},
 }
 
 
