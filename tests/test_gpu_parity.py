@@ -384,15 +384,18 @@ def test_stack_is_camera_independent_and_deterministic():
     assert torch.equal(i1, i2)
 
 
-@pytest.mark.parametrize("res", [1, 6, 19, 64])
+@pytest.mark.parametrize("res,n", [(1, 11), (6, 11), (19, 11), (64, 11), (64, 1), (64, 2), (45, 3)])
 @pytest.mark.parametrize("dtype", [vi.VI_F32, vi.VI_BF16])
-def test_row_layout_matches_its_definition(res, dtype):
+def test_row_layout_matches_its_definition(res, n, dtype):
     """Row layout: the grid row-major with a two-texel border and a leading
     layer that transmit fully (T = 1, optical depth 0) and a trailing layer
-    equal to the last; interior bit for bit equal to the tiled stack."""
+    equal to the last; interior bit for bit equal to the tiled stack.  The
+    sizes span one and several workgroup runs per layer, and one, two and
+    an odd number of slabs (the build pairs slabs and rotates every other
+    layer by half a line)."""
     raw = W.sphere_u8(30, radius=10, density=200, noise=30, seed=res)
     vol, tf = gpu_inputs(raw, W.tf_ramp())
-    light, n = [0.3, -0.5, 0.8], 11
+    light = [0.3, -0.5, 0.8]
     t = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_TILED)
     r = vi.build_attenuation(vol, tf, light, n, res, dtype, layout=vi.VI_STACK_ROWS)
     torch.cuda.synchronize()
@@ -404,6 +407,13 @@ def test_row_layout_matches_its_definition(res, dtype):
     assert r.data.shape == (n + 2, res + 4, vi.row_pitch(res, dtype))
     assert torch.equal(r.padded(), want)
     assert torch.equal(r.dense(), D)
+    # lookups from either layout, the first and last layers included, agree bit for bit
+    cam = W.camera_orbit(40, 32, 0.7, 0.3)
+    for mode, opts in (("shell", {}), ("cone", {}), ("shadow", {"nearest_layer": 1})):
+        a = vi.render(vol, tf, t, cam, mode, 0.5, opts)
+        b = vi.render(vol, tf, r, cam, mode, 0.5, opts)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), mode
 
 
 @pytest.mark.parametrize("res", [1, 19, 64])
