@@ -48,10 +48,33 @@ MEASURED = {
     # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1
     # (lights 0, 0, 1); per launch: FETCH_SIZE / WRITE_SIZE in KiB, SQ_INSTS_VALU, GRBM_GUI_ACTIVE
     # (summed over the 8 XCDs), TA_TA_BUSY_sum and the other SQ counters of the same passes
-    ("build", "large", "rows", 16, "quads"): {"sha256": "ad1989fbc00877495db2fb9ede2db7b5baa4ea8c32229fe1dea82110b4b2039f", "fetch_kib": 273281.2, "write_kib": 2123926.3, "valu_insts": 168757654, "gui_cycles": 14160771, "ta_busy": 274514049, "vmem_rd": 1226619, "vmem_wr": 8487682, "waves": 16896, "wave_cycles": 3220942155, "busy_cycles": 55494959, "wait_inst_any": 565325487, "lds_insts": 11275370, "salu_insts": 108540037, "tcp_accesses": 66858631},
-    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 108673.1, "write_kib": 33389.4, "valu_insts": 511498181, "gui_cycles": 20254768, "ta_busy": 366516519, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2426670527, "busy_cycles": 71604580, "wait_inst_any": 364281201, "lds_insts": 16872411, "salu_insts": 116374954, "tcp_accesses": 448494575},
-    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 120844.3, "write_kib": 33485.0, "valu_insts": 561198279, "gui_cycles": 22594079, "ta_busy": 448467834, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2285667767, "busy_cycles": 78952778, "wait_inst_any": 536788524, "lds_insts": 16872411, "salu_insts": 138693131, "tcp_accesses": 579402332},
+    ("build", "large", "rows", 16, "quads"): {"sha256": "ad1989fbc00877495db2fb9ede2db7b5baa4ea8c32229fe1dea82110b4b2039f", "fetch_kib": 273281.2, "write_kib": 2123926.3, "valu_insts": 168757654, "gui_cycles": 14160771, "ta_busy": 274514049, "vmem_rd": 1226619, "vmem_wr": 8487682, "waves": 16896, "wave_cycles": 3220942155, "busy_cycles": 55494959, "wait_inst_any": 565325487, "lds_insts": 11275370, "salu_insts": 108540037, "tcp_accesses": 66858631, "tcc_read_req": 17092835, "tcc_hit": 29646820, "tcc_miss": 21438139},
+    ("render_shell", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 108673.1, "write_kib": 33389.4, "valu_insts": 511498181, "gui_cycles": 20254768, "ta_busy": 366516519, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2426670527, "busy_cycles": 71604580, "wait_inst_any": 364281201, "lds_insts": 16872411, "salu_insts": 116374954, "tcp_accesses": 448494575, "tcc_read_req": 26142115, "tcc_hit": 24688971, "tcc_miss": 2018424},
+    ("render_cone", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 120844.3, "write_kib": 33485.0, "valu_insts": 561198279, "gui_cycles": 22594079, "ta_busy": 448467834, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2285667767, "busy_cycles": 78952778, "wait_inst_any": 536788524, "lds_insts": 16872411, "salu_insts": 138693131, "tcp_accesses": 579402332, "tcc_read_req": 39975007, "tcc_hit": 38331643, "tcc_miss": 2209483},
 }
+
+
+# The L2 probe (bench.py --l2-probe 2048: libvi_probe.so reads a 2 MiB buffer,
+# resident in every XCD's L2, 4 GiB over): per launch TCP_TCC_READ_REQ_sum (L1
+# to L2 read requests) and GRBM_GUI_ACTIVE from a rocprofv3 --pmc run, and the
+# HIP-event read rate.  The frames' L1 -> L2 read requests per second are
+# quoted against the probe's, counted the same way (requests, not bytes, so no
+# request size is assumed).
+L2_PROBE = {"buffer_bytes": 2097152, "bytes_read": 4294967296, "tcc_read_req": 19846548, "gui_cycles": 2447567,
+            "gbs": 28312.1}
+CLOCK_HZ = 2.4e9
+
+
+def l2_roof(r, ms):
+    """L1 -> L2 read requests of a recorded launch against the L2 probe's rate."""
+    if not r or "tcc_read_req" not in r:
+        return None
+    probe_rate = L2_PROBE["tcc_read_req"] / (L2_PROBE["gui_cycles"] / N_XCDS / CLOCK_HZ)
+    rate = r["tcc_read_req"] / (ms * 1e-3)
+    return {"read_requests": r["tcc_read_req"], "achieved_greq_per_s": round(rate / 1e9, 2),
+            "probe_greq_per_s": round(probe_rate / 1e9, 2), "frac": round(rate / probe_rate, 4),
+            "hit_frac": round(r["tcc_hit"] / max(1, r["tcc_hit"] + r["tcc_miss"]), 4),
+            "probe_read_gbs": L2_PROBE["gbs"]}
 
 
 def source_sha(kind: str) -> str:
@@ -478,6 +501,10 @@ def main():
                     help="stack lookups read the layer nearest each depth index instead of interpolating in depth")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
+    ap.add_argument("--l2-probe", type=int, default=0, metavar="KIB",
+                    help="only run the L2 probe (libvi_probe.so): 4 GiB of reads from one KIB KiB buffer, a "
+                         "power of two of at least 8 KiB that fits in L2 (measures the L2 read rate the "
+                         "gather roof is quoted against)")
     args = ap.parse_args()
     global STACK_LAYOUT
     STACK_LAYOUT = {"tiled": 0, "rows": 1}[args.stack_layout]
@@ -491,6 +518,36 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "launches": 3}), flush=True)
+        return
+    if args.l2_probe:
+        import ctypes
+        import torch
+        probe = ctypes.CDLL(os.path.join(ROOT, "paper_2008_06134_amd", "libvi_probe.so"))
+        probe.vi_probe_l2_read.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+        chunks, step, blocks = args.l2_probe // 4, 37, 4096       # 4 KiB chunks; 37 is coprime to a power of two
+        iters = max(1, (1 << 32) // (blocks * 4096))               # 4 GiB read per launch
+        buf = torch.ones(chunks * 1024, dtype=torch.float32, device="cuda:0")
+        out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda:0")
+
+        def launch():
+            rc = probe.vi_probe_l2_read(ctypes.c_void_p(buf.data_ptr()), chunks, step, iters, blocks,
+                                        ctypes.c_void_p(out.data_ptr()), None)
+            if rc:
+                raise RuntimeError(f"vi_probe_l2_read failed: {rc}")
+        launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(3):
+            e0.record()
+            launch()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[1]
+        nbytes = blocks * 4096 * iters
+        print(json.dumps({"l2_probe_buffer_bytes": chunks * 4096, "bytes_read": nbytes, "launches": 4,
+                          "ms": round(ms, 4), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -588,7 +645,7 @@ def main():
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": tb,
                     "flops_per_launch": int(flops), "flops_per_composited_segment": FLOPS_PER_SAMPLE[mode],
                     "avg_launch_ms": round(avg_ms, 4),
-                    "valu_issue_frac": valu, "address_unit_busy_frac": ta,
+                    "valu_issue_frac": valu, "address_unit_busy_frac": ta, "l2": l2_roof(rec, avg_ms),
                     "hbm": {"compulsory_bytes": ideal,
                             "compulsory_gbs": round(ideal / (avg_ms * 1e-3) / 1e9, 2),
                             "compulsory_frac": round(ideal / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),

@@ -1,4 +1,5 @@
-"""Build libvi.so (HIP, gfx950) in-tree with hipcc.
+"""Build libvi.so (HIP, gfx950) in-tree with hipcc, and the benchmark's L2
+probe libvi_probe.so beside it.
 
     python -m paper_2008_06134_amd.build
 
@@ -18,6 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvi.so")
+# the benchmark's L2 probe, a library of its own that only bench.py loads
+PROBE_SRC, PROBE_OUT = "vi_probe.hip", os.path.join(HERE, "libvi_probe.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["vi_api.hip", "vi_build.hip", "vi_render.hip", "vi_layout.hip", "vi_sched.cpp", "vi_server.hip"]
 ARCH = os.environ.get("VI_OFFLOAD_ARCH", "gfx950")
@@ -63,7 +66,18 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    build_probe(cc)
     return OUT
+
+
+def build_probe(cc: str) -> str:
+    tmp = PROBE_OUT + ".tmp"
+    cmd = [cc, *flags(), "-shared", "-o", tmp, os.path.join(CSRC, PROBE_SRC)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_OUT)
+    return PROBE_OUT
 
 
 if __name__ == "__main__":

@@ -2,6 +2,7 @@
 host-side logic (light frame, validation, sizes) behaves -- no kernel launches."""
 import ctypes as C
 import math
+import os
 import re
 import subprocess
 
@@ -383,3 +384,13 @@ def test_step_bound_keeps_segments_below_2_24():
     good = _desc(f)
     assert _render(f, good, step=1e-6) == -1
     assert "2^24" in vi.lib().vi_last_error().decode()
+
+
+def test_l2_probe_library_exports_its_entry_point():
+    """The benchmark's L2 probe is built beside libvi (its own library, loaded only
+    by bench.py --l2-probe) and exports its one C entry point."""
+    import subprocess
+    path = os.path.join(os.path.dirname(vi.LIB_PATH), "libvi_probe.so")
+    assert os.path.exists(path), "build the libraries first (paper_2008_06134_amd.build)"
+    syms = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True, check=True).stdout
+    assert " vi_probe_l2_read" in syms
