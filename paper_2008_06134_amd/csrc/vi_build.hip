@@ -90,6 +90,7 @@ __device__ __forceinline__ float q_to_float(int64_t H) { return (float)H * (1.0f
 constexpr int kBuildNT = VI_BUILD_NT, kBuildC = VI_BUILD_C, kBuildB = VI_BUILD_BATCH;
 constexpr bool kBuildConsec = VI_BUILD_CONSEC != 0;
 constexpr int kBuildExch = VI_BUILD_EXCH;
+constexpr int kRowsX = 2;  // exchange rows per slab pair: both of its layers
 
 // The slabs of a column whose midpoints lie in the cube: k in [k_in, k_out]
 // (empty when k_in > k_out), exactly as the per-slab test lo <= h_k <= hi
@@ -148,6 +149,37 @@ __device__ __forceinline__ void put_texel(void* out, uint32_t at, float T, float
     if (OUT_DTYPE == VI_F32) *(float*)((char*)out + (at << 2)) = T;
     else if (OUT_DTYPE == VI_BF16) *(uint16_t*)((char*)out + (at << 1)) = f32_to_bf16(tau);
     else *(__half*)((char*)out + (at << 1)) = __float2half_rn(fast_exp2(-tau));
+}
+
+// An empty statement that reads a fetched footprint's registers.  Placed
+// after all loads of a pair of slabs, it is the one point where they must
+// have arrived, so the compiler waits there once for all of them; without it
+// the loads of a slab fetched only by some lanes left their registers pending
+// across the loop's back edge, and the compiler waited for the first slab's
+// loads before issuing the second slab's (8 % slower).
+template <typename T>
+__device__ __forceinline__ void keep_value(const T& x)
+{
+    if constexpr (sizeof(T) == 8) asm volatile("" ::"v"(__builtin_bit_cast(uint64_t, x)));
+    else if constexpr (sizeof(T) == 4) asm volatile("" ::"v"(__builtin_bit_cast(uint32_t, x)));
+    else if constexpr (sizeof(T) == 2) asm volatile("" ::"v"((uint32_t)__builtin_bit_cast(uint16_t, x)));
+    else if constexpr (sizeof(T) == 1) asm volatile("" ::"v"((uint32_t)__builtin_bit_cast(uint8_t, x)));
+    else {
+        struct W { uint64_t lo, hi; };
+        const W w = __builtin_bit_cast(W, x);
+        asm volatile("" ::"v"(w.lo), "v"(w.hi));
+    }
+}
+template <typename VT, int LAYOUT>
+__device__ __forceinline__ void keep_foot(const RawFoot<VT, LAYOUT>& r)
+{
+    if constexpr (LAYOUT == VI_LAYOUT_QUAD4) {
+        keep_value(r.a);
+        keep_value(r.b);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) keep_value(r.v[i]);
+    }
 }
 
 // Shared set-up of both layouts: the TF's opacities and the occupancy bits
@@ -366,19 +398,23 @@ __device__ __forceinline__ void build_tiled(const BuildParams& P)
 // rotated by half a line, so that every wave's store there starts on a line
 // too; only the two half-lines at the ends of the workgroup's run are
 // written in part.  (Stores straddling lines measured at half the write
-// rate.)  The rotated layers of E pairs wait in LDS for one barrier, which
-// every wave reaches the same number of times (E = 4: a barrier per pair
-// held the 2-byte stacks 8 % back); a wave with no slab inside the cube in a
-// pair only stores.  (Issuing the next pair's loads before this pair's
-// stores, so that a wait for loads never waits for stores, measured 6-13 %
-// slower.)
+// rate.)  Both layers of E pairs wait in LDS for one barrier, which every
+// wave reaches the same number of times, and all their stores go out after
+// it (E = 4: a barrier per pair held the 2-byte stacks 8 % back): CDNA
+// counts loads and stores on one counter, so a wait for a pair's loads also
+// waits for every store issued before them, and with no store between the
+// batch's loads only its first pair pays for the previous batch's stores
+// (float 0.76 -> 0.73 ms together with the single wait per pair below).  A
+// wave with no slab inside the cube in a pair only stores.  (Issuing the
+// next pair's loads before this pair's stores measured 6-13 % slower: the
+// compiler then waited for every load at each pair.)
 template <typename VT, int LAYOUT, int OUT_DTYPE, bool PT>
 __device__ __forceinline__ void build_rows(const BuildParams& P)
 {
     static_assert(kBuildC == 1 && !kBuildConsec, "the row-layout build runs one column per lane");
     constexpr uint32_t NT = kBuildNT;
     constexpr uint32_t HALF = OUT_DTYPE == VI_F32 ? 16u : 32u;  // half a 128-byte line, in elements
-    extern __shared__ float s_alpha[];  // K alphas, the occupancy bits, then two sets of E exchange rows of NT
+    extern __shared__ float s_alpha[];  // K alphas, the occupancy bits, then two sets of 2E exchange rows of NT
     uint32_t* s_bits = (uint32_t*)(s_alpha + P.K);
     float* s_x = (float*)(s_bits + stage_build_tables(P, s_alpha, s_bits));
     const bool use_bits = P.occ.bits != nullptr;
@@ -413,12 +449,12 @@ __device__ __forceinline__ void build_rows(const BuildParams& P)
     const VolIndex VI_ = {1u, P.vsy, P.vsz};
     const bool darken = P.darken > 0.0f;
     float T = 1.0f, tau = 0.0f;  // transmittance (float stack), optical depth (2-byte stacks)
-    // E pairs of slabs per exchange: their layers half a line off wait in E
-    // LDS rows and are stored after one barrier (two sets of rows in turn,
-    // so that one barrier per E pairs keeps writes and reads apart)
+    // E pairs of slabs per exchange: their layers wait in 2E LDS rows and
+    // are stored after one barrier (two sets of rows in turn, so that one
+    // barrier per E pairs keeps writes and reads apart)
     constexpr int E = kBuildExch;
     for (int k0 = 0; k0 < P.n; k0 += 2 * E) {
-        float* xs = s_x + ((uint32_t)(k0 / (2 * E)) & 1u) * (E * NT);
+        float* xs = s_x + ((uint32_t)(k0 / (2 * E)) & 1u) * (kRowsX * E * NT);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int kk = k0 + 2 * e;  // this pair: layers kk (half a line off) and kk + 1
@@ -436,6 +472,8 @@ __device__ __forceinline__ void build_rows(const BuildParams& P)
                     if (sp[u].fetch)
                         foot_load_g<VT, LAYOUT>(raw[u], sp[u].wx, sp[u].wy, vol, VI_, P.N, sp[u].gx, sp[u].gy,
                                                 sp[u].gz);
+                keep_foot<VT, LAYOUT>(raw[0]);
+                keep_foot<VT, LAYOUT>(raw[1]);
                 if (sp[0].fetch) slab_step<VT, LAYOUT, OUT_DTYPE>(P, s_alpha, raw[0], sp[0], ex, darken, T, tau);
                 v0 = OUT_DTYPE == VI_F32 ? T : tau;
                 if (sp[1].fetch) slab_step<VT, LAYOUT, OUT_DTYPE>(P, s_alpha, raw[1], sp[1], ex, darken, T, tau);
@@ -443,10 +481,8 @@ __device__ __forceinline__ void build_rows(const BuildParams& P)
                 v0 = OUT_DTYPE == VI_F32 ? T : tau;
             }
             for (int a = 0; a < 3; ++a) H[a] += 2 * A[a];
-            // layer kk + 1, on the line grid: its own lane
-            if (kk + 1 < P.n && col) put_texel<OUT_DTYPE>(P.out, at + layer, T, tau);
-            at += 2 * layer;
-            xs[e * NT + t] = v0;
+            xs[e * NT + t] = v0;                                 // layer kk
+            xs[(E + e) * NT + t] = OUT_DTYPE == VI_F32 ? T : tau;  // layer kk + 1
         }
         __syncthreads();
         // the layers half a line off, rotated by half a line
@@ -456,6 +492,10 @@ __device__ __forceinline__ void build_rows(const BuildParams& P)
             const float w = xs[e * NT + tr];
             if (col_r) put_texel<OUT_DTYPE>(P.out, at_r, w, w);
             at_r += 2 * layer;
+            // layer kk + 1, on the line grid: each lane its own element
+            const float o = xs[(E + e) * NT + t];
+            if (k0 + 2 * e + 1 < P.n && col) put_texel<OUT_DTYPE>(P.out, at + layer, o, o);
+            at += 2 * layer;
         }
     }
     // the trailing layer n repeats layer n - 1
@@ -490,7 +530,7 @@ static hipError_t launch_build_t(const BuildParams& p, hipStream_t s)
         // runs of a layer's element range, border and padding included; two
         // sets of exchange rows of floats
         const dim3 grid(row_run_grid((p.rlayer + per_group - 1) / per_group, 1u));
-        const size_t lds_rows = lds + 2 * sizeof(float) * (size_t)kBuildExch * kBuildNT;
+        const size_t lds_rows = lds + 2 * sizeof(float) * (size_t)kRowsX * kBuildExch * kBuildNT;
         if (p.point) launch_build_k<VT, LAYOUT, VI_STACK_ROWS, true>(p, grid, lds_rows, s);
         else launch_build_k<VT, LAYOUT, VI_STACK_ROWS, false>(p, grid, lds_rows, s);
     } else {
