@@ -501,6 +501,9 @@ def main():
                     help="stack lookups read the layer nearest each depth index instead of interpolating in depth")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
+    ap.add_argument("--store-probe", action="store_true",
+                    help="only run the store-only probe of the build's write pattern (libvi_probe.so): 513 "
+                         "layers of 1024 rows of 1024 floats, rows off and on the 128-byte line grid")
     ap.add_argument("--l2-probe", type=int, default=0, metavar="KIB",
                     help="only run the L2 probe (libvi_probe.so): 4 GiB of reads from one KIB KiB buffer, a "
                          "power of two of at least 8 KiB that fits in L2 (measures the L2 read rate the "
@@ -518,6 +521,42 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "launches": 3}), flush=True)
+        return
+    if args.store_probe:
+        import ctypes
+        import torch
+        probe = ctypes.CDLL(os.path.join(ROOT, "paper_2008_06134_amd", "libvi_probe.so"))
+        probe.vi_probe_store_rows.argtypes = [ctypes.c_void_p] + [ctypes.c_uint32] * 6 + [ctypes.c_void_p]
+        res, layers = 1024, 513
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rows_out = []
+        # (name, first element, row pitch, layer stride): the row layout's pitch with its rows anywhere in a
+        # line, and rows and layers on the line grid
+        for name, org, pitch in (("rows off the line grid (pitch 1028)", 2 * 1028 + 2, 1028),
+                                 ("rows on the line grid (pitch 1056)", 2 * 1056 + 32, 1056)):
+            lstride = (res + 4) * pitch
+            need = org + (layers - 1) * lstride + (res - 1) * pitch + res
+            out = torch.empty(need, dtype=torch.float32, device="cuda:0")
+
+            def launch():
+                rc = probe.vi_probe_store_rows(ctypes.c_void_p(out.data_ptr()), res, res, layers, org, pitch,
+                                               lstride, None)
+                if rc:
+                    raise RuntimeError(f"vi_probe_store_rows failed: {rc}")
+            launch()
+            ts = []
+            for _ in range(5):
+                e0.record()
+                launch()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = sorted(ts)[2]
+            nbytes = res * res * layers * 4
+            rows_out.append({"pattern": name, "bytes": nbytes, "ms": round(ms, 4),
+                             "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)})
+            del out
+        print(json.dumps({"store_probe": rows_out}), flush=True)
         return
     if args.l2_probe:
         import ctypes

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvi.so")
-# the benchmark's L2 probe, a library of its own that only bench.py loads
+# the benchmark's probes (L2 reads, the build's store pattern), a library of its own that only bench.py loads
 PROBE_SRC, PROBE_OUT = "vi_probe.hip", os.path.join(HERE, "libvi_probe.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["vi_api.hip", "vi_build.hip", "vi_render.hip", "vi_layout.hip", "vi_sched.cpp", "vi_server.hip"]

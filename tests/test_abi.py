@@ -387,10 +387,10 @@ def test_step_bound_keeps_segments_below_2_24():
 
 
 def test_l2_probe_library_exports_its_entry_point():
-    """The benchmark's L2 probe is built beside libvi (its own library, loaded only
-    by bench.py --l2-probe) and exports its one C entry point."""
+    """The benchmark's probes are built beside libvi (their own library, loaded only
+    by bench.py --l2-probe and --store-probe) and export their C entry points."""
     import subprocess
     path = os.path.join(os.path.dirname(vi.LIB_PATH), "libvi_probe.so")
     assert os.path.exists(path), "build the libraries first (paper_2008_06134_amd.build)"
     syms = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True, check=True).stdout
-    assert " vi_probe_l2_read" in syms
+    assert " vi_probe_l2_read" in syms and " vi_probe_store_rows" in syms
