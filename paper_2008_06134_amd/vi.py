@@ -300,7 +300,7 @@ def row_layer(res: int, dtype: int = VI_F32) -> int:
 class Slices:
     """An attenuation stack: the device buffer and its descriptor.  Tiled:
     8 x 4 texel tiles per layer, shaped n x R4/4 x R8/8 x 4 x 8.  Rows:
-    (n+2) x (res+4) x P with layer stride row_layer(res), texel (k, j, i) at
+    (n+2) x (res+4) x P with layer stride row_layer(res, dtype), texel (k, j, i) at
     [k+1, j+2, i+2]: a leading layer and a two-texel border around the
     res x res grid, all fully transmitting, and a trailing layer equal to
     the last."""
