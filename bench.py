@@ -48,7 +48,7 @@ MEASURED = {
     # 1024^2 f32 stack in rows, 1920x1080), mean of the three launches of bench --steps 2 --warmup 1
     # (lights 0, 0, 1); per launch: FETCH_SIZE / WRITE_SIZE in KiB, SQ_INSTS_VALU, GRBM_GUI_ACTIVE
     # (summed over the 8 XCDs), TA_TA_BUSY_sum and the other SQ counters of the same passes
-    ("build", "large", "rows", 16, "quads"): {"sha256": "312a7e4347992795e9fe8b221e52fdaed6c1eb85630aa822989d8993ef6ec1be", "fetch_kib": 292007.8, "write_kib": 2123952.4, "valu_insts": 164526486, "gui_cycles": 12876287, "ta_busy": 262863551, "vmem_rd": 1226619, "vmem_wr": 8487682, "waves": 16896, "wave_cycles": 2859996056, "busy_cycles": 49613123, "wait_inst_any": 632566836, "lds_insts": 15502698, "salu_insts": 107482245, "tcp_accesses": 66858631, "tcc_read_req": 14678032, "tcc_hit": 26952260, "tcc_miss": 21715285},
+    ("build", "large", "rows", 16, "quads"): {"sha256": "0980c39b73478c21f25a7a99b84b31e2b5d5b0ead1a7c3475945d33b70f10cbc", "fetch_kib": 292007.8, "write_kib": 2123952.4, "valu_insts": 164526486, "gui_cycles": 12876287, "ta_busy": 262863551, "vmem_rd": 1226619, "vmem_wr": 8487682, "waves": 16896, "wave_cycles": 2859996056, "busy_cycles": 49613123, "wait_inst_any": 632566836, "lds_insts": 15502698, "salu_insts": 107482245, "tcp_accesses": 66858631, "tcc_read_req": 14678032, "tcc_hit": 26952260, "tcc_miss": 21715285},
     ("render_shell", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 108693.1, "write_kib": 33384.4, "valu_insts": 511498181, "gui_cycles": 20077457, "ta_busy": 366366152, "vmem_rd": 17659382, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2432241094, "busy_cycles": 71808189, "wait_inst_any": 363795259, "lds_insts": 16872411, "salu_insts": 116374954, "tcp_accesses": 448494575, "tcc_read_req": 26169923, "tcc_hit": 24717088, "tcc_miss": 2018113},
     ("render_cone", "large", "rows", 16, "quads"): {"sha256": "5a6bcb811cd3c707a1697f9d9ecf6e4f2ec0176bf83397d7ce1c9b0f1a9a7533", "fetch_kib": 120562.9, "write_kib": 33482.7, "valu_insts": 561198279, "gui_cycles": 22652654, "ta_busy": 448381787, "vmem_rd": 22669024, "vmem_wr": 148647, "waves": 130560, "wave_cycles": 2284903712, "busy_cycles": 78246335, "wait_inst_any": 533830761, "lds_insts": 16872411, "salu_insts": 138693131, "tcp_accesses": 579402332, "tcc_read_req": 40094574, "tcc_hit": 38450642, "tcc_miss": 2210050},
 }

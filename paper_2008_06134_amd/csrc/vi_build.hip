@@ -5,8 +5,10 @@
 // midpoint, the transfer-function opacity is looked up and corrected to the
 // slab thickness (extinction form, Eq. 6), and the running transmittance is
 // multiplied by (1 - alpha) -- Eq. 4 applied to opacity.  Every layer is
-// written as soon as it is known, so the pass is one streaming sweep: the
-// volume is read through the caches and the stack is written once.
+// written within a few slabs of being known (the row layout holds the layers
+// of four slab pairs in LDS before storing them), so the pass is one
+// streaming sweep: the volume is read through the caches and the stack is
+// written once.
 //
 // Mapping: one workgroup per run of consecutive elements of a layer, one
 // column per lane (in the tiled layout optionally C columns).  In the row
